@@ -1,0 +1,19 @@
+"""Plain, slow FP64 CPU oracle of the non-nested multilevel smoothed Schwarz
+preconditioned FGMRES solve.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the library or its Python binding may
+import, call or execute anything in this package; only the tests, the smoke
+check and the benchmark's CPU-baseline leg do.  It shares no code with the
+GPU path: its inputs come from the seeded generators in ``workloads`` and
+everything else is written here, from the paper, with NumPy/SciPy primitives
+(sparse products, LAPACK LU) as the only library steps.
+
+Modules
+  fem        P1 discretisation of -div(kappa grad u) = f (Section 2.1)
+  transfer   barycentric point-location interpolation between meshes
+  schwarz    coordinate-bisection partition, overlap, RAS (Section 2.2)
+  multilevel V-cycle of Algorithm 2 (Section 3.3)
+  krylov     right-preconditioned flexible GMRES (Section 2.1, Section 4)
+  problem    glue that builds a whole hierarchy from a workload
+"""
+from . import fem, transfer, schwarz, multilevel, krylov, problem  # noqa: F401

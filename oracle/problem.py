@@ -1,0 +1,61 @@
+"""Whole-hierarchy oracle: assemble every level, build transfers, smoothers
+and the V-cycle, then solve with FGMRES (test infrastructure only).
+
+Input: a ``workloads.Problem`` (meshes fine..coarse, subdomain counts per
+smoothed level, kappa).  The finest level carries the system the outer
+Krylov method solves; coarser levels are rediscretised with kappa at their
+own centroids (the Jacobian each level provides in Algorithm 2).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import List, Optional
+
+import numpy as np
+import scipy.sparse.linalg as spla
+
+from . import fem, krylov, multilevel, schwarz, transfer
+
+
+@dataclass
+class OracleHierarchy:
+    problem: object
+    A: List  # per level, Dirichlet-eliminated CSR
+    b: np.ndarray  # fine load vector (f = 1)
+    P: List  # P[l] maps level l+1 -> l
+    parts: List  # (owned, sets) per smoothed level
+    vcycle: multilevel.VCycle
+
+
+def build(problem, f: float = 1.0, locate=transfer.locate_bucket) -> OracleHierarchy:
+    meshes = problem.meshes
+    L = len(meshes)
+    A, P, parts, levels = [], [], [], []
+    b = None
+    for l, m in enumerate(meshes):
+        Al, bl = fem.assemble(m, problem.kappa, f)
+        A.append(Al)
+        if l == 0:
+            b = bl
+    for l in range(L - 1):
+        P.append(transfer.interpolation(meshes[l], meshes[l + 1], locate=locate))
+        owned, sets = schwarz.partition(meshes[l], problem.nparts[l], problem.overlap)
+        parts.append((owned, sets))
+        ras = schwarz.RAS(A[l], meshes[l].dirichlet, owned, sets)
+        levels.append(multilevel.Level(A[l], meshes[l].dirichlet, ras, P[l]))
+    levels.append(multilevel.Level(A[L - 1], meshes[L - 1].dirichlet))
+    vc = multilevel.VCycle(levels, problem.its)
+    return OracleHierarchy(problem, A, b, P, parts, vc)
+
+
+def solve(h: OracleHierarchy, b: Optional[np.ndarray] = None, rtol: Optional[float] = None,
+          restart: Optional[int] = None, max_it: int = 1000) -> krylov.FGMRESResult:
+    pb = h.problem
+    bb = h.b if b is None else b
+    return krylov.fgmres(h.A[0], bb, h.vcycle, restart or pb.restart, rtol or pb.rtol, max_it)
+
+
+def exact(h: OracleHierarchy, b: Optional[np.ndarray] = None) -> np.ndarray:
+    """x* = A^{-1} b by a sparse direct solve."""
+    bb = h.b if b is None else b
+    return spla.splu(h.A[0].tocsc()).solve(bb)
