@@ -1,0 +1,170 @@
+"""Benchmark: solves/s of the non-nested multilevel smoothed Schwarz FGMRES
+solve on one MI355X, with the dominant kernel's roofline and the CPU oracle
+timed beside it.
+
+One step = one full solve of the three-level jittered 48^3 / 24^3 / 10^3
+problem (log-Gaussian kappa, 64 subdomains, FP64) to relative residual
+1e-8, starting from x0 = 0, with the factors resident in HBM.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|mixed]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def ras_bytes(h, level, s_bytes):
+    """Algorithmic bytes of one smoother application on `level`: every dense
+    factor entry once (n_p^2 values: L below and U above the diagonal), the
+    gathered input and the scattered owned output, and the index map."""
+    owner, sets = h.partition(level)
+    n = np.array([len(S) for S in sets], dtype=np.float64)
+    return float(np.sum(n * n) * s_bytes + np.sum(n) * (s_bytes + 4) + np.sum(n) * s_bytes)
+
+
+def spmv_bytes(h, level, s_bytes):
+    li = h.level_info(level)
+    return float(li.nnz * (4 + s_bytes) + 4 * (li.nv + 1) + 3 * li.nv * s_bytes)
+
+
+def cpu_baseline(pb, seconds_cap=60.0):
+    """The FP64 oracle (NumPy/SciPy, LAPACK) on the host cores: setup once,
+    then one full solve of the same problem; solves/s = 1 / solve time."""
+    from oracle import problem as oprob
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    oh = oprob.build(pb)
+    t1 = time.perf_counter()
+    res = oprob.solve(oh)
+    t2 = time.perf_counter()
+    return {
+        "value": 1.0 / (t2 - t1),
+        "unit": "solves/s",
+        "cores": int(threads),
+        "kind": "oracle",
+        "sample": f"one full solve ({res.iterations} FGMRES iterations) of the same 48^3/24^3/10^3 problem after "
+                  f"the oracle's setup ({t1 - t0:.1f} s, not counted)",
+    }, oh, res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    from paper_2412_08981_amd import nnms
+
+    if not torch.cuda.is_available():
+        raise SystemExit("no GPU visible")
+    torch.cuda.init()
+    pb = W.config2(args.precision)
+    prec = nnms.MIXED if args.precision == "mixed" else nnms.FP64
+    t0 = time.perf_counter()
+    meshes = [nnms.Mesh.from_workload(m) for m in pb.meshes]
+    h = nnms.Hierarchy(meshes, pb.nparts, overlap=pb.overlap, its=pb.its, precision=prec)
+    t1 = time.perf_counter()
+    s = nnms.System(h, pb.kappa, 1.0)
+    t2 = time.perf_counter()
+    log(f"[bench] structure setup {t1 - t0:.2f} s, numeric setup (assembly + LU) {t2 - t1:.3f} s")
+    b = s.rhs()
+    n0 = s.n[0]
+    bd = torch.from_numpy(b).cuda()
+    xd = torch.zeros(n0, dtype=torch.float64, device="cuda")
+    graph = not args.no_graph
+    infos = []
+    for _ in range(args.warmup):
+        infos.append(s.solve_device(bd.data_ptr(), xd.data_ptr(), graph=graph))
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        info = s.solve_device(bd.data_ptr(), xd.data_ptr(), graph=graph)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    value = args.steps / el
+    log(f"[bench] {args.steps} solves in {el:.3f} s: {info.iterations} iterations, relres {info.relres:.3e}")
+
+    # numeric setup per parameter (assembly + extraction + LU), timed separately
+    tp = time.perf_counter()
+    s2 = nnms.System(h, W.kappa_draw(204, 999), 1.0)
+    torch.cuda.synchronize()
+    t_assemble = time.perf_counter() - tp
+    s2.destroy()
+
+    # roofline of the dominant kernel: the fine-level smoother
+    sb = 8 if prec == nnms.FP64 else 4
+    ms = s.time_kernel(0, 0, reps=10)
+    ach = ras_bytes(h, 0, sb) / (ms * 1e-3) / 1e9
+    extra = {}
+    for lvl in range(h.L):
+        extra[f"smoother_l{lvl}_ms"] = round(s.time_kernel(0, lvl, reps=10), 4)
+    for lvl in range(h.L - 1):
+        msr = s.time_kernel(1, lvl, reps=20)
+        extra[f"residual_l{lvl}_ms"] = round(msr, 4)
+        extra[f"residual_l{lvl}_GBs"] = round(spmv_bytes(h, lvl, sb) / (msr * 1e-3) / 1e9, 1)
+        extra[f"prolong_l{lvl}_ms"] = round(s.time_kernel(2, lvl, reps=20), 4)
+        extra[f"restrict_l{lvl}_ms"] = round(s.time_kernel(3, lvl, reps=20), 4)
+    log(f"[bench] kernels: {extra}")
+
+    x = xd.cpu().numpy()
+    out = {
+        "metric": "solves/s to rel-res 1e-8",
+        "value": round(value, 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * el / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == nnms.FP64 else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"jittered unit cube, 3 non-nested levels 48^3/24^3/10^3 "
+                               f"(117649 fine vertices, 663552 tets), log-Gaussian kappa (8 centres), "
+                               f"64+8 subdomains overlap 1, FGMRES(30) to 1e-8, {args.precision}",
+                   "iterations": info.iterations, "relres": info.relres,
+                   "numeric_setup_s": round(t_assemble, 4), "structure_setup_s": round(t1 - t0, 3)},
+        "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_ras (fine-level smoother)", "ms": round(ms, 4)},
+        "kernels": extra,
+    }
+    if not args.no_cpu_baseline:
+        cb, oh, ores = cpu_baseline(pb)
+        out["cpu_baseline"] = cb
+        from oracle import problem as oprob  # the oracle's own x* for the error report
+        xs = ores.x
+        out["config"]["rel_err_vs_oracle_fgmres"] = float(np.linalg.norm(x - xs) / np.linalg.norm(xs))
+        out["config"]["oracle_iterations"] = ores.iterations
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,302 @@
+/*
+ * nnms.h -- C ABI of the non-nested multilevel smoothed Schwarz solver.
+ *
+ * Method: C. Ma, "A non-nested unstructured mesh perspective on highly
+ * parallel multilevel smoothed Schwarz preconditioner for linear parametric
+ * PDEs" (arXiv 2412.08981).  The library solves the P1 discretisation of
+ * -div(kappa grad u) = f on a tetrahedral mesh with homogeneous Dirichlet
+ * data (Section 2.1, equation 'discretized'), right-preconditioned
+ * (equation 'right-preconditioned') by the V-cycle of Algorithm 2
+ * (Section 3.3): on every level but the coarsest, a restricted additive
+ * Schwarz smoother (Section 2.2) over overlapping subdomains with exact
+ * dense subdomain LU solves; between independently meshed (non-nested)
+ * levels, barycentric interpolation P_l (a fine vertex located in a coarse
+ * tetrahedron) and its transpose; a direct solve on the coarsest level.  The
+ * outer Krylov method is flexible GMRES (Section 4 uses GMRES).
+ *
+ * Conventions shared by every call
+ *  - Every call returns nnms_status; no exception crosses the ABI.  After a
+ *    non-OK status, nnms_last_error() returns a thread-local message.
+ *  - Handles are owned by the library and released by the matching
+ *    *_destroy call.  Caller buffers are only accessed during the call; the
+ *    library keeps no caller pointer.
+ *  - Pointers named *_host are host memory; pointers documented as device
+ *    memory must be HIP device pointers on the handle's device.
+ *  - Device work is ordered on the hipStream_t passed as `stream` (NULL is
+ *    the null stream).  Calls that return results to the host synchronise
+ *    that stream before returning.
+ *  - A handle must not be used by two host threads at once; different
+ *    handles may.
+ *  - Indices are 0-based.  Vertex-indexed vectors have one entry per mesh
+ *    vertex; entries at Dirichlet vertices of right-hand sides are ignored
+ *    (treated as 0) and solutions are 0 there.
+ */
+#ifndef NNMS_H
+#define NNMS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NNMS_MAX_LEVELS 8
+#define NNMS_MAX_RESTART 64
+
+typedef enum {
+  NNMS_OK = 0,
+  NNMS_ERR_INVALID_ARG = 1,    /* a null pointer, a size out of range, a bad option */
+  NNMS_ERR_BAD_MESH = 2,       /* vertex index out of range or tetrahedron volume <= 0 */
+  NNMS_ERR_POINT_LOCATION = 3, /* a fine vertex lies outside the next coarser mesh */
+  NNMS_ERR_OUT_OF_MEMORY = 4,  /* host or device allocation failed */
+  NNMS_ERR_BUDGET = 5,         /* request exceeds the memory budget given to the call */
+  NNMS_ERR_SINGULAR = 6,       /* a non-positive or non-finite pivot in a factorisation */
+  NNMS_ERR_NOT_CONVERGED = 7,  /* iteration limit reached; x and info are still filled */
+  NNMS_ERR_DEVICE = 8,         /* a HIP runtime error */
+  NNMS_ERR_IN_USE = 9          /* the handle still has dependants (e.g. live systems) */
+} nnms_status;
+
+typedef enum { NNMS_FP64 = 0, NNMS_MIXED = 1 } nnms_precision;
+
+typedef struct nnms_mesh nnms_mesh;
+typedef struct nnms_hierarchy nnms_hierarchy;
+typedef struct nnms_system nnms_system;
+typedef struct nnms_batch nnms_batch;
+
+/* Device allocator supplied by the caller (e.g. a framework's caching
+ * allocator).  alloc returns a device pointer aligned to 256 bytes or NULL;
+ * free releases it.  When no allocator is given the library calls hipMalloc
+ * and hipFree. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* ctx);
+  void (*free)(void* ptr, void* ctx);
+  void* ctx;
+} nnms_allocator;
+
+const char* nnms_last_error(void);
+/* Bytes of device memory currently held by the library (all handles). */
+int64_t nnms_device_bytes_in_use(void);
+
+/* ---------------------------------------------------------------------------
+ * Meshes (Section 2.1: the mesh perspective M = (K, N) with one unknown per
+ * vertex, N = (1, 0, 0, 0)).
+ *
+ * xyz_host        nv*3 doubles, vertex coordinates (x, y, z per vertex).
+ * tets_host       nt*4 int32 vertex ids; every tetrahedron must have a
+ *                 positive signed volume det[x1-x0, x2-x0, x3-x0] / 6.
+ * dirichlet_host  nv bytes, nonzero marks a homogeneous Dirichlet vertex;
+ *                 NULL marks the vertices lying on the faces of the
+ *                 bounding box (coordinate equal to the min or max).
+ * Errors: NNMS_ERR_INVALID_ARG (nv < 4, nt < 1, null pointers),
+ *         NNMS_ERR_BAD_MESH (index out of range, volume <= 0).
+ * ------------------------------------------------------------------------- */
+nnms_status nnms_mesh_create(int64_t nv, const double* xyz_host, int64_t nt, const int32_t* tets_host,
+                             const uint8_t* dirichlet_host, nnms_mesh** out);
+void nnms_mesh_destroy(nnms_mesh* m);
+
+/* ---------------------------------------------------------------------------
+ * setup(hierarchy): everything that depends on the meshes only and is reused
+ * across parameters (Section 1 and Section 2.1: the mesh perspective is a
+ * reusable object; the hierarchy M_0..M_{L-1} of Algorithm 2).
+ *
+ * Per smoothed level l < L-1: the CSR pattern of the vertex graph (Dirichlet
+ * rows hold only their diagonal, Dirichlet columns are dropped from the
+ * other rows), a partition of the interior vertices into nparts[l] owned
+ * sets by recursive coordinate bisection and their extension by `overlap`
+ * layers (Section 2.2), and the barycentric interpolation P_l from level
+ * l+1 to level l with its transpose.  The coarsest level gets one dense
+ * "subdomain" holding all of its interior vertices (the direct solve).
+ *
+ * levels      L mesh handles, finest first (1 <= L <= NNMS_MAX_LEVELS).
+ * opts        nparts[l]: power of two >= 1 for l < L-1 (0 selects
+ *             max(2, 2^floor(log2(nv_l/1500))));  overlap >= 0;  its >= 1;
+ *             precision NNMS_FP64 or NNMS_MIXED.
+ * alloc       device allocator or NULL (hipMalloc).
+ * stream      stream for the uploads.
+ * Errors: NNMS_ERR_INVALID_ARG, NNMS_ERR_POINT_LOCATION,
+ *         NNMS_ERR_OUT_OF_MEMORY, NNMS_ERR_DEVICE.
+ * nnms_hierarchy_setup_host builds the same structure without touching any
+ * GPU (inspection and host tests); such a handle cannot be assembled.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t nparts[NNMS_MAX_LEVELS];
+  int32_t overlap;
+  int32_t its;
+  int32_t precision;
+  int32_t reserved;
+} nnms_setup_opts;
+
+nnms_status nnms_setup_opts_default(nnms_setup_opts* o);
+nnms_status nnms_hierarchy_setup(const nnms_mesh* const* levels, int32_t L, const nnms_setup_opts* opts,
+                                 const nnms_allocator* alloc, void* stream, nnms_hierarchy** out);
+nnms_status nnms_hierarchy_setup_host(const nnms_mesh* const* levels, int32_t L, const nnms_setup_opts* opts,
+                                      nnms_hierarchy** out);
+/* NNMS_ERR_IN_USE while systems assembled on it are alive. */
+nnms_status nnms_hierarchy_destroy(nnms_hierarchy* h);
+
+typedef struct {
+  int64_t nv;           /* vertices */
+  int64_t nt;           /* tetrahedra */
+  int64_t ninterior;    /* non-Dirichlet vertices */
+  int64_t nnz;          /* CSR entries of the level operator */
+  int32_t nparts;       /* subdomains (1 on the coarsest level) */
+  int32_t max_block;    /* largest subdomain size */
+  int32_t min_block;    /* smallest subdomain size */
+  int32_t reserved;
+  int64_t s_total;      /* sum of subdomain sizes */
+  int64_t factor_elems; /* dense factor entries stored, incl. 64-padding */
+  int64_t p_nnz;        /* entries of P_l^T (0 on the coarsest level) */
+} nnms_level_info;
+
+nnms_status nnms_hierarchy_level_info(const nnms_hierarchy* h, int32_t level, nnms_level_info* out);
+/* CSR pattern of level `level`: row_ptr_host[nv+1], col_host[nnz]. */
+nnms_status nnms_hierarchy_csr(const nnms_hierarchy* h, int32_t level, int32_t* row_ptr_host, int32_t* col_host);
+/* Owner of every vertex (-1 for Dirichlet), and the overlapping sets S_p in
+ * ascending vertex order: s_ptr_host[nparts+1], s_idx_host[s_total]. */
+nnms_status nnms_hierarchy_partition(const nnms_hierarchy* h, int32_t level, int32_t* owner_host,
+                                     int64_t* s_ptr_host, int32_t* s_idx_host);
+/* P_level as 4 entries per fine vertex: idx_host[nv*4] coarse vertex ids,
+ * w_host[nv*4] barycentric weights (0 for Dirichlet rows and columns). */
+nnms_status nnms_hierarchy_transfer(const nnms_hierarchy* h, int32_t level, int32_t* idx_host, double* w_host);
+
+/* ---------------------------------------------------------------------------
+ * assemble(mesh, kappa): numeric setup for one parameter.  On the device:
+ * kappa at every tetrahedron's centroid, P1 stiffness of every level
+ * (coarse levels rediscretised, as Algorithm 2 provides the Jacobian of
+ * every level), the load vector of a constant f on the finest level,
+ * extraction of the dense overlapping subdomain matrices
+ * J_p = R_p J R_p^T (Section 2.2) and their LU factorisation without
+ * pivoting (the matrices are SPD), plus the coarsest dense FP64 LU.
+ *
+ * kappa: kind 0 = constant `value` (> 0);  kind 1 = log-Gaussian,
+ *        log kappa(x) = sum_k mu[k] exp(-|x - centres[k]|^2 / width),
+ *        ncentres <= 64, width > 0 (host arrays).
+ * f:     constant source term of the load vector.
+ * Errors: NNMS_ERR_INVALID_ARG, NNMS_ERR_SINGULAR, NNMS_ERR_OUT_OF_MEMORY,
+ *         NNMS_ERR_DEVICE.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t kind;
+  int32_t ncentres;
+  double value;
+  const double* centres; /* ncentres*3 */
+  const double* mu;      /* ncentres */
+  double width;
+} nnms_kappa;
+
+nnms_status nnms_assemble(nnms_hierarchy* h, const nnms_kappa* kappa, double f, void* stream, nnms_system** out);
+nnms_status nnms_system_destroy(nnms_system* s);
+/* Device bytes held by one assembled system (values, factors, workspace). */
+int64_t nnms_system_device_bytes(const nnms_system* s);
+/* Device bytes an assembly of h would take (for admission decisions). */
+int64_t nnms_hierarchy_system_bytes(const nnms_hierarchy* h, int32_t restart);
+
+/* Read-back for checks: the load vector (nv_0 doubles) and the FP64 CSR
+ * values of a level (nnz doubles, order of nnms_hierarchy_csr). */
+nnms_status nnms_system_rhs(const nnms_system* s, double* b_host);
+nnms_status nnms_system_matrix(const nnms_system* s, int32_t level, double* val_host);
+
+/* Read-back of the stored dense factor of subdomain `part` of `level` (the
+ * coarsest level has one part), for checks.  The subdomain is padded to N
+ * tiles of 64 per side.  lu_host (may be NULL) receives the (N*64)^2 tile
+ * grid row-major as stored: L_ij below the diagonal tiles, U_ij above them,
+ * inv(U_ii) in the diagonal tiles.  invl_host (may be NULL) receives the N
+ * tiles inv(L_ii), each 64x64 row-major.  *N_host receives N. */
+nnms_status nnms_system_factor(const nnms_system* s, int32_t level, int32_t part, double* lu_host, double* invl_host,
+                               int32_t* N_host);
+
+/* ---------------------------------------------------------------------------
+ * Operator applications, one call each, host vectors in and out (FP64 at
+ * the boundary; the level's working precision inside):
+ *   nnms_apply_operator   y = A_l x                        (Section 2.1)
+ *   nnms_apply_smoother   z = B_l^{-1} r, restricted additive Schwarz
+ *                         (Section 2.2); on the coarsest level the direct
+ *                         solve A_{L-1}^{-1} r
+ *   nnms_apply_prolong    z_l = P_l z_{l+1}   (level = l, x has nv_{l+1})
+ *   nnms_apply_restrict   r_{l+1} = P_l^T r_l
+ *   nnms_apply_vcycle     z = M r, one V-cycle of Algorithm 2
+ * ------------------------------------------------------------------------- */
+nnms_status nnms_apply_operator(nnms_system* s, int32_t level, const double* x_host, double* y_host, void* stream);
+nnms_status nnms_apply_smoother(nnms_system* s, int32_t level, const double* r_host, double* z_host, void* stream);
+nnms_status nnms_apply_prolong(nnms_system* s, int32_t level, const double* x_host, double* y_host, void* stream);
+nnms_status nnms_apply_restrict(nnms_system* s, int32_t level, const double* x_host, double* y_host, void* stream);
+nnms_status nnms_apply_vcycle(nnms_system* s, const double* r_host, double* z_host, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Measurement: run one kernel of the solve path `reps` times back to back on
+ * the stream it is launched on, bracketed by HIP events, on the system's
+ * current level vectors; *ms_host receives the mean milliseconds per
+ * launch.  kind: 0 smoother (restricted additive Schwarz apply, or the
+ * coarsest direct solve), 1 level operator residual t = r - A z,
+ * 2 prolongation, 3 restriction.  reps >= 1.
+ * ------------------------------------------------------------------------- */
+nnms_status nnms_time_kernel(nnms_system* s, int32_t kind, int32_t level, int32_t reps, double* ms_host);
+
+/* ---------------------------------------------------------------------------
+ * solve(b) -> x, iterations: right-preconditioned flexible GMRES(restart)
+ * with classical Gram-Schmidt applied twice, x0 = 0, stopping when the true
+ * residual satisfies ||b - A x||_2 <= rtol ||b||_2 (checked at the end of
+ * every cycle).  iterations counts Arnoldi steps over all cycles.
+ *
+ * b, x: nv_0 doubles, host memory unless flags & NNMS_DEVICE_PTRS.
+ * restart in [1, NNMS_MAX_RESTART]; rtol > 0; max_it >= 1.
+ * ||b|| = 0 gives x = 0 and iterations = 0.
+ * NNMS_ERR_NOT_CONVERGED: max_it reached; x holds the last iterate and info
+ * is filled.
+ * ------------------------------------------------------------------------- */
+#define NNMS_DEVICE_PTRS 1
+#define NNMS_NO_GRAPH 2
+
+typedef struct {
+  int32_t restart;
+  int32_t max_it;
+  double rtol;
+  int32_t flags;
+  int32_t reserved;
+} nnms_solve_opts;
+
+typedef struct {
+  int32_t iterations;
+  int32_t cycles;
+  int32_t status;   /* nnms_status of this right-hand side */
+  int32_t reserved;
+  double relres;    /* true ||b - A x|| / ||b|| at the end */
+} nnms_solve_info;
+
+nnms_status nnms_solve_opts_default(nnms_solve_opts* o);
+nnms_status nnms_solve(nnms_system* s, const double* b, double* x, const nnms_solve_opts* opts,
+                       nnms_solve_info* info, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Batched solves: several assembled systems (any mix of hierarchies with
+ * the same number of levels and precision) advance together, one Arnoldi
+ * step per launch sequence, each with its own Krylov basis, rotations and
+ * convergence test; a finished system is masked out while the others go
+ * on.  Each system's arithmetic is independent of its batch neighbours, so
+ * its result is the same alone and in any batch.
+ *
+ * nnms_batch_create   bind systems to the slots of a batch (nb >= 1).
+ * nnms_batch_start    begin solving in `slot` with right-hand side b
+ *                     (device pointer, nv_0 doubles; copied).
+ * nnms_batch_step     run up to `iterations` Arnoldi steps on every active
+ *                     slot (replayed from a captured HIP graph unless
+ *                     NNMS_NO_GRAPH); *active_host receives the number of
+ *                     slots still iterating.
+ * nnms_batch_result   copy slot's solution to x (device pointer) and info.
+ * ------------------------------------------------------------------------- */
+nnms_status nnms_batch_create(nnms_system* const* systems, int32_t nb, const nnms_solve_opts* opts, void* stream,
+                              nnms_batch** out);
+nnms_status nnms_batch_start(nnms_batch* bt, int32_t slot, const double* b_device);
+nnms_status nnms_batch_step(nnms_batch* bt, int32_t iterations, int32_t* active_host);
+nnms_status nnms_batch_result(nnms_batch* bt, int32_t slot, double* x_device, nnms_solve_info* info);
+nnms_status nnms_batch_destroy(nnms_batch* bt);
+
+/* All-in-one batched solve (host or device vectors per opts->flags). */
+nnms_status nnms_solve_batch(nnms_system* const* systems, int32_t nb, const double* const* b, double* const* x,
+                             const nnms_solve_opts* opts, nnms_solve_info* infos, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NNMS_H */

@@ -1,0 +1,1235 @@
+// Driver and C ABI of the nnms library: device upload of a hierarchy,
+// numeric setup per parameter (assembly, extraction, batched LU), batched
+// solve plans (descriptor tables, triangular-solve task order, a HIP graph
+// of one Arnoldi step) and the single-operation entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "devtypes.h"
+#include "kernels.h"
+#include "nnms_internal.h"
+
+namespace nnms {
+
+static thread_local std::string g_last_error;
+void set_last_error(const std::string& m) { g_last_error = m; }
+static std::atomic<int64_t> g_bytes{0};
+
+#define HIP_CHECK(x)                                                                                 \
+  do {                                                                                               \
+    hipError_t e_ = (x);                                                                             \
+    if (e_ != hipSuccess) throw Error(NNMS_ERR_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// device memory: the caller's allocator or hipMalloc; freed together
+// ---------------------------------------------------------------------------
+struct Arena {
+  nnms_allocator a{};
+  bool has = false;
+  std::vector<std::pair<void*, size_t>> bufs;
+  size_t total = 0;
+  Arena() = default;
+  explicit Arena(const nnms_allocator* al) {
+    if (al && al->alloc && al->free) a = *al, has = true;
+  }
+  Arena(const Arena&) = delete;
+  Arena& operator=(const Arena&) = delete;
+  void* raw(size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    bytes = (bytes + 255) & ~size_t(255);
+    void* p = nullptr;
+    if (has) {
+      p = a.alloc(bytes, a.ctx);
+      if (!p) throw Error(NNMS_ERR_OUT_OF_MEMORY, "device allocator returned null for " + std::to_string(bytes) + " bytes");
+    } else {
+      hipError_t e = hipMalloc(&p, bytes);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error(NNMS_ERR_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+      }
+    }
+    bufs.emplace_back(p, bytes);
+    total += bytes;
+    g_bytes += int64_t(bytes);
+    return p;
+  }
+  template <typename T>
+  T* alloc(size_t n, hipStream_t s, bool zero = true) {
+    T* p = (T*)raw(n * sizeof(T));
+    if (zero) HIP_CHECK(hipMemsetAsync(p, 0, std::max<size_t>(n * sizeof(T), 1), s));
+    return p;
+  }
+  template <typename T>
+  T* upload(const std::vector<T>& v, hipStream_t s) {
+    T* p = (T*)raw(v.size() * sizeof(T));
+    if (!v.empty()) HIP_CHECK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    return p;
+  }
+  void release() {
+    for (auto& b : bufs) {
+      if (has)
+        a.free(b.first, a.ctx);
+      else
+        (void)hipFree(b.first);
+      g_bytes -= int64_t(b.second);
+    }
+    bufs.clear();
+    total = 0;
+  }
+  ~Arena() { release(); }
+};
+
+struct DevLevel {
+  int32_t *rp = nullptr, *col = nullptr, *cptr = nullptr, *citem = nullptr, *vptr = nullptr, *vitem = nullptr,
+          *tets = nullptr;
+  double* xyz = nullptr;
+  uint8_t* dmask = nullptr;
+  int32_t *gidx = nullptr, *ext_rs = nullptr, *ext_lc = nullptr;
+  int32_t* p_idx = nullptr;
+  double* p_w64 = nullptr;
+  float* p_w32 = nullptr;
+  int32_t *pt_rp = nullptr, *pt_col = nullptr;
+  double* pt_w64 = nullptr;
+  float* pt_w32 = nullptr;
+};
+
+}  // namespace nnms
+
+using namespace nnms;
+
+struct nnms_hierarchy {
+  HostHierarchy host;
+  bool on_device = false;
+  std::unique_ptr<Arena> mem;
+  std::vector<DevLevel> dev;
+  std::atomic<int> systems{0};
+  nnms_allocator alloc{};
+  bool has_alloc = false;
+};
+
+namespace nnms {
+
+struct SysLevel {
+  double* val64 = nullptr;
+  float* val32 = nullptr;
+  void* fac = nullptr;  // factor tiles (float in mixed smoothed levels, else double)
+  void* yx = nullptr;   // triangular-solve workspace (factor type)
+  void* r = nullptr;    // level vectors, working precision
+  void* z = nullptr;
+  void* t = nullptr;
+};
+
+struct Plan;
+
+}  // namespace nnms
+
+struct nnms_system {
+  nnms_hierarchy* h = nullptr;
+  int prec = NNMS_FP64;
+  std::unique_ptr<Arena> mem;
+  std::vector<SysLevel> lev;
+  double* b0 = nullptr;  // assembled load vector
+  // solve workspace
+  double *V = nullptr, *Z = nullptr, *w = nullptr, *x = nullptr, *bw = nullptr;
+  double *part1 = nullptr, *part2 = nullptr, *partn = nullptr, *partr = nullptr;
+  KState* st = nullptr;
+  int restart_cap = 0;
+  int nblk = 0, nblkr = 0;
+  std::unique_ptr<Plan> solo;   // single-slot solve plan
+  std::unique_ptr<Plan> apply;  // stateless plan for single operator applications
+  hipStream_t stream = nullptr;
+  ~nnms_system();
+};
+
+namespace nnms {
+
+constexpr int SPMV_G_A = 16;   // lanes per row of the level operators
+constexpr int SPMV_G_PT = 32;  // lanes per row of P^T
+static int ras_grid_default() {
+  static int g = [] {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+      hipDeviceProp_t p;
+      if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
+    }
+    return cus * 4;
+  }();
+  return g;
+}
+
+static int spmv_blocks(int64_t n, int G) { return int((n + (256 / G) - 1) / (256 / G)); }
+static int vec_blocks(int64_t n) { return int((n + VBLK - 1) / VBLK); }
+
+// ---------------------------------------------------------------------------
+// a batch plan: descriptor tables for every launch of one Arnoldi step
+// ---------------------------------------------------------------------------
+struct LevelPlan {
+  SpmvDesc* res = nullptr;
+  int res_blocks = 0;
+  SpmvDesc* rst = nullptr;
+  int rst_blocks = 0;
+  ProlongDesc* pro = nullptr;
+  int pro_blocks = 0;
+  RasLaunch ras_r{}, ras_t{};  // input r_l (write) / t_l (add)
+  int nd = 0;
+};
+
+struct Plan {
+  std::vector<nnms_system*> sys;
+  int L = 0, prec = NNMS_FP64, its = 3;
+  bool with_state = true;
+  Arena mem;
+  std::vector<LevelPlan> lev;  // smoothed levels
+  RasLaunch coarse{};
+  int nd = 0;
+  KrylovDesc* kd = nullptr;
+  std::vector<KrylovDesc> kd_host;
+  int kblocks = 0;
+  SpmvDesc* wspmv = nullptr;
+  SpmvDesc* rspmv = nullptr;
+  int wblocks = 0;
+  int* d_active = nullptr;
+  int* h_active = nullptr;
+  hipStream_t stream = nullptr;
+  hipGraphExec_t graph = nullptr;
+  bool use_graph = true;
+  std::vector<int32_t*> counters;
+  Plan() = default;
+  ~Plan() {
+    if (graph) (void)hipGraphExecDestroy(graph);
+    if (h_active) (void)hipHostFree(h_active);
+    if (stream) (void)hipStreamDestroy(stream);
+  }
+};
+
+template <typename T>
+static const void* val_of(const SysLevel& sl) {
+  if (std::is_same<T, float>::value) return sl.val32;
+  return sl.val64;
+}
+
+// task list of one restricted additive Schwarz launch over subdomains with
+// N[q] blocks: forward block i at step i, backward block i at step 2N-1-i,
+// ordered by (step, subdomain) so that every dependency has a lower ticket.
+static std::vector<int32_t> ras_tasks(const std::vector<int32_t>& N) {
+  struct T3 {
+    int step, sub, code;
+  };
+  std::vector<T3> v;
+  for (size_t q = 0; q < N.size(); ++q)
+    for (int i = 0; i < N[q]; ++i) {
+      v.push_back({i, int(q), int((q << 16) | i)});
+      v.push_back({2 * N[q] - 1 - i, int(q), int((q << 16) | (1 << 15) | i)});
+    }
+  std::sort(v.begin(), v.end(), [](const T3& a, const T3& b) { return a.step != b.step ? a.step < b.step : a.sub < b.sub; });
+  std::vector<int32_t> out(v.size());
+  for (size_t k = 0; k < v.size(); ++k) out[k] = v[k].code;
+  return out;
+}
+
+template <typename T>
+static void build_plan(Plan& P, const std::vector<nnms_system*>& sys, bool with_state, hipStream_t s) {
+  P.sys = sys;
+  P.with_state = with_state;
+  nnms_hierarchy* h0 = sys[0]->h;
+  P.L = h0->host.L;
+  P.prec = sys[0]->prec;
+  P.its = h0->host.opts.its;
+  const int L = P.L;
+  P.nd = int(sys.size());
+  if (sys.size() > 32767) throw Error(NNMS_ERR_INVALID_ARG, "too many systems in one batch");
+  for (auto* x : sys)
+    if (x->h->host.L != L || x->prec != P.prec || x->h->host.opts.its != P.its)
+      throw Error(NNMS_ERR_INVALID_ARG, "batched systems must share level count, precision and smoothing steps");
+  P.lev.resize(std::max(0, L - 1));
+  auto make_ras = [&](int l, bool coarse, std::vector<SubDesc>& subs_r, std::vector<SubDesc>& subs_t,
+                      std::vector<int32_t>& Ns) {
+    int flag = 0;
+    for (auto* x : sys) {
+      const HostLevel& hl = x->h->host.lev[l];
+      const DevLevel& dl = x->h->dev[l];
+      const SysLevel& sl = x->lev[l];
+      const size_t fsz = (coarse || P.prec == NNMS_FP64) ? sizeof(double) : sizeof(float);
+      for (int p = 0; p < hl.nparts; ++p) {
+        SubDesc d{};
+        d.fac = (const char*)sl.fac + size_t(hl.fac_off[p]) * fsz;
+        d.gidx = dl.gidx + hl.g_off[p];
+        d.yx = (char*)sl.yx + size_t(hl.g_off[p]) * fsz;
+        d.rin = sl.r;
+        d.zout = sl.z;
+        d.st = with_state ? x->st : nullptr;
+        d.N = hl.nblk[p];
+        d.flag0 = flag;
+        flag += 2 * hl.nblk[p];
+        subs_r.push_back(d);
+        d.rin = sl.t;
+        subs_t.push_back(d);
+        Ns.push_back(hl.nblk[p]);
+      }
+    }
+    if (subs_r.size() > 32767) throw Error(NNMS_ERR_INVALID_ARG, "too many subdomains in one batch");
+    return flag;
+  };
+  auto finish_ras = [&](RasLaunch& rr, RasLaunch& rt, const std::vector<SubDesc>& subs_r,
+                        const std::vector<SubDesc>& subs_t, const std::vector<int32_t>& Ns, int nflags) {
+    std::vector<int32_t> tasks = ras_tasks(Ns);
+    int32_t* flags = P.mem.alloc<int32_t>(std::max(nflags, 1), s);
+    int32_t* counter = P.mem.alloc<int32_t>(4, s);
+    P.counters.push_back(counter);
+    rr.subs = P.mem.upload(subs_r, s);
+    rr.tasks = P.mem.upload(tasks, s);
+    rr.flags = flags;
+    rr.counter = counter;
+    rr.ntasks = int(tasks.size());
+    rr.add = 0;
+    rt = rr;
+    rt.subs = P.mem.upload(subs_t, s);
+    rt.add = 1;
+  };
+  for (int l = 0; l < L - 1; ++l) {
+    LevelPlan& LP = P.lev[l];
+    std::vector<SpmvDesc> res, rst;
+    std::vector<ProlongDesc> pro;
+    int br = 0, bt = 0, bp = 0;
+    for (auto* x : sys) {
+      const HostLevel& hl = x->h->host.lev[l];
+      const HostLevel& hc = x->h->host.lev[l + 1];
+      const DevLevel& dl = x->h->dev[l];
+      const SysLevel& sl = x->lev[l];
+      const SysLevel& sc = x->lev[l + 1];
+      const KState* st = with_state ? x->st : nullptr;
+      SpmvDesc d{};
+      d.rp = dl.rp, d.col = dl.col, d.val = val_of<T>(sl), d.x = sl.z, d.r = sl.r, d.y = sl.t;
+      d.st = st, d.n = int(hl.nv), d.blk0 = br, d.when = WHEN_RUNNING;
+      res.push_back(d);
+      br += spmv_blocks(hl.nv, SPMV_G_A);
+      SpmvDesc e{};
+      e.rp = dl.pt_rp, e.col = dl.pt_col;
+      e.val = std::is_same<T, float>::value ? (const void*)dl.pt_w32 : (const void*)dl.pt_w64;
+      e.x = sl.t, e.r = nullptr, e.y = sc.r, e.st = st, e.n = int(hc.nv), e.blk0 = bt, e.when = WHEN_RUNNING;
+      rst.push_back(e);
+      bt += spmv_blocks(hc.nv, SPMV_G_PT);
+      ProlongDesc pd{};
+      pd.idx = dl.p_idx;
+      pd.w = std::is_same<T, float>::value ? (const void*)dl.p_w32 : (const void*)dl.p_w64;
+      pd.zc = sc.z, pd.zf = sl.z, pd.st = st, pd.n = int(hl.nv), pd.blk0 = bp;
+      pro.push_back(pd);
+      bp += int((hl.nv + 255) / 256);
+    }
+    LP.res = P.mem.upload(res, s), LP.res_blocks = br;
+    LP.rst = P.mem.upload(rst, s), LP.rst_blocks = bt;
+    LP.pro = P.mem.upload(pro, s), LP.pro_blocks = bp;
+    LP.nd = int(sys.size());
+    std::vector<SubDesc> sr, stt;
+    std::vector<int32_t> Ns;
+    int nflags = make_ras(l, false, sr, stt, Ns);
+    finish_ras(LP.ras_r, LP.ras_t, sr, stt, Ns, nflags);
+  }
+  {
+    std::vector<SubDesc> sr, stt;
+    std::vector<int32_t> Ns;
+    int nflags = make_ras(L - 1, true, sr, stt, Ns);
+    RasLaunch dummy{};
+    finish_ras(P.coarse, dummy, sr, stt, Ns, nflags);
+  }
+  // Krylov descriptors
+  if (with_state) {
+    std::vector<SpmvDesc> wd, rd;
+    int kb = 0, wb = 0;
+    for (auto* x : sys) {
+      const HostLevel& h0l = x->h->host.lev[0];
+      const DevLevel& d0 = x->h->dev[0];
+      KrylovDesc k{};
+      k.V = x->V, k.Z = x->Z, k.w = x->w, k.x = x->x, k.b = x->bw, k.dmask = d0.dmask;
+      k.part1 = x->part1, k.part2 = x->part2, k.partn = x->partn, k.partr = x->partr, k.st = x->st;
+      k.r0 = x->lev[0].r, k.z0 = x->lev[0].z;
+      k.n = int(h0l.nv), k.blk0 = kb, k.nblk = x->nblk, k.nblkr = x->nblkr;
+      P.kd_host.push_back(k);
+      kb += x->nblk;
+      SpmvDesc d{};
+      d.rp = d0.rp, d.col = d0.col, d.val = x->lev[0].val64, d.x = x->Z, d.x_jstride = h0l.nv, d.r = nullptr;
+      d.y = x->w, d.st = x->st, d.n = int(h0l.nv), d.blk0 = wb, d.when = WHEN_RUNNING;
+      wd.push_back(d);
+      d.x = x->x, d.x_jstride = 0, d.r = x->bw, d.nrm = x->partr, d.when = WHEN_CYCLE_END;
+      rd.push_back(d);
+      wb += spmv_blocks(h0l.nv, SPMV_G_A);
+    }
+    P.kd = P.mem.upload(P.kd_host, s);
+    P.kblocks = kb;
+    P.wspmv = P.mem.upload(wd, s);
+    P.rspmv = P.mem.upload(rd, s);
+    P.wblocks = wb;
+    P.d_active = P.mem.alloc<int>(1, s);
+    HIP_CHECK(hipHostMalloc((void**)&P.h_active, sizeof(int), hipHostMallocDefault));
+  }
+  HIP_CHECK(hipStreamSynchronize(s));
+}
+
+static void check_counters(Plan& P, hipStream_t s) {
+  for (int32_t* c : P.counters) {
+    int32_t v[4];
+    HIP_CHECK(hipMemcpyAsync(v, c, sizeof v, hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    if (v[2]) throw Error(NNMS_ERR_DEVICE, "triangular-solve wait limit exceeded (error bits " + std::to_string(v[2]) + ")");
+  }
+}
+
+template <typename T>
+static void enqueue_vcycle(Plan& P, hipStream_t s) {
+  const int L = P.L, its = P.its, grid = ras_grid_default();
+  for (int l = 0; l < L - 1; ++l) {
+    LevelPlan& LP = P.lev[l];
+    HIP_CHECK((launch_ras<T, T>(LP.ras_r, grid, s)));
+    for (int k = 1; k < its; ++k) {
+      HIP_CHECK(launch_spmv<T>(LP.res, LP.nd, LP.res_blocks, SPMV_G_A, s));
+      HIP_CHECK((launch_ras<T, T>(LP.ras_t, grid, s)));
+    }
+    HIP_CHECK(launch_spmv<T>(LP.res, LP.nd, LP.res_blocks, SPMV_G_A, s));
+    HIP_CHECK(launch_spmv<T>(LP.rst, LP.nd, LP.rst_blocks, SPMV_G_PT, s));
+  }
+  HIP_CHECK((launch_ras<double, T>(P.coarse, grid, s)));
+  for (int l = L - 2; l >= 0; --l) {
+    LevelPlan& LP = P.lev[l];
+    HIP_CHECK(launch_prolong<T>(LP.pro, LP.nd, LP.pro_blocks, s));
+    for (int k = 0; k < its; ++k) {
+      HIP_CHECK(launch_spmv<T>(LP.res, LP.nd, LP.res_blocks, SPMV_G_A, s));
+      HIP_CHECK((launch_ras<T, T>(LP.ras_t, grid, s)));
+    }
+  }
+}
+
+template <typename T>
+static void enqueue_step(Plan& P, hipStream_t s) {
+  HIP_CHECK(launch_krylov_cast_in<T>(P.kd, P.nd, P.kblocks, s));
+  enqueue_vcycle<T>(P, s);
+  HIP_CHECK(launch_krylov_cast_out<T>(P.kd, P.nd, P.kblocks, s));
+  HIP_CHECK(launch_spmv<double>(P.wspmv, P.nd, P.wblocks, SPMV_G_A, s));
+  HIP_CHECK(launch_krylov_dots1(P.kd, P.nd, P.kblocks, s));
+  HIP_CHECK(launch_krylov_upd1(P.kd, P.nd, P.kblocks, s));
+  HIP_CHECK(launch_krylov_upd2(P.kd, P.nd, P.kblocks, s));
+  HIP_CHECK(launch_krylov_givens(P.kd, P.nd, s));
+  HIP_CHECK(launch_krylov_normalize(P.kd, P.nd, P.kblocks, s));
+  HIP_CHECK(launch_krylov_xupd(P.kd, P.nd, P.kblocks, s));
+  HIP_CHECK(launch_spmv<double>(P.rspmv, P.nd, P.wblocks, SPMV_G_A, s));
+  HIP_CHECK(launch_krylov_cycle(P.kd, P.nd, s));
+}
+
+static void plan_step(Plan& P) {
+  hipStream_t s = P.stream;
+  if (P.use_graph) {
+    if (!P.graph) {
+      hipGraph_t g;
+      HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      try {
+        if (P.prec == NNMS_MIXED)
+          enqueue_step<float>(P, s);
+        else
+          enqueue_step<double>(P, s);
+      } catch (...) {
+        hipGraph_t junk;
+        (void)hipStreamEndCapture(s, &junk);
+        if (junk) (void)hipGraphDestroy(junk);
+        throw;
+      }
+      HIP_CHECK(hipStreamEndCapture(s, &g));
+      hipError_t e = hipGraphInstantiate(&P.graph, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      HIP_CHECK(e);
+    }
+    HIP_CHECK(hipGraphLaunch(P.graph, s));
+  } else {
+    if (P.prec == NNMS_MIXED)
+      enqueue_step<float>(P, s);
+    else
+      enqueue_step<double>(P, s);
+  }
+}
+
+static int plan_active(Plan& P) {
+  HIP_CHECK(launch_count_active(P.kd, P.nd, P.d_active, P.stream));
+  HIP_CHECK(hipMemcpyAsync(P.h_active, P.d_active, sizeof(int), hipMemcpyDeviceToHost, P.stream));
+  HIP_CHECK(hipStreamSynchronize(P.stream));
+  return *P.h_active;
+}
+
+static void plan_start_slot(Plan& P, int k, const double* b_dev, const nnms_solve_opts& o) {
+  nnms_system* x = P.sys[k];
+  const int64_t n = x->h->host.lev[0].nv;
+  if (b_dev != x->bw) HIP_CHECK(hipMemcpyAsync(x->bw, b_dev, n * sizeof(double), hipMemcpyDeviceToDevice, P.stream));
+  const KrylovDesc& kd = P.kd_host[k];
+  HIP_CHECK(launch_krylov_init_slot(P.kd, P.nd, kd.blk0, kd.nblk, P.stream));
+  HIP_CHECK(launch_krylov_start_slot(P.kd + k, o.rtol, o.restart, o.max_it, P.stream));
+}
+
+template <typename T>
+static std::unique_ptr<Plan> make_plan(const std::vector<nnms_system*>& sys, bool with_state) {
+  auto P = std::make_unique<Plan>();
+  HIP_CHECK(hipStreamCreateWithFlags(&P->stream, hipStreamNonBlocking));
+  build_plan<T>(*P, sys, with_state, P->stream);
+  return P;
+}
+
+static std::unique_ptr<Plan> make_plan_any(const std::vector<nnms_system*>& sys, bool with_state) {
+  if (sys[0]->prec == NNMS_MIXED) return make_plan<float>(sys, with_state);
+  return make_plan<double>(sys, with_state);
+}
+
+// order the plan's internal stream after the caller's stream
+static void join_in(hipStream_t user, hipStream_t inner) {
+  hipEvent_t ev;
+  HIP_CHECK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  HIP_CHECK(hipEventRecord(ev, user));
+  HIP_CHECK(hipStreamWaitEvent(inner, ev, 0));
+  (void)hipEventDestroy(ev);
+}
+
+static void validate_solve_opts(const nnms_solve_opts& o) {
+  if (o.restart < 1 || o.restart > NNMS_MAX_RESTART || !(o.rtol > 0) || o.max_it < 1)
+    throw Error(NNMS_ERR_INVALID_ARG, "bad solve options");
+}
+
+}  // namespace nnms
+
+nnms_system::~nnms_system() {
+  solo.reset();
+  apply.reset();
+  mem.reset();
+  if (h) h->systems--;
+}
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+#define ABI_BEGIN try {
+#define ABI_END                                      \
+  }                                                  \
+  catch (const nnms::Error& e) {                     \
+    nnms::set_last_error(e.what());                  \
+    return e.code;                                   \
+  }                                                  \
+  catch (const std::bad_alloc&) {                    \
+    nnms::set_last_error("host out of memory");      \
+    return NNMS_ERR_OUT_OF_MEMORY;                   \
+  }                                                  \
+  catch (const std::exception& e) {                  \
+    nnms::set_last_error(e.what());                  \
+    return NNMS_ERR_INVALID_ARG;                     \
+  }
+
+extern "C" const char* nnms_last_error(void) { return nnms::g_last_error.c_str(); }
+extern "C" int64_t nnms_device_bytes_in_use(void) { return nnms::g_bytes.load(); }
+
+static void build_host(const nnms_mesh* const* levels, int32_t L, const nnms_setup_opts* opts, HostHierarchy& H) {
+  if (!levels || L < 1 || L > NNMS_MAX_LEVELS || !opts) throw Error(NNMS_ERR_INVALID_ARG, "bad hierarchy arguments");
+  if (opts->overlap < 0 || opts->its < 1 || (opts->precision != NNMS_FP64 && opts->precision != NNMS_MIXED))
+    throw Error(NNMS_ERR_INVALID_ARG, "bad setup options");
+  H.L = L;
+  H.opts = *opts;
+  H.lev.resize(L);
+  for (int l = 0; l < L; ++l) {
+    if (!levels[l]) throw Error(NNMS_ERR_INVALID_ARG, "null mesh");
+    HostLevel& lv = H.lev[l];
+    lv.nv = levels[l]->nv, lv.nt = levels[l]->nt;
+    lv.xyz = levels[l]->xyz;
+    lv.tets = levels[l]->tets;
+    lv.dir = levels[l]->dir;
+    build_pattern(lv);
+    const bool direct = (l == L - 1);
+    int np = direct ? 1 : opts->nparts[l];
+    if (!direct && np == 0) np = default_nparts(lv.nv);
+    H.opts.nparts[l] = np;
+    build_partition(lv, np, opts->overlap, direct);
+  }
+  for (int l = 0; l + 1 < L; ++l) build_transfer(H.lev[l], H.lev[l + 1]);
+}
+
+extern "C" nnms_status nnms_hierarchy_setup_host(const nnms_mesh* const* levels, int32_t L, const nnms_setup_opts* opts,
+                                                 nnms_hierarchy** out) {
+  ABI_BEGIN
+  if (!out) throw Error(NNMS_ERR_INVALID_ARG, "null output");
+  *out = nullptr;
+  auto h = std::make_unique<nnms_hierarchy>();
+  build_host(levels, L, opts, h->host);
+  *out = h.release();
+  return NNMS_OK;
+  ABI_END
+}
+
+template <typename A, typename B>
+static std::vector<B> convert(const std::vector<A>& v) {
+  return std::vector<B>(v.begin(), v.end());
+}
+
+extern "C" nnms_status nnms_hierarchy_setup(const nnms_mesh* const* levels, int32_t L, const nnms_setup_opts* opts,
+                                            const nnms_allocator* alloc, void* stream, nnms_hierarchy** out) {
+  ABI_BEGIN
+  if (!out) throw Error(NNMS_ERR_INVALID_ARG, "null output");
+  *out = nullptr;
+  auto h = std::make_unique<nnms_hierarchy>();
+  build_host(levels, L, opts, h->host);
+  hipStream_t s = (hipStream_t)stream;
+  h->mem = std::make_unique<Arena>(alloc);
+  if (alloc && alloc->alloc && alloc->free) h->alloc = *alloc, h->has_alloc = true;
+  h->dev.resize(L);
+  Arena& A = *h->mem;
+  for (int l = 0; l < L; ++l) {
+    const HostLevel& hl = h->host.lev[l];
+    DevLevel& d = h->dev[l];
+    d.rp = A.upload(hl.rp, s);
+    d.col = A.upload(hl.col, s);
+    d.cptr = A.upload(hl.cptr, s);
+    d.citem = A.upload(hl.citem, s);
+    d.vptr = A.upload(hl.vptr, s);
+    d.vitem = A.upload(hl.vitem, s);
+    d.tets = A.upload(hl.tets, s);
+    d.xyz = A.upload(hl.xyz, s);
+    d.dmask = A.upload(hl.dir, s);
+    d.gidx = A.upload(hl.gidx, s);
+    d.ext_rs = A.upload(hl.ext_rs, s);
+    d.ext_lc = A.upload(hl.ext_lc, s);
+    if (l + 1 < L) {
+      d.p_idx = A.upload(hl.p_idx, s);
+      d.p_w64 = A.upload(hl.p_w, s);
+      d.p_w32 = A.upload(convert<double, float>(hl.p_w), s);
+      d.pt_rp = A.upload(hl.pt_rp, s);
+      d.pt_col = A.upload(hl.pt_col, s);
+      d.pt_w64 = A.upload(hl.pt_w, s);
+      d.pt_w32 = A.upload(convert<double, float>(hl.pt_w), s);
+    }
+  }
+  HIP_CHECK(hipStreamSynchronize(s));
+  h->on_device = true;
+  *out = h.release();
+  return NNMS_OK;
+  ABI_END
+}
+
+extern "C" nnms_status nnms_hierarchy_destroy(nnms_hierarchy* h) {
+  if (!h) return NNMS_OK;
+  if (h->systems.load() > 0) {
+    nnms::set_last_error("hierarchy still has live systems");
+    return NNMS_ERR_IN_USE;
+  }
+  delete h;
+  return NNMS_OK;
+}
+
+extern "C" nnms_status nnms_hierarchy_level_info(const nnms_hierarchy* h, int32_t level, nnms_level_info* o) {
+  ABI_BEGIN
+  if (!h || !o || level < 0 || level >= h->host.L) throw Error(NNMS_ERR_INVALID_ARG, "bad level");
+  const HostLevel& lv = h->host.lev[level];
+  std::memset(o, 0, sizeof *o);
+  o->nv = lv.nv, o->nt = lv.nt, o->ninterior = lv.nint, o->nnz = int64_t(lv.col.size());
+  o->nparts = lv.nparts;
+  int mx = 0, mn = INT32_MAX;
+  for (int p = 0; p < lv.nparts; ++p) {
+    int n = int(lv.s_ptr[p + 1] - lv.s_ptr[p]);
+    mx = std::max(mx, n), mn = std::min(mn, n);
+  }
+  o->max_block = mx, o->min_block = lv.nparts ? mn : 0;
+  o->s_total = int64_t(lv.s_idx.size());
+  o->factor_elems = lv.fac_elems;
+  o->p_nnz = int64_t(lv.pt_col.size());
+  return NNMS_OK;
+  ABI_END
+}
+
+extern "C" nnms_status nnms_hierarchy_csr(const nnms_hierarchy* h, int32_t level, int32_t* rp, int32_t* col) {
+  ABI_BEGIN
+  if (!h || !rp || !col || level < 0 || level >= h->host.L) throw Error(NNMS_ERR_INVALID_ARG, "bad arguments");
+  const HostLevel& lv = h->host.lev[level];
+  std::memcpy(rp, lv.rp.data(), lv.rp.size() * sizeof(int32_t));
+  std::memcpy(col, lv.col.data(), lv.col.size() * sizeof(int32_t));
+  return NNMS_OK;
+  ABI_END
+}
+
+extern "C" nnms_status nnms_hierarchy_partition(const nnms_hierarchy* h, int32_t level, int32_t* owner, int64_t* s_ptr,
+                                                int32_t* s_idx) {
+  ABI_BEGIN
+  if (!h || !owner || !s_ptr || !s_idx || level < 0 || level >= h->host.L) throw Error(NNMS_ERR_INVALID_ARG, "bad arguments");
+  const HostLevel& lv = h->host.lev[level];
+  std::memcpy(owner, lv.owner.data(), lv.owner.size() * sizeof(int32_t));
+  std::memcpy(s_ptr, lv.s_ptr.data(), lv.s_ptr.size() * sizeof(int64_t));
+  std::memcpy(s_idx, lv.s_idx.data(), lv.s_idx.size() * sizeof(int32_t));
+  return NNMS_OK;
+  ABI_END
+}
+
+extern "C" nnms_status nnms_hierarchy_transfer(const nnms_hierarchy* h, int32_t level, int32_t* idx, double* w) {
+  ABI_BEGIN
+  if (!h || !idx || !w || level < 0 || level + 1 >= h->host.L) throw Error(NNMS_ERR_INVALID_ARG, "bad arguments");
+  const HostLevel& lv = h->host.lev[level];
+  std::memcpy(idx, lv.p_idx.data(), lv.p_idx.size() * sizeof(int32_t));
+  std::memcpy(w, lv.p_w.data(), lv.p_w.size() * sizeof(double));
+  return NNMS_OK;
+  ABI_END
+}
+
+static int64_t system_bytes(const HostHierarchy& H, int prec, int restart) {
+  int64_t b = 0;
+  for (int l = 0; l < H.L; ++l) {
+    const HostLevel& lv = H.lev[l];
+    const bool coarse = (l == H.L - 1);
+    const int64_t f = (coarse || prec == NNMS_FP64) ? 8 : 4;
+    const int64_t t = prec == NNMS_FP64 ? 8 : 4;
+    b += int64_t(lv.col.size()) * 8 + (prec == NNMS_MIXED ? int64_t(lv.col.size()) * 4 : 0);
+    b += lv.fac_elems * f + lv.g_total * f + 3 * lv.nv * t;
+  }
+  const int64_t n0 = H.lev[0].nv;
+  b += n0 * 8 * (2 * int64_t(restart) + 1 + 4);
+  const int64_t nb = (n0 + VBLK - 1) / VBLK;
+  b += nb * 8 * (2 * MMAX + 2) + ((n0 + 15) / 16) * 8 + int64_t(sizeof(KState));
+  return b;
+}
+
+extern "C" int64_t nnms_hierarchy_system_bytes(const nnms_hierarchy* h, int32_t restart) {
+  if (!h) return -1;
+  return system_bytes(h->host, h->host.opts.precision, restart > 0 ? restart : 30);
+}
+
+extern "C" nnms_status nnms_assemble(nnms_hierarchy* h, const nnms_kappa* k, double f, void* stream, nnms_system** out) {
+  ABI_BEGIN
+  if (!h || !k || !out) throw Error(NNMS_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  if (!h->on_device) throw Error(NNMS_ERR_INVALID_ARG, "hierarchy was set up without a device");
+  KappaDev kd{};
+  kd.kind = k->kind;
+  if (k->kind == 0) {
+    if (!(k->value > 0)) throw Error(NNMS_ERR_INVALID_ARG, "kappa must be positive");
+    kd.value = k->value;
+  } else if (k->kind == 1) {
+    if (k->ncentres < 0 || k->ncentres > MAXC || !(k->width > 0) || (k->ncentres && (!k->centres || !k->mu)))
+      throw Error(NNMS_ERR_INVALID_ARG, "bad log-Gaussian kappa");
+    kd.nc = k->ncentres, kd.width = k->width, kd.value = 1.0;
+    for (int c = 0; c < kd.nc; ++c) {
+      for (int a = 0; a < 3; ++a) kd.c[3 * c + a] = k->centres[3 * c + a];
+      kd.mu[c] = k->mu[c];
+    }
+  } else {
+    throw Error(NNMS_ERR_INVALID_ARG, "unknown kappa kind");
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const HostHierarchy& H = h->host;
+  const int L = H.L, prec = H.opts.precision;
+  auto sys = std::unique_ptr<nnms_system>(new nnms_system);
+  sys->h = h;
+  h->systems++;
+  sys->prec = prec;
+  sys->mem = std::make_unique<Arena>(h->has_alloc ? &h->alloc : nullptr);
+  Arena& A = *sys->mem;
+  sys->lev.resize(L);
+  const size_t tsz = prec == NNMS_FP64 ? 8 : 4;
+  int64_t max_nt = 0;
+  for (int l = 0; l < L; ++l) max_nt = std::max(max_nt, H.lev[l].nt);
+  Arena scratch(h->has_alloc ? &h->alloc : nullptr);
+  double* elem = scratch.alloc<double>(size_t(max_nt) * 17, s, false);
+  int* err = scratch.alloc<int>(1, s);
+  for (int l = 0; l < L; ++l) {
+    const HostLevel& hl = H.lev[l];
+    const DevLevel& dl = h->dev[l];
+    SysLevel& sl = sys->lev[l];
+    const bool coarse = (l == L - 1);
+    const size_t fsz = (coarse || prec == NNMS_FP64) ? 8 : 4;
+    sl.val64 = A.alloc<double>(hl.col.size(), s, false);
+    if (prec == NNMS_MIXED) sl.val32 = A.alloc<float>(hl.col.size(), s, false);
+    sl.fac = A.raw(std::max<size_t>(size_t(hl.fac_elems) * fsz, 256));
+    sl.yx = A.alloc<char>(size_t(hl.g_total) * fsz, s);
+    sl.r = A.alloc<char>(hl.nv * tsz, s);
+    sl.z = A.alloc<char>(hl.nv * tsz, s);
+    sl.t = A.alloc<char>(hl.nv * tsz, s);
+    AsmDesc ad{};
+    ad.xyz = dl.xyz, ad.tets = dl.tets, ad.cptr = dl.cptr, ad.citem = dl.citem, ad.rp = dl.rp;
+    ad.vptr = dl.vptr, ad.vitem = dl.vitem, ad.dmask = dl.dmask, ad.elem = elem;
+    ad.val64 = sl.val64, ad.val32 = sl.val32, ad.nt = hl.nt, ad.nv = hl.nv;
+    if (l == 0) {
+      sys->b0 = A.alloc<double>(hl.nv, s, false);
+      ad.b = sys->b0;
+    }
+    HIP_CHECK(launch_assemble(ad, kd, f, s));
+    // dense subdomain matrices and their factors
+    std::vector<FacDesc> fd;
+    int maxn = 0, maxN = 0;
+    for (int p = 0; p < hl.nparts; ++p) {
+      FacDesc d{};
+      d.fac = (char*)sl.fac + size_t(hl.fac_off[p]) * fsz;
+      d.gidx = dl.gidx + hl.g_off[p];
+      d.ext_rs = dl.ext_rs + hl.s_ptr[p];
+      d.ext_lc = dl.ext_lc;
+      d.rp = dl.rp;
+      d.val = sl.val64;
+      d.n = int(hl.s_ptr[p + 1] - hl.s_ptr[p]);
+      d.N = hl.nblk[p];
+      maxn = std::max(maxn, d.n), maxN = std::max(maxN, d.N);
+      fd.push_back(d);
+    }
+    FacDesc* dfd = scratch.upload(fd, s);
+    if (fsz == 8) {
+      HIP_CHECK(launch_fill<double>((double*)sl.fac, hl.fac_elems, 0.0, s));
+      HIP_CHECK(launch_extract<double>(dfd, int(fd.size()), maxn, s));
+      for (int kk = 0; kk < maxN; ++kk) HIP_CHECK(launch_lu_step<double>(dfd, int(fd.size()), kk, maxN, err, s));
+    } else {
+      HIP_CHECK(launch_fill<float>((float*)sl.fac, hl.fac_elems, 0.0f, s));
+      HIP_CHECK(launch_extract<float>(dfd, int(fd.size()), maxn, s));
+      for (int kk = 0; kk < maxN; ++kk) HIP_CHECK(launch_lu_step<float>(dfd, int(fd.size()), kk, maxN, err, s));
+    }
+  }
+  // solve workspace
+  const int64_t n0 = H.lev[0].nv;
+  const int m = NNMS_MAX_RESTART;
+  sys->restart_cap = m;
+  sys->nblk = vec_blocks(n0);
+  sys->nblkr = spmv_blocks(n0, SPMV_G_A);
+  sys->V = A.alloc<double>(size_t(n0) * (m + 1), s, false);
+  sys->Z = A.alloc<double>(size_t(n0) * m, s, false);
+  sys->w = A.alloc<double>(n0, s);
+  sys->x = A.alloc<double>(n0, s);
+  sys->bw = A.alloc<double>(n0, s);
+  sys->part1 = A.alloc<double>(size_t(sys->nblk) * (MMAX + 1), s);
+  sys->part2 = A.alloc<double>(size_t(sys->nblk) * MMAX, s);
+  sys->partn = A.alloc<double>(sys->nblk, s);
+  sys->partr = A.alloc<double>(sys->nblkr, s);
+  sys->st = (KState*)A.alloc<char>(sizeof(KState), s);
+  {
+    const int32_t idle = ST_IDLE;
+    HIP_CHECK(hipMemcpyAsync(&sys->st->status, &idle, sizeof idle, hipMemcpyHostToDevice, s));
+  }
+  int herr = 0;
+  HIP_CHECK(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  if (herr) throw Error(NNMS_ERR_SINGULAR, "non-positive pivot in a subdomain or coarse factorisation");
+  *out = sys.release();
+  return NNMS_OK;
+  ABI_END
+}
+
+extern "C" nnms_status nnms_system_destroy(nnms_system* s) {
+  delete s;
+  return NNMS_OK;
+}
+
+extern "C" int64_t nnms_system_device_bytes(const nnms_system* s) { return s && s->mem ? int64_t(s->mem->total) : 0; }
+
+extern "C" nnms_status nnms_system_rhs(const nnms_system* s, double* b) {
+  ABI_BEGIN
+  if (!s || !b) throw Error(NNMS_ERR_INVALID_ARG, "null argument");
+  HIP_CHECK(hipMemcpy(b, s->b0, s->h->host.lev[0].nv * sizeof(double), hipMemcpyDeviceToHost));
+  return NNMS_OK;
+  ABI_END
+}
+
+extern "C" nnms_status nnms_system_matrix(const nnms_system* s, int32_t level, double* val) {
+  ABI_BEGIN
+  if (!s || !val || level < 0 || level >= s->h->host.L) throw Error(NNMS_ERR_INVALID_ARG, "bad arguments");
+  HIP_CHECK(hipMemcpy(val, s->lev[level].val64, s->h->host.lev[level].col.size() * sizeof(double), hipMemcpyDeviceToHost));
+  return NNMS_OK;
+  ABI_END
+}
+
+// ---------------------------------------------------------------------------
+// single operator applications (host vectors, FP64 at the boundary)
+// ---------------------------------------------------------------------------
+static Plan& apply_plan(nnms_system* s) {
+  if (!s->apply) s->apply = make_plan_any({s}, false);
+  return *s->apply;
+}
+
+static void put_vec(nnms_system* s, void* dst, const double* src, int64_t n, hipStream_t st) {
+  if (s->prec == NNMS_FP64) {
+    HIP_CHECK(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyHostToDevice, st));
+  } else {
+    std::vector<float> tmp(src, src + n);
+    HIP_CHECK(hipMemcpyAsync(dst, tmp.data(), n * sizeof(float), hipMemcpyHostToDevice, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+  }
+}
+static void get_vec(nnms_system* s, double* dst, const void* src, int64_t n, hipStream_t st) {
+  if (s->prec == NNMS_FP64) {
+    HIP_CHECK(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+  } else {
+    std::vector<float> tmp(n);
+    HIP_CHECK(hipMemcpyAsync(tmp.data(), src, n * sizeof(float), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    for (int64_t i = 0; i < n; ++i) dst[i] = tmp[i];
+  }
+}
+static size_t tsize(const nnms_system* s) { return s->prec == NNMS_FP64 ? 8 : 4; }
+
+extern "C" nnms_status nnms_apply_operator(nnms_system* s, int32_t level, const double* x, double* y, void* stream) {
+  ABI_BEGIN
+  if (!s || !x || !y || level < 0 || level >= s->h->host.L) throw Error(NNMS_ERR_INVALID_ARG, "bad arguments");
+  Plan& P = apply_plan(s);
+  join_in((hipStream_t)stream, P.stream);
+  const int64_t n = s->h->host.lev[level].nv;
+  SysLevel& sl = s->lev[level];
+  const DevLevel& dl = s->h->dev[level];
+  put_vec(s, sl.z, x, n, P.stream);
+  SpmvDesc d{};
+  d.rp = dl.rp, d.col = dl.col, d.x = sl.z, d.y = sl.t, d.n = int(n), d.blk0 = 0, d.when = WHEN_RUNNING;
+  d.val = s->prec == NNMS_FP64 ? (const void*)sl.val64 : (const void*)sl.val32;
+  Arena tmp;
+  std::vector<SpmvDesc> v{d};
+  SpmvDesc* dd = tmp.upload(v, P.stream);
+  if (s->prec == NNMS_FP64)
+    HIP_CHECK(launch_spmv<double>(dd, 1, spmv_blocks(n, SPMV_G_A), SPMV_G_A, P.stream));
+  else
+    HIP_CHECK(launch_spmv<float>(dd, 1, spmv_blocks(n, SPMV_G_A), SPMV_G_A, P.stream));
+  get_vec(s, y, sl.t, n, P.stream);
+  return NNMS_OK;
+  ABI_END
+}
+
+extern "C" nnms_status nnms_apply_smoother(nnms_system* s, int32_t level, const double* r, double* z, void* stream) {
+  ABI_BEGIN
+  if (!s || !r || !z || level < 0 || level >= s->h->host.L) throw Error(NNMS_ERR_INVALID_ARG, "bad arguments");
+  Plan& P = apply_plan(s);
+  join_in((hipStream_t)stream, P.stream);
+  const int64_t n = s->h->host.lev[level].nv;
+  SysLevel& sl = s->lev[level];
+  put_vec(s, sl.r, r, n, P.stream);
+  HIP_CHECK(hipMemsetAsync(sl.z, 0, n * tsize(s), P.stream));
+  const int grid = ras_grid_default();
+  if (level == s->h->host.L - 1) {
+    if (s->prec == NNMS_FP64)
+      HIP_CHECK((launch_ras<double, double>(P.coarse, grid, P.stream)));
+    else
+      HIP_CHECK((launch_ras<double, float>(P.coarse, grid, P.stream)));
+  } else {
+    if (s->prec == NNMS_FP64)
+      HIP_CHECK((launch_ras<double, double>(P.lev[level].ras_r, grid, P.stream)));
+    else
+      HIP_CHECK((launch_ras<float, float>(P.lev[level].ras_r, grid, P.stream)));
+  }
+  get_vec(s, z, sl.z, n, P.stream);
+  check_counters(P, P.stream);
+  return NNMS_OK;
+  ABI_END
+}
+
+extern "C" nnms_status nnms_apply_prolong(nnms_system* s, int32_t level, const double* x, double* y, void* stream) {
+  ABI_BEGIN
+  if (!s || !x || !y || level < 0 || level + 1 >= s->h->host.L) throw Error(NNMS_ERR_INVALID_ARG, "bad arguments");
+  Plan& P = apply_plan(s);
+  join_in((hipStream_t)stream, P.stream);
+  const int64_t nf = s->h->host.lev[level].nv, nc = s->h->host.lev[level + 1].nv;
+  put_vec(s, s->lev[level + 1].z, x, nc, P.stream);
+  HIP_CHECK(hipMemsetAsync(s->lev[level].z, 0, nf * tsize(s), P.stream));
+  if (s->prec == NNMS_FP64)
+    HIP_CHECK(launch_prolong<double>(P.lev[level].pro, 1, P.lev[level].pro_blocks, P.stream));
+  else
+    HIP_CHECK(launch_prolong<float>(P.lev[level].pro, 1, P.lev[level].pro_blocks, P.stream));
+  get_vec(s, y, s->lev[level].z, nf, P.stream);
+  return NNMS_OK;
+  ABI_END
+}
+
+extern "C" nnms_status nnms_apply_restrict(nnms_system* s, int32_t level, const double* x, double* y, void* stream) {
+  ABI_BEGIN
+  if (!s || !x || !y || level < 0 || level + 1 >= s->h->host.L) throw Error(NNMS_ERR_INVALID_ARG, "bad arguments");
+  Plan& P = apply_plan(s);
+  join_in((hipStream_t)stream, P.stream);
+  const int64_t nf = s->h->host.lev[level].nv, nc = s->h->host.lev[level + 1].nv;
+  put_vec(s, s->lev[level].t, x, nf, P.stream);
+  if (s->prec == NNMS_FP64)
+    HIP_CHECK(launch_spmv<double>(P.lev[level].rst, 1, P.lev[level].rst_blocks, SPMV_G_PT, P.stream));
+  else
+    HIP_CHECK(launch_spmv<float>(P.lev[level].rst, 1, P.lev[level].rst_blocks, SPMV_G_PT, P.stream));
+  get_vec(s, y, s->lev[level + 1].r, nc, P.stream);
+  return NNMS_OK;
+  ABI_END
+}
+
+extern "C" nnms_status nnms_apply_vcycle(nnms_system* s, const double* r, double* z, void* stream) {
+  ABI_BEGIN
+  if (!s || !r || !z) throw Error(NNMS_ERR_INVALID_ARG, "bad arguments");
+  Plan& P = apply_plan(s);
+  join_in((hipStream_t)stream, P.stream);
+  const int64_t n = s->h->host.lev[0].nv;
+  put_vec(s, s->lev[0].r, r, n, P.stream);
+  for (int l = 0; l < s->h->host.L; ++l) HIP_CHECK(hipMemsetAsync(s->lev[l].z, 0, s->h->host.lev[l].nv * tsize(s), P.stream));
+  if (s->prec == NNMS_FP64)
+    enqueue_vcycle<double>(P, P.stream);
+  else
+    enqueue_vcycle<float>(P, P.stream);
+  get_vec(s, z, s->lev[0].z, n, P.stream);
+  check_counters(P, P.stream);
+  return NNMS_OK;
+  ABI_END
+}
+
+// ---------------------------------------------------------------------------
+// solves
+// ---------------------------------------------------------------------------
+extern "C" nnms_status nnms_solve_opts_default(nnms_solve_opts* o) {
+  if (!o) return NNMS_ERR_INVALID_ARG;
+  std::memset(o, 0, sizeof *o);
+  o->restart = 30;
+  o->max_it = 1000;
+  o->rtol = 1e-8;
+  return NNMS_OK;
+}
+
+struct nnms_batch {
+  std::unique_ptr<Plan> plan;
+  nnms_solve_opts opts{};
+};
+
+static void run_plan(Plan& P, int max_steps) {
+  for (int k = 0; k < max_steps; ++k) {
+    plan_step(P);
+    if (plan_active(P) == 0) return;
+  }
+}
+
+static nnms_solve_info read_info(nnms_system* s, hipStream_t st) {
+  KState ks;
+  HIP_CHECK(hipMemcpyAsync(&ks, s->st, sizeof(KState), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  nnms_solve_info in{};
+  in.iterations = ks.its;
+  in.cycles = ks.cycles;
+  in.relres = ks.relres;
+  in.status = ks.status == ST_CONVERGED ? NNMS_OK : NNMS_ERR_NOT_CONVERGED;
+  return in;
+}
+
+static nnms_status solve_many(nnms_system* const* systems, int32_t nb, const double* const* b, double* const* x,
+                              const nnms_solve_opts* opts, nnms_solve_info* infos, void* stream, bool use_solo) {
+  nnms_solve_opts o;
+  if (opts)
+    o = *opts;
+  else
+    nnms_solve_opts_default(&o);
+  validate_solve_opts(o);
+  if (!systems || nb < 1 || !b || !x) throw Error(NNMS_ERR_INVALID_ARG, "null argument");
+  std::vector<nnms_system*> sys(systems, systems + nb);
+  for (auto* s : sys)
+    if (!s) throw Error(NNMS_ERR_INVALID_ARG, "null system");
+  std::unique_ptr<Plan> local;
+  Plan* P;
+  if (use_solo) {
+    if (!sys[0]->solo) sys[0]->solo = make_plan_any(sys, true);
+    P = sys[0]->solo.get();
+  } else {
+    local = make_plan_any(sys, true);
+    P = local.get();
+  }
+  P->use_graph = !(o.flags & NNMS_NO_GRAPH);
+  hipStream_t user = (hipStream_t)stream;
+  join_in(user, P->stream);
+  const bool dev = (o.flags & NNMS_DEVICE_PTRS) != 0;
+  for (int k = 0; k < nb; ++k) {
+    nnms_system* s = sys[k];
+    const int64_t n = s->h->host.lev[0].nv;
+    if (dev) {
+      plan_start_slot(*P, k, b[k], o);
+    } else {
+      HIP_CHECK(hipMemcpyAsync(s->bw, b[k], n * sizeof(double), hipMemcpyHostToDevice, P->stream));
+      HIP_CHECK(hipStreamSynchronize(P->stream));
+      plan_start_slot(*P, k, s->bw, o);
+    }
+  }
+  if (plan_active(*P) > 0) run_plan(*P, o.max_it + 1);
+  check_counters(*P, P->stream);
+  nnms_status worst = NNMS_OK;
+  for (int k = 0; k < nb; ++k) {
+    nnms_system* s = sys[k];
+    const int64_t n = s->h->host.lev[0].nv;
+    HIP_CHECK(hipMemcpyAsync(x[k], s->x, n * sizeof(double), dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                             P->stream));
+    nnms_solve_info in = read_info(s, P->stream);
+    if (infos) infos[k] = in;
+    if (in.status != NNMS_OK) worst = NNMS_ERR_NOT_CONVERGED;
+  }
+  HIP_CHECK(hipStreamSynchronize(P->stream));
+  if (worst != NNMS_OK) nnms::set_last_error("iteration limit reached before the tolerance");
+  return worst;
+}
+
+extern "C" nnms_status nnms_solve(nnms_system* s, const double* b, double* x, const nnms_solve_opts* opts,
+                                  nnms_solve_info* info, void* stream) {
+  ABI_BEGIN
+  if (!s || !b || !x) throw Error(NNMS_ERR_INVALID_ARG, "null argument");
+  return solve_many(&s, 1, &b, &x, opts, info, stream, true);
+  ABI_END
+}
+
+extern "C" nnms_status nnms_solve_batch(nnms_system* const* systems, int32_t nb, const double* const* b, double* const* x,
+                                        const nnms_solve_opts* opts, nnms_solve_info* infos, void* stream) {
+  ABI_BEGIN
+  return solve_many(systems, nb, b, x, opts, infos, stream, false);
+  ABI_END
+}
+
+extern "C" nnms_status nnms_batch_create(nnms_system* const* systems, int32_t nb, const nnms_solve_opts* opts,
+                                         void* stream, nnms_batch** out) {
+  ABI_BEGIN
+  if (!systems || nb < 1 || !out) throw Error(NNMS_ERR_INVALID_ARG, "bad arguments");
+  *out = nullptr;
+  auto bt = std::make_unique<nnms_batch>();
+  if (opts)
+    bt->opts = *opts;
+  else
+    nnms_solve_opts_default(&bt->opts);
+  validate_solve_opts(bt->opts);
+  std::vector<nnms_system*> sys(systems, systems + nb);
+  for (auto* s : sys)
+    if (!s) throw Error(NNMS_ERR_INVALID_ARG, "null system");
+  bt->plan = make_plan_any(sys, true);
+  bt->plan->use_graph = !(bt->opts.flags & NNMS_NO_GRAPH);
+  join_in((hipStream_t)stream, bt->plan->stream);
+  // every slot starts idle
+  for (int k = 0; k < nb; ++k) {
+    int32_t idle = ST_IDLE;
+    HIP_CHECK(hipMemcpyAsync(&sys[k]->st->status, &idle, sizeof idle, hipMemcpyHostToDevice, bt->plan->stream));
+    HIP_CHECK(hipStreamSynchronize(bt->plan->stream));
+  }
+  *out = bt.release();
+  return NNMS_OK;
+  ABI_END
+}
+
+extern "C" nnms_status nnms_batch_start(nnms_batch* bt, int32_t slot, const double* b_dev) {
+  ABI_BEGIN
+  if (!bt || !b_dev || slot < 0 || slot >= bt->plan->nd) throw Error(NNMS_ERR_INVALID_ARG, "bad arguments");
+  plan_start_slot(*bt->plan, slot, b_dev, bt->opts);
+  return NNMS_OK;
+  ABI_END
+}
+
+extern "C" nnms_status nnms_batch_step(nnms_batch* bt, int32_t iterations, int32_t* active) {
+  ABI_BEGIN
+  if (!bt || iterations < 0) throw Error(NNMS_ERR_INVALID_ARG, "bad arguments");
+  int a = plan_active(*bt->plan);
+  for (int k = 0; k < iterations && a > 0; ++k) {
+    plan_step(*bt->plan);
+    a = plan_active(*bt->plan);
+  }
+  check_counters(*bt->plan, bt->plan->stream);
+  if (active) *active = a;
+  return NNMS_OK;
+  ABI_END
+}
+
+extern "C" nnms_status nnms_batch_result(nnms_batch* bt, int32_t slot, double* x_dev, nnms_solve_info* info) {
+  ABI_BEGIN
+  if (!bt || slot < 0 || slot >= bt->plan->nd) throw Error(NNMS_ERR_INVALID_ARG, "bad arguments");
+  nnms_system* s = bt->plan->sys[slot];
+  if (x_dev)
+    HIP_CHECK(hipMemcpyAsync(x_dev, s->x, s->h->host.lev[0].nv * sizeof(double), hipMemcpyDeviceToDevice,
+                             bt->plan->stream));
+  nnms_solve_info in = read_info(s, bt->plan->stream);
+  if (info) *info = in;
+  return NNMS_OK;
+  ABI_END
+}
+
+extern "C" nnms_status nnms_batch_destroy(nnms_batch* bt) {
+  if (bt && bt->plan) (void)hipStreamSynchronize(bt->plan->stream);
+  delete bt;
+  return NNMS_OK;
+}
+
+extern "C" nnms_status nnms_time_kernel(nnms_system* s, int32_t kind, int32_t level, int32_t reps, double* ms) {
+  ABI_BEGIN
+  if (!s || !ms || reps < 1 || level < 0 || level >= s->h->host.L || kind < 0 || kind > 3)
+    throw Error(NNMS_ERR_INVALID_ARG, "bad arguments");
+  const int L = s->h->host.L;
+  if (kind != 0 && level == L - 1) throw Error(NNMS_ERR_INVALID_ARG, "the coarsest level has only the direct solve");
+  Plan& P = apply_plan(s);
+  hipStream_t st = P.stream;
+  const bool f64 = s->prec == NNMS_FP64;
+  const int grid = ras_grid_default();
+  auto launch = [&]() {
+    if (kind == 0) {
+      if (level == L - 1) {
+        if (f64)
+          HIP_CHECK((launch_ras<double, double>(P.coarse, grid, st)));
+        else
+          HIP_CHECK((launch_ras<double, float>(P.coarse, grid, st)));
+      } else if (f64) {
+        HIP_CHECK((launch_ras<double, double>(P.lev[level].ras_t, grid, st)));
+      } else {
+        HIP_CHECK((launch_ras<float, float>(P.lev[level].ras_t, grid, st)));
+      }
+    } else if (kind == 1) {
+      if (f64)
+        HIP_CHECK(launch_spmv<double>(P.lev[level].res, 1, P.lev[level].res_blocks, SPMV_G_A, st));
+      else
+        HIP_CHECK(launch_spmv<float>(P.lev[level].res, 1, P.lev[level].res_blocks, SPMV_G_A, st));
+    } else if (kind == 2) {
+      if (f64)
+        HIP_CHECK(launch_prolong<double>(P.lev[level].pro, 1, P.lev[level].pro_blocks, st));
+      else
+        HIP_CHECK(launch_prolong<float>(P.lev[level].pro, 1, P.lev[level].pro_blocks, st));
+    } else {
+      if (f64)
+        HIP_CHECK(launch_spmv<double>(P.lev[level].rst, 1, P.lev[level].rst_blocks, SPMV_G_PT, st));
+      else
+        HIP_CHECK(launch_spmv<float>(P.lev[level].rst, 1, P.lev[level].rst_blocks, SPMV_G_PT, st));
+    }
+  };
+  launch();  // warm-up
+  hipEvent_t e0, e1;
+  HIP_CHECK(hipEventCreate(&e0));
+  HIP_CHECK(hipEventCreate(&e1));
+  HIP_CHECK(hipEventRecord(e0, st));
+  for (int r = 0; r < reps; ++r) launch();
+  HIP_CHECK(hipEventRecord(e1, st));
+  HIP_CHECK(hipEventSynchronize(e1));
+  float t = 0;
+  HIP_CHECK(hipEventElapsedTime(&t, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  check_counters(P, st);
+  *ms = double(t) / reps;
+  return NNMS_OK;
+  ABI_END
+}
+
+extern "C" nnms_status nnms_system_factor(const nnms_system* s, int32_t level, int32_t part, double* lu, double* invl,
+                                          int32_t* Nout) {
+  ABI_BEGIN
+  if (!s || level < 0 || level >= s->h->host.L) throw Error(NNMS_ERR_INVALID_ARG, "bad level");
+  const HostLevel& hl = s->h->host.lev[level];
+  if (part < 0 || part >= hl.nparts) throw Error(NNMS_ERR_INVALID_ARG, "bad part");
+  const int N = hl.nblk[part];
+  if (Nout) *Nout = N;
+  const bool f64 = (level == s->h->host.L - 1) || s->prec == NNMS_FP64;
+  const size_t fsz = f64 ? 8 : 4;
+  const size_t ne = (size_t(N) * N + N) * TILE_ELEMS;
+  std::vector<char> raw(ne * fsz);
+  HIP_CHECK(hipMemcpy(raw.data(), (const char*)s->lev[level].fac + size_t(hl.fac_off[part]) * fsz, raw.size(),
+                      hipMemcpyDeviceToHost));
+  auto get = [&](size_t tile, int r, int c) -> double {
+    if (f64) {
+      const double* t = (const double*)raw.data() + tile * TILE_ELEMS;
+      return t[((c / 2) * 64 + r) * 2 + (c % 2)];
+    }
+    const float* t = (const float*)raw.data() + tile * TILE_ELEMS;
+    return t[((c / 4) * 64 + r) * 4 + (c % 4)];
+  };
+  const size_t np = size_t(N) * 64;
+  if (lu)
+    for (int ti = 0; ti < N; ++ti)
+      for (int tj = 0; tj < N; ++tj)
+        for (int r = 0; r < 64; ++r)
+          for (int c = 0; c < 64; ++c) lu[(size_t(ti) * 64 + r) * np + size_t(tj) * 64 + c] = get(size_t(ti) * N + tj, r, c);
+  if (invl)
+    for (int ti = 0; ti < N; ++ti)
+      for (int r = 0; r < 64; ++r)
+        for (int c = 0; c < 64; ++c) invl[(size_t(ti) * 64 + r) * 64 + c] = get(size_t(N) * N + ti, r, c);
+  return NNMS_OK;
+  ABI_END
+}

@@ -1,0 +1,410 @@
+// Host-side structure setup of a mesh hierarchy: mesh validation, the CSR
+// pattern and its assembly maps, the Schwarz partition with overlap, and
+// the barycentric point-location transfer between non-nested levels.
+// Everything here depends on the meshes only and is reused across
+// parameters (Section 2.1 of the paper: the mesh perspective is a reusable,
+// parameter-independent object).
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "nnms_internal.h"
+
+namespace nnms {
+
+int default_nparts(int64_t nv) {
+  double q = double(nv) / 1500.0;
+  if (q < 2.0) return 2;
+  int e = int(std::floor(std::log2(q)));
+  return std::max(2, 1 << e);
+}
+
+// ---------------------------------------------------------------------------
+// CSR pattern of the vertex graph and the element->entry gather maps.
+// Interior rows keep interior columns; Dirichlet rows keep the diagonal
+// (the symmetric elimination of homogeneous Dirichlet data).
+// ---------------------------------------------------------------------------
+void build_pattern(HostLevel& lv) {
+  const int64_t nv = lv.nv, nt = lv.nt;
+  // vertex -> (element, local index), elements ascending
+  lv.vptr.assign(nv + 1, 0);
+  for (int64_t t = 0; t < nt; ++t)
+    for (int a = 0; a < 4; ++a) lv.vptr[lv.tets[t * 4 + a] + 1]++;
+  for (int64_t i = 0; i < nv; ++i) lv.vptr[i + 1] += lv.vptr[i];
+  lv.vitem.resize(lv.vptr[nv]);
+  {
+    std::vector<int32_t> fill(lv.vptr.begin(), lv.vptr.end() - 1);
+    for (int64_t t = 0; t < nt; ++t)
+      for (int a = 0; a < 4; ++a) lv.vitem[fill[lv.tets[t * 4 + a]]++] = int32_t(t * 4 + a);
+  }
+  // rows
+  lv.rp.assign(nv + 1, 0);
+  std::vector<std::vector<int32_t>> rows(0);
+  lv.col.clear();
+  lv.col.reserve(nv * 15);
+  std::vector<int32_t> nb;
+  for (int64_t i = 0; i < nv; ++i) {
+    nb.clear();
+    if (lv.dir[i]) {
+      nb.push_back(int32_t(i));
+    } else {
+      for (int32_t e = lv.vptr[i]; e < lv.vptr[i + 1]; ++e) {
+        int32_t t = lv.vitem[e] >> 2;
+        for (int b = 0; b < 4; ++b) {
+          int32_t j = lv.tets[t * 4 + b];
+          if (!lv.dir[j]) nb.push_back(j);
+        }
+      }
+      std::sort(nb.begin(), nb.end());
+      nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
+    }
+    lv.col.insert(lv.col.end(), nb.begin(), nb.end());
+    lv.rp[i + 1] = int32_t(lv.col.size());
+  }
+  if (lv.col.size() > size_t(INT32_MAX)) throw Error(NNMS_ERR_INVALID_ARG, "mesh too large for int32 CSR");
+  // element contributions per CSR entry (interior rows only)
+  const int64_t nnz = lv.col.size();
+  lv.cptr.assign(nnz + 1, 0);
+  auto find_slot = [&](int32_t i, int32_t j) -> int32_t {
+    const int32_t* b = lv.col.data() + lv.rp[i];
+    const int32_t* e = lv.col.data() + lv.rp[i + 1];
+    const int32_t* p = std::lower_bound(b, e, j);
+    return int32_t(p - lv.col.data());
+  };
+  for (int pass = 0; pass < 2; ++pass) {
+    std::vector<int32_t> fill;
+    if (pass == 1) {
+      for (int64_t s = 0; s < nnz; ++s) lv.cptr[s + 1] += lv.cptr[s];
+      lv.citem.resize(lv.cptr[nnz]);
+      fill.assign(lv.cptr.begin(), lv.cptr.end() - 1);
+    }
+    for (int64_t i = 0; i < nv; ++i) {
+      if (lv.dir[i]) continue;
+      for (int32_t e = lv.vptr[i]; e < lv.vptr[i + 1]; ++e) {
+        int32_t t = lv.vitem[e] >> 2, a = lv.vitem[e] & 3;
+        for (int b = 0; b < 4; ++b) {
+          int32_t j = lv.tets[t * 4 + b];
+          if (lv.dir[j]) continue;
+          int32_t s = find_slot(int32_t(i), j);
+          if (pass == 0)
+            lv.cptr[s + 1]++;
+          else
+            lv.citem[fill[s]++] = t * 16 + a * 4 + b;
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Recursive coordinate bisection of the interior vertices (axis = depth mod
+// 3, order by (coordinate, vertex id), the lower floor(n/2) to the lower
+// part), then `overlap` layers of 1-ring growth restricted to interior
+// vertices (Section 2.2: subdomains extended by delta layers of elements).
+// ---------------------------------------------------------------------------
+static void rcb(const HostLevel& lv, std::vector<int32_t>& ids, int nparts, int depth,
+                std::vector<std::vector<int32_t>>& out) {
+  if (nparts <= 1) {
+    std::sort(ids.begin(), ids.end());
+    out.push_back(ids);
+    return;
+  }
+  const int ax = depth % 3;
+  std::sort(ids.begin(), ids.end(), [&](int32_t a, int32_t b) {
+    double xa = lv.xyz[size_t(a) * 3 + ax], xb = lv.xyz[size_t(b) * 3 + ax];
+    if (xa != xb) return xa < xb;
+    return a < b;
+  });
+  size_t half = ids.size() / 2;
+  std::vector<int32_t> lo(ids.begin(), ids.begin() + half), hi(ids.begin() + half, ids.end());
+  rcb(lv, lo, nparts / 2, depth + 1, out);
+  rcb(lv, hi, nparts / 2, depth + 1, out);
+}
+
+void build_partition(HostLevel& lv, int nparts, int overlap, bool direct) {
+  const int64_t nv = lv.nv;
+  std::vector<int32_t> interior;
+  for (int64_t i = 0; i < nv; ++i)
+    if (!lv.dir[i]) interior.push_back(int32_t(i));
+  lv.nint = int64_t(interior.size());
+  std::vector<std::vector<int32_t>> owned;
+  if (direct) {
+    nparts = 1;
+    owned.push_back(interior);
+    overlap = 0;
+  } else {
+    if (nparts < 1 || (nparts & (nparts - 1))) throw Error(NNMS_ERR_INVALID_ARG, "nparts must be a power of two");
+    rcb(lv, interior, nparts, 0, owned);
+  }
+  lv.nparts = nparts;
+  lv.owner.assign(nv, -1);
+  for (int p = 0; p < nparts; ++p)
+    for (int32_t v : owned[p]) lv.owner[v] = p;
+  lv.s_ptr.assign(nparts + 1, 0);
+  lv.s_idx.clear();
+  std::vector<uint8_t> mark(nv), nxt(nv);
+  for (int p = 0; p < nparts; ++p) {
+    std::fill(mark.begin(), mark.end(), 0);
+    for (int32_t v : owned[p]) mark[v] = 1;
+    std::vector<int32_t> cur = owned[p];
+    for (int d = 0; d < overlap; ++d) {
+      std::vector<int32_t> grow;
+      for (int32_t v : cur)
+        for (int32_t e = lv.rp[v]; e < lv.rp[v + 1]; ++e) {
+          int32_t c = lv.col[e];
+          if (!mark[c]) {
+            mark[c] = 1;
+            grow.push_back(c);
+          }
+        }
+      cur.insert(cur.end(), grow.begin(), grow.end());
+    }
+    std::sort(cur.begin(), cur.end());
+    lv.s_idx.insert(lv.s_idx.end(), cur.begin(), cur.end());
+    lv.s_ptr[p + 1] = int64_t(lv.s_idx.size());
+  }
+  // dense tiles, padded index map and extraction map
+  lv.nblk.assign(nparts, 0);
+  lv.fac_off.assign(nparts + 1, 0);
+  lv.g_off.assign(nparts + 1, 0);
+  for (int p = 0; p < nparts; ++p) {
+    int64_t n = lv.s_ptr[p + 1] - lv.s_ptr[p];
+    int32_t N = int32_t((n + TILE - 1) / TILE);
+    lv.nblk[p] = N;
+    lv.fac_off[p + 1] = lv.fac_off[p] + (int64_t(N) * N + N) * TILE_ELEMS;
+    lv.g_off[p + 1] = lv.g_off[p] + int64_t(N) * TILE;
+  }
+  lv.fac_elems = lv.fac_off[nparts];
+  lv.g_total = lv.g_off[nparts];
+  lv.gidx.assign(lv.g_total, -1);
+  lv.ext_rs.assign(lv.s_idx.size() + 1, 0);
+  lv.ext_lc.clear();
+  for (int p = 0; p < nparts; ++p) {
+    const int32_t* S = lv.s_idx.data() + lv.s_ptr[p];
+    int64_t n = lv.s_ptr[p + 1] - lv.s_ptr[p];
+    for (int64_t k = 0; k < n; ++k) {
+      int32_t g = S[k];
+      lv.gidx[lv.g_off[p] + k] = (lv.owner[g] == p) ? g : (-g - 2);
+      lv.ext_rs[lv.s_ptr[p] + k] = int32_t(lv.ext_lc.size());
+      for (int32_t e = lv.rp[g]; e < lv.rp[g + 1]; ++e) {
+        int32_t c = lv.col[e];
+        const int32_t* q = std::lower_bound(S, S + n, c);
+        lv.ext_lc.push_back((q != S + n && *q == c) ? int32_t(q - S) : -1);
+      }
+    }
+  }
+  if (lv.ext_lc.size() > size_t(INT32_MAX)) throw Error(NNMS_ERR_INVALID_ARG, "subdomains too large");
+  lv.ext_rs[lv.s_idx.size()] = int32_t(lv.ext_lc.size());
+}
+
+// ---------------------------------------------------------------------------
+// Barycentric transfer: every interior fine vertex is located in a coarse
+// tetrahedron (lowest id with min(lambda) >= -1e-12; otherwise the largest
+// min(lambda), rejected below -1e-8) through a uniform bucket grid.
+// ---------------------------------------------------------------------------
+void build_transfer(HostLevel& fine, const HostLevel& coarse) {
+  const double ACCEPT = -1e-12, REJECT = -1e-8;
+  const int64_t nt = coarse.nt;
+  std::vector<std::array<double, 12>> aff(nt);  // x0 (3) and J^{-1} (9, row-major)
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int64_t v = 0; v < coarse.nv; ++v)
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = std::min(lo[a], coarse.xyz[v * 3 + a]);
+      hi[a] = std::max(hi[a], coarse.xyz[v * 3 + a]);
+    }
+  for (int64_t t = 0; t < nt; ++t) {
+    const double* x0 = &coarse.xyz[size_t(coarse.tets[t * 4]) * 3];
+    double J[3][3];
+    for (int c = 0; c < 3; ++c) {
+      const double* xc = &coarse.xyz[size_t(coarse.tets[t * 4 + c + 1]) * 3];
+      for (int r = 0; r < 3; ++r) J[r][c] = xc[r] - x0[r];
+    }
+    double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                 J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    double id = 1.0 / det;
+    auto& A = aff[t];
+    A[0] = x0[0], A[1] = x0[1], A[2] = x0[2];
+    double* M = &A[3];
+    M[0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) * id;
+    M[1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
+    M[2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
+    M[3] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) * id;
+    M[4] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+    M[5] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+    M[6] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) * id;
+    M[7] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+    M[8] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
+  }
+  int nb = std::max(1, int(std::lround(std::cbrt(double(nt)))));
+  double cell[3], span = 0;
+  for (int a = 0; a < 3; ++a) {
+    cell[a] = std::max((hi[a] - lo[a]) / nb, 1e-300);
+    span = std::max(span, hi[a] - lo[a]);
+  }
+  const double pad = 1e-9 * span;
+  auto bucket = [&](double x, int a) {
+    int b = int(std::floor((x - lo[a]) / cell[a]));
+    return std::min(std::max(b, 0), nb - 1);
+  };
+  const int64_t nbk = int64_t(nb) * nb * nb;
+  std::vector<int32_t> bptr(nbk + 1, 0), bitem;
+  for (int pass = 0; pass < 2; ++pass) {
+    std::vector<int32_t> fill;
+    if (pass == 1) {
+      for (int64_t b = 0; b < nbk; ++b) bptr[b + 1] += bptr[b];
+      bitem.resize(bptr[nbk]);
+      fill.assign(bptr.begin(), bptr.end() - 1);
+    }
+    for (int64_t t = 0; t < nt; ++t) {
+      int bl[3], bh[3];
+      for (int a = 0; a < 3; ++a) {
+        double mn = 1e300, mx = -1e300;
+        for (int k = 0; k < 4; ++k) {
+          double x = coarse.xyz[size_t(coarse.tets[t * 4 + k]) * 3 + a];
+          mn = std::min(mn, x), mx = std::max(mx, x);
+        }
+        bl[a] = bucket(mn - pad, a), bh[a] = bucket(mx + pad, a);
+      }
+      for (int k = bl[2]; k <= bh[2]; ++k)
+        for (int j = bl[1]; j <= bh[1]; ++j)
+          for (int i = bl[0]; i <= bh[0]; ++i) {
+            int64_t b = i + int64_t(nb) * (j + int64_t(nb) * k);
+            if (pass == 0)
+              bptr[b + 1]++;
+            else
+              bitem[fill[b]++] = int32_t(t);  // t ascending within a bucket
+          }
+    }
+  }
+  const int64_t nf = fine.nv;
+  fine.p_idx.assign(nf * 4, 0);
+  fine.p_w.assign(nf * 4, 0.0);
+  fine.ncoarse = coarse.nv;
+  for (int64_t v = 0; v < nf; ++v) {
+    if (fine.dir[v]) continue;
+    const double* x = &fine.xyz[v * 3];
+    int64_t b = bucket(x[0], 0) + int64_t(nb) * (bucket(x[1], 1) + int64_t(nb) * bucket(x[2], 2));
+    int32_t best_t = -1;
+    double best = -1e300, best_l[4] = {0, 0, 0, 0};
+    for (int32_t e = bptr[b]; e < bptr[b + 1]; ++e) {
+      int32_t t = bitem[e];
+      const auto& A = aff[t];
+      double d0 = x[0] - A[0], d1 = x[1] - A[1], d2 = x[2] - A[2];
+      double l[4];
+      l[1] = A[3] * d0 + A[4] * d1 + A[5] * d2;
+      l[2] = A[6] * d0 + A[7] * d1 + A[8] * d2;
+      l[3] = A[9] * d0 + A[10] * d1 + A[11] * d2;
+      l[0] = 1.0 - l[1] - l[2] - l[3];
+      double mn = std::min(std::min(l[0], l[1]), std::min(l[2], l[3]));
+      if (mn >= ACCEPT) {
+        best_t = t, best = 1e300;
+        std::memcpy(best_l, l, sizeof l);
+        break;
+      }
+      if (mn > best) {
+        best_t = t, best = mn;
+        std::memcpy(best_l, l, sizeof l);
+      }
+    }
+    if (best_t < 0 || best < REJECT)
+      throw Error(NNMS_ERR_POINT_LOCATION, "fine vertex " + std::to_string(v) + " lies outside the coarser mesh");
+    for (int a = 0; a < 4; ++a) {
+      int32_t c = coarse.tets[best_t * 4 + a];
+      fine.p_idx[v * 4 + a] = c;
+      fine.p_w[v * 4 + a] = coarse.dir[c] ? 0.0 : best_l[a];
+    }
+  }
+  // explicit transpose: rows = interior coarse vertices, entries ordered by fine id
+  const int64_t nc = coarse.nv;
+  fine.pt_rp.assign(nc + 1, 0);
+  for (int64_t v = 0; v < nf; ++v) {
+    if (fine.dir[v]) continue;
+    for (int a = 0; a < 4; ++a) {
+      int32_t c = fine.p_idx[v * 4 + a];
+      if (!coarse.dir[c]) fine.pt_rp[c + 1]++;
+    }
+  }
+  for (int64_t c = 0; c < nc; ++c) fine.pt_rp[c + 1] += fine.pt_rp[c];
+  fine.pt_col.resize(fine.pt_rp[nc]);
+  fine.pt_w.resize(fine.pt_rp[nc]);
+  std::vector<int32_t> fill(fine.pt_rp.begin(), fine.pt_rp.end() - 1);
+  for (int64_t v = 0; v < nf; ++v) {
+    if (fine.dir[v]) continue;
+    for (int a = 0; a < 4; ++a) {
+      int32_t c = fine.p_idx[v * 4 + a];
+      if (coarse.dir[c]) continue;
+      fine.pt_col[fill[c]] = int32_t(v);
+      fine.pt_w[fill[c]++] = fine.p_w[v * 4 + a];
+    }
+  }
+}
+
+}  // namespace nnms
+
+using namespace nnms;
+
+// ---------------------------------------------------------------------------
+// C ABI: meshes and host-only hierarchy inspection
+// ---------------------------------------------------------------------------
+extern "C" nnms_status nnms_mesh_create(int64_t nv, const double* xyz, int64_t nt, const int32_t* tets,
+                                        const uint8_t* dirichlet, nnms_mesh** out) {
+  try {
+    if (!out || !xyz || !tets || nv < 4 || nt < 1 || nv > INT32_MAX || nt > (INT32_MAX >> 4))
+      throw Error(NNMS_ERR_INVALID_ARG, "nnms_mesh_create: bad arguments");
+    *out = nullptr;
+    auto* m = new nnms_mesh;
+    m->nv = nv, m->nt = nt;
+    m->xyz.assign(xyz, xyz + nv * 3);
+    m->tets.assign(tets, tets + nt * 4);
+    for (int64_t k = 0; k < nt * 4; ++k)
+      if (m->tets[k] < 0 || m->tets[k] >= nv) {
+        delete m;
+        throw Error(NNMS_ERR_BAD_MESH, "tetrahedron " + std::to_string(k / 4) + " has a vertex id out of range");
+      }
+    for (int64_t t = 0; t < nt; ++t) {
+      const double* p[4];
+      for (int a = 0; a < 4; ++a) p[a] = &m->xyz[size_t(m->tets[t * 4 + a]) * 3];
+      double e[3][3];
+      for (int a = 0; a < 3; ++a)
+        for (int r = 0; r < 3; ++r) e[a][r] = p[a + 1][r] - p[0][r];
+      double det = e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) - e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
+                   e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
+      if (!(det > 0)) {
+        delete m;
+        throw Error(NNMS_ERR_BAD_MESH, "tetrahedron " + std::to_string(t) + " has non-positive volume");
+      }
+    }
+    m->dir.assign(nv, 0);
+    if (dirichlet) {
+      for (int64_t v = 0; v < nv; ++v) m->dir[v] = dirichlet[v] ? 1 : 0;
+    } else {
+      double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+      for (int64_t v = 0; v < nv; ++v)
+        for (int a = 0; a < 3; ++a) lo[a] = std::min(lo[a], m->xyz[v * 3 + a]), hi[a] = std::max(hi[a], m->xyz[v * 3 + a]);
+      for (int64_t v = 0; v < nv; ++v)
+        for (int a = 0; a < 3; ++a)
+          if (m->xyz[v * 3 + a] == lo[a] || m->xyz[v * 3 + a] == hi[a]) m->dir[v] = 1;
+    }
+    *out = m;
+    return NNMS_OK;
+  } catch (const Error& e) {
+    set_last_error(e.what());
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_last_error("host out of memory");
+    return NNMS_ERR_OUT_OF_MEMORY;
+  }
+}
+
+extern "C" void nnms_mesh_destroy(nnms_mesh* m) { delete m; }
+
+extern "C" nnms_status nnms_setup_opts_default(nnms_setup_opts* o) {
+  if (!o) return NNMS_ERR_INVALID_ARG;
+  std::memset(o, 0, sizeof *o);
+  o->overlap = 1;
+  o->its = 3;
+  o->precision = NNMS_FP64;
+  return NNMS_OK;
+}

@@ -1,0 +1,51 @@
+// Host-callable launchers of the HIP kernels.  Every launcher enqueues on
+// `stream` and returns the hipError_t of the launch.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "devtypes.h"
+
+namespace nnms {
+
+// sparse.hip
+template <typename T>
+hipError_t launch_spmv(const SpmvDesc* d, int nd, int nblocks, int group, hipStream_t s);
+template <typename T>
+hipError_t launch_prolong(const ProlongDesc* d, int nd, int nblocks, hipStream_t s);
+template <typename T>
+hipError_t launch_fill(T* p, int64_t n, T v, hipStream_t s);
+hipError_t launch_cast_d2f(const double* a, float* b, int64_t n, hipStream_t s);
+hipError_t launch_cast_f2d(const float* a, double* b, int64_t n, hipStream_t s);
+
+// ras.hip: one restricted additive Schwarz application (all subdomains of
+// all slots), forward and backward block triangular solves with gather and
+// scatter fused.  F = factor precision, V = vector precision.
+template <typename F, typename V>
+hipError_t launch_ras(const RasLaunch& p, int grid, hipStream_t s);
+
+// lu.hip
+template <typename F>
+hipError_t launch_extract(const FacDesc* d, int nd, int maxn, hipStream_t s);
+template <typename F>
+hipError_t launch_lu_step(const FacDesc* d, int nd, int k, int maxN, int* err, hipStream_t s);
+
+// assemble.hip
+hipError_t launch_assemble(const AsmDesc& a, const KappaDev& k, double f, hipStream_t s);
+
+// krylov.hip (T = precision of the level-0 preconditioner vectors)
+template <typename T>
+hipError_t launch_krylov_cast_in(const KrylovDesc* d, int nd, int nblocks, hipStream_t s);
+template <typename T>
+hipError_t launch_krylov_cast_out(const KrylovDesc* d, int nd, int nblocks, hipStream_t s);
+hipError_t launch_krylov_dots1(const KrylovDesc* d, int nd, int nblocks, hipStream_t s);
+hipError_t launch_krylov_upd1(const KrylovDesc* d, int nd, int nblocks, hipStream_t s);
+hipError_t launch_krylov_upd2(const KrylovDesc* d, int nd, int nblocks, hipStream_t s);
+hipError_t launch_krylov_givens(const KrylovDesc* d, int nd, hipStream_t s);
+hipError_t launch_krylov_normalize(const KrylovDesc* d, int nd, int nblocks, hipStream_t s);
+hipError_t launch_krylov_xupd(const KrylovDesc* d, int nd, int nblocks, hipStream_t s);
+hipError_t launch_krylov_cycle(const KrylovDesc* d, int nd, hipStream_t s);
+hipError_t launch_krylov_init_slot(const KrylovDesc* d, int nd, int boff, int nblocks, hipStream_t s);
+hipError_t launch_krylov_start_slot(const KrylovDesc* d1, double rtol, int restart, int max_it, hipStream_t s);
+hipError_t launch_count_active(const KrylovDesc* d, int nd, int* out, hipStream_t s);
+
+}  // namespace nnms

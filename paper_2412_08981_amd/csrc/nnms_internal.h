@@ -1,0 +1,84 @@
+// Internal declarations of the nnms library (host structures and the
+// device-side descriptors shared by the HIP kernels and the driver).
+#pragma once
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "devtypes.h"
+#include "nnms.h"
+
+namespace nnms {
+
+// Error carrying an nnms_status across internal C++ code; converted to a
+// status at the C ABI.
+struct Error : std::runtime_error {
+  nnms_status code;
+  Error(nnms_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+void set_last_error(const std::string& msg);
+
+
+// ---------------------------------------------------------------------------
+// Host structure of one level (built once per hierarchy).
+// ---------------------------------------------------------------------------
+struct HostLevel {
+  int64_t nv = 0, nt = 0, nint = 0;
+  std::vector<double> xyz;      // nv*3
+  std::vector<int32_t> tets;    // nt*4
+  std::vector<uint8_t> dir;     // nv
+
+  // CSR pattern (Dirichlet rows: diagonal only; Dirichlet columns dropped)
+  std::vector<int32_t> rp, col;
+  // assembly gather: for every CSR slot, its element contributions
+  // encoded t*16 + a*4 + b, ordered by element id
+  std::vector<int32_t> cptr, citem;
+  // vertex -> incident elements (t*4 + a), ordered by element id
+  std::vector<int32_t> vptr, vitem;
+
+  // Schwarz partition (nparts subdomains; 1 on the coarsest level)
+  int32_t nparts = 0;
+  std::vector<int32_t> owner;       // nv, -1 on Dirichlet vertices
+  std::vector<int64_t> s_ptr;       // nparts+1
+  std::vector<int32_t> s_idx;       // S_p ascending
+  // dense-block bookkeeping
+  std::vector<int32_t> nblk;        // tiles per side of every subdomain
+  std::vector<int64_t> fac_off;     // element offset of every factor
+  int64_t fac_elems = 0;
+  std::vector<int64_t> g_off;       // offset into gidx (multiples of 64)
+  int64_t g_total = 0;
+  std::vector<int32_t> gidx;        // encoded global ids, padded to nblk*64
+  std::vector<int32_t> ext_rs;      // start in ext_lc of every local row (s_total+1, in S order)
+  std::vector<int32_t> ext_lc;      // local column of every CSR entry of every local row, -1 outside S_p
+
+  // transfer P_l from level l+1 to l (empty on the coarsest level)
+  std::vector<int32_t> p_idx;       // nv*4
+  std::vector<double> p_w;          // nv*4
+  std::vector<int32_t> pt_rp, pt_col;  // rows: coarse vertices
+  std::vector<double> pt_w;
+  int64_t ncoarse = 0;
+};
+
+struct HostHierarchy {
+  int L = 0;
+  nnms_setup_opts opts{};
+  std::vector<HostLevel> lev;
+};
+
+// host setup steps
+void build_pattern(HostLevel& lv);
+void build_partition(HostLevel& lv, int nparts, int overlap, bool direct);
+void build_transfer(HostLevel& fine, const HostLevel& coarse);
+int default_nparts(int64_t nv);
+
+}  // namespace nnms
+
+struct nnms_mesh {
+  int64_t nv = 0, nt = 0;
+  std::vector<double> xyz;
+  std::vector<int32_t> tets;
+  std::vector<uint8_t> dir;
+};

@@ -1,0 +1,124 @@
+// CSR sparse matrix-vector products (level operators, residuals, the
+// transposed transfer P^T) and the ELL-4 prolongation P (Section 2.3 of the
+// paper: residuals r - J z and inter-level transfers of the V-cycle).
+//
+// SpMV maps one row to a group of G lanes of a wave (G = 16 covers the at
+// most 15 entries per row of a P1 tetrahedral operator in one pass): the
+// group reads the row's values and column ids contiguously, gathers x and
+// reduces with cross-lane shuffles in a fixed order (deterministic).
+#include "devcommon.h"
+#include "kernels.h"
+
+namespace nnms {
+
+template <typename T, int G>
+__global__ __launch_bounds__(256) void k_spmv(const SpmvDesc* __restrict__ d, int nd) {
+  const int b = blockIdx.x;
+  const SpmvDesc D = d[find_desc(d, nd, b)];
+  if (!slot_active(D.st, D.when)) return;
+  const int lb = b - D.blk0;
+  const int row = lb * (256 / G) + int(threadIdx.x) / G;
+  const int lane = threadIdx.x % G;
+  const T* __restrict__ x = (const T*)D.x;
+  if (D.x_jstride) x += int64_t(D.st->j) * D.x_jstride;
+  const T* __restrict__ val = (const T*)D.val;
+  T sum = 0;
+  if (row < D.n) {
+    const int s = D.rp[row], e = D.rp[row + 1];
+    for (int k = s + lane; k < e; k += G) sum += val[k] * x[D.col[k]];
+  }
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, G);
+  T out = 0;
+  if (lane == 0 && row < D.n) {
+    out = D.r ? ((const T*)D.r)[row] - sum : sum;
+    ((T*)D.y)[row] = out;
+  }
+  if (D.nrm) {  // partial sum of squares of this block's outputs (fixed order)
+    __shared__ double red[4];
+    double q = (lane == 0 && row < D.n) ? double(out) * double(out) : 0.0;
+    q = wave_sum(q);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = q;
+    __syncthreads();
+    if (threadIdx.x == 0) D.nrm[lb] = (red[0] + red[1]) + (red[2] + red[3]);
+  }
+}
+
+template <typename T>
+hipError_t launch_spmv(const SpmvDesc* d, int nd, int nblocks, int group, hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  switch (group) {
+    case 4: hipLaunchKernelGGL((k_spmv<T, 4>), dim3(nblocks), dim3(256), 0, s, d, nd); break;
+    case 8: hipLaunchKernelGGL((k_spmv<T, 8>), dim3(nblocks), dim3(256), 0, s, d, nd); break;
+    case 16: hipLaunchKernelGGL((k_spmv<T, 16>), dim3(nblocks), dim3(256), 0, s, d, nd); break;
+    case 32: hipLaunchKernelGGL((k_spmv<T, 32>), dim3(nblocks), dim3(256), 0, s, d, nd); break;
+    case 64: hipLaunchKernelGGL((k_spmv<T, 64>), dim3(nblocks), dim3(256), 0, s, d, nd); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// zf[i] += sum_a w[4i+a] zc[idx[4i+a]]: coarse-to-fine barycentric transfer.
+template <typename T>
+__global__ __launch_bounds__(256) void k_prolong(const ProlongDesc* __restrict__ d, int nd) {
+  const int b = blockIdx.x;
+  const ProlongDesc D = d[find_desc(d, nd, b)];
+  if (!slot_active(D.st, WHEN_RUNNING)) return;
+  const int i = (b - D.blk0) * 256 + threadIdx.x;
+  if (i >= D.n) return;
+  const int4 id = ((const int4*)D.idx)[i];
+  const T* w = (const T*)D.w + int64_t(i) * 4;
+  const T* zc = (const T*)D.zc;
+  T acc = w[0] * zc[id.x] + w[1] * zc[id.y] + w[2] * zc[id.z] + w[3] * zc[id.w];
+  ((T*)D.zf)[i] += acc;
+}
+
+template <typename T>
+hipError_t launch_prolong(const ProlongDesc* d, int nd, int nblocks, hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_prolong<T>), dim3(nblocks), dim3(256), 0, s, d, nd);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_fill(T* p, int64_t n, T v) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) p[i] = v;
+}
+
+template <typename T>
+hipError_t launch_fill(T* p, int64_t n, T v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL((k_fill<T>), dim3(int(blocks)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+template <typename A, typename B>
+__global__ void k_cast(const A* a, B* b, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    b[i] = B(a[i]);
+}
+
+hipError_t launch_cast_d2f(const double* a, float* b, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL((k_cast<double, float>), dim3(int(blocks)), dim3(256), 0, s, a, b, n);
+  return hipGetLastError();
+}
+hipError_t launch_cast_f2d(const float* a, double* b, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL((k_cast<float, double>), dim3(int(blocks)), dim3(256), 0, s, a, b, n);
+  return hipGetLastError();
+}
+
+template hipError_t launch_spmv<double>(const SpmvDesc*, int, int, int, hipStream_t);
+template hipError_t launch_spmv<float>(const SpmvDesc*, int, int, int, hipStream_t);
+template hipError_t launch_prolong<double>(const ProlongDesc*, int, int, hipStream_t);
+template hipError_t launch_prolong<float>(const ProlongDesc*, int, int, hipStream_t);
+template hipError_t launch_fill<double>(double*, int64_t, double, hipStream_t);
+template hipError_t launch_fill<float>(float*, int64_t, float, hipStream_t);
+template hipError_t launch_fill<int32_t>(int32_t*, int64_t, int32_t, hipStream_t);
+
+}  // namespace nnms

@@ -1,0 +1,408 @@
+"""ctypes binding of libnnms (include/nnms.h): argument marshalling only.
+
+Every step of the solve runs inside the library's HIP kernels.  PyTorch is
+used, when requested, only as the device allocator and for streams.  If the
+built library is missing, importing this module raises: there is no
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnnms.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run paper_2412_08981_amd.build.build() first")
+_lib = C.CDLL(LIB_PATH)
+
+MAX_LEVELS = 8
+MAX_RESTART = 64
+FP64, MIXED = 0, 1
+DEVICE_PTRS, NO_GRAPH = 1, 2
+
+STATUS = {
+    0: "OK", 1: "INVALID_ARG", 2: "BAD_MESH", 3: "POINT_LOCATION", 4: "OUT_OF_MEMORY", 5: "BUDGET",
+    6: "SINGULAR", 7: "NOT_CONVERGED", 8: "DEVICE", 9: "IN_USE",
+}
+
+
+class NNMSError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.name = STATUS.get(code, str(code))
+
+
+class setup_opts(C.Structure):
+    _fields_ = [("nparts", C.c_int32 * MAX_LEVELS), ("overlap", C.c_int32), ("its", C.c_int32),
+                ("precision", C.c_int32), ("reserved", C.c_int32)]
+
+
+class level_info(C.Structure):
+    _fields_ = [("nv", C.c_int64), ("nt", C.c_int64), ("ninterior", C.c_int64), ("nnz", C.c_int64),
+                ("nparts", C.c_int32), ("max_block", C.c_int32), ("min_block", C.c_int32), ("reserved", C.c_int32),
+                ("s_total", C.c_int64), ("factor_elems", C.c_int64), ("p_nnz", C.c_int64)]
+
+
+class kappa_t(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("ncentres", C.c_int32), ("value", C.c_double),
+                ("centres", C.POINTER(C.c_double)), ("mu", C.POINTER(C.c_double)), ("width", C.c_double)]
+
+
+class solve_opts(C.Structure):
+    _fields_ = [("restart", C.c_int32), ("max_it", C.c_int32), ("rtol", C.c_double), ("flags", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class solve_info(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("cycles", C.c_int32), ("status", C.c_int32), ("reserved", C.c_int32),
+                ("relres", C.c_double)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class allocator_t(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p)]
+
+
+vp = C.c_void_p
+_sig = {
+    "nnms_last_error": (C.c_char_p, []),
+    "nnms_device_bytes_in_use": (C.c_int64, []),
+    "nnms_mesh_create": (C.c_int, [C.c_int64, vp, C.c_int64, vp, vp, C.POINTER(vp)]),
+    "nnms_mesh_destroy": (None, [vp]),
+    "nnms_setup_opts_default": (C.c_int, [C.POINTER(setup_opts)]),
+    "nnms_hierarchy_setup": (C.c_int, [vp, C.c_int32, C.POINTER(setup_opts), C.POINTER(allocator_t), vp, C.POINTER(vp)]),
+    "nnms_hierarchy_setup_host": (C.c_int, [vp, C.c_int32, C.POINTER(setup_opts), C.POINTER(vp)]),
+    "nnms_hierarchy_destroy": (C.c_int, [vp]),
+    "nnms_hierarchy_level_info": (C.c_int, [vp, C.c_int32, C.POINTER(level_info)]),
+    "nnms_hierarchy_csr": (C.c_int, [vp, C.c_int32, vp, vp]),
+    "nnms_hierarchy_partition": (C.c_int, [vp, C.c_int32, vp, vp, vp]),
+    "nnms_hierarchy_transfer": (C.c_int, [vp, C.c_int32, vp, vp]),
+    "nnms_hierarchy_system_bytes": (C.c_int64, [vp, C.c_int32]),
+    "nnms_assemble": (C.c_int, [vp, C.POINTER(kappa_t), C.c_double, vp, C.POINTER(vp)]),
+    "nnms_system_destroy": (C.c_int, [vp]),
+    "nnms_system_device_bytes": (C.c_int64, [vp]),
+    "nnms_system_rhs": (C.c_int, [vp, vp]),
+    "nnms_system_matrix": (C.c_int, [vp, C.c_int32, vp]),
+    "nnms_apply_operator": (C.c_int, [vp, C.c_int32, vp, vp, vp]),
+    "nnms_apply_smoother": (C.c_int, [vp, C.c_int32, vp, vp, vp]),
+    "nnms_apply_prolong": (C.c_int, [vp, C.c_int32, vp, vp, vp]),
+    "nnms_apply_restrict": (C.c_int, [vp, C.c_int32, vp, vp, vp]),
+    "nnms_apply_vcycle": (C.c_int, [vp, vp, vp, vp]),
+    "nnms_solve_opts_default": (C.c_int, [C.POINTER(solve_opts)]),
+    "nnms_solve": (C.c_int, [vp, vp, vp, C.POINTER(solve_opts), C.POINTER(solve_info), vp]),
+    "nnms_solve_batch": (C.c_int, [vp, C.c_int32, vp, vp, C.POINTER(solve_opts), C.POINTER(solve_info), vp]),
+    "nnms_batch_create": (C.c_int, [vp, C.c_int32, C.POINTER(solve_opts), vp, C.POINTER(vp)]),
+    "nnms_batch_start": (C.c_int, [vp, C.c_int32, vp]),
+    "nnms_batch_step": (C.c_int, [vp, C.c_int32, C.POINTER(C.c_int32)]),
+    "nnms_batch_result": (C.c_int, [vp, C.c_int32, vp, C.POINTER(solve_info)]),
+    "nnms_batch_destroy": (C.c_int, [vp]),
+    "nnms_time_kernel": (C.c_int, [vp, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double)]),
+    "nnms_system_factor": (C.c_int, [vp, C.c_int32, C.c_int32, vp, vp, C.POINTER(C.c_int32)]),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = sorted(_sig)
+
+
+def last_error() -> str:
+    return _lib.nnms_last_error().decode()
+
+
+def _check(code: int, ok=(0,)):
+    if code not in ok:
+        raise NNMSError(code, last_error())
+    return code
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def device_bytes_in_use() -> int:
+    return int(_lib.nnms_device_bytes_in_use())
+
+
+# ---------------------------------------------------------------------------
+class Mesh:
+    """nnms_mesh_create / nnms_mesh_destroy."""
+
+    def __init__(self, xyz: np.ndarray, tets: np.ndarray, dirichlet: Optional[np.ndarray] = None):
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        tets = np.ascontiguousarray(tets, dtype=np.int32)
+        d = None if dirichlet is None else np.ascontiguousarray(dirichlet, dtype=np.uint8)
+        h = C.c_void_p()
+        _check(_lib.nnms_mesh_create(xyz.shape[0], _ptr(xyz), tets.shape[0], _ptr(tets),
+                                     None if d is None else _ptr(d), C.byref(h)))
+        self.handle = h
+        self.nv = xyz.shape[0]
+
+    @classmethod
+    def from_workload(cls, m) -> "Mesh":
+        return cls(m.xyz, m.tets, m.dirichlet)
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            _lib.nnms_mesh_destroy(self.handle)
+            self.handle = None
+
+
+def _torch_allocator():
+    import torch
+
+    def _alloc(n, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(n))
+        except Exception:
+            return None
+
+    def _free(p, ctx):
+        torch.cuda.caching_allocator_delete(p)
+
+    fa, ff = ALLOC_FN(_alloc), FREE_FN(_free)
+    return allocator_t(fa, ff, None), (fa, ff)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Hierarchy:
+    """setup(hierarchy): nnms_hierarchy_setup (device) or _setup_host (host only)."""
+
+    def __init__(self, meshes: Sequence[Mesh], nparts: Sequence[int] = (), overlap: int = 1, its: int = 3,
+                 precision: int = FP64, device: bool = True, torch_alloc: bool = False, stream=None):
+        o = setup_opts()
+        _check(_lib.nnms_setup_opts_default(C.byref(o)))
+        for l, p in enumerate(nparts):
+            o.nparts[l] = int(p)
+        o.overlap, o.its, o.precision = overlap, its, precision
+        self.meshes = list(meshes)
+        arr = (C.c_void_p * len(meshes))(*[m.handle for m in meshes])
+        h = C.c_void_p()
+        self._keep = None
+        if device:
+            al = None
+            if torch_alloc:
+                al, self._keep = _torch_allocator()
+            _check(_lib.nnms_hierarchy_setup(arr, len(meshes), C.byref(o), None if al is None else C.byref(al),
+                                             _stream_ptr(stream), C.byref(h)))
+        else:
+            _check(_lib.nnms_hierarchy_setup_host(arr, len(meshes), C.byref(o), C.byref(h)))
+        self.handle = h
+        self.L = len(meshes)
+        self.precision = precision
+
+    def level_info(self, level: int) -> level_info:
+        li = level_info()
+        _check(_lib.nnms_hierarchy_level_info(self.handle, level, C.byref(li)))
+        return li
+
+    def csr(self, level: int):
+        li = self.level_info(level)
+        rp = np.empty(li.nv + 1, dtype=np.int32)
+        col = np.empty(li.nnz, dtype=np.int32)
+        _check(_lib.nnms_hierarchy_csr(self.handle, level, _ptr(rp), _ptr(col)))
+        return rp, col
+
+    def partition(self, level: int):
+        li = self.level_info(level)
+        owner = np.empty(li.nv, dtype=np.int32)
+        s_ptr = np.empty(li.nparts + 1, dtype=np.int64)
+        s_idx = np.empty(li.s_total, dtype=np.int32)
+        _check(_lib.nnms_hierarchy_partition(self.handle, level, _ptr(owner), _ptr(s_ptr), _ptr(s_idx)))
+        return owner, [s_idx[s_ptr[p]:s_ptr[p + 1]] for p in range(li.nparts)]
+
+    def transfer(self, level: int):
+        li = self.level_info(level)
+        idx = np.empty(li.nv * 4, dtype=np.int32)
+        w = np.empty(li.nv * 4, dtype=np.float64)
+        _check(_lib.nnms_hierarchy_transfer(self.handle, level, _ptr(idx), _ptr(w)))
+        return idx.reshape(-1, 4), w.reshape(-1, 4)
+
+    def system_bytes(self, restart: int = 30) -> int:
+        return int(_lib.nnms_hierarchy_system_bytes(self.handle, restart))
+
+    def destroy(self):
+        if getattr(self, "handle", None):
+            _check(_lib.nnms_hierarchy_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            _lib.nnms_hierarchy_destroy(self.handle)
+            self.handle = None
+
+
+def _kappa(kappa) -> tuple:
+    k = kappa_t()
+    keep = []
+    if kappa is None or getattr(kappa, "kind", "const") == "const":
+        k.kind, k.value = 0, float(1.0 if kappa is None else kappa.value)
+    else:
+        c = np.ascontiguousarray(kappa.centres, dtype=np.float64).ravel()
+        mu = np.ascontiguousarray(kappa.mu, dtype=np.float64)
+        keep = [c, mu]
+        k.kind, k.ncentres, k.width = 1, int(mu.shape[0]), float(kappa.width)
+        k.centres = c.ctypes.data_as(C.POINTER(C.c_double))
+        k.mu = mu.ctypes.data_as(C.POINTER(C.c_double))
+    return k, keep
+
+
+class System:
+    """assemble(mesh, kappa): nnms_assemble; operator applications; solve(b)."""
+
+    def __init__(self, h: Hierarchy, kappa=None, f: float = 1.0, stream=None):
+        k, keep = _kappa(kappa)
+        s = C.c_void_p()
+        _check(_lib.nnms_assemble(h.handle, C.byref(k), float(f), _stream_ptr(stream), C.byref(s)))
+        self.handle = s
+        self.h = h
+        self.n = [h.level_info(l).nv for l in range(h.L)]
+
+    def device_bytes(self) -> int:
+        return int(_lib.nnms_system_device_bytes(self.handle))
+
+    def rhs(self) -> np.ndarray:
+        b = np.empty(self.n[0])
+        _check(_lib.nnms_system_rhs(self.handle, _ptr(b)))
+        return b
+
+    def matrix_values(self, level: int) -> np.ndarray:
+        v = np.empty(self.h.level_info(level).nnz)
+        _check(_lib.nnms_system_matrix(self.handle, level, _ptr(v)))
+        return v
+
+    def _apply(self, fn, level, x, nout):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        y = np.empty(nout)
+        if level is None:
+            _check(fn(self.handle, _ptr(x), _ptr(y), None))
+        else:
+            _check(fn(self.handle, level, _ptr(x), _ptr(y), None))
+        return y
+
+    def apply_operator(self, level, x):
+        return self._apply(_lib.nnms_apply_operator, level, x, self.n[level])
+
+    def apply_smoother(self, level, r):
+        return self._apply(_lib.nnms_apply_smoother, level, r, self.n[level])
+
+    def apply_prolong(self, level, x):
+        return self._apply(_lib.nnms_apply_prolong, level, x, self.n[level])
+
+    def apply_restrict(self, level, x):
+        return self._apply(_lib.nnms_apply_restrict, level, x, self.n[level + 1])
+
+    def apply_vcycle(self, r):
+        return self._apply(_lib.nnms_apply_vcycle, None, r, self.n[0])
+
+    def factor(self, level: int, part: int):
+        """Stored factor tiles of one subdomain: (grid (N*64)^2, inv(L_ii) tiles [N,64,64])."""
+        N = C.c_int32()
+        _check(_lib.nnms_system_factor(self.handle, level, part, None, None, C.byref(N)))
+        lu = np.empty((N.value * 64, N.value * 64))
+        il = np.empty((N.value, 64, 64))
+        _check(_lib.nnms_system_factor(self.handle, level, part, _ptr(lu), _ptr(il), C.byref(N)))
+        return lu, il
+
+    def time_kernel(self, kind: int, level: int, reps: int = 10) -> float:
+        """Mean milliseconds of one launch (HIP events on the launch stream)."""
+        ms = C.c_double()
+        _check(_lib.nnms_time_kernel(self.handle, kind, level, reps, C.byref(ms)))
+        return ms.value
+
+    def solve(self, b: np.ndarray, restart: int = 30, rtol: float = 1e-8, max_it: int = 1000, graph: bool = True,
+              raise_on_fail: bool = True):
+        """Host vectors; returns (x, info)."""
+        o = solve_opts(restart, max_it, rtol, 0 if graph else NO_GRAPH, 0)
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        x = np.empty(self.n[0])
+        info = solve_info()
+        code = _lib.nnms_solve(self.handle, _ptr(b), _ptr(x), C.byref(o), C.byref(info), None)
+        if raise_on_fail:
+            _check(code)
+        return x, info
+
+    def solve_device(self, b_ptr: int, x_ptr: int, restart: int = 30, rtol: float = 1e-8, max_it: int = 1000,
+                     stream=None, graph: bool = True):
+        """Device pointers (e.g. torch tensors' data_ptr()); returns info."""
+        o = solve_opts(restart, max_it, rtol, DEVICE_PTRS | (0 if graph else NO_GRAPH), 0)
+        info = solve_info()
+        _check(_lib.nnms_solve(self.handle, C.c_void_p(b_ptr), C.c_void_p(x_ptr), C.byref(o), C.byref(info),
+                               _stream_ptr(stream)))
+        return info
+
+    def destroy(self):
+        if getattr(self, "handle", None):
+            _lib.nnms_system_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.destroy()
+
+
+def solve_batch(systems: Sequence[System], bs: Sequence[np.ndarray], restart: int = 30, rtol: float = 1e-8,
+                max_it: int = 1000, graph: bool = True):
+    """nnms_solve_batch with host vectors; returns (xs, infos)."""
+    nb = len(systems)
+    hs = (C.c_void_p * nb)(*[s.handle for s in systems])
+    bs = [np.ascontiguousarray(b, dtype=np.float64) for b in bs]
+    xs = [np.empty(s.n[0]) for s in systems]
+    bp = (C.c_void_p * nb)(*[b.ctypes.data for b in bs])
+    xp = (C.c_void_p * nb)(*[x.ctypes.data for x in xs])
+    infos = (solve_info * nb)()
+    o = solve_opts(restart, max_it, rtol, 0 if graph else NO_GRAPH, 0)
+    _check(_lib.nnms_solve_batch(hs, nb, bp, xp, C.byref(o), infos, None))
+    return xs, list(infos)
+
+
+class Batch:
+    """nnms_batch_*: slots advanced together, one Arnoldi step per launch sequence."""
+
+    def __init__(self, systems: Sequence[System], restart: int = 30, rtol: float = 1e-8, max_it: int = 1000,
+                 graph: bool = True, stream=None):
+        nb = len(systems)
+        self.systems = list(systems)
+        hs = (C.c_void_p * nb)(*[s.handle for s in systems])
+        o = solve_opts(restart, max_it, rtol, 0 if graph else NO_GRAPH, 0)
+        h = C.c_void_p()
+        _check(_lib.nnms_batch_create(hs, nb, C.byref(o), _stream_ptr(stream), C.byref(h)))
+        self.handle = h
+
+    def start(self, slot: int, b_ptr: int):
+        _check(_lib.nnms_batch_start(self.handle, slot, C.c_void_p(b_ptr)))
+
+    def step(self, iterations: int = 1) -> int:
+        a = C.c_int32()
+        _check(_lib.nnms_batch_step(self.handle, iterations, C.byref(a)))
+        return a.value
+
+    def result(self, slot: int, x_ptr: Optional[int]):
+        info = solve_info()
+        _check(_lib.nnms_batch_result(self.handle, slot, None if x_ptr is None else C.c_void_p(x_ptr),
+                                      C.byref(info)))
+        return info
+
+    def destroy(self):
+        if getattr(self, "handle", None):
+            _lib.nnms_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.destroy()

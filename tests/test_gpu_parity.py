@@ -1,0 +1,188 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances (FP64 path): assembly and transfers are the same sums in another
+order, so they agree to a few ulps relative to the row's largest term
+(1e-13); a subdomain solve amplifies rounding by the block's condition
+number (~1e4 here), so smoother and V-cycle outputs are compared to 1e-9
+relative; solves must reach relres <= 1e-8 and match the oracle's
+iteration count within one step, and the exact solution x* = A^{-1} b to
+1e-7 relative.  Mixed precision is compared against x* only.
+"""
+import sys
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import workloads as W
+from oracle import fem, problem as oprob, schwarz, transfer
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2412_08981_amd import nnms
+
+    return nnms
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+class Built:
+    def __init__(self, pb, precision=None):
+        nnms = _gpu()
+        prec = nnms.MIXED if (precision or pb.precision) == "mixed" else nnms.FP64
+        self.pb = pb
+        self.meshes = [nnms.Mesh.from_workload(m) for m in pb.meshes]
+        self.h = nnms.Hierarchy(self.meshes, pb.nparts, overlap=pb.overlap, its=pb.its, precision=prec)
+        self.s = nnms.System(self.h, pb.kappa, 1.0)
+
+
+@pytest.fixture(scope="module")
+def c1():
+    _say("[gpu] building config 1 (16^3 / 6^3, fp64)")
+    pb = W.config1()
+    return Built(pb), oprob.build(pb)
+
+
+@pytest.fixture(scope="module")
+def tiny3():
+    _say("[gpu] building a ragged 3-level case (13^3 / 7^3 / 4^3, log-Gaussian kappa)")
+    pb = W.Problem("tiny3", [W.kuhn_cube(13, 11), W.kuhn_cube(7, 12), W.kuhn_cube(4, 13)], [4, 2],
+                   W.kappa_draw(204, 205))
+    return Built(pb), oprob.build(pb)
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.mark.parametrize("case", ["c1", "tiny3"])
+def test_assembly_matches_oracle(case, request):
+    g, o = request.getfixturevalue(case)
+    for l in range(len(g.pb.meshes)):
+        rp, col = g.h.csr(l)
+        val = g.s.matrix_values(l)
+        A = sp.csr_matrix((val, col, rp), shape=(g.s.n[l], g.s.n[l]))
+        Ao = o.A[l]
+        diff = abs(A - Ao).max()
+        assert diff <= 1e-13 * abs(Ao).max(), (l, diff)
+    b = g.s.rhs()
+    assert np.abs(b - o.b).max() <= 1e-15 * np.abs(o.b).max() * 10
+
+
+@pytest.mark.parametrize("case", ["c1", "tiny3"])
+def test_operator_and_transfers(case, request):
+    g, o = request.getfixturevalue(case)
+    rng = np.random.default_rng(1)
+    for l in range(len(g.pb.meshes)):
+        x = rng.standard_normal(g.s.n[l])
+        x[g.pb.meshes[l].dirichlet != 0] = 0
+        y = g.s.apply_operator(l, x)
+        assert _rel(y, o.A[l] @ x) <= 1e-14
+        if l + 1 < len(g.pb.meshes):
+            xc = rng.standard_normal(g.s.n[l + 1])
+            assert _rel(g.s.apply_prolong(l, xc), o.P[l] @ xc) <= 1e-14
+            assert _rel(g.s.apply_restrict(l, x), o.P[l].T @ x) <= 1e-14
+
+
+@pytest.mark.parametrize("case", ["c1", "tiny3"])
+def test_smoother_and_coarse_solve(case, request):
+    g, o = request.getfixturevalue(case)
+    rng = np.random.default_rng(2)
+    L = len(g.pb.meshes)
+    for l in range(L):
+        r = rng.standard_normal(g.s.n[l])
+        r[g.pb.meshes[l].dirichlet != 0] = 0
+        z = g.s.apply_smoother(l, r)
+        if l < L - 1:
+            ref = o.vcycle.levels[l].ras.apply(r)
+        else:
+            ref = np.linalg.solve(o.A[l].toarray(), r)
+        assert _rel(z, ref) <= 1e-9, (l, _rel(z, ref))
+
+
+@pytest.mark.parametrize("case", ["c1", "tiny3"])
+def test_vcycle_matches_oracle(case, request):
+    g, o = request.getfixturevalue(case)
+    r = np.random.default_rng(3).standard_normal(g.s.n[0])
+    r[g.pb.meshes[0].dirichlet != 0] = 0
+    assert _rel(g.s.apply_vcycle(r), o.vcycle(r)) <= 1e-9
+
+
+@pytest.mark.parametrize("case", ["c1", "tiny3"])
+@pytest.mark.parametrize("graph", [True, False])
+def test_solve_matches_oracle(case, graph, request):
+    g, o = request.getfixturevalue(case)
+    ref = oprob.solve(o)
+    xs = oprob.exact(o)
+    x, info = g.s.solve(o.b, graph=graph)
+    assert info.status == 0 and info.relres <= 1e-8
+    assert abs(info.iterations - ref.iterations) <= 1
+    true = np.linalg.norm(o.b - o.A[0] @ x) / np.linalg.norm(o.b)
+    assert true <= 1e-8
+    assert _rel(x, xs) <= 1e-7
+    # a second solve on the same system reuses the plan and gives the same bits
+    x2, info2 = g.s.solve(o.b, graph=graph)
+    assert np.array_equal(x, x2) and info2.iterations == info.iterations
+
+
+def test_solve_edge_cases(c1):
+    g, o = c1
+    x, info = g.s.solve(np.zeros(g.s.n[0]))
+    assert info.iterations == 0 and np.all(x == 0)
+    # entries at Dirichlet vertices are ignored
+    b = o.b.copy()
+    b[g.pb.meshes[0].dirichlet != 0] = 5.0
+    x, info = g.s.solve(b)
+    assert np.all(x[g.pb.meshes[0].dirichlet != 0] == 0)
+    assert np.linalg.norm(o.b - o.A[0] @ x) <= 1e-8 * np.linalg.norm(o.b)
+    # iteration limit: x and info are still filled
+    x, info = g.s.solve(o.b, max_it=1, raise_on_fail=False)
+    assert info.status == 7 and info.iterations == 1 and np.isfinite(x).all()
+    # restart length 1 still converges (every step is a cycle)
+    x, info = g.s.solve(o.b, restart=1)
+    assert info.status == 0 and info.relres <= 1e-8
+
+
+def test_one_subdomain_no_overlap_is_exact():
+    nnms = _gpu()
+    pb = W.Problem("exact", [W.kuhn_cube(7, 41), W.kuhn_cube(3, 42)], [1], W.kappa_draw(1, 2), overlap=0)
+    g = Built(pb)
+    o = oprob.build(pb)
+    r = np.random.default_rng(4).standard_normal(g.s.n[0])
+    r[pb.meshes[0].dirichlet != 0] = 0
+    z = g.s.apply_smoother(0, r)
+    assert _rel(o.A[0] @ z, r) <= 1e-12
+
+
+def test_mixed_precision_small():
+    pb = W.Problem("mix", [W.kuhn_cube(13, 11), W.kuhn_cube(7, 12), W.kuhn_cube(4, 13)], [4, 2],
+                   W.kappa_draw(204, 205), precision="mixed")
+    g = Built(pb)
+    o = oprob.build(pb)
+    x, info = g.s.solve(o.b)
+    ref = oprob.solve(o)
+    xs = oprob.exact(o)
+    assert info.status == 0 and info.relres <= 1e-8
+    assert info.iterations <= int(np.ceil(1.1 * ref.iterations)) + 1
+    assert _rel(x, xs) <= 1e-7
+
+
+def test_batch_equals_alone(c1):
+    nnms = _gpu()
+    g1, o1 = c1
+    x1, i1 = g1.s.solve(o1.b)
+    # a second system on the c1 hierarchy with another kappa
+    s2 = nnms.System(g1.h, W.kappa_draw(7, 8), 1.0)
+    x2, i2 = s2.solve(o1.b)
+    xs, infos = nnms.solve_batch([g1.s, s2], [o1.b, o1.b])
+    assert np.array_equal(xs[0], x1) and np.array_equal(xs[1], x2)
+    assert infos[0].iterations == i1.iterations and infos[1].iterations == i2.iterations

@@ -1,0 +1,128 @@
+"""The library's host-side structure setup, called through the C ABI without a
+GPU, against the oracle's independent implementations (no GPU)."""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import schwarz, transfer
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+nnms = pytest.importorskip("paper_2412_08981_amd.nnms")
+
+
+def _host(problem, overlap=1):
+    ms = [nnms.Mesh.from_workload(m) for m in problem.meshes]
+    h = nnms.Hierarchy(ms, problem.nparts, overlap=overlap, device=False)
+    return ms, h
+
+
+def test_header_symbols_are_exported():
+    hdr = open(os.path.join(ROOT, "include", "nnms.h")).read()
+    declared = set(re.findall(r"\b(nnms_[a-z_]+)\s*\(", hdr))
+    out = subprocess.run(["nm", "-D", "--defined-only", nnms.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (nnms_[a-z_]+)", out))
+    assert declared, "no declarations found"
+    assert declared <= exported, declared - exported
+    assert declared <= set(nnms.EXPORTED) | {"nnms_mesh_destroy"}
+
+
+@pytest.mark.parametrize("cfg", ["c1", "tiny3"])
+def test_pattern_partition_transfer_match_oracle(cfg):
+    if cfg == "c1":
+        pb = W.config1()
+    else:
+        pb = W.Problem("tiny3", [W.kuhn_cube(9, 1), W.kuhn_cube(5, 2), W.kuhn_cube(3, 3)], [4, 2], W.KappaField())
+    ms, h = _host(pb)
+    for l, m in enumerate(pb.meshes):
+        rp, col = h.csr(l)
+        G = schwarz.vertex_graph(m.nv, m.tets).tocsr()
+        for i in range(m.nv):
+            row = col[rp[i]:rp[i + 1]]
+            if m.dirichlet[i]:
+                assert list(row) == [i]
+            else:
+                ref = G.indices[G.indptr[i]:G.indptr[i + 1]]
+                ref = np.sort(ref[m.dirichlet[ref] == 0])
+                assert np.array_equal(row, ref), i
+        if l < len(pb.meshes) - 1:
+            owned_o, sets_o = schwarz.partition(m, pb.nparts[l], pb.overlap)
+            owner, sets = h.partition(l)
+            assert len(sets) == len(sets_o)
+            for p, (S, So) in enumerate(zip(sets, sets_o)):
+                assert np.array_equal(S, So), p
+                assert np.array_equal(np.nonzero(owner == p)[0], np.sort(owned_o[p]))
+            idx, w = h.transfer(l)
+            P_lib = np.zeros((m.nv, pb.meshes[l + 1].nv))
+            for i in range(m.nv):
+                for a in range(4):
+                    P_lib[i, idx[i, a]] += w[i, a]
+            P_or = transfer.interpolation(m, pb.meshes[l + 1]).toarray()
+            assert np.abs(P_lib - P_or).max() <= 1e-14
+        else:
+            owner, sets = h.partition(l)
+            assert len(sets) == 1 and np.array_equal(sets[0], np.nonzero(m.dirichlet == 0)[0])
+
+
+def test_level_info_counts():
+    pb = W.config1()
+    ms, h = _host(pb)
+    li = h.level_info(0)
+    assert (li.nv, li.nt, li.nnz) == (4913, 24576, 46941)
+    assert li.ninterior == 15 ** 3 and li.nparts == 8
+    li1 = h.level_info(1)
+    assert li1.nparts == 1 and li1.ninterior == 125 and li1.max_block == 125
+
+
+def test_default_nparts_rule():
+    pb = W.Problem("d", [W.kuhn_cube(24, 1), W.kuhn_cube(12, 2), W.kuhn_cube(5, 3)], [0, 0], W.KappaField())
+    ms, h = _host(pb)
+    assert h.level_info(0).nparts == 8  # 15625 vertices
+    assert h.level_info(1).nparts == 2  # 2197 vertices
+    assert W.nparts_rule(117649) == 64 and W.nparts_rule(912673) == 512
+
+
+def test_bad_mesh_rejected():
+    m = W.kuhn_cube(2, 1)
+    tets = m.tets.copy()
+    tets[3, [1, 2]] = tets[3, [2, 1]]  # inverted
+    with pytest.raises(nnms.NNMSError) as e:
+        nnms.Mesh(m.xyz, tets, m.dirichlet)
+    assert e.value.name == "BAD_MESH"
+    tets = m.tets.copy()
+    tets[0, 0] = m.nv + 5
+    with pytest.raises(nnms.NNMSError) as e:
+        nnms.Mesh(m.xyz, tets, m.dirichlet)
+    assert e.value.name == "BAD_MESH"
+
+
+def test_point_location_error():
+    f = W.kuhn_cube(4, 1)
+    c = W.kuhn_cube(3, 2)
+    xyz = c.xyz * 0.5  # coarse mesh covers only [0, 0.5]^3
+    mf, mc = nnms.Mesh.from_workload(f), nnms.Mesh(xyz, c.tets, c.dirichlet)
+    with pytest.raises(nnms.NNMSError) as e:
+        nnms.Hierarchy([mf, mc], [2], device=False)
+    assert e.value.name == "POINT_LOCATION"
+
+
+def test_invalid_options():
+    pb = W.config1()
+    ms = [nnms.Mesh.from_workload(m) for m in pb.meshes]
+    with pytest.raises(nnms.NNMSError) as e:
+        nnms.Hierarchy(ms, [6], device=False)  # not a power of two
+    assert e.value.name == "INVALID_ARG"
+    with pytest.raises(nnms.NNMSError):
+        nnms.Hierarchy(ms, [8], its=0, device=False)
+
+
+def test_dirichlet_default_is_bounding_box():
+    m = W.kuhn_cube(3, 4)
+    a = nnms.Mesh(m.xyz, m.tets, None)
+    h = nnms.Hierarchy([a], [], device=False)
+    owner, sets = h.partition(0)
+    assert np.array_equal(owner >= 0, m.dirichlet == 0)
