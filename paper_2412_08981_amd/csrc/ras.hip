@@ -13,12 +13,34 @@
 // atomic ticket: a work-group only ever waits on tickets drawn before its
 // own, by work-groups that are already running, so the schedule cannot
 // deadlock; every wait is additionally bounded.
+//
+// Block results and flags travel through device-coherent (agent-scope)
+// relaxed atomic loads and stores; a block's results are complete (the
+// wave's stores acknowledged) before its flag is stored.  This avoids a
+// full L2 write-back / invalidate per block, which is what an agent-scope
+// release / acquire pair costs on this GPU.
 #include "devcommon.h"
 #include "kernels.h"
 
 namespace nnms {
 
 constexpr int SPIN_LIMIT = 1 << 22;
+
+template <typename F>
+__device__ __forceinline__ F ld_coh(const F* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename F>
+__device__ __forceinline__ void st_coh(F* p, F v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// all memory operations of this wave issued so far are complete
+__device__ __forceinline__ void wave_drain() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
 
 template <typename F, typename V>
 __global__ __launch_bounds__(256) void k_ras(RasLaunch P, int32_t* err) {
@@ -31,15 +53,16 @@ __global__ __launch_bounds__(256) void k_ras(RasLaunch P, int32_t* err) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int epoch = atomic_load_acq(P.counter + 1) + 1;
 
-  auto wait_flag = [&](const int32_t* fl) {
+  auto spin = [&](const int32_t* fl) {
     int spins = 0;
-    while (atomic_load_acq(fl) != epoch) {
-      __builtin_amdgcn_s_sleep(2);
+    while (atomic_load_rlx(fl) != epoch) {
+      __builtin_amdgcn_s_sleep(1);
       if (++spins > SPIN_LIMIT) {
         if (lane == 0) atomicOr(err, 2);
         break;
       }
     }
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
   };
 
   for (;;) {
@@ -62,11 +85,25 @@ __global__ __launch_bounds__(256) void k_ras(RasLaunch P, int32_t* err) {
     const F* __restrict__ fac = (const F*)S.fac;
     F* yx = (F*)S.yx;
     const size_t NN = size_t(N) * N;
+    const int32_t* fwd_flags = P.flags + S.flag0;
+    const int32_t* bwd_flags = fwd_flags + N;
 
     auto load_tile = [&](size_t tix, C (&reg)[NQ]) {
       const C* base = (const C*)(fac + tix * TILE_ELEMS);
 #pragma unroll
       for (int q = 0; q < NQ; ++q) reg[q] = __builtin_nontemporal_load(base + (wave + 4 * q) * 64 + lane);
+    };
+    // acc += tile . y (y distributed one value per lane)
+    auto gemv = [&](const C (&A)[NQ], F yl, F& acc) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        C yv;
+        F* e = (F*)&yv;
+        const int c0 = (wave + 4 * q) * W;
+#pragma unroll
+        for (int k = 0; k < W; ++k) e[k] = __shfl(yl, c0 + k, 64);
+        acc += chunk_dot(A[q], yv);
+      }
     };
 
     F acc = 0, bval = 0;
@@ -78,35 +115,43 @@ __global__ __launch_bounds__(256) void k_ras(RasLaunch P, int32_t* err) {
         bval = (g != -1) ? F(((const V*)S.rin)[gg]) : F(0);
       }
       load_tile(i > 0 ? size_t(i) * N : NN + i, A);
+      int ready = -1;  // forward blocks known to be complete: 0..ready
       for (int j = 0; j < i; ++j) {
-        wait_flag(P.flags + S.flag0 + j);
-        C yv[NQ];
-        const C* yc = (const C*)(yx + j * 64);
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) yv[q] = yc[wave + 4 * q];
-        load_tile(j + 1 < i ? size_t(i) * N + j + 1 : NN + i, B);
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-          acc += chunk_dot(A[q], yv[q]);
-          A[q] = B[q];
+        if (j > ready) {
+          if (atomic_load_rlx(fwd_flags + i - 1) == epoch) {
+            ready = i - 1;
+          } else {
+            spin(fwd_flags + j);
+            ready = j;
+          }
+          __atomic_signal_fence(__ATOMIC_SEQ_CST);
         }
+        const F yl = ld_coh(yx + j * 64 + lane);
+        load_tile(j + 1 < i ? size_t(i) * N + j + 1 : NN + i, B);
+        gemv(A, yl, acc);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) A[q] = B[q];
       }
     } else {
-      wait_flag(P.flags + S.flag0 + N - 1);  // every forward block of this subdomain is done
-      if (wave == 0) bval = yx[i * 64 + lane];
+      spin(fwd_flags + N - 1);  // every forward block of this subdomain is complete
+      if (wave == 0) bval = ld_coh(yx + i * 64 + lane);
       load_tile(size_t(i) * N + (i < N - 1 ? N - 1 : i), A);
+      int ready = N;  // backward blocks known to be complete: ready..N-1
       for (int j = N - 1; j > i; --j) {
-        wait_flag(P.flags + S.flag0 + N + j);
-        C yv[NQ];
-        const C* yc = (const C*)(yx + j * 64);
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) yv[q] = yc[wave + 4 * q];
-        load_tile(size_t(i) * N + (j - 1 > i ? j - 1 : i), B);
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-          acc += chunk_dot(A[q], yv[q]);
-          A[q] = B[q];
+        if (j < ready) {
+          if (atomic_load_rlx(bwd_flags + i + 1) == epoch) {
+            ready = i + 1;
+          } else {
+            spin(bwd_flags + j);
+            ready = j;
+          }
+          __atomic_signal_fence(__ATOMIC_SEQ_CST);
         }
+        const F yl = ld_coh(yx + j * 64 + lane);
+        load_tile(size_t(i) * N + (j - 1 > i ? j - 1 : i), B);
+        gemv(A, yl, acc);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) A[q] = B[q];
       }
     }
     red[wave][lane] = acc;
@@ -123,7 +168,7 @@ __global__ __launch_bounds__(256) void k_ras(RasLaunch P, int32_t* err) {
     __syncthreads();
     if (wave == 0) {
       const F out = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
-      yx[i * 64 + lane] = out;
+      st_coh(yx + i * 64 + lane, out);
       if (dir == 1) {
         const int g = S.gidx[i * 64 + lane];
         if (g >= 0) {
@@ -131,8 +176,8 @@ __global__ __launch_bounds__(256) void k_ras(RasLaunch P, int32_t* err) {
           z[g] = P.add ? V(z[g] + V(out)) : V(out);
         }
       }
-      __threadfence();
-      if (lane == 0) atomic_store_rel(P.flags + S.flag0 + dir * N + i, epoch);
+      wave_drain();
+      if (lane == 0) __hip_atomic_store(P.flags + S.flag0 + dir * N + i, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
 }
