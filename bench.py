@@ -20,6 +20,35 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_ras_c2_{prec}_pmc.md")
+
+
+def source_hash():
+    """Hash of the smoother kernel's source: counter summaries taken from an
+    older kernel are not reported."""
+    import hashlib
+    path = os.path.join(ROOT, "paper_2412_08981_amd", "csrc", "ras.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def load_traffic(prec):
+    """HBM bytes per launch of the fine-level smoother from the committed
+    rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, scaled by the same
+    counters on a plain copy of known size), or None when absent or stale."""
+    path = PMC_SUMMARY.format(prec=prec)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip().lstrip("- ").strip()] = v.strip()
+    if kv.get("ras_hip_sha256_16") != source_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def log(*a):
@@ -72,6 +101,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="run the copy reference and the fine-level smoother a few times each (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -93,6 +124,15 @@ def main():
     s = nnms.System(h, pb.kappa, 1.0)
     t2 = time.perf_counter()
     log(f"[bench] structure setup {t1 - t0:.2f} s, numeric setup (assembly + LU) {t2 - t1:.3f} s")
+    if args.kernels_only:
+        sb = 8 if prec == nnms.FP64 else 4
+        fac_bytes = h.level_info(0).factor_elems * sb
+        ms_copy = s.time_kernel(4, 0, reps=3)
+        ms_ras = s.time_kernel(0, 0, reps=3)
+        print(json.dumps({"copy_bytes": (fac_bytes // 16) * 16, "copy_launches": 4, "copy_ms": ms_copy,
+                          "ras_launches": 4, "ras_ms": ms_ras, "ras_algorithmic_bytes": ras_bytes(h, 0, sb),
+                          "ras_hip_sha256_16": source_hash()}))
+        return
     b = s.rhs()
     n0 = s.n[0]
     bd = torch.from_numpy(b).cuda()
@@ -152,7 +192,7 @@ def main():
                    "iterations": info.iterations, "relres": info.relres,
                    "numeric_setup_s": round(t_assemble, 4), "structure_setup_s": round(t1 - t0, 3)},
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": load_traffic(args.precision),
                      "kernel": "k_ras (fine-level smoother)", "ms": round(ms, 4)},
         "kernels": extra,
     }

@@ -229,7 +229,9 @@ nnms_status nnms_apply_vcycle(nnms_system* s, const double* r_host, double* z_ho
  * current level vectors; *ms_host receives the mean milliseconds per
  * launch.  kind: 0 smoother (restricted additive Schwarz apply, or the
  * coarsest direct solve), 1 level operator residual t = r - A z,
- * 2 prolongation, 3 restriction.  reps >= 1.
+ * 2 prolongation, 3 restriction, 4 a plain 16-byte streaming copy of the
+ * level's factor storage into a temporary buffer (a reference of known
+ * size for hardware byte counters).  reps >= 1.
  * ------------------------------------------------------------------------- */
 nnms_status nnms_time_kernel(nnms_system* s, int32_t kind, int32_t level, int32_t reps, double* ms_host);
 

@@ -122,3 +122,17 @@ template hipError_t launch_fill<float>(float*, int64_t, float, hipStream_t);
 template hipError_t launch_fill<int32_t>(int32_t*, int64_t, int32_t, hipStream_t);
 
 }  // namespace nnms
+
+namespace nnms {
+// plain streaming copy in 16-byte units (calibration of byte counters)
+__global__ __launch_bounds__(256) void k_copy16(const int4* __restrict__ a, int4* __restrict__ b, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) b[i] = a[i];
+}
+hipError_t launch_copy16(const void* a, void* b, int64_t bytes, hipStream_t s) {
+  const int64_t n = bytes / 16;
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 256 * 16);
+  hipLaunchKernelGGL(k_copy16, dim3(int(blocks)), dim3(256), 0, s, (const int4*)a, (int4*)b, n);
+  return hipGetLastError();
+}
+}  // namespace nnms
