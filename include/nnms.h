@@ -278,7 +278,13 @@ nnms_status nnms_solve(nnms_system* s, const double* b, double* x, const nnms_so
  * on.  Each system's arithmetic is independent of its batch neighbours, so
  * its result is the same alone and in any batch.
  *
- * nnms_batch_create   bind systems to the slots of a batch (nb >= 1).
+ * nnms_batch_create   bind systems to the slots of a batch (nb >= 1).  A
+ *                     slot keeps its system's solve state: a freshly
+ *                     assembled system is idle, and a system still
+ *                     iterating in another batch continues from where it
+ *                     is (this is how a serving loop re-forms its batch
+ *                     when requests join or leave).  A system must not be
+ *                     stepped by two batches at the same time.
  * nnms_batch_start    begin solving in `slot` with right-hand side b
  *                     (device pointer, nv_0 doubles; copied).
  * nnms_batch_step     run up to `iterations` Arnoldi steps on every active

@@ -1089,12 +1089,9 @@ extern "C" nnms_status nnms_batch_create(nnms_system* const* systems, int32_t nb
   bt->plan = make_plan_any(sys, true);
   bt->plan->use_graph = !(bt->opts.flags & NNMS_NO_GRAPH);
   join_in((hipStream_t)stream, bt->plan->stream);
-  // every slot starts idle
-  for (int k = 0; k < nb; ++k) {
-    int32_t idle = ST_IDLE;
-    HIP_CHECK(hipMemcpyAsync(&sys[k]->st->status, &idle, sizeof idle, hipMemcpyHostToDevice, bt->plan->stream));
-    HIP_CHECK(hipStreamSynchronize(bt->plan->stream));
-  }
+  // slots keep their systems' solve state: a freshly assembled system is
+  // idle, a system still iterating in an earlier batch goes on here
+  HIP_CHECK(hipStreamSynchronize(bt->plan->stream));
   *out = bt.release();
   return NNMS_OK;
   ABI_END
