@@ -148,6 +148,81 @@ def run_batched(args):
     print(json.dumps(out))
 
 
+def run_serving(args):
+    """Config 5: Poisson arrivals of parametric solve requests over three
+    resident hierarchies (jittered 32^3, 64^3, 96^3 fine meshes, three levels
+    each), device-memory budget admission, continuous batching.  The closed-
+    loop capacity is measured first (requests all queued at t = 0), then an
+    open-loop Poisson trace at 0.7x that capacity gives p50 / p99 latency.
+    Both precisions are run on the same requests."""
+    import torch
+    import workloads as W
+    from paper_2412_08981_amd import nnms
+    from paper_2412_08981_amd.serve import Request, Server
+
+    sizes = (32, 64, 96)
+    centres = W.config5_centres()
+    t, hs_choice, mus = W.config5_trace(nreq=args.requests, rate=1.0, sizes=sizes)
+    res = {}
+    for precision in ("mixed", "fp64"):
+        prec = nnms.MIXED if precision == "mixed" else nnms.FP64
+        t0 = time.perf_counter()
+        hier, keep = {}, []
+        for n in sizes:
+            meshes = W.config5_hierarchy(n)
+            ms = [nnms.Mesh.from_workload(m) for m in meshes]
+            nps = [W.nparts_rule(m.nv) for m in meshes[:-1]]
+            hier[n] = nnms.Hierarchy(ms, nps, precision=prec)
+            keep.append(ms)
+        log(f"[bench c5] {precision}: hierarchies set up in {time.perf_counter() - t0:.1f} s; bytes per request "
+            f"{ {n: round(h.system_bytes() / 2**30, 2) for n, h in hier.items()} } GiB")
+
+        def make(ids, times):
+            return [Request(int(i), int(hs_choice[i]),
+                            W.KappaField("loggauss", centres=centres, mu=mus[i], width=W.KAPPA_WIDTH), float(tt))
+                    for i, tt in zip(ids, times)]
+
+        # closed-loop capacity: a burst of requests at t = 0
+        nb = min(args.requests, args.burst)
+        srv = Server(hier, args.budget_gib * 2**30)
+        st_cap = srv.run(make(range(nb), np.zeros(nb)))
+        cap = st_cap["solves_per_s"]
+        # open loop: Poisson arrivals at 0.7x capacity (exponential gaps, seeded)
+        gaps = np.random.default_rng(5001).exponential(1.0 / (0.7 * cap), size=args.requests)
+        srv = Server(hier, args.budget_gib * 2**30)
+        st = srv.run(make(range(args.requests), np.cumsum(gaps)))
+        st["rate_per_s"] = 0.7 * cap
+        st["capacity_solves_per_s"] = cap
+        st["batch_forms"] = srv.batch_forms
+        st["steps"] = srv.steps
+        res[precision] = st
+        log(f"[bench c5] {precision}: {st}")
+        del srv, hier, keep
+        torch.cuda.synchronize()
+    m = res["mixed"]
+    out = {
+        "metric": "solves/s to rel-res 1e-8 (continuous-batching serving), p50/p99 latency",
+        "value": round(m["capacity_solves_per_s"], 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.requests,
+        "warmup": 0,
+        "ms_per_step": round(1e3 / m["capacity_solves_per_s"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"serving: {args.requests} Poisson requests over resident jittered 32^3/64^3/96^3 "
+                               f"hierarchies (3 levels), budget {args.budget_gib} GiB, mixed precision",
+                   "p50_ms": m.get("p50_ms"), "p99_ms": m.get("p99_ms"), "open_loop_solves_per_s": m.get("solves_per_s"),
+                   "fp64": res["fp64"],
+                   "mixed": m,
+                   "mixed_over_fp64_capacity": round(m["capacity_solves_per_s"] / res["fp64"]["capacity_solves_per_s"], 3)},
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -156,8 +231,11 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c4"],
-                    help="c2: the three-level 48^3 problem (default); c4: batched parametric instances")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c4", "c5"],
+                    help="c2: the three-level 48^3 problem (default); c4: batched parametric instances; c5: serving")
+    ap.add_argument("--requests", type=int, default=60, help="requests of the serving trace")
+    ap.add_argument("--burst", type=int, default=18, help="requests of the closed-loop capacity run")
+    ap.add_argument("--budget-gib", type=float, default=160.0, help="device-memory budget of the serving loop")
     ap.add_argument("--batch", type=int, default=32, help="instances of the batched workload")
     ap.add_argument("--kernels-only", action="store_true",
                     help="run the copy reference and the fine-level smoother a few times each (for counter runs)")
@@ -175,6 +253,8 @@ def main():
     torch.cuda.init()
     if args.workload == "c4":
         return run_batched(args)
+    if args.workload == "c5":
+        return run_serving(args)
     pb = W.config2(args.precision)
     prec = nnms.MIXED if args.precision == "mixed" else nnms.FP64
     t0 = time.perf_counter()

@@ -261,9 +261,9 @@ typedef struct {
 typedef struct {
   int32_t iterations;
   int32_t cycles;
-  int32_t status;   /* nnms_status of this right-hand side */
-  int32_t reserved;
-  double relres;    /* true ||b - A x|| / ||b|| at the end */
+  int32_t status;   /* nnms_status of this right-hand side (NOT_CONVERGED while running) */
+  int32_t running;  /* 1 while the slot is still iterating, else 0 */
+  double relres;    /* true ||b - A x|| / ||b|| at the last cycle end */
 } nnms_solve_info;
 
 nnms_status nnms_solve_opts_default(nnms_solve_opts* o);

@@ -1001,6 +1001,7 @@ static nnms_solve_info read_info(nnms_system* s, hipStream_t st) {
   in.cycles = ks.cycles;
   in.relres = ks.relres;
   in.status = ks.status == ST_CONVERGED ? NNMS_OK : NNMS_ERR_NOT_CONVERGED;
+  in.running = ks.status == ST_RUNNING ? 1 : 0;
   return in;
 }
 

@@ -60,7 +60,7 @@ class solve_opts(C.Structure):
 
 
 class solve_info(C.Structure):
-    _fields_ = [("iterations", C.c_int32), ("cycles", C.c_int32), ("status", C.c_int32), ("reserved", C.c_int32),
+    _fields_ = [("iterations", C.c_int32), ("cycles", C.c_int32), ("status", C.c_int32), ("running", C.c_int32),
                 ("relres", C.c_double)]
 
 

@@ -1,0 +1,191 @@
+"""Continuous-batching serving loop over resident mesh hierarchies.
+
+Requests (a hierarchy and a parameter of the coefficient) arrive over time.
+A request is admitted when the device-memory budget has room for its system
+(values, factors, Krylov workspace); its numeric setup (assembly + LU) runs
+on a worker thread and its own stream, overlapping the solves in flight.
+Every solve in flight advances one Arnoldi step per launch sequence of the
+library's batch engine; when requests finish or new ones are ready, the
+batch is re-formed at the next step boundary (each system keeps its solve
+state on the device, so a re-formed batch continues where it was).  The
+structure of every hierarchy (partition, transfers, patterns) is set up once
+and reused by every request on it (the paper's parametric reuse of the mesh
+hierarchy, Section 1 and Section 2.1).
+
+Each system's arithmetic is independent of its batch neighbours, so a
+request's result is the same alone and in the mix.
+"""
+from __future__ import annotations
+
+import threading
+import time
+from collections import deque
+from concurrent.futures import ThreadPoolExecutor
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional
+
+import numpy as np
+
+from . import nnms
+
+
+@dataclass
+class Request:
+    rid: int
+    key: object  # hierarchy key
+    kappa: object  # workloads.KappaField-like (kind/value/centres/mu/width)
+    t_arrival: float  # seconds after the start of the run
+    b: Optional[np.ndarray] = None  # None: the assembled load vector
+    t_admit: float = float("nan")
+    t_ready: float = float("nan")
+    t_done: float = float("nan")
+    status: str = "queued"  # queued, rejected, assembling, solving, done, failed
+    iterations: int = 0
+    relres: float = float("nan")
+    x: Optional[np.ndarray] = None
+    nbytes: int = 0
+    error: str = ""
+
+
+class Server:
+    def __init__(self, hierarchies: Dict[object, "nnms.Hierarchy"], budget_bytes: int, restart: int = 30,
+                 rtol: float = 1e-8, max_it: int = 1000, graph: bool = False, keep_x: bool = False,
+                 workers: int = 1):
+        import torch
+
+        self.torch = torch
+        self.h = hierarchies
+        self.budget = int(budget_bytes)
+        self.used = 0
+        self.restart, self.rtol, self.max_it, self.graph = restart, rtol, max_it, graph
+        self.keep_x = keep_x
+        self.sizes = {k: h.system_bytes(restart) for k, h in hierarchies.items()}
+        self.pool = ThreadPoolExecutor(max_workers=workers)
+        self.streams = [torch.cuda.Stream() for _ in range(workers)]
+        self._tls = threading.local()
+        self._stream_ix = 0
+        self._lock = threading.Lock()
+        self.batch_forms = 0
+        self.steps = 0
+
+    # numeric setup on a worker thread and its own stream
+    def _assemble(self, req: Request):
+        with self._lock:
+            if not hasattr(self._tls, "stream"):
+                self._tls.stream = self.streams[self._stream_ix % len(self.streams)]
+                self._stream_ix += 1
+        st = self._tls.stream
+        s = nnms.System(self.h[req.key], req.kappa, 1.0, stream=st)
+        b = s.rhs() if req.b is None else np.asarray(req.b, dtype=np.float64)
+        bd = self.torch.from_numpy(b).to("cuda")
+        self.torch.cuda.current_stream().synchronize()
+        return s, bd
+
+    def run(self, requests: List[Request], log=None) -> dict:
+        torch = self.torch
+        reqs = sorted(requests, key=lambda r: r.t_arrival)
+        arrivals = deque(reqs)
+        queue: deque = deque()
+        assembling = {}  # future -> req
+        active: List[tuple] = []  # (req, system, bdev)
+        ready: List[tuple] = []
+        batch = None
+        t0 = time.perf_counter()
+        now = lambda: time.perf_counter() - t0
+        remaining = len(reqs)
+        while remaining > 0:
+            t = now()
+            while arrivals and arrivals[0].t_arrival <= t:
+                r = arrivals.popleft()
+                r.nbytes = self.sizes[r.key]
+                if r.nbytes > self.budget:
+                    r.status, r.error = "rejected", "exceeds the device-memory budget"
+                    remaining -= 1
+                else:
+                    queue.append(r)
+            # admission in arrival order while the budget has room
+            while queue and self.used + queue[0].nbytes <= self.budget:
+                r = queue.popleft()
+                self.used += r.nbytes
+                r.t_admit, r.status = now(), "assembling"
+                assembling[self.pool.submit(self._assemble, r)] = r
+            for fut in [f for f in assembling if f.done()]:
+                r = assembling.pop(fut)
+                try:
+                    s, bd = fut.result()
+                    r.t_ready, r.status = now(), "solving"
+                    ready.append((r, s, bd))
+                except Exception as e:  # assembly failed: release its budget
+                    r.status, r.error, r.t_done = "failed", str(e), now()
+                    self.used -= r.nbytes
+                    remaining -= 1
+            if ready:
+                # re-form the batch with the newcomers
+                old = batch
+                members = active + ready
+                batch = nnms.Batch([m[1] for m in members], self.restart, self.rtol, self.max_it, graph=self.graph)
+                self.batch_forms += 1
+                if old is not None:
+                    old.destroy()
+                for k in range(len(active), len(members)):
+                    batch.start(k, members[k][2].data_ptr())
+                active, ready = members, []
+            if batch is None or not active:
+                # idle: wait for the next arrival or assembly
+                time.sleep(0.0005)
+                continue
+            batch.step(1)
+            self.steps += 1
+            finished, still = [], []
+            for k, (r, s, bd) in enumerate(active):
+                xo = None
+                if self.keep_x:
+                    xo = torch.empty(s.n[0], dtype=torch.float64, device="cuda")
+                info = batch.result(k, None if xo is None else xo.data_ptr())
+                if not info.running:
+                    r.iterations, r.relres = info.iterations, info.relres
+                    r.status = "done" if info.status == 0 else "failed"
+                    if xo is not None:
+                        torch.cuda.synchronize()
+                        r.x = xo.cpu().numpy()
+                    r.t_done = now()
+                    finished.append((r, s, bd))
+                else:
+                    still.append((r, s, bd))
+            if finished:
+                old = batch
+                batch = (nnms.Batch([m[1] for m in still], self.restart, self.rtol, self.max_it, graph=self.graph)
+                         if still else None)
+                self.batch_forms += 1
+                old.destroy()
+                for r, s, bd in finished:
+                    s.destroy()
+                    self.used -= r.nbytes
+                    remaining -= 1
+                    if log:
+                        log(f"[serve] request {r.rid} ({r.key}) done: {r.iterations} its, latency "
+                            f"{1e3 * (r.t_done - r.t_arrival):.1f} ms")
+                active = still
+        if batch is not None:
+            batch.destroy()
+        self.pool.shutdown(wait=True)
+        return self.stats(reqs)
+
+    @staticmethod
+    def stats(reqs: List[Request]) -> dict:
+        done = [r for r in reqs if r.status == "done"]
+        lat = np.array([r.t_done - r.t_arrival for r in done])
+        out = {"requests": len(reqs), "completed": len(done),
+               "rejected": sum(r.status == "rejected" for r in reqs),
+               "failed": sum(r.status == "failed" for r in reqs)}
+        if done:
+            span = max(r.t_done for r in done) - min(r.t_arrival for r in reqs)
+            out.update({
+                "solves_per_s": len(done) / span if span > 0 else float("nan"),
+                "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                "mean_ms": float(lat.mean() * 1e3),
+                "max_relres": float(max(r.relres for r in done)),
+                "iterations_mean": float(np.mean([r.iterations for r in done])),
+            })
+        return out

@@ -1,0 +1,69 @@
+"""Continuous-batching serving loop: requests that arrive while others are on
+the GPU join the running batch as memory frees up; each result equals the
+same request solved alone (bitwise), and requests larger than the budget are
+rejected."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(precision):
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2412_08981_amd import nnms
+
+    prec = nnms.MIXED if precision == "mixed" else nnms.FP64
+    hier, keep = {}, []
+    for k, n in enumerate((10, 14, 18)):
+        meshes = W.make_hierarchy(W.coarse_sizes(n), [900 + 10 * k + l for l in range(3)])
+        ms = [nnms.Mesh.from_workload(m) for m in meshes]
+        hier[n] = nnms.Hierarchy(ms, [W.nparts_rule(m.nv) for m in meshes[:-1]], precision=prec)
+        keep.append(ms)
+    return nnms, hier, keep
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_serving_results_equal_alone(precision):
+    nnms, hier, keep = _setup(precision)
+    from paper_2412_08981_amd.serve import Request, Server
+
+    rng = np.random.default_rng(3)
+    centres = W.config5_centres()
+    keys = list(hier)
+    reqs = []
+    t = 0.0
+    for i in range(12):
+        t += rng.exponential(0.004)
+        mu = rng.uniform(-2, 2, size=8)
+        reqs.append(Request(i, keys[i % 3], W.KappaField("loggauss", centres=centres, mu=mu, width=0.02), t))
+    # budget for about two requests at once: later arrivals wait for memory
+    budget = 2.5 * max(h.system_bytes() for h in hier.values())
+    srv = Server(hier, budget, keep_x=True)
+    st = srv.run(reqs)
+    assert st["completed"] == 12 and st["rejected"] == 0
+    assert srv.batch_forms >= 3
+    for r in reqs:
+        s = nnms.System(hier[r.key], r.kappa)
+        x, info = s.solve(s.rhs())
+        assert info.iterations == r.iterations and info.status == 0
+        assert np.array_equal(x, r.x), r.rid
+        s.destroy()
+
+
+def test_oversized_request_is_rejected():
+    nnms, hier, keep = _setup("mixed")
+    from paper_2412_08981_amd.serve import Request, Server
+
+    small = min(hier, key=lambda k: hier[k].system_bytes())
+    big = max(hier, key=lambda k: hier[k].system_bytes())
+    budget = hier[small].system_bytes() * 1.01
+    kap = W.KappaField("loggauss", centres=W.config5_centres(), mu=np.zeros(8), width=0.02)
+    reqs = [Request(0, big, kap, 0.0), Request(1, small, kap, 0.0)]
+    st = Server(hier, budget).run(reqs)
+    assert reqs[0].status == "rejected" and reqs[1].status == "done"
+    assert st["rejected"] == 1 and st["completed"] == 1
