@@ -112,6 +112,8 @@ def run_batched(args):
         hs.append(h)
         ss.append(s)
         bs.append(s.rhs())
+    from paper_2412_08981_amd import autotune
+    tuning = autotune.tune(ss[0], cache=args.tuning_cache)
     torch.cuda.synchronize()
     log(f"[bench c4] {len(ss)} instances set up in {time.perf_counter() - t0:.1f} s, "
         f"sizes {[int(pb.meshes[0].n) for pb in probs]}")
@@ -143,7 +145,7 @@ def run_batched(args):
                    "sequential_solves_per_s": round(len(ss) / el_seq, 3),
                    "batch_gain": round(el_seq / el, 3),
                    "iterations": its, "max_relres": max(i.relres for i in infos),
-                   "batch_equals_alone_bitwise": bool(same)},
+                   "batch_equals_alone_bitwise": bool(same), "tuning": tuning},
     }
     print(json.dumps(out))
 
@@ -174,6 +176,11 @@ def run_serving(args):
             nps = [W.nparts_rule(m.nv) for m in meshes[:-1]]
             hier[n] = nnms.Hierarchy(ms, nps, precision=prec)
             keep.append(ms)
+        from paper_2412_08981_amd import autotune
+        for n in sizes:
+            sample = nnms.System(hier[n], W.KappaField("loggauss", centres=centres, mu=mus[0], width=W.KAPPA_WIDTH))
+            autotune.tune(sample, cache=args.tuning_cache)
+            sample.destroy()
         log(f"[bench c5] {precision}: hierarchies set up in {time.perf_counter() - t0:.1f} s; bytes per request "
             f"{ {n: round(h.system_bytes() / 2**30, 2) for n, h in hier.items()} } GiB")
 
@@ -234,6 +241,8 @@ def main():
     ap.add_argument("--workload", default="c2", choices=["c2", "c4", "c5"],
                     help="c2: the three-level 48^3 problem (default); c4: batched parametric instances; c5: serving")
     ap.add_argument("--requests", type=int, default=60, help="requests of the serving trace")
+    ap.add_argument("--tuning-cache", default=os.path.join(ROOT, "paper_2412_08981_amd", "tuning.json"),
+                    help="launch-shape cache (measured on first use)")
     ap.add_argument("--burst", type=int, default=18, help="requests of the closed-loop capacity run")
     ap.add_argument("--budget-gib", type=float, default=160.0, help="device-memory budget of the serving loop")
     ap.add_argument("--batch", type=int, default=32, help="instances of the batched workload")
@@ -273,6 +282,10 @@ def main():
                           "ras_launches": 4, "ras_ms": ms_ras, "ras_algorithmic_bytes": ras_bytes(h, 0, sb),
                           "ras_hip_sha256_16": source_hash()}))
         return
+    from paper_2412_08981_amd import autotune
+    tp = time.perf_counter()
+    tuning = autotune.tune(s, cache=args.tuning_cache)
+    log(f"[bench] launch shapes ({time.perf_counter() - tp:.2f} s): {tuning}")
     b = s.rhs()
     n0 = s.n[0]
     bd = torch.from_numpy(b).cuda()
@@ -330,7 +343,8 @@ def main():
                                f"(117649 fine vertices, 663552 tets), log-Gaussian kappa (8 centres), "
                                f"64+8 subdomains overlap 1, FGMRES(30) to 1e-8, {args.precision}",
                    "iterations": info.iterations, "relres": info.relres,
-                   "numeric_setup_s": round(t_assemble, 4), "structure_setup_s": round(t1 - t0, 3)},
+                   "numeric_setup_s": round(t_assemble, 4), "structure_setup_s": round(t1 - t0, 3),
+                   "tuning": tuning},
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": load_traffic(args.precision),
                      "kernel": "k_ras (fine-level smoother)", "ms": round(ms, 4)},

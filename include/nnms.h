@@ -236,6 +236,30 @@ nnms_status nnms_apply_vcycle(nnms_system* s, const double* r_host, double* z_ho
 nnms_status nnms_time_kernel(nnms_system* s, int32_t kind, int32_t level, int32_t reps, double* ms_host);
 
 /* ---------------------------------------------------------------------------
+ * Launch-shape tuning, per hierarchy (used by every solve plan created after
+ * it is set; a batch uses the tuning of its first system's hierarchy).
+ *   spmv_lanes[l]  lanes of a wave per CSR row of level l's operator (4..64)
+ *   pt_lanes[l]    lanes per row of P_l^T (4..64)
+ *   ras_groups[l]  work-groups of the persistent triangular-solve kernel on
+ *                  level l (0 = 4 per compute unit)
+ *   krylov_lanes   lanes per row of the outer FP64 operator
+ * nnms_autotune times the candidates of every entry on the system's own
+ * data with HIP events (reps launches each), keeps the fastest, stores the
+ * result in the system's hierarchy and in *out (may be NULL).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t spmv_lanes[NNMS_MAX_LEVELS];
+  int32_t pt_lanes[NNMS_MAX_LEVELS];
+  int32_t ras_groups[NNMS_MAX_LEVELS];
+  int32_t krylov_lanes;
+  int32_t tuned; /* 1 after nnms_autotune or a tuning that was set */
+} nnms_tuning;
+
+nnms_status nnms_hierarchy_get_tuning(const nnms_hierarchy* h, nnms_tuning* out);
+nnms_status nnms_hierarchy_set_tuning(nnms_hierarchy* h, const nnms_tuning* t);
+nnms_status nnms_autotune(nnms_system* s, int32_t reps, nnms_tuning* out);
+
+/* ---------------------------------------------------------------------------
  * solve(b) -> x, iterations: right-preconditioned flexible GMRES(restart)
  * with classical Gram-Schmidt applied twice, x0 = 0, stopping when the true
  * residual satisfies ||b - A x||_2 <= rtol ||b||_2 (checked at the end of

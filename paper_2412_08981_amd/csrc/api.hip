@@ -115,6 +115,7 @@ struct nnms_hierarchy {
   std::atomic<int> systems{0};
   nnms_allocator alloc{};
   bool has_alloc = false;
+  nnms_tuning tune{};
 };
 
 namespace nnms {
@@ -174,6 +175,7 @@ static int vec_blocks(int64_t n) { return int((n + VBLK - 1) / VBLK); }
 // a batch plan: descriptor tables for every launch of one Arnoldi step
 // ---------------------------------------------------------------------------
 struct LevelPlan {
+  int g_res = 16, g_rst = 32, ras_grid = 0;
   SpmvDesc* res = nullptr;
   int res_blocks = 0;
   SpmvDesc* rst = nullptr;
@@ -191,6 +193,8 @@ struct Plan {
   Arena mem;
   std::vector<LevelPlan> lev;  // smoothed levels
   RasLaunch coarse{};
+  int coarse_grid = 0;
+  int g_w = 16;
   int nd = 0;
   KrylovDesc* kd = nullptr;
   std::vector<KrylovDesc> kd_host;
@@ -252,6 +256,14 @@ static void build_plan(Plan& P, const std::vector<nnms_system*>& sys, bool with_
     if (x->h->host.L != L || x->prec != P.prec || x->h->host.opts.its != P.its)
       throw Error(NNMS_ERR_INVALID_ARG, "batched systems must share level count, precision and smoothing steps");
   P.lev.resize(std::max(0, L - 1));
+  const nnms_tuning& tu = h0->tune;
+  for (int l = 0; l < L - 1; ++l) {
+    P.lev[l].g_res = tu.spmv_lanes[l];
+    P.lev[l].g_rst = tu.pt_lanes[l];
+    P.lev[l].ras_grid = tu.ras_groups[l] > 0 ? tu.ras_groups[l] : ras_grid_default();
+  }
+  P.coarse_grid = tu.ras_groups[L - 1] > 0 ? tu.ras_groups[L - 1] : ras_grid_default();
+  P.g_w = tu.krylov_lanes;
   auto make_ras = [&](int l, bool coarse, std::vector<SubDesc>& subs_r, std::vector<SubDesc>& subs_t,
                       std::vector<int32_t>& Ns) {
     int flag = 0;
@@ -312,13 +324,13 @@ static void build_plan(Plan& P, const std::vector<nnms_system*>& sys, bool with_
       d.rp = dl.rp, d.col = dl.col, d.val = val_of<T>(sl), d.x = sl.z, d.r = sl.r, d.y = sl.t;
       d.st = st, d.n = int(hl.nv), d.blk0 = br, d.when = WHEN_RUNNING;
       res.push_back(d);
-      br += spmv_blocks(hl.nv, SPMV_G_A);
+      br += spmv_blocks(hl.nv, LP.g_res);
       SpmvDesc e{};
       e.rp = dl.pt_rp, e.col = dl.pt_col;
       e.val = std::is_same<T, float>::value ? (const void*)dl.pt_w32 : (const void*)dl.pt_w64;
       e.x = sl.t, e.r = nullptr, e.y = sc.r, e.st = st, e.n = int(hc.nv), e.blk0 = bt, e.when = WHEN_RUNNING;
       rst.push_back(e);
-      bt += spmv_blocks(hc.nv, SPMV_G_PT);
+      bt += spmv_blocks(hc.nv, LP.g_rst);
       ProlongDesc pd{};
       pd.idx = dl.p_idx;
       pd.w = std::is_same<T, float>::value ? (const void*)dl.p_w32 : (const void*)dl.p_w64;
@@ -353,7 +365,8 @@ static void build_plan(Plan& P, const std::vector<nnms_system*>& sys, bool with_
       k.V = x->V, k.Z = x->Z, k.w = x->w, k.x = x->x, k.b = x->bw, k.dmask = d0.dmask;
       k.part1 = x->part1, k.part2 = x->part2, k.partn = x->partn, k.partr = x->partr, k.st = x->st;
       k.r0 = x->lev[0].r, k.z0 = x->lev[0].z;
-      k.n = int(h0l.nv), k.blk0 = kb, k.nblk = x->nblk, k.nblkr = x->nblkr;
+      k.n = int(h0l.nv), k.blk0 = kb, k.nblk = x->nblk, k.nblkr = spmv_blocks(h0l.nv, P.g_w);
+      if (k.nblkr > x->nblkr) throw Error(NNMS_ERR_INVALID_ARG, "residual partials exceed their buffer");
       P.kd_host.push_back(k);
       kb += x->nblk;
       SpmvDesc d{};
@@ -362,7 +375,7 @@ static void build_plan(Plan& P, const std::vector<nnms_system*>& sys, bool with_
       wd.push_back(d);
       d.x = x->x, d.x_jstride = 0, d.r = x->bw, d.nrm = x->partr, d.when = WHEN_CYCLE_END;
       rd.push_back(d);
-      wb += spmv_blocks(h0l.nv, SPMV_G_A);
+      wb += spmv_blocks(h0l.nv, P.g_w);
     }
     P.kd = P.mem.upload(P.kd_host, s);
     P.kblocks = kb;
@@ -386,24 +399,24 @@ static void check_counters(Plan& P, hipStream_t s) {
 
 template <typename T>
 static void enqueue_vcycle(Plan& P, hipStream_t s) {
-  const int L = P.L, its = P.its, grid = ras_grid_default();
+  const int L = P.L, its = P.its;
   for (int l = 0; l < L - 1; ++l) {
     LevelPlan& LP = P.lev[l];
-    HIP_CHECK((launch_ras<T, T>(LP.ras_r, grid, s)));
+    HIP_CHECK((launch_ras<T, T>(LP.ras_r, LP.ras_grid, s)));
     for (int k = 1; k < its; ++k) {
-      HIP_CHECK(launch_spmv<T>(LP.res, LP.nd, LP.res_blocks, SPMV_G_A, s));
-      HIP_CHECK((launch_ras<T, T>(LP.ras_t, grid, s)));
+      HIP_CHECK(launch_spmv<T>(LP.res, LP.nd, LP.res_blocks, LP.g_res, s));
+      HIP_CHECK((launch_ras<T, T>(LP.ras_t, LP.ras_grid, s)));
     }
-    HIP_CHECK(launch_spmv<T>(LP.res, LP.nd, LP.res_blocks, SPMV_G_A, s));
-    HIP_CHECK(launch_spmv<T>(LP.rst, LP.nd, LP.rst_blocks, SPMV_G_PT, s));
+    HIP_CHECK(launch_spmv<T>(LP.res, LP.nd, LP.res_blocks, LP.g_res, s));
+    HIP_CHECK(launch_spmv<T>(LP.rst, LP.nd, LP.rst_blocks, LP.g_rst, s));
   }
-  HIP_CHECK((launch_ras<double, T>(P.coarse, grid, s)));
+  HIP_CHECK((launch_ras<double, T>(P.coarse, P.coarse_grid, s)));
   for (int l = L - 2; l >= 0; --l) {
     LevelPlan& LP = P.lev[l];
     HIP_CHECK(launch_prolong<T>(LP.pro, LP.nd, LP.pro_blocks, s));
     for (int k = 0; k < its; ++k) {
-      HIP_CHECK(launch_spmv<T>(LP.res, LP.nd, LP.res_blocks, SPMV_G_A, s));
-      HIP_CHECK((launch_ras<T, T>(LP.ras_t, grid, s)));
+      HIP_CHECK(launch_spmv<T>(LP.res, LP.nd, LP.res_blocks, LP.g_res, s));
+      HIP_CHECK((launch_ras<T, T>(LP.ras_t, LP.ras_grid, s)));
     }
   }
 }
@@ -413,14 +426,14 @@ static void enqueue_step(Plan& P, hipStream_t s) {
   HIP_CHECK(launch_krylov_cast_in<T>(P.kd, P.nd, P.kblocks, s));
   enqueue_vcycle<T>(P, s);
   HIP_CHECK(launch_krylov_cast_out<T>(P.kd, P.nd, P.kblocks, s));
-  HIP_CHECK(launch_spmv<double>(P.wspmv, P.nd, P.wblocks, SPMV_G_A, s));
+  HIP_CHECK(launch_spmv<double>(P.wspmv, P.nd, P.wblocks, P.g_w, s));
   HIP_CHECK(launch_krylov_dots1(P.kd, P.nd, P.kblocks, s));
   HIP_CHECK(launch_krylov_upd1(P.kd, P.nd, P.kblocks, s));
   HIP_CHECK(launch_krylov_upd2(P.kd, P.nd, P.kblocks, s));
   HIP_CHECK(launch_krylov_givens(P.kd, P.nd, s));
   HIP_CHECK(launch_krylov_normalize(P.kd, P.nd, P.kblocks, s));
   HIP_CHECK(launch_krylov_xupd(P.kd, P.nd, P.kblocks, s));
-  HIP_CHECK(launch_spmv<double>(P.rspmv, P.nd, P.wblocks, SPMV_G_A, s));
+  HIP_CHECK(launch_spmv<double>(P.rspmv, P.nd, P.wblocks, P.g_w, s));
   HIP_CHECK(launch_krylov_cycle(P.kd, P.nd, s));
 }
 
@@ -529,6 +542,13 @@ nnms_system::~nnms_system() {
 extern "C" const char* nnms_last_error(void) { return nnms::g_last_error.c_str(); }
 extern "C" int64_t nnms_device_bytes_in_use(void) { return nnms::g_bytes.load(); }
 
+static void default_tuning(nnms_tuning& t) {
+  std::memset(&t, 0, sizeof t);
+  for (int l = 0; l < NNMS_MAX_LEVELS; ++l) t.spmv_lanes[l] = SPMV_G_A, t.pt_lanes[l] = SPMV_G_PT, t.ras_groups[l] = 0;
+  t.krylov_lanes = SPMV_G_A;
+  t.tuned = 0;
+}
+
 static void build_host(const nnms_mesh* const* levels, int32_t L, const nnms_setup_opts* opts, HostHierarchy& H) {
   if (!levels || L < 1 || L > NNMS_MAX_LEVELS || !opts) throw Error(NNMS_ERR_INVALID_ARG, "bad hierarchy arguments");
   if (opts->overlap < 0 || opts->its < 1 || (opts->precision != NNMS_FP64 && opts->precision != NNMS_MIXED))
@@ -560,6 +580,7 @@ extern "C" nnms_status nnms_hierarchy_setup_host(const nnms_mesh* const* levels,
   *out = nullptr;
   auto h = std::make_unique<nnms_hierarchy>();
   build_host(levels, L, opts, h->host);
+  default_tuning(h->tune);
   *out = h.release();
   return NNMS_OK;
   ABI_END
@@ -577,6 +598,7 @@ extern "C" nnms_status nnms_hierarchy_setup(const nnms_mesh* const* levels, int3
   *out = nullptr;
   auto h = std::make_unique<nnms_hierarchy>();
   build_host(levels, L, opts, h->host);
+  default_tuning(h->tune);
   hipStream_t s = (hipStream_t)stream;
   h->mem = std::make_unique<Arena>(alloc);
   if (alloc && alloc->alloc && alloc->free) h->alloc = *alloc, h->has_alloc = true;
@@ -789,7 +811,7 @@ extern "C" nnms_status nnms_assemble(nnms_hierarchy* h, const nnms_kappa* k, dou
   const int m = NNMS_MAX_RESTART;
   sys->restart_cap = m;
   sys->nblk = vec_blocks(n0);
-  sys->nblkr = spmv_blocks(n0, SPMV_G_A);
+  sys->nblkr = spmv_blocks(n0, 64);  // most blocks of any lanes-per-row choice (4 rows per block)
   sys->V = A.alloc<double>(size_t(n0) * (m + 1), s, false);
   sys->Z = A.alloc<double>(size_t(n0) * m, s, false);
   sys->w = A.alloc<double>(n0, s);
@@ -899,17 +921,16 @@ extern "C" nnms_status nnms_apply_smoother(nnms_system* s, int32_t level, const 
   SysLevel& sl = s->lev[level];
   put_vec(s, sl.r, r, n, P.stream);
   HIP_CHECK(hipMemsetAsync(sl.z, 0, n * tsize(s), P.stream));
-  const int grid = ras_grid_default();
   if (level == s->h->host.L - 1) {
     if (s->prec == NNMS_FP64)
-      HIP_CHECK((launch_ras<double, double>(P.coarse, grid, P.stream)));
+      HIP_CHECK((launch_ras<double, double>(P.coarse, P.coarse_grid, P.stream)));
     else
-      HIP_CHECK((launch_ras<double, float>(P.coarse, grid, P.stream)));
+      HIP_CHECK((launch_ras<double, float>(P.coarse, P.coarse_grid, P.stream)));
   } else {
     if (s->prec == NNMS_FP64)
-      HIP_CHECK((launch_ras<double, double>(P.lev[level].ras_r, grid, P.stream)));
+      HIP_CHECK((launch_ras<double, double>(P.lev[level].ras_r, P.lev[level].ras_grid, P.stream)));
     else
-      HIP_CHECK((launch_ras<float, float>(P.lev[level].ras_r, grid, P.stream)));
+      HIP_CHECK((launch_ras<float, float>(P.lev[level].ras_r, P.lev[level].ras_grid, P.stream)));
   }
   get_vec(s, z, sl.z, n, P.stream);
   check_counters(P, P.stream);
@@ -942,9 +963,9 @@ extern "C" nnms_status nnms_apply_restrict(nnms_system* s, int32_t level, const 
   const int64_t nf = s->h->host.lev[level].nv, nc = s->h->host.lev[level + 1].nv;
   put_vec(s, s->lev[level].t, x, nf, P.stream);
   if (s->prec == NNMS_FP64)
-    HIP_CHECK(launch_spmv<double>(P.lev[level].rst, 1, P.lev[level].rst_blocks, SPMV_G_PT, P.stream));
+    HIP_CHECK(launch_spmv<double>(P.lev[level].rst, 1, P.lev[level].rst_blocks, P.lev[level].g_rst, P.stream));
   else
-    HIP_CHECK(launch_spmv<float>(P.lev[level].rst, 1, P.lev[level].rst_blocks, SPMV_G_PT, P.stream));
+    HIP_CHECK(launch_spmv<float>(P.lev[level].rst, 1, P.lev[level].rst_blocks, P.lev[level].g_rst, P.stream));
   get_vec(s, y, s->lev[level + 1].r, nc, P.stream);
   return NNMS_OK;
   ABI_END
@@ -1149,7 +1170,6 @@ extern "C" nnms_status nnms_time_kernel(nnms_system* s, int32_t kind, int32_t le
   Plan& P = apply_plan(s);
   hipStream_t st = P.stream;
   const bool f64 = s->prec == NNMS_FP64;
-  const int grid = ras_grid_default();
   const bool fac64 = f64 || level == L - 1;
   const int64_t copy_bytes = (s->h->host.lev[level].fac_elems * (fac64 ? 8 : 4)) & ~int64_t(15);
   std::unique_ptr<Arena> copy_dst;
@@ -1163,19 +1183,19 @@ extern "C" nnms_status nnms_time_kernel(nnms_system* s, int32_t kind, int32_t le
     } else if (kind == 0) {
       if (level == L - 1) {
         if (f64)
-          HIP_CHECK((launch_ras<double, double>(P.coarse, grid, st)));
+          HIP_CHECK((launch_ras<double, double>(P.coarse, P.coarse_grid, st)));
         else
-          HIP_CHECK((launch_ras<double, float>(P.coarse, grid, st)));
+          HIP_CHECK((launch_ras<double, float>(P.coarse, P.coarse_grid, st)));
       } else if (f64) {
-        HIP_CHECK((launch_ras<double, double>(P.lev[level].ras_t, grid, st)));
+        HIP_CHECK((launch_ras<double, double>(P.lev[level].ras_t, P.lev[level].ras_grid, st)));
       } else {
-        HIP_CHECK((launch_ras<float, float>(P.lev[level].ras_t, grid, st)));
+        HIP_CHECK((launch_ras<float, float>(P.lev[level].ras_t, P.lev[level].ras_grid, st)));
       }
     } else if (kind == 1) {
       if (f64)
-        HIP_CHECK(launch_spmv<double>(P.lev[level].res, 1, P.lev[level].res_blocks, SPMV_G_A, st));
+        HIP_CHECK(launch_spmv<double>(P.lev[level].res, 1, P.lev[level].res_blocks, P.lev[level].g_res, st));
       else
-        HIP_CHECK(launch_spmv<float>(P.lev[level].res, 1, P.lev[level].res_blocks, SPMV_G_A, st));
+        HIP_CHECK(launch_spmv<float>(P.lev[level].res, 1, P.lev[level].res_blocks, P.lev[level].g_res, st));
     } else if (kind == 2) {
       if (f64)
         HIP_CHECK(launch_prolong<double>(P.lev[level].pro, 1, P.lev[level].pro_blocks, st));
@@ -1183,9 +1203,9 @@ extern "C" nnms_status nnms_time_kernel(nnms_system* s, int32_t kind, int32_t le
         HIP_CHECK(launch_prolong<float>(P.lev[level].pro, 1, P.lev[level].pro_blocks, st));
     } else {
       if (f64)
-        HIP_CHECK(launch_spmv<double>(P.lev[level].rst, 1, P.lev[level].rst_blocks, SPMV_G_PT, st));
+        HIP_CHECK(launch_spmv<double>(P.lev[level].rst, 1, P.lev[level].rst_blocks, P.lev[level].g_rst, st));
       else
-        HIP_CHECK(launch_spmv<float>(P.lev[level].rst, 1, P.lev[level].rst_blocks, SPMV_G_PT, st));
+        HIP_CHECK(launch_spmv<float>(P.lev[level].rst, 1, P.lev[level].rst_blocks, P.lev[level].g_rst, st));
     }
   };
   launch();  // warm-up
@@ -1238,6 +1258,128 @@ extern "C" nnms_status nnms_system_factor(const nnms_system* s, int32_t level, i
     for (int ti = 0; ti < N; ++ti)
       for (int r = 0; r < 64; ++r)
         for (int c = 0; c < 64; ++c) invl[(size_t(ti) * 64 + r) * 64 + c] = get(size_t(N) * N + ti, r, c);
+  return NNMS_OK;
+  ABI_END
+}
+
+// ---------------------------------------------------------------------------
+// launch-shape tuning
+// ---------------------------------------------------------------------------
+static bool lanes_ok(int g) { return g == 4 || g == 8 || g == 16 || g == 32 || g == 64; }
+
+extern "C" nnms_status nnms_hierarchy_get_tuning(const nnms_hierarchy* h, nnms_tuning* out) {
+  ABI_BEGIN
+  if (!h || !out) throw Error(NNMS_ERR_INVALID_ARG, "null argument");
+  *out = h->tune;
+  return NNMS_OK;
+  ABI_END
+}
+
+extern "C" nnms_status nnms_hierarchy_set_tuning(nnms_hierarchy* h, const nnms_tuning* t) {
+  ABI_BEGIN
+  if (!h || !t) throw Error(NNMS_ERR_INVALID_ARG, "null argument");
+  for (int l = 0; l < NNMS_MAX_LEVELS; ++l)
+    if (!lanes_ok(t->spmv_lanes[l]) || !lanes_ok(t->pt_lanes[l]) || t->ras_groups[l] < 0 || t->ras_groups[l] > 65536)
+      throw Error(NNMS_ERR_INVALID_ARG, "bad tuning entry");
+  if (!lanes_ok(t->krylov_lanes)) throw Error(NNMS_ERR_INVALID_ARG, "bad tuning entry");
+  h->tune = *t;
+  h->tune.tuned = 1;
+  return NNMS_OK;
+  ABI_END
+}
+
+template <typename Fn>
+static double time_ms(hipStream_t st, int reps, Fn&& fn) {
+  fn();
+  hipEvent_t e0, e1;
+  HIP_CHECK(hipEventCreate(&e0));
+  HIP_CHECK(hipEventCreate(&e1));
+  HIP_CHECK(hipEventRecord(e0, st));
+  for (int r = 0; r < reps; ++r) fn();
+  HIP_CHECK(hipEventRecord(e1, st));
+  HIP_CHECK(hipEventSynchronize(e1));
+  float t = 0;
+  HIP_CHECK(hipEventElapsedTime(&t, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return double(t) / reps;
+}
+
+extern "C" nnms_status nnms_autotune(nnms_system* s, int32_t reps, nnms_tuning* out) {
+  ABI_BEGIN
+  if (!s || reps < 1) throw Error(NNMS_ERR_INVALID_ARG, "bad arguments");
+  nnms_hierarchy* h = s->h;
+  const int L = h->host.L;
+  const bool f64 = s->prec == NNMS_FP64;
+  nnms_tuning t = h->tune;
+  Plan& P = apply_plan(s);
+  hipStream_t st = P.stream;
+  Arena tmp(h->has_alloc ? &h->alloc : nullptr);
+  const int lanes[] = {4, 8, 16, 32, 64};
+  auto spmv_best = [&](const int32_t* rp, const int32_t* col, const void* val, const void* x, const void* r, void* y,
+                       int64_t n, bool dbl) {
+    int best = 16;
+    double bt = 1e30;
+    for (int g : lanes) {
+      SpmvDesc d{};
+      d.rp = rp, d.col = col, d.val = val, d.x = x, d.r = r, d.y = y, d.n = int(n), d.blk0 = 0, d.when = WHEN_RUNNING;
+      std::vector<SpmvDesc> v{d};
+      SpmvDesc* dd = tmp.upload(v, st);
+      const int nb = spmv_blocks(n, g);
+      double ms = time_ms(st, reps, [&]() {
+        if (dbl)
+          HIP_CHECK(launch_spmv<double>(dd, 1, nb, g, st));
+        else
+          HIP_CHECK(launch_spmv<float>(dd, 1, nb, g, st));
+      });
+      if (ms < bt) bt = ms, best = g;
+    }
+    return best;
+  };
+  int cus = ras_grid_default() / 4;
+  auto ras_best = [&](const RasLaunch& rl, int kind /*0 TT, 1 coarse*/) {
+    int best = 0;
+    double bt = 1e30;
+    for (int per = 1; per <= 6; ++per) {
+      const int grid = per * cus;
+      double ms = time_ms(st, reps, [&]() {
+        if (kind == 1) {
+          if (f64)
+            HIP_CHECK((launch_ras<double, double>(rl, grid, st)));
+          else
+            HIP_CHECK((launch_ras<double, float>(rl, grid, st)));
+        } else if (f64) {
+          HIP_CHECK((launch_ras<double, double>(rl, grid, st)));
+        } else {
+          HIP_CHECK((launch_ras<float, float>(rl, grid, st)));
+        }
+      });
+      if (ms < bt) bt = ms, best = grid;
+      if (grid >= rl.ntasks) break;  // a larger grid cannot help
+    }
+    return best;
+  };
+  for (int l = 0; l < L - 1; ++l) {
+    const DevLevel& dl = h->dev[l];
+    SysLevel& sl = s->lev[l];
+    const int64_t n = h->host.lev[l].nv, nc = h->host.lev[l + 1].nv;
+    const void* val = f64 ? (const void*)sl.val64 : (const void*)sl.val32;
+    t.spmv_lanes[l] = spmv_best(dl.rp, dl.col, val, sl.z, sl.r, sl.t, n, f64);
+    const void* ptw = f64 ? (const void*)dl.pt_w64 : (const void*)dl.pt_w32;
+    t.pt_lanes[l] = spmv_best(dl.pt_rp, dl.pt_col, ptw, sl.t, nullptr, s->lev[l + 1].r, nc, f64);
+    t.ras_groups[l] = ras_best(P.lev[l].ras_t, 0);
+  }
+  t.ras_groups[L - 1] = ras_best(P.coarse, 1);
+  {
+    const DevLevel& d0 = h->dev[0];
+    t.krylov_lanes = spmv_best(d0.rp, d0.col, s->lev[0].val64, s->x, nullptr, s->w, h->host.lev[0].nv, true);
+  }
+  check_counters(P, st);
+  t.tuned = 1;
+  h->tune = t;
+  s->solo.reset();
+  s->apply.reset();
+  if (out) *out = t;
   return NNMS_OK;
   ABI_END
 }

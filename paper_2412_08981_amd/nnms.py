@@ -64,6 +64,24 @@ class solve_info(C.Structure):
                 ("relres", C.c_double)]
 
 
+class tuning_t(C.Structure):
+    _fields_ = [("spmv_lanes", C.c_int32 * MAX_LEVELS), ("pt_lanes", C.c_int32 * MAX_LEVELS),
+                ("ras_groups", C.c_int32 * MAX_LEVELS), ("krylov_lanes", C.c_int32), ("tuned", C.c_int32)]
+
+    def to_dict(self):
+        return {"spmv_lanes": list(self.spmv_lanes), "pt_lanes": list(self.pt_lanes),
+                "ras_groups": list(self.ras_groups), "krylov_lanes": int(self.krylov_lanes), "tuned": int(self.tuned)}
+
+    @classmethod
+    def from_dict(cls, d):
+        t = cls()
+        for k in ("spmv_lanes", "pt_lanes", "ras_groups"):
+            for i, v in enumerate(d[k]):
+                getattr(t, k)[i] = int(v)
+        t.krylov_lanes, t.tuned = int(d["krylov_lanes"]), int(d.get("tuned", 1))
+        return t
+
+
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
@@ -107,6 +125,9 @@ _sig = {
     "nnms_batch_destroy": (C.c_int, [vp]),
     "nnms_time_kernel": (C.c_int, [vp, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double)]),
     "nnms_system_factor": (C.c_int, [vp, C.c_int32, C.c_int32, vp, vp, C.POINTER(C.c_int32)]),
+    "nnms_hierarchy_get_tuning": (C.c_int, [vp, C.POINTER(tuning_t)]),
+    "nnms_hierarchy_set_tuning": (C.c_int, [vp, C.POINTER(tuning_t)]),
+    "nnms_autotune": (C.c_int, [vp, C.c_int32, C.POINTER(tuning_t)]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -235,6 +256,23 @@ class Hierarchy:
         _check(_lib.nnms_hierarchy_transfer(self.handle, level, _ptr(idx), _ptr(w)))
         return idx.reshape(-1, 4), w.reshape(-1, 4)
 
+    def get_tuning(self) -> dict:
+        t = tuning_t()
+        _check(_lib.nnms_hierarchy_get_tuning(self.handle, C.byref(t)))
+        return t.to_dict()
+
+    def set_tuning(self, d: dict):
+        t = tuning_t.from_dict(d)
+        _check(_lib.nnms_hierarchy_set_tuning(self.handle, C.byref(t)))
+
+    def signature(self) -> str:
+        """Identifies the hierarchy's shapes (sizes, subdomains, precision) for tuning caches."""
+        parts = []
+        for l in range(self.L):
+            li = self.level_info(l)
+            parts.append(f"{li.nv}-{li.nnz}-{li.nparts}")
+        return f"p{self.precision}_" + "_".join(parts)
+
     def system_bytes(self, restart: int = 30) -> int:
         return int(_lib.nnms_hierarchy_system_bytes(self.handle, restart))
 
@@ -320,6 +358,13 @@ class System:
         il = np.empty((N.value, 64, 64))
         _check(_lib.nnms_system_factor(self.handle, level, part, _ptr(lu), _ptr(il), C.byref(N)))
         return lu, il
+
+    def autotune(self, reps: int = 10) -> dict:
+        """nnms_autotune: time the launch-shape candidates on this system and
+        store the fastest in its hierarchy."""
+        t = tuning_t()
+        _check(_lib.nnms_autotune(self.handle, reps, C.byref(t)))
+        return t.to_dict()
 
     def time_kernel(self, kind: int, level: int, reps: int = 10) -> float:
         """Mean milliseconds of one launch (HIP events on the launch stream)."""
