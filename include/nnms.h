@@ -242,6 +242,9 @@ nnms_status nnms_time_kernel(nnms_system* s, int32_t kind, int32_t level, int32_
  *   pt_lanes[l]    lanes per row of P_l^T (4..64)
  *   ras_groups[l]  work-groups of the persistent triangular-solve kernel on
  *                  level l (0 = 4 per compute unit)
+ *   ras_blocks[l]  64-row blocks per work item of that kernel (1, 2 or 4):
+ *                  blocks inside a work item are substituted in order by one
+ *                  work-group, only work items hand results to each other
  *   krylov_lanes   lanes per row of the outer FP64 operator
  * nnms_autotune times the candidates of every entry on the system's own
  * data with HIP events (reps launches each), keeps the fastest, stores the
@@ -251,6 +254,7 @@ typedef struct {
   int32_t spmv_lanes[NNMS_MAX_LEVELS];
   int32_t pt_lanes[NNMS_MAX_LEVELS];
   int32_t ras_groups[NNMS_MAX_LEVELS];
+  int32_t ras_blocks[NNMS_MAX_LEVELS];
   int32_t krylov_lanes;
   int32_t tuned; /* 1 after nnms_autotune or a tuning that was set */
 } nnms_tuning;

@@ -175,7 +175,7 @@ static int vec_blocks(int64_t n) { return int((n + VBLK - 1) / VBLK); }
 // a batch plan: descriptor tables for every launch of one Arnoldi step
 // ---------------------------------------------------------------------------
 struct LevelPlan {
-  int g_res = 16, g_rst = 32, ras_grid = 0;
+  int g_res = 16, g_rst = 32, ras_grid = 0, ras_k = 1;
   SpmvDesc* res = nullptr;
   int res_blocks = 0;
   SpmvDesc* rst = nullptr;
@@ -193,7 +193,7 @@ struct Plan {
   Arena mem;
   std::vector<LevelPlan> lev;  // smoothed levels
   RasLaunch coarse{};
-  int coarse_grid = 0;
+  int coarse_grid = 0, coarse_k = 1;
   int g_w = 16;
   int nd = 0;
   KrylovDesc* kd = nullptr;
@@ -225,20 +225,70 @@ static const void* val_of(const SysLevel& sl) {
 // task list of one restricted additive Schwarz launch over subdomains with
 // N[q] blocks: forward block i at step i, backward block i at step 2N-1-i,
 // ordered by (step, subdomain) so that every dependency has a lower ticket.
-static std::vector<int32_t> ras_tasks(const std::vector<int32_t>& N) {
+static std::vector<int32_t> ras_tasks(const std::vector<int32_t>& N, int K) {
   struct T3 {
     int step, sub, code;
   };
   std::vector<T3> v;
-  for (size_t q = 0; q < N.size(); ++q)
-    for (int i = 0; i < N[q]; ++i) {
+  for (size_t q = 0; q < N.size(); ++q) {
+    const int NB = (N[q] + K - 1) / K;
+    for (int i = 0; i < NB; ++i) {
       v.push_back({i, int(q), int((q << 16) | i)});
-      v.push_back({2 * N[q] - 1 - i, int(q), int((q << 16) | (1 << 15) | i)});
+      v.push_back({2 * NB - 1 - i, int(q), int((q << 16) | (1 << 15) | i)});
     }
+  }
   std::sort(v.begin(), v.end(), [](const T3& a, const T3& b) { return a.step != b.step ? a.step < b.step : a.sub < b.sub; });
   std::vector<int32_t> out(v.size());
   for (size_t k = 0; k < v.size(); ++k) out[k] = v[k].code;
   return out;
+}
+
+// The two smoother launches of level l over a set of systems (input r_l with
+// z written, input t_l with z added), for work items of K blocks; flags,
+// tasks and the ticket counter are allocated in `mem`.
+static void build_ras_pair(Arena& mem, std::vector<int32_t*>& counters, const std::vector<nnms_system*>& sys, int l,
+                           bool coarse, int prec, bool with_state, int K, hipStream_t s, RasLaunch& rr, RasLaunch& rt) {
+  std::vector<SubDesc> subs_r, subs_t;
+  std::vector<int32_t> Ns;
+  int flag = 0;
+  for (auto* x : sys) {
+    const HostLevel& hl = x->h->host.lev[l];
+    const DevLevel& dl = x->h->dev[l];
+    const SysLevel& sl = x->lev[l];
+    const size_t fsz = (coarse || prec == NNMS_FP64) ? sizeof(double) : sizeof(float);
+    for (int p = 0; p < hl.nparts; ++p) {
+      SubDesc d{};
+      d.fac = (const char*)sl.fac + size_t(hl.fac_off[p]) * fsz;
+      d.gidx = dl.gidx + hl.g_off[p];
+      d.yx = (char*)sl.yx + size_t(hl.g_off[p]) * 16;
+      d.rin = sl.r;
+      d.zout = sl.z;
+      d.st = with_state ? x->st : nullptr;
+      d.N = hl.nblk[p];
+      d.flag0 = flag;
+      flag += 2 * ((hl.nblk[p] + K - 1) / K);
+      subs_r.push_back(d);
+      d.rin = sl.t;
+      subs_t.push_back(d);
+      Ns.push_back(hl.nblk[p]);
+    }
+  }
+  if (subs_r.size() > 32767) throw Error(NNMS_ERR_INVALID_ARG, "too many subdomains in one batch");
+  std::vector<int32_t> tasks = ras_tasks(Ns, K);
+  int32_t* flags = mem.alloc<int32_t>(std::max(flag, 1), s);
+  int32_t* counter = mem.alloc<int32_t>(4, s);
+  counters.push_back(counter);
+  rr = RasLaunch{};
+  rr.subs = mem.upload(subs_r, s);
+  rr.tasks = mem.upload(tasks, s);
+  rr.flags = flags;
+  rr.counter = counter;
+  rr.ntasks = int(tasks.size());
+  rr.add = 0;
+  rr.group = K;
+  rt = rr;
+  rt.subs = mem.upload(subs_t, s);
+  rt.add = 1;
 }
 
 template <typename T>
@@ -261,53 +311,11 @@ static void build_plan(Plan& P, const std::vector<nnms_system*>& sys, bool with_
     P.lev[l].g_res = tu.spmv_lanes[l];
     P.lev[l].g_rst = tu.pt_lanes[l];
     P.lev[l].ras_grid = tu.ras_groups[l] > 0 ? tu.ras_groups[l] : ras_grid_default();
+    P.lev[l].ras_k = tu.ras_blocks[l];
   }
   P.coarse_grid = tu.ras_groups[L - 1] > 0 ? tu.ras_groups[L - 1] : ras_grid_default();
+  P.coarse_k = tu.ras_blocks[L - 1];
   P.g_w = tu.krylov_lanes;
-  auto make_ras = [&](int l, bool coarse, std::vector<SubDesc>& subs_r, std::vector<SubDesc>& subs_t,
-                      std::vector<int32_t>& Ns) {
-    int flag = 0;
-    for (auto* x : sys) {
-      const HostLevel& hl = x->h->host.lev[l];
-      const DevLevel& dl = x->h->dev[l];
-      const SysLevel& sl = x->lev[l];
-      const size_t fsz = (coarse || P.prec == NNMS_FP64) ? sizeof(double) : sizeof(float);
-      for (int p = 0; p < hl.nparts; ++p) {
-        SubDesc d{};
-        d.fac = (const char*)sl.fac + size_t(hl.fac_off[p]) * fsz;
-        d.gidx = dl.gidx + hl.g_off[p];
-        d.yx = (char*)sl.yx + size_t(hl.g_off[p]) * fsz;
-        d.rin = sl.r;
-        d.zout = sl.z;
-        d.st = with_state ? x->st : nullptr;
-        d.N = hl.nblk[p];
-        d.flag0 = flag;
-        flag += 2 * hl.nblk[p];
-        subs_r.push_back(d);
-        d.rin = sl.t;
-        subs_t.push_back(d);
-        Ns.push_back(hl.nblk[p]);
-      }
-    }
-    if (subs_r.size() > 32767) throw Error(NNMS_ERR_INVALID_ARG, "too many subdomains in one batch");
-    return flag;
-  };
-  auto finish_ras = [&](RasLaunch& rr, RasLaunch& rt, const std::vector<SubDesc>& subs_r,
-                        const std::vector<SubDesc>& subs_t, const std::vector<int32_t>& Ns, int nflags) {
-    std::vector<int32_t> tasks = ras_tasks(Ns);
-    int32_t* flags = P.mem.alloc<int32_t>(std::max(nflags, 1), s);
-    int32_t* counter = P.mem.alloc<int32_t>(4, s);
-    P.counters.push_back(counter);
-    rr.subs = P.mem.upload(subs_r, s);
-    rr.tasks = P.mem.upload(tasks, s);
-    rr.flags = flags;
-    rr.counter = counter;
-    rr.ntasks = int(tasks.size());
-    rr.add = 0;
-    rt = rr;
-    rt.subs = P.mem.upload(subs_t, s);
-    rt.add = 1;
-  };
   for (int l = 0; l < L - 1; ++l) {
     LevelPlan& LP = P.lev[l];
     std::vector<SpmvDesc> res, rst;
@@ -342,17 +350,11 @@ static void build_plan(Plan& P, const std::vector<nnms_system*>& sys, bool with_
     LP.rst = P.mem.upload(rst, s), LP.rst_blocks = bt;
     LP.pro = P.mem.upload(pro, s), LP.pro_blocks = bp;
     LP.nd = int(sys.size());
-    std::vector<SubDesc> sr, stt;
-    std::vector<int32_t> Ns;
-    int nflags = make_ras(l, false, sr, stt, Ns);
-    finish_ras(LP.ras_r, LP.ras_t, sr, stt, Ns, nflags);
+    build_ras_pair(P.mem, P.counters, sys, l, false, P.prec, with_state, LP.ras_k, s, LP.ras_r, LP.ras_t);
   }
   {
-    std::vector<SubDesc> sr, stt;
-    std::vector<int32_t> Ns;
-    int nflags = make_ras(L - 1, true, sr, stt, Ns);
     RasLaunch dummy{};
-    finish_ras(P.coarse, dummy, sr, stt, Ns, nflags);
+    build_ras_pair(P.mem, P.counters, sys, L - 1, true, P.prec, with_state, P.coarse_k, s, P.coarse, dummy);
   }
   // Krylov descriptors
   if (with_state) {
@@ -544,7 +546,8 @@ extern "C" int64_t nnms_device_bytes_in_use(void) { return nnms::g_bytes.load();
 
 static void default_tuning(nnms_tuning& t) {
   std::memset(&t, 0, sizeof t);
-  for (int l = 0; l < NNMS_MAX_LEVELS; ++l) t.spmv_lanes[l] = SPMV_G_A, t.pt_lanes[l] = SPMV_G_PT, t.ras_groups[l] = 0;
+  for (int l = 0; l < NNMS_MAX_LEVELS; ++l)
+    t.spmv_lanes[l] = SPMV_G_A, t.pt_lanes[l] = SPMV_G_PT, t.ras_groups[l] = 0, t.ras_blocks[l] = 1;
   t.krylov_lanes = SPMV_G_A;
   t.tuned = 0;
 }
@@ -706,7 +709,7 @@ static int64_t system_bytes(const HostHierarchy& H, int prec, int restart) {
     const int64_t f = (coarse || prec == NNMS_FP64) ? 8 : 4;
     const int64_t t = prec == NNMS_FP64 ? 8 : 4;
     b += int64_t(lv.col.size()) * 8 + (prec == NNMS_MIXED ? int64_t(lv.col.size()) * 4 : 0);
-    b += lv.fac_elems * f + lv.g_total * f + 3 * lv.nv * t;
+    b += lv.fac_elems * f + lv.g_total * 16 + 3 * lv.nv * t;
   }
   const int64_t n0 = H.lev[0].nv;
   b += n0 * 8 * (2 * int64_t(restart) + 1 + 4);
@@ -766,7 +769,7 @@ extern "C" nnms_status nnms_assemble(nnms_hierarchy* h, const nnms_kappa* k, dou
     sl.val64 = A.alloc<double>(hl.col.size(), s, false);
     if (prec == NNMS_MIXED) sl.val32 = A.alloc<float>(hl.col.size(), s, false);
     sl.fac = A.raw(std::max<size_t>(size_t(hl.fac_elems) * fsz, 256));
-    sl.yx = A.alloc<char>(size_t(hl.g_total) * fsz, s);
+    sl.yx = A.alloc<char>(size_t(hl.g_total) * 16, s);  // tagged block results: 16 bytes per value
     sl.r = A.alloc<char>(hl.nv * tsz, s);
     sl.z = A.alloc<char>(hl.nv * tsz, s);
     sl.t = A.alloc<char>(hl.nv * tsz, s);
@@ -1279,7 +1282,8 @@ extern "C" nnms_status nnms_hierarchy_set_tuning(nnms_hierarchy* h, const nnms_t
   ABI_BEGIN
   if (!h || !t) throw Error(NNMS_ERR_INVALID_ARG, "null argument");
   for (int l = 0; l < NNMS_MAX_LEVELS; ++l)
-    if (!lanes_ok(t->spmv_lanes[l]) || !lanes_ok(t->pt_lanes[l]) || t->ras_groups[l] < 0 || t->ras_groups[l] > 65536)
+    if (!lanes_ok(t->spmv_lanes[l]) || !lanes_ok(t->pt_lanes[l]) || t->ras_groups[l] < 0 || t->ras_groups[l] > 65536 ||
+        !(t->ras_blocks[l] == 1 || t->ras_blocks[l] == 2 || t->ras_blocks[l] == 4))
       throw Error(NNMS_ERR_INVALID_ARG, "bad tuning entry");
   if (!lanes_ok(t->krylov_lanes)) throw Error(NNMS_ERR_INVALID_ARG, "bad tuning entry");
   h->tune = *t;
@@ -1337,27 +1341,33 @@ extern "C" nnms_status nnms_autotune(nnms_system* s, int32_t reps, nnms_tuning* 
     return best;
   };
   int cus = ras_grid_default() / 4;
-  auto ras_best = [&](const RasLaunch& rl, int kind /*0 TT, 1 coarse*/) {
-    int best = 0;
+  std::vector<int32_t*> tcounters;
+  // best (blocks per work item, grid) of the smoother on level l
+  auto ras_best = [&](int l, bool coarse, int32_t& groups_out, int32_t& blocks_out) {
     double bt = 1e30;
-    for (int per = 1; per <= 6; ++per) {
-      const int grid = per * cus;
-      double ms = time_ms(st, reps, [&]() {
-        if (kind == 1) {
-          if (f64)
+    for (int K : {1, 2, 4}) {
+      RasLaunch rr, rt;
+      build_ras_pair(tmp, tcounters, {s}, l, coarse, s->prec, false, K, st, rr, rt);
+      HIP_CHECK(hipStreamSynchronize(st));
+      const RasLaunch& rl = coarse ? rr : rt;
+      for (int per = 1; per <= 6; ++per) {
+        const int grid = per * cus;
+        double ms = time_ms(st, reps, [&]() {
+          if (coarse) {
+            if (f64)
+              HIP_CHECK((launch_ras<double, double>(rl, grid, st)));
+            else
+              HIP_CHECK((launch_ras<double, float>(rl, grid, st)));
+          } else if (f64) {
             HIP_CHECK((launch_ras<double, double>(rl, grid, st)));
-          else
-            HIP_CHECK((launch_ras<double, float>(rl, grid, st)));
-        } else if (f64) {
-          HIP_CHECK((launch_ras<double, double>(rl, grid, st)));
-        } else {
-          HIP_CHECK((launch_ras<float, float>(rl, grid, st)));
-        }
-      });
-      if (ms < bt) bt = ms, best = grid;
-      if (grid >= rl.ntasks) break;  // a larger grid cannot help
+          } else {
+            HIP_CHECK((launch_ras<float, float>(rl, grid, st)));
+          }
+        });
+        if (ms < bt) bt = ms, groups_out = grid, blocks_out = K;
+        if (grid >= rl.ntasks) break;  // a larger grid cannot help
+      }
     }
-    return best;
   };
   for (int l = 0; l < L - 1; ++l) {
     const DevLevel& dl = h->dev[l];
@@ -1367,9 +1377,14 @@ extern "C" nnms_status nnms_autotune(nnms_system* s, int32_t reps, nnms_tuning* 
     t.spmv_lanes[l] = spmv_best(dl.rp, dl.col, val, sl.z, sl.r, sl.t, n, f64);
     const void* ptw = f64 ? (const void*)dl.pt_w64 : (const void*)dl.pt_w32;
     t.pt_lanes[l] = spmv_best(dl.pt_rp, dl.pt_col, ptw, sl.t, nullptr, s->lev[l + 1].r, nc, f64);
-    t.ras_groups[l] = ras_best(P.lev[l].ras_t, 0);
+    ras_best(l, false, t.ras_groups[l], t.ras_blocks[l]);
   }
-  t.ras_groups[L - 1] = ras_best(P.coarse, 1);
+  ras_best(L - 1, true, t.ras_groups[L - 1], t.ras_blocks[L - 1]);
+  for (int32_t* c : tcounters) {
+    int32_t v[4];
+    HIP_CHECK(hipMemcpy(v, c, sizeof v, hipMemcpyDeviceToHost));
+    if (v[2]) throw Error(NNMS_ERR_DEVICE, "triangular-solve wait limit exceeded while tuning");
+  }
   {
     const DevLevel& d0 = h->dev[0];
     t.krylov_lanes = spmv_best(d0.rp, d0.col, s->lev[0].val64, s->x, nullptr, s->w, h->host.lev[0].nv, true);

@@ -2,23 +2,31 @@
 //   z (+)= sum_p (R^0_p)^T  J_p^{-1}  R^delta_p r        (Section 2.2)
 // with J_p = L_p U_p factored into dense 64x64 tiles.
 //
-// Work unit = one 64-row block of one triangular sweep of one subdomain:
-//   forward  y_i = inv(L_ii) (r[S_p]_i - sum_{j<i} L_ij y_j)
-//   backward x_i = inv(U_ii) (y_i     - sum_{j>i} U_ij x_j)
-// The gather r[S_p] is fused into the forward blocks and the restricted
-// scatter (owned rows only) into the backward blocks.  A block waits only
-// for the blocks it reads, through per-block flags (no grid-wide barrier),
-// so blocks of all subdomains of all batched systems stream their tiles
-// concurrently.  Work items are handed out in dependency order from an
-// atomic ticket: a work-group only ever waits on tickets drawn before its
-// own, by work-groups that are already running, so the schedule cannot
-// deadlock; every wait is additionally bounded.
+// Work unit = a group of K consecutive 64-row blocks of one triangular sweep
+// of one subdomain.  For the forward sweep and a group with rows i:
+//   y_i = inv(L_ii) (r[S_p]_i - sum_{j<i} L_ij y_j)
+// the blocks j of earlier groups come from other work-groups; the blocks
+// inside the group are substituted in order inside the work-group.  The
+// backward sweep x_i = inv(U_ii) (y_i - sum_{j>i} U_ij x_j) mirrors it.  The
+// gather r[S_p] is fused into the forward groups and the restricted scatter
+// (owned rows only) into the backward groups.  A group waits only for the
+// blocks it reads (no grid-wide barrier), so groups of all subdomains of all
+// batched systems stream their tiles concurrently; K trades hand-offs
+// between work-groups (latency) against parallelism.
 //
-// Block results and flags travel through device-coherent (agent-scope)
-// relaxed atomic loads and stores; a block's results are complete (the
-// wave's stores acknowledged) before its flag is stored.  This avoids a
-// full L2 write-back / invalidate per block, which is what an agent-scope
-// release / acquire pair costs on this GPU.
+// Work items are handed out in dependency order from an atomic ticket: a
+// work-group only ever waits on tickets drawn before its own, by
+// work-groups that are already running, so the schedule cannot deadlock;
+// every wait is additionally bounded.
+//
+// Hand-off: every block result is published as tagged 64-bit words through
+// device-coherent (agent-scope) relaxed atomic stores; each word carries the
+// launch's tag (forward or backward) next to 32 bits of the value, so a
+// consumer polls the data itself: one memory round trip per hand-off, with
+// no separate flag, no store drain and no L2 write-back or invalidate (which
+// is what an agent-scope release / acquire pair costs on this GPU).  The
+// yx workspace holds 16 bytes per value: one word (FP32) or the low and high
+// halves of the FP64 bit pattern in two words.
 #include "devcommon.h"
 #include "kernels.h"
 
@@ -26,43 +34,95 @@ namespace nnms {
 
 constexpr int SPIN_LIMIT = 1 << 22;
 
-template <typename F>
-__device__ __forceinline__ F ld_coh(const F* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Launch counter shared by every smoother launch on this device: a launch
+// tags its results with a value above every launch that finished before it
+// started, so results left in a workspace by any earlier launch (of any
+// plan) never carry a current tag.  Concurrent launches may share a value;
+// they never share a workspace.
+__device__ int32_t g_ras_epoch = 0;
+
+// Pointers taken from descriptors are generic; accesses through them would
+// compile to flat loads, which also count as LDS operations, so every LDS
+// wait would drain the tile prefetches.  All device-memory accesses here go
+// through global-address-space pointers instead.
+#define GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ GLOBAL T* gptr(T* p) {
+  return (GLOBAL T*)p;
 }
-template <typename F>
-__device__ __forceinline__ void st_coh(F* p, F v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+template <typename T>
+__device__ __forceinline__ const GLOBAL T* gptr(const T* p) {
+  return (const GLOBAL T*)p;
 }
 
-// all memory operations of this wave issued so far are complete
-__device__ __forceinline__ void wave_drain() {
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  __builtin_amdgcn_s_waitcnt(0);
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+__device__ __forceinline__ uint64_t ld64(const uint64_t* p) {
+  return __hip_atomic_load(gptr(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st64(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(gptr(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <typename F, typename V>
+template <typename F>
+struct Tagged;
+template <>
+struct Tagged<float> {
+  static __device__ __forceinline__ void put(uint64_t* p, float v, uint32_t tag) {
+    st64(p, (uint64_t(tag) << 32) | uint64_t(__float_as_uint(v)));
+  }
+  // returns the word's tag; v receives the value
+  static __device__ __forceinline__ uint32_t get(const uint64_t* p, float& v) {
+    const uint64_t w = ld64(p);
+    v = __uint_as_float(uint32_t(w));
+    return uint32_t(w >> 32);
+  }
+};
+template <>
+struct Tagged<double> {
+  static __device__ __forceinline__ void put(uint64_t* p, double v, uint32_t tag) {
+    const uint64_t b = uint64_t(__double_as_longlong(v));
+    st64(p, (uint64_t(tag) << 32) | (b & 0xffffffffull));
+    st64(p + 1, (uint64_t(tag) << 32) | (b >> 32));
+  }
+  // returns the tag if both halves carry the same one, else 0
+  static __device__ __forceinline__ uint32_t get(const uint64_t* p, double& v) {
+    const uint64_t lo = ld64(p), hi = ld64(p + 1);
+    v = __longlong_as_double((long long)((hi << 32) | (lo & 0xffffffffull)));
+    const uint32_t t0 = uint32_t(lo >> 32), t1 = uint32_t(hi >> 32);
+    return t0 == t1 ? t0 : 0u;
+  }
+};
+
+template <typename F, typename V, int K>
 __global__ __launch_bounds__(256) void k_ras(RasLaunch P, int32_t* err) {
   using C = typename Chunk<F>::type;
   constexpr int W = Chunk<F>::W;
   constexpr int NQ = 16 / W;  // 16-byte chunks per lane per tile
   __shared__ F red[4][64];
   __shared__ __align__(16) F vsh[64];
+  __shared__ __align__(16) F ysh[K][64];
+  __shared__ F bsh[K][64];
+  __shared__ __align__(16) F ywv[4][2][64];  // per-wave staging of fetched result blocks
   __shared__ int s_task;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int epoch = atomic_load_acq(P.counter + 1) + 1;
+  const int epoch = __hip_atomic_load(&g_ras_epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
+  const uint32_t tag_fwd = 2u * uint32_t(epoch), tag_bwd = tag_fwd + 1u;
 
-  auto spin = [&](const int32_t* fl) {
+  // this lane's value of block j, waiting until the whole wave sees `tag`
+  // (or `tag2`, when nonzero) on its words
+  auto fetch = [&](const uint64_t* yx, int j, uint32_t tag, uint32_t tag2) -> F {
+    const uint64_t* p = yx + (size_t(j) * 64 + lane) * 2;
+    F v;
     int spins = 0;
-    while (atomic_load_rlx(fl) != epoch) {
+    for (;;) {
+      const uint32_t t = Tagged<F>::get(p, v);
+      if (__all(t == tag || (tag2 != 0u && t == tag2))) break;
       __builtin_amdgcn_s_sleep(1);
       if (++spins > SPIN_LIMIT) {
         if (lane == 0) atomicOr(err, 2);
         break;
       }
     }
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    return v;
   };
 
   for (;;) {
@@ -73,121 +133,219 @@ __global__ __launch_bounds__(256) void k_ras(RasLaunch P, int32_t* err) {
     if (t >= P.ntasks) {
       if (tid == 0 && t == P.ntasks + int(gridDim.x) - 1) {
         __hip_atomic_store(P.counter, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        atomic_store_rel(P.counter + 1, epoch);
+        __hip_atomic_fetch_max(&g_ras_epoch, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
       return;
     }
-    const int code = P.tasks[t];
-    const int sub = code >> 16, dir = (code >> 15) & 1, i = code & 0x7fff;
+    const int code = gptr(P.tasks)[t];
+    const int sub = code >> 16, dir = (code >> 15) & 1, I = code & 0x7fff;
     const SubDesc S = P.subs[sub];
     if (!slot_active(S.st, WHEN_RUNNING)) continue;
     const int N = S.N;
+    const int i0 = I * K;
+    const int nr = min(K, N - i0);  // blocks in this group
     const F* __restrict__ fac = (const F*)S.fac;
-    F* yx = (F*)S.yx;
+    uint64_t* yx = (uint64_t*)S.yx;
     const size_t NN = size_t(N) * N;
-    const int32_t* fwd_flags = P.flags + S.flag0;
-    const int32_t* bwd_flags = fwd_flags + N;
 
     auto load_tile = [&](size_t tix, C (&reg)[NQ]) {
-      const C* base = (const C*)(fac + tix * TILE_ELEMS);
+      const GLOBAL C* base = gptr((const C*)(fac + tix * TILE_ELEMS));
 #pragma unroll
       for (int q = 0; q < NQ; ++q) reg[q] = __builtin_nontemporal_load(base + (wave + 4 * q) * 64 + lane);
     };
-    // acc += tile . y (y distributed one value per lane)
-    auto gemv = [&](const C (&A)[NQ], F yl, F& acc) {
+    // acc += tile . y, y in LDS
+    auto gemv_lds = [&](const C (&A)[NQ], const F* y, F& acc) {
+      const C* yc = (const C*)y;
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        C yv;
-        F* e = (F*)&yv;
-        const int c0 = (wave + 4 * q) * W;
-#pragma unroll
-        for (int k = 0; k < W; ++k) e[k] = __shfl(yl, c0 + k, 64);
-        acc += chunk_dot(A[q], yv);
+      for (int q = 0; q < NQ; ++q) acc += chunk_dot(A[q], yc[wave + 4 * q]);
+    };
+    // reduce acc over the 4 waves into out[64] (minus it from minuend)
+    auto reduce_into = [&](F acc, F* out, const F* minuend) {
+      red[wave][lane] = acc;
+      __syncthreads();
+      if (wave == 0) {
+        const F s = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+        out[lane] = minuend ? minuend[lane] - s : s;
       }
+      __syncthreads();
     };
 
-    F acc = 0, bval = 0;
-    C A[NQ], B[NQ];
-    if (dir == 0) {
-      if (wave == 0) {
-        const int g = S.gidx[i * 64 + lane];
-        const int gg = g >= 0 ? g : -g - 2;
-        bval = (g != -1) ? F(((const V*)S.rin)[gg]) : F(0);
-      }
-      load_tile(i > 0 ? size_t(i) * N : NN + i, A);
-      int ready = -1;  // forward blocks known to be complete: 0..ready
-      for (int j = 0; j < i; ++j) {
-        if (j > ready) {
-          if (atomic_load_rlx(fwd_flags + i - 1) == epoch) {
-            ready = i - 1;
-          } else {
-            spin(fwd_flags + j);
-            ready = j;
-          }
-          __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        }
-        const F yl = ld_coh(yx + j * 64 + lane);
-        load_tile(j + 1 < i ? size_t(i) * N + j + 1 : NN + i, B);
-        gemv(A, yl, acc);
+    F acc[K];
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) A[q] = B[q];
+    for (int r = 0; r < K; ++r) acc[r] = 0;
+    const bool fwd = dir == 0;
+    const int i1 = i0 + nr - 1;
+    const uint32_t tag_in = fwd ? tag_fwd : tag_bwd;  // tag of the blocks this group reads
+
+    // right-hand sides of the group's rows: gathered r[S_p] (forward) or y (backward)
+    if (fwd) {
+      if (wave < nr) {
+        const int g = gptr(S.gidx)[(i0 + wave) * 64 + lane];
+        const int gg = g >= 0 ? g : -g - 2;
+        bsh[wave][lane] = (g != -1) ? F(gptr((const V*)S.rin)[gg]) : F(0);
       }
     } else {
-      spin(fwd_flags + N - 1);  // every forward block of this subdomain is complete
-      if (wave == 0) bval = ld_coh(yx + i * 64 + lane);
-      load_tile(size_t(i) * N + (i < N - 1 ? N - 1 : i), A);
-      int ready = N;  // backward blocks known to be complete: ready..N-1
-      for (int j = N - 1; j > i; --j) {
-        if (j < ready) {
-          if (atomic_load_rlx(bwd_flags + i + 1) == epoch) {
-            ready = i + 1;
-          } else {
-            spin(bwd_flags + j);
-            ready = j;
+      // the last forward block is published (forward or already backward
+      // tag): every forward group of this subdomain is complete
+      (void)fetch(yx, N - 1, tag_fwd, tag_bwd);
+      if (wave < nr) bsh[wave][lane] = fetch(yx, i0 + wave, tag_fwd, 0u);
+    }
+
+    // Off-diagonal stream: M tiles (blocks of other groups, in the order the
+    // chain produces them), rows of the group innermost; then the first
+    // in-group tile.  Two tiles and their two result blocks per round trip.
+    const int M = (fwd ? i0 : (N - 1 - i1)) * nr;
+    const size_t first_in = fwd ? NN + i0 : size_t(i1) * N + i1;  // inv(L_i0) / inv(U_i1)
+    auto col_of = [&](int k) -> int {
+      const int jj = k / nr;
+      return fwd ? jj : N - 1 - jj;
+    };
+    auto tile_of = [&](int k) -> size_t {
+      if (k >= M) return first_in;
+      const int r = k % nr;
+      return size_t(i0 + r) * N + col_of(k);
+    };
+    auto add_row = [&](int r, F d) {
+#pragma unroll
+      for (int kk = 0; kk < K; ++kk) acc[kk] += (kk == r) ? d : F(0);
+    };
+    C R0[NQ], R1[NQ];
+    load_tile(tile_of(0), R0);
+    if (M >= 1) load_tile(tile_of(1), R1);
+    for (int k = 0; k < M; k += 2) {
+      const bool two = k + 1 < M;
+      const int j0 = col_of(k), j1 = two ? col_of(k + 1) : j0;
+      // fetch both result blocks in one polling loop
+      const uint64_t* p0 = yx + (size_t(j0) * 64 + lane) * 2;
+      const uint64_t* p1 = yx + (size_t(j1) * 64 + lane) * 2;
+      F y0, y1;
+      {
+        int spins = 0;
+        for (;;) {
+          const uint32_t t0 = Tagged<F>::get(p0, y0);
+          const uint32_t t1 = Tagged<F>::get(p1, y1);
+          if (__all(t0 == tag_in && t1 == tag_in)) break;
+          __builtin_amdgcn_s_sleep(1);
+          if (++spins > SPIN_LIMIT) {
+            if (lane == 0) atomicOr(err, 2);
+            break;
           }
-          __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        }
-        const F yl = ld_coh(yx + j * 64 + lane);
-        load_tile(size_t(i) * N + (j - 1 > i ? j - 1 : i), B);
-        gemv(A, yl, acc);
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) A[q] = B[q];
-      }
-    }
-    red[wave][lane] = acc;
-    __syncthreads();
-    if (wave == 0) vsh[lane] = bval - ((red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]));
-    __syncthreads();
-    {
-      const C* vc = (const C*)vsh;
-      F acc2 = 0;
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) acc2 += chunk_dot(A[q], vc[wave + 4 * q]);
-      red[wave][lane] = acc2;
-    }
-    __syncthreads();
-    if (wave == 0) {
-      const F out = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
-      st_coh(yx + i * 64 + lane, out);
-      if (dir == 1) {
-        const int g = S.gidx[i * 64 + lane];
-        if (g >= 0) {
-          V* z = (V*)S.zout;
-          z[g] = P.add ? V(z[g] + V(out)) : V(out);
         }
       }
-      wave_drain();
-      if (lane == 0) __hip_atomic_store(P.flags + S.flag0 + dir * N + i, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      // stage both blocks in this wave's LDS slice; chunks are read back as broadcasts
+      ywv[wave][0][lane] = y0;
+      ywv[wave][1][lane] = y1;
+      __builtin_amdgcn_wave_barrier();
+      F d0 = 0;
+      gemv_lds(R0, ywv[wave][0], d0);
+      add_row(k % nr, d0);
+      if (k + 2 <= M) load_tile(tile_of(k + 2), R0);
+      if (two) {
+        F d1 = 0;
+        gemv_lds(R1, ywv[wave][1], d1);
+        add_row((k + 1) % nr, d1);
+        if (k + 3 <= M) load_tile(tile_of(k + 3), R1);
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+    // the first in-group tile is in R0 when M is even, in R1 when M is odd;
+    // from here on R0 is the current tile (A) and R1 the prefetched one (B)
+    if (M & 1) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) R0[q] = R1[q];
+    }
+    C(&A)[NQ] = R0;
+    C(&B)[NQ] = R1;
+    __syncthreads();  // bsh visible
+
+    if (fwd) {
+      // in-group substitution, rows i0 .. i1; A holds inv(L_i0)
+#pragma unroll
+      for (int r = 0; r < K; ++r) {
+        if (r < nr) {
+#pragma unroll
+          for (int q = 0; q < r; ++q) {  // A = L(i0+r, i0+q)
+            if (q + 1 < r)
+              load_tile(size_t(i0 + r) * N + i0 + q + 1, B);
+            else
+              load_tile(NN + i0 + r, B);
+            F d = 0;
+            gemv_lds(A, ysh[q], d);
+            acc[r] += d;
+#pragma unroll
+            for (int c = 0; c < NQ; ++c) A[c] = B[c];
+          }
+          // A = inv(L_{i0+r}); v = b - acc
+          reduce_into(acc[r], vsh, bsh[r]);
+          if (r + 1 < nr) load_tile(size_t(i0 + r + 1) * N + i0, B);  // next row's first in-group tile
+          F a2 = 0;
+          gemv_lds(A, vsh, a2);
+          reduce_into(a2, ysh[r], nullptr);
+          if (wave == 0) Tagged<F>::put(yx + (size_t(i0 + r) * 64 + lane) * 2, ysh[r][lane], tag_fwd);
+          if (r + 1 < nr) {
+#pragma unroll
+            for (int c = 0; c < NQ; ++c) A[c] = B[c];
+          }
+        }
+      }
+    } else {
+      // in-group back substitution, rows i1 down to i0; A holds inv(U_i1)
+#pragma unroll
+      for (int rr = 0; rr < K; ++rr) {
+        const int r = nr - 1 - rr;
+        if (r >= 0) {
+          F ar = 0;
+#pragma unroll
+          for (int kk = 0; kk < K; ++kk)
+            if (kk == r) ar = acc[kk];
+          // A = U(i0+r, i0+q) for q = nr-1 .. r+1, then inv(U_{i0+r})
+          for (int q = nr - 1; q > r; --q) {
+            if (q - 1 > r)
+              load_tile(size_t(i0 + r) * N + i0 + q - 1, B);
+            else
+              load_tile(size_t(i0 + r) * N + i0 + r, B);
+            F d = 0;
+            gemv_lds(A, ysh[q], d);
+            ar += d;
+#pragma unroll
+            for (int c = 0; c < NQ; ++c) A[c] = B[c];
+          }
+          reduce_into(ar, vsh, bsh[r]);
+          if (r - 1 >= 0) load_tile(size_t(i0 + r - 1) * N + i1, B);  // next row's first in-group tile
+          F a2 = 0;
+          gemv_lds(A, vsh, a2);
+          reduce_into(a2, ysh[r], nullptr);
+          if (wave == 0) {
+            const F out = ysh[r][lane];
+            const int g = gptr(S.gidx)[(i0 + r) * 64 + lane];
+            if (g >= 0) {
+              GLOBAL V* z = gptr((V*)S.zout);
+              z[g] = P.add ? V(z[g] + V(out)) : V(out);
+            }
+            Tagged<F>::put(yx + (size_t(i0 + r) * 64 + lane) * 2, out, tag_bwd);
+          }
+          if (r - 1 >= 0) {
+#pragma unroll
+            for (int c = 0; c < NQ; ++c) A[c] = B[c];
+          }
+        }
+      }
     }
   }
 }
+
 
 template <typename F, typename V>
 hipError_t launch_ras(const RasLaunch& p, int grid, hipStream_t s) {
   if (p.ntasks <= 0) return hipSuccess;
   if (grid > p.ntasks) grid = p.ntasks;
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL((k_ras<F, V>), dim3(grid), dim3(256), 0, s, p, p.counter + 2);
+  switch (p.group) {
+    case 1: hipLaunchKernelGGL((k_ras<F, V, 1>), dim3(grid), dim3(256), 0, s, p, p.counter + 2); break;
+    case 2: hipLaunchKernelGGL((k_ras<F, V, 2>), dim3(grid), dim3(256), 0, s, p, p.counter + 2); break;
+    case 4: hipLaunchKernelGGL((k_ras<F, V, 4>), dim3(grid), dim3(256), 0, s, p, p.counter + 2); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -66,17 +66,19 @@ class solve_info(C.Structure):
 
 class tuning_t(C.Structure):
     _fields_ = [("spmv_lanes", C.c_int32 * MAX_LEVELS), ("pt_lanes", C.c_int32 * MAX_LEVELS),
-                ("ras_groups", C.c_int32 * MAX_LEVELS), ("krylov_lanes", C.c_int32), ("tuned", C.c_int32)]
+                ("ras_groups", C.c_int32 * MAX_LEVELS), ("ras_blocks", C.c_int32 * MAX_LEVELS),
+                ("krylov_lanes", C.c_int32), ("tuned", C.c_int32)]
 
     def to_dict(self):
         return {"spmv_lanes": list(self.spmv_lanes), "pt_lanes": list(self.pt_lanes),
-                "ras_groups": list(self.ras_groups), "krylov_lanes": int(self.krylov_lanes), "tuned": int(self.tuned)}
+                "ras_groups": list(self.ras_groups), "ras_blocks": list(self.ras_blocks),
+                "krylov_lanes": int(self.krylov_lanes), "tuned": int(self.tuned)}
 
     @classmethod
     def from_dict(cls, d):
         t = cls()
-        for k in ("spmv_lanes", "pt_lanes", "ras_groups"):
-            for i, v in enumerate(d[k]):
+        for k in ("spmv_lanes", "pt_lanes", "ras_groups", "ras_blocks"):
+            for i, v in enumerate(d.get(k, [1] * MAX_LEVELS)):
                 getattr(t, k)[i] = int(v)
         t.krylov_lanes, t.tuned = int(d["krylov_lanes"]), int(d.get("tuned", 1))
         return t

@@ -54,3 +54,45 @@ def test_autotune_keeps_results_and_caches(tmp_path):
         bad = dict(t)
         bad["spmv_lanes"] = [3] * 8
         h.set_tuning(bad)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_blocks_per_work_item_same_bits(precision):
+    """Grouping K blocks per work item changes who computes a block, not the
+    order of any sum: the solves for K = 1, 2, 4 are bitwise identical, and
+    the smoother matches the oracle's on every level."""
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from oracle import problem as oprob
+    from paper_2412_08981_amd import nnms
+
+    pb = W.Problem("k", W.make_hierarchy([17, 8, 4], [21, 22, 23]), [4, 2], W.kappa_draw(204, 206),
+                   precision=precision)
+    prec = nnms.MIXED if precision == "mixed" else nnms.FP64
+    ms = [nnms.Mesh.from_workload(m) for m in pb.meshes]
+    h = nnms.Hierarchy(ms, pb.nparts, precision=prec)
+    o = oprob.build(pb)
+    base = h.get_tuning()
+    ref = None
+    rng = np.random.default_rng(5)
+    for K in (1, 2, 4):
+        d = dict(base)
+        d["ras_blocks"] = [K] * 8
+        h.set_tuning(d)
+        s = nnms.System(h, pb.kappa)
+        x, info = s.solve(o.b)
+        assert info.status == 0 and info.relres <= 1e-8
+        if ref is None:
+            ref = x
+        else:
+            assert np.array_equal(x, ref), K
+        if precision == "fp64":
+            for l in range(3):
+                r = rng.standard_normal(s.n[l])
+                r[pb.meshes[l].dirichlet != 0] = 0
+                z = s.apply_smoother(l, r)
+                zr = o.vcycle.levels[l].ras.apply(r) if l < 2 else np.linalg.solve(o.A[l].toarray(), r)
+                assert np.linalg.norm(z - zr) <= 1e-9 * np.linalg.norm(zr), (K, l)
+        s.destroy()
