@@ -315,6 +315,10 @@ def main():
     ms = s.time_kernel(0, 0, reps=10)
     ach = ras_bytes(h, 0, sb) / (ms * 1e-3) / 1e9
     extra = {}
+    fac_bytes = (h.level_info(0).factor_elems * sb // 16) * 16
+    ms_read = s.time_kernel(5, 0, reps=5)
+    extra["read_reference_GBs"] = round(fac_bytes / (ms_read * 1e-3) / 1e9, 1)
+    extra["smoother_l0_frac_of_read_reference"] = round(ach / extra["read_reference_GBs"], 4)
     for lvl in range(h.L):
         extra[f"smoother_l{lvl}_ms"] = round(s.time_kernel(0, lvl, reps=10), 4)
     for lvl in range(h.L - 1):

@@ -231,7 +231,8 @@ nnms_status nnms_apply_vcycle(nnms_system* s, const double* r_host, double* z_ho
  * coarsest direct solve), 1 level operator residual t = r - A z,
  * 2 prolongation, 3 restriction, 4 a plain 16-byte streaming copy of the
  * level's factor storage into a temporary buffer (a reference of known
- * size for hardware byte counters).  reps >= 1.
+ * size for hardware byte counters), 5 a read-only streaming pass over the
+ * level's factor storage (the achievable read bandwidth).  reps >= 1.
  * ------------------------------------------------------------------------- */
 nnms_status nnms_time_kernel(nnms_system* s, int32_t kind, int32_t level, int32_t reps, double* ms_host);
 

@@ -1165,7 +1165,7 @@ extern "C" nnms_status nnms_batch_destroy(nnms_batch* bt) {
 
 extern "C" nnms_status nnms_time_kernel(nnms_system* s, int32_t kind, int32_t level, int32_t reps, double* ms) {
   ABI_BEGIN
-  if (!s || !ms || reps < 1 || level < 0 || level >= s->h->host.L || kind < 0 || kind > 4)
+  if (!s || !ms || reps < 1 || level < 0 || level >= s->h->host.L || kind < 0 || kind > 5)
     throw Error(NNMS_ERR_INVALID_ARG, "bad arguments");
   const int L = s->h->host.L;
   if ((kind == 1 || kind == 2 || kind == 3) && level == L - 1)
@@ -1176,13 +1176,19 @@ extern "C" nnms_status nnms_time_kernel(nnms_system* s, int32_t kind, int32_t le
   const bool fac64 = f64 || level == L - 1;
   const int64_t copy_bytes = (s->h->host.lev[level].fac_elems * (fac64 ? 8 : 4)) & ~int64_t(15);
   std::unique_ptr<Arena> copy_dst;
+  const int read_grid = ras_grid_default() * 2;
   if (kind == 4) {
     copy_dst = std::make_unique<Arena>(s->h->has_alloc ? &s->h->alloc : nullptr);
     copy_dst->raw(size_t(copy_bytes));
+  } else if (kind == 5) {
+    copy_dst = std::make_unique<Arena>(s->h->has_alloc ? &s->h->alloc : nullptr);
+    copy_dst->raw(size_t(read_grid) * 4 * sizeof(int));
   }
   auto launch = [&]() {
     if (kind == 4) {
       HIP_CHECK(launch_copy16(s->lev[level].fac, copy_dst->bufs[0].first, copy_bytes, st));
+    } else if (kind == 5) {
+      HIP_CHECK(launch_read16(s->lev[level].fac, copy_bytes, (int*)copy_dst->bufs[0].first, read_grid, st));
     } else if (kind == 0) {
       if (level == L - 1) {
         if (f64)

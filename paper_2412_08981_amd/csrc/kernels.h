@@ -17,6 +17,7 @@ hipError_t launch_fill(T* p, int64_t n, T v, hipStream_t s);
 hipError_t launch_cast_d2f(const double* a, float* b, int64_t n, hipStream_t s);
 hipError_t launch_cast_f2d(const float* a, double* b, int64_t n, hipStream_t s);
 hipError_t launch_copy16(const void* a, void* b, int64_t bytes, hipStream_t s);
+hipError_t launch_read16(const void* a, int64_t bytes, int* out, int grid, hipStream_t s);
 
 // ras.hip: one restricted additive Schwarz application (all subdomains of
 // all slots), forward and backward block triangular solves with gather and

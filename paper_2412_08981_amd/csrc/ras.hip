@@ -92,8 +92,15 @@ struct Tagged<double> {
   }
 };
 
+// waves per SIMD the register allocation must allow: single-block work items
+// in FP64 are held to three (one spill slot) instead of two
+template <typename F, int K>
+struct RasWaves {
+  static constexpr int value = (K == 1 && sizeof(F) == 8) ? 3 : 1;
+};
+
 template <typename F, typename V, int K>
-__global__ __launch_bounds__(256) void k_ras(RasLaunch P, int32_t* err) {
+__global__ __launch_bounds__(256, (RasWaves<F, K>::value)) void k_ras(RasLaunch P, int32_t* err) {
   using C = typename Chunk<F>::type;
   constexpr int W = Chunk<F>::W;
   constexpr int NQ = 16 / W;  // 16-byte chunks per lane per tile
@@ -239,11 +246,15 @@ __global__ __launch_bounds__(256) void k_ras(RasLaunch P, int32_t* err) {
       F d0 = 0;
       gemv_lds(R0, ywv[wave][0], d0);
       add_row(k % nr, d0);
+      // keep the refill of a tile's registers after their last use, so the
+      // compiler does not double-buffer them (register pressure = occupancy)
+      __builtin_amdgcn_sched_barrier(0);
       if (k + 2 <= M) load_tile(tile_of(k + 2), R0);
       if (two) {
         F d1 = 0;
         gemv_lds(R1, ywv[wave][1], d1);
         add_row((k + 1) % nr, d1);
+        __builtin_amdgcn_sched_barrier(0);
         if (k + 3 <= M) load_tile(tile_of(k + 3), R1);
       }
       __builtin_amdgcn_wave_barrier();

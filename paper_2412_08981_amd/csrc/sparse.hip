@@ -136,3 +136,35 @@ hipError_t launch_copy16(const void* a, void* b, int64_t bytes, hipStream_t s) {
   return hipGetLastError();
 }
 }  // namespace nnms
+
+namespace nnms {
+// read-only streaming reference: every work-item sums 16-byte chunks, eight
+// loads in flight, and writes one value per work-group (the achievable read
+// bandwidth of the memory system for a large resident array)
+typedef int ivec4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_read16(const ivec4* __restrict__ a, int64_t n, int* out) {
+  int acc = 0;
+  const int64_t stride = int64_t(gridDim.x) * 256;
+  int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  for (; i + 7 * stride < n; i += 8 * stride) {
+    ivec4 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = __builtin_nontemporal_load(a + i + u * stride);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
+  }
+  for (; i < n; i += stride) {
+    const ivec4 v = a[i];
+    acc ^= v.x ^ v.y ^ v.z ^ v.w;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc ^= __shfl_xor(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) out[blockIdx.x * 4 + (threadIdx.x >> 6)] = acc;
+}
+hipError_t launch_read16(const void* a, int64_t bytes, int* out, int grid, hipStream_t s) {
+  const int64_t n = bytes / 16;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_read16, dim3(grid), dim3(256), 0, s, (const ivec4*)a, n, out);
+  return hipGetLastError();
+}
+}  // namespace nnms
