@@ -17,10 +17,13 @@ DEFAULT_CACHE = os.path.join(HERE, "tuning.json")
 
 
 def _device_name() -> str:
+    """Architecture and compute-unit count (stable across tools, unlike the
+    marketing name)."""
     try:
         import torch
 
-        return torch.cuda.get_device_name(0)
+        p = torch.cuda.get_device_properties(0)
+        return f"{getattr(p, 'gcnArchName', 'gpu').split(':')[0]}-{p.multi_processor_count}cu"
     except Exception:
         return "unknown"
 

@@ -55,7 +55,8 @@ struct Arena {
       hipError_t e = hipMalloc(&p, bytes);
       if (e != hipSuccess) {
         (void)hipGetLastError();
-        throw Error(NNMS_ERR_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+        throw Error(NNMS_ERR_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
+                                                hipGetErrorName(e));
       }
     }
     bufs.emplace_back(p, bytes);

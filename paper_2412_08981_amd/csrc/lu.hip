@@ -106,13 +106,21 @@ hipError_t launch_extract(const FacDesc* d, int nd, int maxn, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// diagonal tile: LU in LDS, then inv(L_kk) (unit lower) and inv(U_kk)
+// diagonal tile: LU, then inv(L_kk) (unit lower) and inv(U_kk).
+// LU: work-item c < 64 keeps column c in registers; at step c it scales its
+// column below the diagonal and publishes the multipliers through LDS, and
+// every column to its right applies the rank-1 update.  Inverses: one
+// work-item per column of inv(L) (items 0..63) and of inv(U) (items
+// 64..127), each column in registers, the factor rows read from LDS as
+// broadcasts; loops are unrolled so that the register columns have fixed
+// indices.
 // ---------------------------------------------------------------------------
 template <typename F>
 __global__ __launch_bounds__(256) void k_lu_diag(const FacDesc* __restrict__ d, int k, int* err) {
   const FacDesc D = d[blockIdx.x];
   if (k >= D.N) return;
-  __shared__ F a[64][LDP], li[64][LDP], ui[64][LDP];
+  __shared__ F a[64][LDP];
+  __shared__ F lbuf[64];
   const int tid = threadIdx.x;
   const size_t N = D.N;
   F* fac = (F*)D.fac;
@@ -120,42 +128,70 @@ __global__ __launch_bounds__(256) void k_lu_diag(const FacDesc* __restrict__ d, 
   F* linv = fac + (N * N + k) * TILE_ELEMS;
   tile_to_lds<F>(tkk, a);
   __syncthreads();
+  F col[64];
+  if (tid < 64) {
+#pragma unroll
+    for (int r = 0; r < 64; ++r) col[r] = a[r][tid];
+  }
+#pragma unroll
   for (int c = 0; c < 64; ++c) {
-    const F piv = a[c][c];
-    if (tid == 0 && !(piv > F(0) && piv < F(INFINITY))) atomicOr(err, 1);
-    if (tid > c && tid < 64) a[tid][c] = a[tid][c] / piv;
+    if (tid == c) {
+      const F piv = col[c];
+      if (!(piv > F(0) && piv < F(INFINITY))) atomicOr(err, 1);
+      const F rp = F(1) / piv;
+#pragma unroll
+      for (int r = c + 1; r < 64; ++r) {
+        col[r] *= rp;
+        lbuf[r] = col[r];
+      }
+    }
     __syncthreads();
-    const int m = 63 - c;
-    for (int idx = tid; idx < m * m; idx += 256) {
-      const int r = c + 1 + idx / m, cc = c + 1 + idx % m;
-      a[r][cc] -= a[r][c] * a[c][cc];
+    if (tid > c && tid < 64) {
+      const F u = col[c];
+#pragma unroll
+      for (int r = c + 1; r < 64; ++r) col[r] -= lbuf[r] * u;
     }
     __syncthreads();
   }
-  if (tid < 64) {  // column tid of inv(L): forward substitution with unit diagonal
-    const int c = tid;
-    for (int r = 0; r < 64; ++r) {
-      F s = (r == c) ? F(1) : F(0);
-      if (r > c) {
-        for (int q = c; q < r; ++q) s -= a[r][q] * li[q][c];
-      }
-      li[r][c] = s;
-    }
-  } else if (tid < 128) {  // column c of inv(U): back substitution
-    const int c = tid - 64;
-    for (int r = 63; r >= 0; --r) {
-      if (r > c) {
-        ui[r][c] = F(0);
-        continue;
-      }
-      F s = (r == c) ? F(1) : F(0);
-      for (int q = r + 1; q <= c; ++q) s -= a[r][q] * ui[q][c];
-      ui[r][c] = s / a[r][r];
-    }
+  if (tid < 64) {
+#pragma unroll
+    for (int r = 0; r < 64; ++r) a[r][tid] = col[r];
   }
   __syncthreads();
-  lds_to_tile<F>(ui, tkk);
-  lds_to_tile<F>(li, linv);
+  F x[64];
+  if (tid < 64) {  // column c of inv(L): x_r = [r==c] - sum_{q<r} L_rq x_q
+    const int c = tid;
+#pragma unroll
+    for (int r = 0; r < 64; ++r) {
+      F s = (r == c) ? F(1) : F(0);
+#pragma unroll
+      for (int q = 0; q < r; ++q) s -= a[r][q] * x[q];
+      x[r] = (r >= c) ? s : F(0);
+    }
+  } else if (tid < 128) {  // column c of inv(U): x_r = ([r==c] - sum_{q>r} U_rq x_q) / U_rr
+    const int c = tid - 64;
+#pragma unroll
+    for (int r = 63; r >= 0; --r) {
+      F s = (r == c) ? F(1) : F(0);
+#pragma unroll
+      for (int q = r + 1; q < 64; ++q) s -= a[r][q] * x[q];
+      x[r] = (r <= c) ? s / a[r][r] : F(0);
+    }
+  }
+  __syncthreads();  // every column read the factor: reuse a for inv(U), lbuf-free
+  if (tid >= 64 && tid < 128) {
+#pragma unroll
+    for (int r = 0; r < 64; ++r) a[r][tid - 64] = x[r];
+  }
+  __syncthreads();
+  lds_to_tile<F>(a, tkk);
+  __syncthreads();
+  if (tid < 64) {
+#pragma unroll
+    for (int r = 0; r < 64; ++r) a[r][tid] = x[r];
+  }
+  __syncthreads();
+  lds_to_tile<F>(a, linv);
 }
 
 // ---------------------------------------------------------------------------

@@ -18,6 +18,15 @@ LIB_PATH = os.path.join(_HERE, "libnnms.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run paper_2412_08981_amd.build.build() first")
+# One HIP runtime per process.  PyTorch ships its own libamdhip64 and links it
+# by a name that does not match the soname this library asks for, so loading
+# this library first would bring in a second runtime, and whichever of the two
+# opens the device last gets no device.  Loading PyTorch first makes this
+# library bind to PyTorch's runtime (same soname).
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
 _lib = C.CDLL(LIB_PATH)
 
 MAX_LEVELS = 8

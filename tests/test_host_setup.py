@@ -126,3 +126,16 @@ def test_dirichlet_default_is_bounding_box():
     h = nnms.Hierarchy([a], [], device=False)
     owner, sets = h.partition(0)
     assert np.array_equal(owner >= 0, m.dirichlet == 0)
+
+
+def test_one_hip_runtime_whatever_the_import_order():
+    """Importing the binding before PyTorch must not map a second HIP runtime
+    (two runtimes in one process leave the later one without a device)."""
+    code = ("import re, sys; sys.path.insert(0, %r)\n"
+            "from paper_2412_08981_amd import nnms\n"
+            "import torch\n"
+            "maps = open('/proc/self/maps').read()\n"
+            "print(len(set(re.findall(r'(\\S*libamdhip64\\S*)', maps))))\n") % ROOT
+    out = subprocess.run(["python", "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip() == "1"
