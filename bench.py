@@ -20,6 +20,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {8: 78.6, 4: 157.3}  # dense FP64 / FP32 matrix peaks
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_ras_c2_{prec}_pmc.md")
 
 
@@ -62,6 +63,14 @@ def ras_bytes(h, level, s_bytes):
     owner, sets = h.partition(level)
     n = np.array([len(S) for S in sets], dtype=np.float64)
     return float(np.sum(n * n) * s_bytes + np.sum(n) * (s_bytes + 4) + np.sum(n) * s_bytes)
+
+
+def lu_flops(h, level):
+    """Algorithmic flops of the level's dense subdomain LUs: (2/3) n_p^3 each
+    (unpadded sizes; the kernels also run the 64-padding)."""
+    owner, sets = h.partition(level)
+    n = np.array([len(S) for S in sets], dtype=np.float64)
+    return float(np.sum(2.0 / 3.0 * n ** 3))
 
 
 def spmv_bytes(h, level, s_bytes):
@@ -330,6 +339,15 @@ def main():
         extra[f"residual_l{lvl}_GBs"] = round(spmv_bytes(h, lvl, sb) / (msr * 1e-3) / 1e9, 1)
         extra[f"prolong_l{lvl}_ms"] = round(s.time_kernel(2, lvl, reps=20), 4)
         extra[f"restrict_l{lvl}_ms"] = round(s.time_kernel(3, lvl, reps=20), 4)
+    # numeric factorisation per level (fill + extraction + blocked LU) against the MFMA peak
+    for lvl in range(h.L):
+        fb = 8 if (prec == nnms.FP64 or lvl == h.L - 1) else 4
+        msf = s.time_kernel(6, lvl, reps=3)
+        tf = lu_flops(h, lvl) / (msf * 1e-3) / 1e12
+        extra[f"factor_l{lvl}_ms"] = round(msf, 3)
+        extra[f"factor_l{lvl}_TFLOPs"] = round(tf, 2)
+        extra[f"factor_l{lvl}_frac_of_mfma_peak"] = round(tf / MFMA_PEAK_TFLOPS[fb], 4)
+    extra["parametric_solves_per_s"] = round(1.0 / (t_assemble + el / args.steps), 3)
     log(f"[bench] kernels: {extra}")
 
     x = xd.cpu().numpy()

@@ -232,7 +232,10 @@ nnms_status nnms_apply_vcycle(nnms_system* s, const double* r_host, double* z_ho
  * 2 prolongation, 3 restriction, 4 a plain 16-byte streaming copy of the
  * level's factor storage into a temporary buffer (a reference of known
  * size for hardware byte counters), 5 a read-only streaming pass over the
- * level's factor storage (the achievable read bandwidth).  reps >= 1.
+ * level's factor storage (the achievable read bandwidth), 6 the level's
+ * numeric factorisation (zero fill of the tile storage, extraction of the
+ * dense subdomain matrices, blocked LU), redone in place from the same
+ * matrix values, which reproduces the same factors.  reps >= 1.
  * ------------------------------------------------------------------------- */
 nnms_status nnms_time_kernel(nnms_system* s, int32_t kind, int32_t level, int32_t reps, double* ms_host);
 

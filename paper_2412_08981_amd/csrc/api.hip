@@ -724,6 +724,57 @@ extern "C" int64_t nnms_hierarchy_system_bytes(const nnms_hierarchy* h, int32_t 
   return system_bytes(h->host, h->host.opts.precision, restart > 0 ? restart : 30);
 }
 
+// Dense subdomain matrices of one level and their factorisation: zero fill
+// of the tile storage, extraction of A[S_p, S_p], blocked LU.
+struct FactorJob {
+  std::vector<FacDesc> host;  // source of the upload, kept alive with the job
+  FacDesc* d = nullptr;       // device array, one per subdomain
+  int nd = 0, maxn = 0, maxN = 0;
+  bool f64 = true;
+  void* fac = nullptr;
+  int64_t elems = 0;
+};
+
+static FactorJob factor_job(const nnms_system& sys, int l, Arena& mem, hipStream_t s) {
+  const HostLevel& hl = sys.h->host.lev[l];
+  const DevLevel& dl = sys.h->dev[l];
+  const SysLevel& sl = sys.lev[l];
+  FactorJob job;
+  job.f64 = (l == sys.h->host.L - 1) || sys.prec == NNMS_FP64;
+  const size_t fsz = job.f64 ? 8 : 4;
+  std::vector<FacDesc>& fd = job.host;
+  for (int p = 0; p < hl.nparts; ++p) {
+    FacDesc d{};
+    d.fac = (char*)sl.fac + size_t(hl.fac_off[p]) * fsz;
+    d.gidx = dl.gidx + hl.g_off[p];
+    d.ext_rs = dl.ext_rs + hl.s_ptr[p];
+    d.ext_lc = dl.ext_lc;
+    d.rp = dl.rp;
+    d.val = sl.val64;
+    d.n = int(hl.s_ptr[p + 1] - hl.s_ptr[p]);
+    d.N = hl.nblk[p];
+    job.maxn = std::max(job.maxn, d.n), job.maxN = std::max(job.maxN, d.N);
+    fd.push_back(d);
+  }
+  job.d = mem.upload(fd, s);
+  job.nd = int(fd.size());
+  job.fac = sl.fac;
+  job.elems = hl.fac_elems;
+  return job;
+}
+
+static hipError_t enqueue_factor(const FactorJob& j, int* err, hipStream_t s) {
+  hipError_t e;
+  if (j.f64) {
+    if ((e = launch_fill<double>((double*)j.fac, j.elems, 0.0, s)) != hipSuccess) return e;
+    if ((e = launch_extract<double>(j.d, j.nd, j.maxn, s)) != hipSuccess) return e;
+    return launch_lu<double>(j.d, j.nd, j.maxN, err, s);
+  }
+  if ((e = launch_fill<float>((float*)j.fac, j.elems, 0.0f, s)) != hipSuccess) return e;
+  if ((e = launch_extract<float>(j.d, j.nd, j.maxn, s)) != hipSuccess) return e;
+  return launch_lu<float>(j.d, j.nd, j.maxN, err, s);
+}
+
 extern "C" nnms_status nnms_assemble(nnms_hierarchy* h, const nnms_kappa* k, double f, void* stream, nnms_system** out) {
   ABI_BEGIN
   if (!h || !k || !out) throw Error(NNMS_ERR_INVALID_ARG, "null argument");
@@ -784,31 +835,8 @@ extern "C" nnms_status nnms_assemble(nnms_hierarchy* h, const nnms_kappa* k, dou
     }
     HIP_CHECK(launch_assemble(ad, kd, f, s));
     // dense subdomain matrices and their factors
-    std::vector<FacDesc> fd;
-    int maxn = 0, maxN = 0;
-    for (int p = 0; p < hl.nparts; ++p) {
-      FacDesc d{};
-      d.fac = (char*)sl.fac + size_t(hl.fac_off[p]) * fsz;
-      d.gidx = dl.gidx + hl.g_off[p];
-      d.ext_rs = dl.ext_rs + hl.s_ptr[p];
-      d.ext_lc = dl.ext_lc;
-      d.rp = dl.rp;
-      d.val = sl.val64;
-      d.n = int(hl.s_ptr[p + 1] - hl.s_ptr[p]);
-      d.N = hl.nblk[p];
-      maxn = std::max(maxn, d.n), maxN = std::max(maxN, d.N);
-      fd.push_back(d);
-    }
-    FacDesc* dfd = scratch.upload(fd, s);
-    if (fsz == 8) {
-      HIP_CHECK(launch_fill<double>((double*)sl.fac, hl.fac_elems, 0.0, s));
-      HIP_CHECK(launch_extract<double>(dfd, int(fd.size()), maxn, s));
-      for (int kk = 0; kk < maxN; ++kk) HIP_CHECK(launch_lu_step<double>(dfd, int(fd.size()), kk, maxN, err, s));
-    } else {
-      HIP_CHECK(launch_fill<float>((float*)sl.fac, hl.fac_elems, 0.0f, s));
-      HIP_CHECK(launch_extract<float>(dfd, int(fd.size()), maxn, s));
-      for (int kk = 0; kk < maxN; ++kk) HIP_CHECK(launch_lu_step<float>(dfd, int(fd.size()), kk, maxN, err, s));
-    }
+    FactorJob job = factor_job(*sys, l, scratch, s);
+    HIP_CHECK(enqueue_factor(job, err, s));
   }
   // solve workspace
   const int64_t n0 = H.lev[0].nv;
@@ -1166,7 +1194,7 @@ extern "C" nnms_status nnms_batch_destroy(nnms_batch* bt) {
 
 extern "C" nnms_status nnms_time_kernel(nnms_system* s, int32_t kind, int32_t level, int32_t reps, double* ms) {
   ABI_BEGIN
-  if (!s || !ms || reps < 1 || level < 0 || level >= s->h->host.L || kind < 0 || kind > 5)
+  if (!s || !ms || reps < 1 || level < 0 || level >= s->h->host.L || kind < 0 || kind > 6)
     throw Error(NNMS_ERR_INVALID_ARG, "bad arguments");
   const int L = s->h->host.L;
   if ((kind == 1 || kind == 2 || kind == 3) && level == L - 1)
@@ -1185,8 +1213,19 @@ extern "C" nnms_status nnms_time_kernel(nnms_system* s, int32_t kind, int32_t le
     copy_dst = std::make_unique<Arena>(s->h->has_alloc ? &s->h->alloc : nullptr);
     copy_dst->raw(size_t(read_grid) * 4 * sizeof(int));
   }
+  // kind 6 refactors the level in place: the same values give the same factors
+  std::unique_ptr<Arena> fac_mem;
+  FactorJob job;
+  int* ferr = nullptr;
+  if (kind == 6) {
+    fac_mem = std::make_unique<Arena>(s->h->has_alloc ? &s->h->alloc : nullptr);
+    job = factor_job(*s, level, *fac_mem, st);
+    ferr = fac_mem->alloc<int>(1, st);
+  }
   auto launch = [&]() {
-    if (kind == 4) {
+    if (kind == 6) {
+      HIP_CHECK(enqueue_factor(job, ferr, st));
+    } else if (kind == 4) {
       HIP_CHECK(launch_copy16(s->lev[level].fac, copy_dst->bufs[0].first, copy_bytes, st));
     } else if (kind == 5) {
       HIP_CHECK(launch_read16(s->lev[level].fac, copy_bytes, (int*)copy_dst->bufs[0].first, read_grid, st));

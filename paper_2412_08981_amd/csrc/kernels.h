@@ -28,8 +28,9 @@ hipError_t launch_ras(const RasLaunch& p, int grid, hipStream_t s);
 // lu.hip
 template <typename F>
 hipError_t launch_extract(const FacDesc* d, int nd, int maxn, hipStream_t s);
+// complete blocked LU of every subdomain (maxN = largest tile count)
 template <typename F>
-hipError_t launch_lu_step(const FacDesc* d, int nd, int k, int maxN, int* err, hipStream_t s);
+hipError_t launch_lu(const FacDesc* d, int nd, int maxN, int* err, hipStream_t s);
 
 // assemble.hip
 hipError_t launch_assemble(const AsmDesc& a, const KappaDev& k, double f, hipStream_t s);

@@ -9,16 +9,22 @@
 // blocks turn every step of the triangular solves into a 64x64
 // matrix-vector product.
 //
-// Right-looking blocked LU, one launch triple per block column k:
-//   diag   factor A_kk = L_kk U_kk in LDS, invert both triangles;
-//   panel  L_ik = A_ik inv(U_kk),  U_ki = inv(L_kk) A_ki      (MFMA);
-//   update A_ij -= L_ik U_kj for i, j > k                      (MFMA).
+// Right-looking LU blocked twice: 64-wide tile columns, grouped into blocks
+// of LU_DEPTH tile columns.  For block column k0 .. k0+D-1 and each k in it:
+//   diag   A_kk -= sum_{k0<=s<k} L_ks U_sk, then A_kk = L_kk U_kk in
+//          registers, invert both triangles;
+//   panel  A_ik -= sum_s L_is U_sk, L_ik = A_ik inv(U_kk)      (i > k),
+//          A_kj -= sum_s L_ks U_sj, U_kj = inv(L_kk) A_kj      (j > k);
+// then one trailing update A_ij -= sum_{s in block} L_is U_sj for every i, j
+// past the block, so each trailing tile is read and written once per D tile
+// columns instead of once per tile column.  Every product runs on MFMA.
 #include "devcommon.h"
 #include "kernels.h"
 
 namespace nnms {
 
 constexpr int LDP = 65;  // LDS row pitch
+constexpr int LU_DEPTH = 4;  // tile columns per trailing update
 
 template <typename F>
 struct Mma;
@@ -106,7 +112,147 @@ hipError_t launch_extract(const FacDesc* d, int nd, int maxn, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// diagonal tile: LU, then inv(L_kk) (unit lower) and inv(U_kk).
+// C += A * B on 64x64 tiles staged in LDS, MFMA 16x16x4; wave w owns the
+// 32x32 quadrant (w/2, w%2) of C.
+// ---------------------------------------------------------------------------
+template <typename F>
+__device__ __forceinline__ void tile_mma(F (*As)[LDP], F (*Bs)[LDP], typename Mma<F>::acc_t (&acc)[2][2]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int R0 = (wave >> 1) * 32, C0 = (wave & 1) * 32;
+  const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll 4
+  for (int kk = 0; kk < 16; ++kk) {
+    const int kc = kk * 4 + lk;
+    F a0 = As[R0 + lr][kc], a1 = As[R0 + 16 + lr][kc];
+    F b0 = Bs[kc][C0 + lr], b1 = Bs[kc][C0 + 16 + lr];
+    acc[0][0] = Mma<F>::op(a0, b0, acc[0][0]);
+    acc[0][1] = Mma<F>::op(a0, b1, acc[0][1]);
+    acc[1][0] = Mma<F>::op(a1, b0, acc[1][0]);
+    acc[1][1] = Mma<F>::op(a1, b1, acc[1][1]);
+  }
+}
+
+template <typename F>
+__device__ __forceinline__ void acc_to_lds(typename Mma<F>::acc_t (&acc)[2][2], F (*Cs)[LDP]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int R0 = (wave >> 1) * 32, C0 = (wave & 1) * 32;
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Cs[R0 + rb * 16 + Mma<F>::row(lane, v)][C0 + cb * 16 + (lane & 15)] = acc[rb][cb][v];
+}
+
+// ---------------------------------------------------------------------------
+// Products with operands read straight from the tiles in global memory (no
+// LDS, no barriers).  Wave w owns the 32x32 quadrant (w/2, w%2) of the 64x64
+// output; the accumulator holds the quadrant in MFMA output layout.
+// ---------------------------------------------------------------------------
+template <typename F>
+__device__ __forceinline__ void acc_load(const F* __restrict__ T, typename Mma<F>::acc_t (&acc)[2][2]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int R0 = (wave >> 1) * 32, C0 = (wave & 1) * 32;
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        acc[rb][cb][v] = T[tile_off<F>(R0 + rb * 16 + Mma<F>::row(lane, v), C0 + cb * 16 + (lane & 15))];
+}
+
+template <typename F>
+__device__ __forceinline__ void acc_store(typename Mma<F>::acc_t (&acc)[2][2], F* __restrict__ T) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int R0 = (wave >> 1) * 32, C0 = (wave & 1) * 32;
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        T[tile_off<F>(R0 + rb * 16 + Mma<F>::row(lane, v), C0 + cb * 16 + (lane & 15))] = acc[rb][cb][v];
+}
+
+template <typename F>
+__device__ __forceinline__ void acc_negate(typename Mma<F>::acc_t (&acc)[2][2]) {
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = -acc[a][b];
+}
+
+// MFMA operands of 16 consecutive k (four 16x16x4 steps) of one quadrant
+template <typename F>
+struct Frag {
+  F a0[4], a1[4], b0[4], b1[4];
+};
+
+// group g (0..3) of the 64-deep product Lt * Ut
+template <typename F>
+__device__ __forceinline__ void frag_load(Frag<F>& f, const F* __restrict__ Lt, const F* __restrict__ Ut, int g) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int R0 = (wave >> 1) * 32, C0 = (wave & 1) * 32;
+  const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int kc = (4 * g + q) * 4 + lk;
+    f.a0[q] = Lt[tile_off<F>(R0 + lr, kc)];
+    f.a1[q] = Lt[tile_off<F>(R0 + 16 + lr, kc)];
+    f.b0[q] = Ut[tile_off<F>(kc, C0 + lr)];
+    f.b1[q] = Ut[tile_off<F>(kc, C0 + 16 + lr)];
+  }
+}
+
+template <typename F>
+__device__ __forceinline__ void frag_mma(const Frag<F>& f, typename Mma<F>::acc_t (&acc)[2][2]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    acc[0][0] = Mma<F>::op(f.a0[q], f.b0[q], acc[0][0]);
+    acc[0][1] = Mma<F>::op(f.a0[q], f.b1[q], acc[0][1]);
+    acc[1][0] = Mma<F>::op(f.a1[q], f.b0[q], acc[1][0]);
+    acc[1][1] = Mma<F>::op(f.a1[q], f.b1[q], acc[1][1]);
+  }
+}
+
+// acc += sum_{s<depth} Ls(s) * Us(s), where Ls(s) = fac + lt0 + s*lstep tiles and
+// Us(s) = fac + ut0 + s*ustep tiles; operand loads run one group ahead.
+template <typename F>
+__device__ __forceinline__ void acc_add_products(typename Mma<F>::acc_t (&acc)[2][2], const F* __restrict__ fac,
+                                                 size_t lt0, size_t lstep, size_t ut0, size_t ustep, int depth) {
+  if (depth <= 0) return;
+  const int ng = 4 * depth;
+  Frag<F> f0, f1;
+  frag_load<F>(f0, fac + lt0 * TILE_ELEMS, fac + ut0 * TILE_ELEMS, 0);
+  for (int g = 0; g < ng; g += 2) {
+    {
+      const int h = g + 1, s = h >> 2;  // ng is even: h < ng
+      frag_load<F>(f1, fac + (lt0 + s * lstep) * TILE_ELEMS, fac + (ut0 + s * ustep) * TILE_ELEMS, h & 3);
+    }
+    frag_mma<F>(f0, acc);
+    if (g + 2 < ng) {
+      const int h = g + 2, s = h >> 2;
+      frag_load<F>(f0, fac + (lt0 + s * lstep) * TILE_ELEMS, fac + (ut0 + s * ustep) * TILE_ELEMS, h & 3);
+    }
+    frag_mma<F>(f1, acc);
+  }
+}
+
+// acc = T - sum_{s<depth} Ls(s) * Us(s)
+template <typename F>
+__device__ __forceinline__ void acc_updated_tile(typename Mma<F>::acc_t (&acc)[2][2], const F* __restrict__ fac,
+                                                 size_t tt, size_t lt0, size_t lstep, size_t ut0, size_t ustep,
+                                                 int depth) {
+  acc_load<F>(fac + tt * TILE_ELEMS, acc);
+  acc_negate<F>(acc);
+  acc_add_products<F>(acc, fac, lt0, lstep, ut0, ustep, depth);
+  acc_negate<F>(acc);
+}
+
+// ---------------------------------------------------------------------------
+// diagonal tile: pending in-block updates, LU, then inv(L_kk) (unit lower)
+// and inv(U_kk).
 // LU: work-item c < 64 keeps column c in registers; at step c it scales its
 // column below the diagonal and publishes the multipliers through LDS, and
 // every column to its right applies the rank-1 update.  Inverses: one
@@ -116,7 +262,7 @@ hipError_t launch_extract(const FacDesc* d, int nd, int maxn, hipStream_t s) {
 // indices.
 // ---------------------------------------------------------------------------
 template <typename F>
-__global__ __launch_bounds__(256) void k_lu_diag(const FacDesc* __restrict__ d, int k, int* err) {
+__global__ __launch_bounds__(256) void k_lu_diag(const FacDesc* __restrict__ d, int k0, int k, int* err) {
   const FacDesc D = d[blockIdx.x];
   if (k >= D.N) return;
   __shared__ F a[64][LDP];
@@ -126,7 +272,13 @@ __global__ __launch_bounds__(256) void k_lu_diag(const FacDesc* __restrict__ d, 
   F* fac = (F*)D.fac;
   F* tkk = fac + (size_t(k) * N + k) * TILE_ELEMS;
   F* linv = fac + (N * N + k) * TILE_ELEMS;
-  tile_to_lds<F>(tkk, a);
+  if (k > k0) {  // pending updates of this block column
+    typename Mma<F>::acc_t acc[2][2];
+    acc_updated_tile<F>(acc, fac, size_t(k) * N + k, size_t(k) * N + k0, 1, size_t(k0) * N + k, N, k - k0);
+    acc_to_lds<F>(acc, a);
+  } else {
+    tile_to_lds<F>(tkk, a);
+  }
   __syncthreads();
   F col[64];
   if (tid < 64) {
@@ -194,135 +346,74 @@ __global__ __launch_bounds__(256) void k_lu_diag(const FacDesc* __restrict__ d, 
   lds_to_tile<F>(a, linv);
 }
 
-// ---------------------------------------------------------------------------
-// C (=|-=) A * B on 64x64 tiles with MFMA 16x16x4; wave w owns the 32x32
-// quadrant (w/2, w%2) of C.  A, B staged in LDS.
-// ---------------------------------------------------------------------------
+// panel of tile column k: blockIdx.x < nr -> L_{k+1+x, k}, else U_{k, k+1+x'};
+// pending in-block updates fused in front of the product with the inverse.
 template <typename F>
-__device__ __forceinline__ void tile_mma(F (*As)[LDP], F (*Bs)[LDP], typename Mma<F>::acc_t (&acc)[2][2]) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int R0 = (wave >> 1) * 32, C0 = (wave & 1) * 32;
-  const int lr = lane & 15, lk = lane >> 4;
-#pragma unroll 4
-  for (int kk = 0; kk < 16; ++kk) {
-    const int kc = kk * 4 + lk;
-    F a0 = As[R0 + lr][kc], a1 = As[R0 + 16 + lr][kc];
-    F b0 = Bs[kc][C0 + lr], b1 = Bs[kc][C0 + 16 + lr];
-    acc[0][0] = Mma<F>::op(a0, b0, acc[0][0]);
-    acc[0][1] = Mma<F>::op(a0, b1, acc[0][1]);
-    acc[1][0] = Mma<F>::op(a1, b0, acc[1][0]);
-    acc[1][1] = Mma<F>::op(a1, b1, acc[1][1]);
-  }
-}
-
-template <typename F>
-__device__ __forceinline__ void acc_to_lds(typename Mma<F>::acc_t (&acc)[2][2], F (*Cs)[LDP]) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int R0 = (wave >> 1) * 32, C0 = (wave & 1) * 32;
-#pragma unroll
-  for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-    for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) Cs[R0 + rb * 16 + Mma<F>::row(lane, v)][C0 + cb * 16 + (lane & 15)] = acc[rb][cb][v];
-}
-
-template <typename F>
-__device__ __forceinline__ void lds_to_acc(F (*Cs)[LDP], typename Mma<F>::acc_t (&acc)[2][2]) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int R0 = (wave >> 1) * 32, C0 = (wave & 1) * 32;
-#pragma unroll
-  for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-    for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) acc[rb][cb][v] = Cs[R0 + rb * 16 + Mma<F>::row(lane, v)][C0 + cb * 16 + (lane & 15)];
-}
-
-// panel: blockIdx.x < nr -> L_{k+1+x, k} = A * inv(U_kk);  else U_{k, k+1+x'} = inv(L_kk) * A
-template <typename F>
-__global__ __launch_bounds__(256) void k_lu_panel(const FacDesc* __restrict__ d, int k) {
+__global__ __launch_bounds__(256) void k_lu_panel(const FacDesc* __restrict__ d, int k0, int k) {
   const FacDesc D = d[blockIdx.y];
   const int nr = D.N - k - 1;
   if (nr <= 0 || int(blockIdx.x) >= 2 * nr) return;
   __shared__ F As[64][LDP], Bs[64][LDP];
   const size_t N = D.N;
   F* fac = (F*)D.fac;
-  F* target;
-  if (int(blockIdx.x) < nr) {
-    const int i = k + 1 + blockIdx.x;
-    target = fac + (size_t(i) * N + k) * TILE_ELEMS;
-    tile_to_lds<F>(target, As);
+  typename Mma<F>::acc_t acc[2][2];
+  size_t target;
+  if (int(blockIdx.x) < nr) {  // L_ik = (A_ik - sum_s L_is U_sk) inv(U_kk)
+    const size_t i = k + 1 + blockIdx.x;
+    target = i * N + k;
+    acc_updated_tile<F>(acc, fac, target, i * N + k0, 1, size_t(k0) * N + k, N, k - k0);
+    acc_to_lds<F>(acc, As);
     tile_to_lds<F>(fac + (size_t(k) * N + k) * TILE_ELEMS, Bs);
-  } else {
-    const int j = k + 1 + (blockIdx.x - nr);
-    target = fac + (size_t(k) * N + j) * TILE_ELEMS;
+  } else {  // U_kj = inv(L_kk) (A_kj - sum_s L_ks U_sj)
+    const size_t j = k + 1 + (blockIdx.x - nr);
+    target = size_t(k) * N + j;
+    acc_updated_tile<F>(acc, fac, target, size_t(k) * N + k0, 1, size_t(k0) * N + j, N, k - k0);
+    acc_to_lds<F>(acc, Bs);
     tile_to_lds<F>(fac + (N * N + k) * TILE_ELEMS, As);
-    tile_to_lds<F>(target, Bs);
   }
   __syncthreads();
-  typename Mma<F>::acc_t acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = typename Mma<F>::acc_t{0, 0, 0, 0};
   tile_mma<F>(As, Bs, acc);
-  __syncthreads();
-  acc_to_lds<F>(acc, As);
-  __syncthreads();
-  lds_to_tile<F>(As, target);
+  acc_store<F>(acc, fac + target * TILE_ELEMS);
 }
 
-// update: A_ij -= L_ik U_kj for all i, j in k+1..N-1
+// trailing update past block column k0 .. k0+depth-1:
+// A_ij -= sum_{s<depth} L_{i,k0+s} U_{k0+s,j} for all i, j >= k0+depth
 template <typename F>
-__global__ __launch_bounds__(256) void k_lu_update(const FacDesc* __restrict__ d, int k) {
+__global__ __launch_bounds__(256) void k_lu_trail(const FacDesc* __restrict__ d, int k0, int depth) {
   const FacDesc D = d[blockIdx.y];
-  const int nr = D.N - k - 1;
+  const int nr = D.N - k0 - depth;
   if (nr <= 0 || int(blockIdx.x) >= nr * nr) return;
-  __shared__ F As[64][LDP], Bs[64][LDP];
-  const int i = k + 1 + blockIdx.x / nr, j = k + 1 + blockIdx.x % nr;
   const size_t N = D.N;
+  const size_t i = k0 + depth + blockIdx.x / nr, j = k0 + depth + blockIdx.x % nr;
   F* fac = (F*)D.fac;
-  F* target = fac + (size_t(i) * N + j) * TILE_ELEMS;
   typename Mma<F>::acc_t acc[2][2];
-  tile_to_lds<F>(target, As);
-  __syncthreads();
-  lds_to_acc<F>(As, acc);
-  __syncthreads();
-  tile_to_lds<F>(fac + (size_t(i) * N + k) * TILE_ELEMS, As);
-  tile_to_lds<F>(fac + (size_t(k) * N + j) * TILE_ELEMS, Bs);
-  __syncthreads();
-  // C - A B: negate A on the fly
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = -acc[a][b];
-  tile_mma<F>(As, Bs, acc);
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = -acc[a][b];
-  __syncthreads();
-  acc_to_lds<F>(acc, As);
-  __syncthreads();
-  lds_to_tile<F>(As, target);
+  acc_updated_tile<F>(acc, fac, i * N + j, i * N + k0, 1, size_t(k0) * N + j, N, depth);
+  acc_store<F>(acc, fac + (i * N + j) * TILE_ELEMS);
 }
 
 template <typename F>
-hipError_t launch_lu_step(const FacDesc* d, int nd, int k, int maxN, int* err, hipStream_t s) {
-  if (nd <= 0 || k >= maxN) return hipSuccess;
-  hipLaunchKernelGGL((k_lu_diag<F>), dim3(nd), dim3(256), 0, s, d, k, err);
-  const int nr = maxN - k - 1;
-  if (nr > 0) {
-    hipLaunchKernelGGL((k_lu_panel<F>), dim3(2 * nr, nd), dim3(256), 0, s, d, k);
-    hipLaunchKernelGGL((k_lu_update<F>), dim3(nr * nr, nd), dim3(256), 0, s, d, k);
+hipError_t launch_lu(const FacDesc* d, int nd, int maxN, int* err, hipStream_t s) {
+  if (nd <= 0) return hipSuccess;
+  for (int k0 = 0; k0 < maxN; k0 += LU_DEPTH) {
+    const int depth = maxN - k0 < LU_DEPTH ? maxN - k0 : LU_DEPTH;
+    for (int k = k0; k < k0 + depth; ++k) {
+      hipLaunchKernelGGL((k_lu_diag<F>), dim3(nd), dim3(256), 0, s, d, k0, k, err);
+      const int nr = maxN - k - 1;
+      if (nr > 0) hipLaunchKernelGGL((k_lu_panel<F>), dim3(2 * nr, nd), dim3(256), 0, s, d, k0, k);
+    }
+    const int nt = maxN - k0 - depth;
+    if (nt > 0) hipLaunchKernelGGL((k_lu_trail<F>), dim3(nt * nt, nd), dim3(256), 0, s, d, k0, depth);
   }
   return hipGetLastError();
 }
 
 template hipError_t launch_extract<double>(const FacDesc*, int, int, hipStream_t);
 template hipError_t launch_extract<float>(const FacDesc*, int, int, hipStream_t);
-template hipError_t launch_lu_step<double>(const FacDesc*, int, int, int, int*, hipStream_t);
-template hipError_t launch_lu_step<float>(const FacDesc*, int, int, int, int*, hipStream_t);
+template hipError_t launch_lu<double>(const FacDesc*, int, int, int*, hipStream_t);
+template hipError_t launch_lu<float>(const FacDesc*, int, int, int*, hipStream_t);
 
 }  // namespace nnms

@@ -185,7 +185,7 @@ class Mesh:
         return cls(m.xyz, m.tets, m.dirichlet)
 
     def __del__(self):
-        if getattr(self, "handle", None):
+        if getattr(self, "handle", None) and _lib is not None:  # _lib is None at interpreter exit
             _lib.nnms_mesh_destroy(self.handle)
             self.handle = None
 
@@ -293,7 +293,7 @@ class Hierarchy:
             self.handle = None
 
     def __del__(self):
-        if getattr(self, "handle", None):
+        if getattr(self, "handle", None) and _lib is not None:
             _lib.nnms_hierarchy_destroy(self.handle)
             self.handle = None
 
@@ -410,7 +410,8 @@ class System:
             self.handle = None
 
     def __del__(self):
-        self.destroy()
+        if _lib is not None:
+            self.destroy()
 
 
 def solve_batch(systems: Sequence[System], bs: Sequence[np.ndarray], restart: int = 30, rtol: float = 1e-8,
@@ -461,4 +462,5 @@ class Batch:
             self.handle = None
 
     def __del__(self):
-        self.destroy()
+        if _lib is not None:
+            self.destroy()

@@ -186,3 +186,55 @@ def test_batch_equals_alone(c1):
     xs, infos = nnms.solve_batch([g1.s, s2], [o1.b, o1.b])
     assert np.array_equal(xs[0], x1) and np.array_equal(xs[1], x2)
     assert infos[0].iterations == i1.iterations and infos[1].iterations == i2.iterations
+
+
+def _rebuild_lu(lu, il):
+    """A_p = L U from the stored tiles: L_ij (i > j) and U_ij (i < j) as
+    stored, L_ii = inv(stored inv(L_ii)), U_ii = inv(stored inv(U_ii))."""
+    N = il.shape[0]
+    Lm = np.zeros_like(lu)
+    Um = np.zeros_like(lu)
+    for i in range(N):
+        ri = slice(64 * i, 64 * i + 64)
+        for j in range(N):
+            rj = slice(64 * j, 64 * j + 64)
+            if i > j:
+                Lm[ri, rj] = lu[ri, rj]
+            elif i < j:
+                Um[ri, rj] = lu[ri, rj]
+        Lm[ri, ri] = np.linalg.inv(il[i])
+        Um[ri, ri] = np.linalg.inv(lu[ri, ri])
+    return Lm @ Um
+
+
+@pytest.mark.parametrize("case,precision", [("c1", "fp64"), ("tiny3", "fp64"), ("tiny3", "mixed")])
+def test_factors_reproduce_subdomain_matrices(case, precision, request):
+    """Blocked LU (several block columns of 4 tiles and a ragged last one on
+    c1's 600-row subdomains): L U equals the oracle's A[S_p, S_p], the
+    padding block is the identity, and refactoring in place gives the same
+    bits."""
+    g, o = request.getfixturevalue(case)
+    if precision == "mixed":
+        g = Built(g.pb, precision="mixed")
+    L = len(g.pb.meshes)
+    for l in range(L):
+        owner, sets = g.h.partition(l)
+        A = o.A[l].tocsr()
+        # reconstruction inverts the stored inverse diagonal tiles: rounding of the
+        # factor times their condition number (~1e3)
+        tol = 1e-11 if (precision == "fp64" or l == L - 1) else 1e-4
+        before = [g.s.factor(l, p) for p in range(len(sets))]
+        for p, S in enumerate(sets):
+            lu, il = before[p]
+            M = _rebuild_lu(lu, il)
+            n = len(S)
+            Ap = A[S][:, S].toarray()
+            err = np.abs(M[:n, :n] - Ap).max() / np.abs(Ap).max()
+            assert err <= tol, (l, p, err)
+            pad = M[n:, n:]
+            assert np.allclose(pad, np.eye(pad.shape[0]), rtol=0, atol=tol), (l, p)
+            assert np.abs(M[:n, n:]).max(initial=0) <= tol and np.abs(M[n:, :n]).max(initial=0) <= tol
+        g.s.time_kernel(6, l, reps=1)
+        for p in range(len(sets)):
+            lu, il = g.s.factor(l, p)
+            assert np.array_equal(lu, before[p][0]) and np.array_equal(il, before[p][1]), (l, p)
