@@ -6,6 +6,21 @@
 
 namespace nnms {
 
+// Pointers taken from descriptors are generic; accesses through them compile
+// to flat instructions with 64-bit per-lane addresses, and flat loads also
+// count as LDS operations, so every LDS wait would drain outstanding
+// device-memory loads.  Kernels access device memory through
+// global-address-space pointers instead.
+#define GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ GLOBAL T* gptr(T* p) {
+  return (GLOBAL T*)p;
+}
+template <typename T>
+__device__ __forceinline__ const GLOBAL T* gptr(const T* p) {
+  return (const GLOBAL T*)p;
+}
+
 // Index of the descriptor whose first block is the largest one <= b.
 template <typename D>
 __device__ __forceinline__ int find_desc(const D* d, int nd, int b) {

@@ -48,10 +48,10 @@ struct Mma<float> {
 };
 
 template <typename F>
-__device__ __forceinline__ void tile_to_lds(const F* g, F (*s)[LDP]) {
+__device__ __forceinline__ void tile_to_lds(const GLOBAL F* g, F (*s)[LDP]) {
   using C = typename Chunk<F>::type;
   constexpr int W = Chunk<F>::W;
-  const C* gc = (const C*)g;
+  const GLOBAL C* gc = (const GLOBAL C*)g;
   for (int q = threadIdx.x; q < TILE_ELEMS / W; q += 256) {
     const int cg = q / 64, r = q % 64;
     const C v = gc[q];
@@ -62,10 +62,10 @@ __device__ __forceinline__ void tile_to_lds(const F* g, F (*s)[LDP]) {
 }
 
 template <typename F>
-__device__ __forceinline__ void lds_to_tile(F (*s)[LDP], F* g) {
+__device__ __forceinline__ void lds_to_tile(F (*s)[LDP], GLOBAL F* g) {
   using C = typename Chunk<F>::type;
   constexpr int W = Chunk<F>::W;
-  C* gc = (C*)g;
+  GLOBAL C* gc = (GLOBAL C*)g;
   for (int q = threadIdx.x; q < TILE_ELEMS / W; q += 256) {
     const int cg = q / 64, r = q % 64;
     C v;
@@ -150,7 +150,7 @@ __device__ __forceinline__ void acc_to_lds(typename Mma<F>::acc_t (&acc)[2][2], 
 // output; the accumulator holds the quadrant in MFMA output layout.
 // ---------------------------------------------------------------------------
 template <typename F>
-__device__ __forceinline__ void acc_load(const F* __restrict__ T, typename Mma<F>::acc_t (&acc)[2][2]) {
+__device__ __forceinline__ void acc_load(const GLOBAL F* __restrict__ T, typename Mma<F>::acc_t (&acc)[2][2]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int R0 = (wave >> 1) * 32, C0 = (wave & 1) * 32;
 #pragma unroll
@@ -163,7 +163,7 @@ __device__ __forceinline__ void acc_load(const F* __restrict__ T, typename Mma<F
 }
 
 template <typename F>
-__device__ __forceinline__ void acc_store(typename Mma<F>::acc_t (&acc)[2][2], F* __restrict__ T) {
+__device__ __forceinline__ void acc_store(typename Mma<F>::acc_t (&acc)[2][2], GLOBAL F* __restrict__ T) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int R0 = (wave >> 1) * 32, C0 = (wave & 1) * 32;
 #pragma unroll
@@ -191,7 +191,7 @@ struct Frag {
 
 // group g (0..3) of the 64-deep product Lt * Ut
 template <typename F>
-__device__ __forceinline__ void frag_load(Frag<F>& f, const F* __restrict__ Lt, const F* __restrict__ Ut, int g) {
+__device__ __forceinline__ void frag_load(Frag<F>& f, const GLOBAL F* __restrict__ Lt, const GLOBAL F* __restrict__ Ut, int g) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int R0 = (wave >> 1) * 32, C0 = (wave & 1) * 32;
   const int lr = lane & 15, lk = lane >> 4;
@@ -219,7 +219,7 @@ __device__ __forceinline__ void frag_mma(const Frag<F>& f, typename Mma<F>::acc_
 // acc += sum_{s<depth} Ls(s) * Us(s), where Ls(s) = fac + lt0 + s*lstep tiles and
 // Us(s) = fac + ut0 + s*ustep tiles; operand loads run one group ahead.
 template <typename F>
-__device__ __forceinline__ void acc_add_products(typename Mma<F>::acc_t (&acc)[2][2], const F* __restrict__ fac,
+__device__ __forceinline__ void acc_add_products(typename Mma<F>::acc_t (&acc)[2][2], const GLOBAL F* __restrict__ fac,
                                                  size_t lt0, size_t lstep, size_t ut0, size_t ustep, int depth) {
   if (depth <= 0) return;
   const int ng = 4 * depth;
@@ -241,7 +241,7 @@ __device__ __forceinline__ void acc_add_products(typename Mma<F>::acc_t (&acc)[2
 
 // acc = T - sum_{s<depth} Ls(s) * Us(s)
 template <typename F>
-__device__ __forceinline__ void acc_updated_tile(typename Mma<F>::acc_t (&acc)[2][2], const F* __restrict__ fac,
+__device__ __forceinline__ void acc_updated_tile(typename Mma<F>::acc_t (&acc)[2][2], const GLOBAL F* __restrict__ fac,
                                                  size_t tt, size_t lt0, size_t lstep, size_t ut0, size_t ustep,
                                                  int depth) {
   acc_load<F>(fac + tt * TILE_ELEMS, acc);
@@ -269,9 +269,9 @@ __global__ __launch_bounds__(256) void k_lu_diag(const FacDesc* __restrict__ d, 
   __shared__ F lbuf[64];
   const int tid = threadIdx.x;
   const size_t N = D.N;
-  F* fac = (F*)D.fac;
-  F* tkk = fac + (size_t(k) * N + k) * TILE_ELEMS;
-  F* linv = fac + (N * N + k) * TILE_ELEMS;
+  GLOBAL F* fac = gptr((F*)D.fac);
+  GLOBAL F* tkk = fac + (size_t(k) * N + k) * TILE_ELEMS;
+  GLOBAL F* linv = fac + (N * N + k) * TILE_ELEMS;
   if (k > k0) {  // pending updates of this block column
     typename Mma<F>::acc_t acc[2][2];
     acc_updated_tile<F>(acc, fac, size_t(k) * N + k, size_t(k) * N + k0, 1, size_t(k0) * N + k, N, k - k0);
@@ -355,7 +355,7 @@ __global__ __launch_bounds__(256) void k_lu_panel(const FacDesc* __restrict__ d,
   if (nr <= 0 || int(blockIdx.x) >= 2 * nr) return;
   __shared__ F As[64][LDP], Bs[64][LDP];
   const size_t N = D.N;
-  F* fac = (F*)D.fac;
+  GLOBAL F* fac = gptr((F*)D.fac);
   typename Mma<F>::acc_t acc[2][2];
   size_t target;
   if (int(blockIdx.x) < nr) {  // L_ik = (A_ik - sum_s L_is U_sk) inv(U_kk)
@@ -380,19 +380,108 @@ __global__ __launch_bounds__(256) void k_lu_panel(const FacDesc* __restrict__ d,
   acc_store<F>(acc, fac + target * TILE_ELEMS);
 }
 
+// ---------------------------------------------------------------------------
 // trailing update past block column k0 .. k0+depth-1:
-// A_ij -= sum_{s<depth} L_{i,k0+s} U_{k0+s,j} for all i, j >= k0+depth
+// A_ij -= sum_{s<depth} L_{i,k0+s} U_{k0+s,j} for all i, j >= k0+depth.
+// A work-group covers 2x2 tiles; each wave owns one whole 64x64 tile (4x4
+// MFMA blocks, 16 products per 8 operand loads), the wave pairs that share
+// a tile row or column fetch the same L or U operands through L1.
+// ---------------------------------------------------------------------------
 template <typename F>
-__global__ __launch_bounds__(256) void k_lu_trail(const FacDesc* __restrict__ d, int k0, int depth) {
+struct Frag64 {
+  F a[2][4], b[2][4];  // two k-steps of four 16-row (A) and 16-column (B) blocks
+};
+
+// k-steps 2h, 2h+1 (h = 0..7) of the 64-deep product Lt * Ut, whole-tile
+// operands.  With W values per 16-byte chunk, A element (16b + lr, kc) of a
+// tile sits at abase + 512h + 256q + 16Wb and B element (kc, 16b + lr) at
+// bbase + 1024b + 4W(2h + q) (kc = 8h + 4q + lk), so every load is a lane
+// offset plus a constant.
+template <typename F>
+__device__ __forceinline__ void frag64_load(Frag64<F>& f, const GLOBAL F* __restrict__ Lt,
+                                           const GLOBAL F* __restrict__ Ut, int h, int abase, int bbase) {
+  constexpr int W = 16 / sizeof(F);
+  const GLOBAL F* la = Lt + abase + 512 * h;
+  const GLOBAL F* ub = Ut + bbase + 8 * W * h;
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      f.a[q][b] = la[256 * q + 16 * W * b];
+      f.b[q][b] = ub[1024 * b + 4 * W * q];
+    }
+}
+
+template <typename F>
+__device__ __forceinline__ void frag64_mma(const Frag64<F>& f, typename Mma<F>::acc_t (&acc)[4][4]) {
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = Mma<F>::op(f.a[q][rb], f.b[q][cb], acc[rb][cb]);
+}
+
+template <typename F>
+__global__ __launch_bounds__(256, 2) void k_lu_trail(const FacDesc* __restrict__ d, int k0, int depth) {
+  constexpr int W = 16 / sizeof(F);
   const FacDesc D = d[blockIdx.y];
   const int nr = D.N - k0 - depth;
-  if (nr <= 0 || int(blockIdx.x) >= nr * nr) return;
+  if (nr <= 0) return;
+  const int ns = (nr + 1) >> 1;  // 2x2 super-tiles per side
+  if (int(blockIdx.x) >= ns * ns) return;
+  // wave-uniform: keeps the tile base addresses in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int ti = 2 * (blockIdx.x / ns) + (wave >> 1), tj = 2 * (blockIdx.x % ns) + (wave & 1);
+  if (ti >= nr || tj >= nr) return;  // no barriers below: a wave may leave alone
   const size_t N = D.N;
-  const size_t i = k0 + depth + blockIdx.x / nr, j = k0 + depth + blockIdx.x % nr;
-  F* fac = (F*)D.fac;
-  typename Mma<F>::acc_t acc[2][2];
-  acc_updated_tile<F>(acc, fac, i * N + j, i * N + k0, 1, size_t(k0) * N + j, N, depth);
-  acc_store<F>(acc, fac + (i * N + j) * TILE_ELEMS);
+  const size_t i = k0 + depth + ti, j = k0 + depth + tj;
+  GLOBAL F* fac = gptr((F*)D.fac);
+  GLOBAL F* C = fac + (i * N + j) * TILE_ELEMS;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int abase = ((lk / W) * 64 + lr) * W + lk % W;
+  const int bbase = (lr / W) * 64 * W + lk * W + lr % W;
+  typename Mma<F>::acc_t acc[4][4];
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = typename Mma<F>::acc_t{0, 0, 0, 0};
+  const GLOBAL F* L0 = fac + (i * N + k0) * TILE_ELEMS;          // L_{i,k0+s} = L0 + s tiles
+  const GLOBAL F* U0 = fac + (size_t(k0) * N + j) * TILE_ELEMS;  // U_{k0+s,j} = U0 + s*N tiles
+  const int ng = 8 * depth;  // pairs of k-steps
+  Frag64<F> f0, f1;
+  frag64_load<F>(f0, L0, U0, 0, abase, bbase);
+  // branch-free pipeline: the loads of the next pair of k-steps are issued
+  // before the products of the current one (the last pass reloads group
+  // ng-1, which is in bounds and unused)
+  for (int g = 0; g < ng; g += 2) {
+    {
+      const int h = g + 1, s = h >> 3;
+      frag64_load<F>(f1, L0 + size_t(s) * TILE_ELEMS, U0 + size_t(s) * N * TILE_ELEMS, h & 7, abase, bbase);
+    }
+    __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of the products
+    frag64_mma<F>(f0, acc);
+    __builtin_amdgcn_sched_barrier(0);
+    {
+      const int h = min(g + 2, ng - 1), s = h >> 3;
+      frag64_load<F>(f0, L0 + size_t(s) * TILE_ELEMS, U0 + size_t(s) * N * TILE_ELEMS, h & 7, abase, bbase);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    frag64_mma<F>(f1, acc);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  // C -= acc, one 16-row block at a time
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb) {
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        GLOBAL F* e = C + tile_off<F>(16 * rb + Mma<F>::row(lane, v), 16 * cb + lr);
+        *e = *e - acc[rb][cb][v];
+      }
+    __builtin_amdgcn_sched_barrier(0);
+  }
 }
 
 template <typename F>
@@ -405,8 +494,8 @@ hipError_t launch_lu(const FacDesc* d, int nd, int maxN, int* err, hipStream_t s
       const int nr = maxN - k - 1;
       if (nr > 0) hipLaunchKernelGGL((k_lu_panel<F>), dim3(2 * nr, nd), dim3(256), 0, s, d, k0, k);
     }
-    const int nt = maxN - k0 - depth;
-    if (nt > 0) hipLaunchKernelGGL((k_lu_trail<F>), dim3(nt * nt, nd), dim3(256), 0, s, d, k0, depth);
+    const int nt = maxN - k0 - depth, ns = (nt + 1) / 2;
+    if (nt > 0) hipLaunchKernelGGL((k_lu_trail<F>), dim3(ns * ns, nd), dim3(256), 0, s, d, k0, depth);
   }
   return hipGetLastError();
 }

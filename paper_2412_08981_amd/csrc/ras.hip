@@ -41,19 +41,6 @@ constexpr int SPIN_LIMIT = 1 << 22;
 // they never share a workspace.
 __device__ int32_t g_ras_epoch = 0;
 
-// Pointers taken from descriptors are generic; accesses through them would
-// compile to flat loads, which also count as LDS operations, so every LDS
-// wait would drain the tile prefetches.  All device-memory accesses here go
-// through global-address-space pointers instead.
-#define GLOBAL __attribute__((address_space(1)))
-template <typename T>
-__device__ __forceinline__ GLOBAL T* gptr(T* p) {
-  return (GLOBAL T*)p;
-}
-template <typename T>
-__device__ __forceinline__ const GLOBAL T* gptr(const T* p) {
-  return (const GLOBAL T*)p;
-}
 
 __device__ __forceinline__ uint64_t ld64(const uint64_t* p) {
   return __hip_atomic_load(gptr(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
