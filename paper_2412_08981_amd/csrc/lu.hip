@@ -252,22 +252,62 @@ __device__ __forceinline__ void acc_updated_tile(typename Mma<F>::acc_t (&acc)[2
 
 // ---------------------------------------------------------------------------
 // diagonal tile: pending in-block updates, LU, then inv(L_kk) (unit lower)
-// and inv(U_kk).
-// LU: work-item c < 64 keeps column c in registers; at step c it scales its
-// column below the diagonal and publishes the multipliers through LDS, and
-// every column to its right applies the rank-1 update.  Inverses: one
-// work-item per column of inv(L) (items 0..63) and of inv(U) (items
-// 64..127), each column in registers, the factor rows read from LDS as
-// broadcasts; loops are unrolled so that the register columns have fixed
-// indices.
+// and inv(U_kk), all in LDS.  Everything here is on the critical path of the
+// factorisation (one work-group per subdomain), so the kernel is built for
+// latency and small code:
+//   LU in four 16-column steps: one wave factors the 16-wide panel (lane r
+//   keeps row r's 16 entries in registers; pivot-row values come by scalar
+//   broadcast), one wave solves U12 = inv(L11) A12 (a work-item per column),
+//   and the four waves update the trailing block with MFMA (K = 16);
+//   inverses: the 16x16 diagonal blocks by column-parallel substitution,
+//   then the off-diagonal blocks one block diagonal at a time,
+//   X_ij = -X_ii sum_m L_im X_mj (and likewise for U), on MFMA.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ float bcast(float x, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+__device__ __forceinline__ double bcast(double x, int l) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane(int(v), l), hi = __builtin_amdgcn_readlane(int(v >> 32), l);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+
+// acc -= (or +=) A(r0.., k0..k0+15) * B(k0.., c0..), 16x16 output, K = 16, operands in LDS
+template <typename F, bool SUB>
+__device__ __forceinline__ void mma16(F (*A)[LDP], int ar, int ak, F (*B)[LDP], int bk, int bc,
+                                      typename Mma<F>::acc_t& acc) {
+  const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const F av = A[ar + lr][ak + 4 * kk + lk];
+    acc = Mma<F>::op(SUB ? -av : av, B[bk + 4 * kk + lk][bc + lr], acc);
+  }
+}
+
+template <typename F>
+__device__ __forceinline__ void acc16_load(F (*C)[LDP], int r0, int c0, typename Mma<F>::acc_t& acc) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) acc[v] = C[r0 + Mma<F>::row(lane, v)][c0 + (lane & 15)];
+}
+
+template <typename F>
+__device__ __forceinline__ void acc16_store(typename Mma<F>::acc_t acc, F (*C)[LDP], int r0, int c0, F scale) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) C[r0 + Mma<F>::row(lane, v)][c0 + (lane & 15)] = scale * acc[v];
+}
+
 template <typename F>
 __global__ __launch_bounds__(256) void k_lu_diag(const FacDesc* __restrict__ d, int k0, int k, int* err) {
   const FacDesc D = d[blockIdx.x];
   if (k >= D.N) return;
-  __shared__ F a[64][LDP];
-  __shared__ F lbuf[64];
-  const int tid = threadIdx.x;
+  __shared__ F a[64][LDP];  // A, then L (strictly lower) and U
+  __shared__ F X[64][LDP];  // inv(L)
+  __shared__ F Y[64][LDP];  // inv(U)
+  __shared__ F T[4][16][LDP];  // per-wave 16x16 product scratch
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const size_t N = D.N;
   GLOBAL F* fac = gptr((F*)D.fac);
   GLOBAL F* tkk = fac + (size_t(k) * N + k) * TILE_ELEMS;
@@ -279,71 +319,115 @@ __global__ __launch_bounds__(256) void k_lu_diag(const FacDesc* __restrict__ d, 
   } else {
     tile_to_lds<F>(tkk, a);
   }
+  for (int q = tid; q < 64 * 64; q += 256) X[q >> 6][q & 63] = F(0), Y[q >> 6][q & 63] = F(0);
   __syncthreads();
-  F col[64];
-  if (tid < 64) {
+
+  for (int p = 0; p < 4; ++p) {
+    const int c0 = 16 * p;
+    if (wave == 0) {  // panel rows c0..63, columns c0..c0+15
+      F pr[16];
 #pragma unroll
-    for (int r = 0; r < 64; ++r) col[r] = a[r][tid];
-  }
+      for (int q = 0; q < 16; ++q) pr[q] = a[lane][c0 + q];
 #pragma unroll
-  for (int c = 0; c < 64; ++c) {
-    if (tid == c) {
-      const F piv = col[c];
-      if (!(piv > F(0) && piv < F(INFINITY))) atomicOr(err, 1);
-      const F rp = F(1) / piv;
+      for (int jj = 0; jj < 16; ++jj) {
+        const int j = c0 + jj;
+        const F piv = bcast(pr[jj], j);
+        if (lane == 0 && !(piv > F(0) && piv < F(INFINITY))) atomicOr(err, 1);
+        const F rp = F(1) / piv;
+        const bool below = lane > j;
+        if (below) pr[jj] *= rp;
 #pragma unroll
-      for (int r = c + 1; r < 64; ++r) {
-        col[r] *= rp;
-        lbuf[r] = col[r];
+        for (int q = jj + 1; q < 16; ++q) {
+          const F u = bcast(pr[q], j);
+          if (below) pr[q] -= pr[jj] * u;
+        }
+      }
+      if (lane >= c0) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) a[lane][c0 + q] = pr[q];
       }
     }
     __syncthreads();
-    if (tid > c && tid < 64) {
-      const F u = col[c];
+    if (p == 3) break;
+    const int nc = 48 - c0;  // columns right of the panel
+    if (wave == 1 && lane < nc) {  // U12 = inv(L11) A12, one column per work-item
+      const int q = c0 + 16 + lane;
+      F x[16];
 #pragma unroll
-      for (int r = c + 1; r < 64; ++r) col[r] -= lbuf[r] * u;
+      for (int r = 0; r < 16; ++r) {
+        F s = a[c0 + r][q];
+#pragma unroll
+        for (int m = 0; m < r; ++m) s -= a[c0 + r][c0 + m] * x[m];
+        x[r] = s;
+      }
+#pragma unroll
+      for (int r = 1; r < 16; ++r) a[c0 + r][q] = x[r];
+    }
+    __syncthreads();
+    const int nb = 3 - p;  // trailing blocks per side
+    for (int jb = wave; jb < nb * nb; jb += 4) {  // A22 -= L21 U12
+      const int r0 = c0 + 16 + 16 * (jb / nb), cc = c0 + 16 + 16 * (jb % nb);
+      typename Mma<F>::acc_t acc;
+      acc16_load<F>(a, r0, cc, acc);
+      mma16<F, true>(a, r0, c0, a, c0, cc, acc);
+      acc16_store<F>(acc, a, r0, cc, F(1));
     }
     __syncthreads();
   }
-  if (tid < 64) {
+
+  // diagonal 16x16 blocks of inv(L) (wave 0) and inv(U) (wave 1): lane = 16 b + c
+  if (wave < 2) {
+    const int b = lane >> 4, c = lane & 15, o = 16 * b;
+    F x[16];
+    if (wave == 0) {
 #pragma unroll
-    for (int r = 0; r < 64; ++r) a[r][tid] = col[r];
-  }
-  __syncthreads();
-  F x[64];
-  if (tid < 64) {  // column c of inv(L): x_r = [r==c] - sum_{q<r} L_rq x_q
-    const int c = tid;
+      for (int r = 0; r < 16; ++r) {
+        F s = (r == c) ? F(1) : F(0);
 #pragma unroll
-    for (int r = 0; r < 64; ++r) {
-      F s = (r == c) ? F(1) : F(0);
+        for (int m = 0; m < r; ++m) s -= a[o + r][o + m] * x[m];
+        x[r] = (r >= c) ? s : F(0);
+      }
 #pragma unroll
-      for (int q = 0; q < r; ++q) s -= a[r][q] * x[q];
-      x[r] = (r >= c) ? s : F(0);
+      for (int r = 0; r < 16; ++r) X[o + r][o + c] = x[r];
+    } else {
+#pragma unroll
+      for (int r = 15; r >= 0; --r) {
+        F s = (r == c) ? F(1) : F(0);
+#pragma unroll
+        for (int m = r + 1; m < 16; ++m) s -= a[o + r][o + m] * x[m];
+        x[r] = (r <= c) ? s / a[o + r][o + r] : F(0);
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) Y[o + r][o + c] = x[r];
     }
-  } else if (tid < 128) {  // column c of inv(U): x_r = ([r==c] - sum_{q>r} U_rq x_q) / U_rr
-    const int c = tid - 64;
-#pragma unroll
-    for (int r = 63; r >= 0; --r) {
-      F s = (r == c) ? F(1) : F(0);
-#pragma unroll
-      for (int q = r + 1; q < 64; ++q) s -= a[r][q] * x[q];
-      x[r] = (r <= c) ? s / a[r][r] : F(0);
+  }
+  __syncthreads();
+  // off-diagonal blocks, block diagonal dd: 4 - dd blocks of each inverse
+  for (int dd = 1; dd < 4; ++dd) {
+    for (int job = wave; job < 2 * (4 - dd); job += 4) {
+      const bool lower = job < 4 - dd;
+      const int t = lower ? job : job - (4 - dd);
+      typename Mma<F>::acc_t acc = {0, 0, 0, 0};
+      if (lower) {  // X_ij, i = t + dd, j = t: T = sum_{m=j}^{i-1} L_im X_mj, X_ij = -X_ii T
+        const int i = t + dd, j = t;
+        for (int m = j; m < i; ++m) mma16<F, false>(a, 16 * i, 16 * m, X, 16 * m, 16 * j, acc);
+        acc16_store<F>(acc, T[wave], 0, 0, F(1));
+        acc = typename Mma<F>::acc_t{0, 0, 0, 0};
+        mma16<F, false>(X, 16 * i, 16 * i, T[wave], 0, 0, acc);
+        acc16_store<F>(acc, X, 16 * i, 16 * j, F(-1));
+      } else {  // Y_ij, i = t, j = t + dd: T = sum_{m=i+1}^{j} U_im Y_mj, Y_ij = -Y_ii T
+        const int i = t, j = t + dd;
+        for (int m = i + 1; m <= j; ++m) mma16<F, false>(a, 16 * i, 16 * m, Y, 16 * m, 16 * j, acc);
+        acc16_store<F>(acc, T[wave], 0, 0, F(1));
+        acc = typename Mma<F>::acc_t{0, 0, 0, 0};
+        mma16<F, false>(Y, 16 * i, 16 * i, T[wave], 0, 0, acc);
+        acc16_store<F>(acc, Y, 16 * i, 16 * j, F(-1));
+      }
     }
+    __syncthreads();
   }
-  __syncthreads();  // every column read the factor: reuse a for inv(U), lbuf-free
-  if (tid >= 64 && tid < 128) {
-#pragma unroll
-    for (int r = 0; r < 64; ++r) a[r][tid - 64] = x[r];
-  }
-  __syncthreads();
-  lds_to_tile<F>(a, tkk);
-  __syncthreads();
-  if (tid < 64) {
-#pragma unroll
-    for (int r = 0; r < 64; ++r) a[r][tid] = x[r];
-  }
-  __syncthreads();
-  lds_to_tile<F>(a, linv);
+  lds_to_tile<F>(Y, tkk);
+  lds_to_tile<F>(X, linv);
 }
 
 // panel of tile column k: blockIdx.x < nr -> L_{k+1+x, k}, else U_{k, k+1+x'};
