@@ -25,11 +25,14 @@ PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_ras_c2_{prec}_pmc.md")
 
 
 def source_hash():
-    """Hash of the smoother kernel's source: counter summaries taken from an
-    older kernel are not reported."""
+    """Hash of the smoother kernel's sources (the kernel and the device headers
+    it includes): counter summaries taken from an older kernel are not
+    reported."""
     import hashlib
-    path = os.path.join(ROOT, "paper_2412_08981_amd", "csrc", "ras.hip")
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in ("ras.hip", "devcommon.h", "devtypes.h"):
+        h.update(open(os.path.join(ROOT, "paper_2412_08981_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def load_traffic(prec):

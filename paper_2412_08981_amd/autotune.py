@@ -14,6 +14,9 @@ from typing import Optional
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.path.join(HERE, "tuning.json")
+# Revision of the tuned kernels: launch shapes measured on an older revision
+# are not reused.  Raised whenever a tuned kernel changes its resource use.
+KERNEL_REV = 2
 
 
 def _device_name() -> str:
@@ -31,7 +34,7 @@ def _device_name() -> str:
 def tune(system, cache: Optional[str] = DEFAULT_CACHE, reps: int = 10, force: bool = False) -> dict:
     """Apply the cached tuning of system's hierarchy, or measure and cache it."""
     h = system.h
-    key = f"{_device_name()}|{h.signature()}"
+    key = f"r{KERNEL_REV}|{_device_name()}|{h.signature()}"
     db = {}
     if cache and os.path.exists(cache):
         with open(cache) as f:

@@ -79,11 +79,12 @@ struct Tagged<double> {
   }
 };
 
-// waves per SIMD the register allocation must allow: single-block work items
-// in FP64 are held to three (one spill slot) instead of two
+// waves per SIMD the register allocation must allow: FP64 takes the whole
+// register file (the four prefetched tiles alone are 128 VGPRs; one work-group
+// per CU is also the launch shape that streams fastest), FP32 two
 template <typename F, int K>
 struct RasWaves {
-  static constexpr int value = (K == 1 && sizeof(F) == 8) ? 3 : 1;
+  static constexpr int value = sizeof(F) == 8 ? 1 : 2;
 };
 
 template <typename F, typename V, int K>
@@ -203,10 +204,16 @@ __global__ __launch_bounds__(256, (RasWaves<F, K>::value)) void k_ras(RasLaunch 
 #pragma unroll
       for (int kk = 0; kk < K; ++kk) acc[kk] += (kk == r) ? d : F(0);
     };
-    C R0[NQ], R1[NQ];
+    // ring of four register tiles: the loads of tiles k+2 .. k+5 are in
+    // flight while tiles k, k+1 are applied (128 KB per work-group in FP64)
+    C R0[NQ], R1[NQ], R2[NQ], R3[NQ];
     load_tile(tile_of(0), R0);
     if (M >= 1) load_tile(tile_of(1), R1);
-    for (int k = 0; k < M; k += 2) {
+    if (M >= 2) load_tile(tile_of(2), R2);
+    if (M >= 3) load_tile(tile_of(3), R3);
+    // applies tiles k (Ra) and k+1 (Rb, when k+1 < M) and refills them with
+    // tiles k+4, k+5 (tile M is the first in-group tile, also kept)
+    auto pair = [&](int k, C (&Ra)[NQ], C (&Rb)[NQ]) {
       const bool two = k + 1 < M;
       const int j0 = col_of(k), j1 = two ? col_of(k + 1) : j0;
       // fetch both result blocks in one polling loop
@@ -231,26 +238,42 @@ __global__ __launch_bounds__(256, (RasWaves<F, K>::value)) void k_ras(RasLaunch 
       ywv[wave][1][lane] = y1;
       __builtin_amdgcn_wave_barrier();
       F d0 = 0;
-      gemv_lds(R0, ywv[wave][0], d0);
+      gemv_lds(Ra, ywv[wave][0], d0);
       add_row(k % nr, d0);
       // keep the refill of a tile's registers after their last use, so the
       // compiler does not double-buffer them (register pressure = occupancy)
       __builtin_amdgcn_sched_barrier(0);
-      if (k + 2 <= M) load_tile(tile_of(k + 2), R0);
+      if (k + 4 <= M) load_tile(tile_of(k + 4), Ra);
       if (two) {
         F d1 = 0;
-        gemv_lds(R1, ywv[wave][1], d1);
+        gemv_lds(Rb, ywv[wave][1], d1);
         add_row((k + 1) % nr, d1);
         __builtin_amdgcn_sched_barrier(0);
-        if (k + 3 <= M) load_tile(tile_of(k + 3), R1);
+        if (k + 5 <= M) load_tile(tile_of(k + 5), Rb);
       }
       __builtin_amdgcn_wave_barrier();
+    };
+    for (int k = 0; k < M; k += 4) {
+      pair(k, R0, R1);
+      if (k + 2 < M) pair(k + 2, R2, R3);
     }
-    // the first in-group tile is in R0 when M is even, in R1 when M is odd;
-    // from here on R0 is the current tile (A) and R1 the prefetched one (B)
-    if (M & 1) {
+    // the first in-group tile is in register tile M mod 4; from here on R0
+    // is the current tile (A) and R1 the prefetched one (B)
+    switch (M & 3) {
+      case 1:
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) R0[q] = R1[q];
+        for (int q = 0; q < NQ; ++q) R0[q] = R1[q];
+        break;
+      case 2:
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) R0[q] = R2[q];
+        break;
+      case 3:
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) R0[q] = R3[q];
+        break;
+      default:
+        break;
     }
     C(&A)[NQ] = R0;
     C(&B)[NQ] = R1;

@@ -143,19 +143,20 @@ namespace nnms {
 // bandwidth of the memory system for a large resident array)
 typedef int ivec4 __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(256) void k_read16(const ivec4* __restrict__ a, int64_t n, int* out) {
+  // each pass of a work-group reads 8 consecutive 4 KB stretches (one per
+  // load in flight), so every stretch of DRAM is streamed in order
+  constexpr int U = 8;
   int acc = 0;
-  const int64_t stride = int64_t(gridDim.x) * 256;
-  int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
-  for (; i + 7 * stride < n; i += 8 * stride) {
-    ivec4 v[8];
+  const int64_t stride = int64_t(gridDim.x) * 256 * U;
+  for (int64_t base = int64_t(blockIdx.x) * 256 * U; base < n; base += stride) {
+    ivec4 v[U];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = __builtin_nontemporal_load(a + i + u * stride);
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = base + u * 256 + threadIdx.x;
+      v[u] = i < n ? __builtin_nontemporal_load(a + i) : ivec4{0, 0, 0, 0};
+    }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) acc ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
-  }
-  for (; i < n; i += stride) {
-    const ivec4 v = a[i];
-    acc ^= v.x ^ v.y ^ v.z ^ v.w;
+    for (int u = 0; u < U; ++u) acc ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) acc ^= __shfl_xor(acc, off, 64);
