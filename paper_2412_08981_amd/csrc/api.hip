@@ -175,12 +175,50 @@ static int vec_blocks(int64_t n) { return int((n + VBLK - 1) / VBLK); }
 // ---------------------------------------------------------------------------
 // a batch plan: descriptor tables for every launch of one Arnoldi step
 // ---------------------------------------------------------------------------
+// One SpMV launch per lanes-per-row choice among the systems of a plan: the
+// choice fixes the summation order, so every system keeps the one of its own
+// hierarchy's tuning and gives the same bits alone and in any batch.
+struct SpmvGroup {
+  SpmvDesc* d = nullptr;
+  int nd = 0, blocks = 0, g = 16;
+};
+
+// items: (lanes per row, descriptor); blk0 is counted inside each group
+static std::vector<SpmvGroup> spmv_groups(Arena& mem, const std::vector<std::pair<int, SpmvDesc>>& items,
+                                          hipStream_t s) {
+  std::vector<int> gs;
+  for (const auto& it : items)
+    if (std::find(gs.begin(), gs.end(), it.first) == gs.end()) gs.push_back(it.first);
+  std::vector<SpmvGroup> out;
+  for (int g : gs) {
+    std::vector<SpmvDesc> v;
+    int b = 0;
+    for (const auto& it : items)
+      if (it.first == g) {
+        SpmvDesc d = it.second;
+        d.blk0 = b;
+        b += spmv_blocks(d.n, g);
+        v.push_back(d);
+      }
+    SpmvGroup G;
+    G.d = mem.upload(v, s), G.nd = int(v.size()), G.blocks = b, G.g = g;
+    out.push_back(G);
+  }
+  return out;
+}
+
+template <typename T>
+static hipError_t launch_spmv_groups(const std::vector<SpmvGroup>& gs, hipStream_t s) {
+  for (const SpmvGroup& G : gs) {
+    const hipError_t e = launch_spmv<T>(G.d, G.nd, G.blocks, G.g, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 struct LevelPlan {
-  int g_res = 16, g_rst = 32, ras_grid = 0, ras_k = 1;
-  SpmvDesc* res = nullptr;
-  int res_blocks = 0;
-  SpmvDesc* rst = nullptr;
-  int rst_blocks = 0;
+  int ras_grid = 0, ras_k = 1;
+  std::vector<SpmvGroup> res, rst;
   ProlongDesc* pro = nullptr;
   int pro_blocks = 0;
   RasLaunch ras_r{}, ras_t{};  // input r_l (write) / t_l (add)
@@ -195,14 +233,11 @@ struct Plan {
   std::vector<LevelPlan> lev;  // smoothed levels
   RasLaunch coarse{};
   int coarse_grid = 0, coarse_k = 1;
-  int g_w = 16;
   int nd = 0;
   KrylovDesc* kd = nullptr;
   std::vector<KrylovDesc> kd_host;
   int kblocks = 0;
-  SpmvDesc* wspmv = nullptr;
-  SpmvDesc* rspmv = nullptr;
-  int wblocks = 0;
+  std::vector<SpmvGroup> wspmv, rspmv;
   int* d_active = nullptr;
   int* h_active = nullptr;
   hipStream_t stream = nullptr;
@@ -309,19 +344,16 @@ static void build_plan(Plan& P, const std::vector<nnms_system*>& sys, bool with_
   P.lev.resize(std::max(0, L - 1));
   const nnms_tuning& tu = h0->tune;
   for (int l = 0; l < L - 1; ++l) {
-    P.lev[l].g_res = tu.spmv_lanes[l];
-    P.lev[l].g_rst = tu.pt_lanes[l];
     P.lev[l].ras_grid = tu.ras_groups[l] > 0 ? tu.ras_groups[l] : ras_grid_default();
     P.lev[l].ras_k = tu.ras_blocks[l];
   }
   P.coarse_grid = tu.ras_groups[L - 1] > 0 ? tu.ras_groups[L - 1] : ras_grid_default();
   P.coarse_k = tu.ras_blocks[L - 1];
-  P.g_w = tu.krylov_lanes;
   for (int l = 0; l < L - 1; ++l) {
     LevelPlan& LP = P.lev[l];
-    std::vector<SpmvDesc> res, rst;
+    std::vector<std::pair<int, SpmvDesc>> res, rst;
     std::vector<ProlongDesc> pro;
-    int br = 0, bt = 0, bp = 0;
+    int bp = 0;
     for (auto* x : sys) {
       const HostLevel& hl = x->h->host.lev[l];
       const HostLevel& hc = x->h->host.lev[l + 1];
@@ -331,15 +363,13 @@ static void build_plan(Plan& P, const std::vector<nnms_system*>& sys, bool with_
       const KState* st = with_state ? x->st : nullptr;
       SpmvDesc d{};
       d.rp = dl.rp, d.col = dl.col, d.val = val_of<T>(sl), d.x = sl.z, d.r = sl.r, d.y = sl.t;
-      d.st = st, d.n = int(hl.nv), d.blk0 = br, d.when = WHEN_RUNNING;
-      res.push_back(d);
-      br += spmv_blocks(hl.nv, LP.g_res);
+      d.st = st, d.n = int(hl.nv), d.when = WHEN_RUNNING;
+      res.emplace_back(x->h->tune.spmv_lanes[l], d);
       SpmvDesc e{};
       e.rp = dl.pt_rp, e.col = dl.pt_col;
       e.val = std::is_same<T, float>::value ? (const void*)dl.pt_w32 : (const void*)dl.pt_w64;
-      e.x = sl.t, e.r = nullptr, e.y = sc.r, e.st = st, e.n = int(hc.nv), e.blk0 = bt, e.when = WHEN_RUNNING;
-      rst.push_back(e);
-      bt += spmv_blocks(hc.nv, LP.g_rst);
+      e.x = sl.t, e.r = nullptr, e.y = sc.r, e.st = st, e.n = int(hc.nv), e.when = WHEN_RUNNING;
+      rst.emplace_back(x->h->tune.pt_lanes[l], e);
       ProlongDesc pd{};
       pd.idx = dl.p_idx;
       pd.w = std::is_same<T, float>::value ? (const void*)dl.p_w32 : (const void*)dl.p_w64;
@@ -347,8 +377,8 @@ static void build_plan(Plan& P, const std::vector<nnms_system*>& sys, bool with_
       pro.push_back(pd);
       bp += int((hl.nv + 255) / 256);
     }
-    LP.res = P.mem.upload(res, s), LP.res_blocks = br;
-    LP.rst = P.mem.upload(rst, s), LP.rst_blocks = bt;
+    LP.res = spmv_groups(P.mem, res, s);
+    LP.rst = spmv_groups(P.mem, rst, s);
     LP.pro = P.mem.upload(pro, s), LP.pro_blocks = bp;
     LP.nd = int(sys.size());
     build_ras_pair(P.mem, P.counters, sys, l, false, P.prec, with_state, LP.ras_k, s, LP.ras_r, LP.ras_t);
@@ -359,8 +389,8 @@ static void build_plan(Plan& P, const std::vector<nnms_system*>& sys, bool with_
   }
   // Krylov descriptors
   if (with_state) {
-    std::vector<SpmvDesc> wd, rd;
-    int kb = 0, wb = 0;
+    std::vector<std::pair<int, SpmvDesc>> wd, rd;
+    int kb = 0;
     for (auto* x : sys) {
       const HostLevel& h0l = x->h->host.lev[0];
       const DevLevel& d0 = x->h->dev[0];
@@ -368,23 +398,22 @@ static void build_plan(Plan& P, const std::vector<nnms_system*>& sys, bool with_
       k.V = x->V, k.Z = x->Z, k.w = x->w, k.x = x->x, k.b = x->bw, k.dmask = d0.dmask;
       k.part1 = x->part1, k.part2 = x->part2, k.partn = x->partn, k.partr = x->partr, k.st = x->st;
       k.r0 = x->lev[0].r, k.z0 = x->lev[0].z;
-      k.n = int(h0l.nv), k.blk0 = kb, k.nblk = x->nblk, k.nblkr = spmv_blocks(h0l.nv, P.g_w);
+      const int gw = x->h->tune.krylov_lanes;
+      k.n = int(h0l.nv), k.blk0 = kb, k.nblk = x->nblk, k.nblkr = spmv_blocks(h0l.nv, gw);
       if (k.nblkr > x->nblkr) throw Error(NNMS_ERR_INVALID_ARG, "residual partials exceed their buffer");
       P.kd_host.push_back(k);
       kb += x->nblk;
       SpmvDesc d{};
       d.rp = d0.rp, d.col = d0.col, d.val = x->lev[0].val64, d.x = x->Z, d.x_jstride = h0l.nv, d.r = nullptr;
-      d.y = x->w, d.st = x->st, d.n = int(h0l.nv), d.blk0 = wb, d.when = WHEN_RUNNING;
-      wd.push_back(d);
+      d.y = x->w, d.st = x->st, d.n = int(h0l.nv), d.when = WHEN_RUNNING;
+      wd.emplace_back(gw, d);
       d.x = x->x, d.x_jstride = 0, d.r = x->bw, d.nrm = x->partr, d.when = WHEN_CYCLE_END;
-      rd.push_back(d);
-      wb += spmv_blocks(h0l.nv, P.g_w);
+      rd.emplace_back(gw, d);
     }
     P.kd = P.mem.upload(P.kd_host, s);
     P.kblocks = kb;
-    P.wspmv = P.mem.upload(wd, s);
-    P.rspmv = P.mem.upload(rd, s);
-    P.wblocks = wb;
+    P.wspmv = spmv_groups(P.mem, wd, s);
+    P.rspmv = spmv_groups(P.mem, rd, s);
     P.d_active = P.mem.alloc<int>(1, s);
     HIP_CHECK(hipHostMalloc((void**)&P.h_active, sizeof(int), hipHostMallocDefault));
   }
@@ -407,18 +436,18 @@ static void enqueue_vcycle(Plan& P, hipStream_t s) {
     LevelPlan& LP = P.lev[l];
     HIP_CHECK((launch_ras<T, T>(LP.ras_r, LP.ras_grid, s)));
     for (int k = 1; k < its; ++k) {
-      HIP_CHECK(launch_spmv<T>(LP.res, LP.nd, LP.res_blocks, LP.g_res, s));
+      HIP_CHECK(launch_spmv_groups<T>(LP.res, s));
       HIP_CHECK((launch_ras<T, T>(LP.ras_t, LP.ras_grid, s)));
     }
-    HIP_CHECK(launch_spmv<T>(LP.res, LP.nd, LP.res_blocks, LP.g_res, s));
-    HIP_CHECK(launch_spmv<T>(LP.rst, LP.nd, LP.rst_blocks, LP.g_rst, s));
+    HIP_CHECK(launch_spmv_groups<T>(LP.res, s));
+    HIP_CHECK(launch_spmv_groups<T>(LP.rst, s));
   }
   HIP_CHECK((launch_ras<double, T>(P.coarse, P.coarse_grid, s)));
   for (int l = L - 2; l >= 0; --l) {
     LevelPlan& LP = P.lev[l];
     HIP_CHECK(launch_prolong<T>(LP.pro, LP.nd, LP.pro_blocks, s));
     for (int k = 0; k < its; ++k) {
-      HIP_CHECK(launch_spmv<T>(LP.res, LP.nd, LP.res_blocks, LP.g_res, s));
+      HIP_CHECK(launch_spmv_groups<T>(LP.res, s));
       HIP_CHECK((launch_ras<T, T>(LP.ras_t, LP.ras_grid, s)));
     }
   }
@@ -429,14 +458,14 @@ static void enqueue_step(Plan& P, hipStream_t s) {
   HIP_CHECK(launch_krylov_cast_in<T>(P.kd, P.nd, P.kblocks, s));
   enqueue_vcycle<T>(P, s);
   HIP_CHECK(launch_krylov_cast_out<T>(P.kd, P.nd, P.kblocks, s));
-  HIP_CHECK(launch_spmv<double>(P.wspmv, P.nd, P.wblocks, P.g_w, s));
+  HIP_CHECK(launch_spmv_groups<double>(P.wspmv, s));
   HIP_CHECK(launch_krylov_dots1(P.kd, P.nd, P.kblocks, s));
   HIP_CHECK(launch_krylov_upd1(P.kd, P.nd, P.kblocks, s));
   HIP_CHECK(launch_krylov_upd2(P.kd, P.nd, P.kblocks, s));
   HIP_CHECK(launch_krylov_givens(P.kd, P.nd, s));
   HIP_CHECK(launch_krylov_normalize(P.kd, P.nd, P.kblocks, s));
   HIP_CHECK(launch_krylov_xupd(P.kd, P.nd, P.kblocks, s));
-  HIP_CHECK(launch_spmv<double>(P.rspmv, P.nd, P.wblocks, P.g_w, s));
+  HIP_CHECK(launch_spmv_groups<double>(P.rspmv, s));
   HIP_CHECK(launch_krylov_cycle(P.kd, P.nd, s));
 }
 
@@ -995,9 +1024,9 @@ extern "C" nnms_status nnms_apply_restrict(nnms_system* s, int32_t level, const 
   const int64_t nf = s->h->host.lev[level].nv, nc = s->h->host.lev[level + 1].nv;
   put_vec(s, s->lev[level].t, x, nf, P.stream);
   if (s->prec == NNMS_FP64)
-    HIP_CHECK(launch_spmv<double>(P.lev[level].rst, 1, P.lev[level].rst_blocks, P.lev[level].g_rst, P.stream));
+    HIP_CHECK(launch_spmv_groups<double>(P.lev[level].rst, P.stream));
   else
-    HIP_CHECK(launch_spmv<float>(P.lev[level].rst, 1, P.lev[level].rst_blocks, P.lev[level].g_rst, P.stream));
+    HIP_CHECK(launch_spmv_groups<float>(P.lev[level].rst, P.stream));
   get_vec(s, y, s->lev[level + 1].r, nc, P.stream);
   return NNMS_OK;
   ABI_END
@@ -1242,9 +1271,9 @@ extern "C" nnms_status nnms_time_kernel(nnms_system* s, int32_t kind, int32_t le
       }
     } else if (kind == 1) {
       if (f64)
-        HIP_CHECK(launch_spmv<double>(P.lev[level].res, 1, P.lev[level].res_blocks, P.lev[level].g_res, st));
+        HIP_CHECK(launch_spmv_groups<double>(P.lev[level].res, st));
       else
-        HIP_CHECK(launch_spmv<float>(P.lev[level].res, 1, P.lev[level].res_blocks, P.lev[level].g_res, st));
+        HIP_CHECK(launch_spmv_groups<float>(P.lev[level].res, st));
     } else if (kind == 2) {
       if (f64)
         HIP_CHECK(launch_prolong<double>(P.lev[level].pro, 1, P.lev[level].pro_blocks, st));
@@ -1252,9 +1281,9 @@ extern "C" nnms_status nnms_time_kernel(nnms_system* s, int32_t kind, int32_t le
         HIP_CHECK(launch_prolong<float>(P.lev[level].pro, 1, P.lev[level].pro_blocks, st));
     } else {
       if (f64)
-        HIP_CHECK(launch_spmv<double>(P.lev[level].rst, 1, P.lev[level].rst_blocks, P.lev[level].g_rst, st));
+        HIP_CHECK(launch_spmv_groups<double>(P.lev[level].rst, st));
       else
-        HIP_CHECK(launch_spmv<float>(P.lev[level].rst, 1, P.lev[level].rst_blocks, P.lev[level].g_rst, st));
+        HIP_CHECK(launch_spmv_groups<float>(P.lev[level].rst, st));
     }
   };
   launch();  // warm-up

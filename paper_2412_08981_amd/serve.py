@@ -67,6 +67,10 @@ class Server:
         self._lock = threading.Lock()
         self.batch_forms = 0
         self.steps = 0
+        # host seconds spent in each part of the loop
+        self.t_form = 0.0  # building and destroying batch plans
+        self.t_step = 0.0  # launching one Arnoldi step and waiting for it
+        self.t_result = 0.0  # reading slot results, releasing finished systems
 
     # numeric setup on a worker thread and its own stream
     def _assemble(self, req: Request):
@@ -121,6 +125,7 @@ class Server:
                     remaining -= 1
             if ready:
                 # re-form the batch with the newcomers
+                tf = time.perf_counter()
                 old = batch
                 members = active + ready
                 batch = nnms.Batch([m[1] for m in members], self.restart, self.rtol, self.max_it, graph=self.graph)
@@ -130,12 +135,16 @@ class Server:
                 for k in range(len(active), len(members)):
                     batch.start(k, members[k][2].data_ptr())
                 active, ready = members, []
+                self.t_form += time.perf_counter() - tf
             if batch is None or not active:
                 # idle: wait for the next arrival or assembly
                 time.sleep(0.0005)
                 continue
+            ts = time.perf_counter()
             batch.step(1)
             self.steps += 1
+            tr = time.perf_counter()
+            self.t_step += tr - ts
             finished, still = [], []
             for k, (r, s, bd) in enumerate(active):
                 xo = None
@@ -152,12 +161,16 @@ class Server:
                     finished.append((r, s, bd))
                 else:
                     still.append((r, s, bd))
+            self.t_result += time.perf_counter() - tr
             if finished:
+                tf = time.perf_counter()
                 old = batch
                 batch = (nnms.Batch([m[1] for m in still], self.restart, self.rtol, self.max_it, graph=self.graph)
                          if still else None)
                 self.batch_forms += 1
                 old.destroy()
+                self.t_form += time.perf_counter() - tf
+                tr = time.perf_counter()
                 for r, s, bd in finished:
                     s.destroy()
                     self.used -= r.nbytes
@@ -165,11 +178,17 @@ class Server:
                     if log:
                         log(f"[serve] request {r.rid} ({r.key}) done: {r.iterations} its, latency "
                             f"{1e3 * (r.t_done - r.t_arrival):.1f} ms")
+                self.t_result += time.perf_counter() - tr
                 active = still
         if batch is not None:
             batch.destroy()
         self.pool.shutdown(wait=True)
-        return self.stats(reqs)
+        out = self.stats(reqs)
+        setup = [r.t_ready - r.t_admit for r in reqs if r.status == "done"]
+        out.update({"host_s_batch_forms": self.t_form, "host_s_steps": self.t_step,
+                    "host_s_results": self.t_result,
+                    "numeric_setup_ms_mean": float(np.mean(setup) * 1e3) if setup else float("nan")})
+        return out
 
     @staticmethod
     def stats(reqs: List[Request]) -> dict:

@@ -96,3 +96,38 @@ def test_blocks_per_work_item_same_bits(precision):
                 zr = o.vcycle.levels[l].ras.apply(r) if l < 2 else np.linalg.solve(o.A[l].toarray(), r)
                 assert np.linalg.norm(z - zr) <= 1e-9 * np.linalg.norm(zr), (K, l)
         s.destroy()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_of_differently_tuned_hierarchies_same_bits(precision):
+    """Systems whose hierarchies carry different lanes-per-row choices (which
+    fix the summation order) keep their own order inside one batch: every
+    slot equals its solve alone, bitwise."""
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2412_08981_amd import nnms
+
+    prec = nnms.MIXED if precision == "mixed" else nnms.FP64
+    keep, systems, bs, alone = [], [], [], []
+    for n, g, seed in ((14, 4, 11), (12, 64, 21), (14, 16, 31)):
+        pb = W.Problem("t", W.make_hierarchy([n, n // 2, 3], [seed, seed + 1, seed + 2]), [4, 2],
+                       W.kappa_draw(204, seed))
+        ms = [nnms.Mesh.from_workload(m) for m in pb.meshes]
+        h = nnms.Hierarchy(ms, pb.nparts, precision=prec)
+        d = h.get_tuning()
+        d["spmv_lanes"] = [g] * 8
+        d["pt_lanes"] = [64 // g * 4 if g < 16 else 8] * 8
+        d["krylov_lanes"] = g
+        h.set_tuning(d)
+        s = nnms.System(h, pb.kappa)
+        b = s.rhs()
+        keep.append((ms, h))
+        systems.append(s)
+        bs.append(b)
+        alone.append(s.solve(b))
+    xs, infos = nnms.solve_batch(systems, bs)
+    for k, (x, info) in enumerate(alone):
+        assert infos[k].iterations == info.iterations
+        assert np.array_equal(xs[k], x), k
