@@ -191,10 +191,22 @@ def run_serving(args):
             hier[n] = nnms.Hierarchy(ms, nps, precision=prec, torch_alloc=True)
             keep.append(ms)
         from paper_2412_08981_amd import autotune
+        sb = 8 if prec == nnms.FP64 else 4
+        kern = {}
         for n in sizes:
             sample = nnms.System(hier[n], W.KappaField("loggauss", centres=centres, mu=mus[0], width=W.KAPPA_WIDTH))
             autotune.tune(sample, cache=args.tuning_cache)
+            # fine-level kernels of each resident hierarchy (the 96^3 residual
+            # moves ~160 MB: bandwidth-bound, unlike the 21 MB one of 48^3)
+            h = hier[n]
+            msr = sample.time_kernel(1, 0, reps=20)
+            mss = sample.time_kernel(0, 0, reps=5)
+            kern[f"{n}^3"] = {"residual_l0_ms": round(msr, 4),
+                              "residual_l0_GBs": round(spmv_bytes(h, 0, sb) / (msr * 1e-3) / 1e9, 1),
+                              "smoother_l0_ms": round(mss, 4),
+                              "smoother_l0_GBs": round(ras_bytes(h, 0, sb) / (mss * 1e-3) / 1e9, 1)}
             sample.destroy()
+        log(f"[bench c5] {precision}: kernels {kern}")
         log(f"[bench c5] {precision}: hierarchies set up in {time.perf_counter() - t0:.1f} s; bytes per request "
             f"{ {n: round(h.system_bytes() / 2**30, 2) for n, h in hier.items()} } GiB")
 
@@ -216,6 +228,7 @@ def run_serving(args):
         st["capacity_solves_per_s"] = cap
         st["batch_forms"] = srv.batch_forms
         st["steps"] = srv.steps
+        st["kernels"] = kern
         st["capacity_run"] = {k: st_cap[k] for k in ("host_s_batch_forms", "host_s_steps", "host_s_results",
                                                      "numeric_setup_ms_mean", "p50_ms")}
         res[precision] = st

@@ -47,24 +47,75 @@ class Request:
     error: str = ""
 
 
-class Server:
-    def __init__(self, hierarchies: Dict[object, "nnms.Hierarchy"], budget_bytes: int, restart: int = 30,
-                 rtol: float = 1e-8, max_it: int = 1000, graph: bool = False, keep_x: bool = False,
-                 workers: int = 1):
+class DeviceEngine:
+    """The device side of the serving loop: the library's systems and batches
+    on PyTorch streams.  The loop itself only calls these methods, so its
+    host logic runs unchanged against any object with the same methods."""
+
+    def __init__(self, workers: int = 1):
         import torch
 
         self.torch = torch
+        self.streams = [torch.cuda.Stream() for _ in range(workers)]
+        self._tls = threading.local()
+        self._ix = 0
+        self._lock = threading.Lock()
+
+    def system_bytes(self, h, restart: int) -> int:
+        return h.system_bytes(restart)
+
+    # numeric setup on the calling worker thread's own stream
+    def assemble(self, h, kappa, b):
+        with self._lock:
+            if not hasattr(self._tls, "stream"):
+                self._tls.stream = self.streams[self._ix % len(self.streams)]
+                self._ix += 1
+        s = nnms.System(h, kappa, 1.0, stream=self._tls.stream)
+        b = s.rhs() if b is None else np.asarray(b, dtype=np.float64)
+        bd = self.torch.from_numpy(b).to("cuda")
+        self.torch.cuda.current_stream().synchronize()
+        return s, bd
+
+    def batch(self, systems, restart, rtol, max_it, graph):
+        return nnms.Batch(systems, restart, rtol, max_it, graph=graph)
+
+    def start(self, batch, slot: int, bd) -> None:
+        batch.start(slot, bd.data_ptr())
+
+    def step(self, batch) -> None:
+        batch.step(1)
+
+    def result(self, batch, slot: int, system, keep_x: bool):
+        """(info, x or None) of a slot; info.running tells whether it goes on."""
+        torch = self.torch
+        xo = torch.empty(system.n[0], dtype=torch.float64, device="cuda") if keep_x else None
+        info = batch.result(slot, None if xo is None else xo.data_ptr())
+        x = None
+        if xo is not None and not info.running:
+            torch.cuda.synchronize()
+            x = xo.cpu().numpy()
+        return info, x
+
+    def release_batch(self, batch) -> None:
+        batch.destroy()
+
+    def release_system(self, system) -> None:
+        system.destroy()
+
+
+class Server:
+    def __init__(self, hierarchies: Dict[object, "nnms.Hierarchy"], budget_bytes: int, restart: int = 30,
+                 rtol: float = 1e-8, max_it: int = 1000, graph: bool = False, keep_x: bool = False,
+                 workers: int = 1, engine=None):
+        self.engine = engine if engine is not None else DeviceEngine(workers)
         self.h = hierarchies
         self.budget = int(budget_bytes)
         self.used = 0
+        self.max_used = 0
         self.restart, self.rtol, self.max_it, self.graph = restart, rtol, max_it, graph
         self.keep_x = keep_x
-        self.sizes = {k: h.system_bytes(restart) for k, h in hierarchies.items()}
+        self.sizes = {k: self.engine.system_bytes(h, restart) for k, h in hierarchies.items()}
         self.pool = ThreadPoolExecutor(max_workers=workers)
-        self.streams = [torch.cuda.Stream() for _ in range(workers)]
-        self._tls = threading.local()
-        self._stream_ix = 0
-        self._lock = threading.Lock()
         self.batch_forms = 0
         self.steps = 0
         # host seconds spent in each part of the loop
@@ -72,21 +123,11 @@ class Server:
         self.t_step = 0.0  # launching one Arnoldi step and waiting for it
         self.t_result = 0.0  # reading slot results, releasing finished systems
 
-    # numeric setup on a worker thread and its own stream
     def _assemble(self, req: Request):
-        with self._lock:
-            if not hasattr(self._tls, "stream"):
-                self._tls.stream = self.streams[self._stream_ix % len(self.streams)]
-                self._stream_ix += 1
-        st = self._tls.stream
-        s = nnms.System(self.h[req.key], req.kappa, 1.0, stream=st)
-        b = s.rhs() if req.b is None else np.asarray(req.b, dtype=np.float64)
-        bd = self.torch.from_numpy(b).to("cuda")
-        self.torch.cuda.current_stream().synchronize()
-        return s, bd
+        return self.engine.assemble(self.h[req.key], req.kappa, req.b)
 
     def run(self, requests: List[Request], log=None) -> dict:
-        torch = self.torch
+        eng = self.engine
         reqs = sorted(requests, key=lambda r: r.t_arrival)
         arrivals = deque(reqs)
         queue: deque = deque()
@@ -111,6 +152,7 @@ class Server:
             while queue and self.used + queue[0].nbytes <= self.budget:
                 r = queue.popleft()
                 self.used += r.nbytes
+                self.max_used = max(self.max_used, self.used)
                 r.t_admit, r.status = now(), "assembling"
                 assembling[self.pool.submit(self._assemble, r)] = r
             for fut in [f for f in assembling if f.done()]:
@@ -128,12 +170,12 @@ class Server:
                 tf = time.perf_counter()
                 old = batch
                 members = active + ready
-                batch = nnms.Batch([m[1] for m in members], self.restart, self.rtol, self.max_it, graph=self.graph)
+                batch = eng.batch([m[1] for m in members], self.restart, self.rtol, self.max_it, self.graph)
                 self.batch_forms += 1
                 if old is not None:
-                    old.destroy()
+                    eng.release_batch(old)
                 for k in range(len(active), len(members)):
-                    batch.start(k, members[k][2].data_ptr())
+                    eng.start(batch, k, members[k][2])
                 active, ready = members, []
                 self.t_form += time.perf_counter() - tf
             if batch is None or not active:
@@ -141,22 +183,17 @@ class Server:
                 time.sleep(0.0005)
                 continue
             ts = time.perf_counter()
-            batch.step(1)
+            eng.step(batch)
             self.steps += 1
             tr = time.perf_counter()
             self.t_step += tr - ts
             finished, still = [], []
             for k, (r, s, bd) in enumerate(active):
-                xo = None
-                if self.keep_x:
-                    xo = torch.empty(s.n[0], dtype=torch.float64, device="cuda")
-                info = batch.result(k, None if xo is None else xo.data_ptr())
+                info, x = eng.result(batch, k, s, self.keep_x)
                 if not info.running:
                     r.iterations, r.relres = info.iterations, info.relres
                     r.status = "done" if info.status == 0 else "failed"
-                    if xo is not None:
-                        torch.cuda.synchronize()
-                        r.x = xo.cpu().numpy()
+                    r.x = x
                     r.t_done = now()
                     finished.append((r, s, bd))
                 else:
@@ -165,14 +202,13 @@ class Server:
             if finished:
                 tf = time.perf_counter()
                 old = batch
-                batch = (nnms.Batch([m[1] for m in still], self.restart, self.rtol, self.max_it, graph=self.graph)
-                         if still else None)
+                batch = eng.batch([m[1] for m in still], self.restart, self.rtol, self.max_it, self.graph) if still else None
                 self.batch_forms += 1
-                old.destroy()
+                eng.release_batch(old)
                 self.t_form += time.perf_counter() - tf
                 tr = time.perf_counter()
                 for r, s, bd in finished:
-                    s.destroy()
+                    eng.release_system(s)
                     self.used -= r.nbytes
                     remaining -= 1
                     if log:
@@ -181,11 +217,11 @@ class Server:
                 self.t_result += time.perf_counter() - tr
                 active = still
         if batch is not None:
-            batch.destroy()
+            eng.release_batch(batch)
         self.pool.shutdown(wait=True)
         out = self.stats(reqs)
         setup = [r.t_ready - r.t_admit for r in reqs if r.status == "done"]
-        out.update({"host_s_batch_forms": self.t_form, "host_s_steps": self.t_step,
+        out.update({"max_bytes_admitted": self.max_used, "host_s_batch_forms": self.t_form, "host_s_steps": self.t_step,
                     "host_s_results": self.t_result,
                     "numeric_setup_ms_mean": float(np.mean(setup) * 1e3) if setup else float("nan")})
         return out
