@@ -241,15 +241,20 @@ nnms_status nnms_time_kernel(nnms_system* s, int32_t kind, int32_t level, int32_
 
 /* ---------------------------------------------------------------------------
  * Launch-shape tuning, per hierarchy (used by every solve plan created after
- * it is set; a batch uses the tuning of its first system's hierarchy).
- *   spmv_lanes[l]  lanes of a wave per CSR row of level l's operator (4..64)
+ * it is set).  A batch keeps every system's own lanes-per-row choices (they
+ * fix the summation order, so a system gives the same bits alone and in any
+ * batch) and takes the smoother's launch shapes from its first system's
+ * hierarchy (they change no arithmetic).
+ *   spmv_lanes[l]  lanes of a wave per CSR row of level l's operator (4..64),
+ *                  or 0: the operator in sliced ELL layout (64-row slices,
+ *                  one lane per row)
  *   pt_lanes[l]    lanes per row of P_l^T (4..64)
  *   ras_groups[l]  work-groups of the persistent triangular-solve kernel on
  *                  level l (0 = 4 per compute unit)
  *   ras_blocks[l]  64-row blocks per work item of that kernel (1, 2 or 4):
  *                  blocks inside a work item are substituted in order by one
  *                  work-group, only work items hand results to each other
- *   krylov_lanes   lanes per row of the outer FP64 operator
+ *   krylov_lanes   lanes per row of the outer FP64 operator (0: sliced ELL)
  * nnms_autotune times the candidates of every entry on the system's own
  * data with HIP events (reps launches each), keeps the fastest, stores the
  * result in the system's hierarchy and in *out (may be NULL).

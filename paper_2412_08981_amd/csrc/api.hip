@@ -96,6 +96,7 @@ struct DevLevel {
   double* xyz = nullptr;
   uint8_t* dmask = nullptr;
   int32_t *gidx = nullptr, *ext_rs = nullptr, *ext_lc = nullptr;
+  int32_t *sell_off = nullptr, *sell_col = nullptr, *sell_src = nullptr;
   int32_t* p_idx = nullptr;
   double* p_w64 = nullptr;
   float* p_w32 = nullptr;
@@ -124,6 +125,8 @@ namespace nnms {
 struct SysLevel {
   double* val64 = nullptr;
   float* val32 = nullptr;
+  double* ell64 = nullptr;  // the values in the sliced ELL layout of the pattern
+  float* ell32 = nullptr;
   void* fac = nullptr;  // factor tiles (float in mixed smoothed levels, else double)
   void* yx = nullptr;   // triangular-solve workspace (factor type)
   void* r = nullptr;    // level vectors, working precision
@@ -169,7 +172,12 @@ static int ras_grid_default() {
   return g;
 }
 
-static int spmv_blocks(int64_t n, int G) { return int((n + (256 / G) - 1) / (256 / G)); }
+// blocks of one SpMV launch: G lanes per CSR row, or G = 0 for the sliced ELL
+// layout (four 64-row slices per block)
+static int spmv_blocks(int64_t n, int G) {
+  if (G == 0) return int((n + 255) / 256);
+  return int((n + (256 / G) - 1) / (256 / G));
+}
 static int vec_blocks(int64_t n) { return int((n + VBLK - 1) / VBLK); }
 
 // ---------------------------------------------------------------------------
@@ -210,7 +218,7 @@ static std::vector<SpmvGroup> spmv_groups(Arena& mem, const std::vector<std::pai
 template <typename T>
 static hipError_t launch_spmv_groups(const std::vector<SpmvGroup>& gs, hipStream_t s) {
   for (const SpmvGroup& G : gs) {
-    const hipError_t e = launch_spmv<T>(G.d, G.nd, G.blocks, G.g, s);
+    const hipError_t e = G.g == 0 ? launch_sell<T>(G.d, G.nd, G.blocks, s) : launch_spmv<T>(G.d, G.nd, G.blocks, G.g, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -256,6 +264,12 @@ template <typename T>
 static const void* val_of(const SysLevel& sl) {
   if (std::is_same<T, float>::value) return sl.val32;
   return sl.val64;
+}
+
+template <typename T>
+static const void* ell_of(const SysLevel& sl) {
+  if (std::is_same<T, float>::value) return sl.ell32;
+  return sl.ell64;
 }
 
 // task list of one restricted additive Schwarz launch over subdomains with
@@ -362,9 +376,14 @@ static void build_plan(Plan& P, const std::vector<nnms_system*>& sys, bool with_
       const SysLevel& sc = x->lev[l + 1];
       const KState* st = with_state ? x->st : nullptr;
       SpmvDesc d{};
-      d.rp = dl.rp, d.col = dl.col, d.val = val_of<T>(sl), d.x = sl.z, d.r = sl.r, d.y = sl.t;
+      const int ga = x->h->tune.spmv_lanes[l];
+      if (ga == 0)
+        d.rp = dl.sell_off, d.col = dl.sell_col, d.val = ell_of<T>(sl);
+      else
+        d.rp = dl.rp, d.col = dl.col, d.val = val_of<T>(sl);
+      d.x = sl.z, d.r = sl.r, d.y = sl.t;
       d.st = st, d.n = int(hl.nv), d.when = WHEN_RUNNING;
-      res.emplace_back(x->h->tune.spmv_lanes[l], d);
+      res.emplace_back(ga, d);
       SpmvDesc e{};
       e.rp = dl.pt_rp, e.col = dl.pt_col;
       e.val = std::is_same<T, float>::value ? (const void*)dl.pt_w32 : (const void*)dl.pt_w64;
@@ -404,7 +423,11 @@ static void build_plan(Plan& P, const std::vector<nnms_system*>& sys, bool with_
       P.kd_host.push_back(k);
       kb += x->nblk;
       SpmvDesc d{};
-      d.rp = d0.rp, d.col = d0.col, d.val = x->lev[0].val64, d.x = x->Z, d.x_jstride = h0l.nv, d.r = nullptr;
+      if (gw == 0)
+        d.rp = d0.sell_off, d.col = d0.sell_col, d.val = x->lev[0].ell64;
+      else
+        d.rp = d0.rp, d.col = d0.col, d.val = x->lev[0].val64;
+      d.x = x->Z, d.x_jstride = h0l.nv, d.r = nullptr;
       d.y = x->w, d.st = x->st, d.n = int(h0l.nv), d.when = WHEN_RUNNING;
       wd.emplace_back(gw, d);
       d.x = x->x, d.x_jstride = 0, d.r = x->bw, d.nrm = x->partr, d.when = WHEN_CYCLE_END;
@@ -597,6 +620,7 @@ static void build_host(const nnms_mesh* const* levels, int32_t L, const nnms_set
     lv.tets = levels[l]->tets;
     lv.dir = levels[l]->dir;
     build_pattern(lv);
+    build_sell(lv);
     const bool direct = (l == L - 1);
     int np = direct ? 1 : opts->nparts[l];
     if (!direct && np == 0) np = default_nparts(lv.nv);
@@ -652,6 +676,9 @@ extern "C" nnms_status nnms_hierarchy_setup(const nnms_mesh* const* levels, int3
     d.gidx = A.upload(hl.gidx, s);
     d.ext_rs = A.upload(hl.ext_rs, s);
     d.ext_lc = A.upload(hl.ext_lc, s);
+    d.sell_off = A.upload(hl.sell_off, s);
+    d.sell_col = A.upload(hl.sell_col, s);
+    d.sell_src = A.upload(hl.sell_src, s);
     if (l + 1 < L) {
       d.p_idx = A.upload(hl.p_idx, s);
       d.p_w64 = A.upload(hl.p_w, s);
@@ -739,6 +766,8 @@ static int64_t system_bytes(const HostHierarchy& H, int prec, int restart) {
     const int64_t f = (coarse || prec == NNMS_FP64) ? 8 : 4;
     const int64_t t = prec == NNMS_FP64 ? 8 : 4;
     b += int64_t(lv.col.size()) * 8 + (prec == NNMS_MIXED ? int64_t(lv.col.size()) * 4 : 0);
+    const int64_t ne = lv.sell_off.empty() ? 0 : int64_t(lv.sell_off.back());
+    b += ne * 8 + (prec == NNMS_MIXED ? ne * 4 : 0);
     b += lv.fac_elems * f + lv.g_total * 16 + 3 * lv.nv * t;
   }
   const int64_t n0 = H.lev[0].nv;
@@ -849,6 +878,9 @@ extern "C" nnms_status nnms_assemble(nnms_hierarchy* h, const nnms_kappa* k, dou
     const size_t fsz = (coarse || prec == NNMS_FP64) ? 8 : 4;
     sl.val64 = A.alloc<double>(hl.col.size(), s, false);
     if (prec == NNMS_MIXED) sl.val32 = A.alloc<float>(hl.col.size(), s, false);
+    const int64_t nell = int64_t(hl.sell_off.back());
+    sl.ell64 = A.alloc<double>(nell, s, false);
+    if (prec == NNMS_MIXED) sl.ell32 = A.alloc<float>(nell, s, false);
     sl.fac = A.raw(std::max<size_t>(size_t(hl.fac_elems) * fsz, 256));
     sl.yx = A.alloc<char>(size_t(hl.g_total) * 16, s);  // tagged block results: 16 bytes per value
     sl.r = A.alloc<char>(hl.nv * tsz, s);
@@ -863,6 +895,8 @@ extern "C" nnms_status nnms_assemble(nnms_hierarchy* h, const nnms_kappa* k, dou
       ad.b = sys->b0;
     }
     HIP_CHECK(launch_assemble(ad, kd, f, s));
+    HIP_CHECK(launch_gather_ell<double>(dl.sell_src, sl.val64, sl.ell64, nell, s));
+    if (sl.ell32) HIP_CHECK(launch_gather_ell<float>(dl.sell_src, sl.val64, sl.ell32, nell, s));
     // dense subdomain matrices and their factors
     FactorJob job = factor_job(*sys, l, scratch, s);
     HIP_CHECK(enqueue_factor(job, err, s));
@@ -1344,6 +1378,7 @@ extern "C" nnms_status nnms_system_factor(const nnms_system* s, int32_t level, i
 // launch-shape tuning
 // ---------------------------------------------------------------------------
 static bool lanes_ok(int g) { return g == 4 || g == 8 || g == 16 || g == 32 || g == 64; }
+static bool op_lanes_ok(int g) { return g == 0 || lanes_ok(g); }  // 0: sliced ELL
 
 extern "C" nnms_status nnms_hierarchy_get_tuning(const nnms_hierarchy* h, nnms_tuning* out) {
   ABI_BEGIN
@@ -1357,10 +1392,10 @@ extern "C" nnms_status nnms_hierarchy_set_tuning(nnms_hierarchy* h, const nnms_t
   ABI_BEGIN
   if (!h || !t) throw Error(NNMS_ERR_INVALID_ARG, "null argument");
   for (int l = 0; l < NNMS_MAX_LEVELS; ++l)
-    if (!lanes_ok(t->spmv_lanes[l]) || !lanes_ok(t->pt_lanes[l]) || t->ras_groups[l] < 0 || t->ras_groups[l] > 65536 ||
+    if (!op_lanes_ok(t->spmv_lanes[l]) || !lanes_ok(t->pt_lanes[l]) || t->ras_groups[l] < 0 || t->ras_groups[l] > 65536 ||
         !(t->ras_blocks[l] == 1 || t->ras_blocks[l] == 2 || t->ras_blocks[l] == 4))
       throw Error(NNMS_ERR_INVALID_ARG, "bad tuning entry");
-  if (!lanes_ok(t->krylov_lanes)) throw Error(NNMS_ERR_INVALID_ARG, "bad tuning entry");
+  if (!op_lanes_ok(t->krylov_lanes)) throw Error(NNMS_ERR_INVALID_ARG, "bad tuning entry");
   h->tune = *t;
   h->tune.tuned = 1;
   return NNMS_OK;
@@ -1395,21 +1430,36 @@ extern "C" nnms_status nnms_autotune(nnms_system* s, int32_t reps, nnms_tuning* 
   hipStream_t st = P.stream;
   Arena tmp(h->has_alloc ? &h->alloc : nullptr);
   const int lanes[] = {4, 8, 16, 32, 64};
+  // fastest lanes per CSR row; with the sliced ELL arrays given, 0 (that
+  // layout) is a candidate too
   auto spmv_best = [&](const int32_t* rp, const int32_t* col, const void* val, const void* x, const void* r, void* y,
-                       int64_t n, bool dbl) {
+                       int64_t n, bool dbl, const int32_t* soff = nullptr, const int32_t* scol = nullptr,
+                       const void* sval = nullptr) {
     int best = 16;
     double bt = 1e30;
-    for (int g : lanes) {
+    std::vector<int> cand(std::begin(lanes), std::end(lanes));
+    if (soff) cand.push_back(0);
+    for (int g : cand) {
       SpmvDesc d{};
-      d.rp = rp, d.col = col, d.val = val, d.x = x, d.r = r, d.y = y, d.n = int(n), d.blk0 = 0, d.when = WHEN_RUNNING;
+      if (g == 0)
+        d.rp = soff, d.col = scol, d.val = sval;
+      else
+        d.rp = rp, d.col = col, d.val = val;
+      d.x = x, d.r = r, d.y = y, d.n = int(n), d.blk0 = 0, d.when = WHEN_RUNNING;
       std::vector<SpmvDesc> v{d};
       SpmvDesc* dd = tmp.upload(v, st);
       const int nb = spmv_blocks(n, g);
       double ms = time_ms(st, reps, [&]() {
-        if (dbl)
+        if (g == 0) {
+          if (dbl)
+            HIP_CHECK(launch_sell<double>(dd, 1, nb, st));
+          else
+            HIP_CHECK(launch_sell<float>(dd, 1, nb, st));
+        } else if (dbl) {
           HIP_CHECK(launch_spmv<double>(dd, 1, nb, g, st));
-        else
+        } else {
           HIP_CHECK(launch_spmv<float>(dd, 1, nb, g, st));
+        }
       });
       if (ms < bt) bt = ms, best = g;
     }
@@ -1449,7 +1499,8 @@ extern "C" nnms_status nnms_autotune(nnms_system* s, int32_t reps, nnms_tuning* 
     SysLevel& sl = s->lev[l];
     const int64_t n = h->host.lev[l].nv, nc = h->host.lev[l + 1].nv;
     const void* val = f64 ? (const void*)sl.val64 : (const void*)sl.val32;
-    t.spmv_lanes[l] = spmv_best(dl.rp, dl.col, val, sl.z, sl.r, sl.t, n, f64);
+    const void* ell = f64 ? (const void*)sl.ell64 : (const void*)sl.ell32;
+    t.spmv_lanes[l] = spmv_best(dl.rp, dl.col, val, sl.z, sl.r, sl.t, n, f64, dl.sell_off, dl.sell_col, ell);
     const void* ptw = f64 ? (const void*)dl.pt_w64 : (const void*)dl.pt_w32;
     t.pt_lanes[l] = spmv_best(dl.pt_rp, dl.pt_col, ptw, sl.t, nullptr, s->lev[l + 1].r, nc, f64);
     ras_best(l, false, t.ras_groups[l], t.ras_blocks[l]);
@@ -1462,7 +1513,8 @@ extern "C" nnms_status nnms_autotune(nnms_system* s, int32_t reps, nnms_tuning* 
   }
   {
     const DevLevel& d0 = h->dev[0];
-    t.krylov_lanes = spmv_best(d0.rp, d0.col, s->lev[0].val64, s->x, nullptr, s->w, h->host.lev[0].nv, true);
+    t.krylov_lanes = spmv_best(d0.rp, d0.col, s->lev[0].val64, s->x, nullptr, s->w, h->host.lev[0].nv, true,
+                               d0.sell_off, d0.sell_col, s->lev[0].ell64);
   }
   check_counters(P, st);
   t.tuned = 1;

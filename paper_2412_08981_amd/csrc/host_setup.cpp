@@ -123,6 +123,34 @@ static void rcb(const HostLevel& lv, std::vector<int32_t>& ids, int nparts, int 
   rcb(lv, hi, nparts / 2, depth + 1, out);
 }
 
+void build_sell(HostLevel& lv) {
+  const int64_t nv = lv.nv, ns = (nv + 63) / 64;
+  lv.sell_off.assign(ns + 1, 0);
+  for (int64_t sl = 0; sl < ns; ++sl) {
+    int32_t w = 0;
+    for (int64_t i = sl * 64; i < std::min(nv, sl * 64 + 64); ++i) w = std::max(w, lv.rp[i + 1] - lv.rp[i]);
+    if (int64_t(lv.sell_off[sl]) + int64_t(w) * 64 > INT32_MAX) throw Error(NNMS_ERR_INVALID_ARG, "level too large for 32-bit indices");
+    lv.sell_off[sl + 1] = lv.sell_off[sl] + w * 64;
+  }
+  lv.sell_col.assign(lv.sell_off[ns], 0);
+  lv.sell_src.assign(lv.sell_off[ns], -1);
+  for (int64_t sl = 0; sl < ns; ++sl) {
+    const int32_t w = (lv.sell_off[sl + 1] - lv.sell_off[sl]) / 64;
+    for (int l = 0; l < 64; ++l) {
+      const int64_t i = sl * 64 + l;
+      for (int32_t k = 0; k < w; ++k) {
+        const int64_t e = lv.sell_off[sl] + int64_t(k) * 64 + l;
+        if (i < nv && lv.rp[i] + k < lv.rp[i + 1]) {
+          lv.sell_col[e] = lv.col[lv.rp[i] + k];
+          lv.sell_src[e] = lv.rp[i] + k;
+        } else {
+          lv.sell_col[e] = i < nv ? int32_t(i) : 0;  // padding: value 0 times an existing entry of x
+        }
+      }
+    }
+  }
+}
+
 void build_partition(HostLevel& lv, int nparts, int overlap, bool direct) {
   const int64_t nv = lv.nv;
   std::vector<int32_t> interior;

@@ -38,6 +38,11 @@ struct HostLevel {
   std::vector<int32_t> cptr, citem;
   // vertex -> incident elements (t*4 + a), ordered by element id
   std::vector<int32_t> vptr, vitem;
+  // the same pattern as sliced ELL: 64-row slices stored column-major (entry
+  // k of row 64s + l at sell_off[s] + 64k + l), slice width = its longest
+  // row; sell_src = CSR slot of every entry, -1 for padding (column = own row)
+  std::vector<int32_t> sell_off;  // slices + 1
+  std::vector<int32_t> sell_col, sell_src;
 
   // Schwarz partition (nparts subdomains; 1 on the coarsest level)
   int32_t nparts = 0;
@@ -70,6 +75,7 @@ struct HostHierarchy {
 
 // host setup steps
 void build_pattern(HostLevel& lv);
+void build_sell(HostLevel& lv);
 void build_partition(HostLevel& lv, int nparts, int overlap, bool direct);
 void build_transfer(HostLevel& fine, const HostLevel& coarse);
 int default_nparts(int64_t nv);

@@ -44,6 +44,75 @@ __global__ __launch_bounds__(256) void k_spmv(const SpmvDesc* __restrict__ d, in
   }
 }
 
+// Sliced ELL (the level operators): one wave per 64-row slice, lane = row,
+// the slice's columns stored column-major, so every load of a step is 64
+// consecutive values; no row pointers, no cross-lane reduction, each row
+// summed in order (deterministic).  Same descriptor as the CSR kernel with
+// rp = slice offsets, col / val = the ELL arrays; 4 slices per block.
+template <typename T>
+__global__ __launch_bounds__(256) void k_sell(const SpmvDesc* __restrict__ d, int nd) {
+  const int b = blockIdx.x;
+  const SpmvDesc D = d[find_desc(d, nd, b)];
+  if (!slot_active(D.st, D.when)) return;
+  const int lb = b - D.blk0;
+  const int lane = threadIdx.x & 63;
+  const int slice = lb * 4 + (threadIdx.x >> 6);
+  const int row = slice * 64 + lane;
+  const T* __restrict__ x = (const T*)D.x;
+  if (D.x_jstride) x += int64_t(D.st->j) * D.x_jstride;
+  T sum = 0;
+  if (slice * 64 < D.n) {
+    const int e0 = D.rp[slice], w = (D.rp[slice + 1] - e0) >> 6;
+    const GLOBAL int32_t* col = gptr(D.col) + e0 + lane;
+    const GLOBAL T* val = gptr((const T*)D.val) + e0 + lane;
+#pragma unroll 4
+    for (int k = 0; k < w; ++k) sum += val[64 * k] * x[col[64 * k]];
+  }
+  T out = 0;
+  if (row < D.n) {
+    out = D.r ? ((const T*)D.r)[row] - sum : sum;
+    ((T*)D.y)[row] = out;
+  }
+  if (D.nrm) {  // partial sum of squares of this block's outputs (fixed order)
+    __shared__ double red[4];
+    double q = row < D.n ? double(out) * double(out) : 0.0;
+    q = wave_sum(q);
+    if (lane == 0) red[threadIdx.x >> 6] = q;
+    __syncthreads();
+    if (threadIdx.x == 0) D.nrm[lb] = (red[0] + red[1]) + (red[2] + red[3]);
+  }
+}
+
+// ell[e] = csr[src[e]] (0 for padding, src < 0)
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather_ell(const int32_t* __restrict__ src, const double* __restrict__ csr,
+                                                    T* __restrict__ ell, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i < n) {
+    const int32_t q = src[i];
+    ell[i] = q >= 0 ? T(csr[q]) : T(0);
+  }
+}
+
+template <typename T>
+hipError_t launch_sell(const SpmvDesc* d, int nd, int nblocks, hipStream_t s) {
+  if (nd <= 0 || nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_sell<T>), dim3(nblocks), dim3(256), 0, s, d, nd);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gather_ell(const int32_t* src, const double* csr, T* ell, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_gather_ell<T>), dim3((n + 255) / 256), dim3(256), 0, s, src, csr, ell, n);
+  return hipGetLastError();
+}
+
+template hipError_t launch_sell<double>(const SpmvDesc*, int, int, hipStream_t);
+template hipError_t launch_sell<float>(const SpmvDesc*, int, int, hipStream_t);
+template hipError_t launch_gather_ell<double>(const int32_t*, const double*, double*, int64_t, hipStream_t);
+template hipError_t launch_gather_ell<float>(const int32_t*, const double*, float*, int64_t, hipStream_t);
+
 template <typename T>
 hipError_t launch_spmv(const SpmvDesc* d, int nd, int nblocks, int group, hipStream_t s) {
   if (nblocks <= 0) return hipSuccess;

@@ -33,10 +33,10 @@ def test_autotune_keeps_results_and_caches(tmp_path):
     assert i1.iterations == i0.iterations and np.linalg.norm(x1 - x0) <= 1e-10 * np.linalg.norm(x0)
     x1b, _ = s.solve(b)
     assert np.array_equal(x1, x1b)  # a fixed shape is deterministic
-    for g in (4, 8, 32, 64):
+    for g in (0, 4, 8, 32, 64):  # 0: level operators in sliced ELL layout
         d = dict(t)
         d["spmv_lanes"] = [g] * 8
-        d["pt_lanes"] = [g] * 8
+        d["pt_lanes"] = [g or 16] * 8
         d["krylov_lanes"] = g
         d["ras_groups"] = [256] * 8
         h.set_tuning(d)
@@ -101,8 +101,8 @@ def test_blocks_per_work_item_same_bits(precision):
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_batch_of_differently_tuned_hierarchies_same_bits(precision):
     """Systems whose hierarchies carry different lanes-per-row choices (which
-    fix the summation order) keep their own order inside one batch: every
-    slot equals its solve alone, bitwise."""
+    fix the summation order; 0 = sliced ELL) keep their own order inside one
+    batch: every slot equals its solve alone, bitwise."""
     import torch
 
     if not torch.cuda.is_available():
@@ -111,14 +111,14 @@ def test_batch_of_differently_tuned_hierarchies_same_bits(precision):
 
     prec = nnms.MIXED if precision == "mixed" else nnms.FP64
     keep, systems, bs, alone = [], [], [], []
-    for n, g, seed in ((14, 4, 11), (12, 64, 21), (14, 16, 31)):
+    for n, g, seed in ((14, 4, 11), (12, 64, 21), (14, 0, 31)):
         pb = W.Problem("t", W.make_hierarchy([n, n // 2, 3], [seed, seed + 1, seed + 2]), [4, 2],
                        W.kappa_draw(204, seed))
         ms = [nnms.Mesh.from_workload(m) for m in pb.meshes]
         h = nnms.Hierarchy(ms, pb.nparts, precision=prec)
         d = h.get_tuning()
         d["spmv_lanes"] = [g] * 8
-        d["pt_lanes"] = [64 // g * 4 if g < 16 else 8] * 8
+        d["pt_lanes"] = [64 // g * 4 if 0 < g < 16 else 8] * 8
         d["krylov_lanes"] = g
         h.set_tuning(d)
         s = nnms.System(h, pb.kappa)
