@@ -81,6 +81,19 @@ def spmv_bytes(h, level, s_bytes):
     return float(li.nnz * (4 + s_bytes) + 4 * (li.nv + 1) + 3 * li.nv * s_bytes)
 
 
+def prolong_bytes(h, level, s_bytes):
+    """z_f += P z_c: four (index, weight) pairs per fine row, the coarse
+    vector once, the fine vector read and written."""
+    nf, nc = h.level_info(level).nv, h.level_info(level + 1).nv
+    return float(nf * (16 + 4 * s_bytes) + nc * s_bytes + 2 * nf * s_bytes)
+
+
+def restrict_bytes(h, level, s_bytes):
+    """r_c = P^T t: the CSR of P^T over coarse rows, t once, r_c written."""
+    li, lc = h.level_info(level), h.level_info(level + 1)
+    return float(li.p_nnz * (4 + s_bytes) + 4 * (lc.nv + 1) + (li.nv + lc.nv) * s_bytes)
+
+
 def cpu_baseline(pb, seconds_cap=60.0):
     """The FP64 oracle (NumPy/SciPy, LAPACK) on the host cores: setup once,
     then one full solve of the same problem; solves/s = 1 / solve time."""
@@ -201,8 +214,14 @@ def run_serving(args):
             h = hier[n]
             msr = sample.time_kernel(1, 0, reps=20)
             mss = sample.time_kernel(0, 0, reps=5)
+            msp = sample.time_kernel(2, 0, reps=20)
+            msq = sample.time_kernel(3, 0, reps=20)
             kern[f"{n}^3"] = {"residual_l0_ms": round(msr, 4),
                               "residual_l0_GBs": round(spmv_bytes(h, 0, sb) / (msr * 1e-3) / 1e9, 1),
+                              "prolong_l0_ms": round(msp, 4),
+                              "prolong_l0_GBs": round(prolong_bytes(h, 0, sb) / (msp * 1e-3) / 1e9, 1),
+                              "restrict_l0_ms": round(msq, 4),
+                              "restrict_l0_GBs": round(restrict_bytes(h, 0, sb) / (msq * 1e-3) / 1e9, 1),
                               "smoother_l0_ms": round(mss, 4),
                               "smoother_l0_GBs": round(ras_bytes(h, 0, sb) / (mss * 1e-3) / 1e9, 1)}
             sample.destroy()
