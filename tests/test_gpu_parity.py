@@ -238,3 +238,24 @@ def test_factors_reproduce_subdomain_matrices(case, precision, request):
         for p in range(len(sets)):
             lu, il = g.s.factor(l, p)
             assert np.array_equal(lu, before[p][0]) and np.array_equal(il, before[p][1]), (l, p)
+
+
+def test_iterations_roughly_flat_in_subdomain_count():
+    """The multilevel preconditioner's iteration count stays roughly flat as
+    the fine level is split into more subdomains (the soft trend of the
+    paper's scaling tables), while each solve reaches the tolerance."""
+    nnms = _gpu()
+    meshes = [W.kuhn_cube(32, 301), W.kuhn_cube(16, 302), W.kuhn_cube(7, 303)]
+    kappa = W.kappa_draw(204, 205)
+    its = {}
+    for np_ in (8, 16, 32, 64):
+        ms = [nnms.Mesh.from_workload(m) for m in meshes]
+        h = nnms.Hierarchy(ms, [np_])
+        s = nnms.System(h, kappa, 1.0)
+        x, info = s.solve(s.rhs())
+        assert info.status == 0 and info.relres <= 1e-8
+        its[np_] = info.iterations
+        s.destroy()
+        h.destroy()
+    _say(f"[gpu] iterations by fine-level subdomain count: {its}")
+    assert max(its.values()) - min(its.values()) <= 2, its
