@@ -21,7 +21,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {8: 78.6, 4: 157.3}  # dense FP64 / FP32 matrix peaks
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_ras_c2_{prec}_pmc.md")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_ras_cube48_{prec}_pmc.md")
 
 
 def source_hash():
@@ -119,7 +119,7 @@ def cpu_baseline(pb, seconds_cap=60.0):
 
 
 def run_batched(args):
-    """Config 4: parametric instances of uneven mesh and subdomain sizes (fine
+    """Batched parametric instances of uneven mesh and subdomain sizes (fine
     n in {24,32,40,48,64}, three non-nested levels each), mixed precision,
     solved together in one launch sequence per Arnoldi step (HIP graph) vs
     one after the other."""
@@ -127,7 +127,7 @@ def run_batched(args):
     import workloads as W
     from paper_2412_08981_amd import nnms
 
-    probs = W.config4(count=args.batch)
+    probs = W.batched_instances(count=args.batch)
     t0 = time.perf_counter()
     hs, ss, bs = [], [], []
     for pb in probs:
@@ -140,7 +140,7 @@ def run_batched(args):
     from paper_2412_08981_amd import autotune
     tuning = autotune.tune(ss[0], cache=args.tuning_cache)
     torch.cuda.synchronize()
-    log(f"[bench c4] {len(ss)} instances set up in {time.perf_counter() - t0:.1f} s, "
+    log(f"[bench batched] {len(ss)} instances set up in {time.perf_counter() - t0:.1f} s, "
         f"sizes {[int(pb.meshes[0].n) for pb in probs]}")
     xs, infos = nnms.solve_batch(ss, bs)  # warm-up (captures the graph)
     t = time.perf_counter()
@@ -176,7 +176,7 @@ def run_batched(args):
 
 
 def run_serving(args):
-    """Config 5: Poisson arrivals of parametric solve requests over three
+    """Serving: Poisson arrivals of parametric solve requests over three
     resident hierarchies (jittered 32^3, 64^3, 96^3 fine meshes, three levels
     each), device-memory budget admission, continuous batching.  The closed-
     loop capacity is measured first (requests all queued at t = 0), then an
@@ -188,15 +188,15 @@ def run_serving(args):
     from paper_2412_08981_amd.serve import Request, Server
 
     sizes = (32, 64, 96)
-    centres = W.config5_centres()
-    t, hs_choice, mus = W.config5_trace(nreq=args.requests, rate=1.0, sizes=sizes)
+    centres = W.serving_centres()
+    t, hs_choice, mus = W.serving_trace(nreq=args.requests, rate=1.0, sizes=sizes)
     res = {}
     for precision in ("mixed", "fp64"):
         prec = nnms.MIXED if precision == "mixed" else nnms.FP64
         t0 = time.perf_counter()
         hier, keep = {}, []
         for n in sizes:
-            meshes = W.config5_hierarchy(n)
+            meshes = W.served_hierarchy(n)
             ms = [nnms.Mesh.from_workload(m) for m in meshes]
             nps = [W.nparts_rule(m.nv) for m in meshes[:-1]]
             # PyTorch's caching allocator: releasing a finished request's
@@ -225,8 +225,8 @@ def run_serving(args):
                               "smoother_l0_ms": round(mss, 4),
                               "smoother_l0_GBs": round(ras_bytes(h, 0, sb) / (mss * 1e-3) / 1e9, 1)}
             sample.destroy()
-        log(f"[bench c5] {precision}: kernels {kern}")
-        log(f"[bench c5] {precision}: hierarchies set up in {time.perf_counter() - t0:.1f} s; bytes per request "
+        log(f"[bench serving] {precision}: kernels {kern}")
+        log(f"[bench serving] {precision}: hierarchies set up in {time.perf_counter() - t0:.1f} s; bytes per request "
             f"{ {n: round(h.system_bytes() / 2**30, 2) for n, h in hier.items()} } GiB")
 
         def make(ids, times):
@@ -251,7 +251,7 @@ def run_serving(args):
         st["capacity_run"] = {k: st_cap[k] for k in ("host_s_batch_forms", "host_s_steps", "host_s_results",
                                                      "numeric_setup_ms_mean", "p50_ms")}
         res[precision] = st
-        log(f"[bench c5] {precision}: {st}")
+        log(f"[bench serving] {precision}: {st}")
         del srv, hier, keep
         torch.cuda.synchronize()
     m = res["mixed"]
@@ -286,8 +286,9 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c4", "c5"],
-                    help="c2: the three-level 48^3 problem (default); c4: batched parametric instances; c5: serving")
+    ap.add_argument("--workload", default="cube48", choices=["cube48", "batched", "serving"],
+                    help="cube48: the three-level 48^3 problem (default); batched: ragged parametric instances; "
+                         "serving: continuous batching of Poisson arrivals")
     ap.add_argument("--requests", type=int, default=60, help="requests of the serving trace")
     ap.add_argument("--tuning-cache", default=os.path.join(ROOT, "paper_2412_08981_amd", "tuning.json"),
                     help="launch-shape cache (measured on first use)")
@@ -298,7 +299,7 @@ def main():
                     help="run the copy reference and the fine-level smoother a few times each (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark measures one GPU; --gpus must be 1"}))
         sys.exit(2)
 
     import torch
@@ -308,11 +309,11 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("no GPU visible")
     torch.cuda.init()
-    if args.workload == "c4":
+    if args.workload == "batched":
         return run_batched(args)
-    if args.workload == "c5":
+    if args.workload == "serving":
         return run_serving(args)
-    pb = W.config2(args.precision)
+    pb = W.cube48_three_level(args.precision)
     prec = nnms.MIXED if args.precision == "mixed" else nnms.FP64
     t0 = time.perf_counter()
     meshes = [nnms.Mesh.from_workload(m) for m in pb.meshes]

@@ -46,9 +46,9 @@ class Built:
 
 
 @pytest.fixture(scope="module")
-def c1():
-    _say("[gpu] building config 1 (16^3 / 6^3, fp64)")
-    pb = W.config1()
+def cube16():
+    _say("[gpu] building the two-level 16^3 / 6^3 problem (fp64)")
+    pb = W.cube16_two_level()
     return Built(pb), oprob.build(pb)
 
 
@@ -64,7 +64,7 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
-@pytest.mark.parametrize("case", ["c1", "tiny3"])
+@pytest.mark.parametrize("case", ["cube16", "tiny3"])
 def test_assembly_matches_oracle(case, request):
     g, o = request.getfixturevalue(case)
     for l in range(len(g.pb.meshes)):
@@ -78,7 +78,7 @@ def test_assembly_matches_oracle(case, request):
     assert np.abs(b - o.b).max() <= 1e-15 * np.abs(o.b).max() * 10
 
 
-@pytest.mark.parametrize("case", ["c1", "tiny3"])
+@pytest.mark.parametrize("case", ["cube16", "tiny3"])
 def test_operator_and_transfers(case, request):
     g, o = request.getfixturevalue(case)
     rng = np.random.default_rng(1)
@@ -93,7 +93,7 @@ def test_operator_and_transfers(case, request):
             assert _rel(g.s.apply_restrict(l, x), o.P[l].T @ x) <= 1e-14
 
 
-@pytest.mark.parametrize("case", ["c1", "tiny3"])
+@pytest.mark.parametrize("case", ["cube16", "tiny3"])
 def test_smoother_and_coarse_solve(case, request):
     g, o = request.getfixturevalue(case)
     rng = np.random.default_rng(2)
@@ -109,7 +109,7 @@ def test_smoother_and_coarse_solve(case, request):
         assert _rel(z, ref) <= 1e-9, (l, _rel(z, ref))
 
 
-@pytest.mark.parametrize("case", ["c1", "tiny3"])
+@pytest.mark.parametrize("case", ["cube16", "tiny3"])
 def test_vcycle_matches_oracle(case, request):
     g, o = request.getfixturevalue(case)
     r = np.random.default_rng(3).standard_normal(g.s.n[0])
@@ -117,7 +117,7 @@ def test_vcycle_matches_oracle(case, request):
     assert _rel(g.s.apply_vcycle(r), o.vcycle(r)) <= 1e-9
 
 
-@pytest.mark.parametrize("case", ["c1", "tiny3"])
+@pytest.mark.parametrize("case", ["cube16", "tiny3"])
 @pytest.mark.parametrize("graph", [True, False])
 def test_solve_matches_oracle(case, graph, request):
     g, o = request.getfixturevalue(case)
@@ -134,8 +134,8 @@ def test_solve_matches_oracle(case, graph, request):
     assert np.array_equal(x, x2) and info2.iterations == info.iterations
 
 
-def test_solve_edge_cases(c1):
-    g, o = c1
+def test_solve_edge_cases(cube16):
+    g, o = cube16
     x, info = g.s.solve(np.zeros(g.s.n[0]))
     assert info.iterations == 0 and np.all(x == 0)
     # entries at Dirichlet vertices are ignored
@@ -176,11 +176,11 @@ def test_mixed_precision_small():
     assert _rel(x, xs) <= 1e-7
 
 
-def test_batch_equals_alone(c1):
+def test_batch_equals_alone(cube16):
     nnms = _gpu()
-    g1, o1 = c1
+    g1, o1 = cube16
     x1, i1 = g1.s.solve(o1.b)
-    # a second system on the c1 hierarchy with another kappa
+    # a second system on the 16^3 hierarchy with another kappa
     s2 = nnms.System(g1.h, W.kappa_draw(7, 8), 1.0)
     x2, i2 = s2.solve(o1.b)
     xs, infos = nnms.solve_batch([g1.s, s2], [o1.b, o1.b])
@@ -207,10 +207,10 @@ def _rebuild_lu(lu, il):
     return Lm @ Um
 
 
-@pytest.mark.parametrize("case,precision", [("c1", "fp64"), ("tiny3", "fp64"), ("tiny3", "mixed")])
+@pytest.mark.parametrize("case,precision", [("cube16", "fp64"), ("tiny3", "fp64"), ("tiny3", "mixed")])
 def test_factors_reproduce_subdomain_matrices(case, precision, request):
     """Blocked LU (several block columns of 4 tiles and a ragged last one on
-    c1's 600-row subdomains): L U equals the oracle's A[S_p, S_p], the
+    the 16^3 problem's 600-row subdomains): L U equals the oracle's A[S_p, S_p], the
     padding block is the identity, and refactoring in place gives the same
     bits."""
     g, o = request.getfixturevalue(case)

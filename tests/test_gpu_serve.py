@@ -33,7 +33,7 @@ def test_serving_results_equal_alone(precision):
     from paper_2412_08981_amd.serve import Request, Server
 
     rng = np.random.default_rng(3)
-    centres = W.config5_centres()
+    centres = W.serving_centres()
     keys = list(hier)
     reqs = []
     t = 0.0
@@ -62,7 +62,7 @@ def test_oversized_request_is_rejected():
     small = min(hier, key=lambda k: hier[k].system_bytes())
     big = max(hier, key=lambda k: hier[k].system_bytes())
     budget = hier[small].system_bytes() * 1.01
-    kap = W.KappaField("loggauss", centres=W.config5_centres(), mu=np.zeros(8), width=0.02)
+    kap = W.KappaField("loggauss", centres=W.serving_centres(), mu=np.zeros(8), width=0.02)
     reqs = [Request(0, big, kap, 0.0), Request(1, small, kap, 0.0)]
     st = Server(hier, budget).run(reqs)
     assert reqs[0].status == "rejected" and reqs[1].status == "done"

@@ -31,10 +31,10 @@ def test_header_symbols_are_exported():
     assert declared <= set(nnms.EXPORTED) | {"nnms_mesh_destroy"}
 
 
-@pytest.mark.parametrize("cfg", ["c1", "tiny3"])
+@pytest.mark.parametrize("cfg", ["cube16", "tiny3"])
 def test_pattern_partition_transfer_match_oracle(cfg):
-    if cfg == "c1":
-        pb = W.config1()
+    if cfg == "cube16":
+        pb = W.cube16_two_level()
     else:
         pb = W.Problem("tiny3", [W.kuhn_cube(9, 1), W.kuhn_cube(5, 2), W.kuhn_cube(3, 3)], [4, 2], W.KappaField())
     ms, h = _host(pb)
@@ -69,7 +69,7 @@ def test_pattern_partition_transfer_match_oracle(cfg):
 
 
 def test_level_info_counts():
-    pb = W.config1()
+    pb = W.cube16_two_level()
     ms, h = _host(pb)
     li = h.level_info(0)
     assert (li.nv, li.nt, li.nnz) == (4913, 24576, 46941)
@@ -111,7 +111,7 @@ def test_point_location_error():
 
 
 def test_invalid_options():
-    pb = W.config1()
+    pb = W.cube16_two_level()
     ms = [nnms.Mesh.from_workload(m) for m in pb.meshes]
     with pytest.raises(nnms.NNMSError) as e:
         nnms.Hierarchy(ms, [6], device=False)  # not a power of two

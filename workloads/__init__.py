@@ -159,52 +159,52 @@ def make_hierarchy(ns: Sequence[int], seeds: Sequence[int]) -> List[Mesh]:
     return [kuhn_cube(n, s) for n, s in zip(ns, seeds)]
 
 
-def config1() -> Problem:
+def cube16_two_level() -> Problem:
     """Plain FP64, two levels: jittered 16^3 fine, independent jittered 6^3
     coarse, kappa = 1, f = 1, 8 subdomains."""
     meshes = make_hierarchy([16, 6], [101, 102])
-    return Problem("c1_16_6_fp64", meshes, [8], KappaField("const", 1.0))
+    return Problem("cube16_6_fp64", meshes, [8], KappaField("const", 1.0))
 
 
-def config2(precision: str = "fp64") -> Problem:
+def cube48_three_level(precision: str = "fp64") -> Problem:
     """Three levels 48^3 / 24^3 / 10^3, log-Gaussian kappa with 8 seeded
     centres, 64 subdomains on the fine level."""
     meshes = make_hierarchy([48, 24, 10], [201, 202, 203])
     kap = kappa_draw(204, 205)
     np1 = nparts_rule(meshes[1].nv)
-    name = "c2_48_24_10_fp64" if precision == "fp64" else "c3_48_24_10_mixed"
+    name = "cube48_24_10_fp64" if precision == "fp64" else "cube48_24_10_mixed"
     return Problem(name, meshes, [64, np1], kap, precision=precision)
 
 
-def config3() -> Problem:
-    return config2("mixed")
+def cube48_three_level_mixed() -> Problem:
+    return cube48_three_level("mixed")
 
 
-def config4_sizes(count: int = 32, seed: int = 400) -> np.ndarray:
+def batched_sizes(count: int = 32, seed: int = 400) -> np.ndarray:
     """Fine grid sizes of the batched instances, drawn from {24,32,40,48,64}."""
     return np.random.default_rng(seed).choice(np.array([24, 32, 40, 48, 64]), size=count)
 
 
-def config4(count: int = 32, precision: str = "mixed") -> List[Problem]:
+def batched_instances(count: int = 32, precision: str = "mixed") -> List[Problem]:
     """Batched parametric instances with uneven mesh and subdomain sizes."""
     out = []
-    sizes = config4_sizes(count)
+    sizes = batched_sizes(count)
     for i, n in enumerate(sizes):
         ns = coarse_sizes(int(n))
         meshes = make_hierarchy(ns, [4000 + 10 * i + l for l in range(3)])
         kap = kappa_draw(204, 4000 + 10 * i + 9)
         nps = [nparts_rule(m.nv) for m in meshes[:-1]]
-        out.append(Problem(f"c4_{i}_{n}", meshes, nps, kap, precision=precision))
+        out.append(Problem(f"batched_{i}_{n}", meshes, nps, kap, precision=precision))
     return out
 
 
-def config5_hierarchy(size: int) -> List[Mesh]:
+def served_hierarchy(size: int) -> List[Mesh]:
     """A resident serving hierarchy with fine grid 32, 64 or 96."""
     h = {32: 0, 64: 1, 96: 2}[size]
     return make_hierarchy(coarse_sizes(size), [5000 + 100 * h + l for l in range(3)])
 
 
-def config5_trace(nreq: int = 2000, rate: float = 10.0, sizes=(32, 64, 96)):
+def serving_trace(nreq: int = 2000, rate: float = 10.0, sizes=(32, 64, 96)):
     """Poisson arrivals (exponential gaps, rate per second), hierarchy choice
     uniform, kappa amplitudes per request.  Returns (t_arrival[s], hier_size,
     mu[nreq,8])."""
@@ -215,7 +215,7 @@ def config5_trace(nreq: int = 2000, rate: float = 10.0, sizes=(32, 64, 96)):
     return t, hs, mus
 
 
-def config5_centres() -> np.ndarray:
+def serving_centres() -> np.ndarray:
     return np.random.default_rng(204).uniform(0.0, 1.0, size=(8, 3))
 
 
