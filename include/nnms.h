@@ -246,15 +246,18 @@ nnms_status nnms_time_kernel(nnms_system* s, int32_t kind, int32_t level, int32_
  * batch) and takes the smoother's launch shapes from its first system's
  * hierarchy (they change no arithmetic).
  *   spmv_lanes[l]  lanes of a wave per CSR row of level l's operator (4..64),
- *                  or 0: the operator in sliced ELL layout (64-row slices,
- *                  one lane per row)
- *   pt_lanes[l]    lanes per row of P_l^T (4..64)
+ *                  or the operator in sliced ELL layout (64-row slices, one
+ *                  lane per row, slices column-major): 0 = one wave per
+ *                  slice, 1 = the slice's entries split over the four waves
+ *                  of a work-group and the four partial sums of a row added
+ *                  in a fixed order
+ *   pt_lanes[l]    the same choice for P_l^T (4..64, 0 or 1)
  *   ras_groups[l]  work-groups of the persistent triangular-solve kernel on
  *                  level l (0 = 4 per compute unit)
  *   ras_blocks[l]  64-row blocks per work item of that kernel (1, 2 or 4):
  *                  blocks inside a work item are substituted in order by one
  *                  work-group, only work items hand results to each other
- *   krylov_lanes   lanes per row of the outer FP64 operator (0: sliced ELL)
+ *   krylov_lanes   the same choice for the outer FP64 operator
  * nnms_autotune times the candidates of every entry on the system's own
  * data with HIP events (reps launches each), keeps the fastest, stores the
  * result in the system's hierarchy and in *out (may be NULL).

@@ -103,6 +103,9 @@ struct DevLevel {
   int32_t *pt_rp = nullptr, *pt_col = nullptr;
   double* pt_w64 = nullptr;
   float* pt_w32 = nullptr;
+  int32_t *pts_off = nullptr, *pts_col = nullptr;  // P^T in sliced ELL layout
+  double* pts_w64 = nullptr;
+  float* pts_w32 = nullptr;
 };
 
 }  // namespace nnms
@@ -172,10 +175,13 @@ static int ras_grid_default() {
   return g;
 }
 
-// blocks of one SpMV launch: G lanes per CSR row, or G = 0 for the sliced ELL
-// layout (four 64-row slices per block)
+// blocks of one SpMV launch: G lanes per CSR row, or the sliced ELL layout:
+// G = 0 four 64-row slices per block, G = 1 one slice per block (its steps
+// split over the four waves)
+static bool is_sell(int G) { return G == 0 || G == 1; }
 static int spmv_blocks(int64_t n, int G) {
   if (G == 0) return int((n + 255) / 256);
+  if (G == 1) return int((n + 63) / 64);
   return int((n + (256 / G) - 1) / (256 / G));
 }
 static int vec_blocks(int64_t n) { return int((n + VBLK - 1) / VBLK); }
@@ -218,7 +224,8 @@ static std::vector<SpmvGroup> spmv_groups(Arena& mem, const std::vector<std::pai
 template <typename T>
 static hipError_t launch_spmv_groups(const std::vector<SpmvGroup>& gs, hipStream_t s) {
   for (const SpmvGroup& G : gs) {
-    const hipError_t e = G.g == 0 ? launch_sell<T>(G.d, G.nd, G.blocks, s) : launch_spmv<T>(G.d, G.nd, G.blocks, G.g, s);
+    const hipError_t e = is_sell(G.g) ? launch_sell<T>(G.d, G.nd, G.blocks, G.g, s)
+                                      : launch_spmv<T>(G.d, G.nd, G.blocks, G.g, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -377,7 +384,7 @@ static void build_plan(Plan& P, const std::vector<nnms_system*>& sys, bool with_
       const KState* st = with_state ? x->st : nullptr;
       SpmvDesc d{};
       const int ga = x->h->tune.spmv_lanes[l];
-      if (ga == 0)
+      if (is_sell(ga))
         d.rp = dl.sell_off, d.col = dl.sell_col, d.val = ell_of<T>(sl);
       else
         d.rp = dl.rp, d.col = dl.col, d.val = val_of<T>(sl);
@@ -385,10 +392,16 @@ static void build_plan(Plan& P, const std::vector<nnms_system*>& sys, bool with_
       d.st = st, d.n = int(hl.nv), d.when = WHEN_RUNNING;
       res.emplace_back(ga, d);
       SpmvDesc e{};
-      e.rp = dl.pt_rp, e.col = dl.pt_col;
-      e.val = std::is_same<T, float>::value ? (const void*)dl.pt_w32 : (const void*)dl.pt_w64;
+      const int gp = x->h->tune.pt_lanes[l];
+      if (is_sell(gp)) {
+        e.rp = dl.pts_off, e.col = dl.pts_col;
+        e.val = std::is_same<T, float>::value ? (const void*)dl.pts_w32 : (const void*)dl.pts_w64;
+      } else {
+        e.rp = dl.pt_rp, e.col = dl.pt_col;
+        e.val = std::is_same<T, float>::value ? (const void*)dl.pt_w32 : (const void*)dl.pt_w64;
+      }
       e.x = sl.t, e.r = nullptr, e.y = sc.r, e.st = st, e.n = int(hc.nv), e.when = WHEN_RUNNING;
-      rst.emplace_back(x->h->tune.pt_lanes[l], e);
+      rst.emplace_back(gp, e);
       ProlongDesc pd{};
       pd.idx = dl.p_idx;
       pd.w = std::is_same<T, float>::value ? (const void*)dl.p_w32 : (const void*)dl.p_w64;
@@ -423,7 +436,7 @@ static void build_plan(Plan& P, const std::vector<nnms_system*>& sys, bool with_
       P.kd_host.push_back(k);
       kb += x->nblk;
       SpmvDesc d{};
-      if (gw == 0)
+      if (is_sell(gw))
         d.rp = d0.sell_off, d.col = d0.sell_col, d.val = x->lev[0].ell64;
       else
         d.rp = d0.rp, d.col = d0.col, d.val = x->lev[0].val64;
@@ -687,6 +700,10 @@ extern "C" nnms_status nnms_hierarchy_setup(const nnms_mesh* const* levels, int3
       d.pt_col = A.upload(hl.pt_col, s);
       d.pt_w64 = A.upload(hl.pt_w, s);
       d.pt_w32 = A.upload(convert<double, float>(hl.pt_w), s);
+      d.pts_off = A.upload(hl.pts_off, s);
+      d.pts_col = A.upload(hl.pts_col, s);
+      d.pts_w64 = A.upload(hl.pts_w, s);
+      d.pts_w32 = A.upload(convert<double, float>(hl.pts_w), s);
     }
   }
   HIP_CHECK(hipStreamSynchronize(s));
@@ -1377,8 +1394,7 @@ extern "C" nnms_status nnms_system_factor(const nnms_system* s, int32_t level, i
 // ---------------------------------------------------------------------------
 // launch-shape tuning
 // ---------------------------------------------------------------------------
-static bool lanes_ok(int g) { return g == 4 || g == 8 || g == 16 || g == 32 || g == 64; }
-static bool op_lanes_ok(int g) { return g == 0 || lanes_ok(g); }  // 0: sliced ELL
+static bool lanes_ok(int g) { return is_sell(g) || g == 4 || g == 8 || g == 16 || g == 32 || g == 64; }
 
 extern "C" nnms_status nnms_hierarchy_get_tuning(const nnms_hierarchy* h, nnms_tuning* out) {
   ABI_BEGIN
@@ -1392,10 +1408,10 @@ extern "C" nnms_status nnms_hierarchy_set_tuning(nnms_hierarchy* h, const nnms_t
   ABI_BEGIN
   if (!h || !t) throw Error(NNMS_ERR_INVALID_ARG, "null argument");
   for (int l = 0; l < NNMS_MAX_LEVELS; ++l)
-    if (!op_lanes_ok(t->spmv_lanes[l]) || !lanes_ok(t->pt_lanes[l]) || t->ras_groups[l] < 0 || t->ras_groups[l] > 65536 ||
+    if (!lanes_ok(t->spmv_lanes[l]) || !lanes_ok(t->pt_lanes[l]) || t->ras_groups[l] < 0 || t->ras_groups[l] > 65536 ||
         !(t->ras_blocks[l] == 1 || t->ras_blocks[l] == 2 || t->ras_blocks[l] == 4))
       throw Error(NNMS_ERR_INVALID_ARG, "bad tuning entry");
-  if (!op_lanes_ok(t->krylov_lanes)) throw Error(NNMS_ERR_INVALID_ARG, "bad tuning entry");
+  if (!lanes_ok(t->krylov_lanes)) throw Error(NNMS_ERR_INVALID_ARG, "bad tuning entry");
   h->tune = *t;
   h->tune.tuned = 1;
   return NNMS_OK;
@@ -1430,18 +1446,18 @@ extern "C" nnms_status nnms_autotune(nnms_system* s, int32_t reps, nnms_tuning* 
   hipStream_t st = P.stream;
   Arena tmp(h->has_alloc ? &h->alloc : nullptr);
   const int lanes[] = {4, 8, 16, 32, 64};
-  // fastest lanes per CSR row; with the sliced ELL arrays given, 0 (that
-  // layout) is a candidate too
+  // fastest lanes per CSR row; with the sliced ELL arrays given, 0 and 1
+  // (that layout, one wave per slice or four) are candidates too
   auto spmv_best = [&](const int32_t* rp, const int32_t* col, const void* val, const void* x, const void* r, void* y,
                        int64_t n, bool dbl, const int32_t* soff = nullptr, const int32_t* scol = nullptr,
                        const void* sval = nullptr) {
     int best = 16;
     double bt = 1e30;
     std::vector<int> cand(std::begin(lanes), std::end(lanes));
-    if (soff) cand.push_back(0);
+    if (soff) cand.push_back(0), cand.push_back(1);
     for (int g : cand) {
       SpmvDesc d{};
-      if (g == 0)
+      if (is_sell(g))
         d.rp = soff, d.col = scol, d.val = sval;
       else
         d.rp = rp, d.col = col, d.val = val;
@@ -1450,11 +1466,11 @@ extern "C" nnms_status nnms_autotune(nnms_system* s, int32_t reps, nnms_tuning* 
       SpmvDesc* dd = tmp.upload(v, st);
       const int nb = spmv_blocks(n, g);
       double ms = time_ms(st, reps, [&]() {
-        if (g == 0) {
+        if (is_sell(g)) {
           if (dbl)
-            HIP_CHECK(launch_sell<double>(dd, 1, nb, st));
+            HIP_CHECK(launch_sell<double>(dd, 1, nb, g, st));
           else
-            HIP_CHECK(launch_sell<float>(dd, 1, nb, st));
+            HIP_CHECK(launch_sell<float>(dd, 1, nb, g, st));
         } else if (dbl) {
           HIP_CHECK(launch_spmv<double>(dd, 1, nb, g, st));
         } else {
@@ -1502,7 +1518,9 @@ extern "C" nnms_status nnms_autotune(nnms_system* s, int32_t reps, nnms_tuning* 
     const void* ell = f64 ? (const void*)sl.ell64 : (const void*)sl.ell32;
     t.spmv_lanes[l] = spmv_best(dl.rp, dl.col, val, sl.z, sl.r, sl.t, n, f64, dl.sell_off, dl.sell_col, ell);
     const void* ptw = f64 ? (const void*)dl.pt_w64 : (const void*)dl.pt_w32;
-    t.pt_lanes[l] = spmv_best(dl.pt_rp, dl.pt_col, ptw, sl.t, nullptr, s->lev[l + 1].r, nc, f64);
+    const void* ptsw = f64 ? (const void*)dl.pts_w64 : (const void*)dl.pts_w32;
+    t.pt_lanes[l] = spmv_best(dl.pt_rp, dl.pt_col, ptw, sl.t, nullptr, s->lev[l + 1].r, nc, f64, dl.pts_off,
+                              dl.pts_col, ptsw);
     ras_best(l, false, t.ras_groups[l], t.ras_blocks[l]);
   }
   ras_best(L - 1, true, t.ras_groups[L - 1], t.ras_blocks[L - 1]);

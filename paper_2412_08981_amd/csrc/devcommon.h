@@ -21,6 +21,16 @@ __device__ __forceinline__ const GLOBAL T* gptr(const T* p) {
   return (const GLOBAL T*)p;
 }
 
+// Work-groups of a launch are handed to the eight XCDs in turn (block b to
+// XCD b mod 8), and every XCD has its own L2.  This maps the hardware block
+// index to a logical one so that each XCD works through one contiguous range
+// of logical blocks (a bijection on [0, nb)): neighbouring rows, whose
+// gathers touch neighbouring parts of the input vector, share an L2.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7, x = b & 7;
+  return x * q + min(x, r) + (b >> 3);
+}
+
 // Index of the descriptor whose first block is the largest one <= b.
 template <typename D>
 __device__ __forceinline__ int find_desc(const D* d, int nd, int b) {

@@ -123,33 +123,38 @@ static void rcb(const HostLevel& lv, std::vector<int32_t>& ids, int nparts, int 
   rcb(lv, hi, nparts / 2, depth + 1, out);
 }
 
-void build_sell(HostLevel& lv) {
-  const int64_t nv = lv.nv, ns = (nv + 63) / 64;
-  lv.sell_off.assign(ns + 1, 0);
+void build_sell_layout(const std::vector<int32_t>& rp, const std::vector<int32_t>& col, int64_t nrows,
+                       std::vector<int32_t>& off, std::vector<int32_t>& scol, std::vector<int32_t>& src) {
+  const int64_t ns = (nrows + 63) / 64;
+  off.assign(ns + 1, 0);
   for (int64_t sl = 0; sl < ns; ++sl) {
     int32_t w = 0;
-    for (int64_t i = sl * 64; i < std::min(nv, sl * 64 + 64); ++i) w = std::max(w, lv.rp[i + 1] - lv.rp[i]);
-    if (int64_t(lv.sell_off[sl]) + int64_t(w) * 64 > INT32_MAX) throw Error(NNMS_ERR_INVALID_ARG, "level too large for 32-bit indices");
-    lv.sell_off[sl + 1] = lv.sell_off[sl] + w * 64;
+    for (int64_t i = sl * 64; i < std::min(nrows, sl * 64 + 64); ++i) w = std::max(w, rp[i + 1] - rp[i]);
+    if (int64_t(off[sl]) + int64_t(w) * 64 > INT32_MAX) throw Error(NNMS_ERR_INVALID_ARG, "level too large for 32-bit indices");
+    off[sl + 1] = off[sl] + w * 64;
   }
-  lv.sell_col.assign(lv.sell_off[ns], 0);
-  lv.sell_src.assign(lv.sell_off[ns], -1);
+  scol.assign(off[ns], 0);
+  src.assign(off[ns], -1);
   for (int64_t sl = 0; sl < ns; ++sl) {
-    const int32_t w = (lv.sell_off[sl + 1] - lv.sell_off[sl]) / 64;
+    const int32_t w = (off[sl + 1] - off[sl]) / 64;
     for (int l = 0; l < 64; ++l) {
       const int64_t i = sl * 64 + l;
       for (int32_t k = 0; k < w; ++k) {
-        const int64_t e = lv.sell_off[sl] + int64_t(k) * 64 + l;
-        if (i < nv && lv.rp[i] + k < lv.rp[i + 1]) {
-          lv.sell_col[e] = lv.col[lv.rp[i] + k];
-          lv.sell_src[e] = lv.rp[i] + k;
+        const int64_t e = off[sl] + int64_t(k) * 64 + l;
+        if (i < nrows && rp[i] + k < rp[i + 1]) {
+          scol[e] = col[rp[i] + k];
+          src[e] = rp[i] + k;
         } else {
-          lv.sell_col[e] = i < nv ? int32_t(i) : 0;  // padding: value 0 times an existing entry of x
+          // padding: value 0 times an entry of x the row already reads (the
+          // same cache line), or x[0] for a row without entries
+          scol[e] = (i < nrows && rp[i + 1] > rp[i]) ? col[rp[i + 1] - 1] : 0;
         }
       }
     }
   }
 }
+
+void build_sell(HostLevel& lv) { build_sell_layout(lv.rp, lv.col, lv.nv, lv.sell_off, lv.sell_col, lv.sell_src); }
 
 void build_partition(HostLevel& lv, int nparts, int overlap, bool direct) {
   const int64_t nv = lv.nv;
@@ -367,6 +372,11 @@ void build_transfer(HostLevel& fine, const HostLevel& coarse) {
       fine.pt_w[fill[c]++] = fine.p_w[v * 4 + a];
     }
   }
+  std::vector<int32_t> src;
+  build_sell_layout(fine.pt_rp, fine.pt_col, nc, fine.pts_off, fine.pts_col, src);
+  fine.pts_w.assign(src.size(), 0.0);
+  for (size_t e = 0; e < src.size(); ++e)
+    if (src[e] >= 0) fine.pts_w[e] = fine.pt_w[src[e]];
 }
 
 }  // namespace nnms

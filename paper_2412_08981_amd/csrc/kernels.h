@@ -10,9 +10,11 @@ namespace nnms {
 // sparse.hip
 template <typename T>
 hipError_t launch_spmv(const SpmvDesc* d, int nd, int nblocks, int group, hipStream_t s);
-// sliced-ELL level operators (nblocks = ceil(rows / 256) per descriptor)
+// sliced-ELL matrices: split = 0, four slices per block (nblocks =
+// ceil(rows / 256) per descriptor); split = 1, one slice per block with its
+// steps split over the four waves (nblocks = ceil(rows / 64))
 template <typename T>
-hipError_t launch_sell(const SpmvDesc* d, int nd, int nblocks, hipStream_t s);
+hipError_t launch_sell(const SpmvDesc* d, int nd, int nblocks, int split, hipStream_t s);
 template <typename T>
 hipError_t launch_gather_ell(const int32_t* src, const double* csr, T* ell, int64_t n, hipStream_t s);
 template <typename T>

@@ -40,7 +40,8 @@ struct HostLevel {
   std::vector<int32_t> vptr, vitem;
   // the same pattern as sliced ELL: 64-row slices stored column-major (entry
   // k of row 64s + l at sell_off[s] + 64k + l), slice width = its longest
-  // row; sell_src = CSR slot of every entry, -1 for padding (column = own row)
+  // row; sell_src = CSR slot of every entry, -1 for padding (value 0, column
+  // = the row's last column)
   std::vector<int32_t> sell_off;  // slices + 1
   std::vector<int32_t> sell_col, sell_src;
 
@@ -64,6 +65,9 @@ struct HostLevel {
   std::vector<double> p_w;          // nv*4
   std::vector<int32_t> pt_rp, pt_col;  // rows: coarse vertices
   std::vector<double> pt_w;
+  // P_l^T in the sliced ELL layout (same rules as the operator's)
+  std::vector<int32_t> pts_off, pts_col;
+  std::vector<double> pts_w;
   int64_t ncoarse = 0;
 };
 
@@ -75,6 +79,11 @@ struct HostHierarchy {
 
 // host setup steps
 void build_pattern(HostLevel& lv);
+// sliced ELL layout of a CSR matrix with nrows rows: 64-row slices stored
+// column-major, slice width = its longest row; src = CSR slot of every
+// entry, -1 for padding
+void build_sell_layout(const std::vector<int32_t>& rp, const std::vector<int32_t>& col, int64_t nrows,
+                       std::vector<int32_t>& off, std::vector<int32_t>& scol, std::vector<int32_t>& src);
 void build_sell(HostLevel& lv);
 void build_partition(HostLevel& lv, int nparts, int overlap, bool direct);
 void build_transfer(HostLevel& fine, const HostLevel& coarse);

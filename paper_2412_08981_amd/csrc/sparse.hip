@@ -13,19 +13,20 @@ namespace nnms {
 
 template <typename T, int G>
 __global__ __launch_bounds__(256) void k_spmv(const SpmvDesc* __restrict__ d, int nd) {
-  const int b = blockIdx.x;
+  const int b = xcd_block(blockIdx.x, gridDim.x);
   const SpmvDesc D = d[find_desc(d, nd, b)];
   if (!slot_active(D.st, D.when)) return;
   const int lb = b - D.blk0;
   const int row = lb * (256 / G) + int(threadIdx.x) / G;
   const int lane = threadIdx.x % G;
-  const T* __restrict__ x = (const T*)D.x;
+  const GLOBAL T* __restrict__ x = gptr((const T*)D.x);
   if (D.x_jstride) x += int64_t(D.st->j) * D.x_jstride;
-  const T* __restrict__ val = (const T*)D.val;
+  const GLOBAL T* __restrict__ val = gptr((const T*)D.val);
+  const GLOBAL int32_t* __restrict__ col = gptr(D.col);
   T sum = 0;
   if (row < D.n) {
-    const int s = D.rp[row], e = D.rp[row + 1];
-    for (int k = s + lane; k < e; k += G) sum += val[k] * x[D.col[k]];
+    const int s = gptr(D.rp)[row], e = gptr(D.rp)[row + 1];
+    for (int k = s + lane; k < e; k += G) sum += val[k] * x[col[k]];
   }
 #pragma unroll
   for (int off = G / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, G);
@@ -44,6 +45,17 @@ __global__ __launch_bounds__(256) void k_spmv(const SpmvDesc* __restrict__ d, in
   }
 }
 
+// One lane's row of a sliced-ELL slice: the sum of val[64k] * x[col[64k]]
+// over the steps k = k0, k0 + ks, ... < w, accumulated in that order.
+template <typename T>
+__device__ __forceinline__ T sell_row(const GLOBAL int32_t* col, const GLOBAL T* val, const GLOBAL T* x, int k0,
+                                      int ks, int w) {
+  T sum = 0;
+#pragma unroll 4
+  for (int k = k0; k < w; k += ks) sum += val[64 * k] * x[col[64 * k]];
+  return sum;
+}
+
 // Sliced ELL (the level operators): one wave per 64-row slice, lane = row,
 // the slice's columns stored column-major, so every load of a step is 64
 // consecutive values; no row pointers, no cross-lane reduction, each row
@@ -51,22 +63,19 @@ __global__ __launch_bounds__(256) void k_spmv(const SpmvDesc* __restrict__ d, in
 // rp = slice offsets, col / val = the ELL arrays; 4 slices per block.
 template <typename T>
 __global__ __launch_bounds__(256) void k_sell(const SpmvDesc* __restrict__ d, int nd) {
-  const int b = blockIdx.x;
+  const int b = xcd_block(blockIdx.x, gridDim.x);
   const SpmvDesc D = d[find_desc(d, nd, b)];
   if (!slot_active(D.st, D.when)) return;
   const int lb = b - D.blk0;
   const int lane = threadIdx.x & 63;
   const int slice = lb * 4 + (threadIdx.x >> 6);
   const int row = slice * 64 + lane;
-  const T* __restrict__ x = (const T*)D.x;
+  const GLOBAL T* __restrict__ x = gptr((const T*)D.x);
   if (D.x_jstride) x += int64_t(D.st->j) * D.x_jstride;
   T sum = 0;
   if (slice * 64 < D.n) {
-    const int e0 = D.rp[slice], w = (D.rp[slice + 1] - e0) >> 6;
-    const GLOBAL int32_t* col = gptr(D.col) + e0 + lane;
-    const GLOBAL T* val = gptr((const T*)D.val) + e0 + lane;
-#pragma unroll 4
-    for (int k = 0; k < w; ++k) sum += val[64 * k] * x[col[64 * k]];
+    const int e0 = gptr(D.rp)[slice], w = (gptr(D.rp)[slice + 1] - e0) >> 6;
+    sum = sell_row<T>(gptr(D.col) + e0 + lane, gptr((const T*)D.val) + e0 + lane, x, 0, 1, w);
   }
   T out = 0;
   if (row < D.n) {
@@ -83,6 +92,43 @@ __global__ __launch_bounds__(256) void k_sell(const SpmvDesc* __restrict__ d, in
   }
 }
 
+// Sliced ELL with one slice per block: wave w of the four takes the slice's
+// steps w, w + 4, ..., and the four partial sums of a row are added in a
+// fixed order.  Four times the waves of k_sell with a quarter of the steps
+// each, for matrices with few rows of many entries (P^T: ~30 per row),
+// where one wave per slice leaves too few loads in flight.
+template <typename T>
+__global__ __launch_bounds__(256) void k_sell4(const SpmvDesc* __restrict__ d, int nd) {
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const SpmvDesc D = d[find_desc(d, nd, b)];
+  if (!slot_active(D.st, D.when)) return;
+  const int slice = b - D.blk0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row = slice * 64 + lane;
+  const GLOBAL T* __restrict__ x = gptr((const T*)D.x);
+  if (D.x_jstride) x += int64_t(D.st->j) * D.x_jstride;
+  T sum;
+  {
+    const int e0 = gptr(D.rp)[slice], w = (gptr(D.rp)[slice + 1] - e0) >> 6;
+    sum = sell_row<T>(gptr(D.col) + e0 + lane, gptr((const T*)D.val) + e0 + lane, x, wave, 4, w);
+  }
+  __shared__ T part[4][64];
+  part[wave][lane] = sum;
+  __syncthreads();
+  if (wave == 0) {
+    const T s = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+    T out = 0;
+    if (row < D.n) {
+      out = D.r ? ((const T*)D.r)[row] - s : s;
+      ((T*)D.y)[row] = out;
+    }
+    if (D.nrm) {  // partial sum of squares of this slice's outputs (fixed order)
+      const double q = wave_sum(row < D.n ? double(out) * double(out) : 0.0);
+      if (lane == 0) D.nrm[slice] = q;
+    }
+  }
+}
+
 // ell[e] = csr[src[e]] (0 for padding, src < 0)
 template <typename T>
 __global__ __launch_bounds__(256) void k_gather_ell(const int32_t* __restrict__ src, const double* __restrict__ csr,
@@ -95,9 +141,12 @@ __global__ __launch_bounds__(256) void k_gather_ell(const int32_t* __restrict__ 
 }
 
 template <typename T>
-hipError_t launch_sell(const SpmvDesc* d, int nd, int nblocks, hipStream_t s) {
+hipError_t launch_sell(const SpmvDesc* d, int nd, int nblocks, int split, hipStream_t s) {
   if (nd <= 0 || nblocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_sell<T>), dim3(nblocks), dim3(256), 0, s, d, nd);
+  if (split)
+    hipLaunchKernelGGL((k_sell4<T>), dim3(nblocks), dim3(256), 0, s, d, nd);
+  else
+    hipLaunchKernelGGL((k_sell<T>), dim3(nblocks), dim3(256), 0, s, d, nd);
   return hipGetLastError();
 }
 
@@ -108,8 +157,8 @@ hipError_t launch_gather_ell(const int32_t* src, const double* csr, T* ell, int6
   return hipGetLastError();
 }
 
-template hipError_t launch_sell<double>(const SpmvDesc*, int, int, hipStream_t);
-template hipError_t launch_sell<float>(const SpmvDesc*, int, int, hipStream_t);
+template hipError_t launch_sell<double>(const SpmvDesc*, int, int, int, hipStream_t);
+template hipError_t launch_sell<float>(const SpmvDesc*, int, int, int, hipStream_t);
 template hipError_t launch_gather_ell<double>(const int32_t*, const double*, double*, int64_t, hipStream_t);
 template hipError_t launch_gather_ell<float>(const int32_t*, const double*, float*, int64_t, hipStream_t);
 
@@ -130,16 +179,17 @@ hipError_t launch_spmv(const SpmvDesc* d, int nd, int nblocks, int group, hipStr
 // zf[i] += sum_a w[4i+a] zc[idx[4i+a]]: coarse-to-fine barycentric transfer.
 template <typename T>
 __global__ __launch_bounds__(256) void k_prolong(const ProlongDesc* __restrict__ d, int nd) {
-  const int b = blockIdx.x;
+  const int b = xcd_block(blockIdx.x, gridDim.x);
   const ProlongDesc D = d[find_desc(d, nd, b)];
   if (!slot_active(D.st, WHEN_RUNNING)) return;
   const int i = (b - D.blk0) * 256 + threadIdx.x;
   if (i >= D.n) return;
   const int4 id = ((const int4*)D.idx)[i];
-  const T* w = (const T*)D.w + int64_t(i) * 4;
-  const T* zc = (const T*)D.zc;
+  const GLOBAL T* w = gptr((const T*)D.w) + int64_t(i) * 4;
+  const GLOBAL T* zc = gptr((const T*)D.zc);
   T acc = w[0] * zc[id.x] + w[1] * zc[id.y] + w[2] * zc[id.z] + w[3] * zc[id.w];
-  ((T*)D.zf)[i] += acc;
+  GLOBAL T* zf = gptr((T*)D.zf);
+  zf[i] += acc;
 }
 
 template <typename T>

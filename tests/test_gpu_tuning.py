@@ -27,16 +27,17 @@ def test_autotune_keeps_results_and_caches(tmp_path):
     x0, i0 = s.solve(b)
     cache = str(tmp_path / "tuning.json")
     t = autotune.tune(s, cache=cache, reps=3)
-    assert t["tuned"] == 1 and t["spmv_lanes"][0] in (4, 8, 16, 32, 64)
+    assert t["tuned"] == 1 and t["spmv_lanes"][0] in (0, 1, 4, 8, 16, 32, 64)
+    assert t["pt_lanes"][0] in (0, 1, 4, 8, 16, 32, 64)
     assert h.get_tuning() == t
     x1, i1 = s.solve(b)
     assert i1.iterations == i0.iterations and np.linalg.norm(x1 - x0) <= 1e-10 * np.linalg.norm(x0)
     x1b, _ = s.solve(b)
     assert np.array_equal(x1, x1b)  # a fixed shape is deterministic
-    for g in (0, 4, 8, 32, 64):  # 0: level operators in sliced ELL layout
+    for g in (0, 1, 4, 8, 32, 64):  # 0, 1: sliced ELL layout (one or four waves per slice)
         d = dict(t)
         d["spmv_lanes"] = [g] * 8
-        d["pt_lanes"] = [g or 16] * 8
+        d["pt_lanes"] = [g] * 8
         d["krylov_lanes"] = g
         d["ras_groups"] = [256] * 8
         h.set_tuning(d)
@@ -101,8 +102,9 @@ def test_blocks_per_work_item_same_bits(precision):
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_batch_of_differently_tuned_hierarchies_same_bits(precision):
     """Systems whose hierarchies carry different lanes-per-row choices (which
-    fix the summation order; 0 = sliced ELL) keep their own order inside one
-    batch: every slot equals its solve alone, bitwise."""
+    fix the summation order; 0 and 1 = sliced ELL with one or four waves per
+    slice) keep their own order inside one batch: every slot equals its
+    solve alone, bitwise."""
     import torch
 
     if not torch.cuda.is_available():
@@ -111,14 +113,14 @@ def test_batch_of_differently_tuned_hierarchies_same_bits(precision):
 
     prec = nnms.MIXED if precision == "mixed" else nnms.FP64
     keep, systems, bs, alone = [], [], [], []
-    for n, g, seed in ((14, 4, 11), (12, 64, 21), (14, 0, 31)):
+    for n, g, gp, seed in ((14, 4, 64, 11), (12, 64, 8, 21), (14, 0, 1, 31), (13, 1, 0, 41)):
         pb = W.Problem("t", W.make_hierarchy([n, n // 2, 3], [seed, seed + 1, seed + 2]), [4, 2],
                        W.kappa_draw(204, seed))
         ms = [nnms.Mesh.from_workload(m) for m in pb.meshes]
         h = nnms.Hierarchy(ms, pb.nparts, precision=prec)
         d = h.get_tuning()
         d["spmv_lanes"] = [g] * 8
-        d["pt_lanes"] = [64 // g * 4 if 0 < g < 16 else 8] * 8
+        d["pt_lanes"] = [gp] * 8
         d["krylov_lanes"] = g
         h.set_tuning(d)
         s = nnms.System(h, pb.kappa)
