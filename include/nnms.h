@@ -206,6 +206,15 @@ nnms_status nnms_system_matrix(const nnms_system* s, int32_t level, double* val_
 nnms_status nnms_system_factor(const nnms_system* s, int32_t level, int32_t part, double* lu_host, double* invl_host,
                                int32_t* N_host);
 
+/* Read-back of the pair coupling tiles of the same factor: for tile pairs
+ * (a, b) = (2p, 2p+1), p < floor(N/2), the off-diagonal blocks of the
+ * inverses of the 128 x 128 diagonal blocks,
+ *   xl_host[p] = -inv(L_bb) L_ba inv(L_aa),  xu_host[p] = -inv(U_aa) U_ab inv(U_bb),
+ * each 64x64 row-major (either may be NULL); *npairs_host receives
+ * floor(N/2).  The two-block triangular-solve work items apply them. */
+nnms_status nnms_system_factor_pairs(const nnms_system* s, int32_t level, int32_t part, double* xl_host, double* xu_host,
+                                     int32_t* npairs_host);
+
 /* ---------------------------------------------------------------------------
  * Operator applications, one call each, host vectors in and out (FP64 at
  * the boundary; the level's working precision inside):
@@ -254,9 +263,12 @@ nnms_status nnms_time_kernel(nnms_system* s, int32_t kind, int32_t level, int32_
  *   pt_lanes[l]    the same choice for P_l^T (4..64, 0 or 1)
  *   ras_groups[l]  work-groups of the persistent triangular-solve kernel on
  *                  level l (0 = 4 per compute unit)
- *   ras_blocks[l]  64-row blocks per work item of that kernel (1, 2 or 4):
- *                  blocks inside a work item are substituted in order by one
- *                  work-group, only work items hand results to each other
+ *   ras_blocks[l]  64-row blocks per work item of that kernel (1, 2 or 4);
+ *                  only work items hand results to each other.  With 4 the
+ *                  blocks of a work item are substituted one after the other
+ *                  by one work-group (the same sums as 1); with 2 the pair's
+ *                  precomputed 128 x 128 block inverse gives both blocks in
+ *                  one step (other rounding)
  *   krylov_lanes   the same choice for the outer FP64 operator
  * nnms_autotune times the candidates of every entry on the system's own
  * data with HIP events (reps launches each), keeps the fastest, stores the

@@ -1391,6 +1391,36 @@ extern "C" nnms_status nnms_system_factor(const nnms_system* s, int32_t level, i
   ABI_END
 }
 
+extern "C" nnms_status nnms_system_factor_pairs(const nnms_system* s, int32_t level, int32_t part, double* xl,
+                                                double* xu, int32_t* npairs) {
+  ABI_BEGIN
+  if (!s || level < 0 || level >= s->h->host.L) throw Error(NNMS_ERR_INVALID_ARG, "bad level");
+  const HostLevel& hl = s->h->host.lev[level];
+  if (part < 0 || part >= hl.nparts) throw Error(NNMS_ERR_INVALID_ARG, "bad part");
+  const int N = hl.nblk[part], NP = N / 2;
+  if (npairs) *npairs = NP;
+  if (!xl && !xu) return NNMS_OK;
+  const bool f64 = (level == s->h->host.L - 1) || s->prec == NNMS_FP64;
+  const size_t fsz = f64 ? 8 : 4;
+  const size_t first = (size_t(N) * N + N) * TILE_ELEMS, ne = size_t(2 * NP) * TILE_ELEMS;
+  std::vector<char> raw(std::max<size_t>(ne * fsz, 1));
+  if (ne)
+    HIP_CHECK(hipMemcpy(raw.data(), (const char*)s->lev[level].fac + (size_t(hl.fac_off[part]) + first) * fsz,
+                        ne * fsz, hipMemcpyDeviceToHost));
+  auto get = [&](size_t tile, int r, int c) -> double {
+    if (f64) return ((const double*)raw.data())[tile * TILE_ELEMS + ((c / 2) * 64 + r) * 2 + (c % 2)];
+    return ((const float*)raw.data())[tile * TILE_ELEMS + ((c / 4) * 64 + r) * 4 + (c % 4)];
+  };
+  for (int p = 0; p < NP; ++p)
+    for (int r = 0; r < 64; ++r)
+      for (int c = 0; c < 64; ++c) {
+        if (xl) xl[(size_t(p) * 64 + r) * 64 + c] = get(size_t(p), r, c);
+        if (xu) xu[(size_t(p) * 64 + r) * 64 + c] = get(size_t(NP + p), r, c);
+      }
+  return NNMS_OK;
+  ABI_END
+}
+
 // ---------------------------------------------------------------------------
 // launch-shape tuning
 // ---------------------------------------------------------------------------

@@ -206,7 +206,8 @@ void build_partition(HostLevel& lv, int nparts, int overlap, bool direct) {
     int64_t n = lv.s_ptr[p + 1] - lv.s_ptr[p];
     int32_t N = int32_t((n + TILE - 1) / TILE);
     lv.nblk[p] = N;
-    lv.fac_off[p + 1] = lv.fac_off[p] + (int64_t(N) * N + N) * TILE_ELEMS;
+    // N*N tiles (L, U, inv(U_ii)), N tiles inv(L_ii), 2 floor(N/2) pair coupling tiles
+    lv.fac_off[p + 1] = lv.fac_off[p] + (int64_t(N) * N + N + 2 * (N / 2)) * TILE_ELEMS;
     lv.g_off[p + 1] = lv.g_off[p] + int64_t(N) * TILE;
   }
   lv.fac_elems = lv.fac_off[nparts];

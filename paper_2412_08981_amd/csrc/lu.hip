@@ -7,7 +7,8 @@
 // L_ij below the diagonal and U_ij above it; the diagonal tile holds
 // inv(U_ii), and N extra tiles hold inv(L_ii) -- the inverted diagonal
 // blocks turn every step of the triangular solves into a 64x64
-// matrix-vector product.
+// matrix-vector product.  Then 2 floor(N/2) tiles hold the coupling blocks
+// of the inverses of the 128 x 128 diagonal blocks of tile pairs (below).
 //
 // Right-looking LU blocked twice: 64-wide tile columns, grouped into blocks
 // of LU_DEPTH tile columns.  For block column k0 .. k0+D-1 and each k in it:
@@ -568,6 +569,52 @@ __global__ __launch_bounds__(256, 2) void k_lu_trail(const FacDesc* __restrict__
   }
 }
 
+// ---------------------------------------------------------------------------
+// Coupling tiles of the 128 x 128 block inverses of tile pairs (a, b) =
+// (2p, 2p+1), used by the two-block triangular-solve work items:
+//   X_L = -inv(L_bb) L_ba inv(L_aa)   (tile N*N + N + p)
+//   X_U = -inv(U_aa) U_ab inv(U_bb)   (tile N*N + N + N/2 + p)
+// so that inv([L_aa 0; L_ba L_bb]) = [inv(L_aa) 0; X_L inv(L_bb)] and
+// inv([U_aa U_ab; 0 U_bb]) = [inv(U_aa) X_U; 0 inv(U_bb)].
+// blockIdx.x < npmax: X_L of pair x, else X_U of pair x - npmax.
+// ---------------------------------------------------------------------------
+template <typename F>
+__global__ __launch_bounds__(256) void k_lu_pairs(const FacDesc* __restrict__ d, int npmax) {
+  const FacDesc D = d[blockIdx.y];
+  const int N = D.N, np = N / 2;
+  const bool lower = int(blockIdx.x) < npmax;
+  const int p = lower ? int(blockIdx.x) : int(blockIdx.x) - npmax;
+  if (p >= np) return;
+  const size_t a = 2 * size_t(p), b = a + 1, n = size_t(N), NN = n * n;
+  __shared__ F As[64][LDP], Bs[64][LDP];
+  GLOBAL F* fac = gptr((F*)D.fac);
+  // X = -(T1 T2) T3
+  const size_t t1 = lower ? NN + b : a * n + a;
+  const size_t t2 = lower ? b * n + a : a * n + b;
+  const size_t t3 = lower ? NN + a : b * n + b;
+  const size_t out = lower ? NN + n + p : NN + n + np + p;
+  typename Mma<F>::acc_t acc[2][2];
+  tile_to_lds<F>(fac + t1 * TILE_ELEMS, As);
+  tile_to_lds<F>(fac + t2 * TILE_ELEMS, Bs);
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) acc[u][v] = typename Mma<F>::acc_t{0, 0, 0, 0};
+  tile_mma<F>(As, Bs, acc);
+  __syncthreads();
+  acc_to_lds<F>(acc, As);
+  tile_to_lds<F>(fac + t3 * TILE_ELEMS, Bs);
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) acc[u][v] = typename Mma<F>::acc_t{0, 0, 0, 0};
+  tile_mma<F>(As, Bs, acc);
+  acc_negate<F>(acc);
+  acc_store<F>(acc, fac + out * TILE_ELEMS);
+}
+
 template <typename F>
 hipError_t launch_lu(const FacDesc* d, int nd, int maxN, int* err, hipStream_t s) {
   if (nd <= 0) return hipSuccess;
@@ -581,6 +628,8 @@ hipError_t launch_lu(const FacDesc* d, int nd, int maxN, int* err, hipStream_t s
     const int nt = maxN - k0 - depth, ns = (nt + 1) / 2;
     if (nt > 0) hipLaunchKernelGGL((k_lu_trail<F>), dim3(ns * ns, nd), dim3(256), 0, s, d, k0, depth);
   }
+  const int npmax = maxN / 2;
+  if (npmax > 0) hipLaunchKernelGGL((k_lu_pairs<F>), dim3(2 * npmax, nd), dim3(256), 0, s, d, npmax);
   return hipGetLastError();
 }
 

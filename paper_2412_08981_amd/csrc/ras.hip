@@ -185,6 +185,11 @@ __global__ __launch_bounds__(256, (RasWaves<F, K>::value)) void k_ras(RasLaunch 
       (void)fetch(yx, N - 1, tag_fwd, tag_bwd);
       if (wave < nr) bsh[wave][lane] = fetch(yx, i0 + wave, tag_fwd, 0u);
     }
+    // scatter indices of the group's rows (backward), loaded now: the
+    // scatter follows the publication of each block result
+    int gz[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r) gz[r] = (!fwd && r < nr) ? gptr(S.gidx)[(i0 + r) * 64 + lane] : -1;
 
     // Off-diagonal stream: M tiles (blocks of other groups, in the order the
     // chain produces them), rows of the group innermost; then the first
@@ -338,12 +343,16 @@ __global__ __launch_bounds__(256, (RasWaves<F, K>::value)) void k_ras(RasLaunch 
           reduce_into(a2, ysh[r], nullptr);
           if (wave == 0) {
             const F out = ysh[r][lane];
-            const int g = gptr(S.gidx)[(i0 + r) * 64 + lane];
+            // publish first: later blocks of the chain wait for it
+            Tagged<F>::put(yx + (size_t(i0 + r) * 64 + lane) * 2, out, tag_bwd);
+            int g = -1;
+#pragma unroll
+            for (int kk = 0; kk < K; ++kk)
+              if (kk == r) g = gz[kk];
             if (g >= 0) {
               GLOBAL V* z = gptr((V*)S.zout);
               z[g] = P.add ? V(z[g] + V(out)) : V(out);
             }
-            Tagged<F>::put(yx + (size_t(i0 + r) * 64 + lane) * 2, out, tag_bwd);
           }
           if (r - 1 >= 0) {
 #pragma unroll
@@ -356,6 +365,240 @@ __global__ __launch_bounds__(256, (RasWaves<F, K>::value)) void k_ras(RasLaunch 
 }
 
 
+// Work items of two blocks (K = 2) with the pair's 128 x 128 triangular
+// inverse precomputed: for rows a = 2p, b = 2p + 1
+//   forward   y_a = inv(L_aa) v_a,   y_b = X_L v_a + inv(L_bb) v_b,
+//             X_L = -inv(L_bb) L_ba inv(L_aa)
+//   backward  x_a = inv(U_aa) s_a + X_U s_b,   x_b = inv(U_bb) s_b,
+//             X_U = -inv(U_aa) U_ab inv(U_bb)
+// (v, s: right-hand side minus the off-pair products), so both blocks come
+// out of one step with three resident tiles instead of one block after the
+// other: the chain of hand-offs between work-groups halves, and so does the
+// number of work items.  A last single block (odd N) uses its inverse alone.
+template <typename F, typename V>
+__global__ __launch_bounds__(256, (RasWaves<F, 2>::value)) void k_ras2(RasLaunch P, int32_t* err) {
+  using C = typename Chunk<F>::type;
+  constexpr int W = Chunk<F>::W;
+  constexpr int NQ = 16 / W;  // 16-byte chunks per lane per tile
+  __shared__ F red[4][2][64];
+  __shared__ __align__(16) F vsh[2][64];
+  __shared__ F ysh[2][64];
+  __shared__ F bsh[2][64];
+  __shared__ __align__(16) F ywv[4][2][64];  // per-wave staging of fetched result blocks
+  __shared__ int s_task;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int epoch = __hip_atomic_load(&g_ras_epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
+  const uint32_t tag_fwd = 2u * uint32_t(epoch), tag_bwd = tag_fwd + 1u;
+
+  auto fetch = [&](const uint64_t* yx, int j, uint32_t tag, uint32_t tag2) -> F {
+    const uint64_t* p = yx + (size_t(j) * 64 + lane) * 2;
+    F v;
+    int spins = 0;
+    for (;;) {
+      const uint32_t t = Tagged<F>::get(p, v);
+      if (__all(t == tag || (tag2 != 0u && t == tag2))) break;
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > SPIN_LIMIT) {
+        if (lane == 0) atomicOr(err, 2);
+        break;
+      }
+    }
+    return v;
+  };
+
+  for (;;) {
+    if (tid == 0) s_task = atomicAdd(P.counter, 1);
+    __syncthreads();
+    const int t = s_task;
+    __syncthreads();
+    if (t >= P.ntasks) {
+      if (tid == 0 && t == P.ntasks + int(gridDim.x) - 1) {
+        __hip_atomic_store(P.counter, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_max(&g_ras_epoch, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      return;
+    }
+    const int code = gptr(P.tasks)[t];
+    const int sub = code >> 16, dir = (code >> 15) & 1, I = code & 0x7fff;
+    const SubDesc S = P.subs[sub];
+    if (!slot_active(S.st, WHEN_RUNNING)) continue;
+    const int N = S.N, NP = N / 2;
+    const int a = 2 * I;
+    const int nr = min(2, N - a);  // 2: a pair, 1: the last single block
+    const int b = a + nr - 1;
+    const F* __restrict__ fac = (const F*)S.fac;
+    uint64_t* yx = (uint64_t*)S.yx;
+    const size_t NN = size_t(N) * N;
+    const bool fwd = dir == 0;
+    const uint32_t tag_in = fwd ? tag_fwd : tag_bwd;
+
+    auto load_tile = [&](size_t tix, C (&reg)[NQ]) {
+      const GLOBAL C* base = gptr((const C*)(fac + tix * TILE_ELEMS));
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) reg[q] = __builtin_nontemporal_load(base + (wave + 4 * q) * 64 + lane);
+    };
+    // acc += tile . y, y in LDS
+    auto gemv_lds = [&](const C (&A)[NQ], const F* y, F& acc) {
+      const C* yc = (const C*)y;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) acc += chunk_dot(A[q], yc[wave + 4 * q]);
+    };
+    // reduces the two rows' partial sums over the four waves: out[r] =
+    // minuend[r] - sum (or the sum); wave r writes row r
+    auto reduce2 = [&](F acc0, F acc1, F (*out)[64], F (*minuend)[64]) {
+      red[wave][0][lane] = acc0;
+      red[wave][1][lane] = acc1;
+      __syncthreads();
+      if (wave < nr) {
+        const F s = (red[0][wave][lane] + red[1][wave][lane]) + (red[2][wave][lane] + red[3][wave][lane]);
+        out[wave][lane] = minuend ? minuend[wave][lane] - s : s;
+      }
+      __syncthreads();
+    };
+
+    F acc0 = 0, acc1 = 0;
+    // right-hand sides of the rows: gathered r[S_p] (forward) or y (backward)
+    if (fwd) {
+      if (wave < nr) {
+        const int g = gptr(S.gidx)[(a + wave) * 64 + lane];
+        const int gg = g >= 0 ? g : -g - 2;
+        bsh[wave][lane] = (g != -1) ? F(gptr((const V*)S.rin)[gg]) : F(0);
+      }
+    } else {
+      // the last forward block is published (forward or already backward
+      // tag): every forward work item of this subdomain is complete
+      (void)fetch(yx, N - 1, tag_fwd, tag_bwd);
+      if (wave < nr) bsh[wave][lane] = fetch(yx, a + wave, tag_fwd, 0u);
+    }
+    // scatter index of this wave's row (backward), loaded now: the scatter
+    // follows the publication of the block result
+    const int gz = (!fwd && wave < nr) ? gptr(S.gidx)[(a + wave) * 64 + lane] : -1;
+
+    // the pair's inverse tiles, loaded first and kept in registers for the
+    // whole item (they are needed right after the last wait, on the chain's
+    // critical path): forward inv(L_aa), X_L, inv(L_bb), backward inv(U_aa),
+    // X_U, inv(U_bb); a single block has its inverse only
+    C D0[NQ], D1[NQ], D2[NQ];
+    load_tile(fwd ? NN + a : size_t(a) * N + a, D0);
+    if (nr == 2) {
+      load_tile(fwd ? NN + N + I : NN + N + NP + I, D1);
+      load_tile(fwd ? NN + b : size_t(b) * N + b, D2);
+    }
+    // stream positions: the M off-pair tiles (blocks of other work items in
+    // the order the chain produces them, the pair's rows innermost)
+    const int M = (fwd ? a : N - 1 - b) * nr;
+    auto col_of = [&](int k) -> int {
+      const int jj = k / nr;
+      return fwd ? jj : N - 1 - jj;
+    };
+    auto tile_of = [&](int k) -> size_t { return size_t(a + k % nr) * N + col_of(k); };
+    // ring of four register tiles: the loads of positions k+2 .. k+5 are in
+    // flight while k, k+1 are applied (128 KB per work-group in FP64)
+    C R0[NQ], R1[NQ], R2[NQ], R3[NQ];
+    if (M >= 1) load_tile(tile_of(0), R0);
+    if (M >= 2) load_tile(tile_of(1), R1);
+    if (M >= 3) load_tile(tile_of(2), R2);
+    if (M >= 4) load_tile(tile_of(3), R3);
+    // polls result blocks j0 and j1 until the whole wave sees the tag on
+    // both, and stages them in this wave's LDS slice (chunks are read back
+    // as broadcasts)
+    auto poll2 = [&](int j0, int j1) {
+      const uint64_t* p0 = yx + (size_t(j0) * 64 + lane) * 2;
+      const uint64_t* p1 = yx + (size_t(j1) * 64 + lane) * 2;
+      F y0, y1;
+      int spins = 0;
+      for (;;) {
+        const uint32_t t0 = Tagged<F>::get(p0, y0);
+        const uint32_t t1 = Tagged<F>::get(p1, y1);
+        if (__all(t0 == tag_in && t1 == tag_in)) break;
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > SPIN_LIMIT) {
+          if (lane == 0) atomicOr(err, 2);
+          break;
+        }
+      }
+      ywv[wave][0][lane] = y0;
+      ywv[wave][1][lane] = y1;
+      __builtin_amdgcn_wave_barrier();
+    };
+    const int ncols = M / nr;
+    // applies positions k (Ra) and k+1 (Rb, when k+1 < M) and refills them
+    // with positions k+4, k+5.  A pair's positions k, k+1 are its two rows
+    // of one column jj = k/2; the blocks of columns jj and jj+1 are polled
+    // together at even jj, so that the row's last two columns (published
+    // together by the previous pair) cost one wait, not two.  A single
+    // block's positions k, k+1 are two columns, polled together.
+    auto pair = [&](int k, C (&Ra)[NQ], C (&Rb)[NQ]) {
+      const bool two = k + 1 < M;
+      const F* ya;
+      const F* yb;
+      if (nr == 2) {
+        const int jj = k >> 1;
+        if ((jj & 1) == 0) poll2(col_of(k), jj + 1 < ncols ? col_of(k + 2) : col_of(k));
+        ya = yb = ywv[wave][jj & 1];
+      } else {
+        poll2(col_of(k), two ? col_of(k + 1) : col_of(k));
+        ya = ywv[wave][0];
+        yb = ywv[wave][1];
+      }
+      F d0 = 0;
+      gemv_lds(Ra, ya, d0);
+      if (nr == 1 || (k & 1) == 0)
+        acc0 += d0;
+      else
+        acc1 += d0;
+      // keep the refill of a tile's registers after their last use, so the
+      // compiler does not double-buffer them (register pressure = occupancy)
+      __builtin_amdgcn_sched_barrier(0);
+      if (k + 4 < M) load_tile(tile_of(k + 4), Ra);
+      if (two) {
+        F d1 = 0;
+        gemv_lds(Rb, yb, d1);
+        if (nr == 1 || ((k + 1) & 1) == 0)
+          acc0 += d1;
+        else
+          acc1 += d1;
+        __builtin_amdgcn_sched_barrier(0);
+        if (k + 5 < M) load_tile(tile_of(k + 5), Rb);
+      }
+      __builtin_amdgcn_wave_barrier();
+    };
+    for (int k = 0; k < M; k += 4) {
+      pair(k, R0, R1);
+      if (k + 2 < M) pair(k + 2, R2, R3);
+    }
+    __syncthreads();  // bsh visible
+    reduce2(acc0, acc1, vsh, bsh);
+    // the pair's block inverse applied to both rows
+    auto pair_step = [&](const C (&T0)[NQ], const C (&T1)[NQ], const C (&T2)[NQ]) {
+      F o0 = 0, o1 = 0;
+      if (nr == 1) {
+        gemv_lds(T0, vsh[0], o0);
+      } else if (fwd) {
+        gemv_lds(T0, vsh[0], o0);  // inv(L_aa) v_a
+        gemv_lds(T1, vsh[0], o1);  // X_L v_a
+        gemv_lds(T2, vsh[1], o1);  // + inv(L_bb) v_b
+      } else {
+        gemv_lds(T0, vsh[0], o0);  // inv(U_aa) s_a
+        gemv_lds(T1, vsh[1], o0);  // + X_U s_b
+        gemv_lds(T2, vsh[1], o1);  // inv(U_bb) s_b
+      }
+      reduce2(o0, o1, ysh, nullptr);
+    };
+    pair_step(D0, D1, D2);
+    if (wave < nr) {
+      const int i = a + wave;
+      const F out = ysh[wave][lane];
+      // publish first: later blocks of the chain wait for it
+      Tagged<F>::put(yx + (size_t(i) * 64 + lane) * 2, out, fwd ? tag_fwd : tag_bwd);
+      if (gz >= 0) {
+        GLOBAL V* z = gptr((V*)S.zout);
+        z[gz] = P.add ? V(z[gz] + V(out)) : V(out);
+      }
+    }
+  }
+}
+
 template <typename F, typename V>
 hipError_t launch_ras(const RasLaunch& p, int grid, hipStream_t s) {
   if (p.ntasks <= 0) return hipSuccess;
@@ -363,7 +606,7 @@ hipError_t launch_ras(const RasLaunch& p, int grid, hipStream_t s) {
   if (grid < 1) grid = 1;
   switch (p.group) {
     case 1: hipLaunchKernelGGL((k_ras<F, V, 1>), dim3(grid), dim3(256), 0, s, p, p.counter + 2); break;
-    case 2: hipLaunchKernelGGL((k_ras<F, V, 2>), dim3(grid), dim3(256), 0, s, p, p.counter + 2); break;
+    case 2: hipLaunchKernelGGL((k_ras2<F, V>), dim3(grid), dim3(256), 0, s, p, p.counter + 2); break;
     case 4: hipLaunchKernelGGL((k_ras<F, V, 4>), dim3(grid), dim3(256), 0, s, p, p.counter + 2); break;
     default: return hipErrorInvalidValue;
   }

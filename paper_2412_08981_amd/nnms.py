@@ -136,6 +136,7 @@ _sig = {
     "nnms_batch_destroy": (C.c_int, [vp]),
     "nnms_time_kernel": (C.c_int, [vp, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double)]),
     "nnms_system_factor": (C.c_int, [vp, C.c_int32, C.c_int32, vp, vp, C.POINTER(C.c_int32)]),
+    "nnms_system_factor_pairs": (C.c_int, [vp, C.c_int32, C.c_int32, vp, vp, C.POINTER(C.c_int32)]),
     "nnms_hierarchy_get_tuning": (C.c_int, [vp, C.POINTER(tuning_t)]),
     "nnms_hierarchy_set_tuning": (C.c_int, [vp, C.POINTER(tuning_t)]),
     "nnms_autotune": (C.c_int, [vp, C.c_int32, C.POINTER(tuning_t)]),
@@ -369,6 +370,16 @@ class System:
         il = np.empty((N.value, 64, 64))
         _check(_lib.nnms_system_factor(self.handle, level, part, _ptr(lu), _ptr(il), C.byref(N)))
         return lu, il
+
+    def factor_pairs(self, level: int, part: int):
+        """Pair coupling tiles of one subdomain's factor: (X_L [NP,64,64], X_U [NP,64,64])."""
+        NP = C.c_int32()
+        _check(_lib.nnms_system_factor_pairs(self.handle, level, part, None, None, C.byref(NP)))
+        xl = np.empty((NP.value, 64, 64))
+        xu = np.empty((NP.value, 64, 64))
+        if NP.value:
+            _check(_lib.nnms_system_factor_pairs(self.handle, level, part, _ptr(xl), _ptr(xu), C.byref(NP)))
+        return xl, xu
 
     def autotune(self, reps: int = 10) -> dict:
         """nnms_autotune: time the launch-shape candidates on this system and

@@ -234,6 +234,18 @@ def test_factors_reproduce_subdomain_matrices(case, precision, request):
             pad = M[n:, n:]
             assert np.allclose(pad, np.eye(pad.shape[0]), rtol=0, atol=tol), (l, p)
             assert np.abs(M[:n, n:]).max(initial=0) <= tol and np.abs(M[n:, :n]).max(initial=0) <= tol
+            # pair coupling tiles: off-diagonal blocks of the inverses of the
+            # 128 x 128 diagonal blocks, from the stored factor tiles
+            xl, xu = g.s.factor_pairs(l, p)
+            assert xl.shape[0] == lu.shape[0] // 128
+            T = lambda i, j: lu[64 * i:64 * i + 64, 64 * j:64 * j + 64]
+            ptol = 1e-12 if (precision == "fp64" or l == L - 1) else 1e-5
+            for q in range(xl.shape[0]):
+                a_, b_ = 2 * q, 2 * q + 1
+                el = -il[b_] @ T(b_, a_) @ il[a_]
+                eu = -T(a_, a_) @ T(a_, b_) @ T(b_, b_)
+                assert np.abs(xl[q] - el).max() <= ptol * max(np.abs(el).max(), 1.0), (l, p, q)
+                assert np.abs(xu[q] - eu).max() <= ptol * max(np.abs(eu).max(), 1.0), (l, p, q)
         g.s.time_kernel(6, l, reps=1)
         for p in range(len(sets)):
             lu, il = g.s.factor(l, p)

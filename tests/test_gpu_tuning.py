@@ -59,9 +59,12 @@ def test_autotune_keeps_results_and_caches(tmp_path):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_blocks_per_work_item_same_bits(precision):
-    """Grouping K blocks per work item changes who computes a block, not the
-    order of any sum: the solves for K = 1, 2, 4 are bitwise identical, and
-    the smoother matches the oracle's on every level."""
+    """Grouping K blocks per work item: K = 1 and K = 4 (blocks substituted
+    one after the other) only change who computes a block, not the order of
+    any sum, so their solves are bitwise identical; K = 2 applies the
+    precomputed inverse of each 128 x 128 diagonal block pair (other
+    rounding), so it agrees to rounding and is deterministic.  Every K
+    matches the oracle's smoother on every level."""
     import torch
 
     if not torch.cuda.is_available():
@@ -86,7 +89,12 @@ def test_blocks_per_work_item_same_bits(precision):
         x, info = s.solve(o.b)
         assert info.status == 0 and info.relres <= 1e-8
         if ref is None:
-            ref = x
+            ref, ref_its = x, info.iterations
+        elif K == 2:
+            assert abs(info.iterations - ref_its) <= 1
+            assert np.linalg.norm(x - ref) <= 1e-7 * np.linalg.norm(ref), K
+            x2, _ = s.solve(o.b)
+            assert np.array_equal(x, x2)
         else:
             assert np.array_equal(x, ref), K
         if precision == "fp64":
