@@ -423,7 +423,8 @@ def main():
                    "tuning": tuning},
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": load_traffic(args.precision),
-                     "kernel": "k_ras (fine-level smoother)", "ms": round(ms, 4)},
+                     "kernel": ("k_ras2 (fine-level smoother, two-block work items)" if tuning["ras_blocks"][0] == 2
+                                else "k_ras (fine-level smoother)"), "ms": round(ms, 4)},
         "kernels": extra,
     }
     if not args.no_cpu_baseline:
