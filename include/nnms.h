@@ -250,10 +250,11 @@ nnms_status nnms_time_kernel(nnms_system* s, int32_t kind, int32_t level, int32_
 
 /* ---------------------------------------------------------------------------
  * Launch-shape tuning, per hierarchy (used by every solve plan created after
- * it is set).  A batch keeps every system's own lanes-per-row choices (they
- * fix the summation order, so a system gives the same bits alone and in any
- * batch) and takes the smoother's launch shapes from its first system's
- * hierarchy (they change no arithmetic).
+ * it is set).  A batch keeps every system's own lanes-per-row and
+ * blocks-per-work-item choices (they fix the summation order, so a system
+ * gives the same bits alone and in any batch: one launch per distinct
+ * choice) and takes each smoother launch's work-group count from the first
+ * system of its launch (it changes no arithmetic).
  *   spmv_lanes[l]  lanes of a wave per CSR row of level l's operator (4..64),
  *                  or the operator in sliced ELL layout (64-row slices, one
  *                  lane per row, slices column-major): 0 = one wave per

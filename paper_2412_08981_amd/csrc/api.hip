@@ -231,12 +231,28 @@ static hipError_t launch_spmv_groups(const std::vector<SpmvGroup>& gs, hipStream
   return hipSuccess;
 }
 
+// One smoother launch pair per blocks-per-work-item choice among the
+// systems of a plan (one- and two-block items round differently): every
+// system keeps its own hierarchy's choice, alone and in any batch.
+struct RasGroup {
+  RasLaunch r{}, t{};  // input r_l (write) / t_l (add)
+  int grid = 0;
+};
+
+template <typename F, typename V>
+static hipError_t launch_ras_groups(const std::vector<RasGroup>& gs, bool add, hipStream_t s) {
+  for (const RasGroup& G : gs) {
+    const hipError_t e = launch_ras<F, V>(add ? G.t : G.r, G.grid, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 struct LevelPlan {
-  int ras_grid = 0, ras_k = 1;
   std::vector<SpmvGroup> res, rst;
   ProlongDesc* pro = nullptr;
   int pro_blocks = 0;
-  RasLaunch ras_r{}, ras_t{};  // input r_l (write) / t_l (add)
+  std::vector<RasGroup> ras;
   int nd = 0;
 };
 
@@ -246,8 +262,7 @@ struct Plan {
   bool with_state = true;
   Arena mem;
   std::vector<LevelPlan> lev;  // smoothed levels
-  RasLaunch coarse{};
-  int coarse_grid = 0, coarse_k = 1;
+  std::vector<RasGroup> coarse;  // the coarsest direct solve (write launches)
   int nd = 0;
   KrylovDesc* kd = nullptr;
   std::vector<KrylovDesc> kd_host;
@@ -363,13 +378,25 @@ static void build_plan(Plan& P, const std::vector<nnms_system*>& sys, bool with_
     if (x->h->host.L != L || x->prec != P.prec || x->h->host.opts.its != P.its)
       throw Error(NNMS_ERR_INVALID_ARG, "batched systems must share level count, precision and smoothing steps");
   P.lev.resize(std::max(0, L - 1));
-  const nnms_tuning& tu = h0->tune;
-  for (int l = 0; l < L - 1; ++l) {
-    P.lev[l].ras_grid = tu.ras_groups[l] > 0 ? tu.ras_groups[l] : ras_grid_default();
-    P.lev[l].ras_k = tu.ras_blocks[l];
-  }
-  P.coarse_grid = tu.ras_groups[L - 1] > 0 ? tu.ras_groups[L - 1] : ras_grid_default();
-  P.coarse_k = tu.ras_blocks[L - 1];
+  // smoother launches of level l, one per blocks-per-item value (the launch
+  // grid, which changes no arithmetic, from the group's first system)
+  auto ras_groups_of = [&](int l, bool coarse) {
+    std::vector<int> ks;
+    for (auto* x : sys)
+      if (std::find(ks.begin(), ks.end(), x->h->tune.ras_blocks[l]) == ks.end()) ks.push_back(x->h->tune.ras_blocks[l]);
+    std::vector<RasGroup> out;
+    for (int K : ks) {
+      std::vector<nnms_system*> sub;
+      for (auto* x : sys)
+        if (x->h->tune.ras_blocks[l] == K) sub.push_back(x);
+      RasGroup G;
+      const int g = sub[0]->h->tune.ras_groups[l];
+      G.grid = g > 0 ? g : ras_grid_default();
+      build_ras_pair(P.mem, P.counters, sub, l, coarse, P.prec, with_state, K, s, G.r, G.t);
+      out.push_back(G);
+    }
+    return out;
+  };
   for (int l = 0; l < L - 1; ++l) {
     LevelPlan& LP = P.lev[l];
     std::vector<std::pair<int, SpmvDesc>> res, rst;
@@ -413,12 +440,9 @@ static void build_plan(Plan& P, const std::vector<nnms_system*>& sys, bool with_
     LP.rst = spmv_groups(P.mem, rst, s);
     LP.pro = P.mem.upload(pro, s), LP.pro_blocks = bp;
     LP.nd = int(sys.size());
-    build_ras_pair(P.mem, P.counters, sys, l, false, P.prec, with_state, LP.ras_k, s, LP.ras_r, LP.ras_t);
+    LP.ras = ras_groups_of(l, false);
   }
-  {
-    RasLaunch dummy{};
-    build_ras_pair(P.mem, P.counters, sys, L - 1, true, P.prec, with_state, P.coarse_k, s, P.coarse, dummy);
-  }
+  P.coarse = ras_groups_of(L - 1, true);
   // Krylov descriptors
   if (with_state) {
     std::vector<std::pair<int, SpmvDesc>> wd, rd;
@@ -470,21 +494,21 @@ static void enqueue_vcycle(Plan& P, hipStream_t s) {
   const int L = P.L, its = P.its;
   for (int l = 0; l < L - 1; ++l) {
     LevelPlan& LP = P.lev[l];
-    HIP_CHECK((launch_ras<T, T>(LP.ras_r, LP.ras_grid, s)));
+    HIP_CHECK((launch_ras_groups<T, T>(LP.ras, false, s)));
     for (int k = 1; k < its; ++k) {
       HIP_CHECK(launch_spmv_groups<T>(LP.res, s));
-      HIP_CHECK((launch_ras<T, T>(LP.ras_t, LP.ras_grid, s)));
+      HIP_CHECK((launch_ras_groups<T, T>(LP.ras, true, s)));
     }
     HIP_CHECK(launch_spmv_groups<T>(LP.res, s));
     HIP_CHECK(launch_spmv_groups<T>(LP.rst, s));
   }
-  HIP_CHECK((launch_ras<double, T>(P.coarse, P.coarse_grid, s)));
+  HIP_CHECK((launch_ras_groups<double, T>(P.coarse, false, s)));
   for (int l = L - 2; l >= 0; --l) {
     LevelPlan& LP = P.lev[l];
     HIP_CHECK(launch_prolong<T>(LP.pro, LP.nd, LP.pro_blocks, s));
     for (int k = 0; k < its; ++k) {
       HIP_CHECK(launch_spmv_groups<T>(LP.res, s));
-      HIP_CHECK((launch_ras<T, T>(LP.ras_t, LP.ras_grid, s)));
+      HIP_CHECK((launch_ras_groups<T, T>(LP.ras, true, s)));
     }
   }
 }
@@ -1035,14 +1059,14 @@ extern "C" nnms_status nnms_apply_smoother(nnms_system* s, int32_t level, const 
   HIP_CHECK(hipMemsetAsync(sl.z, 0, n * tsize(s), P.stream));
   if (level == s->h->host.L - 1) {
     if (s->prec == NNMS_FP64)
-      HIP_CHECK((launch_ras<double, double>(P.coarse, P.coarse_grid, P.stream)));
+      HIP_CHECK((launch_ras_groups<double, double>(P.coarse, false, P.stream)));
     else
-      HIP_CHECK((launch_ras<double, float>(P.coarse, P.coarse_grid, P.stream)));
+      HIP_CHECK((launch_ras_groups<double, float>(P.coarse, false, P.stream)));
   } else {
     if (s->prec == NNMS_FP64)
-      HIP_CHECK((launch_ras<double, double>(P.lev[level].ras_r, P.lev[level].ras_grid, P.stream)));
+      HIP_CHECK((launch_ras_groups<double, double>(P.lev[level].ras, false, P.stream)));
     else
-      HIP_CHECK((launch_ras<float, float>(P.lev[level].ras_r, P.lev[level].ras_grid, P.stream)));
+      HIP_CHECK((launch_ras_groups<float, float>(P.lev[level].ras, false, P.stream)));
   }
   get_vec(s, z, sl.z, n, P.stream);
   check_counters(P, P.stream);
@@ -1312,13 +1336,13 @@ extern "C" nnms_status nnms_time_kernel(nnms_system* s, int32_t kind, int32_t le
     } else if (kind == 0) {
       if (level == L - 1) {
         if (f64)
-          HIP_CHECK((launch_ras<double, double>(P.coarse, P.coarse_grid, st)));
+          HIP_CHECK((launch_ras_groups<double, double>(P.coarse, false, st)));
         else
-          HIP_CHECK((launch_ras<double, float>(P.coarse, P.coarse_grid, st)));
+          HIP_CHECK((launch_ras_groups<double, float>(P.coarse, false, st)));
       } else if (f64) {
-        HIP_CHECK((launch_ras<double, double>(P.lev[level].ras_t, P.lev[level].ras_grid, st)));
+        HIP_CHECK((launch_ras_groups<double, double>(P.lev[level].ras, true, st)));
       } else {
-        HIP_CHECK((launch_ras<float, float>(P.lev[level].ras_t, P.lev[level].ras_grid, st)));
+        HIP_CHECK((launch_ras_groups<float, float>(P.lev[level].ras, true, st)));
       }
     } else if (kind == 1) {
       if (f64)

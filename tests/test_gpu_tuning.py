@@ -111,8 +111,9 @@ def test_blocks_per_work_item_same_bits(precision):
 def test_batch_of_differently_tuned_hierarchies_same_bits(precision):
     """Systems whose hierarchies carry different lanes-per-row choices (which
     fix the summation order; 0 and 1 = sliced ELL with one or four waves per
-    slice) keep their own order inside one batch: every slot equals its
-    solve alone, bitwise."""
+    slice) and different blocks per smoother work item (two-block items
+    round differently) keep their own order inside one batch: every slot
+    equals its solve alone, bitwise."""
     import torch
 
     if not torch.cuda.is_available():
@@ -121,7 +122,7 @@ def test_batch_of_differently_tuned_hierarchies_same_bits(precision):
 
     prec = nnms.MIXED if precision == "mixed" else nnms.FP64
     keep, systems, bs, alone = [], [], [], []
-    for n, g, gp, seed in ((14, 4, 64, 11), (12, 64, 8, 21), (14, 0, 1, 31), (13, 1, 0, 41)):
+    for n, g, gp, kb, seed in ((14, 4, 64, 1, 11), (12, 64, 8, 2, 21), (14, 0, 1, 4, 31), (13, 1, 0, 2, 41)):
         pb = W.Problem("t", W.make_hierarchy([n, n // 2, 3], [seed, seed + 1, seed + 2]), [4, 2],
                        W.kappa_draw(204, seed))
         ms = [nnms.Mesh.from_workload(m) for m in pb.meshes]
@@ -129,6 +130,7 @@ def test_batch_of_differently_tuned_hierarchies_same_bits(precision):
         d = h.get_tuning()
         d["spmv_lanes"] = [g] * 8
         d["pt_lanes"] = [gp] * 8
+        d["ras_blocks"] = [kb] * 8
         d["krylov_lanes"] = g
         h.set_tuning(d)
         s = nnms.System(h, pb.kappa)
