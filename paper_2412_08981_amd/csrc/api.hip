@@ -298,20 +298,23 @@ static const void* ell_of(const SysLevel& sl) {
 // N[q] blocks: forward block i at step i, backward block i at step 2N-1-i,
 // ordered by (step, subdomain) so that every dependency has a lower ticket.
 static std::vector<int32_t> ras_tasks(const std::vector<int32_t>& N, int K) {
-  struct T3 {
-    int step, sub, code;
-  };
-  std::vector<T3> v;
+  // counting sort by step: inside a step, subdomains stay in ascending order
+  int steps = 0;
+  for (int32_t n : N) steps = std::max(steps, 2 * ((n + K - 1) / K));
+  std::vector<int32_t> cnt(size_t(steps) + 1, 0);
+  for (int32_t n : N) {
+    const int NB = (n + K - 1) / K;
+    for (int s = 0; s < 2 * NB; ++s) cnt[s + 1]++;
+  }
+  for (int s = 0; s < steps; ++s) cnt[s + 1] += cnt[s];
+  std::vector<int32_t> out(cnt[steps]);
   for (size_t q = 0; q < N.size(); ++q) {
     const int NB = (N[q] + K - 1) / K;
     for (int i = 0; i < NB; ++i) {
-      v.push_back({i, int(q), int((q << 16) | i)});
-      v.push_back({2 * NB - 1 - i, int(q), int((q << 16) | (1 << 15) | i)});
+      out[cnt[i]++] = int32_t((q << 16) | i);
+      out[cnt[2 * NB - 1 - i]++] = int32_t((q << 16) | (1 << 15) | i);
     }
   }
-  std::sort(v.begin(), v.end(), [](const T3& a, const T3& b) { return a.step != b.step ? a.step < b.step : a.sub < b.sub; });
-  std::vector<int32_t> out(v.size());
-  for (size_t k = 0; k < v.size(); ++k) out[k] = v[k].code;
   return out;
 }
 
@@ -322,7 +325,6 @@ static void build_ras_pair(Arena& mem, std::vector<int32_t*>& counters, const st
                            bool coarse, int prec, bool with_state, int K, hipStream_t s, RasLaunch& rr, RasLaunch& rt) {
   std::vector<SubDesc> subs_r, subs_t;
   std::vector<int32_t> Ns;
-  int flag = 0;
   for (auto* x : sys) {
     const HostLevel& hl = x->h->host.lev[l];
     const DevLevel& dl = x->h->dev[l];
@@ -337,8 +339,6 @@ static void build_ras_pair(Arena& mem, std::vector<int32_t*>& counters, const st
       d.zout = sl.z;
       d.st = with_state ? x->st : nullptr;
       d.N = hl.nblk[p];
-      d.flag0 = flag;
-      flag += 2 * ((hl.nblk[p] + K - 1) / K);
       subs_r.push_back(d);
       d.rin = sl.t;
       subs_t.push_back(d);
@@ -347,13 +347,11 @@ static void build_ras_pair(Arena& mem, std::vector<int32_t*>& counters, const st
   }
   if (subs_r.size() > 32767) throw Error(NNMS_ERR_INVALID_ARG, "too many subdomains in one batch");
   std::vector<int32_t> tasks = ras_tasks(Ns, K);
-  int32_t* flags = mem.alloc<int32_t>(std::max(flag, 1), s);
   int32_t* counter = mem.alloc<int32_t>(4, s);
   counters.push_back(counter);
   rr = RasLaunch{};
   rr.subs = mem.upload(subs_r, s);
   rr.tasks = mem.upload(tasks, s);
-  rr.flags = flags;
   rr.counter = counter;
   rr.ntasks = int(tasks.size());
   rr.add = 0;

@@ -67,13 +67,12 @@ struct SubDesc {
   void* zout;           // level correction vector
   const KState* st;     // null: always active
   int32_t N;
-  int32_t flag0;        // forward flag of work item g at flag0+g, backward at flag0+NG+g (NG = ceil(N/K))
+  int32_t pad;
 };
 
 struct RasLaunch {
   const SubDesc* subs;
   const int32_t* tasks;  // (sub << 16) | (dir << 15) | work item (group of K blocks)
-  int32_t* flags;
   int32_t* counter;      // [0] ticket, [2] error bits
   int32_t ntasks;
   int32_t add;           // z += x (1) or z = x (0)
