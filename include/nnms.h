@@ -345,6 +345,10 @@ nnms_status nnms_solve(nnms_system* s, const double* b, double* x, const nnms_so
  *                     NNMS_NO_GRAPH); *active_host receives the number of
  *                     slots still iterating.
  * nnms_batch_result   copy slot's solution to x (device pointer) and info.
+ * nnms_batch_destroy  wait for the batch's own stream (not the device) and
+ *                     drop it; its stream, pinned word and small device
+ *                     buffers are kept by the library for later batches
+ *                     (at most 64 MiB of device buffers per process).
  * ------------------------------------------------------------------------- */
 nnms_status nnms_batch_create(nnms_system* const* systems, int32_t nb, const nnms_solve_opts* opts, void* stream,
                               nnms_batch** out);

@@ -8,6 +8,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -33,9 +34,29 @@ static std::atomic<int64_t> g_bytes{0};
 // ---------------------------------------------------------------------------
 // device memory: the caller's allocator or hipMalloc; freed together
 // ---------------------------------------------------------------------------
+
+// Batch plans own only small buffers (descriptors, task lists, counters).
+// They are recycled per device and power-of-two size class instead of
+// freed, because hipFree waits for the whole device: dropping a plan would
+// otherwise wait for unrelated work on other streams (the factorisation of
+// a newly admitted request in the serving loop).  At most kDevCacheCap
+// bytes are kept; buffers beyond that are freed.
+static constexpr size_t kDevCacheCap = size_t(64) << 20;
+struct DevCache {
+  std::mutex mu;
+  std::map<std::pair<int, int>, std::vector<void*>> free;  // (device, log2 size)
+  size_t cached = 0;
+};
+static DevCache& dev_cache() {
+  static DevCache* c = new DevCache();  // never destroyed: outlives every plan
+  return *c;
+}
+
 struct Arena {
   nnms_allocator a{};
   bool has = false;
+  bool pooled = false;  // small buffers of a plan: recycled through dev_cache
+  int dev = -1;
   std::vector<std::pair<void*, size_t>> bufs;
   size_t total = 0;
   Arena() = default;
@@ -48,7 +69,21 @@ struct Arena {
     if (bytes == 0) bytes = 256;
     bytes = (bytes + 255) & ~size_t(255);
     void* p = nullptr;
-    if (has) {
+    if (pooled && !has) {
+      int c = 12;
+      while ((size_t(1) << c) < bytes) ++c;
+      bytes = size_t(1) << c;
+      if (dev < 0) HIP_CHECK(hipGetDevice(&dev));
+      std::lock_guard<std::mutex> g(dev_cache().mu);
+      auto& v = dev_cache().free[{dev, c}];
+      if (!v.empty()) {
+        p = v.back();
+        v.pop_back();
+        dev_cache().cached -= bytes;
+      }
+    }
+    if (p) {
+    } else if (has) {
       p = a.alloc(bytes, a.ctx);
       if (!p) throw Error(NNMS_ERR_OUT_OF_MEMORY, "device allocator returned null for " + std::to_string(bytes) + " bytes");
     } else {
@@ -78,7 +113,19 @@ struct Arena {
   }
   void release() {
     for (auto& b : bufs) {
-      if (has)
+      bool kept = false;
+      if (pooled && !has) {
+        int c = 12;
+        while ((size_t(1) << c) < b.second) ++c;
+        std::lock_guard<std::mutex> g(dev_cache().mu);
+        if (dev_cache().cached + b.second <= kDevCacheCap) {
+          dev_cache().free[{dev, c}].push_back(b.first);
+          dev_cache().cached += b.second;
+          kept = true;
+        }
+      }
+      if (kept) {
+      } else if (has)
         a.free(b.first, a.ctx);
       else
         (void)hipFree(b.first);
@@ -256,6 +303,50 @@ struct LevelPlan {
   int nd = 0;
 };
 
+// Streams and pinned host words of plans are recycled instead of destroyed:
+// hipStreamDestroy and hipHostFree wait for the device, which would make
+// dropping a batch plan wait for unrelated work on other streams (the
+// factorisation of a newly admitted request in the serving loop).  A
+// recycled stream keeps its order: work of the next plan queues behind the
+// last one's.
+struct PlanPools {
+  std::mutex mu;
+  std::vector<hipStream_t> streams;
+  std::vector<int*> words;
+};
+static PlanPools& plan_pools() {
+  static PlanPools* p = new PlanPools();  // never destroyed: outlives every plan
+  return *p;
+}
+static hipStream_t pool_stream() {
+  {
+    std::lock_guard<std::mutex> g(plan_pools().mu);
+    auto& v = plan_pools().streams;
+    if (!v.empty()) {
+      hipStream_t st = v.back();
+      v.pop_back();
+      return st;
+    }
+  }
+  hipStream_t st = nullptr;
+  HIP_CHECK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  return st;
+}
+static int* pool_word() {
+  {
+    std::lock_guard<std::mutex> g(plan_pools().mu);
+    auto& v = plan_pools().words;
+    if (!v.empty()) {
+      int* w = v.back();
+      v.pop_back();
+      return w;
+    }
+  }
+  int* w = nullptr;
+  HIP_CHECK(hipHostMalloc((void**)&w, sizeof(int), hipHostMallocDefault));
+  return w;
+}
+
 struct Plan {
   std::vector<nnms_system*> sys;
   int L = 0, prec = NNMS_FP64, its = 3;
@@ -276,9 +367,13 @@ struct Plan {
   std::vector<int32_t*> counters;
   Plan() = default;
   ~Plan() {
+    // this plan's own work is done before its graph and descriptors go (a
+    // stream synchronisation: other streams are not waited for)
+    if (stream) (void)hipStreamSynchronize(stream);
     if (graph) (void)hipGraphExecDestroy(graph);
-    if (h_active) (void)hipHostFree(h_active);
-    if (stream) (void)hipStreamDestroy(stream);
+    std::lock_guard<std::mutex> g(plan_pools().mu);
+    if (h_active) plan_pools().words.push_back(h_active);
+    if (stream) plan_pools().streams.push_back(stream);
   }
 };
 
@@ -473,7 +568,7 @@ static void build_plan(Plan& P, const std::vector<nnms_system*>& sys, bool with_
     P.wspmv = spmv_groups(P.mem, wd, s);
     P.rspmv = spmv_groups(P.mem, rd, s);
     P.d_active = P.mem.alloc<int>(1, s);
-    HIP_CHECK(hipHostMalloc((void**)&P.h_active, sizeof(int), hipHostMallocDefault));
+    P.h_active = pool_word();
   }
   HIP_CHECK(hipStreamSynchronize(s));
 }
@@ -577,7 +672,8 @@ static void plan_start_slot(Plan& P, int k, const double* b_dev, const nnms_solv
 template <typename T>
 static std::unique_ptr<Plan> make_plan(const std::vector<nnms_system*>& sys, bool with_state) {
   auto P = std::make_unique<Plan>();
-  HIP_CHECK(hipStreamCreateWithFlags(&P->stream, hipStreamNonBlocking));
+  P->mem.pooled = true;
+  P->stream = pool_stream();
   build_plan<T>(*P, sys, with_state, P->stream);
   return P;
 }

@@ -57,6 +57,10 @@ class DeviceEngine:
 
         self.torch = torch
         self.streams = [torch.cuda.Stream() for _ in range(workers)]
+        # the loop's own stream: batch plans order themselves after it, so
+        # forming a batch does not wait for the factorisations running on
+        # the workers' streams (the null stream would)
+        self.loop_stream = torch.cuda.Stream()
         self._tls = threading.local()
         self._ix = 0
         self._lock = threading.Lock()
@@ -77,7 +81,7 @@ class DeviceEngine:
         return s, bd
 
     def batch(self, systems, restart, rtol, max_it, graph):
-        return nnms.Batch(systems, restart, rtol, max_it, graph=graph)
+        return nnms.Batch(systems, restart, rtol, max_it, graph=graph, stream=self.loop_stream)
 
     def start(self, batch, slot: int, bd) -> None:
         batch.start(slot, bd.data_ptr())
@@ -119,7 +123,10 @@ class Server:
         self.batch_forms = 0
         self.steps = 0
         # host seconds spent in each part of the loop
-        self.t_form = 0.0  # building and destroying batch plans
+        self.t_form = 0.0  # building and destroying batch plans, starting new slots
+        self.t_create = 0.0  # of which: building plans
+        self.t_release = 0.0  # of which: destroying plans
+        self.t_start = 0.0  # of which: starting new slots
         self.t_step = 0.0  # launching one Arnoldi step and waiting for it
         self.t_result = 0.0  # reading slot results, releasing finished systems
 
@@ -172,12 +179,18 @@ class Server:
                 members = active + ready
                 batch = eng.batch([m[1] for m in members], self.restart, self.rtol, self.max_it, self.graph)
                 self.batch_forms += 1
+                t1 = time.perf_counter()
                 if old is not None:
                     eng.release_batch(old)
+                t2 = time.perf_counter()
                 for k in range(len(active), len(members)):
                     eng.start(batch, k, members[k][2])
                 active, ready = members, []
-                self.t_form += time.perf_counter() - tf
+                t3 = time.perf_counter()
+                self.t_form += t3 - tf
+                self.t_create += t1 - tf
+                self.t_release += t2 - t1
+                self.t_start += t3 - t2
             if batch is None or not active:
                 # idle: wait for the next arrival or assembly
                 time.sleep(0.0005)
@@ -204,8 +217,12 @@ class Server:
                 old = batch
                 batch = eng.batch([m[1] for m in still], self.restart, self.rtol, self.max_it, self.graph) if still else None
                 self.batch_forms += 1
+                t1 = time.perf_counter()
                 eng.release_batch(old)
-                self.t_form += time.perf_counter() - tf
+                t2 = time.perf_counter()
+                self.t_form += t2 - tf
+                self.t_create += t1 - tf
+                self.t_release += t2 - t1
                 tr = time.perf_counter()
                 for r, s, bd in finished:
                     eng.release_system(s)
@@ -221,7 +238,9 @@ class Server:
         self.pool.shutdown(wait=True)
         out = self.stats(reqs)
         setup = [r.t_ready - r.t_admit for r in reqs if r.status == "done"]
-        out.update({"max_bytes_admitted": self.max_used, "host_s_batch_forms": self.t_form, "host_s_steps": self.t_step,
+        out.update({"max_bytes_admitted": self.max_used, "host_s_batch_forms": self.t_form,
+                    "host_s_batch_create": self.t_create, "host_s_batch_release": self.t_release,
+                    "host_s_slot_start": self.t_start, "host_s_steps": self.t_step,
                     "host_s_results": self.t_result,
                     "numeric_setup_ms_mean": float(np.mean(setup) * 1e3) if setup else float("nan")})
         return out
