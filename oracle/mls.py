@@ -1,0 +1,129 @@
+"""Overlapping moving-least-squares (MLS) interpolation between non-nested
+meshes (oracle; test infrastructure only).
+
+Section 3.2 of the paper.  A value at a target node x* is interpolated from
+the source nodes x~_n of the neighbourhood N(x*) = { x~_n : |x~_n - x*| <
+rho(x*) } by minimising the weighted loss
+
+    L(a) = sum_n w(x* - x~_n) [p(x~_n)^T a - u~_n]^2,
+    w = 1 - 6 r^2 + 8 r^3 - 3 r^4,   r = |x* - x~_n| / rho(x*),
+
+over the coefficients a of the polynomial space with basis p.  Its
+stationary point solves P1 a = P2 u~ with P1 = P D P^T, P2 = P D, where the
+columns of P are p(x~_n) and D = diag(w) (Theorem 1: unique when
+rank(P) = |P|).  The interpolated value is u* = p(x*)^T P1^{-1} P2 u~, so the
+row of the operator for x* is phi = p(x*)^T P1^{-1} P2, and stacking the rows
+of every target node gives the operator (equation *interpolation f*).
+
+Readings where the paper leaves a choice open (the library takes the same):
+  * the polynomial space is linear, p(x) = [1, x, y, z] (|P| = 4), the space
+    of the P1 unknowns;
+  * the scale starts at rho_0 = alpha * h, h = the mean edge length of the
+    source mesh, alpha = 1.5 by default, and grows by the factor 1.25 until
+    rank(P) = 4 (the paper grows rho until the rank is full);
+  * rank(P) = 4 is decided on the centred, rho-scaled basis
+    [1, (x - x*) / rho] (the same space): its smallest singular value must
+    exceed 1e-6 times its largest;
+  * on one device the whole source level is local, so the neighbourhood is
+    not clipped to the overlapping subdomain of the target's processor;
+  * homogeneous Dirichlet conditions: rows of Dirichlet target nodes are
+    empty and the weights of Dirichlet source nodes are dropped after the
+    solve (as for the barycentric transfer).
+
+The coarse-to-fine operator P_l is this interpolation from coarse (source)
+to fine (target) nodes; the fine-to-coarse transfer used by the V-cycle is
+its transpose.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+from scipy.spatial import cKDTree
+
+ALPHA = 1.5
+GROWTH = 1.25
+RANK_TOL = 1e-6
+
+
+def weight(r):
+    """w as a function of r = distance / rho (the loss of Section 3.2)."""
+    r = np.asarray(r, dtype=np.float64)
+    return 1.0 - 6.0 * r ** 2 + 8.0 * r ** 3 - 3.0 * r ** 4
+
+
+def basis(x):
+    """Linear basis p(x) = [1, x, y, z] as columns: shape [4, m]."""
+    x = np.atleast_2d(np.asarray(x, dtype=np.float64))
+    return np.vstack([np.ones(len(x)), x.T])
+
+
+def mean_edge_length(xyz, tets) -> float:
+    """Mean length of the distinct edges of a tetrahedral mesh."""
+    pairs = np.array([(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)])
+    e = np.sort(tets[:, pairs].reshape(-1, 2), axis=1)
+    e = np.unique(e, axis=0)
+    return float(np.linalg.norm(xyz[e[:, 0]] - xyz[e[:, 1]], axis=1).mean())
+
+
+def full_rank(xstar, pts, rho) -> bool:
+    """rank(P) = |P| for the neighbours pts of xstar (Theorem 1's condition)."""
+    if len(pts) < 4:
+        return False
+    Q = basis((pts - xstar) / rho)
+    s = np.linalg.svd(Q, compute_uv=False)
+    return bool(s[-1] > RANK_TOL * s[0])
+
+
+def mls_row(xstar, pts, rho):
+    """phi = p(x*)^T P1^{-1} P2 for the neighbours pts (all within rho)."""
+    r = np.linalg.norm(pts - xstar, axis=1) / rho
+    D = np.diag(weight(r))
+    P = basis(pts)
+    P1 = P @ D @ P.T
+    P2 = P @ D
+    return basis(xstar)[:, 0] @ np.linalg.solve(P1, P2)
+
+
+def neighbourhood(tree, src_xyz, xstar, rho0):
+    """(ids, rho): source nodes strictly within rho of x*, rho grown from rho0
+    by GROWTH until the neighbourhood has full rank."""
+    rho = rho0
+    for _ in range(200):
+        ids = np.array(sorted(tree.query_ball_point(xstar, rho)), dtype=np.int64)
+        if len(ids):
+            ids = ids[np.linalg.norm(src_xyz[ids] - xstar, axis=1) < rho]
+        if full_rank(xstar, src_xyz[ids], rho):
+            return ids, rho
+        rho *= GROWTH
+    raise ValueError("no full-rank neighbourhood")
+
+
+def interpolation(target, source, alpha: float = ALPHA, mask_dirichlet: bool = True, rows=None) -> sp.csr_matrix:
+    """MLS operator from source nodal values to target nodal values, shape
+    [target.nv, source.nv].  rows: optional subset of target nodes to build
+    (the other rows stay empty)."""
+    h = mean_edge_length(source.xyz, source.tets)
+    tree = cKDTree(source.xyz)
+    if rows is None:
+        rows = np.arange(target.nv)
+    ri, ci, vi = [], [], []
+    for v in rows:
+        if mask_dirichlet and target.dirichlet[v]:
+            continue
+        xs = target.xyz[v]
+        ids, rho = neighbourhood(tree, source.xyz, xs, alpha * h)
+        phi = mls_row(xs, source.xyz[ids], rho)
+        if mask_dirichlet:
+            keep = source.dirichlet[ids] == 0
+            ids, phi = ids[keep], phi[keep]
+        ri.append(np.full(len(ids), v))
+        ci.append(ids)
+        vi.append(phi)
+    if ri:
+        ri, ci, vi = np.concatenate(ri), np.concatenate(ci), np.concatenate(vi)
+    return sp.csr_matrix((vi, (ri, ci)), shape=(target.nv, source.nv))
+
+
+def prolongation(fine, coarse, alpha: float = ALPHA, mask_dirichlet: bool = True) -> sp.csr_matrix:
+    """P_l: coarse -> fine by MLS (the coarse nodes are the sources)."""
+    return interpolation(fine, coarse, alpha, mask_dirichlet)

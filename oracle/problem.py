@@ -14,7 +14,7 @@ from typing import List, Optional
 import numpy as np
 import scipy.sparse.linalg as spla
 
-from . import fem, krylov, multilevel, schwarz, transfer
+from . import fem, krylov, mls, multilevel, schwarz, transfer
 
 
 @dataclass
@@ -27,7 +27,9 @@ class OracleHierarchy:
     vcycle: multilevel.VCycle
 
 
-def build(problem, f: float = 1.0, locate=transfer.locate_bucket) -> OracleHierarchy:
+def build(problem, f: float = 1.0, locate=transfer.locate_bucket, mls_alpha: Optional[float] = None) -> OracleHierarchy:
+    """mls_alpha: None for the barycentric transfer, else the MLS transfer of
+    Section 3.2 with initial scale mls_alpha times the coarse mean edge."""
     meshes = problem.meshes
     L = len(meshes)
     A, P, parts, levels = [], [], [], []
@@ -38,7 +40,10 @@ def build(problem, f: float = 1.0, locate=transfer.locate_bucket) -> OracleHiera
         if l == 0:
             b = bl
     for l in range(L - 1):
-        P.append(transfer.interpolation(meshes[l], meshes[l + 1], locate=locate))
+        if mls_alpha is None:
+            P.append(transfer.interpolation(meshes[l], meshes[l + 1], locate=locate))
+        else:
+            P.append(mls.prolongation(meshes[l], meshes[l + 1], mls_alpha))
         owned, sets = schwarz.partition(meshes[l], problem.nparts[l], problem.overlap)
         parts.append((owned, sets))
         ras = schwarz.RAS(A[l], meshes[l].dirichlet, owned, sets)
