@@ -58,6 +58,10 @@ typedef enum {
 } nnms_status;
 
 typedef enum { NNMS_FP64 = 0, NNMS_MIXED = 1 } nnms_precision;
+/* Transfer between levels: barycentric P1 interpolation (each fine vertex
+ * located in a coarse tetrahedron) or the moving-least-squares interpolation
+ * of Section 3.2. */
+typedef enum { NNMS_TRANSFER_BARYCENTRIC = 0, NNMS_TRANSFER_MLS = 1 } nnms_transfer;
 
 typedef struct nnms_mesh nnms_mesh;
 typedef struct nnms_hierarchy nnms_hierarchy;
@@ -104,17 +108,28 @@ void nnms_mesh_destroy(nnms_mesh* m);
  * rows hold only their diagonal, Dirichlet columns are dropped from the
  * other rows), a partition of the interior vertices into nparts[l] owned
  * sets by recursive coordinate bisection and their extension by `overlap`
- * layers (Section 2.2), and the barycentric interpolation P_l from level
- * l+1 to level l with its transpose.  The coarsest level gets one dense
+ * layers (Section 2.2), and the interpolation P_l from level l+1 to level
+ * l with its transpose (the restriction).  The coarsest level gets one dense
  * "subdomain" holding all of its interior vertices (the direct solve).
  *
  * levels      L mesh handles, finest first (1 <= L <= NNMS_MAX_LEVELS).
  * opts        nparts[l]: power of two >= 1 for l < L-1 (0 selects
  *             max(2, 2^floor(log2(nv_l/1500))));  overlap >= 0;  its >= 1;
- *             precision NNMS_FP64 or NNMS_MIXED.
+ *             precision NNMS_FP64 or NNMS_MIXED;
+ *             transfer NNMS_TRANSFER_BARYCENTRIC (default) or
+ *             NNMS_TRANSFER_MLS: the row of P_l for a fine vertex x* is
+ *             the weighted least-squares fit of a linear polynomial to the
+ *             coarse vertices within rho of x* (Section 3.2, the loss with
+ *             w = 1 - 6r^2 + 8r^3 - 3r^4 and its stationary-point system),
+ *             evaluated at x*; rho starts at mls_alpha (default 1.0) times
+ *             the mean coarse edge length and grows by 1.25 until the
+ *             neighbourhood has full rank (Theorem 1).  The neighbourhood
+ *             is not clipped to a subdomain: the whole coarse level is
+ *             resident on the device.
  * alloc       device allocator or NULL (hipMalloc).
  * stream      stream for the uploads.
- * Errors: NNMS_ERR_INVALID_ARG, NNMS_ERR_POINT_LOCATION,
+ * Errors: NNMS_ERR_INVALID_ARG, NNMS_ERR_POINT_LOCATION (a fine vertex
+ *         outside the coarse mesh, or no full-rank MLS neighbourhood),
  *         NNMS_ERR_OUT_OF_MEMORY, NNMS_ERR_DEVICE.
  * nnms_hierarchy_setup_host builds the same structure without touching any
  * GPU (inspection and host tests); such a handle cannot be assembled.
@@ -124,7 +139,8 @@ typedef struct {
   int32_t overlap;
   int32_t its;
   int32_t precision;
-  int32_t reserved;
+  int32_t transfer;  /* nnms_transfer */
+  double mls_alpha;  /* MLS initial scale / mean coarse edge length (> 0) */
 } nnms_setup_opts;
 
 nnms_status nnms_setup_opts_default(nnms_setup_opts* o);
@@ -143,10 +159,10 @@ typedef struct {
   int32_t nparts;       /* subdomains (1 on the coarsest level) */
   int32_t max_block;    /* largest subdomain size */
   int32_t min_block;    /* smallest subdomain size */
-  int32_t reserved;
+  int32_t transfer;     /* nnms_transfer of P_l (smoothed levels) */
   int64_t s_total;      /* sum of subdomain sizes */
   int64_t factor_elems; /* dense factor entries stored, incl. 64-padding */
-  int64_t p_nnz;        /* entries of P_l^T (0 on the coarsest level) */
+  int64_t p_nnz;        /* entries of P_l and of P_l^T (0 on the coarsest level) */
 } nnms_level_info;
 
 nnms_status nnms_hierarchy_level_info(const nnms_hierarchy* h, int32_t level, nnms_level_info* out);
@@ -157,8 +173,15 @@ nnms_status nnms_hierarchy_csr(const nnms_hierarchy* h, int32_t level, int32_t* 
 nnms_status nnms_hierarchy_partition(const nnms_hierarchy* h, int32_t level, int32_t* owner_host,
                                      int64_t* s_ptr_host, int32_t* s_idx_host);
 /* P_level as 4 entries per fine vertex: idx_host[nv*4] coarse vertex ids,
- * w_host[nv*4] barycentric weights (0 for Dirichlet rows and columns). */
+ * w_host[nv*4] barycentric weights (0 for Dirichlet rows and columns).
+ * Barycentric transfer only (NNMS_ERR_INVALID_ARG for MLS). */
 nnms_status nnms_hierarchy_transfer(const nnms_hierarchy* h, int32_t level, int32_t* idx_host, double* w_host);
+/* P_level as CSR over the fine vertices, either transfer: row_ptr_host[nv+1],
+ * col_host[p_nnz], w_host[p_nnz] (p_nnz from nnms_hierarchy_level_info;
+ * Dirichlet rows empty, Dirichlet coarse columns left out, columns ascending
+ * within a row for MLS, in tetrahedron-vertex order for barycentric). */
+nnms_status nnms_hierarchy_transfer_csr(const nnms_hierarchy* h, int32_t level, int32_t* row_ptr_host,
+                                        int32_t* col_host, double* w_host);
 
 /* ---------------------------------------------------------------------------
  * assemble(mesh, kappa): numeric setup for one parameter.  On the device:

@@ -19,7 +19,7 @@ Readings where the paper leaves a choice open (the library takes the same):
   * the polynomial space is linear, p(x) = [1, x, y, z] (|P| = 4), the space
     of the P1 unknowns;
   * the scale starts at rho_0 = alpha * h, h = the mean edge length of the
-    source mesh, alpha = 1.5 by default, and grows by the factor 1.25 until
+    source mesh, alpha = 1.0 by default, and grows by the factor 1.25 until
     rank(P) = 4 (the paper grows rho until the rank is full);
   * rank(P) = 4 is decided on the centred, rho-scaled basis
     [1, (x - x*) / rho] (the same space): its smallest singular value must
@@ -40,7 +40,7 @@ import numpy as np
 import scipy.sparse as sp
 from scipy.spatial import cKDTree
 
-ALPHA = 1.5
+ALPHA = 1.0
 GROWTH = 1.25
 RANK_TOL = 1e-6
 

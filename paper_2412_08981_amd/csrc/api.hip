@@ -153,6 +153,10 @@ struct DevLevel {
   int32_t *pts_off = nullptr, *pts_col = nullptr;  // P^T in sliced ELL layout
   double* pts_w64 = nullptr;
   float* pts_w32 = nullptr;
+  int32_t *pn_off = nullptr, *pn_col = nullptr;  // MLS: -P in sliced ELL layout
+  double* pn_w64 = nullptr;
+  float* pn_w32 = nullptr;
+  int32_t transfer = NNMS_TRANSFER_BARYCENTRIC;
 };
 
 }  // namespace nnms
@@ -297,11 +301,22 @@ static hipError_t launch_ras_groups(const std::vector<RasGroup>& gs, bool add, h
 
 struct LevelPlan {
   std::vector<SpmvGroup> res, rst;
-  ProlongDesc* pro = nullptr;
+  ProlongDesc* pro = nullptr;  // barycentric systems (four entries per row)
   int pro_blocks = 0;
+  std::vector<SpmvGroup> prom;  // MLS systems: z_f - (-P) z_c, sliced ELL
   std::vector<RasGroup> ras;
-  int nd = 0;
+  int nd = 0;  // descriptors in pro
 };
+
+// z_f += P_l z_c for every system of a level plan
+template <typename T>
+static hipError_t launch_prolong_level(const LevelPlan& LP, hipStream_t s) {
+  if (LP.pro_blocks) {
+    const hipError_t e = launch_prolong<T>(LP.pro, LP.nd, LP.pro_blocks, s);
+    if (e != hipSuccess) return e;
+  }
+  return launch_spmv_groups<T>(LP.prom, s);
+}
 
 // Streams and pinned host words of plans are recycled instead of destroyed:
 // hipStreamDestroy and hipHostFree wait for the device, which would make
@@ -494,6 +509,7 @@ static void build_plan(Plan& P, const std::vector<nnms_system*>& sys, bool with_
     LevelPlan& LP = P.lev[l];
     std::vector<std::pair<int, SpmvDesc>> res, rst;
     std::vector<ProlongDesc> pro;
+    std::vector<std::pair<int, SpmvDesc>> prom;
     int bp = 0;
     for (auto* x : sys) {
       const HostLevel& hl = x->h->host.lev[l];
@@ -522,6 +538,14 @@ static void build_plan(Plan& P, const std::vector<nnms_system*>& sys, bool with_
       }
       e.x = sl.t, e.r = nullptr, e.y = sc.r, e.st = st, e.n = int(hc.nv), e.when = WHEN_RUNNING;
       rst.emplace_back(gp, e);
+      if (dl.transfer == NNMS_TRANSFER_MLS) {
+        SpmvDesc m{};
+        m.rp = dl.pn_off, m.col = dl.pn_col;
+        m.val = std::is_same<T, float>::value ? (const void*)dl.pn_w32 : (const void*)dl.pn_w64;
+        m.x = sc.z, m.r = sl.z, m.y = sl.z, m.st = st, m.n = int(hl.nv), m.when = WHEN_RUNNING;
+        prom.emplace_back(0, m);
+        continue;
+      }
       ProlongDesc pd{};
       pd.idx = dl.p_idx;
       pd.w = std::is_same<T, float>::value ? (const void*)dl.p_w32 : (const void*)dl.p_w64;
@@ -531,8 +555,10 @@ static void build_plan(Plan& P, const std::vector<nnms_system*>& sys, bool with_
     }
     LP.res = spmv_groups(P.mem, res, s);
     LP.rst = spmv_groups(P.mem, rst, s);
-    LP.pro = P.mem.upload(pro, s), LP.pro_blocks = bp;
-    LP.nd = int(sys.size());
+    if (!pro.empty()) LP.pro = P.mem.upload(pro, s);
+    LP.pro_blocks = bp;
+    LP.nd = int(pro.size());
+    LP.prom = spmv_groups(P.mem, prom, s);
     LP.ras = ras_groups_of(l, false);
   }
   P.coarse = ras_groups_of(L - 1, true);
@@ -598,7 +624,7 @@ static void enqueue_vcycle(Plan& P, hipStream_t s) {
   HIP_CHECK((launch_ras_groups<double, T>(P.coarse, false, s)));
   for (int l = L - 2; l >= 0; --l) {
     LevelPlan& LP = P.lev[l];
-    HIP_CHECK(launch_prolong<T>(LP.pro, LP.nd, LP.pro_blocks, s));
+    HIP_CHECK(launch_prolong_level<T>(LP, s));
     for (int k = 0; k < its; ++k) {
       HIP_CHECK(launch_spmv_groups<T>(LP.res, s));
       HIP_CHECK((launch_ras_groups<T, T>(LP.ras, true, s)));
@@ -738,7 +764,9 @@ static void default_tuning(nnms_tuning& t) {
 
 static void build_host(const nnms_mesh* const* levels, int32_t L, const nnms_setup_opts* opts, HostHierarchy& H) {
   if (!levels || L < 1 || L > NNMS_MAX_LEVELS || !opts) throw Error(NNMS_ERR_INVALID_ARG, "bad hierarchy arguments");
-  if (opts->overlap < 0 || opts->its < 1 || (opts->precision != NNMS_FP64 && opts->precision != NNMS_MIXED))
+  if (opts->overlap < 0 || opts->its < 1 || (opts->precision != NNMS_FP64 && opts->precision != NNMS_MIXED) ||
+      (opts->transfer != NNMS_TRANSFER_BARYCENTRIC && opts->transfer != NNMS_TRANSFER_MLS) ||
+      (opts->transfer == NNMS_TRANSFER_MLS && !(opts->mls_alpha > 0)))
     throw Error(NNMS_ERR_INVALID_ARG, "bad setup options");
   H.L = L;
   H.opts = *opts;
@@ -758,7 +786,12 @@ static void build_host(const nnms_mesh* const* levels, int32_t L, const nnms_set
     H.opts.nparts[l] = np;
     build_partition(lv, np, opts->overlap, direct);
   }
-  for (int l = 0; l + 1 < L; ++l) build_transfer(H.lev[l], H.lev[l + 1]);
+  for (int l = 0; l + 1 < L; ++l) {
+    if (opts->transfer == NNMS_TRANSFER_MLS)
+      build_transfer_mls(H.lev[l], H.lev[l + 1], opts->mls_alpha);
+    else
+      build_transfer(H.lev[l], H.lev[l + 1]);
+  }
 }
 
 extern "C" nnms_status nnms_hierarchy_setup_host(const nnms_mesh* const* levels, int32_t L, const nnms_setup_opts* opts,
@@ -822,6 +855,13 @@ extern "C" nnms_status nnms_hierarchy_setup(const nnms_mesh* const* levels, int3
       d.pts_col = A.upload(hl.pts_col, s);
       d.pts_w64 = A.upload(hl.pts_w, s);
       d.pts_w32 = A.upload(convert<double, float>(hl.pts_w), s);
+      d.transfer = hl.transfer;
+      if (hl.transfer == NNMS_TRANSFER_MLS) {
+        d.pn_off = A.upload(hl.pn_off, s);
+        d.pn_col = A.upload(hl.pn_col, s);
+        d.pn_w64 = A.upload(hl.pn_w, s);
+        d.pn_w32 = A.upload(convert<double, float>(hl.pn_w), s);
+      }
     }
   }
   HIP_CHECK(hipStreamSynchronize(s));
@@ -857,6 +897,7 @@ extern "C" nnms_status nnms_hierarchy_level_info(const nnms_hierarchy* h, int32_
   o->s_total = int64_t(lv.s_idx.size());
   o->factor_elems = lv.fac_elems;
   o->p_nnz = int64_t(lv.pt_col.size());
+  o->transfer = lv.transfer;
   return NNMS_OK;
   ABI_END
 }
@@ -887,8 +928,22 @@ extern "C" nnms_status nnms_hierarchy_transfer(const nnms_hierarchy* h, int32_t 
   ABI_BEGIN
   if (!h || !idx || !w || level < 0 || level + 1 >= h->host.L) throw Error(NNMS_ERR_INVALID_ARG, "bad arguments");
   const HostLevel& lv = h->host.lev[level];
+  if (lv.transfer != NNMS_TRANSFER_BARYCENTRIC)
+    throw Error(NNMS_ERR_INVALID_ARG, "four-entry form exists for the barycentric transfer only");
   std::memcpy(idx, lv.p_idx.data(), lv.p_idx.size() * sizeof(int32_t));
   std::memcpy(w, lv.p_w.data(), lv.p_w.size() * sizeof(double));
+  return NNMS_OK;
+  ABI_END
+}
+
+extern "C" nnms_status nnms_hierarchy_transfer_csr(const nnms_hierarchy* h, int32_t level, int32_t* rp, int32_t* col,
+                                                   double* w) {
+  ABI_BEGIN
+  if (!h || !rp || !col || !w || level < 0 || level + 1 >= h->host.L) throw Error(NNMS_ERR_INVALID_ARG, "bad arguments");
+  const HostLevel& lv = h->host.lev[level];
+  std::memcpy(rp, lv.p_rp.data(), lv.p_rp.size() * sizeof(int32_t));
+  std::memcpy(col, lv.p_col.data(), lv.p_col.size() * sizeof(int32_t));
+  std::memcpy(w, lv.p_val.data(), lv.p_val.size() * sizeof(double));
   return NNMS_OK;
   ABI_END
 }
@@ -1177,9 +1232,9 @@ extern "C" nnms_status nnms_apply_prolong(nnms_system* s, int32_t level, const d
   put_vec(s, s->lev[level + 1].z, x, nc, P.stream);
   HIP_CHECK(hipMemsetAsync(s->lev[level].z, 0, nf * tsize(s), P.stream));
   if (s->prec == NNMS_FP64)
-    HIP_CHECK(launch_prolong<double>(P.lev[level].pro, 1, P.lev[level].pro_blocks, P.stream));
+    HIP_CHECK(launch_prolong_level<double>(P.lev[level], P.stream));
   else
-    HIP_CHECK(launch_prolong<float>(P.lev[level].pro, 1, P.lev[level].pro_blocks, P.stream));
+    HIP_CHECK(launch_prolong_level<float>(P.lev[level], P.stream));
   get_vec(s, y, s->lev[level].z, nf, P.stream);
   return NNMS_OK;
   ABI_END
@@ -1445,9 +1500,9 @@ extern "C" nnms_status nnms_time_kernel(nnms_system* s, int32_t kind, int32_t le
         HIP_CHECK(launch_spmv_groups<float>(P.lev[level].res, st));
     } else if (kind == 2) {
       if (f64)
-        HIP_CHECK(launch_prolong<double>(P.lev[level].pro, 1, P.lev[level].pro_blocks, st));
+        HIP_CHECK(launch_prolong_level<double>(P.lev[level], st));
       else
-        HIP_CHECK(launch_prolong<float>(P.lev[level].pro, 1, P.lev[level].pro_blocks, st));
+        HIP_CHECK(launch_prolong_level<float>(P.lev[level], st));
     } else {
       if (f64)
         HIP_CHECK(launch_spmv_groups<double>(P.lev[level].rst, st));

@@ -378,6 +378,239 @@ void build_transfer(HostLevel& fine, const HostLevel& coarse) {
   fine.pts_w.assign(src.size(), 0.0);
   for (size_t e = 0; e < src.size(); ++e)
     if (src[e] >= 0) fine.pts_w[e] = fine.pt_w[src[e]];
+  // the same operator as CSR over the fine vertices (inspection)
+  fine.p_rp.assign(nf + 1, 0);
+  fine.p_col.clear();
+  fine.p_val.clear();
+  for (int64_t v = 0; v < nf; ++v) {
+    if (!fine.dir[v])
+      for (int a = 0; a < 4; ++a) {
+        int32_t c = fine.p_idx[v * 4 + a];
+        if (coarse.dir[c]) continue;
+        fine.p_col.push_back(c);
+        fine.p_val.push_back(fine.p_w[v * 4 + a]);
+      }
+    fine.p_rp[v + 1] = int32_t(fine.p_col.size());
+  }
+  fine.transfer = NNMS_TRANSFER_BARYCENTRIC;
+}
+
+// ---------------------------------------------------------------------------
+// Moving-least-squares transfer (Section 3.2).  The row of P_l for a fine
+// vertex x* holds phi_n = q(x*)^T M^{-1} w_n q_n over the coarse vertices
+// x~_n with |x~_n - x*| < rho, where
+//   q(x) = [1, (x - x*) / rho]  the linear basis centred at x* and scaled by
+//                               rho (the space of [1, x, y, z], so the same
+//                               operator, with a well-conditioned M),
+//   w_n = 1 - 6 r^2 + 8 r^3 - 3 r^4,  r = |x~_n - x*| / rho,
+//   M = sum_n w_n q_n q_n^T  (the paper's P1; w_n q_n are P2's columns).
+// rho starts at alpha times the mean coarse edge length and grows by 1.25
+// until rank(P) = 4, decided as lambda_min > 1e-12 lambda_max of the
+// unweighted Gram matrix sum_n q_n q_n^T (singular values of P in the
+// centred basis above 1e-6 of the largest).  Coarse Dirichlet columns are
+// dropped after the solve; fine Dirichlet rows stay empty.
+// ---------------------------------------------------------------------------
+namespace {
+
+// eigenvalues of a symmetric 4x4 matrix by cyclic Jacobi rotations
+void sym4_eigenvalues(double A[4][4], double ev[4]) {
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0, diag = 0;
+    for (int i = 0; i < 4; ++i) {
+      diag += A[i][i] * A[i][i];
+      for (int j = i + 1; j < 4; ++j) off += A[i][j] * A[i][j];
+    }
+    if (off <= 1e-34 * diag) break;
+    for (int p = 0; p < 3; ++p)
+      for (int q = p + 1; q < 4; ++q) {
+        if (A[p][q] == 0.0) continue;
+        const double th = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+        const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+        for (int k = 0; k < 4; ++k) {  // columns p, q
+          const double akp = A[k][p], akq = A[k][q];
+          A[k][p] = c * akp - sn * akq, A[k][q] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < 4; ++k) {  // rows p, q
+          const double apk = A[p][k], aqk = A[q][k];
+          A[p][k] = c * apk - sn * aqk, A[q][k] = sn * apk + c * aqk;
+        }
+      }
+  }
+  for (int i = 0; i < 4; ++i) ev[i] = A[i][i];
+}
+
+// c = M^{-1} e_0 for a symmetric positive definite 4x4 M (Cholesky)
+bool spd4_solve_e0(const double M[4][4], double c[4]) {
+  double L[4][4] = {};
+  for (int j = 0; j < 4; ++j) {
+    double d = M[j][j];
+    for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
+    if (!(d > 0)) return false;
+    L[j][j] = std::sqrt(d);
+    for (int i = j + 1; i < 4; ++i) {
+      double v = M[i][j];
+      for (int k = 0; k < j; ++k) v -= L[i][k] * L[j][k];
+      L[i][j] = v / L[j][j];
+    }
+  }
+  double y[4];
+  for (int i = 0; i < 4; ++i) {
+    double v = (i == 0) ? 1.0 : 0.0;
+    for (int k = 0; k < i; ++k) v -= L[i][k] * y[k];
+    y[i] = v / L[i][i];
+  }
+  for (int i = 3; i >= 0; --i) {
+    double v = y[i];
+    for (int k = i + 1; k < 4; ++k) v -= L[k][i] * c[k];
+    c[i] = v / L[i][i];
+  }
+  return true;
+}
+
+}  // namespace
+
+double mean_edge_length(const HostLevel& lv) {
+  std::vector<uint64_t> e;
+  e.reserve(size_t(lv.nt) * 6);
+  for (int64_t t = 0; t < lv.nt; ++t)
+    for (int a = 0; a < 4; ++a)
+      for (int b = a + 1; b < 4; ++b) {
+        uint64_t i = uint32_t(lv.tets[t * 4 + a]), j = uint32_t(lv.tets[t * 4 + b]);
+        if (i > j) std::swap(i, j);
+        e.push_back((i << 32) | j);
+      }
+  std::sort(e.begin(), e.end());
+  e.erase(std::unique(e.begin(), e.end()), e.end());
+  double sum = 0;
+  for (uint64_t k : e) {
+    const double* x = &lv.xyz[size_t(k >> 32) * 3];
+    const double* y = &lv.xyz[size_t(k & 0xffffffffu) * 3];
+    sum += std::sqrt((x[0] - y[0]) * (x[0] - y[0]) + (x[1] - y[1]) * (x[1] - y[1]) + (x[2] - y[2]) * (x[2] - y[2]));
+  }
+  return e.empty() ? 0.0 : sum / double(e.size());
+}
+
+void build_transfer_mls(HostLevel& fine, const HostLevel& coarse, double alpha) {
+  if (!(alpha > 0)) throw Error(NNMS_ERR_INVALID_ARG, "MLS scale factor must be positive");
+  const double rho0 = alpha * mean_edge_length(coarse);
+  if (!(rho0 > 0)) throw Error(NNMS_ERR_INVALID_ARG, "degenerate coarse mesh");
+  const int64_t nc = coarse.nv, nf = fine.nv;
+  // uniform bucket grid over the coarse vertices, cell edge rho0
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int64_t v = 0; v < nc; ++v)
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = std::min(lo[a], coarse.xyz[v * 3 + a]);
+      hi[a] = std::max(hi[a], coarse.xyz[v * 3 + a]);
+    }
+  int nb[3];
+  for (int a = 0; a < 3; ++a) nb[a] = std::max(1, std::min(1024, int(std::floor((hi[a] - lo[a]) / rho0)) + 1));
+  auto cell = [&](double x, int a) {
+    int b = int(std::floor((x - lo[a]) / rho0));
+    return std::min(std::max(b, 0), nb[a] - 1);
+  };
+  const int64_t ncell = int64_t(nb[0]) * nb[1] * nb[2];
+  std::vector<int32_t> cptr(ncell + 1, 0), citem(nc);
+  for (int64_t v = 0; v < nc; ++v) {
+    const double* x = &coarse.xyz[v * 3];
+    cptr[cell(x[0], 0) + int64_t(nb[0]) * (cell(x[1], 1) + int64_t(nb[1]) * cell(x[2], 2)) + 1]++;
+  }
+  for (int64_t c = 0; c < ncell; ++c) cptr[c + 1] += cptr[c];
+  {
+    std::vector<int32_t> fill(cptr.begin(), cptr.end() - 1);
+    for (int64_t v = 0; v < nc; ++v) {
+      const double* x = &coarse.xyz[v * 3];
+      citem[fill[cell(x[0], 0) + int64_t(nb[0]) * (cell(x[1], 1) + int64_t(nb[1]) * cell(x[2], 2))]++] = int32_t(v);
+    }
+  }
+  fine.p_idx.assign(nf * 4, 0);  // the four-entry form is not used by this transfer
+  fine.p_w.assign(nf * 4, 0.0);
+  fine.ncoarse = nc;
+  fine.p_rp.assign(nf + 1, 0);
+  fine.p_col.clear();
+  fine.p_val.clear();
+  std::vector<int32_t> ids;
+  std::vector<double> q, w;
+  for (int64_t v = 0; v < nf; ++v) {
+    fine.p_rp[v + 1] = fine.p_rp[v];
+    if (fine.dir[v]) continue;
+    const double* xs = &fine.xyz[v * 3];
+    double rho = rho0;
+    bool ok = false;
+    for (int grow = 0; grow < 200 && !ok; ++grow, rho *= 1.25) {
+      ids.clear();
+      int bl[3], bh[3];
+      for (int a = 0; a < 3; ++a) bl[a] = cell(xs[a] - rho, a), bh[a] = cell(xs[a] + rho, a);
+      for (int k = bl[2]; k <= bh[2]; ++k)
+        for (int j = bl[1]; j <= bh[1]; ++j)
+          for (int i = bl[0]; i <= bh[0]; ++i) {
+            const int64_t c = i + int64_t(nb[0]) * (j + int64_t(nb[1]) * k);
+            for (int32_t e = cptr[c]; e < cptr[c + 1]; ++e) {
+              const double* y = &coarse.xyz[size_t(citem[e]) * 3];
+              const double d2 = (y[0] - xs[0]) * (y[0] - xs[0]) + (y[1] - xs[1]) * (y[1] - xs[1]) +
+                                (y[2] - xs[2]) * (y[2] - xs[2]);
+              if (std::sqrt(d2) < rho) ids.push_back(citem[e]);
+            }
+          }
+      if (ids.size() < 4) continue;
+      std::sort(ids.begin(), ids.end());
+      const size_t m = ids.size();
+      q.resize(m * 4), w.resize(m);
+      double G[4][4] = {}, M[4][4] = {};
+      for (size_t n = 0; n < m; ++n) {
+        const double* y = &coarse.xyz[size_t(ids[n]) * 3];
+        double* qn = &q[n * 4];
+        qn[0] = 1.0;
+        for (int a = 0; a < 3; ++a) qn[a + 1] = (y[a] - xs[a]) / rho;
+        const double r = std::sqrt(qn[1] * qn[1] + qn[2] * qn[2] + qn[3] * qn[3]);
+        w[n] = 1.0 + r * r * (-6.0 + r * (8.0 - 3.0 * r));
+        for (int i = 0; i < 4; ++i)
+          for (int j = 0; j < 4; ++j) G[i][j] += qn[i] * qn[j], M[i][j] += w[n] * qn[i] * qn[j];
+      }
+      double ev[4];
+      sym4_eigenvalues(G, ev);
+      const double emax = std::max(std::max(ev[0], ev[1]), std::max(ev[2], ev[3]));
+      const double emin = std::min(std::min(ev[0], ev[1]), std::min(ev[2], ev[3]));
+      if (!(emin > 1e-12 * emax)) continue;
+      double c[4];
+      if (!spd4_solve_e0(M, c)) continue;
+      for (size_t n = 0; n < m; ++n) {
+        if (coarse.dir[ids[n]]) continue;
+        const double* qn = &q[n * 4];
+        fine.p_col.push_back(ids[n]);
+        fine.p_val.push_back(w[n] * (c[0] * qn[0] + c[1] * qn[1] + c[2] * qn[2] + c[3] * qn[3]));
+      }
+      fine.p_rp[v + 1] = int32_t(fine.p_col.size());
+      ok = true;
+    }
+    if (!ok) throw Error(NNMS_ERR_POINT_LOCATION, "no full-rank MLS neighbourhood for fine vertex " + std::to_string(v));
+    if (fine.p_col.size() > size_t(INT32_MAX / 2)) throw Error(NNMS_ERR_INVALID_ARG, "MLS transfer too large");
+  }
+  // explicit transpose: rows = coarse vertices, entries ordered by fine id
+  fine.pt_rp.assign(nc + 1, 0);
+  for (int32_t c : fine.p_col) fine.pt_rp[c + 1]++;
+  for (int64_t c = 0; c < nc; ++c) fine.pt_rp[c + 1] += fine.pt_rp[c];
+  fine.pt_col.resize(fine.pt_rp[nc]);
+  fine.pt_w.resize(fine.pt_rp[nc]);
+  std::vector<int32_t> fill(fine.pt_rp.begin(), fine.pt_rp.end() - 1);
+  for (int64_t v = 0; v < nf; ++v)
+    for (int32_t e = fine.p_rp[v]; e < fine.p_rp[v + 1]; ++e) {
+      const int32_t c = fine.p_col[e];
+      fine.pt_col[fill[c]] = int32_t(v);
+      fine.pt_w[fill[c]++] = fine.p_val[e];
+    }
+  std::vector<int32_t> src;
+  build_sell_layout(fine.pt_rp, fine.pt_col, nc, fine.pts_off, fine.pts_col, src);
+  fine.pts_w.assign(src.size(), 0.0);
+  for (size_t e = 0; e < src.size(); ++e)
+    if (src[e] >= 0) fine.pts_w[e] = fine.pt_w[src[e]];
+  // the prolongation as sliced ELL holding -P: the residual form of the
+  // sliced-ELL product, y = r - A x with r = y = z_f, adds P z_c to z_f
+  build_sell_layout(fine.p_rp, fine.p_col, nf, fine.pn_off, fine.pn_col, src);
+  fine.pn_w.assign(src.size(), 0.0);
+  for (size_t e = 0; e < src.size(); ++e)
+    if (src[e] >= 0) fine.pn_w[e] = -fine.p_val[src[e]];
+  fine.transfer = NNMS_TRANSFER_MLS;
 }
 
 }  // namespace nnms
@@ -445,5 +678,7 @@ extern "C" nnms_status nnms_setup_opts_default(nnms_setup_opts* o) {
   o->overlap = 1;
   o->its = 3;
   o->precision = NNMS_FP64;
+  o->transfer = NNMS_TRANSFER_BARYCENTRIC;
+  o->mls_alpha = 1.0;
   return NNMS_OK;
 }

@@ -69,6 +69,14 @@ struct HostLevel {
   std::vector<int32_t> pts_off, pts_col;
   std::vector<double> pts_w;
   int64_t ncoarse = 0;
+  // transfer kind; P_l as CSR over the fine vertices (Dirichlet rows empty,
+  // Dirichlet coarse columns dropped) for both kinds
+  int32_t transfer = NNMS_TRANSFER_BARYCENTRIC;
+  std::vector<int32_t> p_rp, p_col;
+  std::vector<double> p_val;
+  // MLS only: -P_l in the sliced ELL layout (the prolongation's launch)
+  std::vector<int32_t> pn_off, pn_col;
+  std::vector<double> pn_w;
 };
 
 struct HostHierarchy {
@@ -87,6 +95,10 @@ void build_sell_layout(const std::vector<int32_t>& rp, const std::vector<int32_t
 void build_sell(HostLevel& lv);
 void build_partition(HostLevel& lv, int nparts, int overlap, bool direct);
 void build_transfer(HostLevel& fine, const HostLevel& coarse);
+// moving-least-squares transfer (Section 3.2), initial scale alpha times the
+// mean coarse edge length
+void build_transfer_mls(HostLevel& fine, const HostLevel& coarse, double alpha);
+double mean_edge_length(const HostLevel& lv);
 int default_nparts(int64_t nv);
 
 }  // namespace nnms

@@ -32,6 +32,7 @@ _lib = C.CDLL(LIB_PATH)
 MAX_LEVELS = 8
 MAX_RESTART = 64
 FP64, MIXED = 0, 1
+BARYCENTRIC, MLS = 0, 1  # transfer between levels
 DEVICE_PTRS, NO_GRAPH = 1, 2
 
 STATUS = {
@@ -49,12 +50,12 @@ class NNMSError(RuntimeError):
 
 class setup_opts(C.Structure):
     _fields_ = [("nparts", C.c_int32 * MAX_LEVELS), ("overlap", C.c_int32), ("its", C.c_int32),
-                ("precision", C.c_int32), ("reserved", C.c_int32)]
+                ("precision", C.c_int32), ("transfer", C.c_int32), ("mls_alpha", C.c_double)]
 
 
 class level_info(C.Structure):
     _fields_ = [("nv", C.c_int64), ("nt", C.c_int64), ("ninterior", C.c_int64), ("nnz", C.c_int64),
-                ("nparts", C.c_int32), ("max_block", C.c_int32), ("min_block", C.c_int32), ("reserved", C.c_int32),
+                ("nparts", C.c_int32), ("max_block", C.c_int32), ("min_block", C.c_int32), ("transfer", C.c_int32),
                 ("s_total", C.c_int64), ("factor_elems", C.c_int64), ("p_nnz", C.c_int64)]
 
 
@@ -115,6 +116,7 @@ _sig = {
     "nnms_hierarchy_csr": (C.c_int, [vp, C.c_int32, vp, vp]),
     "nnms_hierarchy_partition": (C.c_int, [vp, C.c_int32, vp, vp, vp]),
     "nnms_hierarchy_transfer": (C.c_int, [vp, C.c_int32, vp, vp]),
+    "nnms_hierarchy_transfer_csr": (C.c_int, [vp, C.c_int32, vp, vp, vp]),
     "nnms_hierarchy_system_bytes": (C.c_int64, [vp, C.c_int32]),
     "nnms_assemble": (C.c_int, [vp, C.POINTER(kappa_t), C.c_double, vp, C.POINTER(vp)]),
     "nnms_system_destroy": (C.c_int, [vp]),
@@ -219,12 +221,14 @@ class Hierarchy:
     """setup(hierarchy): nnms_hierarchy_setup (device) or _setup_host (host only)."""
 
     def __init__(self, meshes: Sequence[Mesh], nparts: Sequence[int] = (), overlap: int = 1, its: int = 3,
-                 precision: int = FP64, device: bool = True, torch_alloc: bool = False, stream=None):
+                 precision: int = FP64, device: bool = True, torch_alloc: bool = False, stream=None,
+                 transfer: int = BARYCENTRIC, mls_alpha: float = 1.0):
         o = setup_opts()
         _check(_lib.nnms_setup_opts_default(C.byref(o)))
         for l, p in enumerate(nparts):
             o.nparts[l] = int(p)
         o.overlap, o.its, o.precision = overlap, its, precision
+        o.transfer, o.mls_alpha = transfer, mls_alpha
         self.meshes = list(meshes)
         arr = (C.c_void_p * len(meshes))(*[m.handle for m in meshes])
         h = C.c_void_p()
@@ -267,6 +271,15 @@ class Hierarchy:
         w = np.empty(li.nv * 4, dtype=np.float64)
         _check(_lib.nnms_hierarchy_transfer(self.handle, level, _ptr(idx), _ptr(w)))
         return idx.reshape(-1, 4), w.reshape(-1, 4)
+
+    def transfer_csr(self, level: int):
+        """P_level as CSR (row_ptr, col, w) over the fine vertices."""
+        li = self.level_info(level)
+        rp = np.empty(li.nv + 1, dtype=np.int32)
+        col = np.empty(li.p_nnz, dtype=np.int32)
+        w = np.empty(li.p_nnz, dtype=np.float64)
+        _check(_lib.nnms_hierarchy_transfer_csr(self.handle, level, _ptr(rp), _ptr(col), _ptr(w)))
+        return rp, col, w
 
     def get_tuning(self) -> dict:
         t = tuning_t()

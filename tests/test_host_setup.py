@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from oracle import schwarz, transfer
+from oracle import mls, schwarz, transfer
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -66,6 +66,62 @@ def test_pattern_partition_transfer_match_oracle(cfg):
         else:
             owner, sets = h.partition(l)
             assert len(sets) == 1 and np.array_equal(sets[0], np.nonzero(m.dirichlet == 0)[0])
+
+
+def _csr_dense(rp, col, w, nr, nc):
+    P = np.zeros((nr, nc))
+    for i in range(nr):
+        for e in range(rp[i], rp[i + 1]):
+            P[i, col[e]] += w[e]
+    return P
+
+
+@pytest.mark.parametrize("alpha", [1.0, 1.5])
+@pytest.mark.parametrize("cfg", ["cube16", "tiny3"])
+def test_mls_transfer_matches_oracle(cfg, alpha):
+    if cfg == "cube16":
+        pb = W.cube16_two_level()
+    else:
+        pb = W.Problem("tiny3", [W.kuhn_cube(9, 1), W.kuhn_cube(5, 2), W.kuhn_cube(3, 3)], [4, 2], W.KappaField())
+    ms = [nnms.Mesh.from_workload(m) for m in pb.meshes]
+    h = nnms.Hierarchy(ms, pb.nparts, device=False, transfer=nnms.MLS, mls_alpha=alpha)
+    for l in range(len(pb.meshes) - 1):
+        f, c = pb.meshes[l], pb.meshes[l + 1]
+        li = h.level_info(l)
+        assert li.transfer == nnms.MLS
+        rp, col, w = h.transfer_csr(l)
+        P_or = mls.interpolation(f, c, alpha).tocsr()
+        P_or.sort_indices()
+        # same neighbourhoods (same scale decisions), values to rounding
+        assert np.array_equal(rp, P_or.indptr)
+        assert np.array_equal(col, P_or.indices)
+        assert np.abs(w - P_or.data).max() <= 1e-12
+        with pytest.raises(nnms.NNMSError):
+            h.transfer(l)  # the four-entry form is barycentric only
+
+
+def test_barycentric_transfer_csr_matches_four_entry_form():
+    pb = W.cube16_two_level()
+    ms, h = _host(pb)
+    f, c = pb.meshes
+    rp, col, w = h.transfer_csr(0)
+    idx, w4 = h.transfer(0)
+    P4 = np.zeros((f.nv, c.nv))
+    for i in range(f.nv):
+        for a in range(4):
+            P4[i, idx[i, a]] += w4[i, a]
+    assert h.level_info(0).transfer == nnms.BARYCENTRIC
+    assert np.array_equal(_csr_dense(rp, col, w, f.nv, c.nv), P4)
+    assert np.all(c.dirichlet[col] == 0)
+
+
+def test_mls_rejects_bad_scale():
+    pb = W.cube16_two_level()
+    ms = [nnms.Mesh.from_workload(m) for m in pb.meshes]
+    for a in (0.0, -1.0, float("nan")):
+        with pytest.raises(nnms.NNMSError) as e:
+            nnms.Hierarchy(ms, pb.nparts, device=False, transfer=nnms.MLS, mls_alpha=a)
+        assert e.value.name == "INVALID_ARG"
 
 
 def test_level_info_counts():
