@@ -82,9 +82,13 @@ def spmv_bytes(h, level, s_bytes):
 
 
 def prolong_bytes(h, level, s_bytes):
-    """z_f += P z_c: four (index, weight) pairs per fine row, the coarse
-    vector once, the fine vector read and written."""
-    nf, nc = h.level_info(level).nv, h.level_info(level + 1).nv
+    """z_f += P z_c: four (index, weight) pairs per fine row (barycentric) or
+    one per entry of P (MLS), the coarse vector once, the fine vector read
+    and written."""
+    li, lc = h.level_info(level), h.level_info(level + 1)
+    nf, nc = li.nv, lc.nv
+    if li.transfer == 1:
+        return float(li.p_nnz * (4 + s_bytes) + nc * s_bytes + 2 * nf * s_bytes)
     return float(nf * (16 + 4 * s_bytes) + nc * s_bytes + 2 * nf * s_bytes)
 
 
@@ -94,7 +98,7 @@ def restrict_bytes(h, level, s_bytes):
     return float(li.p_nnz * (4 + s_bytes) + 4 * (lc.nv + 1) + (li.nv + lc.nv) * s_bytes)
 
 
-def cpu_baseline(pb, seconds_cap=60.0):
+def cpu_baseline(pb, seconds_cap=60.0, mls_alpha=None):
     """The FP64 oracle (NumPy/SciPy, LAPACK) on the host cores: setup once,
     then one full solve of the same problem; solves/s = 1 / solve time."""
     from oracle import problem as oprob
@@ -104,7 +108,7 @@ def cpu_baseline(pb, seconds_cap=60.0):
     except Exception:
         threads = os.cpu_count() or 1
     t0 = time.perf_counter()
-    oh = oprob.build(pb)
+    oh = oprob.build(pb, mls_alpha=mls_alpha)
     t1 = time.perf_counter()
     res = oprob.solve(oh)
     t2 = time.perf_counter()
@@ -295,6 +299,9 @@ def main():
     ap.add_argument("--burst", type=int, default=18, help="requests of the closed-loop capacity run")
     ap.add_argument("--budget-gib", type=float, default=160.0, help="device-memory budget of the serving loop")
     ap.add_argument("--batch", type=int, default=32, help="instances of the batched workload")
+    ap.add_argument("--transfer", default="barycentric", choices=["barycentric", "mls"],
+                    help="transfer between levels: barycentric P1 interpolation or moving least squares")
+    ap.add_argument("--mls-alpha", type=float, default=1.0, help="MLS initial scale / mean coarse edge length")
     ap.add_argument("--kernels-only", action="store_true",
                     help="run the copy reference and the fine-level smoother a few times each (for counter runs)")
     args = ap.parse_args()
@@ -317,7 +324,9 @@ def main():
     prec = nnms.MIXED if args.precision == "mixed" else nnms.FP64
     t0 = time.perf_counter()
     meshes = [nnms.Mesh.from_workload(m) for m in pb.meshes]
-    h = nnms.Hierarchy(meshes, pb.nparts, overlap=pb.overlap, its=pb.its, precision=prec)
+    mls_mode = args.transfer == "mls"
+    h = nnms.Hierarchy(meshes, pb.nparts, overlap=pb.overlap, its=pb.its, precision=prec,
+                       transfer=nnms.MLS if mls_mode else nnms.BARYCENTRIC, mls_alpha=args.mls_alpha)
     t1 = time.perf_counter()
     s = nnms.System(h, pb.kappa, 1.0)
     t2 = time.perf_counter()
@@ -387,8 +396,12 @@ def main():
         msr = s.time_kernel(1, lvl, reps=20)
         extra[f"residual_l{lvl}_ms"] = round(msr, 4)
         extra[f"residual_l{lvl}_GBs"] = round(spmv_bytes(h, lvl, sb) / (msr * 1e-3) / 1e9, 1)
-        extra[f"prolong_l{lvl}_ms"] = round(s.time_kernel(2, lvl, reps=20), 4)
-        extra[f"restrict_l{lvl}_ms"] = round(s.time_kernel(3, lvl, reps=20), 4)
+        msp = s.time_kernel(2, lvl, reps=20)
+        extra[f"prolong_l{lvl}_ms"] = round(msp, 4)
+        extra[f"prolong_l{lvl}_GBs"] = round(prolong_bytes(h, lvl, sb) / (msp * 1e-3) / 1e9, 1)
+        mst = s.time_kernel(3, lvl, reps=20)
+        extra[f"restrict_l{lvl}_ms"] = round(mst, 4)
+        extra[f"restrict_l{lvl}_GBs"] = round(restrict_bytes(h, lvl, sb) / (mst * 1e-3) / 1e9, 1)
     # numeric factorisation per level (fill + extraction + blocked LU) against the MFMA peak
     for lvl in range(h.L):
         fb = 8 if (prec == nnms.FP64 or lvl == h.L - 1) else 4
@@ -417,7 +430,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"jittered unit cube, 3 non-nested levels 48^3/24^3/10^3 "
                                f"(117649 fine vertices, 663552 tets), log-Gaussian kappa (8 centres), "
-                               f"64+8 subdomains overlap 1, FGMRES(30) to 1e-8, {args.precision}",
+                               f"64+8 subdomains overlap 1, FGMRES(30) to 1e-8, {args.precision}"
+                               + (f", MLS transfer (scale {args.mls_alpha} x mean coarse edge)" if mls_mode else ""),
                    "iterations": info.iterations, "relres": info.relres,
                    "numeric_setup_s": round(t_assemble, 4), "structure_setup_s": round(t1 - t0, 3),
                    "tuning": tuning},
@@ -428,7 +442,7 @@ def main():
         "kernels": extra,
     }
     if not args.no_cpu_baseline:
-        cb, oh, ores = cpu_baseline(pb)
+        cb, oh, ores = cpu_baseline(pb, mls_alpha=args.mls_alpha if mls_mode else None)
         out["cpu_baseline"] = cb
         from oracle import problem as oprob  # the oracle's own x* for the error report
         xs = ores.x

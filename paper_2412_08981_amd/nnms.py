@@ -295,7 +295,7 @@ class Hierarchy:
         parts = []
         for l in range(self.L):
             li = self.level_info(l)
-            parts.append(f"{li.nv}-{li.nnz}-{li.nparts}")
+            parts.append(f"{li.nv}-{li.nnz}-{li.nparts}" + (f"-mls{li.p_nnz}" if li.transfer == MLS else ""))
         return f"p{self.precision}_" + "_".join(parts)
 
     def system_bytes(self, restart: int = 30) -> int:
