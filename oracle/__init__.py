@@ -13,8 +13,9 @@ Modules
   transfer   barycentric point-location interpolation between meshes
   mls        moving-least-squares interpolation between meshes (Section 3.2)
   schwarz    coordinate-bisection partition, overlap, RAS (Section 2.2)
+  ilu        ILU(k) subdomain solver (level of fill, i-k-j elimination)
   multilevel V-cycle of Algorithm 2 (Section 3.3)
   krylov     right-preconditioned flexible GMRES (Section 2.1, Section 4)
   problem    glue that builds a whole hierarchy from a workload
 """
-from . import fem, transfer, mls, schwarz, multilevel, krylov, problem  # noqa: F401
+from . import fem, transfer, mls, ilu, schwarz, multilevel, krylov, problem  # noqa: F401

@@ -27,9 +27,12 @@ class OracleHierarchy:
     vcycle: multilevel.VCycle
 
 
-def build(problem, f: float = 1.0, locate=transfer.locate_bucket, mls_alpha: Optional[float] = None) -> OracleHierarchy:
+def build(problem, f: float = 1.0, locate=transfer.locate_bucket, mls_alpha: Optional[float] = None,
+          ilu_fill: Optional[List[int]] = None) -> OracleHierarchy:
     """mls_alpha: None for the barycentric transfer, else the MLS transfer of
-    Section 3.2 with initial scale mls_alpha times the coarse mean edge."""
+    Section 3.2 with initial scale mls_alpha times the coarse mean edge.
+    ilu_fill: None for exact subdomain solves, else the ILU fill level of
+    every smoothed level (the coarsest level is always solved directly)."""
     meshes = problem.meshes
     L = len(meshes)
     A, P, parts, levels = [], [], [], []
@@ -46,7 +49,7 @@ def build(problem, f: float = 1.0, locate=transfer.locate_bucket, mls_alpha: Opt
             P.append(mls.prolongation(meshes[l], meshes[l + 1], mls_alpha))
         owned, sets = schwarz.partition(meshes[l], problem.nparts[l], problem.overlap)
         parts.append((owned, sets))
-        ras = schwarz.RAS(A[l], meshes[l].dirichlet, owned, sets)
+        ras = schwarz.RAS(A[l], meshes[l].dirichlet, owned, sets, None if ilu_fill is None else ilu_fill[l])
         levels.append(multilevel.Level(A[l], meshes[l].dirichlet, ras, P[l]))
     levels.append(multilevel.Level(A[L - 1], meshes[L - 1].dirichlet))
     vc = multilevel.VCycle(levels, problem.its)

@@ -25,6 +25,8 @@ import numpy as np
 import scipy.linalg as sla
 import scipy.sparse as sp
 
+from . import ilu
+
 
 def rcb(points: np.ndarray, ids: np.ndarray, nparts: int, depth: int = 0):
     """Recursive coordinate bisection; returns a list of id arrays, in part
@@ -69,25 +71,30 @@ def partition(mesh, nparts: int, overlap: int = 1):
 
 class RAS:
     """B^{-1} r = sum_p (R^0_p)^T (A[S_p,S_p])^{-1} r[S_p], with LAPACK LU
-    (partial pivoting) as the exact subdomain solver."""
+    (partial pivoting) as the exact subdomain solver, or with ILU(ilu_fill)
+    of A[S_p,S_p] (natural ordering) in place of the exact solve (Section 4
+    runs the smoother with ILU(p) subdomain solvers)."""
 
-    def __init__(self, A: sp.csr_matrix, dmask: np.ndarray, owned, sets):
+    def __init__(self, A: sp.csr_matrix, dmask: np.ndarray, owned, sets, ilu_fill=None):
         self.dmask = dmask.astype(bool)
         self.owned = owned
         self.sets = sets
+        self.ilu_fill = ilu_fill
         self.lu = []
         self.pos = []
         Ad = A.tocsr()
         for own, S in zip(owned, sets):
-            Ap = Ad[S][:, S].toarray()
-            self.lu.append(sla.lu_factor(Ap))
+            if ilu_fill is None:
+                self.lu.append(sla.lu_factor(Ad[S][:, S].toarray()))
+            else:
+                self.lu.append(ilu.ILU(Ad[S][:, S].tocsr(), ilu_fill))
             self.pos.append(np.searchsorted(S, own))
 
     def apply(self, r: np.ndarray) -> np.ndarray:
         z = np.zeros_like(r)
         z[self.dmask] = r[self.dmask]  # identity rows of the eliminated boundary
         for lu, S, own, pos in zip(self.lu, self.sets, self.owned, self.pos):
-            y = sla.lu_solve(lu, r[S])
+            y = sla.lu_solve(lu, r[S]) if self.ilu_fill is None else lu.solve(r[S])
             z[own] = y[pos]
         return z
 
