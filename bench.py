@@ -68,6 +68,15 @@ def ras_bytes(h, level, s_bytes):
     return float(np.sum(n * n) * s_bytes + np.sum(n) * (s_bytes + 4) + np.sum(n) * s_bytes)
 
 
+def ilu_bytes(h, level, s_bytes):
+    """Algorithmic bytes of one ILU smoother application on `level`: every
+    factor entry once (value and local column), the row starts, diagonal
+    positions, level orders and index map of every row, the gathered input
+    and the scattered owned output."""
+    li = h.level_info(level)
+    return float(li.ilu_nnz * (s_bytes + 4) + li.s_total * (4 * 5 + s_bytes) + li.ninterior * s_bytes)
+
+
 def lu_flops(h, level):
     """Algorithmic flops of the level's dense subdomain LUs: (2/3) n_p^3 each
     (unpadded sizes; the kernels also run the 64-padding)."""
@@ -302,6 +311,9 @@ def main():
     ap.add_argument("--transfer", default="barycentric", choices=["barycentric", "mls"],
                     help="transfer between levels: barycentric P1 interpolation or moving least squares")
     ap.add_argument("--mls-alpha", type=float, default=1.0, help="MLS initial scale / mean coarse edge length")
+    ap.add_argument("--subsolver", default="lu", choices=["lu", "ilu"],
+                    help="subdomain solver of the smoother: dense LU or ILU(k)")
+    ap.add_argument("--ilu-fill", default="2,0", help="ILU level of fill per smoothed level (finest first)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="run the copy reference and the fine-level smoother a few times each (for counter runs)")
     args = ap.parse_args()
@@ -325,8 +337,11 @@ def main():
     t0 = time.perf_counter()
     meshes = [nnms.Mesh.from_workload(m) for m in pb.meshes]
     mls_mode = args.transfer == "mls"
+    ilu_mode = args.subsolver == "ilu"
+    ilu_fill = [int(k) for k in args.ilu_fill.split(",")]
     h = nnms.Hierarchy(meshes, pb.nparts, overlap=pb.overlap, its=pb.its, precision=prec,
-                       transfer=nnms.MLS if mls_mode else nnms.BARYCENTRIC, mls_alpha=args.mls_alpha)
+                       transfer=nnms.MLS if mls_mode else nnms.BARYCENTRIC, mls_alpha=args.mls_alpha,
+                       subsolver=nnms.ILU if ilu_mode else nnms.LU, ilu_fill=ilu_fill)
     t1 = time.perf_counter()
     s = nnms.System(h, pb.kappa, 1.0)
     t2 = time.perf_counter()
@@ -384,12 +399,13 @@ def main():
     # roofline of the dominant kernel: the fine-level smoother
     sb = 8 if prec == nnms.FP64 else 4
     ms = s.time_kernel(0, 0, reps=10)
-    ach = ras_bytes(h, 0, sb) / (ms * 1e-3) / 1e9
+    ach = (ilu_bytes(h, 0, sb) if ilu_mode else ras_bytes(h, 0, sb)) / (ms * 1e-3) / 1e9
     extra = {}
-    fac_bytes = (h.level_info(0).factor_elems * sb // 16) * 16
-    ms_read = s.time_kernel(5, 0, reps=5)
-    extra["read_reference_GBs"] = round(fac_bytes / (ms_read * 1e-3) / 1e9, 1)
-    extra["smoother_l0_frac_of_read_reference"] = round(ach / extra["read_reference_GBs"], 4)
+    if not ilu_mode:
+        fac_bytes = (h.level_info(0).factor_elems * sb // 16) * 16
+        ms_read = s.time_kernel(5, 0, reps=5)
+        extra["read_reference_GBs"] = round(fac_bytes / (ms_read * 1e-3) / 1e9, 1)
+        extra["smoother_l0_frac_of_read_reference"] = round(ach / extra["read_reference_GBs"], 4)
     for lvl in range(h.L):
         extra[f"smoother_l{lvl}_ms"] = round(s.time_kernel(0, lvl, reps=10), 4)
     for lvl in range(h.L - 1):
@@ -406,8 +422,10 @@ def main():
     for lvl in range(h.L):
         fb = 8 if (prec == nnms.FP64 or lvl == h.L - 1) else 4
         msf = s.time_kernel(6, lvl, reps=3)
-        tf = lu_flops(h, lvl) / (msf * 1e-3) / 1e12
         extra[f"factor_l{lvl}_ms"] = round(msf, 3)
+        if h.level_info(lvl).subsolver == nnms.ILU:
+            continue  # ILU factorisation: level-scheduled, no dense flops to count
+        tf = lu_flops(h, lvl) / (msf * 1e-3) / 1e12
         extra[f"factor_l{lvl}_TFLOPs"] = round(tf, 2)
         extra[f"factor_l{lvl}_frac_of_mfma_peak"] = round(tf / MFMA_PEAK_TFLOPS[fb], 4)
     extra["parametric_solves_per_s"] = round(1.0 / (t_assemble + el / args.steps), 3)
@@ -431,13 +449,16 @@ def main():
         "config": {"workload": f"jittered unit cube, 3 non-nested levels 48^3/24^3/10^3 "
                                f"(117649 fine vertices, 663552 tets), log-Gaussian kappa (8 centres), "
                                f"64+8 subdomains overlap 1, FGMRES(30) to 1e-8, {args.precision}"
-                               + (f", MLS transfer (scale {args.mls_alpha} x mean coarse edge)" if mls_mode else ""),
+                               + (f", MLS transfer (scale {args.mls_alpha} x mean coarse edge)" if mls_mode else "")
+                               + (f", ILU({args.ilu_fill}) subdomain solves" if ilu_mode else ""),
                    "iterations": info.iterations, "relres": info.relres,
                    "numeric_setup_s": round(t_assemble, 4), "structure_setup_s": round(t1 - t0, 3),
                    "tuning": tuning},
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": load_traffic(args.precision),
-                     "kernel": ("k_ras2 (fine-level smoother, two-block work items)" if tuning["ras_blocks"][0] == 2
+                     "frac": round(ach / HBM_PEAK_GBS, 4),
+                     "traffic": None if ilu_mode else load_traffic(args.precision),
+                     "kernel": ("k_ilu_apply (fine-level ILU smoother)" if ilu_mode else
+                                "k_ras2 (fine-level smoother, two-block work items)" if tuning["ras_blocks"][0] == 2
                                 else "k_ras (fine-level smoother)"), "ms": round(ms, 4)},
         "kernels": extra,
     }

@@ -62,6 +62,10 @@ typedef enum { NNMS_FP64 = 0, NNMS_MIXED = 1 } nnms_precision;
  * located in a coarse tetrahedron) or the moving-least-squares interpolation
  * of Section 3.2. */
 typedef enum { NNMS_TRANSFER_BARYCENTRIC = 0, NNMS_TRANSFER_MLS = 1 } nnms_transfer;
+/* Subdomain solver of the smoother: exact dense LU, or ILU(k) with level of
+ * fill k (Section 4 runs ILU(2) on the finest level and ILU(0) on coarser
+ * ones).  The coarsest level is always solved directly. */
+typedef enum { NNMS_SUBSOLVER_LU = 0, NNMS_SUBSOLVER_ILU = 1 } nnms_subsolver;
 
 typedef struct nnms_mesh nnms_mesh;
 typedef struct nnms_hierarchy nnms_hierarchy;
@@ -125,7 +129,14 @@ void nnms_mesh_destroy(nnms_mesh* m);
  *             the mean coarse edge length and grows by 1.25 until the
  *             neighbourhood has full rank (Theorem 1).  The neighbourhood
  *             is not clipped to a subdomain: the whole coarse level is
- *             resident on the device.
+ *             resident on the device;
+ *             subsolver NNMS_SUBSOLVER_LU (default: dense LU of every
+ *             overlapping subdomain matrix) or NNMS_SUBSOLVER_ILU: ILU(k)
+ *             of A[S_p, S_p] in natural ordering with k = ilu_fill[l]
+ *             (defaults 2 on level 0, 0 elsewhere), factorised on the
+ *             device at every assembly and applied by level-scheduled
+ *             triangular solves; a subdomain may hold at most 8192 rows
+ *             (FP64) or 16384 (mixed) with ILU.
  * alloc       device allocator or NULL (hipMalloc).
  * stream      stream for the uploads.
  * Errors: NNMS_ERR_INVALID_ARG, NNMS_ERR_POINT_LOCATION (a fine vertex
@@ -141,6 +152,8 @@ typedef struct {
   int32_t precision;
   int32_t transfer;  /* nnms_transfer */
   double mls_alpha;  /* MLS initial scale / mean coarse edge length (> 0) */
+  int32_t subsolver; /* nnms_subsolver of every smoothed level */
+  int32_t ilu_fill[NNMS_MAX_LEVELS]; /* ILU level of fill per smoothed level (>= 0) */
 } nnms_setup_opts;
 
 nnms_status nnms_setup_opts_default(nnms_setup_opts* o);
@@ -163,6 +176,9 @@ typedef struct {
   int64_t s_total;      /* sum of subdomain sizes */
   int64_t factor_elems; /* dense factor entries stored, incl. 64-padding */
   int64_t p_nnz;        /* entries of P_l and of P_l^T (0 on the coarsest level) */
+  int32_t subsolver;    /* nnms_subsolver of the level's smoother */
+  int32_t reserved2;
+  int64_t ilu_nnz;      /* entries of all ILU patterns of the level (0 without ILU) */
 } nnms_level_info;
 
 nnms_status nnms_hierarchy_level_info(const nnms_hierarchy* h, int32_t level, nnms_level_info* out);
@@ -182,6 +198,13 @@ nnms_status nnms_hierarchy_transfer(const nnms_hierarchy* h, int32_t level, int3
  * within a row for MLS, in tetrahedron-vertex order for barycentric). */
 nnms_status nnms_hierarchy_transfer_csr(const nnms_hierarchy* h, int32_t level, int32_t* row_ptr_host,
                                         int32_t* col_host, double* w_host);
+/* ILU levels: the ILU(k) pattern of every subdomain in local numbering (the
+ * subdomain's rows in the order of nnms_hierarchy_partition's S_p), rows of
+ * all subdomains concatenated: row_ptr_host[s_total+1] entry offsets,
+ * col_host[ilu_nnz] local columns, ascending within a row.
+ * NNMS_ERR_INVALID_ARG on a level without ILU. */
+nnms_status nnms_hierarchy_ilu_pattern(const nnms_hierarchy* h, int32_t level, int32_t* row_ptr_host,
+                                       int32_t* col_host);
 
 /* ---------------------------------------------------------------------------
  * assemble(mesh, kappa): numeric setup for one parameter.  On the device:
@@ -237,6 +260,13 @@ nnms_status nnms_system_factor(const nnms_system* s, int32_t level, int32_t part
  * floor(N/2).  The two-block triangular-solve work items apply them. */
 nnms_status nnms_system_factor_pairs(const nnms_system* s, int32_t level, int32_t part, double* xl_host, double* xu_host,
                                      int32_t* npairs_host);
+/* Both dense read-backs give NNMS_ERR_INVALID_ARG on an ILU level. */
+
+/* Read-back of the ILU factors of an ILU level: val_host[ilu_nnz] in the
+ * order of nnms_hierarchy_ilu_pattern, L's multipliers (unit diagonal not
+ * stored) below the diagonal, U on and above it; FP32 factors of mixed
+ * precision are widened. */
+nnms_status nnms_system_ilu_values(const nnms_system* s, int32_t level, double* val_host);
 
 /* ---------------------------------------------------------------------------
  * Operator applications, one call each, host vectors in and out (FP64 at

@@ -23,7 +23,7 @@ HIP_FLAGS = [
 ]
 CXX_FLAGS = ["-O2", "-fPIC", "-std=c++17", "-I", INC, "-I", CSRC]
 
-HIP_SOURCES = ["sparse.hip", "ras.hip", "lu.hip", "assemble.hip", "krylov.hip", "api.hip"]
+HIP_SOURCES = ["sparse.hip", "ras.hip", "lu.hip", "ilu.hip", "assemble.hip", "krylov.hip", "api.hip"]
 CXX_SOURCES = ["host_setup.cpp"]
 
 

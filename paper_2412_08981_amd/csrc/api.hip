@@ -157,6 +157,10 @@ struct DevLevel {
   double* pn_w64 = nullptr;
   float* pn_w32 = nullptr;
   int32_t transfer = NNMS_TRANSFER_BARYCENTRIC;
+  // ILU subdomain solver (subsolver == NNMS_SUBSOLVER_ILU)
+  int32_t subsolver = NNMS_SUBSOLVER_LU;
+  int32_t *ilu_rp = nullptr, *ilu_col = nullptr, *ilu_asrc = nullptr, *ilu_dpos = nullptr, *ilu_gid = nullptr;
+  int32_t *ilu_fperm = nullptr, *ilu_bperm = nullptr, *ilu_flev = nullptr, *ilu_blev = nullptr;
 };
 
 }  // namespace nnms
@@ -186,6 +190,7 @@ struct SysLevel {
   void* r = nullptr;    // level vectors, working precision
   void* z = nullptr;
   void* t = nullptr;
+  void* ilu_val = nullptr;  // ILU factor values (factor type), ILU levels only
 };
 
 struct Plan;
@@ -299,12 +304,22 @@ static hipError_t launch_ras_groups(const std::vector<RasGroup>& gs, bool add, h
   return hipSuccess;
 }
 
+// ILU smoother launch of one level over the ILU systems of a plan that share
+// a lanes-per-row choice (it fixes the summation order, so every system
+// keeps its own alone and in any batch): input r_l (write) / t_l (add), one
+// work-group per subdomain
+struct IluGroup {
+  IluDesc *r = nullptr, *t = nullptr;
+  int nd = 0, maxn = 0, lanes = 4;
+};
+
 struct LevelPlan {
   std::vector<SpmvGroup> res, rst;
   ProlongDesc* pro = nullptr;  // barycentric systems (four entries per row)
   int pro_blocks = 0;
   std::vector<SpmvGroup> prom;  // MLS systems: z_f - (-P) z_c, sliced ELL
-  std::vector<RasGroup> ras;
+  std::vector<RasGroup> ras;    // systems with dense subdomain LU
+  std::vector<IluGroup> ilu;    // systems with ILU subdomain solves, per lanes choice
   int nd = 0;  // descriptors in pro
 };
 
@@ -316,6 +331,17 @@ static hipError_t launch_prolong_level(const LevelPlan& LP, hipStream_t s) {
     if (e != hipSuccess) return e;
   }
   return launch_spmv_groups<T>(LP.prom, s);
+}
+
+// one smoother application on a smoothed level: z = B^{-1} r_l (add false)
+// or z += B^{-1} t_l (add true), dense-LU and ILU systems alike
+template <typename T>
+static hipError_t launch_smoother_level(const LevelPlan& LP, bool add, hipStream_t s) {
+  hipError_t e = launch_ras_groups<T, T>(LP.ras, add, s);
+  if (e != hipSuccess) return e;
+  for (const IluGroup& G : LP.ilu)
+    if ((e = launch_ilu_apply<T>(add ? G.t : G.r, G.nd, G.maxn, G.lanes, add ? 1 : 0, s)) != hipSuccess) return e;
+  return hipSuccess;
 }
 
 // Streams and pinned host words of plans are recycled instead of destroyed:
@@ -437,6 +463,8 @@ static void build_ras_pair(Arena& mem, std::vector<int32_t*>& counters, const st
   std::vector<int32_t> Ns;
   for (auto* x : sys) {
     const HostLevel& hl = x->h->host.lev[l];
+    if (!coarse && hl.subsolver == NNMS_SUBSOLVER_ILU)
+      throw Error(NNMS_ERR_INVALID_ARG, "dense smoother launch requested on an ILU level");
     const DevLevel& dl = x->h->dev[l];
     const SysLevel& sl = x->lev[l];
     const size_t fsz = (coarse || prec == NNMS_FP64) ? sizeof(double) : sizeof(float);
@@ -471,6 +499,58 @@ static void build_ras_pair(Arena& mem, std::vector<int32_t*>& counters, const st
   rt.add = 1;
 }
 
+static std::vector<IluDesc> ilu_descs(const nnms_system& x, int l, bool with_state) {
+  const HostLevel& hl = x.h->host.lev[l];
+  const DevLevel& dl = x.h->dev[l];
+  const SysLevel& sl = x.lev[l];
+  std::vector<IluDesc> v;
+  for (int p = 0; p < hl.nparts; ++p) {
+    const int64_t base = hl.s_ptr[p];
+    IluDesc d{};
+    d.rp = dl.ilu_rp + base, d.col = dl.ilu_col, d.dpos = dl.ilu_dpos + base;
+    d.fperm = dl.ilu_fperm + base, d.flev = dl.ilu_flev + hl.ilu_flev_off[p];
+    d.bperm = dl.ilu_bperm + base, d.blev = dl.ilu_blev + hl.ilu_blev_off[p];
+    d.gid = dl.ilu_gid + base, d.val = sl.ilu_val;
+    d.rin = sl.r, d.zout = sl.z, d.st = with_state ? x.st : nullptr;
+    d.n = int32_t(hl.s_ptr[p + 1] - base);
+    d.nfl = int32_t(hl.ilu_flev_off[p + 1] - hl.ilu_flev_off[p]) - 1;
+    d.nbl = int32_t(hl.ilu_blev_off[p + 1] - hl.ilu_blev_off[p]) - 1;
+    v.push_back(d);
+  }
+  return v;
+}
+
+static std::vector<IluGroup> ilu_groups_of(Arena& mem, const std::vector<nnms_system*>& sys, int l, bool with_state,
+                                           hipStream_t s) {
+  std::vector<int> gs;
+  for (auto* x : sys) {
+    const HostLevel& hl = x->h->host.lev[l];
+    if (hl.subsolver == NNMS_SUBSOLVER_ILU && std::find(gs.begin(), gs.end(), hl.ilu_lanes) == gs.end())
+      gs.push_back(hl.ilu_lanes);
+  }
+  std::vector<IluGroup> out;
+  for (int g : gs) {
+    std::vector<IluDesc> r, t;
+    IluGroup G;
+    G.lanes = g;
+    for (auto* x : sys) {
+      const HostLevel& hl = x->h->host.lev[l];
+      if (hl.subsolver != NNMS_SUBSOLVER_ILU || hl.ilu_lanes != g) continue;
+      for (IluDesc d : ilu_descs(*x, l, with_state)) {
+        G.maxn = std::max(G.maxn, int(d.n));
+        r.push_back(d);
+        d.rin = x->lev[l].t;
+        t.push_back(d);
+      }
+    }
+    G.r = mem.upload(r, s);
+    G.t = mem.upload(t, s);
+    G.nd = int(r.size());
+    out.push_back(G);
+  }
+  return out;
+}
+
 template <typename T>
 static void build_plan(Plan& P, const std::vector<nnms_system*>& sys, bool with_state, hipStream_t s) {
   P.sys = sys;
@@ -488,15 +568,19 @@ static void build_plan(Plan& P, const std::vector<nnms_system*>& sys, bool with_
   P.lev.resize(std::max(0, L - 1));
   // smoother launches of level l, one per blocks-per-item value (the launch
   // grid, which changes no arithmetic, from the group's first system)
+  auto dense_at = [&](const nnms_system* x, int l, bool coarse) {
+    return coarse || x->h->host.lev[l].subsolver != NNMS_SUBSOLVER_ILU;
+  };
   auto ras_groups_of = [&](int l, bool coarse) {
     std::vector<int> ks;
     for (auto* x : sys)
-      if (std::find(ks.begin(), ks.end(), x->h->tune.ras_blocks[l]) == ks.end()) ks.push_back(x->h->tune.ras_blocks[l]);
+      if (dense_at(x, l, coarse) && std::find(ks.begin(), ks.end(), x->h->tune.ras_blocks[l]) == ks.end())
+        ks.push_back(x->h->tune.ras_blocks[l]);
     std::vector<RasGroup> out;
     for (int K : ks) {
       std::vector<nnms_system*> sub;
       for (auto* x : sys)
-        if (x->h->tune.ras_blocks[l] == K) sub.push_back(x);
+        if (dense_at(x, l, coarse) && x->h->tune.ras_blocks[l] == K) sub.push_back(x);
       RasGroup G;
       const int g = sub[0]->h->tune.ras_groups[l];
       G.grid = g > 0 ? g : ras_grid_default();
@@ -560,6 +644,7 @@ static void build_plan(Plan& P, const std::vector<nnms_system*>& sys, bool with_
     LP.nd = int(pro.size());
     LP.prom = spmv_groups(P.mem, prom, s);
     LP.ras = ras_groups_of(l, false);
+    LP.ilu = ilu_groups_of(P.mem, sys, l, with_state, s);
   }
   P.coarse = ras_groups_of(L - 1, true);
   // Krylov descriptors
@@ -613,10 +698,10 @@ static void enqueue_vcycle(Plan& P, hipStream_t s) {
   const int L = P.L, its = P.its;
   for (int l = 0; l < L - 1; ++l) {
     LevelPlan& LP = P.lev[l];
-    HIP_CHECK((launch_ras_groups<T, T>(LP.ras, false, s)));
+    HIP_CHECK(launch_smoother_level<T>(LP, false, s));
     for (int k = 1; k < its; ++k) {
       HIP_CHECK(launch_spmv_groups<T>(LP.res, s));
-      HIP_CHECK((launch_ras_groups<T, T>(LP.ras, true, s)));
+      HIP_CHECK(launch_smoother_level<T>(LP, true, s));
     }
     HIP_CHECK(launch_spmv_groups<T>(LP.res, s));
     HIP_CHECK(launch_spmv_groups<T>(LP.rst, s));
@@ -627,7 +712,7 @@ static void enqueue_vcycle(Plan& P, hipStream_t s) {
     HIP_CHECK(launch_prolong_level<T>(LP, s));
     for (int k = 0; k < its; ++k) {
       HIP_CHECK(launch_spmv_groups<T>(LP.res, s));
-      HIP_CHECK((launch_ras_groups<T, T>(LP.ras, true, s)));
+      HIP_CHECK(launch_smoother_level<T>(LP, true, s));
     }
   }
 }
@@ -766,7 +851,8 @@ static void build_host(const nnms_mesh* const* levels, int32_t L, const nnms_set
   if (!levels || L < 1 || L > NNMS_MAX_LEVELS || !opts) throw Error(NNMS_ERR_INVALID_ARG, "bad hierarchy arguments");
   if (opts->overlap < 0 || opts->its < 1 || (opts->precision != NNMS_FP64 && opts->precision != NNMS_MIXED) ||
       (opts->transfer != NNMS_TRANSFER_BARYCENTRIC && opts->transfer != NNMS_TRANSFER_MLS) ||
-      (opts->transfer == NNMS_TRANSFER_MLS && !(opts->mls_alpha > 0)))
+      (opts->transfer == NNMS_TRANSFER_MLS && !(opts->mls_alpha > 0)) ||
+      (opts->subsolver != NNMS_SUBSOLVER_LU && opts->subsolver != NNMS_SUBSOLVER_ILU))
     throw Error(NNMS_ERR_INVALID_ARG, "bad setup options");
   H.L = L;
   H.opts = *opts;
@@ -785,6 +871,15 @@ static void build_host(const nnms_mesh* const* levels, int32_t L, const nnms_set
     if (!direct && np == 0) np = default_nparts(lv.nv);
     H.opts.nparts[l] = np;
     build_partition(lv, np, opts->overlap, direct);
+    if (!direct && opts->subsolver == NNMS_SUBSOLVER_ILU) {
+      if (opts->ilu_fill[l] < 0) throw Error(NNMS_ERR_INVALID_ARG, "ILU fill level must be >= 0");
+      const size_t vsz = opts->precision == NNMS_FP64 ? sizeof(double) : sizeof(float);
+      for (int p = 0; p < lv.nparts; ++p)
+        if (size_t(lv.s_ptr[p + 1] - lv.s_ptr[p]) * vsz > ILU_MAX_LDS)
+          throw Error(NNMS_ERR_INVALID_ARG, "subdomain too large for the ILU smoother (" +
+                                                std::to_string(lv.s_ptr[p + 1] - lv.s_ptr[p]) + " rows)");
+      build_ilu(lv, opts->ilu_fill[l]);
+    }
   }
   for (int l = 0; l + 1 < L; ++l) {
     if (opts->transfer == NNMS_TRANSFER_MLS)
@@ -862,6 +957,18 @@ extern "C" nnms_status nnms_hierarchy_setup(const nnms_mesh* const* levels, int3
         d.pn_w64 = A.upload(hl.pn_w, s);
         d.pn_w32 = A.upload(convert<double, float>(hl.pn_w), s);
       }
+      d.subsolver = hl.subsolver;
+      if (hl.subsolver == NNMS_SUBSOLVER_ILU) {
+        d.ilu_rp = A.upload(hl.ilu_rp, s);
+        d.ilu_col = A.upload(hl.ilu_col, s);
+        d.ilu_asrc = A.upload(hl.ilu_asrc, s);
+        d.ilu_dpos = A.upload(hl.ilu_dpos, s);
+        d.ilu_gid = A.upload(hl.ilu_gid, s);
+        d.ilu_fperm = A.upload(hl.ilu_fperm, s);
+        d.ilu_bperm = A.upload(hl.ilu_bperm, s);
+        d.ilu_flev = A.upload(hl.ilu_flev, s);
+        d.ilu_blev = A.upload(hl.ilu_blev, s);
+      }
     }
   }
   HIP_CHECK(hipStreamSynchronize(s));
@@ -898,6 +1005,8 @@ extern "C" nnms_status nnms_hierarchy_level_info(const nnms_hierarchy* h, int32_
   o->factor_elems = lv.fac_elems;
   o->p_nnz = int64_t(lv.pt_col.size());
   o->transfer = lv.transfer;
+  o->subsolver = lv.subsolver;
+  o->ilu_nnz = int64_t(lv.ilu_col.size());
   return NNMS_OK;
   ABI_END
 }
@@ -948,6 +1057,17 @@ extern "C" nnms_status nnms_hierarchy_transfer_csr(const nnms_hierarchy* h, int3
   ABI_END
 }
 
+extern "C" nnms_status nnms_hierarchy_ilu_pattern(const nnms_hierarchy* h, int32_t level, int32_t* rp, int32_t* col) {
+  ABI_BEGIN
+  if (!h || !rp || !col || level < 0 || level + 1 >= h->host.L) throw Error(NNMS_ERR_INVALID_ARG, "bad arguments");
+  const HostLevel& lv = h->host.lev[level];
+  if (lv.subsolver != NNMS_SUBSOLVER_ILU) throw Error(NNMS_ERR_INVALID_ARG, "the level has no ILU subdomain solver");
+  std::memcpy(rp, lv.ilu_rp.data(), lv.ilu_rp.size() * sizeof(int32_t));
+  std::memcpy(col, lv.ilu_col.data(), lv.ilu_col.size() * sizeof(int32_t));
+  return NNMS_OK;
+  ABI_END
+}
+
 static int64_t system_bytes(const HostHierarchy& H, int prec, int restart) {
   int64_t b = 0;
   for (int l = 0; l < H.L; ++l) {
@@ -958,7 +1078,11 @@ static int64_t system_bytes(const HostHierarchy& H, int prec, int restart) {
     b += int64_t(lv.col.size()) * 8 + (prec == NNMS_MIXED ? int64_t(lv.col.size()) * 4 : 0);
     const int64_t ne = lv.sell_off.empty() ? 0 : int64_t(lv.sell_off.back());
     b += ne * 8 + (prec == NNMS_MIXED ? ne * 4 : 0);
-    b += lv.fac_elems * f + lv.g_total * 16 + 3 * lv.nv * t;
+    if (!coarse && lv.subsolver == NNMS_SUBSOLVER_ILU)
+      b += int64_t(lv.ilu_col.size()) * f + 512;
+    else
+      b += lv.fac_elems * f + lv.g_total * 16;
+    b += 3 * lv.nv * t;
   }
   const int64_t n0 = H.lev[0].nv;
   b += n0 * 8 * (2 * int64_t(restart) + 1 + 4);
@@ -985,6 +1109,8 @@ struct FactorJob {
 
 static FactorJob factor_job(const nnms_system& sys, int l, Arena& mem, hipStream_t s) {
   const HostLevel& hl = sys.h->host.lev[l];
+  if (l < sys.h->host.L - 1 && hl.subsolver == NNMS_SUBSOLVER_ILU)
+    throw Error(NNMS_ERR_INVALID_ARG, "dense factorisation requested on an ILU level");
   const DevLevel& dl = sys.h->dev[l];
   const SysLevel& sl = sys.lev[l];
   FactorJob job;
@@ -1021,6 +1147,43 @@ static hipError_t enqueue_factor(const FactorJob& j, int* err, hipStream_t s) {
   if ((e = launch_fill<float>((float*)j.fac, j.elems, 0.0f, s)) != hipSuccess) return e;
   if ((e = launch_extract<float>(j.d, j.nd, j.maxn, s)) != hipSuccess) return e;
   return launch_lu<float>(j.d, j.nd, j.maxN, err, s);
+}
+
+// ILU factors of one level: values from the level's CSR (0 on fill), then
+// the level-scheduled factorisation, one work-group per subdomain.
+struct IluJob {
+  std::vector<IluDesc> host;
+  IluDesc* d = nullptr;
+  int nd = 0, lanes = 4;
+  bool f64 = true;
+  const int32_t* asrc = nullptr;
+  const double* a = nullptr;
+  void* val = nullptr;
+  int64_t nnz = 0;
+};
+
+static IluJob ilu_job(const nnms_system& sys, int l, Arena& mem, hipStream_t s) {
+  IluJob job;
+  job.f64 = sys.prec == NNMS_FP64;
+  job.host = ilu_descs(sys, l, false);
+  job.d = mem.upload(job.host, s);
+  job.nd = int(job.host.size());
+  job.asrc = sys.h->dev[l].ilu_asrc;
+  job.a = sys.lev[l].val64;
+  job.val = sys.lev[l].ilu_val;
+  job.nnz = int64_t(sys.h->host.lev[l].ilu_col.size());
+  job.lanes = sys.h->host.lev[l].ilu_lanes;
+  return job;
+}
+
+static hipError_t enqueue_ilu(const IluJob& j, int* err, hipStream_t s) {
+  hipError_t e;
+  if (j.f64) {
+    if ((e = launch_ilu_extract<double>(j.asrc, j.a, (double*)j.val, j.nnz, s)) != hipSuccess) return e;
+    return launch_ilu_factor<double>(j.d, j.nd, j.lanes, err, s);
+  }
+  if ((e = launch_ilu_extract<float>(j.asrc, j.a, (float*)j.val, j.nnz, s)) != hipSuccess) return e;
+  return launch_ilu_factor<float>(j.d, j.nd, j.lanes, err, s);
 }
 
 extern "C" nnms_status nnms_assemble(nnms_hierarchy* h, const nnms_kappa* k, double f, void* stream, nnms_system** out) {
@@ -1071,8 +1234,15 @@ extern "C" nnms_status nnms_assemble(nnms_hierarchy* h, const nnms_kappa* k, dou
     const int64_t nell = int64_t(hl.sell_off.back());
     sl.ell64 = A.alloc<double>(nell, s, false);
     if (prec == NNMS_MIXED) sl.ell32 = A.alloc<float>(nell, s, false);
-    sl.fac = A.raw(std::max<size_t>(size_t(hl.fac_elems) * fsz, 256));
-    sl.yx = A.alloc<char>(size_t(hl.g_total) * 16, s);  // tagged block results: 16 bytes per value
+    const bool ilu = !coarse && hl.subsolver == NNMS_SUBSOLVER_ILU;
+    if (ilu) {
+      sl.fac = A.raw(256);
+      sl.yx = A.raw(256);
+      sl.ilu_val = A.raw(std::max<size_t>(hl.ilu_col.size() * fsz, 256));
+    } else {
+      sl.fac = A.raw(std::max<size_t>(size_t(hl.fac_elems) * fsz, 256));
+      sl.yx = A.alloc<char>(size_t(hl.g_total) * 16, s);  // tagged block results: 16 bytes per value
+    }
     sl.r = A.alloc<char>(hl.nv * tsz, s);
     sl.z = A.alloc<char>(hl.nv * tsz, s);
     sl.t = A.alloc<char>(hl.nv * tsz, s);
@@ -1087,9 +1257,15 @@ extern "C" nnms_status nnms_assemble(nnms_hierarchy* h, const nnms_kappa* k, dou
     HIP_CHECK(launch_assemble(ad, kd, f, s));
     HIP_CHECK(launch_gather_ell<double>(dl.sell_src, sl.val64, sl.ell64, nell, s));
     if (sl.ell32) HIP_CHECK(launch_gather_ell<float>(dl.sell_src, sl.val64, sl.ell32, nell, s));
-    // dense subdomain matrices and their factors
-    FactorJob job = factor_job(*sys, l, scratch, s);
-    HIP_CHECK(enqueue_factor(job, err, s));
+    if (ilu) {
+      // ILU(k) values of every subdomain and their factorisation
+      IluJob job = ilu_job(*sys, l, scratch, s);
+      HIP_CHECK(enqueue_ilu(job, err, s));
+    } else {
+      // dense subdomain matrices and their factors
+      FactorJob job = factor_job(*sys, l, scratch, s);
+      HIP_CHECK(enqueue_factor(job, err, s));
+    }
   }
   // solve workspace
   const int64_t n0 = H.lev[0].nv;
@@ -1213,9 +1389,9 @@ extern "C" nnms_status nnms_apply_smoother(nnms_system* s, int32_t level, const 
       HIP_CHECK((launch_ras_groups<double, float>(P.coarse, false, P.stream)));
   } else {
     if (s->prec == NNMS_FP64)
-      HIP_CHECK((launch_ras_groups<double, double>(P.lev[level].ras, false, P.stream)));
+      HIP_CHECK(launch_smoother_level<double>(P.lev[level], false, P.stream));
     else
-      HIP_CHECK((launch_ras_groups<float, float>(P.lev[level].ras, false, P.stream)));
+      HIP_CHECK(launch_smoother_level<float>(P.lev[level], false, P.stream));
   }
   get_vec(s, z, sl.z, n, P.stream);
   check_counters(P, P.stream);
@@ -1445,6 +1621,23 @@ extern "C" nnms_status nnms_batch_destroy(nnms_batch* bt) {
   return NNMS_OK;
 }
 
+extern "C" nnms_status nnms_system_ilu_values(const nnms_system* s, int32_t level, double* val) {
+  ABI_BEGIN
+  if (!s || !val || level < 0 || level + 1 >= s->h->host.L) throw Error(NNMS_ERR_INVALID_ARG, "bad arguments");
+  const HostLevel& hl = s->h->host.lev[level];
+  if (hl.subsolver != NNMS_SUBSOLVER_ILU) throw Error(NNMS_ERR_INVALID_ARG, "the level has no ILU subdomain solver");
+  const size_t n = hl.ilu_col.size();
+  if (s->prec == NNMS_FP64) {
+    HIP_CHECK(hipMemcpy(val, s->lev[level].ilu_val, n * sizeof(double), hipMemcpyDeviceToHost));
+  } else {
+    std::vector<float> f(n);
+    HIP_CHECK(hipMemcpy(f.data(), s->lev[level].ilu_val, n * sizeof(float), hipMemcpyDeviceToHost));
+    for (size_t e = 0; e < n; ++e) val[e] = f[e];
+  }
+  return NNMS_OK;
+  ABI_END
+}
+
 extern "C" nnms_status nnms_time_kernel(nnms_system* s, int32_t kind, int32_t level, int32_t reps, double* ms) {
   ABI_BEGIN
   if (!s || !ms || reps < 1 || level < 0 || level >= s->h->host.L || kind < 0 || kind > 6)
@@ -1452,6 +1645,9 @@ extern "C" nnms_status nnms_time_kernel(nnms_system* s, int32_t kind, int32_t le
   const int L = s->h->host.L;
   if ((kind == 1 || kind == 2 || kind == 3) && level == L - 1)
     throw Error(NNMS_ERR_INVALID_ARG, "the coarsest level has only the direct solve");
+  const bool ilu_level = level < L - 1 && s->h->host.lev[level].subsolver == NNMS_SUBSOLVER_ILU;
+  if ((kind == 4 || kind == 5) && ilu_level)
+    throw Error(NNMS_ERR_INVALID_ARG, "the copy and read references stream dense factors");
   Plan& P = apply_plan(s);
   hipStream_t st = P.stream;
   const bool f64 = s->prec == NNMS_FP64;
@@ -1469,15 +1665,22 @@ extern "C" nnms_status nnms_time_kernel(nnms_system* s, int32_t kind, int32_t le
   // kind 6 refactors the level in place: the same values give the same factors
   std::unique_ptr<Arena> fac_mem;
   FactorJob job;
+  IluJob ijob;
   int* ferr = nullptr;
   if (kind == 6) {
     fac_mem = std::make_unique<Arena>(s->h->has_alloc ? &s->h->alloc : nullptr);
-    job = factor_job(*s, level, *fac_mem, st);
+    if (ilu_level)
+      ijob = ilu_job(*s, level, *fac_mem, st);
+    else
+      job = factor_job(*s, level, *fac_mem, st);
     ferr = fac_mem->alloc<int>(1, st);
   }
   auto launch = [&]() {
     if (kind == 6) {
-      HIP_CHECK(enqueue_factor(job, ferr, st));
+      if (ilu_level)
+        HIP_CHECK(enqueue_ilu(ijob, ferr, st));
+      else
+        HIP_CHECK(enqueue_factor(job, ferr, st));
     } else if (kind == 4) {
       HIP_CHECK(launch_copy16(s->lev[level].fac, copy_dst->bufs[0].first, copy_bytes, st));
     } else if (kind == 5) {
@@ -1489,9 +1692,9 @@ extern "C" nnms_status nnms_time_kernel(nnms_system* s, int32_t kind, int32_t le
         else
           HIP_CHECK((launch_ras_groups<double, float>(P.coarse, false, st)));
       } else if (f64) {
-        HIP_CHECK((launch_ras_groups<double, double>(P.lev[level].ras, true, st)));
+        HIP_CHECK(launch_smoother_level<double>(P.lev[level], true, st));
       } else {
-        HIP_CHECK((launch_ras_groups<float, float>(P.lev[level].ras, true, st)));
+        HIP_CHECK(launch_smoother_level<float>(P.lev[level], true, st));
       }
     } else if (kind == 1) {
       if (f64)
@@ -1534,6 +1737,8 @@ extern "C" nnms_status nnms_system_factor(const nnms_system* s, int32_t level, i
   if (!s || level < 0 || level >= s->h->host.L) throw Error(NNMS_ERR_INVALID_ARG, "bad level");
   const HostLevel& hl = s->h->host.lev[level];
   if (part < 0 || part >= hl.nparts) throw Error(NNMS_ERR_INVALID_ARG, "bad part");
+  if (level < s->h->host.L - 1 && hl.subsolver == NNMS_SUBSOLVER_ILU)
+    throw Error(NNMS_ERR_INVALID_ARG, "the level has ILU factors, not dense ones");
   const int N = hl.nblk[part];
   if (Nout) *Nout = N;
   const bool f64 = (level == s->h->host.L - 1) || s->prec == NNMS_FP64;
@@ -1570,6 +1775,8 @@ extern "C" nnms_status nnms_system_factor_pairs(const nnms_system* s, int32_t le
   if (!s || level < 0 || level >= s->h->host.L) throw Error(NNMS_ERR_INVALID_ARG, "bad level");
   const HostLevel& hl = s->h->host.lev[level];
   if (part < 0 || part >= hl.nparts) throw Error(NNMS_ERR_INVALID_ARG, "bad part");
+  if (level < s->h->host.L - 1 && hl.subsolver == NNMS_SUBSOLVER_ILU)
+    throw Error(NNMS_ERR_INVALID_ARG, "the level has ILU factors, not dense ones");
   const int N = hl.nblk[part], NP = N / 2;
   if (npairs) *npairs = NP;
   if (!xl && !xu) return NNMS_OK;
@@ -1724,7 +1931,8 @@ extern "C" nnms_status nnms_autotune(nnms_system* s, int32_t reps, nnms_tuning* 
     const void* ptsw = f64 ? (const void*)dl.pts_w64 : (const void*)dl.pts_w32;
     t.pt_lanes[l] = spmv_best(dl.pt_rp, dl.pt_col, ptw, sl.t, nullptr, s->lev[l + 1].r, nc, f64, dl.pts_off,
                               dl.pts_col, ptsw);
-    ras_best(l, false, t.ras_groups[l], t.ras_blocks[l]);
+    // the dense smoother's launch shape (ILU levels have no dense factors)
+    if (h->host.lev[l].subsolver != NNMS_SUBSOLVER_ILU) ras_best(l, false, t.ras_groups[l], t.ras_blocks[l]);
   }
   ras_best(L - 1, true, t.ras_groups[L - 1], t.ras_blocks[L - 1]);
   for (int32_t* c : tcounters) {

@@ -80,6 +80,27 @@ struct RasLaunch {
   int32_t pad;
 };
 
+// One subdomain's ILU(k) factor for the factorisation and apply kernels.
+// Row indices are local (0..n-1); entry indices point into the level's
+// concatenated pattern arrays (col, val).
+struct IluDesc {
+  const int32_t* rp;     // n+1: first entry of every row
+  const int32_t* col;    // local column of every entry (the level's array)
+  const int32_t* dpos;   // n: entry of every row's diagonal
+  const int32_t* fperm;  // n: rows by forward level
+  const int32_t* flev;   // nfl+1: level boundaries in fperm
+  const int32_t* bperm;  // n: rows by backward level
+  const int32_t* blev;   // nbl+1
+  const int32_t* gid;    // n: global id (>= 0 owned, -g-2 overlap)
+  void* val;             // factor values of every entry (the level's array)
+  const void* rin;       // level residual vector
+  void* zout;            // level correction vector
+  const KState* st;      // null: always active
+  int32_t n, nfl, nbl, pad;
+};
+// LDS of one apply work-group: the subdomain's vector
+constexpr size_t ILU_MAX_LDS = 65536;
+
 // Dense-factor work of one subdomain (extraction and LU).
 struct FacDesc {
   void* fac;

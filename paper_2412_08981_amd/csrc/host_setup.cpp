@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <set>
 
 #include "nnms_internal.h"
 
@@ -396,6 +397,124 @@ void build_transfer(HostLevel& fine, const HostLevel& coarse) {
 }
 
 // ---------------------------------------------------------------------------
+// ILU(k) structure of every subdomain matrix A[S_p, S_p], natural ordering
+// (the subdomain's rows in ascending global id).  Level of fill: entries of
+// A have level 0; eliminating entry (i, k) gives every (i, j), j > k, of
+// row k's upper part the level lev(i, k) + lev(k, j) + 1, and entries of
+// level <= fill are kept.  Schedules: the forward level of a row is one more
+// than the largest among its lower columns (rows of one level depend only on
+// earlier levels in the factorisation and in the forward solve); the
+// backward level likewise over the upper columns.
+// ---------------------------------------------------------------------------
+void build_ilu(HostLevel& lv, int fill) {
+  if (fill < 0) throw Error(NNMS_ERR_INVALID_ARG, "ILU fill level must be >= 0");
+  const int np = lv.nparts;
+  const int64_t ns = int64_t(lv.s_idx.size());
+  lv.ilu_fill = fill;
+  lv.ilu_rp.assign(ns + 1, 0);
+  lv.ilu_col.clear();
+  lv.ilu_asrc.clear();
+  lv.ilu_dpos.assign(ns, 0);
+  lv.ilu_fperm.assign(ns, 0);
+  lv.ilu_bperm.assign(ns, 0);
+  lv.ilu_gid.assign(ns, 0);
+  lv.ilu_flev.clear();
+  lv.ilu_blev.clear();
+  lv.ilu_flev_off.assign(np + 1, 0);
+  lv.ilu_blev_off.assign(np + 1, 0);
+  std::vector<int32_t> lev_of, slot_of;
+  for (int p = 0; p < np; ++p) {
+    const int64_t base = lv.s_ptr[p];
+    const int32_t n = int32_t(lv.s_ptr[p + 1] - base);
+    const int32_t* S = lv.s_idx.data() + base;
+    lev_of.assign(n, INT32_MAX);
+    slot_of.assign(n, -1);
+    std::vector<std::vector<int32_t>> rcol(n), rlev(n);
+    std::set<int32_t> row;
+    for (int32_t i = 0; i < n; ++i) {
+      const int32_t g = S[i];
+      lv.ilu_gid[base + i] = (lv.owner[g] == p) ? g : (-g - 2);
+      row.clear();
+      const int32_t e0 = lv.ext_rs[base + i], e1 = lv.ext_rs[base + i + 1];
+      for (int32_t e = e0; e < e1; ++e) {
+        const int32_t c = lv.ext_lc[e];
+        if (c < 0) continue;
+        lev_of[c] = 0;
+        slot_of[c] = lv.rp[g] + (e - e0);
+        row.insert(c);
+      }
+      if (lev_of[i] != 0) throw Error(NNMS_ERR_INVALID_ARG, "subdomain matrix without a diagonal entry");
+      for (auto it = row.begin(); it != row.end() && *it < i; ++it) {
+        const int32_t k = *it, lik = lev_of[k];
+        for (size_t t = 0; t < rcol[k].size(); ++t) {
+          const int32_t j = rcol[k][t];
+          if (j <= k) continue;
+          const int32_t nl = lik + rlev[k][t] + 1;
+          if (nl <= fill && nl < lev_of[j]) {
+            if (lev_of[j] == INT32_MAX) row.insert(j);
+            lev_of[j] = nl;
+          }
+        }
+      }
+      lv.ilu_rp[base + i] = int32_t(lv.ilu_col.size());
+      for (int32_t c : row) {
+        rcol[i].push_back(c);
+        rlev[i].push_back(lev_of[c]);
+        if (c == i) lv.ilu_dpos[base + i] = int32_t(lv.ilu_col.size());
+        lv.ilu_col.push_back(c);
+        lv.ilu_asrc.push_back(slot_of[c]);
+        lev_of[c] = INT32_MAX;
+        slot_of[c] = -1;
+      }
+      if (lv.ilu_col.size() > size_t(INT32_MAX / 2)) throw Error(NNMS_ERR_INVALID_ARG, "ILU pattern too large");
+    }
+    // level schedules (counting sort by level, rows ascending within a level)
+    std::vector<int32_t> fl(n, 0), bl(n, 0);
+    int32_t nfl = 0, nbl = 0;
+    for (int32_t i = 0; i < n; ++i) {
+      for (int32_t c : rcol[i])
+        if (c < i) fl[i] = std::max(fl[i], fl[c] + 1);
+      nfl = std::max(nfl, fl[i] + 1);
+    }
+    for (int32_t i = n - 1; i >= 0; --i) {
+      for (int32_t c : rcol[i])
+        if (c > i) bl[i] = std::max(bl[i], bl[c] + 1);
+      nbl = std::max(nbl, bl[i] + 1);
+    }
+    auto schedule = [&](const std::vector<int32_t>& lvl, int32_t nl, int32_t* perm, std::vector<int32_t>& offs) {
+      std::vector<int32_t> cnt(nl + 1, 0);
+      for (int32_t i = 0; i < n; ++i) cnt[lvl[i] + 1]++;
+      for (int32_t k = 0; k < nl; ++k) cnt[k + 1] += cnt[k];
+      offs.insert(offs.end(), cnt.begin(), cnt.end());
+      for (int32_t i = 0; i < n; ++i) perm[cnt[lvl[i]]++] = i;
+    };
+    if (n > 0) {
+      schedule(fl, nfl, lv.ilu_fperm.data() + base, lv.ilu_flev);
+      schedule(bl, nbl, lv.ilu_bperm.data() + base, lv.ilu_blev);
+    }
+    lv.ilu_flev_off[p + 1] = int64_t(lv.ilu_flev.size());
+    lv.ilu_blev_off[p + 1] = int64_t(lv.ilu_blev.size());
+  }
+  lv.ilu_rp[ns] = int32_t(lv.ilu_col.size());
+  // lanes per row of the device kernels: a group stages at most 4 entries
+  // per lane in the factorisation, and takes about two per lane in each
+  // triangular solve
+  int32_t maxlen = 0, maxhalf = 0;
+  for (int64_t r = 0; r < ns; ++r) {
+    const int32_t a = lv.ilu_rp[r], b = lv.ilu_rp[r + 1], d = lv.ilu_dpos[r];
+    maxlen = std::max(maxlen, b - a);
+    maxhalf = std::max(maxhalf, std::max(d - a, b - d - 1));
+  }
+  int32_t lanes = 4;
+  while (lanes < 32 && (4 * lanes < maxlen || 2 * lanes < maxhalf)) lanes *= 2;
+  if (4 * lanes < maxlen)
+    throw Error(NNMS_ERR_INVALID_ARG, "ILU rows too long for the device kernels (" + std::to_string(maxlen) +
+                                          " entries; lower the fill level)");
+  lv.ilu_lanes = lanes;
+  lv.subsolver = NNMS_SUBSOLVER_ILU;
+}
+
+// ---------------------------------------------------------------------------
 // Moving-least-squares transfer (Section 3.2).  The row of P_l for a fine
 // vertex x* holds phi_n = q(x*)^T M^{-1} w_n q_n over the coarse vertices
 // x~_n with |x~_n - x*| < rho, where
@@ -680,5 +799,7 @@ extern "C" nnms_status nnms_setup_opts_default(nnms_setup_opts* o) {
   o->precision = NNMS_FP64;
   o->transfer = NNMS_TRANSFER_BARYCENTRIC;
   o->mls_alpha = 1.0;
+  o->subsolver = NNMS_SUBSOLVER_LU;
+  o->ilu_fill[0] = 2;  // ILU(2) on the finest level, ILU(0) on the others
   return NNMS_OK;
 }

@@ -1,0 +1,185 @@
+// ILU(k) subdomain solver of the RAS smoother (Section 4 of the paper runs
+// the smoother with incomplete LU subdomain solves in place of exact ones).
+//
+// Every subdomain is one work-group, and every row is handled by a group of
+// G lanes of one wave (G = 4..32, chosen from the longest row).  The
+// factorisation is the i-k-j form of Gaussian elimination restricted to the
+// ILU pattern: a row eliminates its lower entries in ascending column order
+// with rows already finished; the rows of one forward level depend only on
+// earlier levels, so a level is processed in parallel and levels are
+// separated by a work-group barrier.  The apply gathers the subdomain's part
+// of the residual into LDS, runs the unit-lower forward and the upper
+// backward solve level by level in LDS (partial sums of a row added in a
+// fixed order, so results are deterministic) and scatters the owned rows.
+#include "devcommon.h"
+#include "kernels.h"
+
+namespace nnms {
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_ilu_extract(const int32_t* __restrict__ asrc, const double* __restrict__ a,
+                                                     T* __restrict__ val, int64_t n) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int32_t s = gptr(asrc)[e];
+  gptr(val)[e] = s >= 0 ? T(gptr(a)[s]) : T(0);
+}
+
+// Row i of the factorisation by a group of G lanes of one wave: the row's
+// values and columns are staged in the group's LDS slice (at most 4G
+// entries); for every lower entry k in ascending order the multiplier
+// l = a_ik / u_kk is formed and the lanes take row k's upper entries j in
+// turn, find j in row i by binary search and update a_ij -= l u_kj (distinct
+// j, distinct targets).  Every a_ij receives its updates in ascending k,
+// the same operations in the same order as the textbook i-k-j loop.
+template <typename T, int G>
+__global__ __launch_bounds__(256) void k_ilu_factor(const IluDesc* __restrict__ d, int* __restrict__ err) {
+  constexpr int NE = 4 * G;  // entries per row that a group can stage
+  __shared__ T svals[256 / G][NE];
+  __shared__ int32_t scols[256 / G][NE];
+  const IluDesc D = d[blockIdx.x];
+  const GLOBAL int32_t* rp = gptr(D.rp);
+  const GLOBAL int32_t* col = gptr(D.col);
+  const GLOBAL int32_t* dpos = gptr(D.dpos);
+  GLOBAL T* val = gptr((T*)D.val);
+  const int grp = int(threadIdx.x) / G, lane = int(threadIdx.x) % G, ngrp = int(blockDim.x) / G;
+  T* rv = svals[grp];
+  int32_t* rc = scols[grp];
+  for (int lv = 0; lv < D.nfl; ++lv) {
+    const int r0 = gptr(D.flev)[lv], r1 = gptr(D.flev)[lv + 1];
+    for (int q = r0 + grp; q < r1; q += ngrp) {  // uniform within a group
+      const int i = gptr(D.fperm)[q];
+      const int a = rp[i], len = rp[i + 1] - a, di = dpos[i] - a;
+      for (int m = lane; m < len; m += G) rv[m] = val[a + m], rc[m] = col[a + m];
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      for (int e = 0; e < di; ++e) {
+        const int k = rc[e];
+        const int dk = dpos[k], bk = rp[k + 1];
+        const T l = rv[e] / val[dk];
+        for (int f = dk + 1 + lane; f < bk; f += G) {
+          const int j = col[f];
+          int lo = e + 1, hi = len;
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (rc[mid] < j)
+              lo = mid + 1;
+            else
+              hi = mid;
+          }
+          if (lo < len && rc[lo] == j) rv[lo] -= l * val[f];
+        }
+        if (lane == 0) rv[e] = l;
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+      }
+      for (int m = lane; m < len; m += G) val[a + m] = rv[m];
+      if (lane == 0 && !(rv[di] > T(0))) *err = 1;
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+  }
+}
+
+// G lanes per row: lane l of a row's group takes entries l, l + G, ... and
+// the group adds its partial sums by a fixed xor tree, so a level's rows
+// issue all their loads at once instead of one dependent chain per row.
+template <typename T, int G>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
+  return v;
+}
+
+template <typename T, int G>
+__global__ __launch_bounds__(256) void k_ilu_apply(const IluDesc* __restrict__ d, int add) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T* y = reinterpret_cast<T*>(lds_raw);
+  const IluDesc D = d[blockIdx.x];
+  if (!slot_active(D.st, WHEN_RUNNING)) return;
+  const GLOBAL int32_t* rp = gptr(D.rp);
+  const GLOBAL int32_t* col = gptr(D.col);
+  const GLOBAL int32_t* dpos = gptr(D.dpos);
+  const GLOBAL int32_t* gid = gptr(D.gid);
+  const GLOBAL T* val = gptr((const T*)D.val);
+  const GLOBAL T* rin = gptr((const T*)D.rin);
+  const int grp = int(threadIdx.x) / G, lane = int(threadIdx.x) % G, ngrp = int(blockDim.x) / G;
+  for (int i = threadIdx.x; i < D.n; i += blockDim.x) {
+    const int g = gid[i];
+    y[i] = rin[g >= 0 ? g : -g - 2];
+  }
+  __syncthreads();
+  for (int lv = 0; lv < D.nfl; ++lv) {
+    const int r0 = gptr(D.flev)[lv], r1 = gptr(D.flev)[lv + 1];
+    for (int q = r0 + grp; q < r1; q += ngrp) {  // uniform within a group
+      const int i = gptr(D.fperm)[q];
+      T s = 0;
+      for (int e = rp[i] + lane, de = dpos[i]; e < de; e += G) s += val[e] * y[col[e]];
+      s = group_sum<T, G>(s);
+      if (lane == 0) y[i] -= s;
+    }
+    __syncthreads();
+  }
+  for (int lv = 0; lv < D.nbl; ++lv) {
+    const int r0 = gptr(D.blev)[lv], r1 = gptr(D.blev)[lv + 1];
+    for (int q = r0 + grp; q < r1; q += ngrp) {
+      const int i = gptr(D.bperm)[q];
+      const int de = dpos[i];
+      T s = 0;
+      for (int e = de + 1 + lane, b = rp[i + 1]; e < b; e += G) s += val[e] * y[col[e]];
+      s = group_sum<T, G>(s);
+      if (lane == 0) y[i] = (y[i] - s) / val[de];
+    }
+    __syncthreads();
+  }
+  GLOBAL T* z = gptr((T*)D.zout);
+  for (int i = threadIdx.x; i < D.n; i += blockDim.x) {
+    const int g = gid[i];
+    if (g >= 0) z[g] = add ? z[g] + y[i] : y[i];
+  }
+}
+
+template <typename T>
+hipError_t launch_ilu_extract(const int32_t* asrc, const double* a, T* val, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_ilu_extract<T><<<dim3(unsigned((n + 255) / 256)), dim3(256), 0, s>>>(asrc, a, val, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_ilu_factor(const IluDesc* d, int nd, int lanes, int* err, hipStream_t s) {
+  if (nd <= 0) return hipSuccess;
+  switch (lanes) {
+    case 4: k_ilu_factor<T, 4><<<dim3(nd), dim3(256), 0, s>>>(d, err); break;
+    case 8: k_ilu_factor<T, 8><<<dim3(nd), dim3(256), 0, s>>>(d, err); break;
+    case 16: k_ilu_factor<T, 16><<<dim3(nd), dim3(256), 0, s>>>(d, err); break;
+    case 32: k_ilu_factor<T, 32><<<dim3(nd), dim3(256), 0, s>>>(d, err); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_ilu_apply(const IluDesc* d, int nd, int maxn, int lanes, int add, hipStream_t s) {
+  if (nd <= 0) return hipSuccess;
+  const size_t lds = size_t(maxn) * sizeof(T);
+  if (lds > ILU_MAX_LDS) return hipErrorInvalidValue;
+  switch (lanes) {
+    case 4: k_ilu_apply<T, 4><<<dim3(nd), dim3(256), lds, s>>>(d, add); break;
+    case 8: k_ilu_apply<T, 8><<<dim3(nd), dim3(256), lds, s>>>(d, add); break;
+    case 16: k_ilu_apply<T, 16><<<dim3(nd), dim3(256), lds, s>>>(d, add); break;
+    case 32: k_ilu_apply<T, 32><<<dim3(nd), dim3(256), lds, s>>>(d, add); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template hipError_t launch_ilu_extract<double>(const int32_t*, const double*, double*, int64_t, hipStream_t);
+template hipError_t launch_ilu_extract<float>(const int32_t*, const double*, float*, int64_t, hipStream_t);
+template hipError_t launch_ilu_factor<double>(const IluDesc*, int, int, int*, hipStream_t);
+template hipError_t launch_ilu_factor<float>(const IluDesc*, int, int, int*, hipStream_t);
+template hipError_t launch_ilu_apply<double>(const IluDesc*, int, int, int, int, hipStream_t);
+template hipError_t launch_ilu_apply<float>(const IluDesc*, int, int, int, int, hipStream_t);
+
+}  // namespace nnms

@@ -39,6 +39,18 @@ hipError_t launch_extract(const FacDesc* d, int nd, int maxn, hipStream_t s);
 template <typename F>
 hipError_t launch_lu(const FacDesc* d, int nd, int maxN, int* err, hipStream_t s);
 
+// ilu.hip: values of the ILU pattern from the level's FP64 CSR values (0 on
+// fill), the factorisation (err set on a non-positive pivot) and the
+// smoother application z = B^{-1} r (add = 0) or z += B^{-1} r (add = 1);
+// maxn = the largest subdomain of the launch, lanes (4, 8, 16 or 32) per row
+// of the triangular solves
+template <typename T>
+hipError_t launch_ilu_extract(const int32_t* asrc, const double* a, T* val, int64_t n, hipStream_t s);
+template <typename T>
+hipError_t launch_ilu_factor(const IluDesc* d, int nd, int lanes, int* err, hipStream_t s);
+template <typename T>
+hipError_t launch_ilu_apply(const IluDesc* d, int nd, int maxn, int lanes, int add, hipStream_t s);
+
 // assemble.hip
 hipError_t launch_assemble(const AsmDesc& a, const KappaDev& k, double f, hipStream_t s);
 

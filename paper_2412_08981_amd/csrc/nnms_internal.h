@@ -77,6 +77,20 @@ struct HostLevel {
   // MLS only: -P_l in the sliced ELL layout (the prolongation's launch)
   std::vector<int32_t> pn_off, pn_col;
   std::vector<double> pn_w;
+
+  // subdomain solver of the smoother; with ILU, the pattern of every
+  // subdomain in local numbering, rows concatenated in S order
+  int32_t subsolver = NNMS_SUBSOLVER_LU;
+  int32_t ilu_fill = 0;
+  int32_t ilu_lanes = 4;             // lanes per row of the ILU kernels
+  std::vector<int32_t> ilu_rp;       // s_total+1, entry index of every row's first entry
+  std::vector<int32_t> ilu_col;      // local column, ascending within a row
+  std::vector<int32_t> ilu_asrc;     // CSR slot of A for every entry, -1 for fill
+  std::vector<int32_t> ilu_dpos;     // entry index of every row's diagonal
+  std::vector<int32_t> ilu_gid;      // global id, >= 0 owned, -g-2 overlap
+  std::vector<int32_t> ilu_fperm, ilu_bperm;  // local rows by forward / backward level
+  std::vector<int32_t> ilu_flev, ilu_blev;    // per subdomain: level boundaries (nlev+1) into its perm
+  std::vector<int64_t> ilu_flev_off, ilu_blev_off;  // nparts+1: start of every subdomain's boundaries
 };
 
 struct HostHierarchy {
@@ -99,6 +113,8 @@ void build_transfer(HostLevel& fine, const HostLevel& coarse);
 // mean coarse edge length
 void build_transfer_mls(HostLevel& fine, const HostLevel& coarse, double alpha);
 double mean_edge_length(const HostLevel& lv);
+// ILU(fill) pattern and level schedules of every subdomain (after the partition)
+void build_ilu(HostLevel& lv, int fill);
 int default_nparts(int64_t nv);
 
 }  // namespace nnms

@@ -33,6 +33,7 @@ MAX_LEVELS = 8
 MAX_RESTART = 64
 FP64, MIXED = 0, 1
 BARYCENTRIC, MLS = 0, 1  # transfer between levels
+LU, ILU = 0, 1  # subdomain solver of the smoother
 DEVICE_PTRS, NO_GRAPH = 1, 2
 
 STATUS = {
@@ -50,13 +51,15 @@ class NNMSError(RuntimeError):
 
 class setup_opts(C.Structure):
     _fields_ = [("nparts", C.c_int32 * MAX_LEVELS), ("overlap", C.c_int32), ("its", C.c_int32),
-                ("precision", C.c_int32), ("transfer", C.c_int32), ("mls_alpha", C.c_double)]
+                ("precision", C.c_int32), ("transfer", C.c_int32), ("mls_alpha", C.c_double),
+                ("subsolver", C.c_int32), ("ilu_fill", C.c_int32 * MAX_LEVELS)]
 
 
 class level_info(C.Structure):
     _fields_ = [("nv", C.c_int64), ("nt", C.c_int64), ("ninterior", C.c_int64), ("nnz", C.c_int64),
                 ("nparts", C.c_int32), ("max_block", C.c_int32), ("min_block", C.c_int32), ("transfer", C.c_int32),
-                ("s_total", C.c_int64), ("factor_elems", C.c_int64), ("p_nnz", C.c_int64)]
+                ("s_total", C.c_int64), ("factor_elems", C.c_int64), ("p_nnz", C.c_int64),
+                ("subsolver", C.c_int32), ("reserved2", C.c_int32), ("ilu_nnz", C.c_int64)]
 
 
 class kappa_t(C.Structure):
@@ -117,6 +120,8 @@ _sig = {
     "nnms_hierarchy_partition": (C.c_int, [vp, C.c_int32, vp, vp, vp]),
     "nnms_hierarchy_transfer": (C.c_int, [vp, C.c_int32, vp, vp]),
     "nnms_hierarchy_transfer_csr": (C.c_int, [vp, C.c_int32, vp, vp, vp]),
+    "nnms_hierarchy_ilu_pattern": (C.c_int, [vp, C.c_int32, vp, vp]),
+    "nnms_system_ilu_values": (C.c_int, [vp, C.c_int32, vp]),
     "nnms_hierarchy_system_bytes": (C.c_int64, [vp, C.c_int32]),
     "nnms_assemble": (C.c_int, [vp, C.POINTER(kappa_t), C.c_double, vp, C.POINTER(vp)]),
     "nnms_system_destroy": (C.c_int, [vp]),
@@ -222,13 +227,17 @@ class Hierarchy:
 
     def __init__(self, meshes: Sequence[Mesh], nparts: Sequence[int] = (), overlap: int = 1, its: int = 3,
                  precision: int = FP64, device: bool = True, torch_alloc: bool = False, stream=None,
-                 transfer: int = BARYCENTRIC, mls_alpha: float = 1.0):
+                 transfer: int = BARYCENTRIC, mls_alpha: float = 1.0, subsolver: int = LU,
+                 ilu_fill: Sequence[int] = ()):
         o = setup_opts()
         _check(_lib.nnms_setup_opts_default(C.byref(o)))
         for l, p in enumerate(nparts):
             o.nparts[l] = int(p)
         o.overlap, o.its, o.precision = overlap, its, precision
         o.transfer, o.mls_alpha = transfer, mls_alpha
+        o.subsolver = subsolver
+        for l, k in enumerate(ilu_fill):
+            o.ilu_fill[l] = int(k)
         self.meshes = list(meshes)
         arr = (C.c_void_p * len(meshes))(*[m.handle for m in meshes])
         h = C.c_void_p()
@@ -272,6 +281,14 @@ class Hierarchy:
         _check(_lib.nnms_hierarchy_transfer(self.handle, level, _ptr(idx), _ptr(w)))
         return idx.reshape(-1, 4), w.reshape(-1, 4)
 
+    def ilu_pattern(self, level: int):
+        """(row_ptr, col) of the level's ILU patterns, subdomains concatenated."""
+        li = self.level_info(level)
+        rp = np.empty(li.s_total + 1, dtype=np.int32)
+        col = np.empty(li.ilu_nnz, dtype=np.int32)
+        _check(_lib.nnms_hierarchy_ilu_pattern(self.handle, level, _ptr(rp), _ptr(col)))
+        return rp, col
+
     def transfer_csr(self, level: int):
         """P_level as CSR (row_ptr, col, w) over the fine vertices."""
         li = self.level_info(level)
@@ -295,7 +312,8 @@ class Hierarchy:
         parts = []
         for l in range(self.L):
             li = self.level_info(l)
-            parts.append(f"{li.nv}-{li.nnz}-{li.nparts}" + (f"-mls{li.p_nnz}" if li.transfer == MLS else ""))
+            parts.append(f"{li.nv}-{li.nnz}-{li.nparts}" + (f"-mls{li.p_nnz}" if li.transfer == MLS else "")
+                         + (f"-ilu{li.ilu_nnz}" if li.subsolver == ILU else ""))
         return f"p{self.precision}_" + "_".join(parts)
 
     def system_bytes(self, restart: int = 30) -> int:
@@ -345,6 +363,11 @@ class System:
         b = np.empty(self.n[0])
         _check(_lib.nnms_system_rhs(self.handle, _ptr(b)))
         return b
+
+    def ilu_values(self, level: int) -> np.ndarray:
+        v = np.empty(self.h.level_info(level).ilu_nnz)
+        _check(_lib.nnms_system_ilu_values(self.handle, level, _ptr(v)))
+        return v
 
     def matrix_values(self, level: int) -> np.ndarray:
         v = np.empty(self.h.level_info(level).nnz)

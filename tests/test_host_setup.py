@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from oracle import mls, schwarz, transfer
+from oracle import ilu, mls, schwarz, transfer
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -122,6 +122,37 @@ def test_mls_rejects_bad_scale():
         with pytest.raises(nnms.NNMSError) as e:
             nnms.Hierarchy(ms, pb.nparts, device=False, transfer=nnms.MLS, mls_alpha=a)
         assert e.value.name == "INVALID_ARG"
+
+
+@pytest.mark.parametrize("fill", [[0, 0], [1, 0], [2, 1]])
+def test_ilu_patterns_match_oracle(fill):
+    pb = W.Problem("tiny3", [W.kuhn_cube(9, 1), W.kuhn_cube(5, 2), W.kuhn_cube(3, 3)], [4, 2], W.KappaField())
+    ms = [nnms.Mesh.from_workload(m) for m in pb.meshes]
+    h = nnms.Hierarchy(ms, pb.nparts, device=False, subsolver=nnms.ILU, ilu_fill=fill)
+    from oracle import fem
+    for l in range(2):
+        m = pb.meshes[l]
+        A, _ = fem.assemble(m, pb.kappa)
+        li = h.level_info(l)
+        assert li.subsolver == nnms.ILU and li.ilu_nnz > 0
+        rp, col = h.ilu_pattern(l)
+        owner, sets = h.partition(l)
+        row = 0
+        for S in sets:
+            cols, _ = ilu.symbolic(A[S][:, S].tocsr(), fill[l])
+            for i in range(len(S)):
+                assert np.array_equal(col[rp[row]:rp[row + 1]], cols[i]), (l, row)
+                row += 1
+        assert rp[row] == li.ilu_nnz
+    assert h.level_info(2).subsolver == nnms.LU  # the coarsest level is solved directly
+
+
+def test_ilu_rejects_bad_fill():
+    pb = W.cube16_two_level()
+    ms = [nnms.Mesh.from_workload(m) for m in pb.meshes]
+    with pytest.raises(nnms.NNMSError) as e:
+        nnms.Hierarchy(ms, pb.nparts, device=False, subsolver=nnms.ILU, ilu_fill=[-1])
+    assert e.value.name == "INVALID_ARG"
 
 
 def test_level_info_counts():
