@@ -160,7 +160,7 @@ struct DevLevel {
   // ILU subdomain solver (subsolver == NNMS_SUBSOLVER_ILU)
   int32_t subsolver = NNMS_SUBSOLVER_LU;
   int32_t *ilu_rp = nullptr, *ilu_col = nullptr, *ilu_asrc = nullptr, *ilu_dpos = nullptr, *ilu_gid = nullptr;
-  int32_t *ilu_fperm = nullptr, *ilu_bperm = nullptr, *ilu_flev = nullptr, *ilu_blev = nullptr;
+  int32_t *ilu_fmeta = nullptr, *ilu_bmeta = nullptr, *ilu_flev = nullptr, *ilu_blev = nullptr;
 };
 
 }  // namespace nnms
@@ -507,9 +507,9 @@ static std::vector<IluDesc> ilu_descs(const nnms_system& x, int l, bool with_sta
   for (int p = 0; p < hl.nparts; ++p) {
     const int64_t base = hl.s_ptr[p];
     IluDesc d{};
-    d.rp = dl.ilu_rp + base, d.col = dl.ilu_col, d.dpos = dl.ilu_dpos + base;
-    d.fperm = dl.ilu_fperm + base, d.flev = dl.ilu_flev + hl.ilu_flev_off[p];
-    d.bperm = dl.ilu_bperm + base, d.blev = dl.ilu_blev + hl.ilu_blev_off[p];
+    d.rp = dl.ilu_rp + base, d.dpos = dl.ilu_dpos + base, d.col = dl.ilu_col;
+    d.fmeta = dl.ilu_fmeta + base * 4, d.flev = dl.ilu_flev + hl.ilu_flev_off[p];
+    d.bmeta = dl.ilu_bmeta + base * 4, d.blev = dl.ilu_blev + hl.ilu_blev_off[p];
     d.gid = dl.ilu_gid + base, d.val = sl.ilu_val;
     d.rin = sl.r, d.zout = sl.z, d.st = with_state ? x.st : nullptr;
     d.n = int32_t(hl.s_ptr[p + 1] - base);
@@ -964,8 +964,8 @@ extern "C" nnms_status nnms_hierarchy_setup(const nnms_mesh* const* levels, int3
         d.ilu_asrc = A.upload(hl.ilu_asrc, s);
         d.ilu_dpos = A.upload(hl.ilu_dpos, s);
         d.ilu_gid = A.upload(hl.ilu_gid, s);
-        d.ilu_fperm = A.upload(hl.ilu_fperm, s);
-        d.ilu_bperm = A.upload(hl.ilu_bperm, s);
+        d.ilu_fmeta = A.upload(hl.ilu_fmeta, s);
+        d.ilu_bmeta = A.upload(hl.ilu_bmeta, s);
         d.ilu_flev = A.upload(hl.ilu_flev, s);
         d.ilu_blev = A.upload(hl.ilu_blev, s);
       }

@@ -85,11 +85,11 @@ struct RasLaunch {
 // concatenated pattern arrays (col, val).
 struct IluDesc {
   const int32_t* rp;     // n+1: first entry of every row
-  const int32_t* col;    // local column of every entry (the level's array)
   const int32_t* dpos;   // n: entry of every row's diagonal
-  const int32_t* fperm;  // n: rows by forward level
-  const int32_t* flev;   // nfl+1: level boundaries in fperm
-  const int32_t* bperm;  // n: rows by backward level
+  const int32_t* col;    // local column of every entry (the level's array)
+  const int32_t* fmeta;  // 4n, by forward level: {row, first entry, diagonal entry, end}
+  const int32_t* flev;   // nfl+1: level boundaries in fmeta
+  const int32_t* bmeta;  // 4n, by backward level: {row, diagonal + 1, end, diagonal entry}
   const int32_t* blev;   // nbl+1
   const int32_t* gid;    // n: global id (>= 0 owned, -g-2 overlap)
   void* val;             // factor values of every entry (the level's array)

@@ -496,9 +496,26 @@ void build_ilu(HostLevel& lv, int fill) {
     lv.ilu_blev_off[p + 1] = int64_t(lv.ilu_blev.size());
   }
   lv.ilu_rp[ns] = int32_t(lv.ilu_col.size());
+  // per schedule position, the row and its entry ranges, so that a kernel
+  // reaches a row's entries with one dependent load instead of three:
+  // forward {row, first, diagonal, end}, backward {row, diagonal + 1, end,
+  // diagonal} (entry indices global, rows local)
+  lv.ilu_fmeta.assign(size_t(ns) * 4, 0);
+  lv.ilu_bmeta.assign(size_t(ns) * 4, 0);
+  for (int p = 0; p < np; ++p) {
+    const int64_t base = lv.s_ptr[p], n = lv.s_ptr[p + 1] - base;
+    for (int64_t q = 0; q < n; ++q) {
+      const int32_t i = lv.ilu_fperm[base + q], r = int32_t(base) + i;
+      int32_t* m = &lv.ilu_fmeta[size_t(base + q) * 4];
+      m[0] = i, m[1] = lv.ilu_rp[r], m[2] = lv.ilu_dpos[r], m[3] = lv.ilu_rp[r + 1];
+      const int32_t j = lv.ilu_bperm[base + q], t = int32_t(base) + j;
+      int32_t* w = &lv.ilu_bmeta[size_t(base + q) * 4];
+      w[0] = j, w[1] = lv.ilu_dpos[t] + 1, w[2] = lv.ilu_rp[t + 1], w[3] = lv.ilu_dpos[t];
+    }
+  }
   // lanes per row of the device kernels: a group stages at most 4 entries
-  // per lane in the factorisation, and takes about two per lane in each
-  // triangular solve
+  // per lane in the factorisation and takes at most 2 per lane of a row's
+  // lower or upper part in the triangular solves
   int32_t maxlen = 0, maxhalf = 0;
   for (int64_t r = 0; r < ns; ++r) {
     const int32_t a = lv.ilu_rp[r], b = lv.ilu_rp[r + 1], d = lv.ilu_dpos[r];
@@ -507,7 +524,7 @@ void build_ilu(HostLevel& lv, int fill) {
   }
   int32_t lanes = 4;
   while (lanes < 32 && (4 * lanes < maxlen || 2 * lanes < maxhalf)) lanes *= 2;
-  if (4 * lanes < maxlen)
+  if (4 * lanes < maxlen || 2 * lanes < maxhalf)
     throw Error(NNMS_ERR_INVALID_ARG, "ILU rows too long for the device kernels (" + std::to_string(maxlen) +
                                           " entries; lower the fill level)");
   lv.ilu_lanes = lanes;

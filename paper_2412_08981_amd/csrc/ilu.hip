@@ -16,6 +16,12 @@
 
 namespace nnms {
 
+// one 16-byte schedule entry through a global-address-space pointer
+__device__ __forceinline__ int4 meta_at(const int32_t* m, int q) {
+  const GLOBAL int32_t* p = gptr(m) + 4 * q;
+  return make_int4(p[0], p[1], p[2], p[3]);
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_ilu_extract(const int32_t* __restrict__ asrc, const double* __restrict__ a,
                                                      T* __restrict__ val, int64_t n) {
@@ -48,8 +54,8 @@ __global__ __launch_bounds__(256) void k_ilu_factor(const IluDesc* __restrict__ 
   for (int lv = 0; lv < D.nfl; ++lv) {
     const int r0 = gptr(D.flev)[lv], r1 = gptr(D.flev)[lv + 1];
     for (int q = r0 + grp; q < r1; q += ngrp) {  // uniform within a group
-      const int i = gptr(D.fperm)[q];
-      const int a = rp[i], len = rp[i + 1] - a, di = dpos[i] - a;
+      const int4 m = meta_at(D.fmeta, q);
+      const int a = m.y, len = m.w - m.y, di = m.z - m.y;
       for (int m = lane; m < len; m += G) rv[m] = val[a + m], rc[m] = col[a + m];
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       __builtin_amdgcn_wave_barrier();
@@ -92,17 +98,80 @@ __device__ __forceinline__ T group_sum(T v) {
   return v;
 }
 
+// Work-group barrier that orders LDS only: the apply's global memory is
+// read-only until the final scatter, so loads issued before the barrier
+// (the next level's factor entries) stay in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// The (at most two per lane) entries of one row's lower (FWD) or upper part
+// that a lane of the row's group takes: entries e0 = first + lane and
+// e1 = e0 + G; the host picks G with 2G >= the longest such part.
+template <typename T, int G, bool FWD>
+struct IluRow {
+  int i = -1, c0 = -1, c1 = -1;
+  T v0 = 0, v1 = 0, diag = 1;
+  __device__ __forceinline__ void load(const IluDesc& D, int q, int lane) {
+    // forward {row, first, diagonal, end}: the lower part is [first, diagonal);
+    // backward {row, diagonal + 1, end, diagonal}: the upper part [y, z)
+    const int4 m = meta_at(FWD ? D.fmeta : D.bmeta, q);
+    i = m.x;
+    const int first = m.y, end = m.z;
+    const int e0 = first + lane, e1 = e0 + G;
+    const GLOBAL T* val = gptr((const T*)D.val);
+    c0 = e0 < end ? gptr(D.col)[e0] : -1;
+    v0 = e0 < end ? val[e0] : T(0);
+    c1 = e1 < end ? gptr(D.col)[e1] : -1;
+    v1 = e1 < end ? val[e1] : T(0);
+    if (!FWD) diag = val[m.w];
+  }
+  // y_i -= sum (forward) or y_i = (y_i - sum) / u_ii (backward), the partial
+  // sums of the group added by a fixed xor tree
+  __device__ __forceinline__ void apply(T* y, int lane) const {
+    T s = c0 >= 0 ? v0 * y[c0] : T(0);
+    if (c1 >= 0) s += v1 * y[c1];
+    s = group_sum<T, G>(s);
+    if (lane == 0) y[i] = FWD ? y[i] - s : (y[i] - s) / diag;
+  }
+};
+
+// One sweep over the levels of one triangular factor.  The group's first
+// row of the next level is loaded before the barrier that ends the current
+// one, so its global loads overlap the barrier and the slowest group.
+template <typename T, int G, bool FWD>
+__device__ __forceinline__ void ilu_sweep(const IluDesc& D, T* y, int grp, int lane, int ngrp) {
+  const int nl = FWD ? D.nfl : D.nbl;
+  const GLOBAL int32_t* lev = gptr(FWD ? D.flev : D.blev);
+  IluRow<T, G, FWD> cur;
+  int r0 = lev[0], r1 = nl > 0 ? lev[1] : 0;
+  if (nl > 0 && r0 + grp < r1) cur.load(D, r0 + grp, lane);
+  for (int lv = 0; lv < nl; ++lv) {
+    const bool have = r0 + grp < r1;  // uniform within a group
+    if (have) cur.apply(y, lane);
+    for (int q = r0 + grp + ngrp; q < r1; q += ngrp) {
+      IluRow<T, G, FWD> more;
+      more.load(D, q, lane);
+      more.apply(y, lane);
+    }
+    if (lv + 1 < nl) {
+      r0 = r1;
+      r1 = lev[lv + 2];
+      if (r0 + grp < r1) cur.load(D, r0 + grp, lane);
+    }
+    lds_barrier();
+  }
+}
+
 template <typename T, int G>
 __global__ __launch_bounds__(256) void k_ilu_apply(const IluDesc* __restrict__ d, int add) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T* y = reinterpret_cast<T*>(lds_raw);
   const IluDesc D = d[blockIdx.x];
   if (!slot_active(D.st, WHEN_RUNNING)) return;
-  const GLOBAL int32_t* rp = gptr(D.rp);
-  const GLOBAL int32_t* col = gptr(D.col);
-  const GLOBAL int32_t* dpos = gptr(D.dpos);
   const GLOBAL int32_t* gid = gptr(D.gid);
-  const GLOBAL T* val = gptr((const T*)D.val);
   const GLOBAL T* rin = gptr((const T*)D.rin);
   const int grp = int(threadIdx.x) / G, lane = int(threadIdx.x) % G, ngrp = int(blockDim.x) / G;
   for (int i = threadIdx.x; i < D.n; i += blockDim.x) {
@@ -110,29 +179,8 @@ __global__ __launch_bounds__(256) void k_ilu_apply(const IluDesc* __restrict__ d
     y[i] = rin[g >= 0 ? g : -g - 2];
   }
   __syncthreads();
-  for (int lv = 0; lv < D.nfl; ++lv) {
-    const int r0 = gptr(D.flev)[lv], r1 = gptr(D.flev)[lv + 1];
-    for (int q = r0 + grp; q < r1; q += ngrp) {  // uniform within a group
-      const int i = gptr(D.fperm)[q];
-      T s = 0;
-      for (int e = rp[i] + lane, de = dpos[i]; e < de; e += G) s += val[e] * y[col[e]];
-      s = group_sum<T, G>(s);
-      if (lane == 0) y[i] -= s;
-    }
-    __syncthreads();
-  }
-  for (int lv = 0; lv < D.nbl; ++lv) {
-    const int r0 = gptr(D.blev)[lv], r1 = gptr(D.blev)[lv + 1];
-    for (int q = r0 + grp; q < r1; q += ngrp) {
-      const int i = gptr(D.bperm)[q];
-      const int de = dpos[i];
-      T s = 0;
-      for (int e = de + 1 + lane, b = rp[i + 1]; e < b; e += G) s += val[e] * y[col[e]];
-      s = group_sum<T, G>(s);
-      if (lane == 0) y[i] = (y[i] - s) / val[de];
-    }
-    __syncthreads();
-  }
+  ilu_sweep<T, G, true>(D, y, grp, lane, ngrp);
+  ilu_sweep<T, G, false>(D, y, grp, lane, ngrp);
   GLOBAL T* z = gptr((T*)D.zout);
   for (int i = threadIdx.x; i < D.n; i += blockDim.x) {
     const int g = gid[i];

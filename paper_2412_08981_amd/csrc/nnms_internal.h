@@ -89,6 +89,7 @@ struct HostLevel {
   std::vector<int32_t> ilu_dpos;     // entry index of every row's diagonal
   std::vector<int32_t> ilu_gid;      // global id, >= 0 owned, -g-2 overlap
   std::vector<int32_t> ilu_fperm, ilu_bperm;  // local rows by forward / backward level
+  std::vector<int32_t> ilu_fmeta, ilu_bmeta;  // 4 per schedule position (see build_ilu)
   std::vector<int32_t> ilu_flev, ilu_blev;    // per subdomain: level boundaries (nlev+1) into its perm
   std::vector<int64_t> ilu_flev_off, ilu_blev_off;  // nparts+1: start of every subdomain's boundaries
 };
