@@ -104,7 +104,7 @@ def prolong_bytes(h, level, s_bytes):
 def restrict_bytes(h, level, s_bytes):
     """r_c = P^T t: the CSR of P^T over coarse rows, t once, r_c written."""
     li, lc = h.level_info(level), h.level_info(level + 1)
-    return float(li.p_nnz * (4 + s_bytes) + 4 * (lc.nv + 1) + (li.nv + lc.nv) * s_bytes)
+    return float(li.r_nnz * (4 + s_bytes) + 4 * (lc.nv + 1) + (li.nv + lc.nv) * s_bytes)
 
 
 def cpu_baseline(pb, seconds_cap=60.0, mls_alpha=None):

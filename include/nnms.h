@@ -129,7 +129,10 @@ void nnms_mesh_destroy(nnms_mesh* m);
  *             the mean coarse edge length and grows by 1.25 until the
  *             neighbourhood has full rank (Theorem 1).  The neighbourhood
  *             is not clipped to a subdomain: the whole coarse level is
- *             resident on the device;
+ *             resident on the device; with mls_restrict = 1 the residual
+ *             goes down by the second MLS interpolation of Algorithm 2, from
+ *             the fine to the coarse nodes (scale from the mean fine edge
+ *             length), instead of P_l^T;
  *             subsolver NNMS_SUBSOLVER_LU (default: dense LU of every
  *             overlapping subdomain matrix) or NNMS_SUBSOLVER_ILU: ILU(k)
  *             of A[S_p, S_p] in natural ordering with k = ilu_fill[l]
@@ -154,6 +157,8 @@ typedef struct {
   double mls_alpha;  /* MLS initial scale / mean coarse edge length (> 0) */
   int32_t subsolver; /* nnms_subsolver of every smoothed level */
   int32_t ilu_fill[NNMS_MAX_LEVELS]; /* ILU level of fill per smoothed level (>= 0) */
+  int32_t mls_restrict; /* with MLS: 1 = restrict by the MLS interpolation from
+                           the fine to the coarse nodes, 0 = by P_l^T */
 } nnms_setup_opts;
 
 nnms_status nnms_setup_opts_default(nnms_setup_opts* o);
@@ -175,10 +180,11 @@ typedef struct {
   int32_t transfer;     /* nnms_transfer of P_l (smoothed levels) */
   int64_t s_total;      /* sum of subdomain sizes */
   int64_t factor_elems; /* dense factor entries stored, incl. 64-padding */
-  int64_t p_nnz;        /* entries of P_l and of P_l^T (0 on the coarsest level) */
+  int64_t p_nnz;        /* entries of P_l (0 on the coarsest level) */
   int32_t subsolver;    /* nnms_subsolver of the level's smoother */
-  int32_t reserved2;
+  int32_t mls_restrict; /* 1: the restriction is the fine-to-coarse MLS operator */
   int64_t ilu_nnz;      /* entries of all ILU patterns of the level (0 without ILU) */
+  int64_t r_nnz;        /* entries of the restriction (P_l^T or the MLS operator) */
 } nnms_level_info;
 
 nnms_status nnms_hierarchy_level_info(const nnms_hierarchy* h, int32_t level, nnms_level_info* out);
@@ -198,6 +204,11 @@ nnms_status nnms_hierarchy_transfer(const nnms_hierarchy* h, int32_t level, int3
  * within a row for MLS, in tetrahedron-vertex order for barycentric). */
 nnms_status nnms_hierarchy_transfer_csr(const nnms_hierarchy* h, int32_t level, int32_t* row_ptr_host,
                                         int32_t* col_host, double* w_host);
+/* The restriction of level `level` as CSR over the coarse vertices:
+ * row_ptr_host[nv_{l+1}+1], col_host[r_nnz], w_host[r_nnz] (P_l^T, or the
+ * fine-to-coarse MLS operator with mls_restrict). */
+nnms_status nnms_hierarchy_restriction_csr(const nnms_hierarchy* h, int32_t level, int32_t* row_ptr_host,
+                                           int32_t* col_host, double* w_host);
 /* ILU levels: the ILU(k) pattern of every subdomain in local numbering (the
  * subdomain's rows in the order of nnms_hierarchy_partition's S_p), rows of
  * all subdomains concatenated: row_ptr_host[s_total+1] entry offsets,

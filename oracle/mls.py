@@ -127,3 +127,10 @@ def interpolation(target, source, alpha: float = ALPHA, mask_dirichlet: bool = T
 def prolongation(fine, coarse, alpha: float = ALPHA, mask_dirichlet: bool = True) -> sp.csr_matrix:
     """P_l: coarse -> fine by MLS (the coarse nodes are the sources)."""
     return interpolation(fine, coarse, alpha, mask_dirichlet)
+
+
+def restriction(fine, coarse, alpha: float = ALPHA, mask_dirichlet: bool = True) -> sp.csr_matrix:
+    """R_l: fine -> coarse by MLS (the fine nodes are the sources; the scale
+    starts at alpha times the fine mesh's mean edge length): the paper's
+    second interpolation, applied to the residual as it stands."""
+    return interpolation(coarse, fine, alpha, mask_dirichlet)

@@ -5,7 +5,8 @@ Algorithm 2 of the paper (Section 3.3), read as follows:
     steps z <- z + B_i^{-1}(r_i - A_i z) are taken (its = 3, Section 4; the
     loop runs its times, since its output is z^(its));
   * the residual r_i - A_i z_i is carried to level i+1 by the fine-to-coarse
-    operator, here P_i^T;
+    operator, here P_i^T, or a fine-to-coarse interpolation R_i of its own
+    when one is given (the paper's second MLS interpolation);
   * the coarsest level is solved directly (a dense LU), instead of being
     smoothed;
   * on the way up, z_i <- z_i + P_i z_{i+1}, followed by `its` more
@@ -32,6 +33,7 @@ class Level:
     dmask: np.ndarray
     ras: Optional[RAS] = None  # None on the coarsest level
     P: Optional[sp.csr_matrix] = None  # maps level i+1 -> level i
+    R: Optional[sp.csr_matrix] = None  # maps level i -> level i+1 (None: P^T)
 
 
 class VCycle:
@@ -52,7 +54,8 @@ class VCycle:
             for _ in range(self.its):
                 zi = zi + lev.ras.apply(r[i] - lev.A @ zi)
             z[i] = zi
-            r[i + 1] = lev.P.T @ (r[i] - lev.A @ zi)
+            t = r[i] - lev.A @ zi
+            r[i + 1] = lev.P.T @ t if lev.R is None else lev.R @ t
         z[L - 1] = sla.lu_solve(self.coarse_lu, r[L - 1])
         for i in range(L - 2, -1, -1):
             lev = self.levels[i]

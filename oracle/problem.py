@@ -28,11 +28,13 @@ class OracleHierarchy:
 
 
 def build(problem, f: float = 1.0, locate=transfer.locate_bucket, mls_alpha: Optional[float] = None,
-          ilu_fill: Optional[List[int]] = None) -> OracleHierarchy:
+          ilu_fill: Optional[List[int]] = None, mls_restrict: bool = False) -> OracleHierarchy:
     """mls_alpha: None for the barycentric transfer, else the MLS transfer of
     Section 3.2 with initial scale mls_alpha times the coarse mean edge.
     ilu_fill: None for exact subdomain solves, else the ILU fill level of
-    every smoothed level (the coarsest level is always solved directly)."""
+    every smoothed level (the coarsest level is always solved directly).
+    mls_restrict: with the MLS transfer, restrict by the fine-to-coarse MLS
+    interpolation instead of P^T."""
     meshes = problem.meshes
     L = len(meshes)
     A, P, parts, levels = [], [], [], []
@@ -50,7 +52,10 @@ def build(problem, f: float = 1.0, locate=transfer.locate_bucket, mls_alpha: Opt
         owned, sets = schwarz.partition(meshes[l], problem.nparts[l], problem.overlap)
         parts.append((owned, sets))
         ras = schwarz.RAS(A[l], meshes[l].dirichlet, owned, sets, None if ilu_fill is None else ilu_fill[l])
-        levels.append(multilevel.Level(A[l], meshes[l].dirichlet, ras, P[l]))
+        R = None
+        if mls_restrict and mls_alpha is not None:
+            R = mls.restriction(meshes[l], meshes[l + 1], mls_alpha)
+        levels.append(multilevel.Level(A[l], meshes[l].dirichlet, ras, P[l], R))
     levels.append(multilevel.Level(A[L - 1], meshes[L - 1].dirichlet))
     vc = multilevel.VCycle(levels, problem.its)
     return OracleHierarchy(problem, A, b, P, parts, vc)

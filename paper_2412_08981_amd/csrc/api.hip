@@ -883,7 +883,7 @@ static void build_host(const nnms_mesh* const* levels, int32_t L, const nnms_set
   }
   for (int l = 0; l + 1 < L; ++l) {
     if (opts->transfer == NNMS_TRANSFER_MLS)
-      build_transfer_mls(H.lev[l], H.lev[l + 1], opts->mls_alpha);
+      build_transfer_mls(H.lev[l], H.lev[l + 1], opts->mls_alpha, opts->mls_restrict != 0);
     else
       build_transfer(H.lev[l], H.lev[l + 1]);
   }
@@ -1003,10 +1003,12 @@ extern "C" nnms_status nnms_hierarchy_level_info(const nnms_hierarchy* h, int32_
   o->max_block = mx, o->min_block = lv.nparts ? mn : 0;
   o->s_total = int64_t(lv.s_idx.size());
   o->factor_elems = lv.fac_elems;
-  o->p_nnz = int64_t(lv.pt_col.size());
   o->transfer = lv.transfer;
   o->subsolver = lv.subsolver;
   o->ilu_nnz = int64_t(lv.ilu_col.size());
+  o->mls_restrict = lv.mls_restrict;
+  o->p_nnz = int64_t(lv.p_col.size());
+  o->r_nnz = int64_t(lv.pt_col.size());
   return NNMS_OK;
   ABI_END
 }
@@ -1053,6 +1055,18 @@ extern "C" nnms_status nnms_hierarchy_transfer_csr(const nnms_hierarchy* h, int3
   std::memcpy(rp, lv.p_rp.data(), lv.p_rp.size() * sizeof(int32_t));
   std::memcpy(col, lv.p_col.data(), lv.p_col.size() * sizeof(int32_t));
   std::memcpy(w, lv.p_val.data(), lv.p_val.size() * sizeof(double));
+  return NNMS_OK;
+  ABI_END
+}
+
+extern "C" nnms_status nnms_hierarchy_restriction_csr(const nnms_hierarchy* h, int32_t level, int32_t* rp,
+                                                      int32_t* col, double* w) {
+  ABI_BEGIN
+  if (!h || !rp || !col || !w || level < 0 || level + 1 >= h->host.L) throw Error(NNMS_ERR_INVALID_ARG, "bad arguments");
+  const HostLevel& lv = h->host.lev[level];
+  std::memcpy(rp, lv.pt_rp.data(), lv.pt_rp.size() * sizeof(int32_t));
+  std::memcpy(col, lv.pt_col.data(), lv.pt_col.size() * sizeof(int32_t));
+  std::memcpy(w, lv.pt_w.data(), lv.pt_w.size() * sizeof(double));
   return NNMS_OK;
   ABI_END
 }

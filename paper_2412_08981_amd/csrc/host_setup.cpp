@@ -627,10 +627,14 @@ double mean_edge_length(const HostLevel& lv) {
   return e.empty() ? 0.0 : sum / double(e.size());
 }
 
-void build_transfer_mls(HostLevel& fine, const HostLevel& coarse, double alpha) {
+// The MLS operator from the nodal values of `src` to the nodes of `dst`
+// (rows: dst vertices, Dirichlet rows empty, Dirichlet src columns dropped),
+// scale starting at alpha times the mean edge length of src.
+static void mls_operator(const HostLevel& fine, const HostLevel& coarse, double alpha, std::vector<int32_t>& p_rp,
+                         std::vector<int32_t>& p_col, std::vector<double>& p_val) {
   if (!(alpha > 0)) throw Error(NNMS_ERR_INVALID_ARG, "MLS scale factor must be positive");
   const double rho0 = alpha * mean_edge_length(coarse);
-  if (!(rho0 > 0)) throw Error(NNMS_ERR_INVALID_ARG, "degenerate coarse mesh");
+  if (!(rho0 > 0)) throw Error(NNMS_ERR_INVALID_ARG, "degenerate source mesh");
   const int64_t nc = coarse.nv, nf = fine.nv;
   // uniform bucket grid over the coarse vertices, cell edge rho0
   double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
@@ -659,16 +663,13 @@ void build_transfer_mls(HostLevel& fine, const HostLevel& coarse, double alpha) 
       citem[fill[cell(x[0], 0) + int64_t(nb[0]) * (cell(x[1], 1) + int64_t(nb[1]) * cell(x[2], 2))]++] = int32_t(v);
     }
   }
-  fine.p_idx.assign(nf * 4, 0);  // the four-entry form is not used by this transfer
-  fine.p_w.assign(nf * 4, 0.0);
-  fine.ncoarse = nc;
-  fine.p_rp.assign(nf + 1, 0);
-  fine.p_col.clear();
-  fine.p_val.clear();
+  p_rp.assign(nf + 1, 0);
+  p_col.clear();
+  p_val.clear();
   std::vector<int32_t> ids;
   std::vector<double> q, w;
   for (int64_t v = 0; v < nf; ++v) {
-    fine.p_rp[v + 1] = fine.p_rp[v];
+    p_rp[v + 1] = p_rp[v];
     if (fine.dir[v]) continue;
     const double* xs = &fine.xyz[v * 3];
     double rho = rho0;
@@ -713,28 +714,43 @@ void build_transfer_mls(HostLevel& fine, const HostLevel& coarse, double alpha) 
       for (size_t n = 0; n < m; ++n) {
         if (coarse.dir[ids[n]]) continue;
         const double* qn = &q[n * 4];
-        fine.p_col.push_back(ids[n]);
-        fine.p_val.push_back(w[n] * (c[0] * qn[0] + c[1] * qn[1] + c[2] * qn[2] + c[3] * qn[3]));
+        p_col.push_back(ids[n]);
+        p_val.push_back(w[n] * (c[0] * qn[0] + c[1] * qn[1] + c[2] * qn[2] + c[3] * qn[3]));
       }
-      fine.p_rp[v + 1] = int32_t(fine.p_col.size());
+      p_rp[v + 1] = int32_t(p_col.size());
       ok = true;
     }
-    if (!ok) throw Error(NNMS_ERR_POINT_LOCATION, "no full-rank MLS neighbourhood for fine vertex " + std::to_string(v));
-    if (fine.p_col.size() > size_t(INT32_MAX / 2)) throw Error(NNMS_ERR_INVALID_ARG, "MLS transfer too large");
+    if (!ok) throw Error(NNMS_ERR_POINT_LOCATION, "no full-rank MLS neighbourhood for vertex " + std::to_string(v));
+    if (p_col.size() > size_t(INT32_MAX / 2)) throw Error(NNMS_ERR_INVALID_ARG, "MLS transfer too large");
   }
-  // explicit transpose: rows = coarse vertices, entries ordered by fine id
-  fine.pt_rp.assign(nc + 1, 0);
-  for (int32_t c : fine.p_col) fine.pt_rp[c + 1]++;
-  for (int64_t c = 0; c < nc; ++c) fine.pt_rp[c + 1] += fine.pt_rp[c];
-  fine.pt_col.resize(fine.pt_rp[nc]);
-  fine.pt_w.resize(fine.pt_rp[nc]);
-  std::vector<int32_t> fill(fine.pt_rp.begin(), fine.pt_rp.end() - 1);
-  for (int64_t v = 0; v < nf; ++v)
-    for (int32_t e = fine.p_rp[v]; e < fine.p_rp[v + 1]; ++e) {
-      const int32_t c = fine.p_col[e];
-      fine.pt_col[fill[c]] = int32_t(v);
-      fine.pt_w[fill[c]++] = fine.p_val[e];
-    }
+}
+
+void build_transfer_mls(HostLevel& fine, const HostLevel& coarse, double alpha, bool mls_restrict) {
+  const int64_t nc = coarse.nv, nf = fine.nv;
+  mls_operator(fine, coarse, alpha, fine.p_rp, fine.p_col, fine.p_val);
+  fine.p_idx.assign(nf * 4, 0);  // the four-entry form is not used by this transfer
+  fine.p_w.assign(nf * 4, 0.0);
+  fine.ncoarse = nc;
+  if (mls_restrict) {
+    // the paper's second interpolation: fine nodal values to the coarse
+    // nodes by MLS, in place of the transpose
+    mls_operator(coarse, fine, alpha, fine.pt_rp, fine.pt_col, fine.pt_w);
+  } else {
+    // explicit transpose: rows = coarse vertices, entries ordered by fine id
+    fine.pt_rp.assign(nc + 1, 0);
+    for (int32_t c : fine.p_col) fine.pt_rp[c + 1]++;
+    for (int64_t c = 0; c < nc; ++c) fine.pt_rp[c + 1] += fine.pt_rp[c];
+    fine.pt_col.resize(fine.pt_rp[nc]);
+    fine.pt_w.resize(fine.pt_rp[nc]);
+    std::vector<int32_t> fill(fine.pt_rp.begin(), fine.pt_rp.end() - 1);
+    for (int64_t v = 0; v < nf; ++v)
+      for (int32_t e = fine.p_rp[v]; e < fine.p_rp[v + 1]; ++e) {
+        const int32_t c = fine.p_col[e];
+        fine.pt_col[fill[c]] = int32_t(v);
+        fine.pt_w[fill[c]++] = fine.p_val[e];
+      }
+  }
+  fine.mls_restrict = mls_restrict ? 1 : 0;
   std::vector<int32_t> src;
   build_sell_layout(fine.pt_rp, fine.pt_col, nc, fine.pts_off, fine.pts_col, src);
   fine.pts_w.assign(src.size(), 0.0);
@@ -818,5 +834,6 @@ extern "C" nnms_status nnms_setup_opts_default(nnms_setup_opts* o) {
   o->mls_alpha = 1.0;
   o->subsolver = NNMS_SUBSOLVER_LU;
   o->ilu_fill[0] = 2;  // ILU(2) on the finest level, ILU(0) on the others
+  o->mls_restrict = 0;
   return NNMS_OK;
 }

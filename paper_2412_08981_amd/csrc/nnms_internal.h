@@ -72,6 +72,7 @@ struct HostLevel {
   // transfer kind; P_l as CSR over the fine vertices (Dirichlet rows empty,
   // Dirichlet coarse columns dropped) for both kinds
   int32_t transfer = NNMS_TRANSFER_BARYCENTRIC;
+  int32_t mls_restrict = 0;  // pt_* hold the fine-to-coarse MLS operator, not P^T
   std::vector<int32_t> p_rp, p_col;
   std::vector<double> p_val;
   // MLS only: -P_l in the sliced ELL layout (the prolongation's launch)
@@ -111,8 +112,9 @@ void build_sell(HostLevel& lv);
 void build_partition(HostLevel& lv, int nparts, int overlap, bool direct);
 void build_transfer(HostLevel& fine, const HostLevel& coarse);
 // moving-least-squares transfer (Section 3.2), initial scale alpha times the
-// mean coarse edge length
-void build_transfer_mls(HostLevel& fine, const HostLevel& coarse, double alpha);
+// mean coarse edge length; with mls_restrict the restriction is the MLS
+// interpolation from the fine to the coarse nodes, else P^T
+void build_transfer_mls(HostLevel& fine, const HostLevel& coarse, double alpha, bool mls_restrict);
 double mean_edge_length(const HostLevel& lv);
 // ILU(fill) pattern and level schedules of every subdomain (after the partition)
 void build_ilu(HostLevel& lv, int fill);

@@ -52,14 +52,15 @@ class NNMSError(RuntimeError):
 class setup_opts(C.Structure):
     _fields_ = [("nparts", C.c_int32 * MAX_LEVELS), ("overlap", C.c_int32), ("its", C.c_int32),
                 ("precision", C.c_int32), ("transfer", C.c_int32), ("mls_alpha", C.c_double),
-                ("subsolver", C.c_int32), ("ilu_fill", C.c_int32 * MAX_LEVELS)]
+                ("subsolver", C.c_int32), ("ilu_fill", C.c_int32 * MAX_LEVELS), ("mls_restrict", C.c_int32)]
 
 
 class level_info(C.Structure):
     _fields_ = [("nv", C.c_int64), ("nt", C.c_int64), ("ninterior", C.c_int64), ("nnz", C.c_int64),
                 ("nparts", C.c_int32), ("max_block", C.c_int32), ("min_block", C.c_int32), ("transfer", C.c_int32),
                 ("s_total", C.c_int64), ("factor_elems", C.c_int64), ("p_nnz", C.c_int64),
-                ("subsolver", C.c_int32), ("reserved2", C.c_int32), ("ilu_nnz", C.c_int64)]
+                ("subsolver", C.c_int32), ("mls_restrict", C.c_int32), ("ilu_nnz", C.c_int64),
+                ("r_nnz", C.c_int64)]
 
 
 class kappa_t(C.Structure):
@@ -121,6 +122,7 @@ _sig = {
     "nnms_hierarchy_transfer": (C.c_int, [vp, C.c_int32, vp, vp]),
     "nnms_hierarchy_transfer_csr": (C.c_int, [vp, C.c_int32, vp, vp, vp]),
     "nnms_hierarchy_ilu_pattern": (C.c_int, [vp, C.c_int32, vp, vp]),
+    "nnms_hierarchy_restriction_csr": (C.c_int, [vp, C.c_int32, vp, vp, vp]),
     "nnms_system_ilu_values": (C.c_int, [vp, C.c_int32, vp]),
     "nnms_hierarchy_system_bytes": (C.c_int64, [vp, C.c_int32]),
     "nnms_assemble": (C.c_int, [vp, C.POINTER(kappa_t), C.c_double, vp, C.POINTER(vp)]),
@@ -228,7 +230,7 @@ class Hierarchy:
     def __init__(self, meshes: Sequence[Mesh], nparts: Sequence[int] = (), overlap: int = 1, its: int = 3,
                  precision: int = FP64, device: bool = True, torch_alloc: bool = False, stream=None,
                  transfer: int = BARYCENTRIC, mls_alpha: float = 1.0, subsolver: int = LU,
-                 ilu_fill: Sequence[int] = ()):
+                 ilu_fill: Sequence[int] = (), mls_restrict: bool = False):
         o = setup_opts()
         _check(_lib.nnms_setup_opts_default(C.byref(o)))
         for l, p in enumerate(nparts):
@@ -236,6 +238,7 @@ class Hierarchy:
         o.overlap, o.its, o.precision = overlap, its, precision
         o.transfer, o.mls_alpha = transfer, mls_alpha
         o.subsolver = subsolver
+        o.mls_restrict = 1 if mls_restrict else 0
         for l, k in enumerate(ilu_fill):
             o.ilu_fill[l] = int(k)
         self.meshes = list(meshes)
@@ -281,6 +284,16 @@ class Hierarchy:
         _check(_lib.nnms_hierarchy_transfer(self.handle, level, _ptr(idx), _ptr(w)))
         return idx.reshape(-1, 4), w.reshape(-1, 4)
 
+    def restriction_csr(self, level: int):
+        """The restriction (P^T or the fine-to-coarse MLS operator) as CSR
+        (row_ptr, col, w) over the coarse vertices."""
+        li, lc = self.level_info(level), self.level_info(level + 1)
+        rp = np.empty(lc.nv + 1, dtype=np.int32)
+        col = np.empty(li.r_nnz, dtype=np.int32)
+        w = np.empty(li.r_nnz, dtype=np.float64)
+        _check(_lib.nnms_hierarchy_restriction_csr(self.handle, level, _ptr(rp), _ptr(col), _ptr(w)))
+        return rp, col, w
+
     def ilu_pattern(self, level: int):
         """(row_ptr, col) of the level's ILU patterns, subdomains concatenated."""
         li = self.level_info(level)
@@ -312,7 +325,7 @@ class Hierarchy:
         parts = []
         for l in range(self.L):
             li = self.level_info(l)
-            parts.append(f"{li.nv}-{li.nnz}-{li.nparts}" + (f"-mls{li.p_nnz}" if li.transfer == MLS else "")
+            parts.append(f"{li.nv}-{li.nnz}-{li.nparts}" + (f"-mls{li.p_nnz}-{li.r_nnz}" if li.transfer == MLS else "")
                          + (f"-ilu{li.ilu_nnz}" if li.subsolver == ILU else ""))
         return f"p{self.precision}_" + "_".join(parts)
 

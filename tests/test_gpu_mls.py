@@ -43,13 +43,14 @@ def _rel(a, b):
 
 
 class Built:
-    def __init__(self, pb, precision=None, alpha=mls.ALPHA, transfer=None):
+    def __init__(self, pb, precision=None, alpha=mls.ALPHA, transfer=None, mls_restrict=False):
         nnms = _gpu()
         prec = nnms.MIXED if (precision or pb.precision) == "mixed" else nnms.FP64
         self.pb = pb
         self.meshes = [nnms.Mesh.from_workload(m) for m in pb.meshes]
         self.h = nnms.Hierarchy(self.meshes, pb.nparts, overlap=pb.overlap, its=pb.its, precision=prec,
-                                transfer=nnms.MLS if transfer is None else transfer, mls_alpha=alpha)
+                                transfer=nnms.MLS if transfer is None else transfer, mls_alpha=alpha,
+                                mls_restrict=mls_restrict)
         self.s = nnms.System(self.h, pb.kappa, 1.0)
 
 
@@ -108,6 +109,34 @@ def test_solve_matches_oracle(case, graph, request):
     assert abs(info.iterations - ref.iterations) <= 1
     assert np.linalg.norm(o.b - o.A[0] @ x) <= 1e-8 * np.linalg.norm(o.b)
     assert _rel(x, xs) <= 1e-7
+
+
+def test_mls_restriction_matches_oracle():
+    """The paper's second MLS interpolation (fine to coarse nodes) as the
+    restriction: device operator, V-cycle and solve against the oracle."""
+    pb = _tiny3()
+    g = Built(pb, mls_restrict=True)
+    o = oprob.build(pb, mls_alpha=mls.ALPHA, mls_restrict=True)
+    rng = np.random.default_rng(14)
+    for l in range(2):
+        rp, col, w = g.h.restriction_csr(l)
+        R = sp.csr_matrix((w, col, rp), shape=(g.s.n[l + 1], g.s.n[l]))
+        Ro = o.vcycle.levels[l].R
+        # fine nodes are the sources: a smaller scale rho than for P, so the
+        # oracle's raw-basis fit is worse conditioned (~(|x| / rho)^2)
+        assert abs(R - Ro).max() <= 1e-11
+        x = rng.standard_normal(g.s.n[l])
+        x[pb.meshes[l].dirichlet != 0] = 0
+        y = g.s.apply_restrict(l, x)
+        assert _rel(y, R @ x) <= 1e-14 and _rel(y, Ro @ x) <= 1e-11
+    r = rng.standard_normal(g.s.n[0])
+    r[pb.meshes[0].dirichlet != 0] = 0
+    assert _rel(g.s.apply_vcycle(r), o.vcycle(r)) <= 1e-9
+    ref = oprob.solve(o)
+    x, info = g.s.solve(o.b)
+    assert info.status == 0 and info.relres <= 1e-8
+    assert abs(info.iterations - ref.iterations) <= 1
+    assert _rel(x, oprob.exact(o)) <= 1e-7
 
 
 def test_mixed_precision_mls():

@@ -100,6 +100,34 @@ def test_mls_transfer_matches_oracle(cfg, alpha):
             h.transfer(l)  # the four-entry form is barycentric only
 
 
+def test_mls_restriction_matches_oracle():
+    pb = W.Problem("tiny3", [W.kuhn_cube(9, 1), W.kuhn_cube(5, 2), W.kuhn_cube(3, 3)], [4, 2], W.KappaField())
+    ms = [nnms.Mesh.from_workload(m) for m in pb.meshes]
+    h = nnms.Hierarchy(ms, pb.nparts, device=False, transfer=nnms.MLS, mls_alpha=1.0, mls_restrict=True)
+    for l in range(2):
+        f, c = pb.meshes[l], pb.meshes[l + 1]
+        li = h.level_info(l)
+        assert li.mls_restrict == 1
+        rp, col, w = h.restriction_csr(l)
+        R = mls.restriction(f, c, 1.0).tocsr()
+        R.sort_indices()
+        assert np.array_equal(rp, R.indptr) and np.array_equal(col, R.indices)
+        assert np.abs(w - R.data).max() <= 1e-11  # raw-basis oracle, fine-mesh scale
+        # the prolongation is unchanged
+        rpp, colp, wp = h.transfer_csr(l)
+        P = mls.prolongation(f, c, 1.0).tocsr()
+        P.sort_indices()
+        assert np.array_equal(colp, P.indices) and np.abs(wp - P.data).max() <= 1e-12
+    # without the option the restriction is the transpose of P
+    h2 = nnms.Hierarchy(ms, pb.nparts, device=False, transfer=nnms.MLS, mls_alpha=1.0)
+    rp, col, w = h2.restriction_csr(0)
+    rpp, colp, wp = h2.transfer_csr(0)
+    import scipy.sparse as sp
+    PT = sp.csr_matrix((wp, colp, rpp), shape=(pb.meshes[0].nv, pb.meshes[1].nv)).T.tocsr()
+    RT = sp.csr_matrix((w, col, rp), shape=PT.shape)
+    assert abs(RT - PT).max() == 0
+
+
 def test_barycentric_transfer_csr_matches_four_entry_form():
     pb = W.cube16_two_level()
     ms, h = _host(pb)
