@@ -131,6 +131,27 @@ def cpu_baseline(pb, seconds_cap=60.0, mls_alpha=None):
     }, oh, res
 
 
+def hierarchy_options(args, nnms):
+    """Transfer and subdomain-solver keywords of nnms.Hierarchy from the
+    command line, and a short description for the workload name."""
+    kw = {"transfer": nnms.MLS if args.transfer == "mls" else nnms.BARYCENTRIC, "mls_alpha": args.mls_alpha,
+          "subsolver": nnms.ILU if args.subsolver == "ilu" else nnms.LU,
+          "ilu_fill": [int(k) for k in args.ilu_fill.split(",")]}
+    desc = ""
+    if args.transfer == "mls":
+        desc += f", MLS transfer (scale {args.mls_alpha} x mean coarse edge)"
+    if args.subsolver == "ilu":
+        desc += f", ILU({args.ilu_fill}) subdomain solves"
+    return kw, desc
+
+
+def smoother_bytes(h, level, s_bytes):
+    """Algorithmic bytes of one smoother application, dense LU or ILU."""
+    if h.level_info(level).subsolver == 1:
+        return ilu_bytes(h, level, s_bytes)
+    return ras_bytes(h, level, s_bytes)
+
+
 def run_batched(args):
     """Batched parametric instances of uneven mesh and subdomain sizes (fine
     n in {24,32,40,48,64}, three non-nested levels each), mixed precision,
@@ -141,11 +162,12 @@ def run_batched(args):
     from paper_2412_08981_amd import nnms
 
     probs = W.batched_instances(count=args.batch)
+    hkw, hdesc = hierarchy_options(args, nnms)
     t0 = time.perf_counter()
     hs, ss, bs = [], [], []
     for pb in probs:
         ms = [nnms.Mesh.from_workload(m) for m in pb.meshes]
-        h = nnms.Hierarchy(ms, pb.nparts, overlap=pb.overlap, its=pb.its, precision=nnms.MIXED)
+        h = nnms.Hierarchy(ms, pb.nparts, overlap=pb.overlap, its=pb.its, precision=nnms.MIXED, **hkw)
         s = nnms.System(h, pb.kappa, 1.0)
         hs.append(h)
         ss.append(s)
@@ -179,7 +201,7 @@ def run_batched(args):
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"{len(ss)} parametric instances, fine n in {{24,32,40,48,64}}, 3 non-nested levels, "
-                               "mixed precision, one batched launch sequence per Arnoldi step (HIP graph)",
+                               "mixed precision, one batched launch sequence per Arnoldi step (HIP graph)" + hdesc,
                    "sequential_solves_per_s": round(len(ss) / el_seq, 3),
                    "batch_gain": round(el_seq / el, 3),
                    "iterations": its, "max_relres": max(i.relres for i in infos),
@@ -204,6 +226,7 @@ def run_serving(args):
     centres = W.serving_centres()
     t, hs_choice, mus = W.serving_trace(nreq=args.requests, rate=1.0, sizes=sizes)
     res = {}
+    hkw, hdesc = hierarchy_options(args, nnms)
     for precision in ("mixed", "fp64"):
         prec = nnms.MIXED if precision == "mixed" else nnms.FP64
         t0 = time.perf_counter()
@@ -214,7 +237,7 @@ def run_serving(args):
             nps = [W.nparts_rule(m.nv) for m in meshes[:-1]]
             # PyTorch's caching allocator: releasing a finished request's
             # system or a batch plan does not synchronise the device
-            hier[n] = nnms.Hierarchy(ms, nps, precision=prec, torch_alloc=True)
+            hier[n] = nnms.Hierarchy(ms, nps, precision=prec, torch_alloc=True, **hkw)
             keep.append(ms)
         from paper_2412_08981_amd import autotune
         sb = 8 if prec == nnms.FP64 else 4
@@ -236,7 +259,7 @@ def run_serving(args):
                               "restrict_l0_ms": round(msq, 4),
                               "restrict_l0_GBs": round(restrict_bytes(h, 0, sb) / (msq * 1e-3) / 1e9, 1),
                               "smoother_l0_ms": round(mss, 4),
-                              "smoother_l0_GBs": round(ras_bytes(h, 0, sb) / (mss * 1e-3) / 1e9, 1)}
+                              "smoother_l0_GBs": round(smoother_bytes(h, 0, sb) / (mss * 1e-3) / 1e9, 1)}
             sample.destroy()
         log(f"[bench serving] {precision}: kernels {kern}")
         log(f"[bench serving] {precision}: hierarchies set up in {time.perf_counter() - t0:.1f} s; bytes per request "
@@ -282,7 +305,7 @@ def run_serving(args):
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"serving: {args.requests} Poisson requests over resident jittered 32^3/64^3/96^3 "
-                               f"hierarchies (3 levels), budget {args.budget_gib} GiB, mixed precision",
+                               f"hierarchies (3 levels), budget {args.budget_gib} GiB, mixed precision" + hdesc,
                    "p50_ms": m.get("p50_ms"), "p99_ms": m.get("p99_ms"), "open_loop_solves_per_s": m.get("solves_per_s"),
                    "fp64": res["fp64"],
                    "mixed": m,
