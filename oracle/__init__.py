@@ -14,8 +14,9 @@ Modules
   mls        moving-least-squares interpolation between meshes (Section 3.2)
   schwarz    coordinate-bisection partition, overlap, RAS (Section 2.2)
   ilu        ILU(k) subdomain solver (level of fill, i-k-j elimination)
+  coarsen    geometry-preserving coarsening of Algorithm 1 (MIS + contraction)
   multilevel V-cycle of Algorithm 2 (Section 3.3)
   krylov     right-preconditioned flexible GMRES (Section 2.1, Section 4)
   problem    glue that builds a whole hierarchy from a workload
 """
-from . import fem, transfer, mls, ilu, schwarz, multilevel, krylov, problem  # noqa: F401
+from . import fem, transfer, mls, ilu, coarsen, schwarz, multilevel, krylov, problem  # noqa: F401
