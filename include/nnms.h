@@ -161,6 +161,24 @@ typedef struct {
                            the fine to the coarse nodes, 0 = by P_l^T */
 } nnms_setup_opts;
 
+/* Geometry-preserving coarsening (Algorithm 1, Section 3.1): `rounds`
+ * times (the paper's M, 8 in 3D), take a maximal independent set of the
+ * interior (non-Dirichlet) vertices and remove every vertex of it by
+ * contracting it onto the neighbour whose new elements have the best
+ * smallest quality q = sqrt(2) 6V / l_rms^3 (at least 0.02, else the vertex
+ * stays).  The MIS is Luby's with priorities splitmix64(seed + 2^40 round +
+ * v).  Boundary vertices, their positions and the boundary surface are
+ * kept; surviving vertices keep their positions, in ascending old id, with
+ * their Dirichlet flags.  *out is a new mesh (nnms_mesh_destroy);
+ * *removed (may be NULL) receives the number of removed vertices.
+ * Errors: NNMS_ERR_INVALID_ARG (null mesh or output, rounds < 0). */
+nnms_status nnms_mesh_coarsen(const nnms_mesh* fine, int32_t rounds, uint64_t seed, nnms_mesh** out,
+                              int64_t* removed);
+/* Read-back of a mesh: xyz_host[nv*3], tets_host[nt*4], dirichlet_host[nv]
+ * (each may be NULL); *nv / *nt receive the counts. */
+nnms_status nnms_mesh_read(const nnms_mesh* m, int64_t* nv, int64_t* nt, double* xyz_host, int32_t* tets_host,
+                           uint8_t* dirichlet_host);
+
 nnms_status nnms_setup_opts_default(nnms_setup_opts* o);
 nnms_status nnms_hierarchy_setup(const nnms_mesh* const* levels, int32_t L, const nnms_setup_opts* opts,
                                  const nnms_allocator* alloc, void* stream, nnms_hierarchy** out);

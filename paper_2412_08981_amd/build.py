@@ -21,10 +21,12 @@ HIP_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", INC, "-I", CSRC,
 ]
-CXX_FLAGS = ["-O2", "-fPIC", "-std=c++17", "-I", INC, "-I", CSRC]
+# host geometry decisions (point location, MLS neighbourhoods, coarsening
+# qualities) are taken without contracted multiply-adds
+CXX_FLAGS = ["-O2", "-fPIC", "-std=c++17", "-ffp-contract=off", "-I", INC, "-I", CSRC]
 
 HIP_SOURCES = ["sparse.hip", "ras.hip", "lu.hip", "ilu.hip", "assemble.hip", "krylov.hip", "api.hip"]
-CXX_SOURCES = ["host_setup.cpp"]
+CXX_SOURCES = ["host_setup.cpp", "coarsen.cpp"]
 
 
 def _run(cmd):

@@ -112,6 +112,8 @@ _sig = {
     "nnms_device_bytes_in_use": (C.c_int64, []),
     "nnms_mesh_create": (C.c_int, [C.c_int64, vp, C.c_int64, vp, vp, C.POINTER(vp)]),
     "nnms_mesh_destroy": (None, [vp]),
+    "nnms_mesh_coarsen": (C.c_int, [vp, C.c_int32, C.c_uint64, C.POINTER(vp), C.POINTER(C.c_int64)]),
+    "nnms_mesh_read": (C.c_int, [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), vp, vp, vp]),
     "nnms_setup_opts_default": (C.c_int, [C.POINTER(setup_opts)]),
     "nnms_hierarchy_setup": (C.c_int, [vp, C.c_int32, C.POINTER(setup_opts), C.POINTER(allocator_t), vp, C.POINTER(vp)]),
     "nnms_hierarchy_setup_host": (C.c_int, [vp, C.c_int32, C.POINTER(setup_opts), C.POINTER(vp)]),
@@ -193,6 +195,29 @@ class Mesh:
     @classmethod
     def from_workload(cls, m) -> "Mesh":
         return cls(m.xyz, m.tets, m.dirichlet)
+
+    def coarsen(self, rounds: int = 8, seed: int = 0):
+        """Algorithm 1: (coarse Mesh, number of removed vertices)."""
+        h = C.c_void_p()
+        removed = C.c_int64()
+        _check(_lib.nnms_mesh_coarsen(self.handle, rounds, C.c_uint64(seed & (2 ** 64 - 1)), C.byref(h),
+                                      C.byref(removed)))
+        m = Mesh.__new__(Mesh)
+        m.handle = h
+        nv = C.c_int64()
+        _check(_lib.nnms_mesh_read(h, C.byref(nv), None, None, None, None))
+        m.nv = nv.value
+        return m, removed.value
+
+    def read(self):
+        """(xyz [nv,3], tets [nt,4], dirichlet [nv]) of the mesh."""
+        nv, nt = C.c_int64(), C.c_int64()
+        _check(_lib.nnms_mesh_read(self.handle, C.byref(nv), C.byref(nt), None, None, None))
+        xyz = np.empty((nv.value, 3))
+        tets = np.empty((nt.value, 4), dtype=np.int32)
+        d = np.empty(nv.value, dtype=np.uint8)
+        _check(_lib.nnms_mesh_read(self.handle, None, None, _ptr(xyz), _ptr(tets), _ptr(d)))
+        return xyz, tets, d
 
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:  # _lib is None at interpreter exit

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from oracle import ilu, mls, schwarz, transfer
+from oracle import coarsen, ilu, mls, schwarz, transfer
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -180,6 +180,29 @@ def test_ilu_rejects_bad_fill():
     ms = [nnms.Mesh.from_workload(m) for m in pb.meshes]
     with pytest.raises(nnms.NNMSError) as e:
         nnms.Hierarchy(ms, pb.nparts, device=False, subsolver=nnms.ILU, ilu_fill=[-1])
+    assert e.value.name == "INVALID_ARG"
+
+
+@pytest.mark.parametrize("n,rounds,seed", [(7, 1, 3), (9, 8, 7), (12, 4, 19), (16, 8, 5)])
+def test_coarsening_matches_oracle(n, rounds, seed):
+    """Algorithm 1 in the library equals the oracle's, bit for bit (same
+    MIS, same contraction choices, same output numbering)."""
+    m = W.kuhn_cube(n, seed)
+    r = coarsen.coarsen(m.xyz, m.tets, m.dirichlet, rounds, seed)
+    c, removed = nnms.Mesh.from_workload(m).coarsen(rounds, seed)
+    xyz, tets, d = c.read()
+    assert removed == r.removed
+    assert np.array_equal(xyz, r.xyz) and np.array_equal(tets, r.tets) and np.array_equal(d, r.dirichlet)
+    # a coarsened mesh is a valid coarse level: point location of every
+    # fine vertex succeeds and the hierarchy sets up
+    h = nnms.Hierarchy([nnms.Mesh.from_workload(m), c], [2], device=False)
+    assert h.level_info(1).nv == len(xyz)
+
+
+def test_coarsening_rejects_bad_arguments():
+    m = nnms.Mesh.from_workload(W.kuhn_cube(3, 1))
+    with pytest.raises(nnms.NNMSError) as e:
+        m.coarsen(-1, 0)
     assert e.value.name == "INVALID_ARG"
 
 
