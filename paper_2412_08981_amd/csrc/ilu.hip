@@ -114,10 +114,9 @@ template <typename T, int G, bool FWD>
 struct IluRow {
   int i = -1, c0 = -1, c1 = -1;
   T v0 = 0, v1 = 0, diag = 1;
-  __device__ __forceinline__ void load(const IluDesc& D, int q, int lane) {
-    // forward {row, first, diagonal, end}: the lower part is [first, diagonal);
-    // backward {row, diagonal + 1, end, diagonal}: the upper part [y, z)
-    const int4 m = meta_at(FWD ? D.fmeta : D.bmeta, q);
+  // m: forward {row, first, diagonal, end}, the lower part is [y, z);
+  // backward {row, diagonal + 1, end, diagonal}, the upper part [y, z)
+  __device__ __forceinline__ void load(const IluDesc& D, const int4 m, int lane) {
     i = m.x;
     const int first = m.y, end = m.z;
     const int e0 = first + lane, e1 = e0 + G;
@@ -139,28 +138,29 @@ struct IluRow {
 };
 
 // One sweep over the levels of one triangular factor.  The group's first
-// row of the next level is loaded before the barrier that ends the current
-// one, so its global loads overlap the barrier and the slowest group.
+// row of a level is prefetched in two stages: its schedule entry two levels
+// ahead and its factor entries one level ahead, both issued before the
+// barrier that ends the current level, so no load of the critical path
+// waits for another one between two barriers.
 template <typename T, int G, bool FWD>
 __device__ __forceinline__ void ilu_sweep(const IluDesc& D, T* y, int grp, int lane, int ngrp) {
   const int nl = FWD ? D.nfl : D.nbl;
   const GLOBAL int32_t* lev = gptr(FWD ? D.flev : D.blev);
+  const int32_t* meta = FWD ? D.fmeta : D.bmeta;
   IluRow<T, G, FWD> cur;
-  int r0 = lev[0], r1 = nl > 0 ? lev[1] : 0;
-  if (nl > 0 && r0 + grp < r1) cur.load(D, r0 + grp, lane);
+  int4 mnext = make_int4(-1, 0, 0, 0);
+  if (nl > 0 && lev[0] + grp < lev[1]) cur.load(D, meta_at(meta, lev[0] + grp), lane);
+  if (nl > 1 && lev[1] + grp < lev[2]) mnext = meta_at(meta, lev[1] + grp);
   for (int lv = 0; lv < nl; ++lv) {
-    const bool have = r0 + grp < r1;  // uniform within a group
-    if (have) cur.apply(y, lane);
+    const int r0 = lev[lv], r1 = lev[lv + 1];
+    if (r0 + grp < r1) cur.apply(y, lane);  // uniform within a group
     for (int q = r0 + grp + ngrp; q < r1; q += ngrp) {
       IluRow<T, G, FWD> more;
-      more.load(D, q, lane);
+      more.load(D, meta_at(meta, q), lane);
       more.apply(y, lane);
     }
-    if (lv + 1 < nl) {
-      r0 = r1;
-      r1 = lev[lv + 2];
-      if (r0 + grp < r1) cur.load(D, r0 + grp, lane);
-    }
+    if (lv + 1 < nl && lev[lv + 1] + grp < lev[lv + 2]) cur.load(D, mnext, lane);
+    if (lv + 2 < nl && lev[lv + 2] + grp < lev[lv + 3]) mnext = meta_at(meta, lev[lv + 2] + grp);
     lds_barrier();
   }
 }
