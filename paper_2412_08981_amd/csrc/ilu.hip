@@ -35,14 +35,19 @@ __global__ __launch_bounds__(256) void k_ilu_extract(const int32_t* __restrict__
 // values and columns are staged in the group's LDS slice (at most 4G
 // entries); for every lower entry k in ascending order the multiplier
 // l = a_ik / u_kk is formed and the lanes take row k's upper entries j in
-// turn, find j in row i by binary search and update a_ij -= l u_kj (distinct
-// j, distinct targets).  Every a_ij receives its updates in ascending k,
-// the same operations in the same order as the textbook i-k-j loop.
+// turn (at most 2G of them), find j in row i by binary search and update
+// a_ij -= l u_kj (distinct j, distinct targets).  Every a_ij receives its
+// updates in ascending k, the same operations in the same order as the
+// textbook i-k-j loop.  The rows k are final, so their loads do not wait
+// for the eliminations: the diagonal and end of every row k are fetched
+// for all steps at once, and the upper entries of four steps at a time.
 template <typename T, int G>
 __global__ __launch_bounds__(256) void k_ilu_factor(const IluDesc* __restrict__ d, int* __restrict__ err) {
   constexpr int NE = 4 * G;  // entries per row that a group can stage
+  constexpr int CH = 4;      // elimination steps whose row data is loaded together
   __shared__ T svals[256 / G][NE];
   __shared__ int32_t scols[256 / G][NE];
+  __shared__ int32_t sdk[256 / G][NE], sbk[256 / G][NE];
   const IluDesc D = d[blockIdx.x];
   const GLOBAL int32_t* rp = gptr(D.rp);
   const GLOBAL int32_t* col = gptr(D.col);
@@ -51,35 +56,62 @@ __global__ __launch_bounds__(256) void k_ilu_factor(const IluDesc* __restrict__ 
   const int grp = int(threadIdx.x) / G, lane = int(threadIdx.x) % G, ngrp = int(blockDim.x) / G;
   T* rv = svals[grp];
   int32_t* rc = scols[grp];
+  int32_t* kd = sdk[grp];
+  int32_t* kb = sbk[grp];
   for (int lv = 0; lv < D.nfl; ++lv) {
     const int r0 = gptr(D.flev)[lv], r1 = gptr(D.flev)[lv + 1];
     for (int q = r0 + grp; q < r1; q += ngrp) {  // uniform within a group
       const int4 m = meta_at(D.fmeta, q);
       const int a = m.y, len = m.w - m.y, di = m.z - m.y;
-      for (int m = lane; m < len; m += G) rv[m] = val[a + m], rc[m] = col[a + m];
+      for (int t = lane; t < len; t += G) rv[t] = val[a + t], rc[t] = col[a + t];
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       __builtin_amdgcn_wave_barrier();
-      for (int e = 0; e < di; ++e) {
+      for (int e = lane; e < di; e += G) {
         const int k = rc[e];
-        const int dk = dpos[k], bk = rp[k + 1];
-        const T l = rv[e] / val[dk];
-        for (int f = dk + 1 + lane; f < bk; f += G) {
-          const int j = col[f];
-          int lo = e + 1, hi = len;
-          while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (rc[mid] < j)
-              lo = mid + 1;
-            else
-              hi = mid;
-          }
-          if (lo < len && rc[lo] == j) rv[lo] -= l * val[f];
-        }
-        if (lane == 0) rv[e] = l;
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        __builtin_amdgcn_wave_barrier();
+        kd[e] = dpos[k], kb[e] = rp[k + 1];
       }
-      for (int m = lane; m < len; m += G) val[a + m] = rv[m];
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      for (int e0 = 0; e0 < di; e0 += CH) {
+        T ukk[CH], fv[CH][2];
+        int fc[CH][2];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+          const int e = e0 + c;
+          ukk[c] = T(1), fc[c][0] = fc[c][1] = -1, fv[c][0] = fv[c][1] = T(0);
+          if (e < di) {
+            const int dk = kd[e], bk = kb[e];
+            const int f0 = dk + 1 + lane, f1 = f0 + G;
+            ukk[c] = val[dk];
+            if (f0 < bk) fc[c][0] = col[f0], fv[c][0] = val[f0];
+            if (f1 < bk) fc[c][1] = col[f1], fv[c][1] = val[f1];
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+          const int e = e0 + c;
+          if (e >= di) break;  // uniform within a group
+          const T l = rv[e] / ukk[c];
+#pragma unroll
+          for (int x = 0; x < 2; ++x) {
+            const int j = fc[c][x];
+            if (j < 0) continue;
+            int lo = e + 1, hi = len;
+            while (lo < hi) {
+              const int mid = (lo + hi) >> 1;
+              if (rc[mid] < j)
+                lo = mid + 1;
+              else
+                hi = mid;
+            }
+            if (lo < len && rc[lo] == j) rv[lo] -= l * fv[c][x];
+          }
+          if (lane == 0) rv[e] = l;
+          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+        }
+      }
+      for (int t = lane; t < len; t += G) val[a + t] = rv[t];
       if (lane == 0 && !(rv[di] > T(0))) *err = 1;
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       __builtin_amdgcn_wave_barrier();
