@@ -178,6 +178,19 @@ def test_autotune_on_ilu_levels_keeps_results(tiny3i):
     assert i1.iterations == i0.iterations and _rel(x1, x0) <= 1e-10
 
 
+def test_one_subdomain_full_fill_is_exact():
+    """One subdomain, no overlap, fill level above the matrix size: nothing
+    is dropped, so the smoother is the exact inverse."""
+    nnms = _gpu()
+    pb = W.Problem("exact", [W.kuhn_cube(4, 41), W.kuhn_cube(2, 42)], [1], W.kappa_draw(1, 2), overlap=0)
+    g = Built(pb, [64])
+    o = oprob.build(pb)
+    r = np.random.default_rng(5).standard_normal(g.s.n[0])
+    r[pb.meshes[0].dirichlet != 0] = 0
+    z = g.s.apply_smoother(0, r)
+    assert _rel(o.A[0] @ z, r) <= 1e-12
+
+
 def test_dense_readback_is_refused_on_ilu_levels(cube16i):
     nnms = _gpu()
     g, o = cube16i

@@ -175,6 +175,16 @@ def test_ilu_patterns_match_oracle(fill):
     assert h.level_info(2).subsolver == nnms.LU  # the coarsest level is solved directly
 
 
+def test_ilu_rows_too_long_are_rejected():
+    # a high fill level on a 9^3 subdomain fills rows far beyond what a
+    # group of lanes can stage: a clear error at setup, not at launch
+    pb = W.Problem("t", [W.kuhn_cube(9, 1), W.kuhn_cube(4, 2)], [1], W.KappaField())
+    ms = [nnms.Mesh.from_workload(m) for m in pb.meshes]
+    with pytest.raises(nnms.NNMSError) as e:
+        nnms.Hierarchy(ms, pb.nparts, device=False, subsolver=nnms.ILU, ilu_fill=[40])
+    assert e.value.name == "INVALID_ARG" and "too long" in str(e.value)
+
+
 def test_ilu_rejects_bad_fill():
     pb = W.cube16_two_level()
     ms = [nnms.Mesh.from_workload(m) for m in pb.meshes]
