@@ -630,18 +630,18 @@ double mean_edge_length(const HostLevel& lv) {
 // The MLS operator from the nodal values of `src` to the nodes of `dst`
 // (rows: dst vertices, Dirichlet rows empty, Dirichlet src columns dropped),
 // scale starting at alpha times the mean edge length of src.
-static void mls_operator(const HostLevel& fine, const HostLevel& coarse, double alpha, std::vector<int32_t>& p_rp,
+static void mls_operator(const HostLevel& dst, const HostLevel& src, double alpha, std::vector<int32_t>& p_rp,
                          std::vector<int32_t>& p_col, std::vector<double>& p_val) {
   if (!(alpha > 0)) throw Error(NNMS_ERR_INVALID_ARG, "MLS scale factor must be positive");
-  const double rho0 = alpha * mean_edge_length(coarse);
+  const double rho0 = alpha * mean_edge_length(src);
   if (!(rho0 > 0)) throw Error(NNMS_ERR_INVALID_ARG, "degenerate source mesh");
-  const int64_t nc = coarse.nv, nf = fine.nv;
-  // uniform bucket grid over the coarse vertices, cell edge rho0
+  const int64_t nc = src.nv, nf = dst.nv;  // source / target vertices
+  // uniform bucket grid over the source vertices, cell edge rho0
   double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
   for (int64_t v = 0; v < nc; ++v)
     for (int a = 0; a < 3; ++a) {
-      lo[a] = std::min(lo[a], coarse.xyz[v * 3 + a]);
-      hi[a] = std::max(hi[a], coarse.xyz[v * 3 + a]);
+      lo[a] = std::min(lo[a], src.xyz[v * 3 + a]);
+      hi[a] = std::max(hi[a], src.xyz[v * 3 + a]);
     }
   int nb[3];
   for (int a = 0; a < 3; ++a) nb[a] = std::max(1, std::min(1024, int(std::floor((hi[a] - lo[a]) / rho0)) + 1));
@@ -652,14 +652,14 @@ static void mls_operator(const HostLevel& fine, const HostLevel& coarse, double 
   const int64_t ncell = int64_t(nb[0]) * nb[1] * nb[2];
   std::vector<int32_t> cptr(ncell + 1, 0), citem(nc);
   for (int64_t v = 0; v < nc; ++v) {
-    const double* x = &coarse.xyz[v * 3];
+    const double* x = &src.xyz[v * 3];
     cptr[cell(x[0], 0) + int64_t(nb[0]) * (cell(x[1], 1) + int64_t(nb[1]) * cell(x[2], 2)) + 1]++;
   }
   for (int64_t c = 0; c < ncell; ++c) cptr[c + 1] += cptr[c];
   {
     std::vector<int32_t> fill(cptr.begin(), cptr.end() - 1);
     for (int64_t v = 0; v < nc; ++v) {
-      const double* x = &coarse.xyz[v * 3];
+      const double* x = &src.xyz[v * 3];
       citem[fill[cell(x[0], 0) + int64_t(nb[0]) * (cell(x[1], 1) + int64_t(nb[1]) * cell(x[2], 2))]++] = int32_t(v);
     }
   }
@@ -670,8 +670,8 @@ static void mls_operator(const HostLevel& fine, const HostLevel& coarse, double 
   std::vector<double> q, w;
   for (int64_t v = 0; v < nf; ++v) {
     p_rp[v + 1] = p_rp[v];
-    if (fine.dir[v]) continue;
-    const double* xs = &fine.xyz[v * 3];
+    if (dst.dir[v]) continue;
+    const double* xs = &dst.xyz[v * 3];
     double rho = rho0;
     bool ok = false;
     for (int grow = 0; grow < 200 && !ok; ++grow, rho *= 1.25) {
@@ -683,7 +683,7 @@ static void mls_operator(const HostLevel& fine, const HostLevel& coarse, double 
           for (int i = bl[0]; i <= bh[0]; ++i) {
             const int64_t c = i + int64_t(nb[0]) * (j + int64_t(nb[1]) * k);
             for (int32_t e = cptr[c]; e < cptr[c + 1]; ++e) {
-              const double* y = &coarse.xyz[size_t(citem[e]) * 3];
+              const double* y = &src.xyz[size_t(citem[e]) * 3];
               const double d2 = (y[0] - xs[0]) * (y[0] - xs[0]) + (y[1] - xs[1]) * (y[1] - xs[1]) +
                                 (y[2] - xs[2]) * (y[2] - xs[2]);
               if (std::sqrt(d2) < rho) ids.push_back(citem[e]);
@@ -695,7 +695,7 @@ static void mls_operator(const HostLevel& fine, const HostLevel& coarse, double 
       q.resize(m * 4), w.resize(m);
       double G[4][4] = {}, M[4][4] = {};
       for (size_t n = 0; n < m; ++n) {
-        const double* y = &coarse.xyz[size_t(ids[n]) * 3];
+        const double* y = &src.xyz[size_t(ids[n]) * 3];
         double* qn = &q[n * 4];
         qn[0] = 1.0;
         for (int a = 0; a < 3; ++a) qn[a + 1] = (y[a] - xs[a]) / rho;
@@ -712,7 +712,7 @@ static void mls_operator(const HostLevel& fine, const HostLevel& coarse, double 
       double c[4];
       if (!spd4_solve_e0(M, c)) continue;
       for (size_t n = 0; n < m; ++n) {
-        if (coarse.dir[ids[n]]) continue;
+        if (src.dir[ids[n]]) continue;
         const double* qn = &q[n * 4];
         p_col.push_back(ids[n]);
         p_val.push_back(w[n] * (c[0] * qn[0] + c[1] * qn[1] + c[2] * qn[2] + c[3] * qn[3]));
