@@ -121,13 +121,40 @@ __global__ __launch_bounds__(256) void k_ilu_factor(const IluDesc* __restrict__ 
 }
 
 // G lanes per row: lane l of a row's group takes entries l, l + G, ... and
-// the group adds its partial sums by a fixed xor tree, so a level's rows
-// issue all their loads at once instead of one dependent chain per row.
+// the group adds its partial sums in a fixed order, so a level's rows issue
+// all their loads at once instead of one dependent chain per row.  Groups of
+// up to 16 lanes are a quad, half row or row of the wave's DPP lanes, and
+// add with DPP moves inside the ALU (swap within pairs, then pairs of a
+// quad, then mirrored quads of a half row, then mirrored half rows) instead
+// of LDS-routed shuffles; 32-lane groups use the shuffles.
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+constexpr int DPP_QUAD_1032 = 0xB1;     // quad_perm(1, 0, 3, 2)
+constexpr int DPP_QUAD_2301 = 0x4E;     // quad_perm(2, 3, 0, 1)
+constexpr int DPP_HALF_MIRROR = 0x141;  // lane i <-> 7 - i within 8 lanes
+constexpr int DPP_ROW_MIRROR = 0x140;   // lane i <-> 15 - i within 16 lanes
+
 template <typename T, int G>
 __device__ __forceinline__ T group_sum(T v) {
+  if constexpr (G <= 16) {
+    v += dpp_move<DPP_QUAD_1032>(v);
+    v += dpp_move<DPP_QUAD_2301>(v);
+    if constexpr (G >= 8) v += dpp_move<DPP_HALF_MIRROR>(v);
+    if constexpr (G >= 16) v += dpp_move<DPP_ROW_MIRROR>(v);
+    return v;
+  } else {
 #pragma unroll
-  for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
-  return v;
+    for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
+    return v;
+  }
 }
 
 // Work-group barrier that orders LDS only: the apply's global memory is
