@@ -334,8 +334,9 @@ def main():
     ap.add_argument("--transfer", default="barycentric", choices=["barycentric", "mls"],
                     help="transfer between levels: barycentric P1 interpolation or moving least squares")
     ap.add_argument("--mls-alpha", type=float, default=1.0, help="MLS initial scale / mean coarse edge length")
-    ap.add_argument("--coarsen", type=int, default=0, metavar="M",
-                    help="derive the coarse levels from the fine mesh by Algorithm 1 with M rounds per level")
+    ap.add_argument("--coarsen", default="", metavar="M[,M2]",
+                    help="derive the coarse levels from the fine mesh by Algorithm 1 with M rounds per level "
+                         "(a list gives the rounds of each coarse level)")
     ap.add_argument("--subsolver", default="lu", choices=["lu", "ilu"],
                     help="subdomain solver of the smoother: dense LU or ILU(k)")
     ap.add_argument("--ilu-fill", default="2,0", help="ILU level of fill per smoothed level (finest first)")
@@ -362,11 +363,13 @@ def main():
     t0 = time.perf_counter()
     meshes = [nnms.Mesh.from_workload(m) for m in pb.meshes]
     coarsened = None
-    if args.coarsen > 0:
+    rounds = [int(r) for r in args.coarsen.split(",")] if args.coarsen else []
+    if rounds:
+        rounds += [rounds[-1]] * (len(pb.meshes) - 1 - len(rounds))
         # coarse levels from the fine mesh (Algorithm 1), not meshed on their own
         meshes = meshes[:1]
         for l in range(1, len(pb.meshes)):
-            c, _ = meshes[-1].coarsen(args.coarsen, l)
+            c, _ = meshes[-1].coarsen(rounds[l - 1], l)
             meshes.append(c)
         coarsened = []
         for l, m in enumerate(meshes):
@@ -375,7 +378,7 @@ def main():
         pb = W.Problem(pb.name + "-coarsened", coarsened, [W.nparts_rule(m.nv) if l else pb.nparts[0]
                                                           for l, m in enumerate(coarsened[:-1])],
                        pb.kappa, precision=pb.precision)
-        log(f"[bench] coarsened levels (Algorithm 1, {args.coarsen} rounds each): vertices "
+        log(f"[bench] coarsened levels (Algorithm 1, rounds {rounds}): vertices "
             f"{[m.nv for m in coarsened]}, interior {[int((m.dirichlet == 0).sum()) for m in coarsened]}")
     mls_mode = args.transfer == "mls"
     ilu_mode = args.subsolver == "ilu"
@@ -492,7 +495,7 @@ def main():
                                f"64+8 subdomains overlap 1, FGMRES(30) to 1e-8, {args.precision}"
                                + (f", MLS transfer (scale {args.mls_alpha} x mean coarse edge)" if mls_mode else "")
                                + (f", ILU({args.ilu_fill}) subdomain solves" if ilu_mode else "")
-                               + (f", coarse levels by Algorithm 1 ({args.coarsen} rounds each; interior vertices "
+                               + (f", coarse levels by Algorithm 1 (rounds {rounds}; interior vertices "
                                   f"{[int((m.dirichlet == 0).sum()) for m in coarsened]})" if coarsened else ""),
                    "iterations": info.iterations, "relres": info.relres,
                    "numeric_setup_s": round(t_assemble, 4), "structure_setup_s": round(t1 - t0, 3),
@@ -512,7 +515,7 @@ def main():
             from oracle import coarsen as ocoarsen
             om = [W.cube48_three_level(args.precision).meshes[0]]
             for l in range(1, len(coarsened)):
-                r = ocoarsen.coarsen(om[-1].xyz, om[-1].tets, om[-1].dirichlet, args.coarsen, l)
+                r = ocoarsen.coarsen(om[-1].xyz, om[-1].tets, om[-1].dirichlet, rounds[l - 1], l)
                 om.append(W.Mesh(r.xyz, r.tets.astype(np.int32), r.dirichlet, 0))
             pb_o = W.Problem(pb.name, om, pb.nparts, pb.kappa, precision=pb.precision)
         cb, oh, ores = cpu_baseline(pb_o, mls_alpha=args.mls_alpha if mls_mode else None)
