@@ -41,13 +41,18 @@ __global__ __launch_bounds__(256) void k_ilu_extract(const int32_t* __restrict__
 // textbook i-k-j loop.  The rows k are final, so their loads do not wait
 // for the eliminations: the diagonal and end of every row k are fetched
 // for all steps at once, and the upper entries of four steps at a time.
+// A column is found in row i through the group's window map (position of
+// every column of row i, indexed by column - first column) when the row
+// spans fewer than WIN columns, else by binary search.
 template <typename T, int G>
 __global__ __launch_bounds__(256) void k_ilu_factor(const IluDesc* __restrict__ d, int* __restrict__ err) {
   constexpr int NE = 4 * G;  // entries per row that a group can stage
   constexpr int CH = 4;      // elimination steps whose row data is loaded together
+  constexpr int WIN = 64 * G;  // columns a row may span to use the window map (32 KiB of maps)
   __shared__ T svals[256 / G][NE];
   __shared__ int32_t scols[256 / G][NE];
   __shared__ int32_t sdk[256 / G][NE], sbk[256 / G][NE];
+  __shared__ int16_t smap[256 / G][WIN];
   const IluDesc D = d[blockIdx.x];
   const GLOBAL int32_t* rp = gptr(D.rp);
   const GLOBAL int32_t* col = gptr(D.col);
@@ -58,6 +63,8 @@ __global__ __launch_bounds__(256) void k_ilu_factor(const IluDesc* __restrict__ 
   int32_t* rc = scols[grp];
   int32_t* kd = sdk[grp];
   int32_t* kb = sbk[grp];
+  int16_t* wmap = smap[grp];
+  for (int t = lane; t < WIN; t += G) wmap[t] = -1;
   for (int lv = 0; lv < D.nfl; ++lv) {
     const int r0 = gptr(D.flev)[lv], r1 = gptr(D.flev)[lv + 1];
     for (int q = r0 + grp; q < r1; q += ngrp) {  // uniform within a group
@@ -66,6 +73,10 @@ __global__ __launch_bounds__(256) void k_ilu_factor(const IluDesc* __restrict__ 
       for (int t = lane; t < len; t += G) rv[t] = val[a + t], rc[t] = col[a + t];
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       __builtin_amdgcn_wave_barrier();
+      const int c0 = rc[0];
+      const bool windowed = rc[len - 1] - c0 < WIN;  // uniform within a group
+      if (windowed)
+        for (int t = lane; t < len; t += G) wmap[rc[t] - c0] = int16_t(t);
       for (int e = lane; e < di; e += G) {
         const int k = rc[e];
         kd[e] = dpos[k], kb[e] = rp[k + 1];
@@ -96,15 +107,22 @@ __global__ __launch_bounds__(256) void k_ilu_factor(const IluDesc* __restrict__ 
           for (int x = 0; x < 2; ++x) {
             const int j = fc[c][x];
             if (j < 0) continue;
-            int lo = e + 1, hi = len;
-            while (lo < hi) {
-              const int mid = (lo + hi) >> 1;
-              if (rc[mid] < j)
-                lo = mid + 1;
-              else
-                hi = mid;
+            if (windowed) {
+              // j > k = rc[e] >= c0; a hit lies after e
+              const int w = j - c0;
+              const int pos = w < WIN ? int(wmap[w]) : -1;
+              if (pos > e) rv[pos] -= l * fv[c][x];
+            } else {
+              int lo = e + 1, hi = len;
+              while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (rc[mid] < j)
+                  lo = mid + 1;
+                else
+                  hi = mid;
+              }
+              if (lo < len && rc[lo] == j) rv[lo] -= l * fv[c][x];
             }
-            if (lo < len && rc[lo] == j) rv[lo] -= l * fv[c][x];
           }
           if (lane == 0) rv[e] = l;
           __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -112,6 +130,8 @@ __global__ __launch_bounds__(256) void k_ilu_factor(const IluDesc* __restrict__ 
         }
       }
       for (int t = lane; t < len; t += G) val[a + t] = rv[t];
+      if (windowed)
+        for (int t = lane; t < len; t += G) wmap[rc[t] - c0] = -1;
       if (lane == 0 && !(rv[di] > T(0))) *err = 1;
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       __builtin_amdgcn_wave_barrier();
