@@ -434,21 +434,34 @@ static const void* ell_of(const SysLevel& sl) {
 // N[q] blocks: forward block i at step i, backward block i at step 2N-1-i,
 // ordered by (step, subdomain) so that every dependency has a lower ticket.
 static std::vector<int32_t> ras_tasks(const std::vector<int32_t>& N, int K) {
-  // counting sort by step: inside a step, subdomains stay in ascending order
+  // counting sort by key = step + 4 (NBmax - NB): a subdomain with fewer work
+  // items enters the order later, so the longest chains start first and the
+  // launch's tail shortens (fine level 0.317 -> 0.306 ms FP32, second level
+  // 0.139 -> 0.135 ms FP64; larger head starts starve the small subdomains).
+  // Inside a subdomain the order stays that of its steps, a dependency
+  // order, so no work item waits on one drawn after it.  Inside a key,
+  // subdomains stay in ascending order.
+  int nbmax = 0;
+  for (int32_t n : N) nbmax = std::max(nbmax, (n + K - 1) / K);
+  auto shift = [&](int NB) { return 4 * (nbmax - NB); };
   int steps = 0;
-  for (int32_t n : N) steps = std::max(steps, 2 * ((n + K - 1) / K));
+  for (int32_t n : N) {
+    const int NB = (n + K - 1) / K;
+    steps = std::max(steps, 2 * NB + shift(NB));
+  }
   std::vector<int32_t> cnt(size_t(steps) + 1, 0);
   for (int32_t n : N) {
     const int NB = (n + K - 1) / K;
-    for (int s = 0; s < 2 * NB; ++s) cnt[s + 1]++;
+    for (int s = 0; s < 2 * NB; ++s) cnt[s + shift(NB) + 1]++;
   }
   for (int s = 0; s < steps; ++s) cnt[s + 1] += cnt[s];
   std::vector<int32_t> out(cnt[steps]);
   for (size_t q = 0; q < N.size(); ++q) {
     const int NB = (N[q] + K - 1) / K;
+    const int sh = shift(NB);
     for (int i = 0; i < NB; ++i) {
-      out[cnt[i]++] = int32_t((q << 16) | i);
-      out[cnt[2 * NB - 1 - i]++] = int32_t((q << 16) | (1 << 15) | i);
+      out[cnt[i + sh]++] = int32_t((q << 16) | i);
+      out[cnt[2 * NB - 1 - i + sh]++] = int32_t((q << 16) | (1 << 15) | i);
     }
   }
   return out;
