@@ -12,7 +12,8 @@ mixed precision against x* (1e-7; its FP32 smoother on sampled subdomains
 to 1e-2, FP32 rounding times block condition numbers up to ~1e5).
 96^3 / 48^3 / 20^3 (the largest served hierarchy, 512 fine subdomains,
 mixed): the true residual of a solve computed from the oracle's assembly,
-and sampled subdomains of the fine smoother.
+and sampled subdomains of the fine smoother.  The 32 batched instances:
+true residuals and bitwise equality with solves alone.
 """
 import os
 import sys
@@ -134,3 +135,31 @@ def test_served_96_mixed_full_size():
     assert info.status == 0 and info.relres <= 1e-8
     assert np.linalg.norm(b - A @ x) <= 1e-8 * np.linalg.norm(b)
     _check_smoother_samples(s, meshes[0], A, nps[0], [0, 511], 1e-2)
+
+
+def test_batched_32_instances_full_size():
+    """The batched workload as benchmarked (32 ragged instances, fine n in
+    {24, 32, 40, 48, 64}, mixed precision, one launch sequence per Arnoldi
+    step): every slot reaches the true relative residual 1e-8 computed from
+    the oracle's assembly of its own fine level, and equals its solve alone
+    bit for bit."""
+    nnms = _gpu()
+    _say("[gpu] 32 batched instances (mixed)")
+    probs = W.batched_instances(count=32)
+    keep, systems, bs, As = [], [], [], []
+    for pb in probs:
+        ms = [nnms.Mesh.from_workload(m) for m in pb.meshes]
+        h = nnms.Hierarchy(ms, pb.nparts, overlap=pb.overlap, its=pb.its, precision=nnms.MIXED)
+        s = nnms.System(h, pb.kappa, 1.0)
+        keep.append((ms, h))
+        systems.append(s)
+        A, b = fem.assemble(pb.meshes[0], pb.kappa)
+        As.append(A)
+        bs.append(b)
+    xs, infos = nnms.solve_batch(systems, bs)
+    for i, (A, b, x, info) in enumerate(zip(As, bs, xs, infos)):
+        assert info.status == 0 and info.relres <= 1e-8, i
+        assert np.linalg.norm(b - A @ x) <= 1e-8 * np.linalg.norm(b), i
+    for i in (0, 7, 31):
+        x, info = systems[i].solve(bs[i])
+        assert np.array_equal(x, xs[i]) and info.iterations == infos[i].iterations, i
