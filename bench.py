@@ -94,9 +94,11 @@ def prolong_bytes(h, level, s_bytes):
     """z_f += P z_c: four (index, weight) pairs per fine row (barycentric) or
     one per entry of P (MLS), the coarse vector once, the fine vector read
     and written."""
+    from paper_2412_08981_amd import nnms
+
     li, lc = h.level_info(level), h.level_info(level + 1)
     nf, nc = li.nv, lc.nv
-    if li.transfer == 1:
+    if li.transfer == nnms.MLS:
         return float(li.p_nnz * (4 + s_bytes) + nc * s_bytes + 2 * nf * s_bytes)
     return float(nf * (16 + 4 * s_bytes) + nc * s_bytes + 2 * nf * s_bytes)
 
@@ -147,7 +149,9 @@ def hierarchy_options(args, nnms):
 
 def smoother_bytes(h, level, s_bytes):
     """Algorithmic bytes of one smoother application, dense LU or ILU."""
-    if h.level_info(level).subsolver == 1:
+    from paper_2412_08981_amd import nnms
+
+    if h.level_info(level).subsolver == nnms.ILU:
         return ilu_bytes(h, level, s_bytes)
     return ras_bytes(h, level, s_bytes)
 
