@@ -139,7 +139,9 @@ void nnms_mesh_destroy(nnms_mesh* m);
  *             (defaults 2 on level 0, 0 elsewhere), factorised on the
  *             device at every assembly and applied by level-scheduled
  *             triangular solves; a subdomain may hold at most 8192 rows
- *             (FP64) or 16384 (mixed) with ILU.
+ *             (FP64) or 16384 (mixed) with ILU, and a row of its ILU
+ *             pattern at most 128 entries (64 below and 64 above the
+ *             diagonal): NNMS_ERR_INVALID_ARG otherwise (lower the fill).
  * alloc       device allocator or NULL (hipMalloc).
  * stream      stream for the uploads.
  * Errors: NNMS_ERR_INVALID_ARG, NNMS_ERR_POINT_LOCATION (a fine vertex
