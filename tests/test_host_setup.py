@@ -209,6 +209,25 @@ def test_coarsening_matches_oracle(n, rounds, seed):
     assert h.level_info(1).nv == len(xyz)
 
 
+@pytest.mark.parametrize("name", ["regular", "lopsided", "flat02", "flat007", "flat005"])
+def test_coarsening_hand_checked_stars(name):
+    """The library's contraction choice on the bipyramid stars whose
+    qualities are closed forms (tests/golden/tet_quality.txt): the same
+    elements as fixed by hand, and the vertex kept below the quality floor."""
+    from test_oracle_coarsen import expected_star_tets, quality_golden
+
+    rows, _ = quality_golden()
+    hd, he, _, _, _, expected = rows[name]
+    m = W.bipyramid_star(hd, he)
+    c, removed = nnms.Mesh.from_workload(m).coarsen(1, 9)
+    xyz, tets, d = c.read()
+    if expected == "keep":
+        assert removed == 0 and np.array_equal(tets, m.tets)
+        return
+    assert removed == 1 and np.array_equal(xyz, m.xyz[:5])
+    assert {frozenset(int(x) for x in t) for t in tets} == expected_star_tets(expected)
+
+
 def test_coarsening_rejects_bad_arguments():
     m = nnms.Mesh.from_workload(W.kuhn_cube(3, 1))
     with pytest.raises(nnms.NNMSError) as e:

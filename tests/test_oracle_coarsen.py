@@ -139,3 +139,76 @@ def test_coarsened_hierarchy_converges():
     assert res.converged
     x = problem.exact(h)
     assert np.linalg.norm(res.x - x) <= 1e-6 * np.linalg.norm(x)
+
+
+QGOLD = os.path.join(os.path.dirname(__file__), "golden", "tet_quality.txt")
+
+
+def quality_golden():
+    """Rows of tests/golden/tet_quality.txt: {name: (hd, he, q_abc_min,
+    q_abc_mean, q_de, expected)} and the Kuhn tetrahedron's quality."""
+    rows, kuhn = {}, None
+    for line in open(QGOLD):
+        if not line.strip() or line.startswith("#"):
+            continue
+        f = line.split()
+        if f[0] == "kuhn_q":
+            kuhn = float(f[1])
+        else:
+            rows[f[0]] = tuple(float(x) for x in f[1:6]) + (f[6],)
+    return rows, kuhn
+
+
+def expected_star_tets(kind):
+    """Vertex sets of the elements a bipyramid star leaves (ids A..E = 0..4)."""
+    A, B, C, D, E = range(5)
+    if kind == "abc":
+        return {frozenset((A, B, C, D)), frozenset((A, B, C, E))}
+    return {frozenset((D, E, A, B)), frozenset((D, E, B, C)), frozenset((D, E, C, A))}
+
+
+def test_quality_closed_forms():
+    """q = 1 for a regular tetrahedron whatever its position, size and
+    rotation (and -1 mirrored), sqrt(2) (3/5)^(3/2) for the Kuhn
+    tetrahedron, 0 for a flat one: fixes the constant, the volume and that
+    l_rms is the root mean square of the edges (a mean edge gives 0.7068 on
+    the Kuhn tetrahedron)."""
+    _, kuhn = quality_golden()
+    reg = np.array([[1, -1, -1], [1, 1, 1], [-1, 1, -1], [-1, -1, 1]], dtype=float)
+    assert coarsen.det6(*reg) > 0
+    Q, _ = np.linalg.qr(np.random.default_rng(3).standard_normal((3, 3)))
+    if np.linalg.det(Q) < 0:
+        Q[:, 0] = -Q[:, 0]
+    for scale, shift in ((1.0, 0.0), (0.37, 5.0), (12.5, -3.25)):
+        p = reg @ Q.T * scale + shift
+        assert abs(coarsen.quality(*p) - 1.0) <= 1e-14
+        assert abs(coarsen.quality(p[1], p[0], p[2], p[3]) + 1.0) <= 1e-14
+    k = np.array([[0, 0, 0], [1, 0, 0], [1, 1, 0], [1, 1, 1]], dtype=float)
+    assert abs(coarsen.quality(*k) - kuhn) <= 1e-15
+    assert abs(coarsen.quality(*(0.01 * k + 0.5)) - kuhn) <= 1e-13
+    flat = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0.3, 0.4, 0]], dtype=float)
+    assert coarsen.quality(*flat) == 0.0
+
+
+@pytest.mark.parametrize("name", ["regular", "lopsided", "flat02", "flat007", "flat005"])
+def test_contraction_choice_on_hand_checked_stars(name):
+    """The removed vertex goes to the neighbour whose new elements have the
+    largest smallest quality, and only above the floor 0.02 (Section 3.1,
+    reading of the cavity re-meshing): the bipyramid stars of the golden
+    file, whose qualities are closed forms, leave the elements fixed by hand
+    ('lopsided' needs the smallest quality: the mean or the largest would
+    take A, B or C)."""
+    rows, _ = quality_golden()
+    hd, he, q_abc_min, q_abc_mean, q_de, expected = rows[name]
+    m = W.bipyramid_star(hd, he)
+    r = coarsen.coarsen(m.xyz, m.tets, m.dirichlet, 1, 9)
+    if expected == "keep":
+        assert r.removed == 0 and np.array_equal(r.tets, m.tets)
+        assert max(q_abc_min, q_de) < coarsen.QMIN
+        return
+    assert r.removed == 1 and list(r.kept_ids) == [0, 1, 2, 3, 4]
+    got = {frozenset(int(x) for x in t) for t in r.tets}
+    assert got == expected_star_tets(expected)
+    q = [coarsen.quality(*(r.xyz[i] for i in t)) for t in r.tets]
+    assert min(q) > 0
+    assert abs(min(q) - (q_abc_min if expected == "abc" else q_de)) <= 1e-13

@@ -225,3 +225,20 @@ def random_vector(n: int, seed: int, mask: Optional[np.ndarray] = None) -> np.nd
     if mask is not None:
         v[mask.astype(bool)] = 0.0
     return v
+
+
+def bipyramid_star(hd: float, he: float) -> Mesh:
+    """One interior vertex in a triangular bipyramid (a hand-checkable star for
+    the coarsening): vertices A, B, C (an equilateral triangle of side 1 in
+    z = 0, centroid at the origin, counter-clockwise seen from +z), D =
+    (0, 0, hd), E = (0, 0, -he) are Dirichlet; v (id 5) at the origin is the
+    only interior vertex.  The six tetrahedra join v to the faces ABD, BCD,
+    CAD (above) and BAE, CBE, ACE (below), each positively oriented by the
+    counter-clockwise order of A, B, C."""
+    r = 1.0 / np.sqrt(3.0)
+    xyz = np.array([[r, 0.0, 0.0], [-r / 2, 0.5, 0.0], [-r / 2, -0.5, 0.0],
+                    [0.0, 0.0, hd], [0.0, 0.0, -he], [0.0, 0.0, 0.0]])
+    A, B, C, D, E, v = range(6)
+    tets = np.array([[v, A, B, D], [v, B, C, D], [v, C, A, D],
+                     [v, B, A, E], [v, C, B, E], [v, A, C, E]], dtype=np.int32)
+    return Mesh(xyz, tets, np.array([1, 1, 1, 1, 1, 0], dtype=np.uint8), 0)
