@@ -72,6 +72,41 @@ def load_const(xyz, tets, f: float = 1.0) -> np.ndarray:
     return b
 
 
+def load_per_tet(xyz, tets, fT: np.ndarray) -> np.ndarray:
+    """Load vector of an f constant on every tetrahedron (values fT[nt]):
+    b_a = sum over the tetrahedra T at a of f_T |T| / 4, the exact integral
+    of f lambda_a (int_T lambda_a = |T| / 4)."""
+    vol, _, _ = tet_geometry(xyz, tets)
+    b = np.zeros(xyz.shape[0])
+    np.add.at(b, tets.ravel(), np.repeat(np.asarray(fT, dtype=np.float64) * np.abs(vol) / 4.0, 4))
+    return b
+
+
+def load_nodal(xyz, tets, fv: np.ndarray) -> np.ndarray:
+    """Load vector of the P1 interpolant f_h = sum_j f_j phi_j of nodal values
+    fv[nv], integrated exactly: b = M f with the P1 mass matrix, whose element
+    entries are int_T lambda_a lambda_b = |T| (1 + delta_ab) / 20."""
+    vol, _, _ = tet_geometry(xyz, tets)
+    fv = np.asarray(fv, dtype=np.float64)
+    Me = np.abs(vol)[:, None, None] * (np.ones((4, 4)) + np.eye(4))[None, :, :] / 20.0
+    contrib = np.einsum("tab,tb->ta", Me, fv[tets])
+    b = np.zeros(xyz.shape[0])
+    np.add.at(b, tets.ravel(), contrib.ravel())
+    return b
+
+
+def load(mesh, f) -> np.ndarray:
+    """Load vector of a source term: a number (constant f) or a field with
+    kind 'per_tet' / 'nodal' and values on this mesh."""
+    if isinstance(f, (int, float, np.floating)):
+        return load_const(mesh.xyz, mesh.tets, float(f))
+    if f.kind == "per_tet":
+        return load_per_tet(mesh.xyz, mesh.tets, f.values)
+    if f.kind == "nodal":
+        return load_nodal(mesh.xyz, mesh.tets, f.values)
+    raise ValueError(f.kind)
+
+
 def grundmann_moeller(s: int, dim: int = 3):
     """Grundmann-Moeller rule of degree 2s+1 on a simplex (SIAM J. Numer.
     Anal. 15, 1978).  Returns barycentric points [q, dim+1] and weights [q]
@@ -133,9 +168,10 @@ def dirichlet_eliminate(A_N: sp.csr_matrix, b: np.ndarray, dmask: np.ndarray):
     return A, bb
 
 
-def assemble(mesh, kappa, f: float = 1.0):
-    """The Dirichlet-eliminated system (A, b) of one mesh and coefficient."""
+def assemble(mesh, kappa, f=1.0):
+    """The Dirichlet-eliminated system (A, b) of one mesh and coefficient; f
+    as in `load`."""
     check_mesh(mesh.xyz, mesh.tets)
     A_N = stiffness_neumann(mesh.xyz, mesh.tets, kappa)
-    b = load_const(mesh.xyz, mesh.tets, f)
+    b = load(mesh, f)
     return dirichlet_eliminate(A_N, b, mesh.dirichlet)

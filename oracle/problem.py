@@ -27,9 +27,19 @@ class OracleHierarchy:
     vcycle: multilevel.VCycle
 
 
-def build(problem, f: float = 1.0, locate=transfer.locate_bucket, mls_alpha: Optional[float] = None,
+def level_kappa(kappa, l: int):
+    """The coefficient of level l: per-tetrahedron values come as one array
+    per level, any other kind is a field of the whole domain."""
+    if getattr(kappa, "kind", None) == "per_tet" and isinstance(kappa.value, (list, tuple)):
+        return type(kappa)(kind="per_tet", value=kappa.value[l])
+    return kappa
+
+
+def build(problem, f=1.0, locate=transfer.locate_bucket, mls_alpha: Optional[float] = None,
           ilu_fill: Optional[List[int]] = None, mls_restrict: bool = False) -> OracleHierarchy:
-    """mls_alpha: None for the barycentric transfer, else the MLS transfer of
+    """f: the source term of the finest level's load (a number, or a field of
+    kind 'per_tet' / 'nodal' with values on the finest mesh).
+    mls_alpha: None for the barycentric transfer, else the MLS transfer of
     Section 3.2 with initial scale mls_alpha times the coarse mean edge.
     ilu_fill: None for exact subdomain solves, else the ILU fill level of
     every smoothed level (the coarsest level is always solved directly).
@@ -40,7 +50,7 @@ def build(problem, f: float = 1.0, locate=transfer.locate_bucket, mls_alpha: Opt
     A, P, parts, levels = [], [], [], []
     b = None
     for l, m in enumerate(meshes):
-        Al, bl = fem.assemble(m, problem.kappa, f)
+        Al, bl = fem.assemble(m, level_kappa(problem.kappa, l), f if l == 0 else 1.0)
         A.append(Al)
         if l == 0:
             b = bl

@@ -155,3 +155,63 @@ def test_l2_error_second_order():
         errs.append(fem.l2_error(m.xyz, m.tets, x, u, s=2))
     rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert np.all(rates >= 1.8), (errs, rates)
+
+
+def test_per_tet_load_is_the_exact_integral():
+    """f constant per element: b_a = sum f_T |T| / 4 equals a constant f's load
+    when all values agree, and the quadrature of the element-wise constant
+    function (the rule, pinned by its exactness above, integrates lambda_a
+    exactly)."""
+    m = W.kuhn_cube(5, 21)
+    assert np.abs(fem.load_per_tet(m.xyz, m.tets, np.full(m.nt, 2.5)) - fem.load_const(m.xyz, m.tets, 2.5)).max() \
+        <= 1e-16
+    fT = np.random.default_rng(4).uniform(-3, 3, m.nt)
+    bq = fem.load_quadrature(m.xyz, m.tets, lambda p: fT, s=1)
+    b = fem.load_per_tet(m.xyz, m.tets, fT)
+    assert np.abs(b - bq).max() <= 1e-15 * np.abs(bq).max() * 10
+
+
+def test_nodal_load_is_the_exact_integral_of_the_interpolant():
+    """b = M f for P1 nodal values: constant values give the constant load,
+    and for a linear f (which its P1 interpolant reproduces) the load equals
+    the degree-3 quadrature of f lambda_a entry by entry -- this fixes the
+    element mass matrix |T| (1 + delta_ab) / 20."""
+    m = W.kuhn_cube(5, 22)
+    assert np.abs(fem.load_nodal(m.xyz, m.tets, np.full(m.nv, -1.5)) - fem.load_const(m.xyz, m.tets, -1.5)).max() \
+        <= 1e-16
+    lin = lambda p: 0.7 - 2.0 * p[:, 0] + 3.5 * p[:, 1] + 1.25 * p[:, 2]
+    b = fem.load_nodal(m.xyz, m.tets, lin(m.xyz))
+    bq = fem.load_quadrature(m.xyz, m.tets, lin, s=1)
+    assert np.abs(b - bq).max() <= 1e-14 * np.abs(bq).max()
+    # a quadratic is not reproduced: the nodal load then differs
+    quad = lambda p: p[:, 0] ** 2
+    assert np.abs(fem.load_nodal(m.xyz, m.tets, quad(m.xyz)) - fem.load_quadrature(m.xyz, m.tets, quad, s=1)).max() \
+        > 1e-6
+
+
+@pytest.mark.slow
+def test_l2_error_second_order_nodal_load():
+    """The same O(h^2) rate with the load of the P1 interpolant of f
+    (nodal values), the form the library takes for a general f."""
+    u = lambda p: np.sin(np.pi * p[:, 0]) * np.sin(np.pi * p[:, 1]) * np.sin(np.pi * p[:, 2])
+    errs = []
+    for n in [8, 16, 32]:
+        m = W.kuhn_cube(n, 1000 + n)
+        A, b = fem.assemble(m, W.KappaField(), W.LoadField("nodal", 3 * np.pi ** 2 * u(m.xyz)))
+        x = spla.spsolve(A.tocsc(), b)
+        errs.append(fem.l2_error(m.xyz, m.tets, x, u, s=2))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(rates >= 1.8), (errs, rates)
+
+
+def test_per_level_kappa_arrays_in_the_hierarchy():
+    """Per-tetrahedron kappa given per level equals the field evaluated at
+    each level's own centroids (the oracle's hierarchy takes either)."""
+    from oracle import problem
+
+    pb = W.Problem("t", [W.kuhn_cube(6, 1), W.kuhn_cube(3, 2)], [2], W.kappa_draw(204, 205))
+    arrs = [fem.kappa_eval(fem.tet_geometry(m.xyz, m.tets)[2], pb.kappa) for m in pb.meshes]
+    pb2 = W.Problem("t", pb.meshes, [2], W.KappaField("per_tet", value=arrs))
+    h1, h2 = problem.build(pb), problem.build(pb2)
+    for A1, A2 in zip(h1.A, h2.A):
+        assert (A1 != A2).nnz == 0

@@ -109,14 +109,24 @@ def kuhn_cube(n: int, seed: Optional[int] = None, jitter: float = JITTER) -> Mes
 class KappaField:
     """Parameters of log kappa(x) = sum_k mu_k exp(-|x - c_k|^2 / width).
 
-    kind 'const' means kappa == value everywhere.
+    kind 'const' means kappa == value everywhere; kind 'per_tet' carries the
+    values of every tetrahedron in `value` (one array per mesh level).
     """
 
     kind: str = "const"
-    value: float = 1.0
+    value: object = 1.0  # float, or per-level arrays for 'per_tet'
     centres: Optional[np.ndarray] = None  # [K,3]
     mu: Optional[np.ndarray] = None  # [K]
     width: float = KAPPA_WIDTH
+
+
+@dataclass
+class LoadField:
+    """Values of a source term f on the finest mesh: kind 'per_tet' (one value
+    per tetrahedron, f constant on each) or 'nodal' (P1 nodal values)."""
+
+    kind: str
+    values: np.ndarray
 
 
 def kappa_draw(centre_seed: int, mu_seed: int, k: int = 8, mu_range: float = 2.0) -> KappaField:
