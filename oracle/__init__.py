@@ -18,5 +18,7 @@ Modules
   multilevel V-cycle of Algorithm 2 (Section 3.3)
   krylov     right-preconditioned flexible GMRES (Section 2.1, Section 4)
   problem    glue that builds a whole hierarchy from a workload
+  elasticity P1 linear elasticity (Section 4.2) with the field-split
+             interpolation of Section 3.2
 """
-from . import fem, transfer, mls, ilu, coarsen, schwarz, multilevel, krylov, problem  # noqa: F401
+from . import fem, transfer, mls, ilu, coarsen, schwarz, multilevel, krylov, problem, elasticity  # noqa: F401
