@@ -238,35 +238,84 @@ nnms_status nnms_hierarchy_ilu_pattern(const nnms_hierarchy* h, int32_t level, i
                                        int32_t* col_host);
 
 /* ---------------------------------------------------------------------------
- * assemble(mesh, kappa): numeric setup for one parameter.  On the device:
- * kappa at every tetrahedron's centroid, P1 stiffness of every level
- * (coarse levels rediscretised, as Algorithm 2 provides the Jacobian of
- * every level), the load vector of a constant f on the finest level,
- * extraction of the dense overlapping subdomain matrices
- * J_p = R_p J R_p^T (Section 2.2) and their LU factorisation without
- * pivoting (the matrices are SPD), plus the coarsest dense FP64 LU.
+ * assemble(mesh, kappa): numeric setup for one parameter (Section 2.1: the
+ * parameters mu of a parametric problem enter the coefficients, and the mesh
+ * hierarchy is reused across them).  On the device: kappa of every
+ * tetrahedron, P1 stiffness of every level (coarse levels rediscretised, as
+ * Algorithm 2 provides the Jacobian of every level), the load vector on the
+ * finest level, extraction of the overlapping subdomain matrices
+ * J_p = R_p J R_p^T (Section 2.2) and their factorisation without pivoting
+ * (the matrices are SPD), plus the coarsest dense FP64 LU.
  *
- * kappa: kind 0 = constant `value` (> 0);  kind 1 = log-Gaussian,
- *        log kappa(x) = sum_k mu[k] exp(-|x - centres[k]|^2 / width),
- *        ncentres <= 64, width > 0 (host arrays).
- * f:     constant source term of the load vector.
- * Errors: NNMS_ERR_INVALID_ARG, NNMS_ERR_SINGULAR, NNMS_ERR_OUT_OF_MEMORY,
+ * kappa (host memory; nothing is kept after the call):
+ *   kind 0  constant `value` (> 0);
+ *   kind 1  log-Gaussian, log kappa(x) = sum_k mu[k] exp(-|x - centres[k]|^2
+ *           / width) at every tetrahedron's centroid, ncentres <= 64,
+ *           width > 0;
+ *   kind 2  given per tetrahedron: per_tet[l] holds nt_l doubles, the value
+ *           on every tetrahedron of level l, for every level l of the
+ *           hierarchy (finite and > 0; coarse levels carry their own values,
+ *           e.g. the field at their own centroids).
+ * rhs, the source term f of the load vector b_i = int f phi_i on the finest
+ * level (host memory):
+ *   kind 0  constant `value`: b_i = f sum_{T at i} |T| / 4;
+ *   kind 1  one value per tetrahedron of the finest level (values[nt_0]),
+ *           f constant on each: b_i = sum_{T at i} f_T |T| / 4;
+ *   kind 2  P1 nodal values of the finest level (values[nv_0]), f taken as
+ *           its interpolant sum_j f_j phi_j and integrated exactly with the
+ *           element mass matrix |T| (1 + delta_ab) / 20: b_i =
+ *           sum_{T at i} |T| / 20 (f_i + sum_{a in T} f_a).
+ *   Values must be finite.  Entries of Dirichlet vertices are 0.
+ * Errors: NNMS_ERR_INVALID_ARG (a bad kind, size or value: before any device
+ *         work), NNMS_ERR_BUDGET, NNMS_ERR_SINGULAR, NNMS_ERR_OUT_OF_MEMORY,
  *         NNMS_ERR_DEVICE.
  * ------------------------------------------------------------------------- */
 typedef struct {
   int32_t kind;
   int32_t ncentres;
   double value;
-  const double* centres; /* ncentres*3 */
-  const double* mu;      /* ncentres */
-  double width;
+  const double* centres; /* kind 1: ncentres*3 */
+  const double* mu;      /* kind 1: ncentres */
+  double width;          /* kind 1 */
+  const double* const* per_tet; /* kind 2: one array per level, nt_l doubles each */
 } nnms_kappa;
 
+typedef struct {
+  int32_t kind;
+  int32_t reserved;
+  double value;          /* kind 0 */
+  const double* values;  /* kind 1: nt_0 doubles; kind 2: nv_0 doubles */
+} nnms_rhs;
+
+/* restart_cap  Krylov basis columns kept with the system for its solves
+ *              (1..NNMS_MAX_RESTART; 0 = NNMS_MAX_RESTART); a solve or batch
+ *              asking for a larger restart gives NNMS_ERR_INVALID_ARG.
+ * max_device_bytes  > 0: the device memory this assembly may take; the
+ *              assembly is refused with NNMS_ERR_BUDGET, before any device
+ *              work, when nnms_hierarchy_system_bytes(h, restart_cap) (the
+ *              peak of any assembly of h) exceeds it.  0: no limit. */
+typedef struct {
+  const nnms_kappa* kappa; /* required */
+  const nnms_rhs* rhs;     /* NULL: f = 1 */
+  int32_t restart_cap;
+  int32_t reserved;
+  int64_t max_device_bytes;
+} nnms_assemble_opts;
+
+nnms_status nnms_assemble_ex(nnms_hierarchy* h, const nnms_assemble_opts* opts, void* stream, nnms_system** out);
+/* The same with a constant load f, restart_cap NNMS_MAX_RESTART and no budget. */
 nnms_status nnms_assemble(nnms_hierarchy* h, const nnms_kappa* kappa, double f, void* stream, nnms_system** out);
 nnms_status nnms_system_destroy(nnms_system* s);
 /* Device bytes held by one assembled system (values, factors, workspace). */
 int64_t nnms_system_device_bytes(const nnms_system* s);
-/* Device bytes an assembly of h would take (for admission decisions). */
+/* Device bytes an assembly of h with restart_cap = restart (0: NNMS_MAX_RESTART)
+ * takes at its peak: what the system keeps (nnms_system_device_bytes) plus
+ * what the assembly holds only while it runs (element matrices of the
+ * largest level, per-tetrahedron kappa and load arrays, descriptors), for
+ * admission decisions; -1 for a null handle or a restart out of range.  The
+ * solve plans a system's first solve and operator calls build add a few KiB
+ * to a few MiB (descriptors, task lists), recycled through a per-process
+ * cache of at most 64 MiB. */
 int64_t nnms_hierarchy_system_bytes(const nnms_hierarchy* h, int32_t restart);
 
 /* Read-back for checks: the load vector (nv_0 doubles) and the FP64 CSR

@@ -499,6 +499,7 @@ static void build_ras_pair(Arena& mem, std::vector<int32_t*>& counters, const st
   if (subs_r.size() > 32767) throw Error(NNMS_ERR_INVALID_ARG, "too many subdomains in one batch");
   std::vector<int32_t> tasks = ras_tasks(Ns, K);
   int32_t* counter = mem.alloc<int32_t>(4, s);
+  HIP_CHECK(launch_ras_seed(counter, s));
   counters.push_back(counter);
   rr = RasLaunch{};
   rr.subs = mem.upload(subs_r, s);
@@ -702,7 +703,12 @@ static void check_counters(Plan& P, hipStream_t s) {
     int32_t v[4];
     HIP_CHECK(hipMemcpyAsync(v, c, sizeof v, hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipStreamSynchronize(s));
-    if (v[2]) throw Error(NNMS_ERR_DEVICE, "triangular-solve wait limit exceeded (error bits " + std::to_string(v[2]) + ")");
+    if (v[2]) {
+      // reported once: later calls through the same plan report only their own failures
+      HIP_CHECK(hipMemsetAsync(c + 2, 0, sizeof(int32_t), s));
+      HIP_CHECK(hipStreamSynchronize(s));
+      throw Error(NNMS_ERR_DEVICE, "triangular-solve wait limit exceeded (error bits " + std::to_string(v[2]) + ")");
+    }
   }
 }
 
@@ -819,6 +825,14 @@ static void join_in(hipStream_t user, hipStream_t inner) {
 static void validate_solve_opts(const nnms_solve_opts& o) {
   if (o.restart < 1 || o.restart > NNMS_MAX_RESTART || !(o.rtol > 0) || o.max_it < 1)
     throw Error(NNMS_ERR_INVALID_ARG, "bad solve options");
+}
+
+// a system keeps Krylov bases of restart_cap columns
+static void check_restart(const std::vector<nnms_system*>& sys, const nnms_solve_opts& o) {
+  for (auto* s : sys)
+    if (o.restart > s->restart_cap)
+      throw Error(NNMS_ERR_INVALID_ARG, "restart " + std::to_string(o.restart) + " exceeds the system's restart_cap " +
+                                            std::to_string(s->restart_cap));
 }
 
 }  // namespace nnms
@@ -1095,32 +1109,62 @@ extern "C" nnms_status nnms_hierarchy_ilu_pattern(const nnms_hierarchy* h, int32
   ABI_END
 }
 
-static int64_t system_bytes(const HostHierarchy& H, int prec, int restart) {
-  int64_t b = 0;
+// Device memory of one assembly, allocation by allocation (each rounded up to
+// 256 bytes, as the arena does): `resident` stays with the system,
+// `transient` is held only while the assembly runs.  kappa_kind / rhs_kind
+// select the per-tetrahedron and load arrays the assembly uploads.
+struct SysLayout {
+  int64_t resident = 0, transient = 0;
+};
+static int64_t round256(int64_t b) { return ((b ? b : 1) + 255) & ~int64_t(255); }
+
+static SysLayout system_layout(const HostHierarchy& H, int prec, int cap, int kappa_kind, int rhs_kind) {
+  SysLayout o;
+  auto R = [&](int64_t b) { o.resident += round256(b); };
+  auto T = [&](int64_t b) { o.transient += round256(b); };
+  int64_t max_nt = 0;
+  for (int l = 0; l < H.L; ++l) max_nt = std::max(max_nt, H.lev[l].nt);
+  T(max_nt * 17 * 8);  // element matrices and volumes
+  T(sizeof(int));      // pivot error flag
+  const int64_t tsz = prec == NNMS_FP64 ? 8 : 4;
   for (int l = 0; l < H.L; ++l) {
     const HostLevel& lv = H.lev[l];
     const bool coarse = (l == H.L - 1);
-    const int64_t f = (coarse || prec == NNMS_FP64) ? 8 : 4;
-    const int64_t t = prec == NNMS_FP64 ? 8 : 4;
-    b += int64_t(lv.col.size()) * 8 + (prec == NNMS_MIXED ? int64_t(lv.col.size()) * 4 : 0);
-    const int64_t ne = lv.sell_off.empty() ? 0 : int64_t(lv.sell_off.back());
-    b += ne * 8 + (prec == NNMS_MIXED ? ne * 4 : 0);
-    if (!coarse && lv.subsolver == NNMS_SUBSOLVER_ILU)
-      b += int64_t(lv.ilu_col.size()) * f + 512;
-    else
-      b += lv.fac_elems * f + lv.g_total * 16;
-    b += 3 * lv.nv * t;
+    const int64_t fsz = (coarse || prec == NNMS_FP64) ? 8 : 4;
+    const int64_t nnz = int64_t(lv.col.size()), nell = int64_t(lv.sell_off.back());
+    R(nnz * 8);
+    if (prec == NNMS_MIXED) R(nnz * 4);
+    R(nell * 8);
+    if (prec == NNMS_MIXED) R(nell * 4);
+    if (!coarse && lv.subsolver == NNMS_SUBSOLVER_ILU) {
+      R(256), R(256), R(std::max<int64_t>(int64_t(lv.ilu_col.size()) * fsz, 256));
+      T(int64_t(lv.nparts) * int64_t(sizeof(IluDesc)));
+    } else {
+      R(std::max<int64_t>(lv.fac_elems * fsz, 256)), R(lv.g_total * 16);
+      T(int64_t(lv.nparts) * int64_t(sizeof(FacDesc)));
+    }
+    R(lv.nv * tsz), R(lv.nv * tsz), R(lv.nv * tsz);
+    if (l == 0) R(lv.nv * 8);  // load vector
+    if (kappa_kind == 2) T(lv.nt * 8);
   }
-  const int64_t n0 = H.lev[0].nv;
-  b += n0 * 8 * (2 * int64_t(restart) + 1 + 4);
-  const int64_t nb = (n0 + VBLK - 1) / VBLK;
-  b += nb * 8 * (2 * MMAX + 2) + ((n0 + 15) / 16) * 8 + int64_t(sizeof(KState));
-  return b;
+  const int64_t n0 = H.lev[0].nv, nt0 = H.lev[0].nt;
+  if (rhs_kind == 1) T(nt0 * 8);
+  if (rhs_kind == 2) T(n0 * 8);
+  const int64_t nblk = (n0 + VBLK - 1) / VBLK, nblkr = (n0 + 3) / 4;
+  R(n0 * (cap + 1) * 8), R(n0 * cap * 8);  // Krylov bases V, Z
+  R(n0 * 8), R(n0 * 8), R(n0 * 8);          // w, x, b
+  R(nblk * (MMAX + 1) * 8), R(nblk * MMAX * 8), R(nblk * 8), R(nblkr * 8);
+  R(int64_t(sizeof(KState)));
+  return o;
 }
 
 extern "C" int64_t nnms_hierarchy_system_bytes(const nnms_hierarchy* h, int32_t restart) {
-  if (!h) return -1;
-  return system_bytes(h->host, h->host.opts.precision, restart > 0 ? restart : 30);
+  if (!h || restart < 0 || restart > NNMS_MAX_RESTART) return -1;
+  const HostHierarchy& H = h->host;
+  // the larger of the two per-element-array choices of the load: per tetrahedron
+  const SysLayout o = system_layout(H, H.opts.precision, restart ? restart : NNMS_MAX_RESTART, 2,
+                                    H.lev[0].nt >= H.lev[0].nv ? 1 : 2);
+  return o.resident + o.transient;
 }
 
 // Dense subdomain matrices of one level and their factorisation: zero fill
@@ -1213,15 +1257,25 @@ static hipError_t enqueue_ilu(const IluJob& j, int* err, hipStream_t s) {
   return launch_ilu_factor<float>(j.d, j.nd, j.lanes, err, s);
 }
 
-extern "C" nnms_status nnms_assemble(nnms_hierarchy* h, const nnms_kappa* k, double f, void* stream, nnms_system** out) {
+static bool all_finite(const double* v, int64_t n, bool positive) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(v[i]) || (positive && !(v[i] > 0))) return false;
+  return true;
+}
+
+extern "C" nnms_status nnms_assemble_ex(nnms_hierarchy* h, const nnms_assemble_opts* o, void* stream,
+                                        nnms_system** out) {
   ABI_BEGIN
-  if (!h || !k || !out) throw Error(NNMS_ERR_INVALID_ARG, "null argument");
+  if (!h || !o || !o->kappa || !out) throw Error(NNMS_ERR_INVALID_ARG, "null argument");
   *out = nullptr;
   if (!h->on_device) throw Error(NNMS_ERR_INVALID_ARG, "hierarchy was set up without a device");
+  const nnms_kappa* k = o->kappa;
+  const HostHierarchy& H = h->host;
+  const int L = H.L, prec = H.opts.precision;
   KappaDev kd{};
   kd.kind = k->kind;
   if (k->kind == 0) {
-    if (!(k->value > 0)) throw Error(NNMS_ERR_INVALID_ARG, "kappa must be positive");
+    if (!(k->value > 0) || !std::isfinite(k->value)) throw Error(NNMS_ERR_INVALID_ARG, "kappa must be positive");
     kd.value = k->value;
   } else if (k->kind == 1) {
     if (k->ncentres < 0 || k->ncentres > MAXC || !(k->width > 0) || (k->ncentres && (!k->centres || !k->mu)))
@@ -1231,12 +1285,37 @@ extern "C" nnms_status nnms_assemble(nnms_hierarchy* h, const nnms_kappa* k, dou
       for (int a = 0; a < 3; ++a) kd.c[3 * c + a] = k->centres[3 * c + a];
       kd.mu[c] = k->mu[c];
     }
+  } else if (k->kind == 2) {
+    if (!k->per_tet) throw Error(NNMS_ERR_INVALID_ARG, "per-tetrahedron kappa needs one array per level");
+    for (int l = 0; l < L; ++l)
+      if (!k->per_tet[l] || !all_finite(k->per_tet[l], H.lev[l].nt, true))
+        throw Error(NNMS_ERR_INVALID_ARG, "per-tetrahedron kappa of level " + std::to_string(l) +
+                                              " must be finite and positive");
   } else {
     throw Error(NNMS_ERR_INVALID_ARG, "unknown kappa kind");
   }
+  nnms_rhs rhs{};
+  rhs.kind = 0, rhs.value = 1.0;
+  if (o->rhs) rhs = *o->rhs;
+  if (rhs.kind == 0) {
+    if (!std::isfinite(rhs.value)) throw Error(NNMS_ERR_INVALID_ARG, "the load must be finite");
+  } else if (rhs.kind == 1 || rhs.kind == 2) {
+    const int64_t n = rhs.kind == 1 ? H.lev[0].nt : H.lev[0].nv;
+    if (!rhs.values || !all_finite(rhs.values, n, false))
+      throw Error(NNMS_ERR_INVALID_ARG, "load values missing or not finite");
+  } else {
+    throw Error(NNMS_ERR_INVALID_ARG, "unknown load kind");
+  }
+  const int cap = o->restart_cap ? o->restart_cap : NNMS_MAX_RESTART;
+  if (cap < 1 || cap > NNMS_MAX_RESTART) throw Error(NNMS_ERR_INVALID_ARG, "restart_cap out of range");
+  if (o->max_device_bytes < 0) throw Error(NNMS_ERR_INVALID_ARG, "negative device-memory budget");
+  if (o->max_device_bytes > 0) {
+    const int64_t need = nnms_hierarchy_system_bytes(h, cap);
+    if (need > o->max_device_bytes)
+      throw Error(NNMS_ERR_BUDGET, "the assembly needs up to " + std::to_string(need) +
+                                       " device bytes, the budget is " + std::to_string(o->max_device_bytes));
+  }
   hipStream_t s = (hipStream_t)stream;
-  const HostHierarchy& H = h->host;
-  const int L = H.L, prec = H.opts.precision;
   auto sys = std::unique_ptr<nnms_system>(new nnms_system);
   sys->h = h;
   h->systems++;
@@ -1250,6 +1329,11 @@ extern "C" nnms_status nnms_assemble(nnms_hierarchy* h, const nnms_kappa* k, dou
   Arena scratch(h->has_alloc ? &h->alloc : nullptr);
   double* elem = scratch.alloc<double>(size_t(max_nt) * 17, s, false);
   int* err = scratch.alloc<int>(1, s);
+  const double* fval = nullptr;
+  if (rhs.kind != 0) {
+    const int64_t n = rhs.kind == 1 ? H.lev[0].nt : H.lev[0].nv;
+    fval = scratch.upload(std::vector<double>(rhs.values, rhs.values + n), s);
+  }
   for (int l = 0; l < L; ++l) {
     const HostLevel& hl = H.lev[l];
     const DevLevel& dl = h->dev[l];
@@ -1277,11 +1361,14 @@ extern "C" nnms_status nnms_assemble(nnms_hierarchy* h, const nnms_kappa* k, dou
     ad.xyz = dl.xyz, ad.tets = dl.tets, ad.cptr = dl.cptr, ad.citem = dl.citem, ad.rp = dl.rp;
     ad.vptr = dl.vptr, ad.vitem = dl.vitem, ad.dmask = dl.dmask, ad.elem = elem;
     ad.val64 = sl.val64, ad.val32 = sl.val32, ad.nt = hl.nt, ad.nv = hl.nv;
+    if (k->kind == 2) ad.kappa_tet = scratch.upload(std::vector<double>(k->per_tet[l], k->per_tet[l] + hl.nt), s);
     if (l == 0) {
       sys->b0 = A.alloc<double>(hl.nv, s, false);
       ad.b = sys->b0;
+      ad.fkind = rhs.kind;
+      ad.fval = fval;
     }
-    HIP_CHECK(launch_assemble(ad, kd, f, s));
+    HIP_CHECK(launch_assemble(ad, kd, rhs.value, s));
     HIP_CHECK(launch_gather_ell<double>(dl.sell_src, sl.val64, sl.ell64, nell, s));
     if (sl.ell32) HIP_CHECK(launch_gather_ell<float>(dl.sell_src, sl.val64, sl.ell32, nell, s));
     if (ilu) {
@@ -1294,14 +1381,13 @@ extern "C" nnms_status nnms_assemble(nnms_hierarchy* h, const nnms_kappa* k, dou
       HIP_CHECK(enqueue_factor(job, err, s));
     }
   }
-  // solve workspace
+  // solve workspace: Krylov bases of restart_cap columns
   const int64_t n0 = H.lev[0].nv;
-  const int m = NNMS_MAX_RESTART;
-  sys->restart_cap = m;
+  sys->restart_cap = cap;
   sys->nblk = vec_blocks(n0);
   sys->nblkr = spmv_blocks(n0, 64);  // most blocks of any lanes-per-row choice (4 rows per block)
-  sys->V = A.alloc<double>(size_t(n0) * (m + 1), s, false);
-  sys->Z = A.alloc<double>(size_t(n0) * m, s, false);
+  sys->V = A.alloc<double>(size_t(n0) * (cap + 1), s, false);
+  sys->Z = A.alloc<double>(size_t(n0) * cap, s, false);
   sys->w = A.alloc<double>(n0, s);
   sys->x = A.alloc<double>(n0, s);
   sys->bw = A.alloc<double>(n0, s);
@@ -1321,6 +1407,14 @@ extern "C" nnms_status nnms_assemble(nnms_hierarchy* h, const nnms_kappa* k, dou
   *out = sys.release();
   return NNMS_OK;
   ABI_END
+}
+
+extern "C" nnms_status nnms_assemble(nnms_hierarchy* h, const nnms_kappa* k, double f, void* stream, nnms_system** out) {
+  nnms_rhs rhs{};
+  rhs.kind = 0, rhs.value = f;
+  nnms_assemble_opts o{};
+  o.kappa = k, o.rhs = &rhs;
+  return nnms_assemble_ex(h, &o, stream, out);
 }
 
 extern "C" nnms_status nnms_system_destroy(nnms_system* s) {
@@ -1526,6 +1620,7 @@ static nnms_status solve_many(nnms_system* const* systems, int32_t nb, const dou
   std::vector<nnms_system*> sys(systems, systems + nb);
   for (auto* s : sys)
     if (!s) throw Error(NNMS_ERR_INVALID_ARG, "null system");
+  check_restart(sys, o);
   std::unique_ptr<Plan> local;
   Plan* P;
   if (use_solo) {
@@ -1596,6 +1691,7 @@ extern "C" nnms_status nnms_batch_create(nnms_system* const* systems, int32_t nb
   std::vector<nnms_system*> sys(systems, systems + nb);
   for (auto* s : sys)
     if (!s) throw Error(NNMS_ERR_INVALID_ARG, "null system");
+  check_restart(sys, bt->opts);
   bt->plan = make_plan_any(sys, true);
   bt->plan->use_graph = !(bt->opts.flags & NNMS_NO_GRAPH);
   join_in((hipStream_t)stream, bt->plan->stream);

@@ -6,8 +6,11 @@
 //             element matrix kappa_T |T| grad(lambda_a).grad(lambda_b)
 //   k_gather: per CSR row, every entry sums its element contributions in
 //             element order (deterministic, no atomics); Dirichlet rows
-//             get a unit diagonal; the load vector of a constant f sums
-//             f |T| / 4 over the incident elements of interior vertices.
+//             get a unit diagonal; the load vector sums over the incident
+//             elements of interior vertices: f |T| / 4 for a constant f,
+//             f_T |T| / 4 for an f constant per element, and the element
+//             mass matrix |T| (1 + delta_ab) / 20 applied to P1 nodal values
+//             (the exact integral of the interpolant against phi_i).
 #include "devcommon.h"
 #include "kernels.h"
 
@@ -46,7 +49,9 @@ __global__ __launch_bounds__(256) void k_elem(AsmDesc a, KappaDev kap) {
   for (int c = 0; c < 3; ++c) g[0][c] = -(g[1][c] + g[2][c] + g[3][c]);
   const double vol = fabs(det) / 6.0;
   double kT = kap.value;
-  if (kap.kind == 1) {
+  if (kap.kind == 2) {
+    kT = a.kappa_tet[t];
+  } else if (kap.kind == 1) {
     double cx = 0.25 * (x[0][0] + x[1][0] + x[2][0] + x[3][0]);
     double cy = 0.25 * (x[0][1] + x[1][1] + x[2][1] + x[3][1]);
     double cz = 0.25 * (x[0][2] + x[1][2] + x[2][2] + x[3][2]);
@@ -84,8 +89,25 @@ __global__ __launch_bounds__(256) void k_gather(AsmDesc a, double f) {
   }
   if (a.b) {
     double acc = 0.0;
-    for (int c = a.vptr[i]; c < a.vptr[i + 1]; ++c) acc += a.elem[a.nt * 16 + (a.vitem[c] >> 2)];
-    a.b[i] = f * acc * 0.25;
+    if (a.fkind == 0) {
+      for (int c = a.vptr[i]; c < a.vptr[i + 1]; ++c) acc += a.elem[a.nt * 16 + (a.vitem[c] >> 2)];
+      a.b[i] = f * acc * 0.25;
+    } else if (a.fkind == 1) {
+      for (int c = a.vptr[i]; c < a.vptr[i + 1]; ++c) {
+        const int t = a.vitem[c] >> 2;
+        acc += a.fval[t] * a.elem[a.nt * 16 + t];
+      }
+      a.b[i] = acc * 0.25;
+    } else {
+      const double fi = a.fval[i];
+      for (int c = a.vptr[i]; c < a.vptr[i + 1]; ++c) {
+        const int t = a.vitem[c] >> 2;
+        const int4 v = ((const int4*)a.tets)[t];
+        const double s4 = (a.fval[v.x] + a.fval[v.y]) + (a.fval[v.z] + a.fval[v.w]);
+        acc += a.elem[a.nt * 16 + t] * (s4 + fi);
+      }
+      a.b[i] = acc / 20.0;
+    }
   }
 }
 

@@ -73,7 +73,7 @@ struct SubDesc {
 struct RasLaunch {
   const SubDesc* subs;
   const int32_t* tasks;  // (sub << 16) | (dir << 15) | work item (group of K blocks)
-  int32_t* counter;      // [0] ticket, [2] error bits
+  int32_t* counter;      // [0] ticket, [1] this launch's epoch, [2] error bits
   int32_t ntasks;
   int32_t add;           // z += x (1) or z = x (0)
   int32_t group;         // 64-row blocks per work item (1, 2 or 4)
@@ -155,8 +155,12 @@ struct AsmDesc {
   double* val64;
   float* val32;     // may be null
   double* b;        // may be null (load vector)
+  const double* kappa_tet;  // kappa kind 2: value per tetrahedron
+  const double* fval;       // load kinds 1 (per tetrahedron) and 2 (P1 nodal values)
   int64_t nt;
   int64_t nv;
+  int32_t fkind;            // 0 constant, 1 per tetrahedron, 2 nodal
+  int32_t pad;
 };
 
 }  // namespace nnms

@@ -34,12 +34,40 @@ namespace nnms {
 
 constexpr int SPIN_LIMIT = 1 << 22;
 
-// Launch counter shared by every smoother launch on this device: a launch
-// tags its results with a value above every launch that finished before it
-// started, so results left in a workspace by any earlier launch (of any
-// plan) never carry a current tag.  Concurrent launches may share a value;
-// they never share a workspace.
+// Epochs.  A launch tags its results with its epoch e (2e forward, 2e + 1
+// backward).  The epoch lives in word 1 of the launch's counter array and is
+// read by every work-group when it starts; it is set before the launch, by
+// the seeding kernel when the counter array is created or by the last
+// work-group of the previous launch on the same counter array (launches on
+// one counter array are stream-ordered), from the device-wide counter below.
+// So every launch has one epoch for all its work-groups, whatever runs on
+// other streams meanwhile, and no two launches share one (until the 31-bit
+// counter wraps): results left in a workspace by any earlier launch never
+// carry a current tag.
 __device__ int32_t g_ras_epoch = 0;
+
+__device__ __forceinline__ int32_t fresh_epoch() {
+  int32_t e = (atomicAdd(&g_ras_epoch, 1) + 1) & 0x7fffffff;
+  return e ? e : 1;  // tag 0 never matches: zeroed words and torn FP64 halves read as 0
+}
+
+__global__ void k_ras_seed(int32_t* counter) {
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(counter, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(counter + 1, fresh_epoch(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+hipError_t launch_ras_seed(int32_t* counter, hipStream_t s) {
+  hipLaunchKernelGGL(k_ras_seed, dim3(1), dim3(64), 0, s, counter);
+  return hipGetLastError();
+}
+
+// the last work-group of a launch: ticket back to 0, the next launch's epoch
+__device__ __forceinline__ void finish_launch(int32_t* counter) {
+  __hip_atomic_store(counter, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(counter + 1, fresh_epoch(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 
 __device__ __forceinline__ uint64_t ld64(const uint64_t* p) {
@@ -99,7 +127,7 @@ __global__ __launch_bounds__(256, (RasWaves<F, K>::value)) void k_ras(RasLaunch 
   __shared__ __align__(16) F ywv[4][2][64];  // per-wave staging of fetched result blocks
   __shared__ int s_task;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int epoch = __hip_atomic_load(&g_ras_epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
+  const int epoch = __hip_atomic_load(P.counter + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const uint32_t tag_fwd = 2u * uint32_t(epoch), tag_bwd = tag_fwd + 1u;
 
   // this lane's value of block j, waiting until the whole wave sees `tag`
@@ -127,8 +155,7 @@ __global__ __launch_bounds__(256, (RasWaves<F, K>::value)) void k_ras(RasLaunch 
     __syncthreads();
     if (t >= P.ntasks) {
       if (tid == 0 && t == P.ntasks + int(gridDim.x) - 1) {
-        __hip_atomic_store(P.counter, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_max(&g_ras_epoch, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        finish_launch(P.counter);
       }
       return;
     }
@@ -387,7 +414,7 @@ __global__ __launch_bounds__(256, (RasWaves<F, 2>::value)) void k_ras2(RasLaunch
   __shared__ __align__(16) F ywv[4][2][64];  // per-wave staging of fetched result blocks
   __shared__ int s_task;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int epoch = __hip_atomic_load(&g_ras_epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
+  const int epoch = __hip_atomic_load(P.counter + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const uint32_t tag_fwd = 2u * uint32_t(epoch), tag_bwd = tag_fwd + 1u;
 
   auto fetch = [&](const uint64_t* yx, int j, uint32_t tag, uint32_t tag2) -> F {
@@ -413,8 +440,7 @@ __global__ __launch_bounds__(256, (RasWaves<F, 2>::value)) void k_ras2(RasLaunch
     __syncthreads();
     if (t >= P.ntasks) {
       if (tid == 0 && t == P.ntasks + int(gridDim.x) - 1) {
-        __hip_atomic_store(P.counter, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_max(&g_ras_epoch, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        finish_launch(P.counter);
       }
       return;
     }

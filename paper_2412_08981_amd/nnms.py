@@ -65,7 +65,18 @@ class level_info(C.Structure):
 
 class kappa_t(C.Structure):
     _fields_ = [("kind", C.c_int32), ("ncentres", C.c_int32), ("value", C.c_double),
-                ("centres", C.POINTER(C.c_double)), ("mu", C.POINTER(C.c_double)), ("width", C.c_double)]
+                ("centres", C.POINTER(C.c_double)), ("mu", C.POINTER(C.c_double)), ("width", C.c_double),
+                ("per_tet", C.POINTER(C.POINTER(C.c_double)))]
+
+
+class rhs_t(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("value", C.c_double),
+                ("values", C.POINTER(C.c_double))]
+
+
+class assemble_opts_t(C.Structure):
+    _fields_ = [("kappa", C.POINTER(kappa_t)), ("rhs", C.POINTER(rhs_t)), ("restart_cap", C.c_int32),
+                ("reserved", C.c_int32), ("max_device_bytes", C.c_int64)]
 
 
 class solve_opts(C.Structure):
@@ -128,6 +139,7 @@ _sig = {
     "nnms_system_ilu_values": (C.c_int, [vp, C.c_int32, vp]),
     "nnms_hierarchy_system_bytes": (C.c_int64, [vp, C.c_int32]),
     "nnms_assemble": (C.c_int, [vp, C.POINTER(kappa_t), C.c_double, vp, C.POINTER(vp)]),
+    "nnms_assemble_ex": (C.c_int, [vp, C.POINTER(assemble_opts_t), vp, C.POINTER(vp)]),
     "nnms_system_destroy": (C.c_int, [vp]),
     "nnms_system_device_bytes": (C.c_int64, [vp]),
     "nnms_system_rhs": (C.c_int, [vp, vp]),
@@ -369,10 +381,19 @@ class Hierarchy:
 
 
 def _kappa(kappa) -> tuple:
+    """kappa_t of a coefficient: None or kind 'const' (value), 'loggauss'
+    (centres, mu, width) or 'per_tet' (value = one array of per-tetrahedron
+    values per level); the arrays it points to are returned to be kept alive."""
     k = kappa_t()
     keep = []
-    if kappa is None or getattr(kappa, "kind", "const") == "const":
+    kind = "const" if kappa is None else getattr(kappa, "kind", "const")
+    if kind == "const":
         k.kind, k.value = 0, float(1.0 if kappa is None else kappa.value)
+    elif kind == "per_tet":
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in kappa.value]
+        ptrs = (C.POINTER(C.c_double) * len(arrs))(*[a.ctypes.data_as(C.POINTER(C.c_double)) for a in arrs])
+        keep = [arrs, ptrs]
+        k.kind, k.per_tet = 2, C.cast(ptrs, C.POINTER(C.POINTER(C.c_double)))
     else:
         c = np.ascontiguousarray(kappa.centres, dtype=np.float64).ravel()
         mu = np.ascontiguousarray(kappa.mu, dtype=np.float64)
@@ -383,13 +404,35 @@ def _kappa(kappa) -> tuple:
     return k, keep
 
 
-class System:
-    """assemble(mesh, kappa): nnms_assemble; operator applications; solve(b)."""
+def _rhs(f) -> tuple:
+    """rhs_t of a source term: a number (constant f) or an object with kind
+    'per_tet' (one value per finest-level tetrahedron) or 'nodal' (P1 nodal
+    values of the finest level) and `values`."""
+    r = rhs_t()
+    if isinstance(f, (int, float, np.floating)):
+        r.kind, r.value = 0, float(f)
+        return r, None
+    v = np.ascontiguousarray(f.values, dtype=np.float64)
+    r.kind = {"per_tet": 1, "nodal": 2}[f.kind]
+    r.values = v.ctypes.data_as(C.POINTER(C.c_double))
+    return r, v
 
-    def __init__(self, h: Hierarchy, kappa=None, f: float = 1.0, stream=None):
+
+class System:
+    """assemble(mesh, kappa): nnms_assemble_ex; operator applications; solve(b).
+
+    f: a constant or a load field (see _rhs); restart_cap: Krylov columns kept
+    (0 = the maximum); budget: device bytes the assembly may take (0 = no
+    limit; NNMSError BUDGET beyond)."""
+
+    def __init__(self, h: Hierarchy, kappa=None, f=1.0, stream=None, restart_cap: int = 0, budget: int = 0):
         k, keep = _kappa(kappa)
+        r, keep_r = _rhs(f)
+        o = assemble_opts_t()
+        o.kappa, o.rhs = C.pointer(k), C.pointer(r)
+        o.restart_cap, o.max_device_bytes = int(restart_cap), int(budget)
         s = C.c_void_p()
-        _check(_lib.nnms_assemble(h.handle, C.byref(k), float(f), _stream_ptr(stream), C.byref(s)))
+        _check(_lib.nnms_assemble_ex(h.handle, C.byref(o), _stream_ptr(stream), C.byref(s)))
         self.handle = s
         self.h = h
         self.n = [h.level_info(l).nv for l in range(h.L)]

@@ -45,6 +45,7 @@ class Request:
     x: Optional[np.ndarray] = None
     nbytes: int = 0
     error: str = ""
+    shared_steps: int = 0  # steps this request ran with at least one other request in the batch
 
 
 class DeviceEngine:
@@ -68,13 +69,14 @@ class DeviceEngine:
     def system_bytes(self, h, restart: int) -> int:
         return h.system_bytes(restart)
 
-    # numeric setup on the calling worker thread's own stream
-    def assemble(self, h, kappa, b):
+    # numeric setup on the calling worker thread's own stream, within the
+    # bytes admitted for it (the library refuses an assembly that needs more)
+    def assemble(self, h, kappa, b, restart: int, nbytes: int):
         with self._lock:
             if not hasattr(self._tls, "stream"):
                 self._tls.stream = self.streams[self._ix % len(self.streams)]
                 self._ix += 1
-        s = nnms.System(h, kappa, 1.0, stream=self._tls.stream)
+        s = nnms.System(h, kappa, 1.0, stream=self._tls.stream, restart_cap=restart, budget=nbytes)
         b = s.rhs() if b is None else np.asarray(b, dtype=np.float64)
         bd = self.torch.from_numpy(b).to("cuda")
         self.torch.cuda.current_stream().synchronize()
@@ -122,6 +124,7 @@ class Server:
         self.pool = ThreadPoolExecutor(max_workers=workers)
         self.batch_forms = 0
         self.steps = 0
+        self.max_active = 0  # most requests stepped together
         # host seconds spent in each part of the loop
         self.t_form = 0.0  # building and destroying batch plans, starting new slots
         self.t_create = 0.0  # of which: building plans
@@ -131,7 +134,7 @@ class Server:
         self.t_result = 0.0  # reading slot results, releasing finished systems
 
     def _assemble(self, req: Request):
-        return self.engine.assemble(self.h[req.key], req.kappa, req.b)
+        return self.engine.assemble(self.h[req.key], req.kappa, req.b, self.restart, req.nbytes)
 
     def run(self, requests: List[Request], log=None) -> dict:
         eng = self.engine
@@ -198,6 +201,10 @@ class Server:
             ts = time.perf_counter()
             eng.step(batch)
             self.steps += 1
+            self.max_active = max(self.max_active, len(active))
+            if len(active) > 1:
+                for m in active:
+                    m[0].shared_steps += 1
             tr = time.perf_counter()
             self.t_step += tr - ts
             finished, still = [], []

@@ -47,6 +47,9 @@ def test_serving_results_equal_alone(precision):
     st = srv.run(reqs)
     assert st["completed"] == 12 and st["rejected"] == 0
     assert srv.batch_forms >= 3
+    # requests really shared launch steps: the comparison below covers the mix
+    assert srv.max_active >= 2
+    assert sum(r.shared_steps > 0 for r in reqs) >= 4
     for r in reqs:
         s = nnms.System(hier[r.key], r.kappa)
         x, info = s.solve(s.rhs())

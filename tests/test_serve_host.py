@@ -41,7 +41,8 @@ class FakeEngine:
     def system_bytes(self, h, restart):
         return self.sizes[h]
 
-    def assemble(self, h, kappa, b):
+    def assemble(self, h, kappa, b, restart, nbytes):
+        assert nbytes == self.sizes[h]
         time.sleep(self.setup_s)
         s = _System(kappa, self.need[kappa])
         with self.lock:
