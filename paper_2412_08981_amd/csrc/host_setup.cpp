@@ -199,7 +199,14 @@ void build_partition(HostLevel& lv, int nparts, int overlap, bool direct) {
     lv.s_idx.insert(lv.s_idx.end(), cur.begin(), cur.end());
     lv.s_ptr[p + 1] = int64_t(lv.s_idx.size());
   }
-  // dense tiles, padded index map and extraction map
+  build_blocks(lv);
+}
+
+// Dense-factor bookkeeping of the level's subdomains (tile counts, factor
+// offsets, padded index maps with ownership, extraction map of every local
+// row's CSR entries), from the partition and the level's CSR.
+void build_blocks(HostLevel& lv) {
+  const int nparts = lv.nparts;
   lv.nblk.assign(nparts, 0);
   lv.fac_off.assign(nparts + 1, 0);
   lv.g_off.assign(nparts + 1, 0);
@@ -232,6 +239,122 @@ void build_partition(HostLevel& lv, int nparts, int overlap, bool direct) {
   }
   if (lv.ext_lc.size() > size_t(INT32_MAX)) throw Error(NNMS_ERR_INVALID_ARG, "subdomains too large");
   lv.ext_rs[lv.s_idx.size()] = int32_t(lv.ext_lc.size());
+}
+
+// ---------------------------------------------------------------------------
+// Field splitting (Section 3.2, equations field-split and interpolation
+// split).  A level of a problem with K unknowns per vertex (the three
+// displacement components of linear elasticity, numbered K v + c) is built
+// from the vertex-level structure: every field has one unknown per vertex, so
+// the pattern, the partition and the transfer of each field are those of
+// the vertices.  The pattern couples every component of a vertex with every
+// component of its neighbours (K x K blocks; a Dirichlet vertex keeps K
+// identity rows), the element gather map addresses the 4K x 4K element
+// matrices (row K a + c, column K b + d), a subdomain holds all components
+// of its vertices, and the interpolation sum_f R_f^T P R~_f keeps every
+// field apart: unknown K v + c takes P's row v applied to component c.
+// Vertex-level arrays that assembly reads (coordinates, elements, the
+// vertex -> element map) stay per vertex.
+// ---------------------------------------------------------------------------
+namespace {
+// CSR of A (x) I_K: row K r + c holds the entries (K col + c, val) of row r
+void kron_csr(const std::vector<int32_t>& rp, const std::vector<int32_t>& col, const std::vector<double>& val,
+              int64_t nrows, int K, std::vector<int32_t>& orp, std::vector<int32_t>& ocol, std::vector<double>& oval) {
+  orp.assign(nrows * K + 1, 0);
+  ocol.clear(), oval.clear();
+  ocol.reserve(col.size() * K), oval.reserve(col.size() * K);
+  for (int64_t r = 0; r < nrows; ++r)
+    for (int c = 0; c < K; ++c) {
+      for (int32_t e = rp[r]; e < rp[r + 1]; ++e) {
+        ocol.push_back(K * col[e] + c);
+        oval.push_back(val[e]);
+      }
+      orp[r * K + c + 1] = int32_t(ocol.size());
+    }
+}
+}  // namespace
+
+void expand_fields(HostLevel& lv, int K) {
+  lv.ncomp = K;
+  lv.nvert = lv.nv;
+  if (K == 1) return;
+  const int64_t nv = lv.nv;
+  if (nv * K > INT32_MAX / 2) throw Error(NNMS_ERR_INVALID_ARG, "level too large for 32-bit unknown ids");
+  const std::vector<uint8_t> vdir = lv.dir;
+  // pattern and element gather map
+  std::vector<int32_t> rp(nv * K + 1, 0), col, cptr(1, 0), citem;
+  col.reserve(lv.col.size() * K * K);
+  citem.reserve(lv.citem.size() * K * K);
+  for (int64_t i = 0; i < nv; ++i)
+    for (int c = 0; c < K; ++c) {
+      if (vdir[i]) {
+        col.push_back(int32_t(K * i + c));
+        cptr.push_back(int32_t(citem.size()));
+      } else {
+        for (int32_t s = lv.rp[i]; s < lv.rp[i + 1]; ++s)
+          for (int d = 0; d < K; ++d) {
+            col.push_back(K * lv.col[s] + d);
+            for (int32_t q = lv.cptr[s]; q < lv.cptr[s + 1]; ++q) {
+              const int32_t it = lv.citem[q], t = it >> 4, a = (it >> 2) & 3, b = it & 3;
+              citem.push_back(t * (16 * K * K) + (K * a + c) * (4 * K) + K * b + d);
+            }
+            cptr.push_back(int32_t(citem.size()));
+          }
+      }
+      rp[i * K + c + 1] = int32_t(col.size());
+    }
+  if (int64_t(lv.nt) * 16 * K * K > INT32_MAX) throw Error(NNMS_ERR_INVALID_ARG, "mesh too large for the element map");
+  lv.rp.swap(rp), lv.col.swap(col), lv.cptr.swap(cptr), lv.citem.swap(citem);
+  lv.dir.assign(nv * K, 0);
+  for (int64_t i = 0; i < nv; ++i)
+    for (int c = 0; c < K; ++c) lv.dir[i * K + c] = vdir[i];
+  lv.nv = nv * K;
+  lv.nint *= K;
+  build_sell(lv);
+  // partition: every component of a vertex with the vertex
+  std::vector<int32_t> owner(nv * K);
+  for (int64_t i = 0; i < nv; ++i)
+    for (int c = 0; c < K; ++c) owner[i * K + c] = lv.owner[i];
+  lv.owner.swap(owner);
+  std::vector<int32_t> sidx;
+  sidx.reserve(lv.s_idx.size() * K);
+  for (int32_t v : lv.s_idx)
+    for (int c = 0; c < K; ++c) sidx.push_back(K * v + c);
+  lv.s_idx.swap(sidx);
+  for (auto& p : lv.s_ptr) p *= K;
+  build_blocks(lv);
+  // transfers of every field (smoothed levels only)
+  if (lv.p_rp.empty()) return;
+  const int64_t nc = lv.ncoarse;
+  if (!lv.p_idx.empty()) {
+    std::vector<int32_t> idx(nv * K * 4);
+    std::vector<double> w(nv * K * 4);
+    for (int64_t v = 0; v < nv; ++v)
+      for (int c = 0; c < K; ++c)
+        for (int a = 0; a < 4; ++a) {
+          idx[(v * K + c) * 4 + a] = K * lv.p_idx[v * 4 + a] + c;
+          w[(v * K + c) * 4 + a] = lv.p_w[v * 4 + a];
+        }
+    lv.p_idx.swap(idx), lv.p_w.swap(w);
+  }
+  std::vector<int32_t> orp, ocol;
+  std::vector<double> oval;
+  kron_csr(lv.p_rp, lv.p_col, lv.p_val, nv, K, orp, ocol, oval);
+  lv.p_rp.swap(orp), lv.p_col.swap(ocol), lv.p_val.swap(oval);
+  kron_csr(lv.pt_rp, lv.pt_col, lv.pt_w, nc, K, orp, ocol, oval);
+  lv.pt_rp.swap(orp), lv.pt_col.swap(ocol), lv.pt_w.swap(oval);
+  lv.ncoarse = nc * K;
+  std::vector<int32_t> src;
+  build_sell_layout(lv.pt_rp, lv.pt_col, lv.ncoarse, lv.pts_off, lv.pts_col, src);
+  lv.pts_w.assign(src.size(), 0.0);
+  for (size_t e = 0; e < src.size(); ++e)
+    if (src[e] >= 0) lv.pts_w[e] = lv.pt_w[src[e]];
+  if (lv.transfer == NNMS_TRANSFER_MLS) {
+    build_sell_layout(lv.p_rp, lv.p_col, lv.nv, lv.pn_off, lv.pn_col, src);
+    lv.pn_w.assign(src.size(), 0.0);
+    for (size_t e = 0; e < src.size(); ++e)
+      if (src[e] >= 0) lv.pn_w[e] = -lv.p_val[src[e]];
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -26,7 +26,12 @@ void set_last_error(const std::string& msg);
 // Host structure of one level (built once per hierarchy).
 // ---------------------------------------------------------------------------
 struct HostLevel {
+  // nv: unknowns (rows of the level operator); nint: interior unknowns.  With
+  // ncomp unknowns per vertex (field splitting) nvert is the vertex count and
+  // nv = ncomp * nvert; per-vertex arrays: xyz, tets, vptr / vitem
   int64_t nv = 0, nt = 0, nint = 0;
+  int64_t nvert = 0;
+  int32_t ncomp = 1;
   std::vector<double> xyz;      // nv*3
   std::vector<int32_t> tets;    // nt*4
   std::vector<uint8_t> dir;     // nv
@@ -110,6 +115,11 @@ void build_sell_layout(const std::vector<int32_t>& rp, const std::vector<int32_t
                        std::vector<int32_t>& off, std::vector<int32_t>& scol, std::vector<int32_t>& src);
 void build_sell(HostLevel& lv);
 void build_partition(HostLevel& lv, int nparts, int overlap, bool direct);
+// dense-factor bookkeeping of the partition (called by build_partition)
+void build_blocks(HostLevel& lv);
+// field splitting: carries a vertex-level level (pattern, partition,
+// transfer to the next level) to K unknowns per vertex
+void expand_fields(HostLevel& lv, int K);
 void build_transfer(HostLevel& fine, const HostLevel& coarse);
 // moving-least-squares transfer (Section 3.2), initial scale alpha times the
 // mean coarse edge length; with mls_restrict the restriction is the MLS
