@@ -133,6 +133,44 @@ def cpu_baseline(pb, seconds_cap=60.0, mls_alpha=None):
     }, oh, res
 
 
+def cpu_baseline_extra():
+    """The oracle on the other workloads, bounded samples: the two-level 16^3
+    problem (setup, then the solve timed over 5 repeats) and one instance of
+    each of the two smallest fine sizes of the batched instances (24^3 and
+    32^3; the batch's larger instances take minutes each on the host)."""
+    import workloads as W
+    from oracle import problem as oprob
+
+    out = {}
+    pb = W.cube16_two_level()
+    oh = oprob.build(pb)
+    t = time.perf_counter()
+    for _ in range(5):
+        res = oprob.solve(oh)
+    out["cube16_two_level"] = {"solves_per_s": round(5 / (time.perf_counter() - t), 3), "iterations": res.iterations,
+                               "sample": "5 solves of the two-level 16^3/6^3 problem (kappa = 1, 8 subdomains)"}
+    probs = W.batched_instances(count=32)
+    picked, seen = [], set()
+    for i, p in enumerate(probs):
+        n = int(p.meshes[0].n)
+        if n in (24, 32) and n not in seen:
+            seen.add(n)
+            picked.append((i, p))
+    el, its = 0.0, []
+    for i, p in picked:
+        oh = oprob.build(p)
+        t = time.perf_counter()
+        res = oprob.solve(oh)
+        el += time.perf_counter() - t
+        its.append(res.iterations)
+    out["batched_instances_sample"] = {
+        "solves_per_s": round(len(picked) / el, 3), "iterations": its,
+        "sample": f"instances {[i for i, _ in picked]} of the 32 batched instances (fine n = "
+                  f"{[int(p.meshes[0].n) for _, p in picked]}), solved one after the other in FP64 (the oracle has no "
+                  "FP32 path); the full batch mixes in 40^3 to 64^3 instances, so its oracle rate is lower"}
+    return out
+
+
 def hierarchy_options(args, nnms):
     """Transfer and subdomain-solver keywords of nnms.Hierarchy from the
     command line, and a short description for the workload name."""
@@ -156,11 +194,11 @@ def smoother_bytes(h, level, s_bytes):
     return ras_bytes(h, level, s_bytes)
 
 
-def run_batched(args):
-    """Batched parametric instances of uneven mesh and subdomain sizes (fine
-    n in {24,32,40,48,64}, three non-nested levels each), mixed precision,
-    solved together in one launch sequence per Arnoldi step (HIP graph) vs
-    one after the other."""
+def batched_leg(args, steps):
+    """The batched instances (config of the batched workload) solved `steps`
+    times as one batch and once one after the other: (batched solves/s,
+    sequential solves/s, iterations, max relres, every batched result
+    bitwise equal to its solve alone, tuning, ms per batched solve)."""
     import torch
     import workloads as W
     from paper_2412_08981_amd import nnms
@@ -183,33 +221,48 @@ def run_batched(args):
         f"sizes {[int(pb.meshes[0].n) for pb in probs]}")
     xs, infos = nnms.solve_batch(ss, bs)  # warm-up (captures the graph)
     t = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         xs, infos = nnms.solve_batch(ss, bs)
-    el = (time.perf_counter() - t) / args.steps
+    el = (time.perf_counter() - t) / steps
     t = time.perf_counter()
     alone = [s.solve(b) for s, b in zip(ss, bs)]
     el_seq = time.perf_counter() - t
     same = all(np.array_equal(x, a[0]) for x, a in zip(xs, alone))
     its = [i.iterations for i in infos]
+    res = {"solves_per_s": len(ss) / el, "sequential_solves_per_s": len(ss) / el_seq, "iterations": its,
+           "max_relres": max(i.relres for i in infos), "bitwise_equal_alone": bool(same), "tuning": tuning,
+           "ms_per_batch": 1e3 * el, "count": len(ss), "desc": hdesc}
+    for s in ss:
+        s.destroy()
+    return res
+
+
+def run_batched(args):
+    """Batched parametric instances of uneven mesh and subdomain sizes (fine
+    n in {24,32,40,48,64}, three non-nested levels each), mixed precision,
+    solved together in one launch sequence per Arnoldi step (HIP graph) vs
+    one after the other."""
+    r = batched_leg(args, args.steps)
     out = {
         "metric": "solves/s to rel-res 1e-8 (batched)",
-        "value": round(len(ss) / el, 3),
+        "value": round(r["solves_per_s"], 3),
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": 1,
-        "ms_per_step": round(1e3 * el, 3),
+        "ms_per_step": round(r["ms_per_batch"], 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"{len(ss)} parametric instances, fine n in {{24,32,40,48,64}}, 3 non-nested levels, "
-                               "mixed precision, one batched launch sequence per Arnoldi step (HIP graph)" + hdesc,
-                   "sequential_solves_per_s": round(len(ss) / el_seq, 3),
-                   "batch_gain": round(el_seq / el, 3),
-                   "iterations": its, "max_relres": max(i.relres for i in infos),
-                   "batch_equals_alone_bitwise": bool(same), "tuning": tuning},
+        "config": {"workload": f"{r['count']} parametric instances, fine n in {{24,32,40,48,64}}, 3 non-nested "
+                               "levels, mixed precision, one batched launch sequence per Arnoldi step (HIP graph)"
+                               + r["desc"],
+                   "sequential_solves_per_s": round(r["sequential_solves_per_s"], 3),
+                   "batch_gain": round(r["solves_per_s"] / r["sequential_solves_per_s"], 3),
+                   "iterations": r["iterations"], "max_relres": r["max_relres"],
+                   "batch_equals_alone_bitwise": r["bitwise_equal_alone"], "tuning": r["tuning"]},
     }
     print(json.dumps(out))
 
@@ -344,6 +397,11 @@ def main():
     ap.add_argument("--subsolver", default="lu", choices=["lu", "ilu"],
                     help="subdomain solver of the smoother: dense LU or ILU(k)")
     ap.add_argument("--ilu-fill", default="2,0", help="ILU level of fill per smoothed level (finest first)")
+    ap.add_argument("--nparts", default="", metavar="P0[,P1]",
+                    help="default workload: subdomains per smoothed level (e.g. 64,64: the same count on every "
+                         "smoothed level, as the paper partitions every level)")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="default workload: skip the mixed-precision and batched legs")
     ap.add_argument("--kernels-only", action="store_true",
                     help="run the copy reference and the fine-level smoother a few times each (for counter runs)")
     args = ap.parse_args()
@@ -384,6 +442,9 @@ def main():
                        pb.kappa, precision=pb.precision)
         log(f"[bench] coarsened levels (Algorithm 1, rounds {rounds}): vertices "
             f"{[m.nv for m in coarsened]}, interior {[int((m.dirichlet == 0).sum()) for m in coarsened]}")
+    if args.nparts:
+        nps = [int(p) for p in args.nparts.split(",")]
+        pb = W.Problem(pb.name, pb.meshes, nps + pb.nparts[len(nps):], pb.kappa, precision=pb.precision)
     mls_mode = args.transfer == "mls"
     ilu_mode = args.subsolver == "ilu"
     ilu_fill = [int(k) for k in args.ilu_fill.split(",")]
@@ -480,6 +541,42 @@ def main():
     extra["host_buffer_solves_per_s"] = round(host_rate, 3)
     log(f"[bench] kernels: {extra}")
 
+    # the metric's other legs on the same problem and the batched instances
+    legs = {}
+    x_mixed = None
+    if not args.no_legs and not coarsened and args.precision == "fp64" and not mls_mode and not ilu_mode:
+        hm = nnms.Hierarchy(meshes, pb.nparts, overlap=pb.overlap, its=pb.its, precision=nnms.MIXED)
+        sm = nnms.System(hm, pb.kappa, 1.0)
+        tm = autotune.tune(sm, cache=args.tuning_cache)
+        xm = torch.zeros(n0, dtype=torch.float64, device="cuda")
+        for _ in range(args.warmup):
+            sm.solve_device(bd.data_ptr(), xm.data_ptr(), graph=graph)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            im = sm.solve_device(bd.data_ptr(), xm.data_ptr(), graph=graph)
+        torch.cuda.synchronize()
+        elm = time.perf_counter() - t
+        x_mixed = xm.cpu().numpy()
+        legs["mixed"] = {"workload": "the same 48^3/24^3/10^3 problem in mixed precision (FP32 subdomain factors, "
+                                     "smoothing and transfers; FP64 FGMRES, Arnoldi and coarsest LU)",
+                         "solves_per_s": round(args.steps / elm, 3), "ms_per_solve": round(1e3 * elm / args.steps, 3),
+                         "iterations": im.iterations, "relres": im.relres,
+                         "gain_over_fp64": round(el / elm, 3), "tuning": tm}
+        log(f"[bench] mixed leg: {legs['mixed']}")
+        sm.destroy()
+        del hm
+        b_r = batched_leg(args, 3)
+        legs["batched"] = {"workload": f"{b_r['count']} parametric instances, fine n in {{24,32,40,48,64}}, "
+                                       "3 non-nested levels each, mixed precision, one launch sequence per Arnoldi "
+                                       "step for all (HIP graph)",
+                           "solves_per_s": round(b_r["solves_per_s"], 3),
+                           "sequential_solves_per_s": round(b_r["sequential_solves_per_s"], 3),
+                           "batch_gain": round(b_r["solves_per_s"] / b_r["sequential_solves_per_s"], 3),
+                           "max_relres": b_r["max_relres"], "iterations_max": max(b_r["iterations"]),
+                           "batch_equals_alone_bitwise": b_r["bitwise_equal_alone"]}
+        log(f"[bench] batched leg: {legs['batched']}")
+
     x = xd.cpu().numpy()
     out = {
         "metric": "solves/s to rel-res 1e-8",
@@ -496,7 +593,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"jittered unit cube, 3 non-nested levels 48^3/24^3/10^3 "
                                f"(117649 fine vertices, 663552 tets), log-Gaussian kappa (8 centres), "
-                               f"64+8 subdomains overlap 1, FGMRES(30) to 1e-8, {args.precision}"
+                               f"{'+'.join(str(p) for p in pb.nparts)} subdomains overlap 1, FGMRES(30) to 1e-8, "
+                               f"{args.precision}"
                                + (f", MLS transfer (scale {args.mls_alpha} x mean coarse edge)" if mls_mode else "")
                                + (f", ILU({args.ilu_fill}) subdomain solves" if ilu_mode else "")
                                + (f", coarse levels by Algorithm 1 (rounds {rounds}; interior vertices "
@@ -512,6 +610,8 @@ def main():
                                 else "k_ras (fine-level smoother)"), "ms": round(ms, 4)},
         "kernels": extra,
     }
+    if legs:
+        out["legs"] = legs
     if not args.no_cpu_baseline:
         pb_o = pb
         if coarsened:
@@ -528,6 +628,10 @@ def main():
         xs = ores.x
         out["config"]["rel_err_vs_oracle_fgmres"] = float(np.linalg.norm(x - xs) / np.linalg.norm(xs))
         out["config"]["oracle_iterations"] = ores.iterations
+        if x_mixed is not None:
+            legs["mixed"]["rel_err_vs_oracle_fgmres"] = float(np.linalg.norm(x_mixed - xs) / np.linalg.norm(xs))
+        if legs:
+            cb["other_workloads"] = cpu_baseline_extra()
     print(json.dumps(out))
 
 
