@@ -366,6 +366,32 @@ nnms_status nnms_apply_restrict(nnms_system* s, int32_t level, const double* x_h
 nnms_status nnms_apply_vcycle(nnms_system* s, const double* r_host, double* z_host, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid allocation): nnms_apply_smoother on device vectors,
+ * allocating nothing.  The launch's tables (ticket, epoch and error words,
+ * subdomain or ILU descriptors, task list) go to a static array of
+ * NNMS_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends, instead
+ * of library-allocated memory; the level vectors and hand-off workspace
+ * are the system's own (allocated by its assembly).  Results are bitwise
+ * those of nnms_apply_smoother.
+ *
+ * r_dev, z_dev  device pointers, nv_level doubles each (r read, z written;
+ *               z is 0 at Dirichlet unknowns).
+ * Errors: NNMS_ERR_INVALID_ARG (null pointers, bad level, the calling
+ *         thread's current device is not the system's, or the level's
+ *         tables exceed the array: e.g. about 16,000 subdomains on one
+ *         level), NNMS_ERR_DEVICE (a HIP error or a triangular-solve wait
+ *         limit reached; the error word is cleared for later calls).
+ * Every call on one GPU shares that GPU's array and leaves it with the last
+ * call's tables: calls that overlap on one GPU (other streams or host
+ * threads) race and must be serialised by the caller.  The call synchronises
+ * `stream` to read the launch's error word.
+ * ------------------------------------------------------------------------- */
+#define NNMS_NOALLOC_SCRATCH_BYTES (1 << 20)
+nnms_status nnms_apply_smoother_noalloc(nnms_system* s, int32_t level, const double* r_dev, double* z_dev,
+                                        void* stream);
+
+/* ---------------------------------------------------------------------------
  * Measurement: run one kernel of the solve path `reps` times back to back on
  * the stream it is launched on, bracketed by HIP events, on the system's
  * current level vectors; *ms_host receives the mean milliseconds per

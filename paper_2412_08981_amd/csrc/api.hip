@@ -200,6 +200,7 @@ struct Plan;
 struct nnms_system {
   nnms_hierarchy* h = nullptr;
   int prec = NNMS_FP64;
+  int dev = -1;  // device the system was assembled on
   std::unique_ptr<Arena> mem;
   std::vector<SysLevel> lev;
   double* b0 = nullptr;  // assembled load vector
@@ -470,10 +471,10 @@ static std::vector<int32_t> ras_tasks(const std::vector<int32_t>& N, int K) {
 // The two smoother launches of level l over a set of systems (input r_l with
 // z written, input t_l with z added), for work items of K blocks; flags,
 // tasks and the ticket counter are allocated in `mem`.
-static void build_ras_pair(Arena& mem, std::vector<int32_t*>& counters, const std::vector<nnms_system*>& sys, int l,
-                           bool coarse, int prec, bool with_state, int K, hipStream_t s, RasLaunch& rr, RasLaunch& rt) {
-  std::vector<SubDesc> subs_r, subs_t;
-  std::vector<int32_t> Ns;
+// subdomain descriptors of level l over a set of systems: input r_l (subs_r)
+// and t_l (subs_t), and the block count of every subdomain
+static void ras_subdescs(const std::vector<nnms_system*>& sys, int l, bool coarse, int prec, bool with_state,
+                         std::vector<SubDesc>& subs_r, std::vector<SubDesc>& subs_t, std::vector<int32_t>& Ns) {
   for (auto* x : sys) {
     const HostLevel& hl = x->h->host.lev[l];
     if (!coarse && hl.subsolver == NNMS_SUBSOLVER_ILU)
@@ -497,6 +498,13 @@ static void build_ras_pair(Arena& mem, std::vector<int32_t*>& counters, const st
     }
   }
   if (subs_r.size() > 32767) throw Error(NNMS_ERR_INVALID_ARG, "too many subdomains in one batch");
+}
+
+static void build_ras_pair(Arena& mem, std::vector<int32_t*>& counters, const std::vector<nnms_system*>& sys, int l,
+                           bool coarse, int prec, bool with_state, int K, hipStream_t s, RasLaunch& rr, RasLaunch& rt) {
+  std::vector<SubDesc> subs_r, subs_t;
+  std::vector<int32_t> Ns;
+  ras_subdescs(sys, l, coarse, prec, with_state, subs_r, subs_t, Ns);
   std::vector<int32_t> tasks = ras_tasks(Ns, K);
   int32_t* counter = mem.alloc<int32_t>(4, s);
   HIP_CHECK(launch_ras_seed(counter, s));
@@ -1320,6 +1328,7 @@ extern "C" nnms_status nnms_assemble_ex(nnms_hierarchy* h, const nnms_assemble_o
   sys->h = h;
   h->systems++;
   sys->prec = prec;
+  HIP_CHECK(hipGetDevice(&sys->dev));
   sys->mem = std::make_unique<Arena>(h->has_alloc ? &h->alloc : nullptr);
   Arena& A = *sys->mem;
   sys->lev.resize(L);
@@ -1516,6 +1525,132 @@ extern "C" nnms_status nnms_apply_smoother(nnms_system* s, int32_t level, const 
   }
   get_vec(s, z, sl.z, n, P.stream);
   check_counters(P, P.stream);
+  return NNMS_OK;
+  ABI_END
+}
+
+// ---------------------------------------------------------------------------
+// smoother application for callers that cannot allocate device memory
+// ---------------------------------------------------------------------------
+// The tables of one smoother launch (counter words, subdomain or ILU
+// descriptors, task list) live in this file-scope array instead of memory the
+// library allocates: one copy per GPU, held until the process ends.  Host code
+// never uses the array's name as an address: each device's address comes
+// from hipGetSymbolAddress, with that device current, on its first use.
+static __device__ __align__(256) unsigned char scratch[NNMS_NOALLOC_SCRATCH_BYTES];
+
+namespace nnms {
+constexpr int kMaxDevices = 64;
+constexpr size_t kScratchTables = 256;  // offset of the descriptors (counter words first)
+struct ScratchTable {
+  std::mutex mu;
+  char* ptr[kMaxDevices] = {};
+};
+static ScratchTable& scratch_table() {
+  static ScratchTable* t = new ScratchTable();  // never destroyed: outlives every call
+  return *t;
+}
+
+// device address of this device's `scratch`; on the first call per device its
+// counter words are zeroed and given the first launch epoch
+static char* scratch_on(int dev, hipStream_t s) {
+  if (dev < 0 || dev >= kMaxDevices) throw Error(NNMS_ERR_INVALID_ARG, "device id out of range");
+  ScratchTable& T = scratch_table();
+  std::lock_guard<std::mutex> g(T.mu);
+  if (!T.ptr[dev]) {
+    void* p = nullptr;
+    HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    HIP_CHECK(launch_ras_seed((int32_t*)p, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    T.ptr[dev] = (char*)p;
+  }
+  return T.ptr[dev];
+}
+
+template <typename T>
+static void noalloc_smoother(nnms_system* s, int level, const double* r, double* z, hipStream_t st) {
+  const HostHierarchy& H = s->h->host;
+  const HostLevel& hl = H.lev[level];
+  const bool coarse = level == H.L - 1;
+  const bool ilu = !coarse && hl.subsolver == NNMS_SUBSOLVER_ILU;
+  SysLevel& sl = s->lev[level];
+  const int64_t n = hl.nv;
+  // host images of the launch's tables, sized against the scratch array
+  // before any device work
+  std::vector<SubDesc> subs, unused;
+  std::vector<IluDesc> ilus;
+  std::vector<int32_t> Ns, tasks;
+  const int K = s->h->tune.ras_blocks[level];
+  size_t desc_bytes = 0;
+  if (ilu) {
+    ilus = ilu_descs(*s, level, false);
+    desc_bytes = ilus.size() * sizeof(IluDesc);
+  } else {
+    ras_subdescs({s}, level, coarse, s->prec, false, subs, unused, Ns);
+    tasks = ras_tasks(Ns, K);
+    desc_bytes = subs.size() * sizeof(SubDesc);
+  }
+  const size_t task_off = kScratchTables + ((desc_bytes + 255) & ~size_t(255));
+  const size_t need = task_off + tasks.size() * sizeof(int32_t);
+  if (need > NNMS_NOALLOC_SCRATCH_BYTES)
+    throw Error(NNMS_ERR_INVALID_ARG, "the level's smoother tables need " + std::to_string(need) +
+                                          " bytes of scratch, the maximum is " +
+                                          std::to_string(size_t(NNMS_NOALLOC_SCRATCH_BYTES)));
+  char* sp = scratch_on(s->dev, st);
+  int32_t* counter = (int32_t*)sp;
+  // input in the level's working precision, output zeroed (Dirichlet rows stay 0)
+  if (std::is_same<T, double>::value)
+    HIP_CHECK(hipMemcpyAsync(sl.r, r, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  else
+    HIP_CHECK(launch_cast_d2f(r, (float*)sl.r, n, st));
+  HIP_CHECK(launch_fill<T>((T*)sl.z, n, T(0), st));
+  if (ilu) {
+    int maxn = 0;
+    for (const IluDesc& d : ilus) maxn = std::max(maxn, int(d.n));
+    HIP_CHECK(hipMemcpyAsync(sp + kScratchTables, ilus.data(), desc_bytes, hipMemcpyHostToDevice, st));
+    HIP_CHECK(launch_ilu_apply<T>((const IluDesc*)(sp + kScratchTables), int(ilus.size()), maxn, hl.ilu_lanes, 0, st));
+  } else {
+    HIP_CHECK(hipMemcpyAsync(sp + kScratchTables, subs.data(), desc_bytes, hipMemcpyHostToDevice, st));
+    HIP_CHECK(hipMemcpyAsync(sp + task_off, tasks.data(), tasks.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    RasLaunch rl{};
+    rl.subs = (const SubDesc*)(sp + kScratchTables);
+    rl.tasks = (const int32_t*)(sp + task_off);
+    rl.counter = counter;
+    rl.ntasks = int(tasks.size());
+    rl.add = 0;
+    rl.group = K;
+    const int g = s->h->tune.ras_groups[level];
+    if (coarse)
+      HIP_CHECK((launch_ras<double, T>(rl, g > 0 ? g : ras_grid_default(), st)));
+    else
+      HIP_CHECK((launch_ras<T, T>(rl, g > 0 ? g : ras_grid_default(), st)));
+  }
+  if (std::is_same<T, double>::value)
+    HIP_CHECK(hipMemcpyAsync(z, sl.z, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  else
+    HIP_CHECK(launch_cast_f2d((const float*)sl.z, z, n, st));
+  int32_t werr = 0;
+  HIP_CHECK(hipMemcpyAsync(&werr, counter + 2, sizeof werr, hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  if (werr) {
+    HIP_CHECK(launch_ras_seed(counter, st));  // clears the error word for later calls
+    HIP_CHECK(hipStreamSynchronize(st));
+    throw Error(NNMS_ERR_DEVICE, "triangular-solve wait limit exceeded (error bits " + std::to_string(werr) + ")");
+  }
+}
+}  // namespace nnms
+
+extern "C" nnms_status nnms_apply_smoother_noalloc(nnms_system* s, int32_t level, const double* r_dev, double* z_dev,
+                                                   void* stream) {
+  ABI_BEGIN
+  if (!s || !r_dev || !z_dev || level < 0 || level >= s->h->host.L) throw Error(NNMS_ERR_INVALID_ARG, "bad arguments");
+  int dev = -1;
+  HIP_CHECK(hipGetDevice(&dev));
+  if (dev != s->dev) throw Error(NNMS_ERR_INVALID_ARG, "the current device is not the system's");
+  if (s->prec == NNMS_FP64)
+    noalloc_smoother<double>(s, level, r_dev, z_dev, (hipStream_t)stream);
+  else
+    noalloc_smoother<float>(s, level, r_dev, z_dev, (hipStream_t)stream);
   return NNMS_OK;
   ABI_END
 }

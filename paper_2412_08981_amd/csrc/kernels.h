@@ -31,8 +31,8 @@ hipError_t launch_read16(const void* a, int64_t bytes, int* out, int grid, hipSt
 // scatter fused.  F = factor precision, V = vector precision.
 template <typename F, typename V>
 hipError_t launch_ras(const RasLaunch& p, int grid, hipStream_t s);
-// gives a new counter array of launch_ras (4 words, zeroed) the epoch of its
-// first launch; every launch leaves the next one's
+// readies a counter array of launch_ras (4 words): ticket and error words
+// zeroed, the epoch of its next launch set; every launch leaves the next one's
 hipError_t launch_ras_seed(int32_t* counter, hipStream_t s);
 
 // lu.hip

@@ -149,6 +149,7 @@ _sig = {
     "nnms_apply_prolong": (C.c_int, [vp, C.c_int32, vp, vp, vp]),
     "nnms_apply_restrict": (C.c_int, [vp, C.c_int32, vp, vp, vp]),
     "nnms_apply_vcycle": (C.c_int, [vp, vp, vp, vp]),
+    "nnms_apply_smoother_noalloc": (C.c_int, [vp, C.c_int32, vp, vp, vp]),
     "nnms_solve_opts_default": (C.c_int, [C.POINTER(solve_opts)]),
     "nnms_solve": (C.c_int, [vp, vp, vp, C.POINTER(solve_opts), C.POINTER(solve_info), vp]),
     "nnms_solve_batch": (C.c_int, [vp, C.c_int32, vp, vp, C.POINTER(solve_opts), C.POINTER(solve_info), vp]),
@@ -478,6 +479,11 @@ class System:
 
     def apply_vcycle(self, r):
         return self._apply(_lib.nnms_apply_vcycle, None, r, self.n[0])
+
+    def apply_smoother_noalloc(self, level: int, r_ptr: int, z_ptr: int, stream=None):
+        """nnms_apply_smoother_noalloc on device pointers (nv_level doubles each)."""
+        _check(_lib.nnms_apply_smoother_noalloc(self.handle, level, C.c_void_p(r_ptr), C.c_void_p(z_ptr),
+                                                _stream_ptr(stream)))
 
     def factor(self, level: int, part: int):
         """Stored factor tiles of one subdomain: (grid (N*64)^2, inv(L_ii) tiles [N,64,64])."""
