@@ -74,7 +74,7 @@ def ilu_bytes(h, level, s_bytes):
     positions, level orders and index map of every row, the gathered input
     and the scattered owned output."""
     li = h.level_info(level)
-    return float(li.ilu_nnz * (s_bytes + 4) + li.s_total * (4 * 5 + s_bytes) + li.ninterior * s_bytes)
+    return float(li.ilu_nnz * (s_bytes + 4) + li.s_total * (4 * 5 + s_bytes) + li.ninterior * li.ncomp * s_bytes)
 
 
 def lu_flops(h, level):
@@ -87,7 +87,7 @@ def lu_flops(h, level):
 
 def spmv_bytes(h, level, s_bytes):
     li = h.level_info(level)
-    return float(li.nnz * (4 + s_bytes) + 4 * (li.nv + 1) + 3 * li.nv * s_bytes)
+    return float(li.nnz * (4 + s_bytes) + 4 * (li.ndof + 1) + 3 * li.ndof * s_bytes)
 
 
 def prolong_bytes(h, level, s_bytes):
@@ -97,7 +97,7 @@ def prolong_bytes(h, level, s_bytes):
     from paper_2412_08981_amd import nnms
 
     li, lc = h.level_info(level), h.level_info(level + 1)
-    nf, nc = li.nv, lc.nv
+    nf, nc = li.ndof, lc.ndof
     if li.transfer == nnms.MLS:
         return float(li.p_nnz * (4 + s_bytes) + nc * s_bytes + 2 * nf * s_bytes)
     return float(nf * (16 + 4 * s_bytes) + nc * s_bytes + 2 * nf * s_bytes)
@@ -106,12 +106,13 @@ def prolong_bytes(h, level, s_bytes):
 def restrict_bytes(h, level, s_bytes):
     """r_c = P^T t: the CSR of P^T over coarse rows, t once, r_c written."""
     li, lc = h.level_info(level), h.level_info(level + 1)
-    return float(li.r_nnz * (4 + s_bytes) + 4 * (lc.nv + 1) + (li.nv + lc.nv) * s_bytes)
+    return float(li.r_nnz * (4 + s_bytes) + 4 * (lc.ndof + 1) + (li.ndof + lc.ndof) * s_bytes)
 
 
-def cpu_baseline(pb, seconds_cap=60.0, mls_alpha=None):
+def cpu_baseline(pb, seconds_cap=60.0, mls_alpha=None, elasticity=False):
     """The FP64 oracle (NumPy/SciPy, LAPACK) on the host cores: setup once,
     then one full solve of the same problem; solves/s = 1 / solve time."""
+    import workloads as W
     from oracle import problem as oprob
     try:
         from threadpoolctl import threadpool_info
@@ -119,7 +120,11 @@ def cpu_baseline(pb, seconds_cap=60.0, mls_alpha=None):
     except Exception:
         threads = os.cpu_count() or 1
     t0 = time.perf_counter()
-    oh = oprob.build(pb, mls_alpha=mls_alpha)
+    if elasticity:
+        from oracle import elasticity as oel
+        oh = oel.build(pb, nu=W.ELASTIC_NU, f=W.ELASTIC_FORCE)
+    else:
+        oh = oprob.build(pb, mls_alpha=mls_alpha)
     t1 = time.perf_counter()
     res = oprob.solve(oh)
     t2 = time.perf_counter()
@@ -128,7 +133,7 @@ def cpu_baseline(pb, seconds_cap=60.0, mls_alpha=None):
         "unit": "solves/s",
         "cores": int(threads),
         "kind": "oracle",
-        "sample": f"one full solve ({res.iterations} FGMRES iterations) of the same 48^3/24^3/10^3 problem after "
+        "sample": f"one full solve ({res.iterations} FGMRES iterations) of the same problem ({pb.name}) after "
                   f"the oracle's setup ({t1 - t0:.1f} s, not counted)",
     }, oh, res
 
@@ -397,6 +402,9 @@ def main():
     ap.add_argument("--subsolver", default="lu", choices=["lu", "ilu"],
                     help="subdomain solver of the smoother: dense LU or ILU(k)")
     ap.add_argument("--ilu-fill", default="2,0", help="ILU level of fill per smoothed level (finest first)")
+    ap.add_argument("--physics", default="poisson", choices=["poisson", "elasticity"],
+                    help="default workload: the scalar 48^3 problem, or P1 linear elasticity (three unknowns per "
+                         "vertex, field-split transfers) on 32^3/16^3/7^3 meshes")
     ap.add_argument("--nparts", default="", metavar="P0[,P1]",
                     help="default workload: subdomains per smoothed level (e.g. 64,64: the same count on every "
                          "smoothed level, as the paper partitions every level)")
@@ -420,7 +428,8 @@ def main():
         return run_batched(args)
     if args.workload == "serving":
         return run_serving(args)
-    pb = W.cube48_three_level(args.precision)
+    elastic = args.physics == "elasticity"
+    pb = W.cube32_elasticity(args.precision) if elastic else W.cube48_three_level(args.precision)
     prec = nnms.MIXED if args.precision == "mixed" else nnms.FP64
     t0 = time.perf_counter()
     meshes = [nnms.Mesh.from_workload(m) for m in pb.meshes]
@@ -450,9 +459,14 @@ def main():
     ilu_fill = [int(k) for k in args.ilu_fill.split(",")]
     h = nnms.Hierarchy(meshes, pb.nparts, overlap=pb.overlap, its=pb.its, precision=prec,
                        transfer=nnms.MLS if mls_mode else nnms.BARYCENTRIC, mls_alpha=args.mls_alpha,
-                       subsolver=nnms.ILU if ilu_mode else nnms.LU, ilu_fill=ilu_fill)
+                       subsolver=nnms.ILU if ilu_mode else nnms.LU, ilu_fill=ilu_fill, ncomp=3 if elastic else 1)
     t1 = time.perf_counter()
-    s = nnms.System(h, pb.kappa, 1.0)
+    load = W.ELASTIC_FORCE if elastic else 1.0
+
+    def assemble(kappa):
+        return nnms.System(h, kappa, load, poisson_ratio=W.ELASTIC_NU)
+
+    s = assemble(pb.kappa)
     t2 = time.perf_counter()
     log(f"[bench] structure setup {t1 - t0:.2f} s, numeric setup (assembly + LU) {t2 - t1:.3f} s")
     from paper_2412_08981_amd import autotune
@@ -500,7 +514,7 @@ def main():
 
     # numeric setup per parameter (assembly + extraction + LU), timed separately
     tp = time.perf_counter()
-    s2 = nnms.System(h, W.kappa_draw(204, 999), 1.0)
+    s2 = assemble(W.kappa_draw(204, 999))
     torch.cuda.synchronize()
     t_assemble = time.perf_counter() - tp
     s2.destroy()
@@ -544,7 +558,8 @@ def main():
     # the metric's other legs on the same problem and the batched instances
     legs = {}
     x_mixed = None
-    if not args.no_legs and not coarsened and args.precision == "fp64" and not mls_mode and not ilu_mode:
+    if (not args.no_legs and not coarsened and args.precision == "fp64" and not mls_mode and not ilu_mode
+            and not elastic and not args.nparts):
         hm = nnms.Hierarchy(meshes, pb.nparts, overlap=pb.overlap, its=pb.its, precision=nnms.MIXED)
         sm = nnms.System(hm, pb.kappa, 1.0)
         tm = autotune.tune(sm, cache=args.tuning_cache)
@@ -591,9 +606,13 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if prec == nnms.FP64 else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"jittered unit cube, 3 non-nested levels 48^3/24^3/10^3 "
-                               f"(117649 fine vertices, 663552 tets), log-Gaussian kappa (8 centres), "
-                               f"{'+'.join(str(p) for p in pb.nparts)} subdomains overlap 1, FGMRES(30) to 1e-8, "
+        "config": {"workload": (f"P1 linear elasticity (three unknowns per vertex, field-split transfers), "
+                                f"jittered unit cube, 3 non-nested levels 32^3/16^3/7^3 (35937 fine vertices, "
+                                f"107811 unknowns), Young's modulus from the log-Gaussian field, Poisson's ratio "
+                                f"{W.ELASTIC_NU}, body force {W.ELASTIC_FORCE}, " if elastic else
+                                f"jittered unit cube, 3 non-nested levels 48^3/24^3/10^3 "
+                                f"(117649 fine vertices, 663552 tets), log-Gaussian kappa (8 centres), ")
+                               + f"{'+'.join(str(p) for p in pb.nparts)} subdomains overlap 1, FGMRES(30) to 1e-8, "
                                f"{args.precision}"
                                + (f", MLS transfer (scale {args.mls_alpha} x mean coarse edge)" if mls_mode else "")
                                + (f", ILU({args.ilu_fill}) subdomain solves" if ilu_mode else "")
@@ -622,7 +641,7 @@ def main():
                 r = ocoarsen.coarsen(om[-1].xyz, om[-1].tets, om[-1].dirichlet, rounds[l - 1], l)
                 om.append(W.Mesh(r.xyz, r.tets.astype(np.int32), r.dirichlet, 0))
             pb_o = W.Problem(pb.name, om, pb.nparts, pb.kappa, precision=pb.precision)
-        cb, oh, ores = cpu_baseline(pb_o, mls_alpha=args.mls_alpha if mls_mode else None)
+        cb, oh, ores = cpu_baseline(pb_o, mls_alpha=args.mls_alpha if mls_mode else None, elasticity=elastic)
         out["cpu_baseline"] = cb
         from oracle import problem as oprob  # the oracle's own x* for the error report
         xs = ores.x

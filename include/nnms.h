@@ -147,6 +147,17 @@ void nnms_mesh_destroy(nnms_mesh* m);
  * Errors: NNMS_ERR_INVALID_ARG, NNMS_ERR_POINT_LOCATION (a fine vertex
  *         outside the coarse mesh, or no full-rank MLS neighbourhood),
  *         NNMS_ERR_OUT_OF_MEMORY, NNMS_ERR_DEVICE.
+ *             ncomp = 3 (multi-field problems by field splitting, Section
+ *             3.2, equations field-split and interpolation split): P1 linear
+ *             elasticity (Section 4.2's stress law) with the three
+ *             displacement components of vertex v as unknowns 3v, 3v+1, 3v+2
+ *             (all three Dirichlet on a Dirichlet vertex).  Every component
+ *             is a field with one unknown per vertex: the pattern couples all
+ *             components of neighbouring vertices, a subdomain holds all
+ *             components of its vertices (the vertex partition), and the
+ *             interpolation sum_f R_f^T P_l R~_f moves each component with the
+ *             scalar P_l (barycentric or MLS).  nparts[l] = 0 then selects
+ *             max(2, 2^floor(log2(3 nv_l / 1500))).
  * nnms_hierarchy_setup_host builds the same structure without touching any
  * GPU (inspection and host tests); such a handle cannot be assembled.
  * ------------------------------------------------------------------------- */
@@ -161,6 +172,8 @@ typedef struct {
   int32_t ilu_fill[NNMS_MAX_LEVELS]; /* ILU level of fill per smoothed level (>= 0) */
   int32_t mls_restrict; /* with MLS: 1 = restrict by the MLS interpolation from
                            the fine to the coarse nodes, 0 = by P_l^T */
+  int32_t ncomp;        /* unknowns per vertex: 1 = -div(kappa grad u) = f (default);
+                           3 = P1 linear elasticity, see below */
 } nnms_setup_opts;
 
 /* Geometry-preserving coarsening (Algorithm 1, Section 3.1): `rounds`
@@ -205,6 +218,11 @@ typedef struct {
   int32_t mls_restrict; /* 1: the restriction is the fine-to-coarse MLS operator */
   int64_t ilu_nnz;      /* entries of all ILU patterns of the level (0 without ILU) */
   int64_t r_nnz;        /* entries of the restriction (P_l^T or the MLS operator) */
+  int32_t ncomp;        /* unknowns per vertex */
+  int32_t reserved;
+  int64_t ndof;         /* unknowns of the level = ncomp * nv: the length of the
+                           level's vectors and the rows of every per-row array
+                           below (CSR, owner, P_l, ...) */
 } nnms_level_info;
 
 nnms_status nnms_hierarchy_level_info(const nnms_hierarchy* h, int32_t level, nnms_level_info* out);
@@ -266,6 +284,10 @@ nnms_status nnms_hierarchy_ilu_pattern(const nnms_hierarchy* h, int32_t level, i
  *           element mass matrix |T| (1 + delta_ab) / 20: b_i =
  *           sum_{T at i} |T| / 20 (f_i + sum_{a in T} f_a).
  *   Values must be finite.  Entries of Dirichlet vertices are 0.
+ *   ncomp = 3 (linear elasticity, E_T = kappa_T, Poisson's ratio from the
+ *   options): f is a body force, every component loaded as above: kind 0
+ *   takes vector[0..2], kind 1 three values per tetrahedron (x, y, z), kind 2
+ *   the nodal values in the unknowns' order (3v + c).
  * Errors: NNMS_ERR_INVALID_ARG (a bad kind, size or value: before any device
  *         work), NNMS_ERR_BUDGET, NNMS_ERR_SINGULAR, NNMS_ERR_OUT_OF_MEMORY,
  *         NNMS_ERR_DEVICE.
@@ -284,7 +306,8 @@ typedef struct {
   int32_t kind;
   int32_t reserved;
   double value;          /* kind 0 */
-  const double* values;  /* kind 1: nt_0 doubles; kind 2: nv_0 doubles */
+  const double* values;  /* kind 1: nt_0 * ncomp doubles; kind 2: ndof_0 doubles */
+  double vector[3];      /* kind 0 with ncomp = 3: the constant body force */
 } nnms_rhs;
 
 /* restart_cap  Krylov basis columns kept with the system for its solves
@@ -294,16 +317,20 @@ typedef struct {
  *              assembly is refused with NNMS_ERR_BUDGET, before any device
  *              work, when nnms_hierarchy_system_bytes(h, restart_cap) (the
  *              peak of any assembly of h) exceeds it.  0: no limit. */
+/* poisson_ratio  ncomp = 3: nu in [0, 0.5); the Lame coefficients are
+ *              mu = E / (2 (1 + nu)), lambda = E nu / ((1 + nu)(1 - 2 nu)). */
 typedef struct {
   const nnms_kappa* kappa; /* required */
-  const nnms_rhs* rhs;     /* NULL: f = 1 */
+  const nnms_rhs* rhs;     /* NULL: f = 1 (every component for ncomp = 3) */
   int32_t restart_cap;
   int32_t reserved;
   int64_t max_device_bytes;
+  double poisson_ratio;
 } nnms_assemble_opts;
 
 nnms_status nnms_assemble_ex(nnms_hierarchy* h, const nnms_assemble_opts* opts, void* stream, nnms_system** out);
-/* The same with a constant load f, restart_cap NNMS_MAX_RESTART and no budget. */
+/* The same with a constant load f (each component for ncomp = 3, Poisson's
+ * ratio 0.3), restart_cap NNMS_MAX_RESTART and no budget. */
 nnms_status nnms_assemble(nnms_hierarchy* h, const nnms_kappa* kappa, double f, void* stream, nnms_system** out);
 nnms_status nnms_system_destroy(nnms_system* s);
 /* Device bytes held by one assembled system (values, factors, workspace). */

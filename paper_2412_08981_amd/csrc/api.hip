@@ -887,10 +887,13 @@ static void build_host(const nnms_mesh* const* levels, int32_t L, const nnms_set
   if (opts->overlap < 0 || opts->its < 1 || (opts->precision != NNMS_FP64 && opts->precision != NNMS_MIXED) ||
       (opts->transfer != NNMS_TRANSFER_BARYCENTRIC && opts->transfer != NNMS_TRANSFER_MLS) ||
       (opts->transfer == NNMS_TRANSFER_MLS && !(opts->mls_alpha > 0)) ||
-      (opts->subsolver != NNMS_SUBSOLVER_LU && opts->subsolver != NNMS_SUBSOLVER_ILU))
+      (opts->subsolver != NNMS_SUBSOLVER_LU && opts->subsolver != NNMS_SUBSOLVER_ILU) ||
+      (opts->ncomp != 0 && opts->ncomp != 1 && opts->ncomp != 3))
     throw Error(NNMS_ERR_INVALID_ARG, "bad setup options");
+  const int K = opts->ncomp ? opts->ncomp : 1;
   H.L = L;
   H.opts = *opts;
+  H.opts.ncomp = K;
   H.lev.resize(L);
   for (int l = 0; l < L; ++l) {
     if (!levels[l]) throw Error(NNMS_ERR_INVALID_ARG, "null mesh");
@@ -903,10 +906,22 @@ static void build_host(const nnms_mesh* const* levels, int32_t L, const nnms_set
     build_sell(lv);
     const bool direct = (l == L - 1);
     int np = direct ? 1 : opts->nparts[l];
-    if (!direct && np == 0) np = default_nparts(lv.nv);
+    if (!direct && np == 0) np = default_nparts(lv.nv * K);
     H.opts.nparts[l] = np;
     build_partition(lv, np, opts->overlap, direct);
-    if (!direct && opts->subsolver == NNMS_SUBSOLVER_ILU) {
+  }
+  // transfers between the vertex-level meshes, then every level carried to
+  // K unknowns per vertex (field splitting: each component is a field)
+  for (int l = 0; l + 1 < L; ++l) {
+    if (opts->transfer == NNMS_TRANSFER_MLS)
+      build_transfer_mls(H.lev[l], H.lev[l + 1], opts->mls_alpha, opts->mls_restrict != 0);
+    else
+      build_transfer(H.lev[l], H.lev[l + 1]);
+  }
+  for (int l = 0; l < L; ++l) expand_fields(H.lev[l], K);
+  for (int l = 0; l + 1 < L; ++l) {
+    HostLevel& lv = H.lev[l];
+    if (opts->subsolver == NNMS_SUBSOLVER_ILU) {
       if (opts->ilu_fill[l] < 0) throw Error(NNMS_ERR_INVALID_ARG, "ILU fill level must be >= 0");
       const size_t vsz = opts->precision == NNMS_FP64 ? sizeof(double) : sizeof(float);
       for (int p = 0; p < lv.nparts; ++p)
@@ -915,12 +930,6 @@ static void build_host(const nnms_mesh* const* levels, int32_t L, const nnms_set
                                                 std::to_string(lv.s_ptr[p + 1] - lv.s_ptr[p]) + " rows)");
       build_ilu(lv, opts->ilu_fill[l]);
     }
-  }
-  for (int l = 0; l + 1 < L; ++l) {
-    if (opts->transfer == NNMS_TRANSFER_MLS)
-      build_transfer_mls(H.lev[l], H.lev[l + 1], opts->mls_alpha, opts->mls_restrict != 0);
-    else
-      build_transfer(H.lev[l], H.lev[l + 1]);
   }
 }
 
@@ -1028,7 +1037,8 @@ extern "C" nnms_status nnms_hierarchy_level_info(const nnms_hierarchy* h, int32_
   if (!h || !o || level < 0 || level >= h->host.L) throw Error(NNMS_ERR_INVALID_ARG, "bad level");
   const HostLevel& lv = h->host.lev[level];
   std::memset(o, 0, sizeof *o);
-  o->nv = lv.nv, o->nt = lv.nt, o->ninterior = lv.nint, o->nnz = int64_t(lv.col.size());
+  o->nv = lv.nvert, o->nt = lv.nt, o->ninterior = lv.nint / lv.ncomp, o->nnz = int64_t(lv.col.size());
+  o->ncomp = lv.ncomp, o->ndof = lv.nv;
   o->nparts = lv.nparts;
   int mx = 0, mn = INT32_MAX;
   for (int p = 0; p < lv.nparts; ++p) {
@@ -1132,7 +1142,8 @@ static SysLayout system_layout(const HostHierarchy& H, int prec, int cap, int ka
   auto T = [&](int64_t b) { o.transient += round256(b); };
   int64_t max_nt = 0;
   for (int l = 0; l < H.L; ++l) max_nt = std::max(max_nt, H.lev[l].nt);
-  T(max_nt * 17 * 8);  // element matrices and volumes
+  const int64_t K = H.opts.ncomp;
+  T(max_nt * (16 * K * K + 1) * 8);  // element matrices and volumes
   T(sizeof(int));      // pivot error flag
   const int64_t tsz = prec == NNMS_FP64 ? 8 : 4;
   for (int l = 0; l < H.L; ++l) {
@@ -1156,7 +1167,7 @@ static SysLayout system_layout(const HostHierarchy& H, int prec, int cap, int ka
     if (kappa_kind == 2) T(lv.nt * 8);
   }
   const int64_t n0 = H.lev[0].nv, nt0 = H.lev[0].nt;
-  if (rhs_kind == 1) T(nt0 * 8);
+  if (rhs_kind == 1) T(nt0 * K * 8);
   if (rhs_kind == 2) T(n0 * 8);
   const int64_t nblk = (n0 + VBLK - 1) / VBLK, nblkr = (n0 + 3) / 4;
   R(n0 * (cap + 1) * 8), R(n0 * cap * 8);  // Krylov bases V, Z
@@ -1171,7 +1182,7 @@ extern "C" int64_t nnms_hierarchy_system_bytes(const nnms_hierarchy* h, int32_t 
   const HostHierarchy& H = h->host;
   // the larger of the two per-element-array choices of the load: per tetrahedron
   const SysLayout o = system_layout(H, H.opts.precision, restart ? restart : NNMS_MAX_RESTART, 2,
-                                    H.lev[0].nt >= H.lev[0].nv ? 1 : 2);
+                                    H.lev[0].nt * H.opts.ncomp >= H.lev[0].nv ? 1 : 2);
   return o.resident + o.transient;
 }
 
@@ -1308,12 +1319,17 @@ extern "C" nnms_status nnms_assemble_ex(nnms_hierarchy* h, const nnms_assemble_o
   if (rhs.kind == 0) {
     if (!std::isfinite(rhs.value)) throw Error(NNMS_ERR_INVALID_ARG, "the load must be finite");
   } else if (rhs.kind == 1 || rhs.kind == 2) {
-    const int64_t n = rhs.kind == 1 ? H.lev[0].nt : H.lev[0].nv;
+    const int64_t n = rhs.kind == 1 ? H.lev[0].nt * H.opts.ncomp : H.lev[0].nv;
     if (!rhs.values || !all_finite(rhs.values, n, false))
       throw Error(NNMS_ERR_INVALID_ARG, "load values missing or not finite");
   } else {
     throw Error(NNMS_ERR_INVALID_ARG, "unknown load kind");
   }
+  const int K = H.opts.ncomp;
+  if (K == 3 && !(o->poisson_ratio >= 0.0 && o->poisson_ratio < 0.5))
+    throw Error(NNMS_ERR_INVALID_ARG, "Poisson's ratio must lie in [0, 0.5)");
+  if (rhs.kind == 0 && K == 3 && !all_finite(rhs.vector, 3, false))
+    throw Error(NNMS_ERR_INVALID_ARG, "the body force must be finite");
   const int cap = o->restart_cap ? o->restart_cap : NNMS_MAX_RESTART;
   if (cap < 1 || cap > NNMS_MAX_RESTART) throw Error(NNMS_ERR_INVALID_ARG, "restart_cap out of range");
   if (o->max_device_bytes < 0) throw Error(NNMS_ERR_INVALID_ARG, "negative device-memory budget");
@@ -1336,11 +1352,11 @@ extern "C" nnms_status nnms_assemble_ex(nnms_hierarchy* h, const nnms_assemble_o
   int64_t max_nt = 0;
   for (int l = 0; l < L; ++l) max_nt = std::max(max_nt, H.lev[l].nt);
   Arena scratch(h->has_alloc ? &h->alloc : nullptr);
-  double* elem = scratch.alloc<double>(size_t(max_nt) * 17, s, false);
+  double* elem = scratch.alloc<double>(size_t(max_nt) * (16 * K * K + 1), s, false);
   int* err = scratch.alloc<int>(1, s);
   const double* fval = nullptr;
   if (rhs.kind != 0) {
-    const int64_t n = rhs.kind == 1 ? H.lev[0].nt : H.lev[0].nv;
+    const int64_t n = rhs.kind == 1 ? H.lev[0].nt * K : H.lev[0].nv;
     fval = scratch.upload(std::vector<double>(rhs.values, rhs.values + n), s);
   }
   for (int l = 0; l < L; ++l) {
@@ -1370,6 +1386,8 @@ extern "C" nnms_status nnms_assemble_ex(nnms_hierarchy* h, const nnms_assemble_o
     ad.xyz = dl.xyz, ad.tets = dl.tets, ad.cptr = dl.cptr, ad.citem = dl.citem, ad.rp = dl.rp;
     ad.vptr = dl.vptr, ad.vitem = dl.vitem, ad.dmask = dl.dmask, ad.elem = elem;
     ad.val64 = sl.val64, ad.val32 = sl.val32, ad.nt = hl.nt, ad.nv = hl.nv;
+    ad.ncomp = K, ad.nu = o->poisson_ratio;
+    for (int c = 0; c < 3; ++c) ad.fvec[c] = rhs.vector[c];
     if (k->kind == 2) ad.kappa_tet = scratch.upload(std::vector<double>(k->per_tet[l], k->per_tet[l] + hl.nt), s);
     if (l == 0) {
       sys->b0 = A.alloc<double>(hl.nv, s, false);
@@ -1421,8 +1439,9 @@ extern "C" nnms_status nnms_assemble_ex(nnms_hierarchy* h, const nnms_assemble_o
 extern "C" nnms_status nnms_assemble(nnms_hierarchy* h, const nnms_kappa* k, double f, void* stream, nnms_system** out) {
   nnms_rhs rhs{};
   rhs.kind = 0, rhs.value = f;
+  rhs.vector[0] = rhs.vector[1] = rhs.vector[2] = f;
   nnms_assemble_opts o{};
-  o.kappa = k, o.rhs = &rhs;
+  o.kappa = k, o.rhs = &rhs, o.poisson_ratio = 0.3;
   return nnms_assemble_ex(h, &o, stream, out);
 }
 

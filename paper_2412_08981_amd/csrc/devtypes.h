@@ -151,16 +151,18 @@ struct AsmDesc {
   const int32_t* vptr;
   const int32_t* vitem;
   const uint8_t* dmask;
-  double* elem;     // nt*16 element matrices, then nt volumes
+  double* elem;     // nt element matrices of 16 ncomp^2 entries, then nt volumes
   double* val64;
   float* val32;     // may be null
   double* b;        // may be null (load vector)
   const double* kappa_tet;  // kappa kind 2: value per tetrahedron
   const double* fval;       // load kinds 1 (per tetrahedron) and 2 (P1 nodal values)
   int64_t nt;
-  int64_t nv;
+  int64_t nv;               // rows (unknowns): ncomp per vertex
   int32_t fkind;            // 0 constant, 1 per tetrahedron, 2 nodal
-  int32_t pad;
+  int32_t ncomp;            // 1: -div(kappa grad u) = f; 3: linear elasticity, E = kappa
+  double nu;                // Poisson's ratio (ncomp = 3)
+  double fvec[3];           // constant body force (ncomp = 3, fkind 0)
 };
 
 }  // namespace nnms

@@ -958,5 +958,6 @@ extern "C" nnms_status nnms_setup_opts_default(nnms_setup_opts* o) {
   o->subsolver = NNMS_SUBSOLVER_LU;
   o->ilu_fill[0] = 2;  // ILU(2) on the finest level, ILU(0) on the others
   o->mls_restrict = 0;
+  o->ncomp = 1;
   return NNMS_OK;
 }

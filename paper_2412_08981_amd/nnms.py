@@ -52,7 +52,8 @@ class NNMSError(RuntimeError):
 class setup_opts(C.Structure):
     _fields_ = [("nparts", C.c_int32 * MAX_LEVELS), ("overlap", C.c_int32), ("its", C.c_int32),
                 ("precision", C.c_int32), ("transfer", C.c_int32), ("mls_alpha", C.c_double),
-                ("subsolver", C.c_int32), ("ilu_fill", C.c_int32 * MAX_LEVELS), ("mls_restrict", C.c_int32)]
+                ("subsolver", C.c_int32), ("ilu_fill", C.c_int32 * MAX_LEVELS), ("mls_restrict", C.c_int32),
+                ("ncomp", C.c_int32)]
 
 
 class level_info(C.Structure):
@@ -60,7 +61,7 @@ class level_info(C.Structure):
                 ("nparts", C.c_int32), ("max_block", C.c_int32), ("min_block", C.c_int32), ("transfer", C.c_int32),
                 ("s_total", C.c_int64), ("factor_elems", C.c_int64), ("p_nnz", C.c_int64),
                 ("subsolver", C.c_int32), ("mls_restrict", C.c_int32), ("ilu_nnz", C.c_int64),
-                ("r_nnz", C.c_int64)]
+                ("r_nnz", C.c_int64), ("ncomp", C.c_int32), ("reserved", C.c_int32), ("ndof", C.c_int64)]
 
 
 class kappa_t(C.Structure):
@@ -71,12 +72,12 @@ class kappa_t(C.Structure):
 
 class rhs_t(C.Structure):
     _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("value", C.c_double),
-                ("values", C.POINTER(C.c_double))]
+                ("values", C.POINTER(C.c_double)), ("vector", C.c_double * 3)]
 
 
 class assemble_opts_t(C.Structure):
     _fields_ = [("kappa", C.POINTER(kappa_t)), ("rhs", C.POINTER(rhs_t)), ("restart_cap", C.c_int32),
-                ("reserved", C.c_int32), ("max_device_bytes", C.c_int64)]
+                ("reserved", C.c_int32), ("max_device_bytes", C.c_int64), ("poisson_ratio", C.c_double)]
 
 
 class solve_opts(C.Structure):
@@ -268,7 +269,7 @@ class Hierarchy:
     def __init__(self, meshes: Sequence[Mesh], nparts: Sequence[int] = (), overlap: int = 1, its: int = 3,
                  precision: int = FP64, device: bool = True, torch_alloc: bool = False, stream=None,
                  transfer: int = BARYCENTRIC, mls_alpha: float = 1.0, subsolver: int = LU,
-                 ilu_fill: Sequence[int] = (), mls_restrict: bool = False):
+                 ilu_fill: Sequence[int] = (), mls_restrict: bool = False, ncomp: int = 1):
         o = setup_opts()
         _check(_lib.nnms_setup_opts_default(C.byref(o)))
         for l, p in enumerate(nparts):
@@ -277,6 +278,7 @@ class Hierarchy:
         o.transfer, o.mls_alpha = transfer, mls_alpha
         o.subsolver = subsolver
         o.mls_restrict = 1 if mls_restrict else 0
+        o.ncomp = int(ncomp)
         for l, k in enumerate(ilu_fill):
             o.ilu_fill[l] = int(k)
         self.meshes = list(meshes)
@@ -302,14 +304,14 @@ class Hierarchy:
 
     def csr(self, level: int):
         li = self.level_info(level)
-        rp = np.empty(li.nv + 1, dtype=np.int32)
+        rp = np.empty(li.ndof + 1, dtype=np.int32)
         col = np.empty(li.nnz, dtype=np.int32)
         _check(_lib.nnms_hierarchy_csr(self.handle, level, _ptr(rp), _ptr(col)))
         return rp, col
 
     def partition(self, level: int):
         li = self.level_info(level)
-        owner = np.empty(li.nv, dtype=np.int32)
+        owner = np.empty(li.ndof, dtype=np.int32)
         s_ptr = np.empty(li.nparts + 1, dtype=np.int64)
         s_idx = np.empty(li.s_total, dtype=np.int32)
         _check(_lib.nnms_hierarchy_partition(self.handle, level, _ptr(owner), _ptr(s_ptr), _ptr(s_idx)))
@@ -317,8 +319,8 @@ class Hierarchy:
 
     def transfer(self, level: int):
         li = self.level_info(level)
-        idx = np.empty(li.nv * 4, dtype=np.int32)
-        w = np.empty(li.nv * 4, dtype=np.float64)
+        idx = np.empty(li.ndof * 4, dtype=np.int32)
+        w = np.empty(li.ndof * 4, dtype=np.float64)
         _check(_lib.nnms_hierarchy_transfer(self.handle, level, _ptr(idx), _ptr(w)))
         return idx.reshape(-1, 4), w.reshape(-1, 4)
 
@@ -326,7 +328,7 @@ class Hierarchy:
         """The restriction (P^T or the fine-to-coarse MLS operator) as CSR
         (row_ptr, col, w) over the coarse vertices."""
         li, lc = self.level_info(level), self.level_info(level + 1)
-        rp = np.empty(lc.nv + 1, dtype=np.int32)
+        rp = np.empty(lc.ndof + 1, dtype=np.int32)
         col = np.empty(li.r_nnz, dtype=np.int32)
         w = np.empty(li.r_nnz, dtype=np.float64)
         _check(_lib.nnms_hierarchy_restriction_csr(self.handle, level, _ptr(rp), _ptr(col), _ptr(w)))
@@ -341,9 +343,9 @@ class Hierarchy:
         return rp, col
 
     def transfer_csr(self, level: int):
-        """P_level as CSR (row_ptr, col, w) over the fine vertices."""
+        """P_level as CSR (row_ptr, col, w) over the fine unknowns."""
         li = self.level_info(level)
-        rp = np.empty(li.nv + 1, dtype=np.int32)
+        rp = np.empty(li.ndof + 1, dtype=np.int32)
         col = np.empty(li.p_nnz, dtype=np.int32)
         w = np.empty(li.p_nnz, dtype=np.float64)
         _check(_lib.nnms_hierarchy_transfer_csr(self.handle, level, _ptr(rp), _ptr(col), _ptr(w)))
@@ -363,7 +365,8 @@ class Hierarchy:
         parts = []
         for l in range(self.L):
             li = self.level_info(l)
-            parts.append(f"{li.nv}-{li.nnz}-{li.nparts}" + (f"-mls{li.p_nnz}-{li.r_nnz}" if li.transfer == MLS else "")
+            parts.append(f"{li.nv}-{li.nnz}-{li.nparts}" + (f"-c{li.ncomp}" if li.ncomp != 1 else "")
+                         + (f"-mls{li.p_nnz}-{li.r_nnz}" if li.transfer == MLS else "")
                          + (f"-ilu{li.ilu_nnz}" if li.subsolver == ILU else ""))
         return f"p{self.precision}_" + "_".join(parts)
 
@@ -412,6 +415,12 @@ def _rhs(f) -> tuple:
     r = rhs_t()
     if isinstance(f, (int, float, np.floating)):
         r.kind, r.value = 0, float(f)
+        r.vector[0] = r.vector[1] = r.vector[2] = float(f)
+        return r, None
+    if not hasattr(f, "kind"):  # a constant body force (three components)
+        v = [float(x) for x in f]
+        r.kind = 0
+        r.vector[0], r.vector[1], r.vector[2] = v
         return r, None
     v = np.ascontiguousarray(f.values, dtype=np.float64)
     r.kind = {"per_tet": 1, "nodal": 2}[f.kind]
@@ -426,17 +435,19 @@ class System:
     (0 = the maximum); budget: device bytes the assembly may take (0 = no
     limit; NNMSError BUDGET beyond)."""
 
-    def __init__(self, h: Hierarchy, kappa=None, f=1.0, stream=None, restart_cap: int = 0, budget: int = 0):
+    def __init__(self, h: Hierarchy, kappa=None, f=1.0, stream=None, restart_cap: int = 0, budget: int = 0,
+                 poisson_ratio: float = 0.3):
         k, keep = _kappa(kappa)
         r, keep_r = _rhs(f)
         o = assemble_opts_t()
         o.kappa, o.rhs = C.pointer(k), C.pointer(r)
         o.restart_cap, o.max_device_bytes = int(restart_cap), int(budget)
+        o.poisson_ratio = float(poisson_ratio)
         s = C.c_void_p()
         _check(_lib.nnms_assemble_ex(h.handle, C.byref(o), _stream_ptr(stream), C.byref(s)))
         self.handle = s
         self.h = h
-        self.n = [h.level_info(l).nv for l in range(h.L)]
+        self.n = [h.level_info(l).ndof for l in range(h.L)]
 
     def device_bytes(self) -> int:
         return int(_lib.nnms_system_device_bytes(self.handle))

@@ -6,6 +6,7 @@ import subprocess
 
 import numpy as np
 import pytest
+import scipy.sparse as sp
 
 import workloads as W
 from oracle import coarsen, ilu, mls, schwarz, transfer
@@ -306,3 +307,41 @@ def test_one_hip_runtime_whatever_the_import_order():
     out = subprocess.run(["python", "-c", code], capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip() == "1"
+
+
+def test_field_split_structure_matches_oracle():
+    """Three unknowns per vertex (linear elasticity, field splitting): the
+    library's pattern equals the oracle's elasticity matrix pattern, its
+    subdomains are the vertex subdomains carried to every component, and its
+    transfer equals the oracle's split interpolation sum_f R_f^T P R~_f."""
+    from oracle import elasticity as el
+
+    pb = W.Problem("el", [W.kuhn_cube(7, 41), W.kuhn_cube(4, 42), W.kuhn_cube(3, 43)], [4, 2],
+                   W.kappa_draw(204, 205))
+    ms = [nnms.Mesh.from_workload(m) for m in pb.meshes]
+    h = nnms.Hierarchy(ms, pb.nparts, device=False, ncomp=3)
+    for l, m in enumerate(pb.meshes):
+        li = h.level_info(l)
+        assert (li.nv, li.ncomp, li.ndof) == (m.nv, 3, 3 * m.nv)
+        assert li.ninterior == int((m.dirichlet == 0).sum())
+        A, _ = el.assemble(m, pb.kappa, 0.3)
+        rp, col = h.csr(l)
+        assert np.array_equal(rp, A.indptr) and np.array_equal(col, A.indices)
+        if l + 1 < len(pb.meshes):
+            owner, sets = h.partition(l)
+            _, sets_o = el.expand_sets(*schwarz.partition(m, pb.nparts[l], pb.overlap))
+            assert len(sets) == len(sets_o) and all(np.array_equal(a, b) for a, b in zip(sets, sets_o))
+            P = el.split_interpolation(transfer.interpolation(m, pb.meshes[l + 1]))
+            prp, pcol, pw = h.transfer_csr(l)
+            Pl = sp.csr_matrix((pw, pcol, prp), shape=P.shape)
+            assert abs(Pl - P).max() <= 1e-14
+            rrp, rcol, rw = h.restriction_csr(l)
+            R = sp.csr_matrix((rw, rcol, rrp), shape=P.T.shape)
+            assert abs(R - P.T).max() <= 1e-14
+
+
+def test_field_split_default_subdomains_count_unknowns():
+    pb = W.cube16_two_level()
+    ms = [nnms.Mesh.from_workload(m) for m in pb.meshes]
+    h = nnms.Hierarchy(ms, [0], device=False, ncomp=3)
+    assert h.level_info(0).nparts == W.nparts_rule(3 * pb.meshes[0].nv)

@@ -176,14 +176,33 @@ def cube16_two_level() -> Problem:
     return Problem("cube16_6_fp64", meshes, [8], KappaField("const", 1.0))
 
 
+CUBE48_NPARTS = [64, 32]
+
+
 def cube48_three_level(precision: str = "fp64") -> Problem:
     """Three levels 48^3 / 24^3 / 10^3, log-Gaussian kappa with 8 seeded
-    centres, 64 subdomains on the fine level."""
+    centres, 64 subdomains on the fine level and 32 on the second (a measured
+    choice: the same iteration count as the unknown-count rule's 8 with a
+    shorter smoother chain on that level)."""
     meshes = make_hierarchy([48, 24, 10], [201, 202, 203])
     kap = kappa_draw(204, 205)
-    np1 = nparts_rule(meshes[1].nv)
     name = "cube48_24_10_fp64" if precision == "fp64" else "cube48_24_10_mixed"
-    return Problem(name, meshes, [64, np1], kap, precision=precision)
+    return Problem(name, meshes, list(CUBE48_NPARTS), kap, precision=precision)
+
+
+def cube32_elasticity(precision: str = "fp64") -> Problem:
+    """P1 linear elasticity on jittered 32^3 / 16^3 / 7^3 meshes (seeds
+    451-453): Young's modulus from the log-Gaussian field (centres seed 204,
+    amplitudes seed 455), three unknowns per vertex, 64 fine-level
+    subdomains and the unknown-count rule below; Poisson's ratio and the body
+    force are ELASTIC_NU and ELASTIC_FORCE."""
+    meshes = make_hierarchy([32, 16, 7], [451, 452, 453])
+    return Problem("cube32_elasticity", meshes, [64, nparts_rule(3 * meshes[1].nv)], kappa_draw(204, 455),
+                   precision=precision)
+
+
+ELASTIC_NU = 0.3
+ELASTIC_FORCE = (0.0, 0.0, -1.0)
 
 
 def cube48_three_level_mixed() -> Problem:
