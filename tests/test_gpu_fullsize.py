@@ -1,19 +1,22 @@
 """The default path (dense subdomain LU, barycentric transfer) at the
 benchmark's full size and launch configuration (the tuned shapes of the
-committed cache), against the FP64 oracle.
+committed cache), against the FP64 oracle, entry by entry.
 
-48^3 / 24^3 / 10^3, 64 + 8 subdomains: the assembled operators, the load
-vector and both transfers on every entry (the same sums in another order,
-1e-13 relative); the smoother on sampled subdomains, each solved by the
-oracle one by one with LAPACK (its owned rows, 1e-9 relative: rounding
-times the block's condition number); a full solve in FP64 against the
-oracle's own FGMRES solution (same iteration count within one, 1e-7) and in
-mixed precision against x* (1e-7; its FP32 smoother on sampled subdomains
-to 1e-2, FP32 rounding times block condition numbers up to ~1e5).
-96^3 / 48^3 / 20^3 (the largest served hierarchy, 512 fine subdomains,
-mixed): the true residual of a solve computed from the oracle's assembly,
-and sampled subdomains of the fine smoother.  The 32 batched instances:
-true residuals and bitwise equality with solves alone.
+A vector v is compared with the oracle's r entry-wise: max_i |v_i - r_i| <=
+tol * max_i |r_i|.  48^3 / 24^3 / 10^3, 64 + 32 subdomains: the assembled
+operators, the load vector, every entry of P_l and P_l^T as stored, and the
+device products with them (the same sums in another order, 1e-13); the
+smoother on every level, all subdomains at once, against the oracle's
+restricted additive Schwarz with LAPACK (1e-9: rounding times the blocks'
+condition numbers), the coarsest direct solve, one V-cycle against the
+oracle's V-cycle (1e-9), and a full FP64 solve against the oracle's own FGMRES
+solution (same iteration count within one, 1e-7).  Mixed precision: the FP32
+smoother on both levels against the oracle's (1e-2: FP32 rounding times block
+condition numbers up to ~1e5) and a solve against x* (1e-7).  96^3 / 48^3 /
+20^3 (the largest served hierarchy, 512 fine subdomains, mixed): the true
+residual of a solve from the oracle's assembly, and eight subdomains of the
+fine smoother solved one by one by LAPACK.  The 32 batched instances: true
+residuals and bitwise equality with solves alone.
 """
 import os
 import sys
@@ -22,7 +25,6 @@ import numpy as np
 import pytest
 import scipy.linalg as sla
 import scipy.sparse as sp
-import scipy.sparse.linalg as spla
 
 import workloads as W
 from oracle import fem, problem as oprob, schwarz
@@ -47,8 +49,13 @@ def _say(*a):
     sys.stdout.flush()
 
 
-def _rel(a, b):
-    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+def _close(v, ref, tol):
+    """Entry-wise agreement: max |v - ref| <= tol max |ref|."""
+    return float(np.abs(v - ref).max()) <= tol * max(float(np.abs(ref).max()), 1e-300)
+
+
+def _err(v, ref):
+    return float(np.abs(v - ref).max()) / max(float(np.abs(ref).max()), 1e-300)
 
 
 def _system(pb, precision):
@@ -64,10 +71,15 @@ def _system(pb, precision):
     return nnms.System(h, pb.kappa, 1.0), h, ms
 
 
-def _check_smoother_samples(s, mesh, A, nparts, parts, tol):
-    rng = np.random.default_rng(7)
+def _interior_random(rng, mesh):
     r = rng.standard_normal(mesh.nv)
     r[mesh.dirichlet != 0] = 0
+    return r
+
+
+def _check_smoother_samples(s, mesh, A, nparts, parts, tol):
+    rng = np.random.default_rng(7)
+    r = _interior_random(rng, mesh)
     z = s.apply_smoother(0, r)
     owned, sets = schwarz.partition(mesh, nparts, 1)
     for p in parts:
@@ -75,7 +87,19 @@ def _check_smoother_samples(s, mesh, A, nparts, parts, tol):
         y = sla.lu_solve(sla.lu_factor(A[S][:, S].toarray()), r[S])
         own = np.sort(owned[p])
         ref = y[np.searchsorted(S, own)]
-        assert _rel(z[own], ref) <= tol, (p, _rel(z[own], ref))
+        assert _close(z[own], ref, tol), (p, _err(z[own], ref))
+
+
+def _check_smoothers(s, pb, o, tol):
+    """Every level's smoother, all subdomains, against the oracle's RAS (and
+    the coarsest direct solve against numpy.linalg.solve)."""
+    rng = np.random.default_rng(11)
+    L = len(pb.meshes)
+    for l in range(L):
+        r = _interior_random(rng, pb.meshes[l])
+        z = s.apply_smoother(l, r)
+        ref = o.vcycle.levels[l].ras.apply(r) if l < L - 1 else np.linalg.solve(o.A[l].toarray(), r)
+        assert _close(z, ref, tol), (l, _err(z, ref))
 
 
 def test_cube48_fp64_full_size():
@@ -87,40 +111,53 @@ def test_cube48_fp64_full_size():
         rp, col = h.csr(l)
         A = sp.csr_matrix((s.matrix_values(l), col, rp), shape=(s.n[l], s.n[l]))
         assert abs(A - o.A[l]).max() <= 1e-13 * abs(o.A[l]).max(), l
-    assert np.abs(s.rhs() - o.b).max() <= 1e-14 * np.abs(o.b).max()
+    assert _close(s.rhs(), o.b, 1e-14)
     rng = np.random.default_rng(3)
     for l in range(2):
+        # the stored operators, every entry
+        rp, col, w = h.transfer_csr(l)
+        P = sp.csr_matrix((w, col, rp), shape=o.P[l].shape)
+        assert abs(P - o.P[l]).max() <= 1e-14, l
+        rp, col, w = h.restriction_csr(l)
+        R = sp.csr_matrix((w, col, rp), shape=o.P[l].T.shape)
+        assert abs(R - o.P[l].T).max() <= 1e-14, l
+        idx, wl = h.transfer(l)
+        Pe = sp.csr_matrix((wl.ravel(), idx.ravel(), np.arange(0, 4 * s.n[l] + 1, 4)), shape=o.P[l].shape)
+        assert abs(Pe - o.P[l]).max() <= 1e-14, l
+        # the device products, every entry
         xc = rng.standard_normal(s.n[l + 1])
-        assert _rel(s.apply_prolong(l, xc), o.P[l] @ xc) <= 1e-13
-        x = rng.standard_normal(s.n[l])
-        x[pb.meshes[l].dirichlet != 0] = 0
-        assert _rel(s.apply_restrict(l, x), o.P[l].T @ x) <= 1e-13
-        x = rng.standard_normal(s.n[l])
-        x[pb.meshes[l].dirichlet != 0] = 0
-        assert _rel(s.apply_operator(l, x), o.A[l] @ x) <= 1e-13
-    _check_smoother_samples(s, pb.meshes[0], o.A[0], pb.nparts[0], [0, 21, 63], 1e-9)
+        assert _close(s.apply_prolong(l, xc), o.P[l] @ xc, 1e-13), l
+        x = _interior_random(rng, pb.meshes[l])
+        assert _close(s.apply_restrict(l, x), o.P[l].T @ x, 1e-13), l
+        x = _interior_random(rng, pb.meshes[l])
+        assert _close(s.apply_operator(l, x), o.A[l] @ x, 1e-13), l
+    _check_smoothers(s, pb, o, 1e-9)
+    r = _interior_random(rng, pb.meshes[0])
+    zv = s.apply_vcycle(r)
+    assert _close(zv, o.vcycle(r), 1e-9), _err(zv, o.vcycle(r))
     ref = oprob.solve(o)
     x, info = s.solve(o.b)
     _say(f"[gpu] 48^3 fp64: {info.iterations} iterations (oracle {ref.iterations})")
     assert info.status == 0 and info.relres <= 1e-8
     assert abs(info.iterations - ref.iterations) <= 1
     assert np.linalg.norm(o.b - o.A[0] @ x) <= 1e-8 * np.linalg.norm(o.b)
-    assert _rel(x, ref.x) <= 1e-7
+    assert _close(x, ref.x, 1e-7), _err(x, ref.x)
 
 
 def test_cube48_mixed_full_size():
     _say("[gpu] 48^3 / 24^3 / 10^3 at the benchmark's launch shapes (mixed)")
     pb = W.cube48_three_level("mixed")
     s, h, keep = _system(pb, "mixed")
-    A, b = fem.assemble(pb.meshes[0], pb.kappa)
+    o = oprob.build(pb)
+    A, b = o.A[0], o.b
     x, info = s.solve(b)
     assert info.status == 0 and info.relres <= 1e-8
     assert np.linalg.norm(b - A @ x) <= 1e-8 * np.linalg.norm(b)
-    xs = spla.splu(A.tocsc()).solve(b)  # x* by a sparse direct solve
-    assert _rel(x, xs) <= 1e-7
-    # FP32 smoother on sampled subdomains: FP32 rounding (6e-8) times the
-    # block's condition number (up to ~1e5 with this kappa)
-    _check_smoother_samples(s, pb.meshes[0], A, pb.nparts[0], [5, 40], 1e-2)
+    xs = oprob.exact(o)  # x* by a sparse direct solve
+    assert _close(x, xs, 1e-7), _err(x, xs)
+    # FP32 smoother, all subdomains of both levels: FP32 rounding (6e-8)
+    # times the blocks' condition numbers (up to ~1e5 with this kappa)
+    _check_smoothers(s, pb, o, 1e-2)
 
 
 def test_served_96_mixed_full_size():
@@ -134,7 +171,7 @@ def test_served_96_mixed_full_size():
     _say(f"[gpu] 96^3 mixed: {info.iterations} iterations, relres {info.relres:.2e}")
     assert info.status == 0 and info.relres <= 1e-8
     assert np.linalg.norm(b - A @ x) <= 1e-8 * np.linalg.norm(b)
-    _check_smoother_samples(s, meshes[0], A, nps[0], [0, 511], 1e-2)
+    _check_smoother_samples(s, meshes[0], A, nps[0], [0, 73, 146, 219, 292, 365, 438, 511], 1e-2)
 
 
 def test_batched_32_instances_full_size():
