@@ -384,9 +384,10 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
-    ap.add_argument("--workload", default="cube48", choices=["cube48", "batched", "serving"],
-                    help="cube48: the three-level 48^3 problem (default); batched: ragged parametric instances; "
-                         "serving: continuous batching of Poisson arrivals")
+    ap.add_argument("--workload", default="cube48", choices=["cube48", "cube16", "batched", "serving"],
+                    help="cube48: the three-level 48^3 problem (default); cube16: the two-level 16^3/6^3 problem "
+                         "(kappa = 1, 8 subdomains); batched: ragged parametric instances; serving: continuous "
+                         "batching of Poisson arrivals")
     ap.add_argument("--requests", type=int, default=60, help="requests of the serving trace")
     ap.add_argument("--tuning-cache", default=os.path.join(ROOT, "paper_2412_08981_amd", "tuning.json"),
                     help="launch-shape cache (measured on first use)")
@@ -429,10 +430,17 @@ def main():
     if args.workload == "serving":
         return run_serving(args)
     elastic = args.physics == "elasticity"
-    pb = W.cube32_elasticity(args.precision) if elastic else W.cube48_three_level(args.precision)
+    if elastic:
+        pb = W.cube32_elasticity(args.precision)
+    elif args.workload == "cube16":
+        pb = W.cube16_two_level()
+        pb.precision = args.precision
+    else:
+        pb = W.cube48_three_level(args.precision)
     prec = nnms.MIXED if args.precision == "mixed" else nnms.FP64
     t0 = time.perf_counter()
     meshes = [nnms.Mesh.from_workload(m) for m in pb.meshes]
+    fine_mesh = pb.meshes[0]
     coarsened = None
     rounds = [int(r) for r in args.coarsen.split(",")] if args.coarsen else []
     if rounds:
@@ -559,7 +567,7 @@ def main():
     legs = {}
     x_mixed = None
     if (not args.no_legs and not coarsened and args.precision == "fp64" and not mls_mode and not ilu_mode
-            and not elastic and not args.nparts):
+            and not elastic and not args.nparts and args.workload == "cube48"):
         hm = nnms.Hierarchy(meshes, pb.nparts, overlap=pb.overlap, its=pb.its, precision=nnms.MIXED)
         sm = nnms.System(hm, pb.kappa, 1.0)
         tm = autotune.tune(sm, cache=args.tuning_cache)
@@ -610,6 +618,8 @@ def main():
                                 f"jittered unit cube, 3 non-nested levels 32^3/16^3/7^3 (35937 fine vertices, "
                                 f"107811 unknowns), Young's modulus from the log-Gaussian field, Poisson's ratio "
                                 f"{W.ELASTIC_NU}, body force {W.ELASTIC_FORCE}, " if elastic else
+                                "jittered unit cube, 2 non-nested levels 16^3/6^3 (4913 fine vertices, 24576 tets), "
+                                "kappa = 1, f = 1, " if args.workload == "cube16" else
                                 f"jittered unit cube, 3 non-nested levels 48^3/24^3/10^3 "
                                 f"(117649 fine vertices, 663552 tets), log-Gaussian kappa (8 centres), ")
                                + f"{'+'.join(str(p) for p in pb.nparts)} subdomains overlap 1, FGMRES(30) to 1e-8, "
@@ -636,7 +646,7 @@ def main():
         if coarsened:
             # the oracle coarsens the fine mesh itself (equal to the library's, bit for bit)
             from oracle import coarsen as ocoarsen
-            om = [W.cube48_three_level(args.precision).meshes[0]]
+            om = [fine_mesh]
             for l in range(1, len(coarsened)):
                 r = ocoarsen.coarsen(om[-1].xyz, om[-1].tets, om[-1].dirichlet, rounds[l - 1], l)
                 om.append(W.Mesh(r.xyz, r.tets.astype(np.int32), r.dirichlet, 0))
