@@ -24,8 +24,14 @@ Readings where the paper leaves a choice open (the library takes the same):
   * rank(P) = 4 is decided on the centred, rho-scaled basis
     [1, (x - x*) / rho] (the same space): its smallest singular value must
     exceed 1e-6 times its largest;
-  * on one device the whole source level is local, so the neighbourhood is
-    not clipped to the overlapping subdomain of the target's processor;
+  * by default the neighbourhood is not clipped: on one device the whole
+    source level is local.  With `clip` it is the paper's
+    N~(x*) = {x~_n in Omega~^delta_p : |x~_n - x*| < rho(x*)}: processor p
+    owns the target node (its subdomain on the target level), and its
+    overlapping subdomain of the source level is the source level's own
+    coordinate bisection into the same number of parts (every level is split
+    across the same processors, Section 3.1), extended by delta layers, as
+    the nodes of the elements that touch it (`clip_sets`);
   * homogeneous Dirichlet conditions: rows of Dirichlet target nodes are
     empty and the weights of Dirichlet source nodes are dropped after the
     solve (as for the barycentric transfer).
@@ -84,24 +90,54 @@ def mls_row(xstar, pts, rho):
     return basis(xstar)[:, 0] @ np.linalg.solve(P1, P2)
 
 
-def neighbourhood(tree, src_xyz, xstar, rho0):
-    """(ids, rho): source nodes strictly within rho of x*, rho grown from rho0
-    by GROWTH until the neighbourhood has full rank."""
+def neighbourhood(tree, src_xyz, xstar, rho0, allowed=None):
+    """(ids, rho): source nodes strictly within rho of x* (and in `allowed`, a
+    boolean mask, when given), rho grown from rho0 by GROWTH until the
+    neighbourhood has full rank."""
     rho = rho0
     for _ in range(200):
         ids = np.array(sorted(tree.query_ball_point(xstar, rho)), dtype=np.int64)
         if len(ids):
             ids = ids[np.linalg.norm(src_xyz[ids] - xstar, axis=1) < rho]
+        if allowed is not None and len(ids):
+            ids = ids[allowed[ids]]
         if full_rank(xstar, src_xyz[ids], rho):
             return ids, rho
         rho *= GROWTH
     raise ValueError("no full-rank neighbourhood")
 
 
-def interpolation(target, source, alpha: float = ALPHA, mask_dirichlet: bool = True, rows=None) -> sp.csr_matrix:
+def clip_sets(target, source, nparts: int, overlap: int = 1):
+    """(owner of every target node, boolean masks of the source nodes of every
+    processor): the target level's partition into nparts and the source
+    level's own partition into the same nparts, extended by `overlap` layers,
+    taken as the nodes of the source elements touching it (its subdomain
+    Omega~^delta_p, boundary nodes included)."""
+    from . import schwarz
+
+    owned_t, _ = schwarz.partition(target, nparts, overlap)
+    owner = -np.ones(target.nv, dtype=np.int64)
+    for p, o in enumerate(owned_t):
+        owner[o] = p
+    _, sets_s = schwarz.partition(source, nparts, overlap)
+    masks = []
+    for S in sets_s:
+        inset = np.zeros(source.nv, dtype=bool)
+        inset[S] = True
+        touch = inset[source.tets].any(axis=1)
+        m = np.zeros(source.nv, dtype=bool)
+        m[source.tets[touch].ravel()] = True
+        masks.append(m)
+    return owner, masks
+
+
+def interpolation(target, source, alpha: float = ALPHA, mask_dirichlet: bool = True, rows=None,
+                  clip=None) -> sp.csr_matrix:
     """MLS operator from source nodal values to target nodal values, shape
     [target.nv, source.nv].  rows: optional subset of target nodes to build
-    (the other rows stay empty)."""
+    (the other rows stay empty).  clip: None, or (owner, masks) of
+    clip_sets -- the neighbourhood of a target node owned by p is clipped to
+    masks[p]."""
     h = mean_edge_length(source.xyz, source.tets)
     tree = cKDTree(source.xyz)
     if rows is None:
@@ -111,7 +147,8 @@ def interpolation(target, source, alpha: float = ALPHA, mask_dirichlet: bool = T
         if mask_dirichlet and target.dirichlet[v]:
             continue
         xs = target.xyz[v]
-        ids, rho = neighbourhood(tree, source.xyz, xs, alpha * h)
+        allowed = None if clip is None else clip[1][clip[0][v]]
+        ids, rho = neighbourhood(tree, source.xyz, xs, alpha * h, allowed)
         phi = mls_row(xs, source.xyz[ids], rho)
         if mask_dirichlet:
             keep = source.dirichlet[ids] == 0
@@ -124,13 +161,19 @@ def interpolation(target, source, alpha: float = ALPHA, mask_dirichlet: bool = T
     return sp.csr_matrix((vi, (ri, ci)), shape=(target.nv, source.nv))
 
 
-def prolongation(fine, coarse, alpha: float = ALPHA, mask_dirichlet: bool = True) -> sp.csr_matrix:
-    """P_l: coarse -> fine by MLS (the coarse nodes are the sources)."""
-    return interpolation(fine, coarse, alpha, mask_dirichlet)
+def prolongation(fine, coarse, alpha: float = ALPHA, mask_dirichlet: bool = True, clip_parts: int = 0,
+                 overlap: int = 1) -> sp.csr_matrix:
+    """P_l: coarse -> fine by MLS (the coarse nodes are the sources);
+    clip_parts > 0 clips every neighbourhood to the target's processor's
+    coarse subdomain (clip_sets)."""
+    clip = clip_sets(fine, coarse, clip_parts, overlap) if clip_parts else None
+    return interpolation(fine, coarse, alpha, mask_dirichlet, clip=clip)
 
 
-def restriction(fine, coarse, alpha: float = ALPHA, mask_dirichlet: bool = True) -> sp.csr_matrix:
+def restriction(fine, coarse, alpha: float = ALPHA, mask_dirichlet: bool = True, clip_parts: int = 0,
+                overlap: int = 1) -> sp.csr_matrix:
     """R_l: fine -> coarse by MLS (the fine nodes are the sources; the scale
     starts at alpha times the fine mesh's mean edge length): the paper's
     second interpolation, applied to the residual as it stands."""
-    return interpolation(coarse, fine, alpha, mask_dirichlet)
+    clip = clip_sets(coarse, fine, clip_parts, overlap) if clip_parts else None
+    return interpolation(coarse, fine, alpha, mask_dirichlet, clip=clip)

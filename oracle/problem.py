@@ -36,7 +36,8 @@ def level_kappa(kappa, l: int):
 
 
 def build(problem, f=1.0, locate=transfer.locate_bucket, mls_alpha: Optional[float] = None,
-          ilu_fill: Optional[List[int]] = None, mls_restrict: bool = False) -> OracleHierarchy:
+          ilu_fill: Optional[List[int]] = None, mls_restrict: bool = False,
+          mls_clip: bool = False) -> OracleHierarchy:
     """f: the source term of the finest level's load (a number, or a field of
     kind 'per_tet' / 'nodal' with values on the finest mesh).
     mls_alpha: None for the barycentric transfer, else the MLS transfer of
@@ -44,7 +45,10 @@ def build(problem, f=1.0, locate=transfer.locate_bucket, mls_alpha: Optional[flo
     ilu_fill: None for exact subdomain solves, else the ILU fill level of
     every smoothed level (the coarsest level is always solved directly).
     mls_restrict: with the MLS transfer, restrict by the fine-to-coarse MLS
-    interpolation instead of P^T."""
+    interpolation instead of P^T.
+    mls_clip: with the MLS transfer, clip every neighbourhood to the
+    overlapping subdomain of the target's processor (the fine level's
+    subdomain count on both levels)."""
     meshes = problem.meshes
     L = len(meshes)
     A, P, parts, levels = [], [], [], []
@@ -58,13 +62,15 @@ def build(problem, f=1.0, locate=transfer.locate_bucket, mls_alpha: Optional[flo
         if mls_alpha is None:
             P.append(transfer.interpolation(meshes[l], meshes[l + 1], locate=locate))
         else:
-            P.append(mls.prolongation(meshes[l], meshes[l + 1], mls_alpha))
+            clip = problem.nparts[l] if mls_clip else 0
+            P.append(mls.prolongation(meshes[l], meshes[l + 1], mls_alpha, clip_parts=clip, overlap=problem.overlap))
         owned, sets = schwarz.partition(meshes[l], problem.nparts[l], problem.overlap)
         parts.append((owned, sets))
         ras = schwarz.RAS(A[l], meshes[l].dirichlet, owned, sets, None if ilu_fill is None else ilu_fill[l])
         R = None
         if mls_restrict and mls_alpha is not None:
-            R = mls.restriction(meshes[l], meshes[l + 1], mls_alpha)
+            R = mls.restriction(meshes[l], meshes[l + 1], mls_alpha, clip_parts=problem.nparts[l] if mls_clip else 0,
+                                overlap=problem.overlap)
         levels.append(multilevel.Level(A[l], meshes[l].dirichlet, ras, P[l], R))
     levels.append(multilevel.Level(A[L - 1], meshes[L - 1].dirichlet))
     vc = multilevel.VCycle(levels, problem.its)

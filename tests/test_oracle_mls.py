@@ -150,3 +150,39 @@ def test_vcycle_with_mls_transfer_converges():
     assert r.converged
     x = problem.exact(h)
     assert np.linalg.norm(r.x - x) <= 1e-6 * np.linalg.norm(x)
+
+
+def test_clipped_neighbourhoods():
+    """The paper's neighbourhood clipped to the overlapping subdomain of the
+    target's processor (Section 3.2): every row's support lies in that
+    subdomain's nodes, linear functions are still reproduced exactly, and a
+    row whose unclipped neighbourhood already lies inside the subdomain is
+    the same row."""
+    fine, coarse = W.kuhn_cube(9, 71), W.kuhn_cube(5, 72)
+    owner, masks = mls.clip_sets(fine, coarse, 4, 1)
+    Pc = mls.interpolation(fine, coarse, mls.ALPHA, mask_dirichlet=False, clip=(owner, masks)).tocsr()
+    Pu = mls.interpolation(fine, coarse, mls.ALPHA, mask_dirichlet=False).tocsr()
+    lin = lambda X: 0.3 + 1.1 * X[:, 0] - 0.7 * X[:, 1] + 2.0 * X[:, 2]
+    inner = fine.dirichlet == 0
+    assert np.abs((Pc @ lin(coarse.xyz) - lin(fine.xyz))[inner]).max() <= 1e-12
+    same = 0
+    for v in np.nonzero(inner)[0]:
+        cols = Pc.indices[Pc.indptr[v]:Pc.indptr[v + 1]]
+        assert masks[owner[v]][cols].all(), v
+        ucols = Pu.indices[Pu.indptr[v]:Pu.indptr[v + 1]]
+        if masks[owner[v]][ucols].all():
+            same += 1
+            assert np.array_equal(np.sort(cols), np.sort(ucols))
+            assert np.abs(Pc[v].toarray() - Pu[v].toarray()).max() <= 1e-14
+    assert same > 0.5 * inner.sum()
+    # some rows do change: the clipping is not vacuous
+    assert abs(Pc - Pu).max() > 1e-6
+
+
+def test_clipped_vcycle_converges():
+    pb = W.Problem("clip", [W.kuhn_cube(10, 73), W.kuhn_cube(6, 74), W.kuhn_cube(3, 75)], [4, 2],
+                   W.kappa_draw(204, 205))
+    h = problem.build(pb, mls_alpha=1.0, mls_clip=True)
+    res = problem.solve(h)
+    xs = problem.exact(h)
+    assert res.converged and np.linalg.norm(res.x - xs) <= 1e-7 * np.linalg.norm(xs)
