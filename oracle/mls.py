@@ -137,7 +137,7 @@ def interpolation(target, source, alpha: float = ALPHA, mask_dirichlet: bool = T
     [target.nv, source.nv].  rows: optional subset of target nodes to build
     (the other rows stay empty).  clip: None, or (owner, masks) of
     clip_sets -- the neighbourhood of a target node owned by p is clipped to
-    masks[p]."""
+    masks[p] (nodes without an owner, Dirichlet ones, are not clipped)."""
     h = mean_edge_length(source.xyz, source.tets)
     tree = cKDTree(source.xyz)
     if rows is None:
@@ -147,7 +147,7 @@ def interpolation(target, source, alpha: float = ALPHA, mask_dirichlet: bool = T
         if mask_dirichlet and target.dirichlet[v]:
             continue
         xs = target.xyz[v]
-        allowed = None if clip is None else clip[1][clip[0][v]]
+        allowed = None if clip is None or clip[0][v] < 0 else clip[1][clip[0][v]]
         ids, rho = neighbourhood(tree, source.xyz, xs, alpha * h, allowed)
         phi = mls_row(xs, source.xyz[ids], rho)
         if mask_dirichlet:

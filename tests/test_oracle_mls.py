@@ -175,8 +175,8 @@ def test_clipped_neighbourhoods():
             assert np.array_equal(np.sort(cols), np.sort(ucols))
             assert np.abs(Pc[v].toarray() - Pu[v].toarray()).max() <= 1e-14
     assert same > 0.5 * inner.sum()
-    # some rows do change: the clipping is not vacuous
-    assert abs(Pc - Pu).max() > 1e-6
+    # some interior rows do change: the clipping is not vacuous
+    assert abs(Pc[np.nonzero(inner)[0]] - Pu[np.nonzero(inner)[0]]).max() > 1e-6
 
 
 def test_clipped_vcycle_converges():
