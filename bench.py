@@ -109,7 +109,7 @@ def restrict_bytes(h, level, s_bytes):
     return float(li.r_nnz * (4 + s_bytes) + 4 * (lc.ndof + 1) + (li.ndof + lc.ndof) * s_bytes)
 
 
-def cpu_baseline(pb, seconds_cap=60.0, mls_alpha=None, elasticity=False):
+def cpu_baseline(pb, seconds_cap=60.0, mls_alpha=None, elasticity=False, mls_clip=False):
     """The FP64 oracle (NumPy/SciPy, LAPACK) on the host cores: setup once,
     then one full solve of the same problem; solves/s = 1 / solve time."""
     import workloads as W
@@ -124,7 +124,7 @@ def cpu_baseline(pb, seconds_cap=60.0, mls_alpha=None, elasticity=False):
         from oracle import elasticity as oel
         oh = oel.build(pb, nu=W.ELASTIC_NU, f=W.ELASTIC_FORCE)
     else:
-        oh = oprob.build(pb, mls_alpha=mls_alpha)
+        oh = oprob.build(pb, mls_alpha=mls_alpha, mls_clip=mls_clip)
     t1 = time.perf_counter()
     res = oprob.solve(oh)
     t2 = time.perf_counter()
@@ -397,6 +397,9 @@ def main():
     ap.add_argument("--transfer", default="barycentric", choices=["barycentric", "mls"],
                     help="transfer between levels: barycentric P1 interpolation or moving least squares")
     ap.add_argument("--mls-alpha", type=float, default=1.0, help="MLS initial scale / mean coarse edge length")
+    ap.add_argument("--mls-clip", action="store_true",
+                    help="with the MLS transfer: clip every neighbourhood to the overlapping subdomain of the "
+                         "target's processor (Section 3.2)")
     ap.add_argument("--coarsen", default="", metavar="M[,M2]",
                     help="derive the coarse levels from the fine mesh by Algorithm 1 with M rounds per level "
                          "(a list gives the rounds of each coarse level)")
@@ -411,6 +414,8 @@ def main():
                          "smoothed level, as the paper partitions every level)")
     ap.add_argument("--no-legs", action="store_true",
                     help="default workload: skip the mixed-precision and batched legs")
+    ap.add_argument("--factor-only", action="store_true",
+                    help="time the fine level's numeric factorisation a few times (for counter runs)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="run the copy reference and the fine-level smoother a few times each (for counter runs)")
     args = ap.parse_args()
@@ -467,7 +472,8 @@ def main():
     ilu_fill = [int(k) for k in args.ilu_fill.split(",")]
     h = nnms.Hierarchy(meshes, pb.nparts, overlap=pb.overlap, its=pb.its, precision=prec,
                        transfer=nnms.MLS if mls_mode else nnms.BARYCENTRIC, mls_alpha=args.mls_alpha,
-                       subsolver=nnms.ILU if ilu_mode else nnms.LU, ilu_fill=ilu_fill, ncomp=3 if elastic else 1)
+                       subsolver=nnms.ILU if ilu_mode else nnms.LU, ilu_fill=ilu_fill, ncomp=3 if elastic else 1,
+                       mls_clip=args.mls_clip)
     t1 = time.perf_counter()
     load = W.ELASTIC_FORCE if elastic else 1.0
 
@@ -481,6 +487,14 @@ def main():
     tp = time.perf_counter()
     tuning = autotune.tune(s, cache=args.tuning_cache)
     log(f"[bench] launch shapes ({time.perf_counter() - tp:.2f} s): {tuning}")
+    if args.factor_only:
+        # the fine level's numeric factorisation alone (for counter runs)
+        fb = 8 if prec == nnms.FP64 else 4
+        msf = s.time_kernel(6, 0, reps=3)
+        tf = lu_flops(h, 0) / (msf * 1e-3) / 1e12
+        print(json.dumps({"factor_l0_launches": 1 + 3, "factor_l0_ms": msf, "factor_l0_flops": lu_flops(h, 0),
+                          "factor_l0_TFLOPs": tf, "frac_of_mfma_peak": tf / MFMA_PEAK_TFLOPS[fb]}))
+        return
     if args.kernels_only:
         # same launch shapes and repetition counts as the roofline figures below
         sb = 8 if prec == nnms.FP64 else 4
@@ -488,10 +502,17 @@ def main():
         ms_copy = s.time_kernel(4, 0, reps=3)
         ms_read = s.time_kernel(5, 0, reps=5)
         ms_ras = s.time_kernel(0, 0, reps=10)
-        print(json.dumps({"copy_bytes": (fac_bytes // 16) * 16, "copy_launches": 1 + 3, "copy_ms": ms_copy,
-                          "read_launches": 1 + 5, "read_ms": ms_read,
-                          "ras_launches": 1 + 10, "ras_ms": ms_ras, "ras_algorithmic_bytes": ras_bytes(h, 0, sb),
-                          "ras_hip_sha256_16": source_hash()}))
+        out = {"copy_bytes": (fac_bytes // 16) * 16, "copy_launches": 1 + 3, "copy_ms": ms_copy,
+               "read_launches": 1 + 5, "read_ms": ms_read,
+               "ras_launches": 1 + 10, "ras_ms": ms_ras, "ras_algorithmic_bytes": ras_bytes(h, 0, sb),
+               "ras_hip_sha256_16": source_hash()}
+        if h.L > 2 and h.level_info(1).subsolver != nnms.ILU:
+            # the second level: its own copy reference and smoother launches
+            fb1 = h.level_info(1).factor_elems * sb
+            out.update({"l1_copy_bytes": (fb1 // 16) * 16, "l1_copy_ms": s.time_kernel(4, 1, reps=3),
+                        "l1_ras_launches": 1 + 20, "l1_ras_ms": s.time_kernel(0, 1, reps=20),
+                        "l1_ras_algorithmic_bytes": ras_bytes(h, 1, sb)})
+        print(json.dumps(out))
         return
     b = s.rhs()
     n0 = s.n[0]
@@ -624,7 +645,9 @@ def main():
                                 f"(117649 fine vertices, 663552 tets), log-Gaussian kappa (8 centres), ")
                                + f"{'+'.join(str(p) for p in pb.nparts)} subdomains overlap 1, FGMRES(30) to 1e-8, "
                                f"{args.precision}"
-                               + (f", MLS transfer (scale {args.mls_alpha} x mean coarse edge)" if mls_mode else "")
+                               + (f", MLS transfer (scale {args.mls_alpha} x mean coarse edge"
+                                  + (", neighbourhoods clipped to the target's subdomain)" if args.mls_clip else ")")
+                                  if mls_mode else "")
                                + (f", ILU({args.ilu_fill}) subdomain solves" if ilu_mode else "")
                                + (f", coarse levels by Algorithm 1 (rounds {rounds}; interior vertices "
                                   f"{[int((m.dirichlet == 0).sum()) for m in coarsened]})" if coarsened else ""),
@@ -651,7 +674,8 @@ def main():
                 r = ocoarsen.coarsen(om[-1].xyz, om[-1].tets, om[-1].dirichlet, rounds[l - 1], l)
                 om.append(W.Mesh(r.xyz, r.tets.astype(np.int32), r.dirichlet, 0))
             pb_o = W.Problem(pb.name, om, pb.nparts, pb.kappa, precision=pb.precision)
-        cb, oh, ores = cpu_baseline(pb_o, mls_alpha=args.mls_alpha if mls_mode else None, elasticity=elastic)
+        cb, oh, ores = cpu_baseline(pb_o, mls_alpha=args.mls_alpha if mls_mode else None, elasticity=elastic,
+                                    mls_clip=args.mls_clip)
         out["cpu_baseline"] = cb
         from oracle import problem as oprob  # the oracle's own x* for the error report
         xs = ores.x

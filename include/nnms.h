@@ -147,6 +147,13 @@ void nnms_mesh_destroy(nnms_mesh* m);
  * Errors: NNMS_ERR_INVALID_ARG, NNMS_ERR_POINT_LOCATION (a fine vertex
  *         outside the coarse mesh, or no full-rank MLS neighbourhood),
  *         NNMS_ERR_OUT_OF_MEMORY, NNMS_ERR_DEVICE.
+ *             mls_clip = 1: the paper's clipped neighbourhood (Section 3.2):
+ *             both levels of a transfer are split across the same
+ *             nparts[l] processors by coordinate bisection of their interior
+ *             vertices with `overlap` layers; a target vertex owned by p
+ *             takes its MLS neighbourhood only from the nodes of the source
+ *             elements touching p's overlapping subdomain (boundary nodes
+ *             included), rho grown until that neighbourhood has full rank;
  *             ncomp = 3 (multi-field problems by field splitting, Section
  *             3.2, equations field-split and interpolation split): P1 linear
  *             elasticity (Section 4.2's stress law) with the three
@@ -174,6 +181,8 @@ typedef struct {
                            the fine to the coarse nodes, 0 = by P_l^T */
   int32_t ncomp;        /* unknowns per vertex: 1 = -div(kappa grad u) = f (default);
                            3 = P1 linear elasticity, see below */
+  int32_t mls_clip;     /* with MLS: 1 = clip every neighbourhood to the overlapping
+                           subdomain of the target's processor, see below */
 } nnms_setup_opts;
 
 /* Geometry-preserving coarsening (Algorithm 1, Section 3.1): `rounds`

@@ -888,7 +888,7 @@ static void build_host(const nnms_mesh* const* levels, int32_t L, const nnms_set
       (opts->transfer != NNMS_TRANSFER_BARYCENTRIC && opts->transfer != NNMS_TRANSFER_MLS) ||
       (opts->transfer == NNMS_TRANSFER_MLS && !(opts->mls_alpha > 0)) ||
       (opts->subsolver != NNMS_SUBSOLVER_LU && opts->subsolver != NNMS_SUBSOLVER_ILU) ||
-      (opts->ncomp != 0 && opts->ncomp != 1 && opts->ncomp != 3))
+      (opts->ncomp != 0 && opts->ncomp != 1 && opts->ncomp != 3) || (opts->mls_clip != 0 && opts->mls_clip != 1))
     throw Error(NNMS_ERR_INVALID_ARG, "bad setup options");
   const int K = opts->ncomp ? opts->ncomp : 1;
   H.L = L;
@@ -914,7 +914,8 @@ static void build_host(const nnms_mesh* const* levels, int32_t L, const nnms_set
   // K unknowns per vertex (field splitting: each component is a field)
   for (int l = 0; l + 1 < L; ++l) {
     if (opts->transfer == NNMS_TRANSFER_MLS)
-      build_transfer_mls(H.lev[l], H.lev[l + 1], opts->mls_alpha, opts->mls_restrict != 0);
+      build_transfer_mls(H.lev[l], H.lev[l + 1], opts->mls_alpha, opts->mls_restrict != 0,
+                         opts->mls_clip ? H.opts.nparts[l] : 0, opts->overlap);
     else
       build_transfer(H.lev[l], H.lev[l + 1]);
   }

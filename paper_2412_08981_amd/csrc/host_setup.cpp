@@ -8,6 +8,7 @@
 #include <array>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <numeric>
 #include <set>
 
@@ -158,6 +159,13 @@ void build_sell_layout(const std::vector<int32_t>& rp, const std::vector<int32_t
 void build_sell(HostLevel& lv) { build_sell_layout(lv.rp, lv.col, lv.nv, lv.sell_off, lv.sell_col, lv.sell_src); }
 
 void build_partition(HostLevel& lv, int nparts, int overlap, bool direct) {
+  partition_sets(lv, nparts, overlap, direct);
+  build_blocks(lv);
+}
+
+// owned sets by coordinate bisection and their overlapping extension (no
+// factor bookkeeping)
+void partition_sets(HostLevel& lv, int nparts, int overlap, bool direct) {
   const int64_t nv = lv.nv;
   std::vector<int32_t> interior;
   for (int64_t i = 0; i < nv; ++i)
@@ -199,7 +207,26 @@ void build_partition(HostLevel& lv, int nparts, int overlap, bool direct) {
     lv.s_idx.insert(lv.s_idx.end(), cur.begin(), cur.end());
     lv.s_ptr[p + 1] = int64_t(lv.s_idx.size());
   }
-  build_blocks(lv);
+}
+
+void clip_partition(const HostLevel& lv, int nparts, int overlap, std::vector<int32_t>& owner,
+                    std::vector<std::vector<uint8_t>>& nodes) {
+  HostLevel t;
+  t.nv = lv.nv, t.nt = lv.nt;
+  t.xyz = lv.xyz, t.tets = lv.tets, t.dir = lv.dir, t.rp = lv.rp, t.col = lv.col;
+  partition_sets(t, nparts, overlap, false);
+  owner = t.owner;
+  nodes.assign(nparts, std::vector<uint8_t>(lv.nv, 0));
+  std::vector<uint8_t> inset(lv.nv);
+  for (int p = 0; p < nparts; ++p) {
+    std::fill(inset.begin(), inset.end(), 0);
+    for (int64_t k = t.s_ptr[p]; k < t.s_ptr[p + 1]; ++k) inset[t.s_idx[k]] = 1;
+    for (int64_t e = 0; e < lv.nt; ++e) {
+      const int32_t* v = &lv.tets[e * 4];
+      if (inset[v[0]] | inset[v[1]] | inset[v[2]] | inset[v[3]])
+        for (int a = 0; a < 4; ++a) nodes[p][v[a]] = 1;
+    }
+  }
 }
 
 // Dense-factor bookkeeping of the level's subdomains (tile counts, factor
@@ -753,8 +780,15 @@ double mean_edge_length(const HostLevel& lv) {
 // The MLS operator from the nodal values of `src` to the nodes of `dst`
 // (rows: dst vertices, Dirichlet rows empty, Dirichlet src columns dropped),
 // scale starting at alpha times the mean edge length of src.
+// clip: null, or (owner of every target vertex, source-node masks of every
+// processor): the neighbourhood of a target owned by p is clipped to mask p
+struct MlsClip {
+  std::vector<int32_t> owner;
+  std::vector<std::vector<uint8_t>> nodes;
+};
+
 static void mls_operator(const HostLevel& dst, const HostLevel& src, double alpha, std::vector<int32_t>& p_rp,
-                         std::vector<int32_t>& p_col, std::vector<double>& p_val) {
+                         std::vector<int32_t>& p_col, std::vector<double>& p_val, const MlsClip* clip = nullptr) {
   if (!(alpha > 0)) throw Error(NNMS_ERR_INVALID_ARG, "MLS scale factor must be positive");
   const double rho0 = alpha * mean_edge_length(src);
   if (!(rho0 > 0)) throw Error(NNMS_ERR_INVALID_ARG, "degenerate source mesh");
@@ -795,6 +829,7 @@ static void mls_operator(const HostLevel& dst, const HostLevel& src, double alph
     p_rp[v + 1] = p_rp[v];
     if (dst.dir[v]) continue;
     const double* xs = &dst.xyz[v * 3];
+    const uint8_t* allowed = clip ? clip->nodes[clip->owner[v]].data() : nullptr;
     double rho = rho0;
     bool ok = false;
     for (int grow = 0; grow < 200 && !ok; ++grow, rho *= 1.25) {
@@ -809,7 +844,7 @@ static void mls_operator(const HostLevel& dst, const HostLevel& src, double alph
               const double* y = &src.xyz[size_t(citem[e]) * 3];
               const double d2 = (y[0] - xs[0]) * (y[0] - xs[0]) + (y[1] - xs[1]) * (y[1] - xs[1]) +
                                 (y[2] - xs[2]) * (y[2] - xs[2]);
-              if (std::sqrt(d2) < rho) ids.push_back(citem[e]);
+              if (std::sqrt(d2) < rho && (!allowed || allowed[citem[e]])) ids.push_back(citem[e]);
             }
           }
       if (ids.size() < 4) continue;
@@ -848,16 +883,26 @@ static void mls_operator(const HostLevel& dst, const HostLevel& src, double alph
   }
 }
 
-void build_transfer_mls(HostLevel& fine, const HostLevel& coarse, double alpha, bool mls_restrict) {
+void build_transfer_mls(HostLevel& fine, const HostLevel& coarse, double alpha, bool mls_restrict, int clip_parts,
+                        int overlap) {
   const int64_t nc = coarse.nv, nf = fine.nv;
-  mls_operator(fine, coarse, alpha, fine.p_rp, fine.p_col, fine.p_val);
+  // clipping: every level split across the same clip_parts processors
+  std::unique_ptr<MlsClip> cp, cr;
+  if (clip_parts > 0) {
+    MlsClip fc, cc;
+    clip_partition(fine, clip_parts, overlap, fc.owner, fc.nodes);
+    clip_partition(coarse, clip_parts, overlap, cc.owner, cc.nodes);
+    cp.reset(new MlsClip{fc.owner, cc.nodes});  // fine targets, coarse sources
+    cr.reset(new MlsClip{cc.owner, fc.nodes});  // coarse targets, fine sources
+  }
+  mls_operator(fine, coarse, alpha, fine.p_rp, fine.p_col, fine.p_val, cp.get());
   fine.p_idx.assign(nf * 4, 0);  // the four-entry form is not used by this transfer
   fine.p_w.assign(nf * 4, 0.0);
   fine.ncoarse = nc;
   if (mls_restrict) {
     // the paper's second interpolation: fine nodal values to the coarse
     // nodes by MLS, in place of the transpose
-    mls_operator(coarse, fine, alpha, fine.pt_rp, fine.pt_col, fine.pt_w);
+    mls_operator(coarse, fine, alpha, fine.pt_rp, fine.pt_col, fine.pt_w, cr.get());
   } else {
     // explicit transpose: rows = coarse vertices, entries ordered by fine id
     fine.pt_rp.assign(nc + 1, 0);

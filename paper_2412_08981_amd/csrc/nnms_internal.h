@@ -124,7 +124,19 @@ void build_transfer(HostLevel& fine, const HostLevel& coarse);
 // moving-least-squares transfer (Section 3.2), initial scale alpha times the
 // mean coarse edge length; with mls_restrict the restriction is the MLS
 // interpolation from the fine to the coarse nodes, else P^T
-void build_transfer_mls(HostLevel& fine, const HostLevel& coarse, double alpha, bool mls_restrict);
+// clip_parts > 0: every neighbourhood clipped to the overlapping subdomain of
+// the target's processor, both levels split into clip_parts subdomains by
+// coordinate bisection with `overlap` layers, a subdomain's nodes being those
+// of the elements that touch it
+void build_transfer_mls(HostLevel& fine, const HostLevel& coarse, double alpha, bool mls_restrict, int clip_parts = 0,
+                        int overlap = 1);
+// the owned sets and overlapping sets of a partition (build_partition without
+// the factor bookkeeping), and a clipping partition: the owner of every
+// vertex and the node set (vertices of the elements touching the overlapping
+// set) of every part
+void partition_sets(HostLevel& lv, int nparts, int overlap, bool direct);
+void clip_partition(const HostLevel& lv, int nparts, int overlap, std::vector<int32_t>& owner,
+                    std::vector<std::vector<uint8_t>>& nodes);
 double mean_edge_length(const HostLevel& lv);
 // ILU(fill) pattern and level schedules of every subdomain (after the partition)
 void build_ilu(HostLevel& lv, int fill);

@@ -53,7 +53,7 @@ class setup_opts(C.Structure):
     _fields_ = [("nparts", C.c_int32 * MAX_LEVELS), ("overlap", C.c_int32), ("its", C.c_int32),
                 ("precision", C.c_int32), ("transfer", C.c_int32), ("mls_alpha", C.c_double),
                 ("subsolver", C.c_int32), ("ilu_fill", C.c_int32 * MAX_LEVELS), ("mls_restrict", C.c_int32),
-                ("ncomp", C.c_int32)]
+                ("ncomp", C.c_int32), ("mls_clip", C.c_int32)]
 
 
 class level_info(C.Structure):
@@ -269,7 +269,7 @@ class Hierarchy:
     def __init__(self, meshes: Sequence[Mesh], nparts: Sequence[int] = (), overlap: int = 1, its: int = 3,
                  precision: int = FP64, device: bool = True, torch_alloc: bool = False, stream=None,
                  transfer: int = BARYCENTRIC, mls_alpha: float = 1.0, subsolver: int = LU,
-                 ilu_fill: Sequence[int] = (), mls_restrict: bool = False, ncomp: int = 1):
+                 ilu_fill: Sequence[int] = (), mls_restrict: bool = False, ncomp: int = 1, mls_clip: bool = False):
         o = setup_opts()
         _check(_lib.nnms_setup_opts_default(C.byref(o)))
         for l, p in enumerate(nparts):
@@ -279,6 +279,7 @@ class Hierarchy:
         o.subsolver = subsolver
         o.mls_restrict = 1 if mls_restrict else 0
         o.ncomp = int(ncomp)
+        o.mls_clip = 1 if mls_clip else 0
         for l, k in enumerate(ilu_fill):
             o.ilu_fill[l] = int(k)
         self.meshes = list(meshes)

@@ -22,5 +22,5 @@ def test_options_are_known():
                          timeout=300, cwd=ROOT)
     assert out.returncode == 0
     for opt in ("--gpus", "--steps", "--warmup", "--precision", "--workload", "--transfer", "--mls-alpha",
-                "--subsolver", "--ilu-fill", "--coarsen", "--kernels-only", "--no-cpu-baseline", "--no-legs", "--nparts", "--physics"):
+                "--subsolver", "--ilu-fill", "--coarsen", "--kernels-only", "--no-cpu-baseline", "--no-legs", "--nparts", "--physics", "--mls-clip", "--factor-only"):
         assert opt in out.stdout, opt

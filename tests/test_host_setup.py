@@ -345,3 +345,31 @@ def test_field_split_default_subdomains_count_unknowns():
     ms = [nnms.Mesh.from_workload(m) for m in pb.meshes]
     h = nnms.Hierarchy(ms, [0], device=False, ncomp=3)
     assert h.level_info(0).nparts == W.nparts_rule(3 * pb.meshes[0].nv)
+
+
+@pytest.mark.parametrize("restrict", [False, True])
+def test_clipped_mls_matches_oracle(restrict):
+    """MLS neighbourhoods clipped to the overlapping subdomain of the target's
+    processor (both levels split across the fine level's subdomain count):
+    the library's operators have the oracle's neighbourhoods and entries."""
+    pb = W.Problem("tiny3", [W.kuhn_cube(9, 1), W.kuhn_cube(5, 2), W.kuhn_cube(3, 3)], [4, 2], W.KappaField())
+    ms = [nnms.Mesh.from_workload(m) for m in pb.meshes]
+    h = nnms.Hierarchy(ms, pb.nparts, device=False, transfer=nnms.MLS, mls_alpha=1.0, mls_clip=True,
+                       mls_restrict=restrict)
+    hu = nnms.Hierarchy(ms, pb.nparts, device=False, transfer=nnms.MLS, mls_alpha=1.0, mls_restrict=restrict)
+    for l in range(2):
+        f, c = pb.meshes[l], pb.meshes[l + 1]
+        rp, col, w = h.transfer_csr(l)
+        P = mls.prolongation(f, c, 1.0, clip_parts=pb.nparts[l]).tocsr()
+        P.sort_indices()
+        assert np.array_equal(rp, P.indptr) and np.array_equal(col, P.indices)
+        assert np.abs(w - P.data).max() <= 1e-12
+        urp, ucol, uw = hu.transfer_csr(l)
+        Pu = sp.csr_matrix((uw, ucol, urp), shape=P.shape)
+        assert abs(P - Pu).max() > 1e-6  # clipping changes some rows
+        if restrict:
+            rp, col, w = h.restriction_csr(l)
+            R = mls.restriction(f, c, 1.0, clip_parts=pb.nparts[l]).tocsr()
+            R.sort_indices()
+            assert np.array_equal(rp, R.indptr) and np.array_equal(col, R.indices)
+            assert np.abs(w - R.data).max() <= 1e-11
