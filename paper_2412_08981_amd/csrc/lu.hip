@@ -510,14 +510,20 @@ __device__ __forceinline__ void frag64_mma(const Frag64<F>& f, typename Mma<F>::
 template <typename F>
 __global__ __launch_bounds__(256, 2) void k_lu_trail(const FacDesc* __restrict__ d, int k0, int depth) {
   constexpr int W = 16 / sizeof(F);
-  const FacDesc D = d[blockIdx.y];
+  // XCD-aware order: each XCD takes a contiguous range of (subdomain,
+  // super-tile) work items, so the panels one subdomain's super-tiles share
+  // stay in one XCD's L2 instead of being fetched by all eight
+  const int gx = int(gridDim.x);
+  const int lin = xcd_block(int(blockIdx.y) * gx + int(blockIdx.x), gx * int(gridDim.y));
+  const int bx = lin % gx;
+  const FacDesc D = d[lin / gx];
   const int nr = D.N - k0 - depth;
   if (nr <= 0) return;
   const int ns = (nr + 1) >> 1;  // 2x2 super-tiles per side
-  if (int(blockIdx.x) >= ns * ns) return;
+  if (bx >= ns * ns) return;
   // wave-uniform: keeps the tile base addresses in scalar registers
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const int ti = 2 * (blockIdx.x / ns) + (wave >> 1), tj = 2 * (blockIdx.x % ns) + (wave & 1);
+  const int ti = 2 * (bx / ns) + (wave >> 1), tj = 2 * (bx % ns) + (wave & 1);
   if (ti >= nr || tj >= nr) return;  // no barriers below: a wave may leave alone
   const size_t N = D.N;
   const size_t i = k0 + depth + ti, j = k0 + depth + tj;
