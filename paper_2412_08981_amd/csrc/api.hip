@@ -1277,6 +1277,21 @@ static hipError_t enqueue_ilu(const IluJob& j, int* err, hipStream_t s) {
   return launch_ilu_factor<float>(j.d, j.nd, j.lanes, err, s);
 }
 
+// Per-device stream on which assemblies run their coarse levels'
+// factorisations beside the fine level's (created once, never destroyed:
+// destroying a stream waits for the device).  Only ever waits on events
+// recorded before, so assemblies on several threads may share it.
+static hipStream_t assembly_side_stream() {
+  static std::mutex mu;
+  static hipStream_t streams[64] = {};
+  int dev = 0;
+  HIP_CHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) throw Error(NNMS_ERR_INVALID_ARG, "device id out of range");
+  std::lock_guard<std::mutex> g(mu);
+  if (!streams[dev]) HIP_CHECK(hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking));
+  return streams[dev];
+}
+
 static bool all_finite(const double* v, int64_t n, bool positive) {
   for (int64_t i = 0; i < n; ++i)
     if (!std::isfinite(v[i]) || (positive && !(v[i] > 0))) return false;
@@ -1353,6 +1368,9 @@ extern "C" nnms_status nnms_assemble_ex(nnms_hierarchy* h, const nnms_assemble_o
   int64_t max_nt = 0;
   for (int l = 0; l < L; ++l) max_nt = std::max(max_nt, H.lev[l].nt);
   Arena scratch(h->has_alloc ? &h->alloc : nullptr);
+  std::vector<FactorJob> fac_jobs;
+  std::vector<IluJob> ilu_jobs;
+  std::vector<int> job_level;
   double* elem = scratch.alloc<double>(size_t(max_nt) * (16 * K * K + 1), s, false);
   int* err = scratch.alloc<int>(1, s);
   const double* fval = nullptr;
@@ -1399,15 +1417,36 @@ extern "C" nnms_status nnms_assemble_ex(nnms_hierarchy* h, const nnms_assemble_o
     HIP_CHECK(launch_assemble(ad, kd, rhs.value, s));
     HIP_CHECK(launch_gather_ell<double>(dl.sell_src, sl.val64, sl.ell64, nell, s));
     if (sl.ell32) HIP_CHECK(launch_gather_ell<float>(dl.sell_src, sl.val64, sl.ell32, nell, s));
-    if (ilu) {
-      // ILU(k) values of every subdomain and their factorisation
-      IluJob job = ilu_job(*sys, l, scratch, s);
-      HIP_CHECK(enqueue_ilu(job, err, s));
-    } else {
-      // dense subdomain matrices and their factors
-      FactorJob job = factor_job(*sys, l, scratch, s);
-      HIP_CHECK(enqueue_factor(job, err, s));
+    if (ilu)
+      ilu_jobs.push_back(ilu_job(*sys, l, scratch, s));  // ILU(k) values and factorisation
+    else
+      fac_jobs.push_back(factor_job(*sys, l, scratch, s));  // dense subdomain matrices and factors
+    job_level.push_back(l);
+  }
+  // The levels' factorisations are independent: the finest on `s`, the
+  // coarser ones on the library's side stream beside it (their launches are
+  // short and latency-bound and fill gaps of the fine level's), joined back
+  // into `s` before the system is handed out.
+  {
+    hipStream_t side = assembly_side_stream();
+    hipEvent_t assembled, factored;
+    HIP_CHECK(hipEventCreateWithFlags(&assembled, hipEventDisableTiming));
+    HIP_CHECK(hipEventCreateWithFlags(&factored, hipEventDisableTiming));
+    HIP_CHECK(hipEventRecord(assembled, s));
+    HIP_CHECK(hipStreamWaitEvent(side, assembled, 0));
+    size_t fi = 0, ii = 0;
+    for (int l : job_level) {
+      const bool ilu = l < L - 1 && H.lev[l].subsolver == NNMS_SUBSOLVER_ILU;
+      hipStream_t st = l == 0 ? s : side;
+      if (ilu)
+        HIP_CHECK(enqueue_ilu(ilu_jobs[ii++], err, st));
+      else
+        HIP_CHECK(enqueue_factor(fac_jobs[fi++], err, st));
     }
+    HIP_CHECK(hipEventRecord(factored, side));
+    HIP_CHECK(hipStreamWaitEvent(s, factored, 0));
+    (void)hipEventDestroy(assembled);
+    (void)hipEventDestroy(factored);
   }
   // solve workspace: Krylov bases of restart_cap columns
   const int64_t n0 = H.lev[0].nv;
