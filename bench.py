@@ -25,13 +25,19 @@ PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_ras_cube48_{prec}_pmc.md")
 
 
 def source_hash():
-    """Hash of the smoother kernel's sources (the kernel and the device headers
-    it includes): counter summaries taken from an older kernel are not
+    """Hash of the smoother kernel's sources (the kernel, the device headers
+    it includes, and the host functions that lay out its subdomains and its
+    work items): counter summaries taken from an older kernel are not
     reported."""
     import hashlib
     h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2412_08981_amd", "csrc")
     for name in ("ras.hip", "devcommon.h", "devtypes.h"):
-        h.update(open(os.path.join(ROOT, "paper_2412_08981_amd", "csrc", name), "rb").read())
+        h.update(open(os.path.join(csrc, name), "rb").read())
+    for name, sig in (("api.hip", b"static std::vector<int32_t> ras_tasks("), ("host_setup.cpp", b"void build_blocks(")):
+        text = open(os.path.join(csrc, name), "rb").read()
+        i = text.find(sig)
+        h.update(text[i:text.find(b"\n}\n", i)] if i >= 0 else b"")
     return h.hexdigest()[:16]
 
 
@@ -60,12 +66,18 @@ def log(*a):
 
 
 def ras_bytes(h, level, s_bytes):
-    """Algorithmic bytes of one smoother application on `level`: every dense
-    factor entry once (n_p^2 values: L below and U above the diagonal), the
-    gathered input and the scattered owned output, and the index map."""
+    """Algorithmic bytes of one smoother application on `level`: the forward
+    sweep reads L on and below the diagonal (n_p (n_p + 1) / 2 values), the
+    backward sweep U on and above it in the owned rows only (n_o (n_o + 1) / 2:
+    the restriction keeps x_o = inv(U_oo) y_o, and the owned rows come last),
+    plus the gathered input, the index map and the scattered owned output.
+    The coarsest level (one subdomain, every row owned) reads n^2 + n."""
     owner, sets = h.partition(level)
+    owner = np.asarray(owner)
     n = np.array([len(S) for S in sets], dtype=np.float64)
-    return float(np.sum(n * n) * s_bytes + np.sum(n) * (s_bytes + 4) + np.sum(n) * s_bytes)
+    no = np.array([np.count_nonzero(owner[np.asarray(S)] == p) for p, S in enumerate(sets)], dtype=np.float64)
+    vals = n * (n + 1) / 2 + no * (no + 1) / 2
+    return float(np.sum(vals) * s_bytes + np.sum(n) * (s_bytes + 4) + np.sum(no) * s_bytes)
 
 
 def ilu_bytes(h, level, s_bytes):

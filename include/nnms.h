@@ -364,7 +364,12 @@ nnms_status nnms_system_matrix(const nnms_system* s, int32_t level, double* val_
  * tiles of 64 per side.  lu_host (may be NULL) receives the (N*64)^2 tile
  * grid row-major as stored: L_ij below the diagonal tiles, U_ij above them,
  * inv(U_ii) in the diagonal tiles.  invl_host (may be NULL) receives the N
- * tiles inv(L_ii), each 64x64 row-major.  *N_host receives N. */
+ * tiles inv(L_ii), each 64x64 row-major.  *N_host receives N.
+ * Row and column k < |S_p| of the factor is vertex (unknown) k of the local
+ * order: on a smoothed level the members of S_p that the part does not own,
+ * ascending, then the ones it owns, ascending (the restricted solve keeps
+ * only x_o = inv(U_oo) y_o, so its backward sweep runs over the owned rows
+ * alone); on the coarsest level S order.  The padding rows follow. */
 nnms_status nnms_system_factor(const nnms_system* s, int32_t level, int32_t part, double* lu_host, double* invl_host,
                                int32_t* N_host);
 

@@ -434,7 +434,10 @@ static const void* ell_of(const SysLevel& sl) {
 // task list of one restricted additive Schwarz launch over subdomains with
 // N[q] blocks: forward block i at step i, backward block i at step 2N-1-i,
 // ordered by (step, subdomain) so that every dependency has a lower ticket.
-static std::vector<int32_t> ras_tasks(const std::vector<int32_t>& N, int K) {
+// The backward sweep of subdomain q starts at the work item holding block
+// B0[q] (the first owned one): the rows before it are not owned, and with
+// them last in the sweep nothing after them depends on them.
+static std::vector<int32_t> ras_tasks(const std::vector<int32_t>& N, const std::vector<int32_t>& B0, int K) {
   // counting sort by key = step + 4 (NBmax - NB): a subdomain with fewer work
   // items enters the order later, so the longest chains start first and the
   // launch's tail shortens (fine level 0.317 -> 0.306 ms FP32, second level
@@ -451,18 +454,18 @@ static std::vector<int32_t> ras_tasks(const std::vector<int32_t>& N, int K) {
     steps = std::max(steps, 2 * NB + shift(NB));
   }
   std::vector<int32_t> cnt(size_t(steps) + 1, 0);
-  for (int32_t n : N) {
-    const int NB = (n + K - 1) / K;
-    for (int s = 0; s < 2 * NB; ++s) cnt[s + shift(NB) + 1]++;
+  for (size_t q = 0; q < N.size(); ++q) {
+    const int NB = (N[q] + K - 1) / K, I0 = std::min(B0[q] / K, NB - 1);
+    for (int s = 0; s < 2 * NB - I0; ++s) cnt[s + shift(NB) + 1]++;
   }
   for (int s = 0; s < steps; ++s) cnt[s + 1] += cnt[s];
   std::vector<int32_t> out(cnt[steps]);
   for (size_t q = 0; q < N.size(); ++q) {
-    const int NB = (N[q] + K - 1) / K;
+    const int NB = (N[q] + K - 1) / K, I0 = std::min(B0[q] / K, NB - 1);
     const int sh = shift(NB);
     for (int i = 0; i < NB; ++i) {
       out[cnt[i + sh]++] = int32_t((q << 16) | i);
-      out[cnt[2 * NB - 1 - i + sh]++] = int32_t((q << 16) | (1 << 15) | i);
+      if (i >= I0) out[cnt[2 * NB - 1 - i + sh]++] = int32_t((q << 16) | (1 << 15) | i);
     }
   }
   return out;
@@ -474,7 +477,8 @@ static std::vector<int32_t> ras_tasks(const std::vector<int32_t>& N, int K) {
 // subdomain descriptors of level l over a set of systems: input r_l (subs_r)
 // and t_l (subs_t), and the block count of every subdomain
 static void ras_subdescs(const std::vector<nnms_system*>& sys, int l, bool coarse, int prec, bool with_state,
-                         std::vector<SubDesc>& subs_r, std::vector<SubDesc>& subs_t, std::vector<int32_t>& Ns) {
+                         std::vector<SubDesc>& subs_r, std::vector<SubDesc>& subs_t, std::vector<int32_t>& Ns,
+                         std::vector<int32_t>& B0s) {
   for (auto* x : sys) {
     const HostLevel& hl = x->h->host.lev[l];
     if (!coarse && hl.subsolver == NNMS_SUBSOLVER_ILU)
@@ -495,6 +499,7 @@ static void ras_subdescs(const std::vector<nnms_system*>& sys, int l, bool coars
       d.rin = sl.t;
       subs_t.push_back(d);
       Ns.push_back(hl.nblk[p]);
+      B0s.push_back(hl.bwd0.empty() ? 0 : hl.bwd0[p]);
     }
   }
   if (subs_r.size() > 32767) throw Error(NNMS_ERR_INVALID_ARG, "too many subdomains in one batch");
@@ -503,9 +508,9 @@ static void ras_subdescs(const std::vector<nnms_system*>& sys, int l, bool coars
 static void build_ras_pair(Arena& mem, std::vector<int32_t*>& counters, const std::vector<nnms_system*>& sys, int l,
                            bool coarse, int prec, bool with_state, int K, hipStream_t s, RasLaunch& rr, RasLaunch& rt) {
   std::vector<SubDesc> subs_r, subs_t;
-  std::vector<int32_t> Ns;
-  ras_subdescs(sys, l, coarse, prec, with_state, subs_r, subs_t, Ns);
-  std::vector<int32_t> tasks = ras_tasks(Ns, K);
+  std::vector<int32_t> Ns, B0s;
+  ras_subdescs(sys, l, coarse, prec, with_state, subs_r, subs_t, Ns, B0s);
+  std::vector<int32_t> tasks = ras_tasks(Ns, B0s, K);
   int32_t* counter = mem.alloc<int32_t>(4, s);
   HIP_CHECK(launch_ras_seed(counter, s));
   counters.push_back(counter);
@@ -908,6 +913,7 @@ static void build_host(const nnms_mesh* const* levels, int32_t L, const nnms_set
     int np = direct ? 1 : opts->nparts[l];
     if (!direct && np == 0) np = default_nparts(lv.nv * K);
     H.opts.nparts[l] = np;
+    lv.owned_last = !direct && opts->subsolver == NNMS_SUBSOLVER_LU;
     build_partition(lv, np, opts->overlap, direct);
   }
   // transfers between the vertex-level meshes, then every level carried to
@@ -1638,15 +1644,15 @@ static void noalloc_smoother(nnms_system* s, int level, const double* r, double*
   // before any device work
   std::vector<SubDesc> subs, unused;
   std::vector<IluDesc> ilus;
-  std::vector<int32_t> Ns, tasks;
+  std::vector<int32_t> Ns, B0s, tasks;
   const int K = s->h->tune.ras_blocks[level];
   size_t desc_bytes = 0;
   if (ilu) {
     ilus = ilu_descs(*s, level, false);
     desc_bytes = ilus.size() * sizeof(IluDesc);
   } else {
-    ras_subdescs({s}, level, coarse, s->prec, false, subs, unused, Ns);
-    tasks = ras_tasks(Ns, K);
+    ras_subdescs({s}, level, coarse, s->prec, false, subs, unused, Ns, B0s);
+    tasks = ras_tasks(Ns, B0s, K);
     desc_bytes = subs.size() * sizeof(SubDesc);
   }
   const size_t task_off = kScratchTables + ((desc_bytes + 255) & ~size_t(255));

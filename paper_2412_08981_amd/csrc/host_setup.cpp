@@ -231,7 +231,10 @@ void clip_partition(const HostLevel& lv, int nparts, int overlap, std::vector<in
 
 // Dense-factor bookkeeping of the level's subdomains (tile counts, factor
 // offsets, padded index maps with ownership, extraction map of every local
-// row's CSR entries), from the partition and the level's CSR.
+// row's CSR entries), from the partition and the level's CSR.  With
+// lv.owned_last the local order puts the overlap rows first: the restricted
+// solve R^0_p J_p^{-1} needs x_o = inv(U_oo) y_o of the owned rows only
+// (U is upper triangular), so its backward sweep stops at block bwd0[p].
 void build_blocks(HostLevel& lv) {
   const int nparts = lv.nparts;
   lv.nblk.assign(nparts, 0);
@@ -250,17 +253,31 @@ void build_blocks(HostLevel& lv) {
   lv.gidx.assign(lv.g_total, -1);
   lv.ext_rs.assign(lv.s_idx.size() + 1, 0);
   lv.ext_lc.clear();
+  lv.bwd0.assign(nparts, 0);
+  std::vector<int32_t> ord, loc;  // local row -> position in S, and back
   for (int p = 0; p < nparts; ++p) {
     const int32_t* S = lv.s_idx.data() + lv.s_ptr[p];
     int64_t n = lv.s_ptr[p + 1] - lv.s_ptr[p];
+    ord.clear();
+    if (lv.owned_last) {
+      for (int32_t k = 0; k < int32_t(n); ++k)
+        if (lv.owner[S[k]] != p) ord.push_back(k);
+      lv.bwd0[p] = int32_t(ord.size() / TILE);
+      for (int32_t k = 0; k < int32_t(n); ++k)
+        if (lv.owner[S[k]] == p) ord.push_back(k);
+    } else {
+      for (int32_t k = 0; k < int32_t(n); ++k) ord.push_back(k);
+    }
+    loc.assign(n, 0);
+    for (int32_t k = 0; k < int32_t(n); ++k) loc[ord[k]] = k;
     for (int64_t k = 0; k < n; ++k) {
-      int32_t g = S[k];
+      int32_t g = S[ord[k]];
       lv.gidx[lv.g_off[p] + k] = (lv.owner[g] == p) ? g : (-g - 2);
       lv.ext_rs[lv.s_ptr[p] + k] = int32_t(lv.ext_lc.size());
       for (int32_t e = lv.rp[g]; e < lv.rp[g + 1]; ++e) {
         int32_t c = lv.col[e];
         const int32_t* q = std::lower_bound(S, S + n, c);
-        lv.ext_lc.push_back((q != S + n && *q == c) ? int32_t(q - S) : -1);
+        lv.ext_lc.push_back((q != S + n && *q == c) ? loc[q - S] : -1);
       }
     }
   }

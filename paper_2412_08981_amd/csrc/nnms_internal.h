@@ -62,8 +62,16 @@ struct HostLevel {
   std::vector<int64_t> g_off;       // offset into gidx (multiples of 64)
   int64_t g_total = 0;
   std::vector<int32_t> gidx;        // encoded global ids, padded to nblk*64
-  std::vector<int32_t> ext_rs;      // start in ext_lc of every local row (s_total+1, in S order)
+  std::vector<int32_t> ext_rs;      // start in ext_lc of every local row (s_total+1, in local order)
   std::vector<int32_t> ext_lc;      // local column of every CSR entry of every local row, -1 outside S_p
+  // Local order of a dense subdomain: with owned_last, the rows the
+  // subdomain does not own come first and the owned ones last (each part in
+  // ascending global order), so the backward sweep of the restricted solve
+  // only has to run over the owned rows; otherwise S order (ILU levels,
+  // whose factorisation depends on the order).  bwd0[p] = first 64-row block
+  // holding an owned row.
+  bool owned_last = false;
+  std::vector<int32_t> bwd0;
 
   // transfer P_l from level l+1 to l (empty on the coarsest level)
   std::vector<int32_t> p_idx;       // nv*4
