@@ -21,7 +21,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {8: 78.6, 4: 157.3}  # dense FP64 / FP32 matrix peaks
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_ras_cube48_{prec}_pmc.md")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "{kernel}_cube48_{prec}_pmc.md")
 
 
 def source_hash():
@@ -34,18 +34,19 @@ def source_hash():
     csrc = os.path.join(ROOT, "paper_2412_08981_amd", "csrc")
     for name in ("ras.hip", "devcommon.h", "devtypes.h"):
         h.update(open(os.path.join(csrc, name), "rb").read())
-    for name, sig in (("api.hip", b"static std::vector<int32_t> ras_tasks("), ("host_setup.cpp", b"void build_blocks(")):
+    for name, sig in (("api.hip", b"static std::vector<int32_t> ras_tasks("),
+                      ("api.hip", b"static std::vector<int32_t> xpanel_tasks("), ("host_setup.cpp", b"void build_blocks(")):
         text = open(os.path.join(csrc, name), "rb").read()
         i = text.find(sig)
         h.update(text[i:text.find(b"\n}\n", i)] if i >= 0 else b"")
     return h.hexdigest()[:16]
 
 
-def load_traffic(prec):
+def load_traffic(prec, kernel="k_ras"):
     """HBM bytes per launch of the fine-level smoother from the committed
     rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, scaled by the same
     counters on a plain copy of known size), or None when absent or stale."""
-    path = PMC_SUMMARY.format(prec=prec)
+    path = PMC_SUMMARY.format(kernel=kernel, prec=prec)
     if not os.path.exists(path):
         return None
     kv = {}
@@ -63,6 +64,19 @@ def load_traffic(prec):
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def xpanel_bytes(h, level, s_bytes):
+    """Algorithmic bytes of one inverse-panel smoother application on
+    `level`: every entry of X_p = J_p^{-1} E_o once (n_p n_o values), the
+    gathered input and index map, and the scattered owned output."""
+    owner, sets = h.partition(level)
+    owner = np.asarray(owner)
+    n = np.array([len(S) for S in sets], dtype=np.float64)
+    no = np.array([np.count_nonzero(owner[np.asarray(S)] == p) for p, S in enumerate(sets)], dtype=np.float64)
+    if level == h.L - 1:
+        no = n
+    return float(np.sum(n * no) * s_bytes + np.sum(n) * (s_bytes + 4) + np.sum(no) * s_bytes)
 
 
 def ras_bytes(h, level, s_bytes):
@@ -193,12 +207,15 @@ def hierarchy_options(args, nnms):
     command line, and a short description for the workload name."""
     kw = {"transfer": nnms.MLS if args.transfer == "mls" else nnms.BARYCENTRIC, "mls_alpha": args.mls_alpha,
           "subsolver": nnms.ILU if args.subsolver == "ilu" else nnms.LU,
-          "ilu_fill": [int(k) for k in args.ilu_fill.split(",")]}
+          "ilu_fill": [int(k) for k in args.ilu_fill.split(",")],
+          "dense_apply": nnms.INVERSE if args.dense_apply == "inverse" else nnms.SWEEPS}
     desc = ""
     if args.transfer == "mls":
         desc += f", MLS transfer (scale {args.mls_alpha} x mean coarse edge)"
     if args.subsolver == "ilu":
         desc += f", ILU({args.ilu_fill}) subdomain solves"
+    if args.dense_apply == "inverse":
+        desc += ", dense subdomain solves through inverse panels"
     return kw, desc
 
 
@@ -206,8 +223,11 @@ def smoother_bytes(h, level, s_bytes):
     """Algorithmic bytes of one smoother application, dense LU or ILU."""
     from paper_2412_08981_amd import nnms
 
-    if h.level_info(level).subsolver == nnms.ILU:
+    li = h.level_info(level)
+    if li.subsolver == nnms.ILU and level < h.L - 1:
         return ilu_bytes(h, level, s_bytes)
+    if li.dense_apply == nnms.INVERSE:
+        return xpanel_bytes(h, level, s_bytes)
     return ras_bytes(h, level, s_bytes)
 
 
@@ -418,6 +438,9 @@ def main():
     ap.add_argument("--subsolver", default="lu", choices=["lu", "ilu"],
                     help="subdomain solver of the smoother: dense LU or ILU(k)")
     ap.add_argument("--ilu-fill", default="2,0", help="ILU level of fill per smoothed level (finest first)")
+    ap.add_argument("--dense-apply", default="sweeps", choices=["sweeps", "inverse"],
+                    help="dense-LU subdomain solves applied by forward/backward sweeps over the factors, or "
+                         "through the stored owned columns of each subdomain inverse (inverse panels)")
     ap.add_argument("--physics", default="poisson", choices=["poisson", "elasticity"],
                     help="default workload: the scalar 48^3 problem, or P1 linear elasticity (three unknowns per "
                          "vertex, field-split transfers) on 32^3/16^3/7^3 meshes")
@@ -481,11 +504,12 @@ def main():
         pb = W.Problem(pb.name, pb.meshes, nps + pb.nparts[len(nps):], pb.kappa, precision=pb.precision)
     mls_mode = args.transfer == "mls"
     ilu_mode = args.subsolver == "ilu"
+    xinv_mode = args.dense_apply == "inverse"
     ilu_fill = [int(k) for k in args.ilu_fill.split(",")]
     h = nnms.Hierarchy(meshes, pb.nparts, overlap=pb.overlap, its=pb.its, precision=prec,
                        transfer=nnms.MLS if mls_mode else nnms.BARYCENTRIC, mls_alpha=args.mls_alpha,
                        subsolver=nnms.ILU if ilu_mode else nnms.LU, ilu_fill=ilu_fill, ncomp=3 if elastic else 1,
-                       mls_clip=args.mls_clip)
+                       mls_clip=args.mls_clip, dense_apply=nnms.INVERSE if xinv_mode else nnms.SWEEPS)
     t1 = time.perf_counter()
     load = W.ELASTIC_FORCE if elastic else 1.0
 
@@ -516,14 +540,14 @@ def main():
         ms_ras = s.time_kernel(0, 0, reps=10)
         out = {"copy_bytes": (fac_bytes // 16) * 16, "copy_launches": 1 + 3, "copy_ms": ms_copy,
                "read_launches": 1 + 5, "read_ms": ms_read,
-               "ras_launches": 1 + 10, "ras_ms": ms_ras, "ras_algorithmic_bytes": ras_bytes(h, 0, sb),
+               "ras_launches": 1 + 10, "ras_ms": ms_ras, "ras_algorithmic_bytes": smoother_bytes(h, 0, sb),
                "ras_hip_sha256_16": source_hash()}
         if h.L > 2 and h.level_info(1).subsolver != nnms.ILU:
             # the second level: its own copy reference and smoother launches
             fb1 = h.level_info(1).factor_elems * sb
             out.update({"l1_copy_bytes": (fb1 // 16) * 16, "l1_copy_ms": s.time_kernel(4, 1, reps=3),
                         "l1_ras_launches": 1 + 20, "l1_ras_ms": s.time_kernel(0, 1, reps=20),
-                        "l1_ras_algorithmic_bytes": ras_bytes(h, 1, sb)})
+                        "l1_ras_algorithmic_bytes": smoother_bytes(h, 1, sb)})
         print(json.dumps(out))
         return
     b = s.rhs()
@@ -563,7 +587,7 @@ def main():
     # roofline of the dominant kernel: the fine-level smoother
     sb = 8 if prec == nnms.FP64 else 4
     ms = s.time_kernel(0, 0, reps=10)
-    ach = (ilu_bytes(h, 0, sb) if ilu_mode else ras_bytes(h, 0, sb)) / (ms * 1e-3) / 1e9
+    ach = smoother_bytes(h, 0, sb) / (ms * 1e-3) / 1e9
     extra = {}
     if not ilu_mode:
         fac_bytes = (h.level_info(0).factor_elems * sb // 16) * 16
@@ -601,7 +625,8 @@ def main():
     x_mixed = None
     if (not args.no_legs and not coarsened and args.precision == "fp64" and not mls_mode and not ilu_mode
             and not elastic and not args.nparts and args.workload == "cube48"):
-        hm = nnms.Hierarchy(meshes, pb.nparts, overlap=pb.overlap, its=pb.its, precision=nnms.MIXED)
+        hm = nnms.Hierarchy(meshes, pb.nparts, overlap=pb.overlap, its=pb.its, precision=nnms.MIXED,
+                            dense_apply=nnms.INVERSE if xinv_mode else nnms.SWEEPS)
         sm = nnms.System(hm, pb.kappa, 1.0)
         tm = autotune.tune(sm, cache=args.tuning_cache)
         xm = torch.zeros(n0, dtype=torch.float64, device="cuda")
@@ -661,6 +686,7 @@ def main():
                                   + (", neighbourhoods clipped to the target's subdomain)" if args.mls_clip else ")")
                                   if mls_mode else "")
                                + (f", ILU({args.ilu_fill}) subdomain solves" if ilu_mode else "")
+                               + (", dense subdomain solves through inverse panels" if xinv_mode else "")
                                + (f", coarse levels by Algorithm 1 (rounds {rounds}; interior vertices "
                                   f"{[int((m.dirichlet == 0).sum()) for m in coarsened]})" if coarsened else ""),
                    "iterations": info.iterations, "relres": info.relres,
@@ -668,8 +694,10 @@ def main():
                    "tuning": tuning},
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(ach / HBM_PEAK_GBS, 4),
-                     "traffic": None if ilu_mode else load_traffic(args.precision),
+                     "traffic": None if ilu_mode else load_traffic(args.precision,
+                                                                   "k_xapply" if xinv_mode else "k_ras"),
                      "kernel": ("k_ilu_apply (fine-level ILU smoother)" if ilu_mode else
+                                "k_xapply (fine-level smoother, inverse panels)" if xinv_mode else
                                 "k_ras2 (fine-level smoother, two-block work items)" if tuning["ras_blocks"][0] == 2
                                 else "k_ras (fine-level smoother)"), "ms": round(ms, 4)},
         "kernels": extra,

@@ -66,6 +66,7 @@ typedef enum { NNMS_TRANSFER_BARYCENTRIC = 0, NNMS_TRANSFER_MLS = 1 } nnms_trans
  * fill k (Section 4 runs ILU(2) on the finest level and ILU(0) on coarser
  * ones).  The coarsest level is always solved directly. */
 typedef enum { NNMS_SUBSOLVER_LU = 0, NNMS_SUBSOLVER_ILU = 1 } nnms_subsolver;
+typedef enum { NNMS_APPLY_SWEEPS = 0, NNMS_APPLY_INVERSE = 1 } nnms_dense_apply;
 
 typedef struct nnms_mesh nnms_mesh;
 typedef struct nnms_hierarchy nnms_hierarchy;
@@ -165,6 +166,17 @@ void nnms_mesh_destroy(nnms_mesh* m);
  *             interpolation sum_f R_f^T P_l R~_f moves each component with the
  *             scalar P_l (barycentric or MLS).  nparts[l] = 0 then selects
  *             max(2, 2^floor(log2(3 nv_l / 1500))).
+ *             dense_apply (levels with dense LU, the coarsest included):
+ *             NNMS_APPLY_SWEEPS (default) applies R^0_p J_p^{-1} by the
+ *             blocked forward and backward sweeps over the LU factors;
+ *             NNMS_APPLY_INVERSE stores, at every assembly, the owned
+ *             columns of the inverse, X_p = J_p^{-1} E_o (n_p x n_o, from
+ *             the same LU factors by block forward and back substitution;
+ *             on the coarsest level the whole inverse), and applies
+ *             z_o = X_p^T r[S_p] (J_p is symmetric, so X_p^T holds the owned
+ *             rows of J_p^{-1}): the same operator up to rounding, read as
+ *             independent 64-column panels instead of chains of dependent
+ *             blocks, for about twice the numeric setup.
  * nnms_hierarchy_setup_host builds the same structure without touching any
  * GPU (inspection and host tests); such a handle cannot be assembled.
  * ------------------------------------------------------------------------- */
@@ -183,6 +195,7 @@ typedef struct {
                            3 = P1 linear elasticity, see below */
   int32_t mls_clip;     /* with MLS: 1 = clip every neighbourhood to the overlapping
                            subdomain of the target's processor, see below */
+  int32_t dense_apply;  /* nnms_dense_apply of the dense-LU levels, see below */
 } nnms_setup_opts;
 
 /* Geometry-preserving coarsening (Algorithm 1, Section 3.1): `rounds`
@@ -221,14 +234,15 @@ typedef struct {
   int32_t min_block;    /* smallest subdomain size */
   int32_t transfer;     /* nnms_transfer of P_l (smoothed levels) */
   int64_t s_total;      /* sum of subdomain sizes */
-  int64_t factor_elems; /* dense factor entries stored, incl. 64-padding */
+  int64_t factor_elems; /* dense factor entries stored, incl. 64-padding (the
+                           inverse panels of NNMS_APPLY_INVERSE not counted) */
   int64_t p_nnz;        /* entries of P_l (0 on the coarsest level) */
   int32_t subsolver;    /* nnms_subsolver of the level's smoother */
   int32_t mls_restrict; /* 1: the restriction is the fine-to-coarse MLS operator */
   int64_t ilu_nnz;      /* entries of all ILU patterns of the level (0 without ILU) */
   int64_t r_nnz;        /* entries of the restriction (P_l^T or the MLS operator) */
   int32_t ncomp;        /* unknowns per vertex */
-  int32_t reserved;
+  int32_t dense_apply;  /* nnms_dense_apply of a dense level */
   int64_t ndof;         /* unknowns of the level = ncomp * nv: the length of the
                            level's vectors and the rows of every per-row array
                            below (CSR, owner, P_l, ...) */
@@ -382,6 +396,17 @@ nnms_status nnms_system_factor(const nnms_system* s, int32_t level, int32_t part
 nnms_status nnms_system_factor_pairs(const nnms_system* s, int32_t level, int32_t part, double* xl_host, double* xu_host,
                                      int32_t* npairs_host);
 /* Both dense read-backs give NNMS_ERR_INVALID_ARG on an ILU level. */
+
+/* Read-back of the inverse panels of subdomain `part` of `level`
+ * (NNMS_APPLY_INVERSE levels only, else NNMS_ERR_INVALID_ARG), for checks:
+ * X_p = J_p^{-1} E_o, the owned columns of the inverse of the subdomain
+ * matrix in the factor's local order.  x_host (may be NULL: sizes only)
+ * receives the (N*64) x (No*64) matrix row-major, FP32 panels widened;
+ * row k < |S_p| is local row k, column c < n_o is owned row c (local row
+ * |S_p| - n_o + c); padding rows and columns are zero.  *N_out and *No_out
+ * (either may be NULL) receive N and No = ceil(n_o / 64). */
+nnms_status nnms_system_inverse_panels(const nnms_system* s, int32_t level, int32_t part, double* x_host,
+                                       int32_t* N_out, int32_t* No_out);
 
 /* Read-back of the ILU factors of an ILU level: val_host[ilu_nnz] in the
  * order of nnms_hierarchy_ilu_pattern, L's multipliers (unit diagonal not

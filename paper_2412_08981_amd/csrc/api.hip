@@ -191,6 +191,7 @@ struct SysLevel {
   void* z = nullptr;
   void* t = nullptr;
   void* ilu_val = nullptr;  // ILU factor values (factor type), ILU levels only
+  void* xinv = nullptr;     // inverse panels X_p (factor type), NNMS_APPLY_INVERSE only
 };
 
 struct Plan;
@@ -471,6 +472,21 @@ static std::vector<int32_t> ras_tasks(const std::vector<int32_t>& N, const std::
   return out;
 }
 
+// work items of an inverse-panel launch: one per (subdomain, tile column of
+// X_p), the subdomain in the high 16 bits
+static std::vector<int32_t> xpanel_tasks(const std::vector<SubDesc>& subs) {
+  std::vector<int32_t> out;
+  for (size_t q = 0; q < subs.size(); ++q)
+    for (int j = 0; j < (subs[q].no + TILE - 1) / TILE; ++j) out.push_back(int32_t((q << 16) | j));
+  return out;
+}
+
+// smoother work-item kind of a system's level: blocks per triangular-sweep
+// work item (the hierarchy's tuning), or 0 for inverse panels
+static int ras_kind(const nnms_system* x, int l) {
+  return x->h->host.lev[l].xinv ? 0 : x->h->tune.ras_blocks[l];
+}
+
 // The two smoother launches of level l over a set of systems (input r_l with
 // z written, input t_l with z added), for work items of K blocks; flags,
 // tasks and the ticket counter are allocated in `mem`.
@@ -488,8 +504,13 @@ static void ras_subdescs(const std::vector<nnms_system*>& sys, int l, bool coars
     const size_t fsz = (coarse || prec == NNMS_FP64) ? sizeof(double) : sizeof(float);
     for (int p = 0; p < hl.nparts; ++p) {
       SubDesc d{};
-      d.fac = (const char*)sl.fac + size_t(hl.fac_off[p]) * fsz;
+      if (hl.xinv)
+        d.fac = (const char*)sl.xinv + size_t(hl.x_off[p]) * fsz;
+      else
+        d.fac = (const char*)sl.fac + size_t(hl.fac_off[p]) * fsz;
       d.gidx = dl.gidx + hl.g_off[p];
+      d.no = hl.nown[p];
+      d.nv = int32_t(hl.s_ptr[p + 1] - hl.s_ptr[p]) - hl.nown[p];
       d.yx = (char*)sl.yx + size_t(hl.g_off[p]) * 16;
       d.rin = sl.r;
       d.zout = sl.z;
@@ -510,7 +531,7 @@ static void build_ras_pair(Arena& mem, std::vector<int32_t*>& counters, const st
   std::vector<SubDesc> subs_r, subs_t;
   std::vector<int32_t> Ns, B0s;
   ras_subdescs(sys, l, coarse, prec, with_state, subs_r, subs_t, Ns, B0s);
-  std::vector<int32_t> tasks = ras_tasks(Ns, B0s, K);
+  std::vector<int32_t> tasks = K == 0 ? xpanel_tasks(subs_r) : ras_tasks(Ns, B0s, K);
   int32_t* counter = mem.alloc<int32_t>(4, s);
   HIP_CHECK(launch_ras_seed(counter, s));
   counters.push_back(counter);
@@ -521,6 +542,7 @@ static void build_ras_pair(Arena& mem, std::vector<int32_t*>& counters, const st
   rr.ntasks = int(tasks.size());
   rr.add = 0;
   rr.group = K;
+  for (int32_t n : Ns) rr.max_tiles = std::max(rr.max_tiles, n);
   rt = rr;
   rt.subs = mem.upload(subs_t, s);
   rt.add = 1;
@@ -601,13 +623,13 @@ static void build_plan(Plan& P, const std::vector<nnms_system*>& sys, bool with_
   auto ras_groups_of = [&](int l, bool coarse) {
     std::vector<int> ks;
     for (auto* x : sys)
-      if (dense_at(x, l, coarse) && std::find(ks.begin(), ks.end(), x->h->tune.ras_blocks[l]) == ks.end())
-        ks.push_back(x->h->tune.ras_blocks[l]);
+      if (dense_at(x, l, coarse) && std::find(ks.begin(), ks.end(), ras_kind(x, l)) == ks.end())
+        ks.push_back(ras_kind(x, l));
     std::vector<RasGroup> out;
     for (int K : ks) {
       std::vector<nnms_system*> sub;
       for (auto* x : sys)
-        if (dense_at(x, l, coarse) && x->h->tune.ras_blocks[l] == K) sub.push_back(x);
+        if (dense_at(x, l, coarse) && ras_kind(x, l) == K) sub.push_back(x);
       RasGroup G;
       const int g = sub[0]->h->tune.ras_groups[l];
       G.grid = g > 0 ? g : ras_grid_default();
@@ -893,7 +915,8 @@ static void build_host(const nnms_mesh* const* levels, int32_t L, const nnms_set
       (opts->transfer != NNMS_TRANSFER_BARYCENTRIC && opts->transfer != NNMS_TRANSFER_MLS) ||
       (opts->transfer == NNMS_TRANSFER_MLS && !(opts->mls_alpha > 0)) ||
       (opts->subsolver != NNMS_SUBSOLVER_LU && opts->subsolver != NNMS_SUBSOLVER_ILU) ||
-      (opts->ncomp != 0 && opts->ncomp != 1 && opts->ncomp != 3) || (opts->mls_clip != 0 && opts->mls_clip != 1))
+      (opts->ncomp != 0 && opts->ncomp != 1 && opts->ncomp != 3) || (opts->mls_clip != 0 && opts->mls_clip != 1) ||
+      (opts->dense_apply != NNMS_APPLY_SWEEPS && opts->dense_apply != NNMS_APPLY_INVERSE))
     throw Error(NNMS_ERR_INVALID_ARG, "bad setup options");
   const int K = opts->ncomp ? opts->ncomp : 1;
   H.L = L;
@@ -914,6 +937,7 @@ static void build_host(const nnms_mesh* const* levels, int32_t L, const nnms_set
     if (!direct && np == 0) np = default_nparts(lv.nv * K);
     H.opts.nparts[l] = np;
     lv.owned_last = !direct && opts->subsolver == NNMS_SUBSOLVER_LU;
+    lv.xinv = opts->dense_apply == NNMS_APPLY_INVERSE && (direct || opts->subsolver == NNMS_SUBSOLVER_LU);
     build_partition(lv, np, opts->overlap, direct);
   }
   // transfers between the vertex-level meshes, then every level carried to
@@ -1046,6 +1070,7 @@ extern "C" nnms_status nnms_hierarchy_level_info(const nnms_hierarchy* h, int32_
   std::memset(o, 0, sizeof *o);
   o->nv = lv.nvert, o->nt = lv.nt, o->ninterior = lv.nint / lv.ncomp, o->nnz = int64_t(lv.col.size());
   o->ncomp = lv.ncomp, o->ndof = lv.nv;
+  o->dense_apply = lv.xinv ? NNMS_APPLY_INVERSE : NNMS_APPLY_SWEEPS;
   o->nparts = lv.nparts;
   int mx = 0, mn = INT32_MAX;
   for (int p = 0; p < lv.nparts; ++p) {
@@ -1167,6 +1192,7 @@ static SysLayout system_layout(const HostHierarchy& H, int prec, int cap, int ka
       T(int64_t(lv.nparts) * int64_t(sizeof(IluDesc)));
     } else {
       R(std::max<int64_t>(lv.fac_elems * fsz, 256)), R(lv.g_total * 16);
+      if (lv.xinv) R(lv.x_elems * fsz);
       T(int64_t(lv.nparts) * int64_t(sizeof(FacDesc)));
     }
     R(lv.nv * tsz), R(lv.nv * tsz), R(lv.nv * tsz);
@@ -1202,6 +1228,11 @@ struct FactorJob {
   bool f64 = true;
   void* fac = nullptr;
   int64_t elems = 0;
+  // inverse panels: X_p from the factors (forward steps over the owned tile
+  // rows' span, then backward steps over all tile rows)
+  void* x = nullptr;
+  int64_t x_elems = 0;
+  int maxNo = 0, fsteps = 0, bsteps = 0;
 };
 
 static FactorJob factor_job(const nnms_system& sys, int l, Arena& mem, hipStream_t s) {
@@ -1225,8 +1256,17 @@ static FactorJob factor_job(const nnms_system& sys, int l, Arena& mem, hipStream
     d.n = int(hl.s_ptr[p + 1] - hl.s_ptr[p]);
     d.N = hl.nblk[p];
     job.maxn = std::max(job.maxn, d.n), job.maxN = std::max(job.maxN, d.N);
+    if (hl.xinv) {
+      d.X = (char*)sl.xinv + size_t(hl.x_off[p]) * fsz;
+      d.nv = d.n - hl.nown[p];
+      d.No = (hl.nown[p] + TILE - 1) / TILE;
+      job.maxNo = std::max(job.maxNo, d.No);
+      job.fsteps = std::max(job.fsteps, d.N - d.nv / TILE);
+      job.bsteps = std::max(job.bsteps, d.N);
+    }
     fd.push_back(d);
   }
+  if (hl.xinv) job.x = sl.xinv, job.x_elems = hl.x_elems;
   job.d = mem.upload(fd, s);
   job.nd = int(fd.size());
   job.fac = sl.fac;
@@ -1234,16 +1274,19 @@ static FactorJob factor_job(const nnms_system& sys, int l, Arena& mem, hipStream
   return job;
 }
 
-static hipError_t enqueue_factor(const FactorJob& j, int* err, hipStream_t s) {
+template <typename F>
+static hipError_t enqueue_factor_t(const FactorJob& j, int* err, hipStream_t s) {
   hipError_t e;
-  if (j.f64) {
-    if ((e = launch_fill<double>((double*)j.fac, j.elems, 0.0, s)) != hipSuccess) return e;
-    if ((e = launch_extract<double>(j.d, j.nd, j.maxn, s)) != hipSuccess) return e;
-    return launch_lu<double>(j.d, j.nd, j.maxN, err, s);
-  }
-  if ((e = launch_fill<float>((float*)j.fac, j.elems, 0.0f, s)) != hipSuccess) return e;
-  if ((e = launch_extract<float>(j.d, j.nd, j.maxn, s)) != hipSuccess) return e;
-  return launch_lu<float>(j.d, j.nd, j.maxN, err, s);
+  if ((e = launch_fill<F>((F*)j.fac, j.elems, F(0), s)) != hipSuccess) return e;
+  if ((e = launch_extract<F>(j.d, j.nd, j.maxn, s)) != hipSuccess) return e;
+  if ((e = launch_lu<F>(j.d, j.nd, j.maxN, err, s)) != hipSuccess) return e;
+  if (!j.x) return hipSuccess;
+  if ((e = launch_fill<F>((F*)j.x, j.x_elems, F(0), s)) != hipSuccess) return e;
+  return launch_xinv<F>(j.d, j.nd, j.maxNo, j.fsteps, j.bsteps, s);
+}
+
+static hipError_t enqueue_factor(const FactorJob& j, int* err, hipStream_t s) {
+  return j.f64 ? enqueue_factor_t<double>(j, err, s) : enqueue_factor_t<float>(j, err, s);
 }
 
 // ILU factors of one level: values from the level's CSR (0 on fill), then
@@ -1403,6 +1446,7 @@ extern "C" nnms_status nnms_assemble_ex(nnms_hierarchy* h, const nnms_assemble_o
     } else {
       sl.fac = A.raw(std::max<size_t>(size_t(hl.fac_elems) * fsz, 256));
       sl.yx = A.alloc<char>(size_t(hl.g_total) * 16, s);  // tagged block results: 16 bytes per value
+      if (hl.xinv) sl.xinv = A.raw(size_t(hl.x_elems) * fsz);
     }
     sl.r = A.alloc<char>(hl.nv * tsz, s);
     sl.z = A.alloc<char>(hl.nv * tsz, s);
@@ -1645,14 +1689,14 @@ static void noalloc_smoother(nnms_system* s, int level, const double* r, double*
   std::vector<SubDesc> subs, unused;
   std::vector<IluDesc> ilus;
   std::vector<int32_t> Ns, B0s, tasks;
-  const int K = s->h->tune.ras_blocks[level];
+  const int K = ras_kind(s, level);
   size_t desc_bytes = 0;
   if (ilu) {
     ilus = ilu_descs(*s, level, false);
     desc_bytes = ilus.size() * sizeof(IluDesc);
   } else {
     ras_subdescs({s}, level, coarse, s->prec, false, subs, unused, Ns, B0s);
-    tasks = ras_tasks(Ns, B0s, K);
+    tasks = K == 0 ? xpanel_tasks(subs) : ras_tasks(Ns, B0s, K);
     desc_bytes = subs.size() * sizeof(SubDesc);
   }
   const size_t task_off = kScratchTables + ((desc_bytes + 255) & ~size_t(255));
@@ -1684,6 +1728,7 @@ static void noalloc_smoother(nnms_system* s, int level, const double* r, double*
     rl.ntasks = int(tasks.size());
     rl.add = 0;
     rl.group = K;
+    for (int32_t nb : Ns) rl.max_tiles = std::max(rl.max_tiles, nb);
     const int g = s->h->tune.ras_groups[level];
     if (coarse)
       HIP_CHECK((launch_ras<double, T>(rl, g > 0 ? g : ras_grid_default(), st)));
@@ -2092,6 +2137,37 @@ extern "C" nnms_status nnms_system_factor(const nnms_system* s, int32_t level, i
   ABI_END
 }
 
+extern "C" nnms_status nnms_system_inverse_panels(const nnms_system* s, int32_t level, int32_t part, double* x,
+                                                  int32_t* N_out, int32_t* No_out) {
+  ABI_BEGIN
+  if (!s || level < 0 || level >= s->h->host.L) throw Error(NNMS_ERR_INVALID_ARG, "bad level");
+  const HostLevel& hl = s->h->host.lev[level];
+  if (part < 0 || part >= hl.nparts) throw Error(NNMS_ERR_INVALID_ARG, "bad part");
+  if (!hl.xinv) throw Error(NNMS_ERR_INVALID_ARG, "the level does not apply inverse panels");
+  const int N = hl.nblk[part], No = (hl.nown[part] + TILE - 1) / TILE;
+  if (N_out) *N_out = N;
+  if (No_out) *No_out = No;
+  if (!x) return NNMS_OK;
+  const bool f64 = (level == s->h->host.L - 1) || s->prec == NNMS_FP64;
+  const size_t fsz = f64 ? 8 : 4;
+  std::vector<char> raw(size_t(N) * No * TILE_ELEMS * fsz);
+  HIP_CHECK(hipMemcpy(raw.data(), (const char*)s->lev[level].xinv + size_t(hl.x_off[part]) * fsz, raw.size(),
+                      hipMemcpyDeviceToHost));
+  const size_t cols = size_t(No) * 64;
+  for (int tj = 0; tj < No; ++tj)
+    for (int ti = 0; ti < N; ++ti) {
+      const size_t tile = size_t(tj) * N + ti;
+      for (int r = 0; r < 64; ++r)
+        for (int c = 0; c < 64; ++c) {
+          const double v = f64 ? ((const double*)raw.data())[tile * TILE_ELEMS + ((c / 2) * 64 + r) * 2 + (c % 2)]
+                               : ((const float*)raw.data())[tile * TILE_ELEMS + ((c / 4) * 64 + r) * 4 + (c % 4)];
+          x[(size_t(ti) * 64 + r) * cols + size_t(tj) * 64 + c] = v;
+        }
+    }
+  return NNMS_OK;
+  ABI_END
+}
+
 extern "C" nnms_status nnms_system_factor_pairs(const nnms_system* s, int32_t level, int32_t part, double* xl,
                                                 double* xu, int32_t* npairs) {
   ABI_BEGIN
@@ -2255,9 +2331,11 @@ extern "C" nnms_status nnms_autotune(nnms_system* s, int32_t reps, nnms_tuning* 
     t.pt_lanes[l] = spmv_best(dl.pt_rp, dl.pt_col, ptw, sl.t, nullptr, s->lev[l + 1].r, nc, f64, dl.pts_off,
                               dl.pts_col, ptsw);
     // the dense smoother's launch shape (ILU levels have no dense factors)
-    if (h->host.lev[l].subsolver != NNMS_SUBSOLVER_ILU) ras_best(l, false, t.ras_groups[l], t.ras_blocks[l]);
+    // (ILU levels have no dense factors; inverse panels have no shape to choose)
+    if (h->host.lev[l].subsolver != NNMS_SUBSOLVER_ILU && !h->host.lev[l].xinv)
+      ras_best(l, false, t.ras_groups[l], t.ras_blocks[l]);
   }
-  ras_best(L - 1, true, t.ras_groups[L - 1], t.ras_blocks[L - 1]);
+  if (!h->host.lev[L - 1].xinv) ras_best(L - 1, true, t.ras_groups[L - 1], t.ras_blocks[L - 1]);
   for (int32_t* c : tcounters) {
     int32_t v[4];
     HIP_CHECK(hipMemcpy(v, c, sizeof v, hipMemcpyDeviceToHost));

@@ -58,7 +58,9 @@ struct ProlongDesc {
   int32_t blk0;
 };
 
-// One overlapping subdomain of one system, for the triangular-solve kernel.
+// One overlapping subdomain of one system, for the triangular-solve kernel
+// (sweeps) or the inverse-panel kernel (fac = X_p, N x No tiles, column-major
+// tile order; the owned rows are local rows nv .. nv + no - 1).
 struct SubDesc {
   const void* fac;      // N*N tiles (L below, U above, inv(U_ii) on the diagonal) + N tiles inv(L_ii)
   const int32_t* gidx;  // N*64 encoded global ids: >=0 owned, <=-2 overlap (-g-2), -1 padding
@@ -67,17 +69,20 @@ struct SubDesc {
   void* zout;           // level correction vector
   const KState* st;     // null: always active
   int32_t N;
+  int32_t nv;           // local rows before the owned ones (inverse panels)
+  int32_t no;           // owned rows (inverse panels)
   int32_t pad;
 };
 
 struct RasLaunch {
   const SubDesc* subs;
-  const int32_t* tasks;  // (sub << 16) | (dir << 15) | work item (group of K blocks)
+  const int32_t* tasks;  // (sub << 16) | (dir << 15) | work item (group of K blocks);
+                         // inverse panels (group 0): (sub << 16) | tile column
   int32_t* counter;      // [0] ticket, [1] this launch's epoch, [2] error bits
   int32_t ntasks;
   int32_t add;           // z += x (1) or z = x (0)
-  int32_t group;         // 64-row blocks per work item (1, 2 or 4)
-  int32_t pad;
+  int32_t group;         // 64-row blocks per work item (1, 2 or 4); 0: inverse panels
+  int32_t max_tiles;     // largest N among the subdomains
 };
 
 // One subdomain's ILU(k) factor for the factorisation and apply kernels.
@@ -111,6 +116,9 @@ struct FacDesc {
   const double* val;      // level FP64 values
   int32_t n;
   int32_t N;
+  void* X;                // inverse panels (null: sweeps only), N x No tiles, column-major tile order
+  int32_t nv;             // local rows before the owned ones
+  int32_t No;             // tile columns of X: ceil(owned rows / 64)
 };
 
 struct KrylovDesc {

@@ -254,6 +254,8 @@ void build_blocks(HostLevel& lv) {
   lv.ext_rs.assign(lv.s_idx.size() + 1, 0);
   lv.ext_lc.clear();
   lv.bwd0.assign(nparts, 0);
+  lv.nown.assign(nparts, 0);
+  lv.x_off.assign(nparts + 1, 0);
   std::vector<int32_t> ord, loc;  // local row -> position in S, and back
   for (int p = 0; p < nparts; ++p) {
     const int32_t* S = lv.s_idx.data() + lv.s_ptr[p];
@@ -270,6 +272,11 @@ void build_blocks(HostLevel& lv) {
     }
     loc.assign(n, 0);
     for (int32_t k = 0; k < int32_t(n); ++k) loc[ord[k]] = k;
+    for (int32_t k = 0; k < int32_t(n); ++k) lv.nown[p] += lv.owner[S[k]] == p;
+    if (lv.xinv && !lv.owned_last && lv.nown[p] != int32_t(n))
+      throw Error(NNMS_ERR_INVALID_ARG, "inverse panels need the owned rows last");
+    const int64_t No = (lv.nown[p] + TILE - 1) / TILE;
+    lv.x_off[p + 1] = lv.x_off[p] + (lv.xinv ? int64_t(lv.nblk[p]) * No * TILE_ELEMS : 0);
     for (int64_t k = 0; k < n; ++k) {
       int32_t g = S[ord[k]];
       lv.gidx[lv.g_off[p] + k] = (lv.owner[g] == p) ? g : (-g - 2);
@@ -283,6 +290,7 @@ void build_blocks(HostLevel& lv) {
   }
   if (lv.ext_lc.size() > size_t(INT32_MAX)) throw Error(NNMS_ERR_INVALID_ARG, "subdomains too large");
   lv.ext_rs[lv.s_idx.size()] = int32_t(lv.ext_lc.size());
+  lv.x_elems = lv.x_off[nparts];
 }
 
 // ---------------------------------------------------------------------------

@@ -41,6 +41,11 @@ hipError_t launch_extract(const FacDesc* d, int nd, int maxn, hipStream_t s);
 // complete blocked LU of every subdomain (maxN = largest tile count)
 template <typename F>
 hipError_t launch_lu(const FacDesc* d, int nd, int maxN, int* err, hipStream_t s);
+// inverse panels X_p = J_p^{-1} E_o of every subdomain with d.X set, from its
+// LU factors: fsteps block forward-substitution launches, then bsteps block
+// back-substitution launches (X zero-filled before)
+template <typename F>
+hipError_t launch_xinv(const FacDesc* d, int nd, int maxNo, int fsteps, int bsteps, hipStream_t s);
 
 // ilu.hip: values of the ILU pattern from the level's FP64 CSR values (0 on
 // fill), the factorisation (err set on a non-positive pivot) and the

@@ -217,27 +217,34 @@ __device__ __forceinline__ void frag_mma(const Frag<F>& f, typename Mma<F>::acc_
   }
 }
 
-// acc += sum_{s<depth} Ls(s) * Us(s), where Ls(s) = fac + lt0 + s*lstep tiles and
-// Us(s) = fac + ut0 + s*ustep tiles; operand loads run one group ahead.
+// acc += sum_{s<depth} Ls(s) * Us(s), where Ls(s) = a + lt0 + s*lstep tiles and
+// Us(s) = b + ut0 + s*ustep tiles; operand loads run one group ahead.
 template <typename F>
-__device__ __forceinline__ void acc_add_products(typename Mma<F>::acc_t (&acc)[2][2], const GLOBAL F* __restrict__ fac,
-                                                 size_t lt0, size_t lstep, size_t ut0, size_t ustep, int depth) {
+__device__ __forceinline__ void acc_add_products(typename Mma<F>::acc_t (&acc)[2][2], const GLOBAL F* __restrict__ a,
+                                                 size_t lt0, size_t lstep, const GLOBAL F* __restrict__ b, size_t ut0,
+                                                 size_t ustep, int depth) {
   if (depth <= 0) return;
   const int ng = 4 * depth;
   Frag<F> f0, f1;
-  frag_load<F>(f0, fac + lt0 * TILE_ELEMS, fac + ut0 * TILE_ELEMS, 0);
+  frag_load<F>(f0, a + lt0 * TILE_ELEMS, b + ut0 * TILE_ELEMS, 0);
   for (int g = 0; g < ng; g += 2) {
     {
       const int h = g + 1, s = h >> 2;  // ng is even: h < ng
-      frag_load<F>(f1, fac + (lt0 + s * lstep) * TILE_ELEMS, fac + (ut0 + s * ustep) * TILE_ELEMS, h & 3);
+      frag_load<F>(f1, a + (lt0 + s * lstep) * TILE_ELEMS, b + (ut0 + s * ustep) * TILE_ELEMS, h & 3);
     }
     frag_mma<F>(f0, acc);
     if (g + 2 < ng) {
       const int h = g + 2, s = h >> 2;
-      frag_load<F>(f0, fac + (lt0 + s * lstep) * TILE_ELEMS, fac + (ut0 + s * ustep) * TILE_ELEMS, h & 3);
+      frag_load<F>(f0, a + (lt0 + s * lstep) * TILE_ELEMS, b + (ut0 + s * ustep) * TILE_ELEMS, h & 3);
     }
     frag_mma<F>(f1, acc);
   }
+}
+
+template <typename F>
+__device__ __forceinline__ void acc_add_products(typename Mma<F>::acc_t (&acc)[2][2], const GLOBAL F* __restrict__ fac,
+                                                 size_t lt0, size_t lstep, size_t ut0, size_t ustep, int depth) {
+  acc_add_products<F>(acc, fac, lt0, lstep, fac, ut0, ustep, depth);
 }
 
 // acc = T - sum_{s<depth} Ls(s) * Us(s)
@@ -639,9 +646,88 @@ hipError_t launch_lu(const FacDesc* d, int nd, int maxN, int* err, hipStream_t s
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Inverse panels.  With the owned rows last (local rows nv .. n-1), the
+// owned columns of J^{-1} are X = U^{-1} L^{-1} E_o, E_o = [0; I]: column c
+// of E_o is the unit vector of local row nv + c.  In 64 x 64 tiles (X has
+// the factor's tile rows i and tile columns j over the owned columns):
+//   forward   Y_ij = inv(L_ii) (E_ij - sum_{m0(j) <= m < i} L_im Y_mj),
+//             where Y_mj = 0 for m < m0(j) = floor((nv + 64 j) / 64) (the
+//             unit vectors of column tile j start in tile row m0(j));
+//   backward  X_ij = inv(U_ii) (Y_ij - sum_{m > i} U_im X_mj),  i = N-1 .. 0,
+// one launch per tile row (the rows depend on each other), every
+// (subdomain, tile column) of that row a work-group; X overwrites Y in
+// place.  Tile (i, j) of X sits at tile j N + i.  Padding rows (unit
+// diagonal in the factor, no unit vector) and padding columns stay zero.
+// ---------------------------------------------------------------------------
+template <typename F>
+__global__ __launch_bounds__(256) void k_xinv(const FacDesc* __restrict__ d, int step, int fwd) {
+  const FacDesc D = d[blockIdx.y];
+  const int j = int(blockIdx.x);
+  if (!D.X || j >= D.No) return;
+  const int N = D.N;
+  int i, m0 = 0;
+  if (fwd) {
+    m0 = (D.nv + 64 * j) / 64;
+    i = D.nv / 64 + step;
+    if (i >= N || i < m0) return;  // past the last tile row, or a zero tile
+  } else {
+    i = N - 1 - step;
+    if (i < 0) return;
+  }
+  __shared__ F As[64][LDP], Bs[64][LDP];
+  const size_t n = size_t(N), NN = n * n, col = size_t(j) * n;
+  const GLOBAL F* fac = gptr((const F*)D.fac);
+  GLOBAL F* X = gptr((F*)D.X);
+  typename Mma<F>::acc_t acc[2][2];
+  if (fwd) {
+    // acc = -E_ij: E(r, c) = 1 where 64 i + r = nv + 64 j + c, for owned columns 64 j + c < n - nv
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int R0 = (wave >> 1) * 32, C0 = (wave & 1) * 32;
+    const int off = D.nv + 64 * j - 64 * i, nown = D.n - D.nv;
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = R0 + rb * 16 + Mma<F>::row(lane, v), c = C0 + cb * 16 + (lane & 15);
+          acc[rb][cb][v] = (r == c + off && 64 * j + c < nown) ? F(-1) : F(0);
+        }
+    acc_add_products<F>(acc, fac, size_t(i) * n + m0, 1, X, col + m0, 1, i - m0);
+    acc_negate<F>(acc);
+    acc_to_lds<F>(acc, Bs);
+    tile_to_lds<F>(fac + (NN + i) * TILE_ELEMS, As);  // inv(L_ii)
+  } else {
+    acc_load<F>(X + (col + i) * TILE_ELEMS, acc);
+    acc_negate<F>(acc);
+    acc_add_products<F>(acc, fac, size_t(i) * n + i + 1, 1, X, col + i + 1, 1, N - 1 - i);
+    acc_negate<F>(acc);
+    acc_to_lds<F>(acc, Bs);
+    tile_to_lds<F>(fac + (size_t(i) * n + i) * TILE_ELEMS, As);  // inv(U_ii), the diagonal tile
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) acc[u][v] = typename Mma<F>::acc_t{0, 0, 0, 0};
+  tile_mma<F>(As, Bs, acc);
+  acc_store<F>(acc, X + (col + i) * TILE_ELEMS);
+}
+
+template <typename F>
+hipError_t launch_xinv(const FacDesc* d, int nd, int maxNo, int fsteps, int bsteps, hipStream_t s) {
+  if (nd <= 0 || maxNo <= 0) return hipSuccess;
+  for (int k = 0; k < fsteps; ++k) hipLaunchKernelGGL((k_xinv<F>), dim3(maxNo, nd), dim3(256), 0, s, d, k, 1);
+  for (int k = 0; k < bsteps; ++k) hipLaunchKernelGGL((k_xinv<F>), dim3(maxNo, nd), dim3(256), 0, s, d, k, 0);
+  return hipGetLastError();
+}
+
 template hipError_t launch_extract<double>(const FacDesc*, int, int, hipStream_t);
 template hipError_t launch_extract<float>(const FacDesc*, int, int, hipStream_t);
 template hipError_t launch_lu<double>(const FacDesc*, int, int, int*, hipStream_t);
 template hipError_t launch_lu<float>(const FacDesc*, int, int, int*, hipStream_t);
+template hipError_t launch_xinv<double>(const FacDesc*, int, int, int, int, hipStream_t);
+template hipError_t launch_xinv<float>(const FacDesc*, int, int, int, int, hipStream_t);
 
 }  // namespace nnms

@@ -72,6 +72,14 @@ struct HostLevel {
   // holding an owned row.
   bool owned_last = false;
   std::vector<int32_t> bwd0;
+  // Explicit inverse panels (NNMS_APPLY_INVERSE): X_p = J_p^{-1} E_o, N x No
+  // tiles in column-major tile order (tile (i, j) at x_off[p] + (j N + i)
+  // tiles), No = ceil(n_o / 64); nown[p] = n_o, the owned rows, which are
+  // local rows n - n_o .. n-1.
+  bool xinv = false;
+  std::vector<int32_t> nown;
+  std::vector<int64_t> x_off;
+  int64_t x_elems = 0;
 
   // transfer P_l from level l+1 to l (empty on the coarsest level)
   std::vector<int32_t> p_idx;       // nv*4

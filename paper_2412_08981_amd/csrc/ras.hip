@@ -627,9 +627,117 @@ __global__ __launch_bounds__(256, (RasWaves<F, 2>::value)) void k_ras2(RasLaunch
   }
 }
 
+// ---------------------------------------------------------------------------
+// Inverse panels: z_o = X_p^T r[S_p] with X_p = J_p^{-1} E_o stored as N x No
+// tiles, column-major tile order.  A work-group takes one tile column j of
+// one subdomain (owned rows 64 j .. 64 j + 63) and streams its N tiles: lane
+// l of wave w keeps row l of every tile and the 16-byte column chunks w,
+// w + 4, ..., accumulating X[r][c] r[S_p][r] per column over the tiles;
+// the 64 row partial sums of every column are added at the end through
+// LDS, in a fixed order (so a batch gives every system the bits it gets
+// alone).  No work-group waits for another.  r[S_p] is gathered into LDS
+// first (YL), or read per tile when it does not fit.
+// ---------------------------------------------------------------------------
+template <typename F, typename V, bool YL>
+__global__ __launch_bounds__(256, 2) void k_xapply(RasLaunch P) {
+  using C = typename Chunk<F>::type;
+  constexpr int W = Chunk<F>::W;
+  constexpr int NQ = 16 / W;  // 16-byte chunks per lane per tile
+  extern __shared__ __align__(16) unsigned char xsh[];
+  F* ysh = (F*)xsh;  // N*64 gathered values, then the column reduction
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int code = gptr(P.tasks)[blockIdx.x];
+  const int sub = code >> 16, j = code & 0xffff;
+  const SubDesc S = P.subs[sub];
+  if (!slot_active(S.st, WHEN_RUNNING)) return;
+  const int N = S.N;
+  const GLOBAL C* base = gptr((const C*)((const F*)S.fac + size_t(j) * N * TILE_ELEMS));
+  const GLOBAL int32_t* gidx = gptr(S.gidx);
+  const GLOBAL V* rin = gptr((const V*)S.rin);
+  auto load_tile = [&](int i, C (&reg)[NQ]) {
+    const GLOBAL C* t = base + size_t(i) * (TILE_ELEMS / W);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) reg[q] = __builtin_nontemporal_load(t + (wave + 4 * q) * 64 + lane);
+  };
+  auto gathered = [&](int k) -> F {
+    const int g = gidx[k];
+    return g == -1 ? F(0) : F(rin[g >= 0 ? g : -g - 2]);
+  };
+  C R0[NQ], R1[NQ], R2[NQ], R3[NQ];
+  load_tile(0, R0);
+  if (N > 1) load_tile(1, R1);
+  if (N > 2) load_tile(2, R2);
+  if (N > 3) load_tile(3, R3);
+  if (YL) {
+    for (int k = tid; k < N * 64; k += 256) ysh[k] = gathered(k);
+    __syncthreads();
+  }
+  C acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) acc[q] = C{};
+  auto apply = [&](const C (&R)[NQ], int i) {
+    const F y = YL ? ysh[i * 64 + lane] : gathered(i * 64 + lane);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] += R[q] * y;
+  };
+  for (int i = 0; i < N; i += 4) {
+    apply(R0, i);
+    // refill a ring slot only after its last use (no double buffering)
+    __builtin_amdgcn_sched_barrier(0);
+    if (i + 4 < N) load_tile(i + 4, R0);
+    if (i + 1 < N) {
+      apply(R1, i + 1);
+      __builtin_amdgcn_sched_barrier(0);
+      if (i + 5 < N) load_tile(i + 5, R1);
+    }
+    if (i + 2 < N) {
+      apply(R2, i + 2);
+      __builtin_amdgcn_sched_barrier(0);
+      if (i + 6 < N) load_tile(i + 6, R2);
+    }
+    if (i + 3 < N) {
+      apply(R3, i + 3);
+      __builtin_amdgcn_sched_barrier(0);
+      if (i + 7 < N) load_tile(i + 7, R3);
+    }
+  }
+  __syncthreads();  // every read of the gathered values is done
+  F(*red)[65] = (F(*)[65])xsh;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int k = 0; k < W; ++k) red[(wave + 4 * q) * W + k][lane] = acc[q][k];
+  __syncthreads();
+  if (tid < 64) {
+    F sum = 0;
+    for (int r = 0; r < 64; ++r) sum += red[tid][r];
+    const int oc = 64 * j + tid;  // owned row index; local row nv + oc
+    if (oc < S.no) {
+      const int g = gidx[S.nv + oc];
+      GLOBAL V* z = gptr((V*)S.zout);
+      z[g] = P.add ? V(z[g] + V(sum)) : V(sum);
+    }
+  }
+}
+
+// LDS of an inverse-panel work-group holding the gathered vector (else only
+// the column reduction)
+constexpr size_t XAPPLY_MAX_LDS = 65536;
+
+template <typename F, typename V>
+static hipError_t launch_xapply(const RasLaunch& p, hipStream_t s) {
+  const size_t red = 64 * 65 * sizeof(F), ylds = size_t(p.max_tiles) * 64 * sizeof(F);
+  if (ylds <= XAPPLY_MAX_LDS)
+    hipLaunchKernelGGL((k_xapply<F, V, true>), dim3(p.ntasks), dim3(256), ylds > red ? ylds : red, s, p);
+  else
+    hipLaunchKernelGGL((k_xapply<F, V, false>), dim3(p.ntasks), dim3(256), red, s, p);
+  return hipGetLastError();
+}
+
 template <typename F, typename V>
 hipError_t launch_ras(const RasLaunch& p, int grid, hipStream_t s) {
   if (p.ntasks <= 0) return hipSuccess;
+  if (p.group == 0) return launch_xapply<F, V>(p, s);
   if (grid > p.ntasks) grid = p.ntasks;
   if (grid < 1) grid = 1;
   switch (p.group) {

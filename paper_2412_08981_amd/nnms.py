@@ -34,6 +34,7 @@ MAX_RESTART = 64
 FP64, MIXED = 0, 1
 BARYCENTRIC, MLS = 0, 1  # transfer between levels
 LU, ILU = 0, 1  # subdomain solver of the smoother
+SWEEPS, INVERSE = 0, 1  # how dense-LU subdomain solves are applied
 DEVICE_PTRS, NO_GRAPH = 1, 2
 
 STATUS = {
@@ -53,7 +54,7 @@ class setup_opts(C.Structure):
     _fields_ = [("nparts", C.c_int32 * MAX_LEVELS), ("overlap", C.c_int32), ("its", C.c_int32),
                 ("precision", C.c_int32), ("transfer", C.c_int32), ("mls_alpha", C.c_double),
                 ("subsolver", C.c_int32), ("ilu_fill", C.c_int32 * MAX_LEVELS), ("mls_restrict", C.c_int32),
-                ("ncomp", C.c_int32), ("mls_clip", C.c_int32)]
+                ("ncomp", C.c_int32), ("mls_clip", C.c_int32), ("dense_apply", C.c_int32)]
 
 
 class level_info(C.Structure):
@@ -61,7 +62,7 @@ class level_info(C.Structure):
                 ("nparts", C.c_int32), ("max_block", C.c_int32), ("min_block", C.c_int32), ("transfer", C.c_int32),
                 ("s_total", C.c_int64), ("factor_elems", C.c_int64), ("p_nnz", C.c_int64),
                 ("subsolver", C.c_int32), ("mls_restrict", C.c_int32), ("ilu_nnz", C.c_int64),
-                ("r_nnz", C.c_int64), ("ncomp", C.c_int32), ("reserved", C.c_int32), ("ndof", C.c_int64)]
+                ("r_nnz", C.c_int64), ("ncomp", C.c_int32), ("dense_apply", C.c_int32), ("ndof", C.c_int64)]
 
 
 class kappa_t(C.Structure):
@@ -162,6 +163,8 @@ _sig = {
     "nnms_time_kernel": (C.c_int, [vp, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double)]),
     "nnms_system_factor": (C.c_int, [vp, C.c_int32, C.c_int32, vp, vp, C.POINTER(C.c_int32)]),
     "nnms_system_factor_pairs": (C.c_int, [vp, C.c_int32, C.c_int32, vp, vp, C.POINTER(C.c_int32)]),
+    "nnms_system_inverse_panels": (C.c_int, [vp, C.c_int32, C.c_int32, vp, C.POINTER(C.c_int32),
+                                             C.POINTER(C.c_int32)]),
     "nnms_hierarchy_get_tuning": (C.c_int, [vp, C.POINTER(tuning_t)]),
     "nnms_hierarchy_set_tuning": (C.c_int, [vp, C.POINTER(tuning_t)]),
     "nnms_autotune": (C.c_int, [vp, C.c_int32, C.POINTER(tuning_t)]),
@@ -269,7 +272,8 @@ class Hierarchy:
     def __init__(self, meshes: Sequence[Mesh], nparts: Sequence[int] = (), overlap: int = 1, its: int = 3,
                  precision: int = FP64, device: bool = True, torch_alloc: bool = False, stream=None,
                  transfer: int = BARYCENTRIC, mls_alpha: float = 1.0, subsolver: int = LU,
-                 ilu_fill: Sequence[int] = (), mls_restrict: bool = False, ncomp: int = 1, mls_clip: bool = False):
+                 ilu_fill: Sequence[int] = (), mls_restrict: bool = False, ncomp: int = 1, mls_clip: bool = False,
+                 dense_apply: int = SWEEPS):
         o = setup_opts()
         _check(_lib.nnms_setup_opts_default(C.byref(o)))
         for l, p in enumerate(nparts):
@@ -280,6 +284,7 @@ class Hierarchy:
         o.mls_restrict = 1 if mls_restrict else 0
         o.ncomp = int(ncomp)
         o.mls_clip = 1 if mls_clip else 0
+        o.dense_apply = int(dense_apply)
         for l, k in enumerate(ilu_fill):
             o.ilu_fill[l] = int(k)
         self.meshes = list(meshes)
@@ -368,7 +373,8 @@ class Hierarchy:
             li = self.level_info(l)
             parts.append(f"{li.nv}-{li.nnz}-{li.nparts}" + (f"-c{li.ncomp}" if li.ncomp != 1 else "")
                          + (f"-mls{li.p_nnz}-{li.r_nnz}" if li.transfer == MLS else "")
-                         + (f"-ilu{li.ilu_nnz}" if li.subsolver == ILU else ""))
+                         + (f"-ilu{li.ilu_nnz}" if li.subsolver == ILU else "")
+                         + ("-inv" if li.dense_apply == INVERSE else ""))
         return f"p{self.precision}_" + "_".join(parts)
 
     def system_bytes(self, restart: int = 30) -> int:
@@ -505,6 +511,14 @@ class System:
         il = np.empty((N.value, 64, 64))
         _check(_lib.nnms_system_factor(self.handle, level, part, _ptr(lu), _ptr(il), C.byref(N)))
         return lu, il
+
+    def inverse_panels(self, level: int, part: int) -> np.ndarray:
+        """Inverse panels X_p = J_p^{-1} E_o of one subdomain: (N*64, No*64), local rows x owned columns."""
+        N, No = C.c_int32(), C.c_int32()
+        _check(_lib.nnms_system_inverse_panels(self.handle, level, part, None, C.byref(N), C.byref(No)))
+        x = np.empty((N.value * 64, No.value * 64))
+        _check(_lib.nnms_system_inverse_panels(self.handle, level, part, _ptr(x), C.byref(N), C.byref(No)))
+        return x
 
     def factor_pairs(self, level: int, part: int):
         """Pair coupling tiles of one subdomain's factor: (X_L [NP,64,64], X_U [NP,64,64])."""
