@@ -68,15 +68,18 @@ def log(*a):
 
 def xpanel_bytes(h, level, s_bytes):
     """Algorithmic bytes of one inverse-panel smoother application on
-    `level`: every entry of X_p = J_p^{-1} E_o once (n_p n_o values), the
-    gathered input and index map, and the scattered owned output."""
+    `level`: X_p = J_p^{-1} E_o read once in its stored symmetric form, the
+    overlap rows (n_v n_o values) and the lower triangle of the owned block
+    (n_o (n_o + 1) / 2), plus the gathered input, the index map and the
+    scattered owned output."""
     owner, sets = h.partition(level)
     owner = np.asarray(owner)
     n = np.array([len(S) for S in sets], dtype=np.float64)
     no = np.array([np.count_nonzero(owner[np.asarray(S)] == p) for p, S in enumerate(sets)], dtype=np.float64)
     if level == h.L - 1:
         no = n
-    return float(np.sum(n * no) * s_bytes + np.sum(n) * (s_bytes + 4) + np.sum(no) * s_bytes)
+    vals = (n - no) * no + no * (no + 1) / 2
+    return float(np.sum(vals) * s_bytes + np.sum(n) * (s_bytes + 4) + np.sum(no) * s_bytes)
 
 
 def ras_bytes(h, level, s_bytes):

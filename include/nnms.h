@@ -172,11 +172,13 @@ void nnms_mesh_destroy(nnms_mesh* m);
  *             NNMS_APPLY_INVERSE stores, at every assembly, the owned
  *             columns of the inverse, X_p = J_p^{-1} E_o (n_p x n_o, from
  *             the same LU factors by block forward and back substitution;
- *             on the coarsest level the whole inverse), and applies
- *             z_o = X_p^T r[S_p] (J_p is symmetric, so X_p^T holds the owned
- *             rows of J_p^{-1}): the same operator up to rounding, read as
- *             independent 64-column panels instead of chains of dependent
- *             blocks, for about twice the numeric setup.
+ *             on the coarsest level the whole inverse), kept as its
+ *             overlap rows and the lower triangle of its symmetric owned
+ *             block, and applies z_o = X_p^T r[S_p] (J_p is symmetric, so
+ *             X_p^T holds the owned rows of J_p^{-1}): the same operator up
+ *             to rounding, read as independent 64-column panels instead of
+ *             chains of dependent blocks, for about twice the numeric
+ *             setup.
  * nnms_hierarchy_setup_host builds the same structure without touching any
  * GPU (inspection and host tests); such a handle cannot be assembled.
  * ------------------------------------------------------------------------- */
@@ -400,7 +402,9 @@ nnms_status nnms_system_factor_pairs(const nnms_system* s, int32_t level, int32_
 /* Read-back of the inverse panels of subdomain `part` of `level`
  * (NNMS_APPLY_INVERSE levels only, else NNMS_ERR_INVALID_ARG), for checks:
  * X_p = J_p^{-1} E_o, the owned columns of the inverse of the subdomain
- * matrix in the factor's local order.  x_host (may be NULL: sizes only)
+ * matrix in the factor's local order, unpacked from the stored form (the
+ * overlap rows and the lower triangle of the symmetric owned block; its
+ * upper triangle is the transpose).  x_host (may be NULL: sizes only)
  * receives the (N*64) x (No*64) matrix row-major, FP32 panels widened;
  * row k < |S_p| is local row k, column c < n_o is owned row c (local row
  * |S_p| - n_o + c); padding rows and columns are zero.  *N_out and *No_out

@@ -192,6 +192,7 @@ struct SysLevel {
   void* t = nullptr;
   void* ilu_val = nullptr;  // ILU factor values (factor type), ILU levels only
   void* xinv = nullptr;     // inverse panels X_p (factor type), NNMS_APPLY_INVERSE only
+  void* xpart = nullptr;    // their smoother's partial sums (factor type)
 };
 
 struct Plan;
@@ -472,12 +473,24 @@ static std::vector<int32_t> ras_tasks(const std::vector<int32_t>& N, const std::
   return out;
 }
 
-// work items of an inverse-panel launch: one per (subdomain, tile column of
-// X_p), the subdomain in the high 16 bits
+// work items of an inverse-panel launch: per subdomain q and owned tile
+// column b, the overlap part (Nv tiles, when there are overlap rows) and the
+// owned part (No - b tiles): (q << 16) | (owned << 15) | b.  Ordered by
+// decreasing tile count (ties by subdomain, then column), so the long items
+// start first and the launch's tail is short.
 static std::vector<int32_t> xpanel_tasks(const std::vector<SubDesc>& subs) {
+  std::vector<std::pair<int, int32_t>> items;  // (-tiles, code)
+  for (size_t q = 0; q < subs.size(); ++q) {
+    const int No = (subs[q].no + TILE - 1) / TILE, Nv = (subs[q].nv + TILE - 1) / TILE;
+    for (int b = 0; b < No; ++b) {
+      if (Nv > 0) items.emplace_back(-Nv, int32_t((q << 16) | b));
+      items.emplace_back(-(No - b), int32_t((q << 16) | (1 << 15) | b));
+    }
+  }
+  std::stable_sort(items.begin(), items.end(),
+                   [](const std::pair<int, int32_t>& x, const std::pair<int, int32_t>& y) { return x.first < y.first; });
   std::vector<int32_t> out;
-  for (size_t q = 0; q < subs.size(); ++q)
-    for (int j = 0; j < (subs[q].no + TILE - 1) / TILE; ++j) out.push_back(int32_t((q << 16) | j));
+  for (auto& it : items) out.push_back(it.second);
   return out;
 }
 
@@ -504,8 +517,10 @@ static void ras_subdescs(const std::vector<nnms_system*>& sys, int l, bool coars
     const size_t fsz = (coarse || prec == NNMS_FP64) ? sizeof(double) : sizeof(float);
     for (int p = 0; p < hl.nparts; ++p) {
       SubDesc d{};
-      if (hl.xinv)
-        d.fac = (const char*)sl.xinv + size_t(hl.x_off[p]) * fsz;
+      if (hl.xinv) {
+        d.fac = (const char*)sl.xinv + size_t(hl.xs_off[p]) * fsz;
+        d.part = (char*)sl.xpart + size_t(hl.xp_off[p]) * fsz;
+      }
       else
         d.fac = (const char*)sl.fac + size_t(hl.fac_off[p]) * fsz;
       d.gidx = dl.gidx + hl.g_off[p];
@@ -1192,7 +1207,7 @@ static SysLayout system_layout(const HostHierarchy& H, int prec, int cap, int ka
       T(int64_t(lv.nparts) * int64_t(sizeof(IluDesc)));
     } else {
       R(std::max<int64_t>(lv.fac_elems * fsz, 256)), R(lv.g_total * 16);
-      if (lv.xinv) R(lv.x_elems * fsz);
+      if (lv.xinv) R(lv.xs_elems * fsz), R(lv.xp_elems * fsz), T(lv.x_elems * fsz);
       T(int64_t(lv.nparts) * int64_t(sizeof(FacDesc)));
     }
     R(lv.nv * tsz), R(lv.nv * tsz), R(lv.nv * tsz);
@@ -1232,7 +1247,7 @@ struct FactorJob {
   // rows' span, then backward steps over all tile rows)
   void* x = nullptr;
   int64_t x_elems = 0;
-  int maxNo = 0, fsteps = 0, bsteps = 0;
+  int maxNo = 0, fsteps = 0, bsteps = 0, maxPacked = 0;
 };
 
 static FactorJob factor_job(const nnms_system& sys, int l, Arena& mem, hipStream_t s) {
@@ -1244,6 +1259,8 @@ static FactorJob factor_job(const nnms_system& sys, int l, Arena& mem, hipStream
   FactorJob job;
   job.f64 = (l == sys.h->host.L - 1) || sys.prec == NNMS_FP64;
   const size_t fsz = job.f64 ? 8 : 4;
+  // the full inverse panels exist only while the packed form is made
+  void* xfull = hl.xinv ? mem.raw(size_t(hl.x_elems) * fsz) : nullptr;
   std::vector<FacDesc>& fd = job.host;
   for (int p = 0; p < hl.nparts; ++p) {
     FacDesc d{};
@@ -1257,16 +1274,19 @@ static FactorJob factor_job(const nnms_system& sys, int l, Arena& mem, hipStream
     d.N = hl.nblk[p];
     job.maxn = std::max(job.maxn, d.n), job.maxN = std::max(job.maxN, d.N);
     if (hl.xinv) {
-      d.X = (char*)sl.xinv + size_t(hl.x_off[p]) * fsz;
+      d.X = (char*)xfull + size_t(hl.x_off[p]) * fsz;
+      d.Xs = (char*)sl.xinv + size_t(hl.xs_off[p]) * fsz;
       d.nv = d.n - hl.nown[p];
       d.No = (hl.nown[p] + TILE - 1) / TILE;
       job.maxNo = std::max(job.maxNo, d.No);
       job.fsteps = std::max(job.fsteps, d.N - d.nv / TILE);
       job.bsteps = std::max(job.bsteps, d.N);
+      const int Nv = (d.nv + TILE - 1) / TILE;
+      job.maxPacked = std::max(job.maxPacked, Nv * d.No + d.No * (d.No + 1) / 2);
     }
     fd.push_back(d);
   }
-  if (hl.xinv) job.x = sl.xinv, job.x_elems = hl.x_elems;
+  if (hl.xinv) job.x = xfull, job.x_elems = hl.x_elems;
   job.d = mem.upload(fd, s);
   job.nd = int(fd.size());
   job.fac = sl.fac;
@@ -1282,7 +1302,8 @@ static hipError_t enqueue_factor_t(const FactorJob& j, int* err, hipStream_t s) 
   if ((e = launch_lu<F>(j.d, j.nd, j.maxN, err, s)) != hipSuccess) return e;
   if (!j.x) return hipSuccess;
   if ((e = launch_fill<F>((F*)j.x, j.x_elems, F(0), s)) != hipSuccess) return e;
-  return launch_xinv<F>(j.d, j.nd, j.maxNo, j.fsteps, j.bsteps, s);
+  if ((e = launch_xinv<F>(j.d, j.nd, j.maxNo, j.fsteps, j.bsteps, s)) != hipSuccess) return e;
+  return launch_xpack<F>(j.d, j.nd, j.maxPacked, s);
 }
 
 static hipError_t enqueue_factor(const FactorJob& j, int* err, hipStream_t s) {
@@ -1446,7 +1467,7 @@ extern "C" nnms_status nnms_assemble_ex(nnms_hierarchy* h, const nnms_assemble_o
     } else {
       sl.fac = A.raw(std::max<size_t>(size_t(hl.fac_elems) * fsz, 256));
       sl.yx = A.alloc<char>(size_t(hl.g_total) * 16, s);  // tagged block results: 16 bytes per value
-      if (hl.xinv) sl.xinv = A.raw(size_t(hl.x_elems) * fsz);
+      if (hl.xinv) sl.xinv = A.raw(size_t(hl.xs_elems) * fsz), sl.xpart = A.raw(size_t(hl.xp_elems) * fsz);
     }
     sl.r = A.alloc<char>(hl.nv * tsz, s);
     sl.z = A.alloc<char>(hl.nv * tsz, s);
@@ -2150,19 +2171,30 @@ extern "C" nnms_status nnms_system_inverse_panels(const nnms_system* s, int32_t 
   if (!x) return NNMS_OK;
   const bool f64 = (level == s->h->host.L - 1) || s->prec == NNMS_FP64;
   const size_t fsz = f64 ? 8 : 4;
-  std::vector<char> raw(size_t(N) * No * TILE_ELEMS * fsz);
-  HIP_CHECK(hipMemcpy(raw.data(), (const char*)s->lev[level].xinv + size_t(hl.x_off[part]) * fsz, raw.size(),
+  // the packed symmetric form, unpacked: X_v tiles, then X_oo's lower
+  // triangle by columns (its upper triangle by transposition)
+  const int n = int(hl.s_ptr[part + 1] - hl.s_ptr[part]), no = hl.nown[part], nv = n - no;
+  const int Nv = (nv + TILE - 1) / TILE;
+  std::vector<char> raw(size_t(hl.xs_off[part + 1] - hl.xs_off[part]) * fsz);
+  HIP_CHECK(hipMemcpy(raw.data(), (const char*)s->lev[level].xinv + size_t(hl.xs_off[part]) * fsz, raw.size(),
                       hipMemcpyDeviceToHost));
+  auto get = [&](size_t tile, int r, int c) -> double {
+    return f64 ? ((const double*)raw.data())[tile * TILE_ELEMS + ((c / 2) * 64 + r) * 2 + (c % 2)]
+               : ((const float*)raw.data())[tile * TILE_ELEMS + ((c / 4) * 64 + r) * 4 + (c % 4)];
+  };
+  auto low = [&](int a, int b) { return size_t(Nv) * No + size_t(b) * No - size_t(b) * (b - 1) / 2 + (a - b); };
   const size_t cols = size_t(No) * 64;
-  for (int tj = 0; tj < No; ++tj)
-    for (int ti = 0; ti < N; ++ti) {
-      const size_t tile = size_t(tj) * N + ti;
-      for (int r = 0; r < 64; ++r)
-        for (int c = 0; c < 64; ++c) {
-          const double v = f64 ? ((const double*)raw.data())[tile * TILE_ELEMS + ((c / 2) * 64 + r) * 2 + (c % 2)]
-                               : ((const float*)raw.data())[tile * TILE_ELEMS + ((c / 4) * 64 + r) * 4 + (c % 4)];
-          x[(size_t(ti) * 64 + r) * cols + size_t(tj) * 64 + c] = v;
-        }
+  for (int lr = 0; lr < N * 64; ++lr)
+    for (int col = 0; col < No * 64; ++col) {
+      double v = 0.0;
+      const int b = col / 64, c = col % 64;
+      if (lr < nv) {
+        v = get(size_t(b) * Nv + lr / 64, lr % 64, c);
+      } else if (lr < n && col < no) {
+        const int oi = lr - nv, a = oi / 64, r = oi % 64;
+        v = a >= b ? get(low(a, b), r, c) : get(low(b, a), c, r);
+      }
+      x[size_t(lr) * cols + col] = v;
     }
   return NNMS_OK;
   ABI_END

@@ -59,8 +59,9 @@ struct ProlongDesc {
 };
 
 // One overlapping subdomain of one system, for the triangular-solve kernel
-// (sweeps) or the inverse-panel kernel (fac = X_p, N x No tiles, column-major
-// tile order; the owned rows are local rows nv .. nv + no - 1).
+// (sweeps) or the inverse-panel kernel (fac = the packed symmetric panels:
+// X_v, Nv x No tiles column-major, then the lower triangle of X_oo by
+// columns; the owned rows are local rows nv .. nv + no - 1).
 struct SubDesc {
   const void* fac;      // N*N tiles (L below, U above, inv(U_ii) on the diagonal) + N tiles inv(L_ii)
   const int32_t* gidx;  // N*64 encoded global ids: >=0 owned, <=-2 overlap (-g-2), -1 padding
@@ -68,6 +69,7 @@ struct SubDesc {
   const void* rin;      // level residual vector
   void* zout;           // level correction vector
   const KState* st;     // null: always active
+  void* part;           // inverse panels: column parts and pair partials (F)
   int32_t N;
   int32_t nv;           // local rows before the owned ones (inverse panels)
   int32_t no;           // owned rows (inverse panels)
@@ -117,6 +119,7 @@ struct FacDesc {
   int32_t n;
   int32_t N;
   void* X;                // inverse panels (null: sweeps only), N x No tiles, column-major tile order
+  void* Xs;               // their packed symmetric form (overlap rows, lower triangle of the owned block)
   int32_t nv;             // local rows before the owned ones
   int32_t No;             // tile columns of X: ceil(owned rows / 64)
 };

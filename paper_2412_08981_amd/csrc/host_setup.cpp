@@ -256,6 +256,8 @@ void build_blocks(HostLevel& lv) {
   lv.bwd0.assign(nparts, 0);
   lv.nown.assign(nparts, 0);
   lv.x_off.assign(nparts + 1, 0);
+  lv.xs_off.assign(nparts + 1, 0);
+  lv.xp_off.assign(nparts + 1, 0);
   std::vector<int32_t> ord, loc;  // local row -> position in S, and back
   for (int p = 0; p < nparts; ++p) {
     const int32_t* S = lv.s_idx.data() + lv.s_ptr[p];
@@ -277,6 +279,9 @@ void build_blocks(HostLevel& lv) {
       throw Error(NNMS_ERR_INVALID_ARG, "inverse panels need the owned rows last");
     const int64_t No = (lv.nown[p] + TILE - 1) / TILE;
     lv.x_off[p + 1] = lv.x_off[p] + (lv.xinv ? int64_t(lv.nblk[p]) * No * TILE_ELEMS : 0);
+    const int64_t Nv = (n - lv.nown[p] + TILE - 1) / TILE;
+    lv.xs_off[p + 1] = lv.xs_off[p] + (lv.xinv ? (Nv * No + No * (No + 1) / 2) * TILE_ELEMS : 0);
+    lv.xp_off[p + 1] = lv.xp_off[p] + (lv.xinv ? 128 * No + 256 * (No * (No - 1) / 2) : 0);
     for (int64_t k = 0; k < n; ++k) {
       int32_t g = S[ord[k]];
       lv.gidx[lv.g_off[p] + k] = (lv.owner[g] == p) ? g : (-g - 2);
@@ -291,6 +296,8 @@ void build_blocks(HostLevel& lv) {
   if (lv.ext_lc.size() > size_t(INT32_MAX)) throw Error(NNMS_ERR_INVALID_ARG, "subdomains too large");
   lv.ext_rs[lv.s_idx.size()] = int32_t(lv.ext_lc.size());
   lv.x_elems = lv.x_off[nparts];
+  lv.xs_elems = lv.xs_off[nparts];
+  lv.xp_elems = lv.xp_off[nparts];
 }
 
 // ---------------------------------------------------------------------------

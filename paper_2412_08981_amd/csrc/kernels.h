@@ -46,6 +46,10 @@ hipError_t launch_lu(const FacDesc* d, int nd, int maxN, int* err, hipStream_t s
 // back-substitution launches (X zero-filled before)
 template <typename F>
 hipError_t launch_xinv(const FacDesc* d, int nd, int maxNo, int fsteps, int bsteps, hipStream_t s);
+// packed symmetric form d.Xs of every subdomain's panels d.X (maxPacked =
+// most packed tiles of a subdomain)
+template <typename F>
+hipError_t launch_xpack(const FacDesc* d, int nd, int maxPacked, hipStream_t s);
 
 // ilu.hip: values of the ILU pattern from the level's FP64 CSR values (0 on
 // fill), the factorisation (err set on a non-positive pivot) and the

@@ -723,11 +723,58 @@ hipError_t launch_xinv(const FacDesc* d, int nd, int maxNo, int fsteps, int bste
   return hipGetLastError();
 }
 
+// Packed symmetric form of the panels (what the smoother reads): the overlap
+// rows X_v in tile rows of 64 local rows (zero past nv), then the lower
+// triangle of X_oo = J^{-1}[o, o] in tile rows of 64 owned rows, by columns
+// (X_oo is symmetric: its upper triangle is the transpose of the lower one,
+// so the smoother reads 0.68 of the full panels on the benchmark's
+// subdomains).  One work-group per packed tile; every element comes from
+// the full panels' tile row (local row) / 64.
+template <typename F>
+__global__ __launch_bounds__(256) void k_xpack(const FacDesc* __restrict__ d) {
+  const FacDesc D = d[blockIdx.y];
+  if (!D.X) return;
+  const int No = D.No, Nv = (D.nv + 63) / 64, nown = D.n - D.nv;
+  int t = int(blockIdx.x), a, b, row0, rows;  // destination tile (a, b): local rows row0 .. row0 + rows - 1
+  if (t < Nv * No) {
+    b = t / Nv, a = t % Nv;
+    row0 = 64 * a, rows = min(64, D.nv - 64 * a);
+  } else {
+    t -= Nv * No;
+    if (t >= No * (No + 1) / 2) return;
+    b = 0;
+    while (t >= No - b) t -= No - b, ++b;  // column b holds tiles a = b .. No-1
+    a = b + t;
+    row0 = D.nv + 64 * a, rows = min(64, nown - 64 * a);
+  }
+  const GLOBAL F* X = gptr((const F*)D.X);
+  GLOBAL F* out = gptr((F*)D.Xs) + size_t(blockIdx.x) * TILE_ELEMS;
+  const size_t N = size_t(D.N);
+  for (int e = threadIdx.x; e < TILE_ELEMS; e += 256) {
+    const int r = e % 64, c = e / 64;
+    F v = F(0);
+    if (r < rows) {
+      const int lr = row0 + r;
+      v = X[(size_t(b) * N + lr / 64) * TILE_ELEMS + tile_off<F>(lr % 64, c)];
+    }
+    out[tile_off<F>(r, c)] = v;
+  }
+}
+
+template <typename F>
+hipError_t launch_xpack(const FacDesc* d, int nd, int maxPacked, hipStream_t s) {
+  if (nd <= 0 || maxPacked <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_xpack<F>), dim3(maxPacked, nd), dim3(256), 0, s, d);
+  return hipGetLastError();
+}
+
 template hipError_t launch_extract<double>(const FacDesc*, int, int, hipStream_t);
 template hipError_t launch_extract<float>(const FacDesc*, int, int, hipStream_t);
 template hipError_t launch_lu<double>(const FacDesc*, int, int, int*, hipStream_t);
 template hipError_t launch_lu<float>(const FacDesc*, int, int, int*, hipStream_t);
 template hipError_t launch_xinv<double>(const FacDesc*, int, int, int, int, hipStream_t);
 template hipError_t launch_xinv<float>(const FacDesc*, int, int, int, int, hipStream_t);
+template hipError_t launch_xpack<double>(const FacDesc*, int, int, hipStream_t);
+template hipError_t launch_xpack<float>(const FacDesc*, int, int, hipStream_t);
 
 }  // namespace nnms

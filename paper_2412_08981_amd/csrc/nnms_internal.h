@@ -75,11 +75,24 @@ struct HostLevel {
   // Explicit inverse panels (NNMS_APPLY_INVERSE): X_p = J_p^{-1} E_o, N x No
   // tiles in column-major tile order (tile (i, j) at x_off[p] + (j N + i)
   // tiles), No = ceil(n_o / 64); nown[p] = n_o, the owned rows, which are
-  // local rows n - n_o .. n-1.
+  // local rows n - n_o .. n-1.  That full form only exists during the
+  // numeric setup; what stays is the packed symmetric form at xs_off[p]:
+  // the overlap rows X_v (Nv = ceil(n_v / 64) tile rows of 64 local rows
+  // 0 .. n_v-1, zero past n_v), Nv x No tiles column-major (tile (t, b) at
+  // b Nv + t), then the lower triangle of the symmetric owned block X_oo
+  // (tile rows of 64 owned rows, zero past n_o) by columns: tile (a, b),
+  // a >= b, at Nv No + b No - b (b - 1) / 2 + (a - b).
   bool xinv = false;
   std::vector<int32_t> nown;
   std::vector<int64_t> x_off;
   int64_t x_elems = 0;
+  std::vector<int64_t> xs_off;
+  int64_t xs_elems = 0;
+  // the smoother's partial sums per subdomain: 2 x 64 No column parts (overlap
+  // and owned rows) and 256 per pair of owned tile columns (four waves'
+  // 64-vectors)
+  std::vector<int64_t> xp_off;
+  int64_t xp_elems = 0;
 
   // transfer P_l from level l+1 to l (empty on the coarsest level)
   std::vector<int32_t> p_idx;       // nv*4

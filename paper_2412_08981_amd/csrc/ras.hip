@@ -628,77 +628,129 @@ __global__ __launch_bounds__(256, (RasWaves<F, 2>::value)) void k_ras2(RasLaunch
 }
 
 // ---------------------------------------------------------------------------
-// Inverse panels: z_o = X_p^T r[S_p] with X_p = J_p^{-1} E_o stored as N x No
-// tiles, column-major tile order.  A work-group takes one tile column j of
-// one subdomain (owned rows 64 j .. 64 j + 63) and streams its N tiles: lane
-// l of wave w keeps row l of every tile and the 16-byte column chunks w,
-// w + 4, ..., accumulating X[r][c] r[S_p][r] per column over the tiles;
-// the 64 row partial sums of every column are added at the end through
-// LDS, in a fixed order (so a batch gives every system the bits it gets
-// alone).  No work-group waits for another.  r[S_p] is gathered into LDS
-// first (YL), or read per tile when it does not fit.
+// Inverse panels: z_o = X_p^T r[S_p], X_p = J_p^{-1} E_o, from the packed
+// symmetric form (overlap rows X_v, then the lower triangle of the owned
+// block X_oo by columns), every stored tile read once.  Two kinds of work
+// item per owned tile column b of subdomain p:
+//   overlap part: X_v(t, b), t < Nv;
+//   owned part:   X_oo(a, b), a >= b.
+// Each streams its tiles and accumulates z_b += T^T y (y: the tile's rows
+// of r[S_p]; lane l keeps row l and the 16-byte column chunks w, w + 4, ...
+// of wave w, per column over the tiles; the 64 row partials are added
+// through LDS at the end), stored as the column part Cv_b or Co_b.  The
+// owned part also adds, for a > b and by symmetry X_oo(b, a) = X_oo(a, b)^T,
+// the contribution of the owned rows of tile b to z_a: T y_b, one 64-vector
+// per wave (lane l: row l of T against the entries of y_b under its
+// chunks), stored as P_{b,a,w}.  A second launch adds
+//   z_a = Cv_a + Co_a + sum_{b < a} sum_w P_{b,a,w}
+// in that fixed order, so a batch gives every system the bits it gets
+// alone.  No work-group waits for another.  The rows of r[S_p] are gathered
+// into LDS first (YL: overlap rows, zero past nv, then owned rows, zero past
+// no), or read per tile when they do not fit.  Partials of subdomain p at
+// S.part: Cv_b at 64 b, Co_b at 64 (No + b), P_{b,a,w} at 128 No + 256
+// pair(b, a) + 64 w, pair(b, a) = b (No - 1) - b (b - 1) / 2 + (a - b - 1).
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ size_t xpair(int b, int a, int No) {
+  return size_t(b) * (No - 1) - size_t(b) * (b - 1) / 2 + (a - b - 1);
+}
+
 template <typename F, typename V, bool YL>
 __global__ __launch_bounds__(256, 2) void k_xapply(RasLaunch P) {
   using C = typename Chunk<F>::type;
   constexpr int W = Chunk<F>::W;
   constexpr int NQ = 16 / W;  // 16-byte chunks per lane per tile
   extern __shared__ __align__(16) unsigned char xsh[];
-  F* ysh = (F*)xsh;  // N*64 gathered values, then the column reduction
+  F* ysh = (F*)xsh;  // the gathered rows the item reads, then the column reduction
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int code = gptr(P.tasks)[blockIdx.x];
-  const int sub = code >> 16, j = code & 0xffff;
+  const int sub = code >> 16, owned = (code >> 15) & 1, b = code & 0x7fff;
   const SubDesc S = P.subs[sub];
   if (!slot_active(S.st, WHEN_RUNNING)) return;
-  const int N = S.N;
-  const GLOBAL C* base = gptr((const C*)((const F*)S.fac + size_t(j) * N * TILE_ELEMS));
+  const int nv = S.nv, no = S.no;
+  const int Nv = (nv + 63) / 64, No = (no + 63) / 64;
+  const int NT = owned ? No - b : Nv;
+  // the item's tiles are contiguous: X_v column b, or X_oo column b from the diagonal down
+  const size_t first = owned ? size_t(Nv) * No + size_t(b) * No - size_t(b) * (b - 1) / 2 : size_t(b) * Nv;
+  const GLOBAL C* base = gptr((const C*)S.fac) + first * (TILE_ELEMS / W);
   const GLOBAL int32_t* gidx = gptr(S.gidx);
   const GLOBAL V* rin = gptr((const V*)S.rin);
-  auto load_tile = [&](int i, C (&reg)[NQ]) {
-    const GLOBAL C* t = base + size_t(i) * (TILE_ELEMS / W);
+  GLOBAL F* part = gptr((F*)S.part);
+  auto load_tile = [&](int k, C (&reg)[NQ]) {
+    const GLOBAL C* t = base + size_t(k) * (TILE_ELEMS / W);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) reg[q] = __builtin_nontemporal_load(t + (wave + 4 * q) * 64 + lane);
   };
-  auto gathered = [&](int k) -> F {
-    const int g = gidx[k];
+  // row e of the item's tiles: overlap row e (< nv), or owned row 64 b + e (< no)
+  auto gathered = [&](int e) -> F {
+    int lr;
+    if (owned)
+      lr = 64 * b + e < no ? nv + 64 * b + e : -1;
+    else
+      lr = e < nv ? e : -1;
+    if (lr < 0) return F(0);
+    const int g = gidx[lr];
     return g == -1 ? F(0) : F(rin[g >= 0 ? g : -g - 2]);
   };
   C R0[NQ], R1[NQ], R2[NQ], R3[NQ];
   load_tile(0, R0);
-  if (N > 1) load_tile(1, R1);
-  if (N > 2) load_tile(2, R2);
-  if (N > 3) load_tile(3, R3);
+  if (NT > 1) load_tile(1, R1);
+  if (NT > 2) load_tile(2, R2);
+  if (NT > 3) load_tile(3, R3);
   if (YL) {
-    for (int k = tid; k < N * 64; k += 256) ysh[k] = gathered(k);
+    for (int e = tid; e < NT * 64; e += 256) ysh[e] = gathered(e);
     __syncthreads();
+  }
+  // y_b under this lane's chunks (the owned part's row products)
+  C yb[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    if (!owned) {
+      yb[q] = C{};
+    } else if (YL) {
+      yb[q] = ((const C*)ysh)[wave + 4 * q];
+    } else {
+#pragma unroll
+      for (int w = 0; w < W; ++w) yb[q][w] = gathered((wave + 4 * q) * W + w);
+    }
   }
   C acc[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) acc[q] = C{};
-  auto apply = [&](const C (&R)[NQ], int i) {
-    const F y = YL ? ysh[i * 64 + lane] : gathered(i * 64 + lane);
+  GLOBAL F* pp = part + 128 * No + 64 * wave + lane;
+  auto apply = [&](const C (&R)[NQ], int k) {
+    const F y = YL ? ysh[k * 64 + lane] : gathered(k * 64 + lane);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[q] += R[q] * y;
+    if (owned && k > 0) {
+      F racc = F(0);
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const C p = R[q] * yb[q];
+#pragma unroll
+        for (int w = 0; w < W; ++w) racc += p[w];
+      }
+      pp[256 * xpair(b, b + k, No)] = racc;
+    }
   };
-  for (int i = 0; i < N; i += 4) {
-    apply(R0, i);
+  for (int k = 0; k < NT; k += 4) {
+    apply(R0, k);
     // refill a ring slot only after its last use (no double buffering)
     __builtin_amdgcn_sched_barrier(0);
-    if (i + 4 < N) load_tile(i + 4, R0);
-    if (i + 1 < N) {
-      apply(R1, i + 1);
+    if (k + 4 < NT) load_tile(k + 4, R0);
+    if (k + 1 < NT) {
+      apply(R1, k + 1);
       __builtin_amdgcn_sched_barrier(0);
-      if (i + 5 < N) load_tile(i + 5, R1);
+      if (k + 5 < NT) load_tile(k + 5, R1);
     }
-    if (i + 2 < N) {
-      apply(R2, i + 2);
+    if (k + 2 < NT) {
+      apply(R2, k + 2);
       __builtin_amdgcn_sched_barrier(0);
-      if (i + 6 < N) load_tile(i + 6, R2);
+      if (k + 6 < NT) load_tile(k + 6, R2);
     }
-    if (i + 3 < N) {
-      apply(R3, i + 3);
+    if (k + 3 < NT) {
+      apply(R3, k + 3);
       __builtin_amdgcn_sched_barrier(0);
-      if (i + 7 < N) load_tile(i + 7, R3);
+      if (k + 7 < NT) load_tile(k + 7, R3);
     }
   }
   __syncthreads();  // every read of the gathered values is done
@@ -711,12 +763,35 @@ __global__ __launch_bounds__(256, 2) void k_xapply(RasLaunch P) {
   if (tid < 64) {
     F sum = 0;
     for (int r = 0; r < 64; ++r) sum += red[tid][r];
-    const int oc = 64 * j + tid;  // owned row index; local row nv + oc
-    if (oc < S.no) {
-      const int g = gidx[S.nv + oc];
-      GLOBAL V* z = gptr((V*)S.zout);
-      z[g] = P.add ? V(z[g] + V(sum)) : V(sum);
-    }
+    part[64 * (owned ? No + b : b) + tid] = sum;
+  }
+}
+
+// z_a = Cv_a + Co_a + sum_{b < a} sum_w P_{b,a,w}, scattered to the owned
+// rows (tasks: the owned parts' codes; Cv_a only where there are overlap rows)
+template <typename F, typename V>
+__global__ __launch_bounds__(64) void k_xreduce(RasLaunch P) {
+  const int code = gptr(P.tasks)[blockIdx.x];
+  if (!((code >> 15) & 1)) return;
+  const int sub = code >> 16, a = code & 0x7fff;
+  const SubDesc S = P.subs[sub];
+  if (!slot_active(S.st, WHEN_RUNNING)) return;
+  const int lane = threadIdx.x, No = (S.no + 63) / 64;
+  const GLOBAL F* part = gptr((const F*)S.part);
+  F sum = S.nv > 0 ? part[64 * a + lane] : F(0);
+  sum += part[64 * (No + a) + lane];
+  for (int b = 0; b < a; ++b) {
+    const GLOBAL F* pw = part + 128 * No + 256 * xpair(b, a, No) + lane;
+    sum += pw[0];
+    sum += pw[64];
+    sum += pw[128];
+    sum += pw[192];
+  }
+  const int oc = 64 * a + lane;  // owned row index; local row nv + oc
+  if (oc < S.no) {
+    const int g = gptr(S.gidx)[S.nv + oc];
+    GLOBAL V* z = gptr((V*)S.zout);
+    z[g] = P.add ? V(z[g] + V(sum)) : V(sum);
   }
 }
 
@@ -726,11 +801,13 @@ constexpr size_t XAPPLY_MAX_LDS = 65536;
 
 template <typename F, typename V>
 static hipError_t launch_xapply(const RasLaunch& p, hipStream_t s) {
-  const size_t red = 64 * 65 * sizeof(F), ylds = size_t(p.max_tiles) * 64 * sizeof(F);
+  // gathered rows: at most N tiles per work item; column reduction: 64 x 65
+  const size_t red = 64 * 65 * sizeof(F), ylds = size_t(p.max_tiles + 1) * 64 * sizeof(F);
   if (ylds <= XAPPLY_MAX_LDS)
     hipLaunchKernelGGL((k_xapply<F, V, true>), dim3(p.ntasks), dim3(256), ylds > red ? ylds : red, s, p);
   else
     hipLaunchKernelGGL((k_xapply<F, V, false>), dim3(p.ntasks), dim3(256), red, s, p);
+  hipLaunchKernelGGL((k_xreduce<F, V>), dim3(p.ntasks), dim3(64), 0, s, p);
   return hipGetLastError();
 }
 
