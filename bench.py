@@ -441,9 +441,11 @@ def main():
     ap.add_argument("--subsolver", default="lu", choices=["lu", "ilu"],
                     help="subdomain solver of the smoother: dense LU or ILU(k)")
     ap.add_argument("--ilu-fill", default="2,0", help="ILU level of fill per smoothed level (finest first)")
-    ap.add_argument("--dense-apply", default="sweeps", choices=["sweeps", "inverse"],
+    ap.add_argument("--dense-apply", default=None, choices=["sweeps", "inverse"],
                     help="dense-LU subdomain solves applied by forward/backward sweeps over the factors, or "
-                         "through the stored owned columns of each subdomain inverse (inverse panels)")
+                         "through the stored owned columns of each subdomain inverse (inverse panels; about "
+                         "twice the numeric setup).  Default: inverse, except for the serving workload, whose "
+                         "requests are each assembled once and solved once (sweeps)")
     ap.add_argument("--physics", default="poisson", choices=["poisson", "elasticity"],
                     help="default workload: the scalar 48^3 problem, or P1 linear elasticity (three unknowns per "
                          "vertex, field-split transfers) on 32^3/16^3/7^3 meshes")
@@ -457,6 +459,8 @@ def main():
     ap.add_argument("--kernels-only", action="store_true",
                     help="run the copy reference and the fine-level smoother a few times each (for counter runs)")
     args = ap.parse_args()
+    if args.dense_apply is None:
+        args.dense_apply = "sweeps" if args.workload == "serving" else "inverse"
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark measures one GPU; --gpus must be 1"}))
         sys.exit(2)

@@ -12,7 +12,9 @@ condition numbers), the coarsest direct solve, one V-cycle against the
 oracle's V-cycle (1e-9), and a full FP64 solve against the oracle's own FGMRES
 solution (same iteration count within one, 1e-7).  Mixed precision: the FP32
 smoother on both levels against the oracle's (1e-2: FP32 rounding times block
-condition numbers up to ~1e5) and a solve against x* (1e-7).  96^3 / 48^3 /
+condition numbers up to ~1e5) and a solve against x* (1e-7).  The same
+smoother, V-cycle and solve checks with the dense solves applied through
+inverse panels (the benchmark's default), in both precisions.  96^3 / 48^3 /
 20^3 (the largest served hierarchy, 512 fine subdomains, mixed): the true
 residual of a solve from the oracle's assembly, and eight subdomains of the
 fine smoother solved one by one by LAPACK.  The 32 batched instances: true
@@ -58,13 +60,14 @@ def _err(v, ref):
     return float(np.abs(v - ref).max()) / max(float(np.abs(ref).max()), 1e-300)
 
 
-def _system(pb, precision):
+def _system(pb, precision, dense_apply=None):
     nnms = _gpu()
     from paper_2412_08981_amd import autotune
 
     prec = nnms.MIXED if precision == "mixed" else nnms.FP64
     ms = [nnms.Mesh.from_workload(m) for m in pb.meshes]
-    h = nnms.Hierarchy(ms, pb.nparts, overlap=pb.overlap, its=pb.its, precision=prec)
+    h = nnms.Hierarchy(ms, pb.nparts, overlap=pb.overlap, its=pb.its, precision=prec,
+                       dense_apply=nnms.SWEEPS if dense_apply is None else dense_apply)
     s = nnms.System(h, pb.kappa, 1.0)
     autotune.tune(s, cache=CACHE)  # the benchmark's launch shapes
     s.destroy()
@@ -160,6 +163,38 @@ def test_cube48_mixed_full_size():
     _check_smoothers(s, pb, o, 1e-2)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_cube48_inverse_panels_full_size(precision):
+    """The benchmark's default: dense subdomain solves through inverse
+    panels, at the benchmark's size and launch configuration.  Every level's
+    smoother (all subdomains) against the oracle's restricted additive
+    Schwarz (FP64 1e-9; FP32 1e-2 as above), one V-cycle (FP64 1e-9), and a
+    solve against the oracle's FGMRES solution (FP64: iterations within one,
+    1e-7) or x* (mixed, 1e-7)."""
+    nnms = _gpu()
+    _say(f"[gpu] 48^3 / 24^3 / 10^3 with inverse panels ({precision})")
+    pb = W.cube48_three_level(precision)
+    s, h, keep = _system(pb, precision, nnms.INVERSE)
+    assert all(h.level_info(l).dense_apply == nnms.INVERSE for l in range(3))
+    o = oprob.build(pb)
+    _check_smoothers(s, pb, o, 1e-9 if precision == "fp64" else 1e-2)
+    rng = np.random.default_rng(5)
+    x, info = s.solve(o.b)
+    assert info.status == 0 and info.relres <= 1e-8
+    assert np.linalg.norm(o.b - o.A[0] @ x) <= 1e-8 * np.linalg.norm(o.b)
+    if precision == "fp64":
+        r = _interior_random(rng, pb.meshes[0])
+        zv = s.apply_vcycle(r)
+        assert _close(zv, o.vcycle(r), 1e-9), _err(zv, o.vcycle(r))
+        ref = oprob.solve(o)
+        _say(f"[gpu] 48^3 inverse panels fp64: {info.iterations} iterations (oracle {ref.iterations})")
+        assert abs(info.iterations - ref.iterations) <= 1
+        assert _close(x, ref.x, 1e-7), _err(x, ref.x)
+    else:
+        xs = oprob.exact(o)
+        assert _close(x, xs, 1e-7), _err(x, xs)
+
+
 def test_served_96_mixed_full_size():
     _say("[gpu] served 96^3 / 48^3 / 20^3 hierarchy, 512 fine subdomains (mixed)")
     meshes = W.served_hierarchy(96)
@@ -176,17 +211,18 @@ def test_served_96_mixed_full_size():
 
 def test_batched_32_instances_full_size():
     """The batched workload as benchmarked (32 ragged instances, fine n in
-    {24, 32, 40, 48, 64}, mixed precision, one launch sequence per Arnoldi
-    step): every slot reaches the true relative residual 1e-8 computed from
-    the oracle's assembly of its own fine level, and equals its solve alone
-    bit for bit."""
+    {24, 32, 40, 48, 64}, mixed precision, dense solves through inverse
+    panels, one launch sequence per Arnoldi step): every slot reaches the
+    true relative residual 1e-8 computed from the oracle's assembly of its
+    own fine level, and equals its solve alone bit for bit."""
     nnms = _gpu()
     _say("[gpu] 32 batched instances (mixed)")
     probs = W.batched_instances(count=32)
     keep, systems, bs, As = [], [], [], []
     for pb in probs:
         ms = [nnms.Mesh.from_workload(m) for m in pb.meshes]
-        h = nnms.Hierarchy(ms, pb.nparts, overlap=pb.overlap, its=pb.its, precision=nnms.MIXED)
+        h = nnms.Hierarchy(ms, pb.nparts, overlap=pb.overlap, its=pb.its, precision=nnms.MIXED,
+                           dense_apply=nnms.INVERSE)
         s = nnms.System(h, pb.kappa, 1.0)
         keep.append((ms, h))
         systems.append(s)

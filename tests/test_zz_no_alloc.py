@@ -1,8 +1,9 @@
 """nnms_apply_smoother_noalloc (the smoother for callers that cannot
 allocate device memory, working in a per-GPU static scratch array) against
 nnms_apply_smoother on the same system: bitwise equal on every level (dense
-FP64, mixed precision, ILU), two calls in a row with the second on a smaller
-system, and tables beyond the scratch array's size refused."""
+FP64, mixed precision, ILU, dense solves through inverse panels in both
+precisions), two calls in a row with the second on a smaller system, and
+tables beyond the scratch array's size refused."""
 import numpy as np
 import pytest
 
@@ -41,12 +42,14 @@ def _check(nnms, torch, meshes, s, level, seed):
     assert np.array_equal(z, ref), (level, np.abs(z - ref).max())
 
 
-@pytest.mark.parametrize("kind", ["fp64", "mixed", "ilu"])
+@pytest.mark.parametrize("kind", ["fp64", "mixed", "ilu", "inverse", "inverse-mixed"])
 def test_noalloc_equals_apply_smoother(env, kind):
     nnms, torch = env
-    kw = {"precision": nnms.MIXED if kind == "mixed" else nnms.FP64}
+    kw = {"precision": nnms.MIXED if kind.endswith("mixed") else nnms.FP64}
     if kind == "ilu":
         kw.update(subsolver=nnms.ILU, ilu_fill=[2, 0])
+    if kind.startswith("inverse"):
+        kw.update(dense_apply=nnms.INVERSE)
     big = _system(nnms, (13, 7, 4), (11, 12, 13), [8, 2], **kw)
     small = _system(nnms, (9, 5, 3), (21, 22, 23), [4, 2], **kw)
     # two calls in a row, the second on a smaller input, then every level
