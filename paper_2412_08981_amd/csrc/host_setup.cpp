@@ -281,7 +281,7 @@ void build_blocks(HostLevel& lv) {
     lv.x_off[p + 1] = lv.x_off[p] + (lv.xinv ? int64_t(lv.nblk[p]) * No * TILE_ELEMS : 0);
     const int64_t Nv = (n - lv.nown[p] + TILE - 1) / TILE;
     lv.xs_off[p + 1] = lv.xs_off[p] + (lv.xinv ? (Nv * No + No * (No + 1) / 2) * TILE_ELEMS : 0);
-    lv.xp_off[p + 1] = lv.xp_off[p] + (lv.xinv ? 128 * No + 256 * (No * (No - 1) / 2) : 0);
+    lv.xp_off[p + 1] = lv.xp_off[p] + (lv.xinv ? 128 * No + 64 * (No * (No - 1) / 2) : 0);
     for (int64_t k = 0; k < n; ++k) {
       int32_t g = S[ord[k]];
       lv.gidx[lv.g_off[p] + k] = (lv.owner[g] == p) ? g : (-g - 2);

@@ -89,8 +89,7 @@ struct HostLevel {
   std::vector<int64_t> xs_off;
   int64_t xs_elems = 0;
   // the smoother's partial sums per subdomain: 2 x 64 No column parts (overlap
-  // and owned rows) and 256 per pair of owned tile columns (four waves'
-  // 64-vectors)
+  // and owned rows) and 64 per pair of owned tile columns
   std::vector<int64_t> xp_off;
   int64_t xp_elems = 0;
 

@@ -634,21 +634,22 @@ __global__ __launch_bounds__(256, (RasWaves<F, 2>::value)) void k_ras2(RasLaunch
 // item per owned tile column b of subdomain p:
 //   overlap part: X_v(t, b), t < Nv;
 //   owned part:   X_oo(a, b), a >= b.
-// Each streams its tiles and accumulates z_b += T^T y (y: the tile's rows
-// of r[S_p]; lane l keeps row l and the 16-byte column chunks w, w + 4, ...
-// of wave w, per column over the tiles; the 64 row partials are added
-// through LDS at the end), stored as the column part Cv_b or Co_b.  The
-// owned part also adds, for a > b and by symmetry X_oo(b, a) = X_oo(a, b)^T,
-// the contribution of the owned rows of tile b to z_a: T y_b, one 64-vector
-// per wave (lane l: row l of T against the entries of y_b under its
-// chunks), stored as P_{b,a,w}.  A second launch adds
-//   z_a = Cv_a + Co_a + sum_{b < a} sum_w P_{b,a,w}
+// A tile is split by rows: wave w holds rows 16 w .. 16 w + 15, lane l row
+// 16 w + l % 16 and the 16-byte column chunks l / 16, l / 16 + 4, ...  Each
+// item accumulates z_b += T^T y per column over its tiles (y: the tile's
+// rows of r[S_p]); the 64 row partials of every column are added through LDS
+// at the end and stored as the column part Cv_b or Co_b.  The owned part also
+// forms, for a > b and by symmetry X_oo(b, a) = X_oo(a, b)^T, the
+// contribution of the owned rows of tile b to z_a: T y_b, whose rows are
+// complete inside a wave (the four lanes of a row add their chunks by two
+// exchanges), stored as P_{b,a}.  A second launch adds
+//   z_a = Cv_a + Co_a + sum_{b < a} P_{b,a}
 // in that fixed order, so a batch gives every system the bits it gets
 // alone.  No work-group waits for another.  The rows of r[S_p] are gathered
 // into LDS first (YL: overlap rows, zero past nv, then owned rows, zero past
 // no), or read per tile when they do not fit.  Partials of subdomain p at
-// S.part: Cv_b at 64 b, Co_b at 64 (No + b), P_{b,a,w} at 128 No + 256
-// pair(b, a) + 64 w, pair(b, a) = b (No - 1) - b (b - 1) / 2 + (a - b - 1).
+// S.part: Cv_b at 64 b, Co_b at 64 (No + b), P_{b,a} at 128 No + 64 pair(b, a),
+// pair(b, a) = b (No - 1) - b (b - 1) / 2 + (a - b - 1).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ size_t xpair(int b, int a, int No) {
   return size_t(b) * (No - 1) - size_t(b) * (b - 1) / 2 + (a - b - 1);
@@ -662,6 +663,7 @@ __global__ __launch_bounds__(256, 2) void k_xapply(RasLaunch P) {
   extern __shared__ __align__(16) unsigned char xsh[];
   F* ysh = (F*)xsh;  // the gathered rows the item reads, then the column reduction
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int row = 16 * wave + (lane & 15), cgrp = lane >> 4;  // this lane's tile row and first chunk
   const int code = gptr(P.tasks)[blockIdx.x];
   const int sub = code >> 16, owned = (code >> 15) & 1, b = code & 0x7fff;
   const SubDesc S = P.subs[sub];
@@ -678,7 +680,7 @@ __global__ __launch_bounds__(256, 2) void k_xapply(RasLaunch P) {
   auto load_tile = [&](int k, C (&reg)[NQ]) {
     const GLOBAL C* t = base + size_t(k) * (TILE_ELEMS / W);
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) reg[q] = __builtin_nontemporal_load(t + (wave + 4 * q) * 64 + lane);
+    for (int q = 0; q < NQ; ++q) reg[q] = __builtin_nontemporal_load(t + (cgrp + 4 * q) * 64 + row);
   };
   // row e of the item's tiles: overlap row e (< nv), or owned row 64 b + e (< no)
   auto gathered = [&](int e) -> F {
@@ -707,18 +709,18 @@ __global__ __launch_bounds__(256, 2) void k_xapply(RasLaunch P) {
     if (!owned) {
       yb[q] = C{};
     } else if (YL) {
-      yb[q] = ((const C*)ysh)[wave + 4 * q];
+      yb[q] = ((const C*)ysh)[cgrp + 4 * q];
     } else {
 #pragma unroll
-      for (int w = 0; w < W; ++w) yb[q][w] = gathered((wave + 4 * q) * W + w);
+      for (int w = 0; w < W; ++w) yb[q][w] = gathered((cgrp + 4 * q) * W + w);
     }
   }
   C acc[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) acc[q] = C{};
-  GLOBAL F* pp = part + 128 * No + 64 * wave + lane;
+  GLOBAL F* pp = part + 128 * No + row;
   auto apply = [&](const C (&R)[NQ], int k) {
-    const F y = YL ? ysh[k * 64 + lane] : gathered(k * 64 + lane);
+    const F y = YL ? ysh[k * 64 + row] : gathered(k * 64 + row);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[q] += R[q] * y;
     if (owned && k > 0) {
@@ -729,7 +731,9 @@ __global__ __launch_bounds__(256, 2) void k_xapply(RasLaunch P) {
 #pragma unroll
         for (int w = 0; w < W; ++w) racc += p[w];
       }
-      pp[256 * xpair(b, b + k, No)] = racc;
+      racc += __shfl_xor(racc, 16, 64);
+      racc += __shfl_xor(racc, 32, 64);
+      if (cgrp == 0) pp[64 * xpair(b, b + k, No)] = racc;
     }
   };
   for (int k = 0; k < NT; k += 4) {
@@ -758,7 +762,7 @@ __global__ __launch_bounds__(256, 2) void k_xapply(RasLaunch P) {
 #pragma unroll
   for (int q = 0; q < NQ; ++q)
 #pragma unroll
-    for (int k = 0; k < W; ++k) red[(wave + 4 * q) * W + k][lane] = acc[q][k];
+    for (int k = 0; k < W; ++k) red[(cgrp + 4 * q) * W + k][row] = acc[q][k];
   __syncthreads();
   if (tid < 64) {
     F sum = 0;
@@ -767,8 +771,8 @@ __global__ __launch_bounds__(256, 2) void k_xapply(RasLaunch P) {
   }
 }
 
-// z_a = Cv_a + Co_a + sum_{b < a} sum_w P_{b,a,w}, scattered to the owned
-// rows (tasks: the owned parts' codes; Cv_a only where there are overlap rows)
+// z_a = Cv_a + Co_a + sum_{b < a} P_{b,a}, scattered to the owned rows
+// (tasks: the owned parts' codes; Cv_a only where there are overlap rows)
 template <typename F, typename V>
 __global__ __launch_bounds__(64) void k_xreduce(RasLaunch P) {
   const int code = gptr(P.tasks)[blockIdx.x];
@@ -780,13 +784,7 @@ __global__ __launch_bounds__(64) void k_xreduce(RasLaunch P) {
   const GLOBAL F* part = gptr((const F*)S.part);
   F sum = S.nv > 0 ? part[64 * a + lane] : F(0);
   sum += part[64 * (No + a) + lane];
-  for (int b = 0; b < a; ++b) {
-    const GLOBAL F* pw = part + 128 * No + 256 * xpair(b, a, No) + lane;
-    sum += pw[0];
-    sum += pw[64];
-    sum += pw[128];
-    sum += pw[192];
-  }
+  for (int b = 0; b < a; ++b) sum += part[128 * No + 64 * xpair(b, a, No) + lane];
   const int oc = 64 * a + lane;  // owned row index; local row nv + oc
   if (oc < S.no) {
     const int g = gptr(S.gidx)[S.nv + oc];
