@@ -677,10 +677,12 @@ __global__ __launch_bounds__(256, 2) void k_xapply(RasLaunch P) {
   const GLOBAL int32_t* gidx = gptr(S.gidx);
   const GLOBAL V* rin = gptr((const V*)S.rin);
   GLOBAL F* part = gptr((F*)S.part);
+  // rows of a tile past nv (overlap part) or no (owned part) hold zeros: not read
   auto load_tile = [&](int k, C (&reg)[NQ]) {
     const GLOBAL C* t = base + size_t(k) * (TILE_ELEMS / W);
+    const bool live = row < (owned ? no - 64 * (b + k) : nv - 64 * k);
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) reg[q] = __builtin_nontemporal_load(t + (cgrp + 4 * q) * 64 + row);
+    for (int q = 0; q < NQ; ++q) reg[q] = live ? __builtin_nontemporal_load(t + (cgrp + 4 * q) * 64 + row) : C{};
   };
   // row e of the item's tiles: overlap row e (< nv), or owned row 64 b + e (< no)
   auto gathered = [&](int e) -> F {
