@@ -363,7 +363,8 @@ int64_t nnms_system_device_bytes(const nnms_system* s);
 /* Device bytes an assembly of h with restart_cap = restart (0: NNMS_MAX_RESTART)
  * takes at its peak: what the system keeps (nnms_system_device_bytes) plus
  * what the assembly holds only while it runs (element matrices of the
- * largest level, per-tetrahedron kappa and load arrays, descriptors), for
+ * largest level, per-tetrahedron kappa and load arrays, descriptors, and
+ * with NNMS_APPLY_INVERSE the full panels of every level before packing), for
  * admission decisions; -1 for a null handle or a restart out of range.  The
  * solve plans a system's first solve and operator calls build add a few KiB
  * to a few MiB (descriptors, task lists), recycled through a per-process

@@ -673,7 +673,11 @@ __global__ __launch_bounds__(256) void k_xinv(const FacDesc* __restrict__ d, int
     if (i >= N || i < m0) return;  // past the last tile row, or a zero tile
   } else {
     i = N - 1 - step;
-    if (i < 0) return;
+    // Without overlap rows (the coarsest level: X is the whole inverse,
+    // symmetric, and its tile rows are its tile columns) only the lower
+    // triangle is kept, and X_ij, i >= j, reads only X_mj, m > i: the
+    // upper tiles are not formed.
+    if (i < 0 || (D.nv == 0 && j > i)) return;
   }
   __shared__ F As[64][LDP], Bs[64][LDP];
   const size_t n = size_t(N), NN = n * n, col = size_t(j) * n;

@@ -373,3 +373,22 @@ def test_clipped_mls_matches_oracle(restrict):
             R.sort_indices()
             assert np.array_equal(rp, R.indptr) and np.array_equal(col, R.indices)
             assert np.abs(w - R.data).max() <= 1e-11
+
+
+def test_dense_apply_option():
+    """The inverse-panel option is reported per dense level (the coarsest
+    level too, ILU levels never), costs more device memory per system than
+    the sweeps (the packed panels and their partial sums beside the LU), and
+    an unknown value is refused."""
+    pb = W.Problem("t3", [W.kuhn_cube(9, 1), W.kuhn_cube(5, 2), W.kuhn_cube(3, 3)], [4, 2], W.KappaField())
+    ms = [nnms.Mesh.from_workload(m) for m in pb.meshes]
+    hs = nnms.Hierarchy(ms, pb.nparts, device=False)
+    hi = nnms.Hierarchy(ms, pb.nparts, device=False, dense_apply=nnms.INVERSE)
+    assert all(hs.level_info(l).dense_apply == nnms.SWEEPS for l in range(3))
+    assert all(hi.level_info(l).dense_apply == nnms.INVERSE for l in range(3))
+    assert hi.system_bytes() > hs.system_bytes()
+    hl = nnms.Hierarchy(ms, pb.nparts, device=False, subsolver=nnms.ILU, dense_apply=nnms.INVERSE)
+    assert [hl.level_info(l).dense_apply for l in range(3)] == [nnms.SWEEPS, nnms.SWEEPS, nnms.INVERSE]
+    with pytest.raises(nnms.NNMSError) as e:
+        nnms.Hierarchy(ms, pb.nparts, device=False, dense_apply=7)
+    assert e.value.name == "INVALID_ARG"
