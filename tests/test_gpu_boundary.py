@@ -32,9 +32,10 @@ def _problem(kappa=None):
     return W.Problem("boundary", ms, [4, 2], kappa if kappa is not None else W.kappa_draw(204, 205))
 
 
-def _hier(nnms, pb, precision=None):
+def _hier(nnms, pb, precision=None, dense_apply=0):
     ms = [nnms.Mesh.from_workload(m) for m in pb.meshes]
-    return ms, nnms.Hierarchy(ms, pb.nparts, precision=nnms.FP64 if precision is None else precision)
+    return ms, nnms.Hierarchy(ms, pb.nparts, precision=nnms.FP64 if precision is None else precision,
+                              dense_apply=dense_apply)
 
 
 def _per_tet(pb):
@@ -131,10 +132,10 @@ def test_bad_kappa_and_load_values_refused(nnms):
     assert nnms.device_bytes_in_use() == before
 
 
-@pytest.mark.parametrize("restart", [30, 64])
-def test_budget_and_system_bytes(nnms, restart):
+@pytest.mark.parametrize("restart,mode", [(30, 0), (64, 0), (30, 1)])
+def test_budget_and_system_bytes(nnms, restart, mode):
     pb = _problem()
-    ms, h = _hier(nnms, pb)
+    ms, h = _hier(nnms, pb, dense_apply=mode)
     need = h.system_bytes(restart)
     before = nnms.device_bytes_in_use()
     with pytest.raises(nnms.NNMSError) as e:
@@ -145,6 +146,13 @@ def test_budget_and_system_bytes(nnms, restart):
     # resident bytes within the peak the budget covers; the transient part is
     # the element matrices of the largest level and the kappa / load arrays
     tr = 8 * 17 * max(m.nt for m in pb.meshes) + 8 * sum(m.nt for m in pb.meshes) + 8 * pb.meshes[0].nt
+    if mode == nnms.INVERSE:
+        # and the full inverse panels of every level before packing (N x No tiles)
+        for l in range(len(pb.meshes)):
+            owner, sets = h.partition(l)
+            for p, S in enumerate(sets):
+                no = len(S) if l == len(pb.meshes) - 1 else int(np.count_nonzero(np.asarray(owner)[S] == p))
+                tr += 8 * 4096 * ((len(S) + 63) // 64) * ((no + 63) // 64)
     assert need - tr - 64 * 1024 <= s.device_bytes() <= need
 
 

@@ -170,3 +170,29 @@ def test_full_size_32(nnms):
     ref = oprob.solve(o)
     assert abs(info.iterations - ref.iterations) <= 1
     assert np.linalg.norm(x - ref.x) <= 1e-7 * np.linalg.norm(ref.x)
+
+
+def test_inverse_panels(nnms, small):
+    """Dense subdomain solves through inverse panels (the benchmark's
+    default) on the three-component problem: smoother on every level and one
+    V-cycle entry by entry against the oracle (1e-9), a solve within one
+    iteration of the oracle's and x* to 1e-7."""
+    pb, _, o = small
+    ms, h, s = _lib(nnms, pb, dense_apply=nnms.INVERSE)
+    assert all(h.level_info(l).dense_apply == nnms.INVERSE for l in range(3))
+    rng = np.random.default_rng(9)
+    for l in range(3):
+        r = rng.standard_normal(s.n[l])
+        r[el.dof_mask(pb.meshes[l].dirichlet) != 0] = 0
+        z = s.apply_smoother(l, r)
+        ref = o.vcycle.levels[l].ras.apply(r) if l < 2 else np.linalg.solve(o.A[l].toarray(), r)
+        assert _entrywise(z, ref, 1e-9), l
+    r = rng.standard_normal(s.n[0])
+    r[el.dof_mask(pb.meshes[0].dirichlet) != 0] = 0
+    assert _entrywise(s.apply_vcycle(r), o.vcycle(r), 1e-9)
+    x, info = s.solve(s.rhs())
+    ref = oprob.solve(o)
+    assert info.status == 0 and info.relres <= 1e-8
+    assert abs(info.iterations - ref.iterations) <= 1
+    xs = oprob.exact(o)
+    assert np.linalg.norm(x - xs) <= 1e-7 * np.linalg.norm(xs)

@@ -173,3 +173,33 @@ def test_refactoring_in_place_gives_the_same_panels(cases):
     g.s.time_kernel(6, 0, reps=1)
     for p, X in enumerate(before):
         assert np.array_equal(g.s.inverse_panels(0, p), X), p
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_large_direct_level(precision):
+    """One level only: the whole system is the coarsest level, solved through
+    its whole inverse.  9,261 unknowns (145 tiles per side) are more rows
+    than the smoother stages in LDS, so its work items read the gathered
+    rows from global memory instead: the direct solve against a sparse
+    direct solve, entry by entry (1e-10 relative in FP64; 2e-5 in mixed
+    precision, whose level vectors are FP32: their rounding times the
+    condition number), and one FGMRES iteration (two in mixed precision)."""
+    import scipy.sparse.linalg as spla
+
+    nnms = _gpu()
+    from oracle import fem
+
+    mesh = W.kuhn_cube(22, 77)
+    pb = W.Problem("direct22", [mesh], [], W.kappa_draw(204, 205), precision=precision)
+    g = Built(pb, precision=precision)
+    li = g.h.level_info(0)
+    assert li.dense_apply == nnms.INVERSE and (li.ninterior + 63) // 64 > 128
+    A, b = fem.assemble(mesh, pb.kappa)
+    r = np.random.default_rng(21).standard_normal(mesh.nv)
+    r[mesh.dirichlet != 0] = 0
+    z = g.s.apply_smoother(0, r)
+    ref = spla.spsolve(A.tocsc(), r)
+    tol = 1e-10 if precision == "fp64" else 2e-5
+    assert np.abs(z - ref).max() <= tol * np.abs(ref).max()
+    x, info = g.s.solve(b)
+    assert info.status == 0 and info.relres <= 1e-8 and info.iterations <= (1 if precision == "fp64" else 2)
