@@ -203,3 +203,38 @@ def test_large_direct_level(precision):
     assert np.abs(z - ref).max() <= tol * np.abs(ref).max()
     x, info = g.s.solve(b)
     assert info.status == 0 and info.relres <= 1e-8 and info.iterations <= (1 if precision == "fp64" else 2)
+
+
+@pytest.mark.parametrize("overlap", [0, 1, 2])
+def test_tiny_and_ragged_subdomains(overlap):
+    """Subdomains smaller than one tile (9^3 fine mesh in 16 parts: 32 owned
+    rows), no overlap (every subdomain its own whole inverse, lower triangle
+    only, no overlap part) and two layers (more overlap rows than owned
+    ones): panels, smoother and V-cycle against the oracle, and a solve."""
+    pb = W.Problem("tiny", [W.kuhn_cube(9, 31), W.kuhn_cube(5, 32), W.kuhn_cube(3, 33)], [16, 4],
+                   W.kappa_draw(204, 205), overlap=overlap)
+    g = Built(pb)
+    o = oprob.build(pb)
+    L = len(pb.meshes)
+    for l in range(L):
+        owner, sets = g.h.partition(l)
+        A = o.A[l].tocsr()
+        for p, S in enumerate(sets):
+            order = _local_order(S, owner, p, l < L - 1)
+            n = len(order)
+            nv = n - int(np.count_nonzero(np.asarray(owner)[order] == p)) if l < L - 1 else 0
+            ref = np.linalg.inv(A[order][:, order].toarray())[:, nv:]
+            X = g.s.inverse_panels(l, p)
+            assert np.abs(X[:n, :n - nv] - ref).max() <= 1e-11 * np.abs(ref).max(), (l, p)
+        rng = np.random.default_rng(40 + l)
+        r = rng.standard_normal(g.s.n[l])
+        r[pb.meshes[l].dirichlet != 0] = 0
+        z = g.s.apply_smoother(l, r)
+        ref = o.vcycle.levels[l].ras.apply(r) if l < L - 1 else np.linalg.solve(o.A[l].toarray(), r)
+        assert _rel(z, ref) <= 1e-9, (l, _rel(z, ref))
+    r = np.random.default_rng(3).standard_normal(g.s.n[0])
+    r[pb.meshes[0].dirichlet != 0] = 0
+    assert _rel(g.s.apply_vcycle(r), o.vcycle(r)) <= 1e-9
+    x, info = g.s.solve(o.b)
+    assert info.status == 0 and info.relres <= 1e-8
+    assert abs(info.iterations - oprob.solve(o).iterations) <= 1
