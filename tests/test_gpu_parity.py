@@ -209,7 +209,7 @@ def _rebuild_lu(lu, il):
 
 @pytest.mark.parametrize("case,precision", [("cube16", "fp64"), ("tiny3", "fp64"), ("tiny3", "mixed")])
 def test_factors_reproduce_subdomain_matrices(case, precision, request):
-    """Blocked LU (several block columns of 4 tiles and a ragged last one on
+    """Blocked LU (a block column of six tiles and a ragged last one on
     the 16^3 problem's 600-row subdomains): L U equals the oracle's A[S_p, S_p]
     in the documented local order (overlap rows first, owned rows last on the
     smoothed levels), the padding block is the identity, and refactoring in
