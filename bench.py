@@ -108,10 +108,25 @@ def ilu_bytes(h, level, s_bytes):
 
 def lu_flops(h, level):
     """Algorithmic flops of the level's dense subdomain LUs: (2/3) n_p^3 each
-    (unpadded sizes; the kernels also run the 64-padding)."""
+    (unpadded sizes; the kernels also run the 64-padding), plus, with inverse
+    panels, their block substitutions: the forward one over the owned
+    columns' unit vectors (n_o^3 / 3) and the backward one of every owned
+    column (n_p^2 n_o); on the coarsest level, whose whole inverse is kept
+    as its lower triangle, n^3 / 3 + n^3 / 2."""
+    from paper_2412_08981_amd import nnms
+
     owner, sets = h.partition(level)
+    owner = np.asarray(owner)
     n = np.array([len(S) for S in sets], dtype=np.float64)
-    return float(np.sum(2.0 / 3.0 * n ** 3))
+    fl = float(np.sum(2.0 / 3.0 * n ** 3))
+    if h.level_info(level).dense_apply == nnms.INVERSE:
+        if level == h.L - 1:
+            fl += float(np.sum(n ** 3 / 3.0 + n ** 3 / 2.0))
+        else:
+            no = np.array([np.count_nonzero(owner[np.asarray(S)] == p) for p, S in enumerate(sets)],
+                          dtype=np.float64)
+            fl += float(np.sum(no ** 3 / 3.0 + n * n * no))
+    return fl
 
 
 def spmv_bytes(h, level, s_bytes):
