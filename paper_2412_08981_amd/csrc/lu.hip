@@ -114,8 +114,22 @@ hipError_t launch_extract(const FacDesc* d, int nd, int maxn, hipStream_t s) {
 
 // ---------------------------------------------------------------------------
 // C += A * B on 64x64 tiles staged in LDS, MFMA 16x16x4; wave w owns the
-// 32x32 quadrant (w/2, w%2) of C.
+// 32x32 quadrant (w/2, w%2) of C.  Quadrant accumulators, here and in the
+// products from global memory below, hold rows R0 + 16 rb + (MFMA row) and
+// columns C0 + 2 lr + cb (lr = lane % 16, cb = 0, 1): a lane's two column
+// blocks are adjacent columns, one 8- or 16-byte piece of a tile row.
 // ---------------------------------------------------------------------------
+template <typename F>
+struct Pair;
+template <>
+struct Pair<double> {
+  typedef double type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Pair<float> {
+  typedef float type __attribute__((ext_vector_type(2)));
+};
+
 template <typename F>
 __device__ __forceinline__ void tile_mma(F (*As)[LDP], F (*Bs)[LDP], typename Mma<F>::acc_t (&acc)[2][2]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -125,7 +139,7 @@ __device__ __forceinline__ void tile_mma(F (*As)[LDP], F (*Bs)[LDP], typename Mm
   for (int kk = 0; kk < 16; ++kk) {
     const int kc = kk * 4 + lk;
     F a0 = As[R0 + lr][kc], a1 = As[R0 + 16 + lr][kc];
-    F b0 = Bs[kc][C0 + lr], b1 = Bs[kc][C0 + 16 + lr];
+    F b0 = Bs[kc][C0 + 2 * lr], b1 = Bs[kc][C0 + 2 * lr + 1];
     acc[0][0] = Mma<F>::op(a0, b0, acc[0][0]);
     acc[0][1] = Mma<F>::op(a0, b1, acc[0][1]);
     acc[1][0] = Mma<F>::op(a1, b0, acc[1][0]);
@@ -142,7 +156,7 @@ __device__ __forceinline__ void acc_to_lds(typename Mma<F>::acc_t (&acc)[2][2], 
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) Cs[R0 + rb * 16 + Mma<F>::row(lane, v)][C0 + cb * 16 + (lane & 15)] = acc[rb][cb][v];
+      for (int v = 0; v < 4; ++v) Cs[R0 + rb * 16 + Mma<F>::row(lane, v)][C0 + 2 * (lane & 15) + cb] = acc[rb][cb][v];
 }
 
 // ---------------------------------------------------------------------------
@@ -152,28 +166,33 @@ __device__ __forceinline__ void acc_to_lds(typename Mma<F>::acc_t (&acc)[2][2], 
 // ---------------------------------------------------------------------------
 template <typename F>
 __device__ __forceinline__ void acc_load(const GLOBAL F* __restrict__ T, typename Mma<F>::acc_t (&acc)[2][2]) {
+  using P = typename Pair<F>::type;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int R0 = (wave >> 1) * 32, C0 = (wave & 1) * 32;
 #pragma unroll
   for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-        acc[rb][cb][v] = T[tile_off<F>(R0 + rb * 16 + Mma<F>::row(lane, v), C0 + cb * 16 + (lane & 15))];
+    for (int v = 0; v < 4; ++v) {
+      const P x = *(const GLOBAL P*)(T + tile_off<F>(R0 + rb * 16 + Mma<F>::row(lane, v), C0 + 2 * (lane & 15)));
+      acc[rb][0][v] = x[0];
+      acc[rb][1][v] = x[1];
+    }
 }
 
 template <typename F>
 __device__ __forceinline__ void acc_store(typename Mma<F>::acc_t (&acc)[2][2], GLOBAL F* __restrict__ T) {
+  using P = typename Pair<F>::type;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int R0 = (wave >> 1) * 32, C0 = (wave & 1) * 32;
 #pragma unroll
   for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-        T[tile_off<F>(R0 + rb * 16 + Mma<F>::row(lane, v), C0 + cb * 16 + (lane & 15))] = acc[rb][cb][v];
+    for (int v = 0; v < 4; ++v) {
+      P x;
+      x[0] = acc[rb][0][v];
+      x[1] = acc[rb][1][v];
+      *(GLOBAL P*)(T + tile_off<F>(R0 + rb * 16 + Mma<F>::row(lane, v), C0 + 2 * (lane & 15))) = x;
+    }
 }
 
 template <typename F>
@@ -184,37 +203,50 @@ __device__ __forceinline__ void acc_negate(typename Mma<F>::acc_t (&acc)[2][2]) 
     for (int b = 0; b < 2; ++b) acc[a][b] = -acc[a][b];
 }
 
-// MFMA operands of 16 consecutive k (four 16x16x4 steps) of one quadrant
+// MFMA operands of 16 consecutive k of one quadrant, in NS = 4 / W
+// sub-groups of 4W k: 16-byte A chunks (W consecutive k of one row) and B
+// pairs (one k, the lane's two adjacent columns).  In sub-group u, step
+// s = 0 .. W-1 of lane (lr, lk) takes k = 16 g + 4W u + W lk + s, so one A
+// chunk serves W MFMA steps; the sum over k is the same, only the order in
+// which the MFMAs add the k values differs.
 template <typename F>
 struct Frag {
-  F a0[4], a1[4], b0[4], b1[4];
+  static constexpr int W = Chunk<F>::W, NS = 4 / W;
+  typename Chunk<F>::type a[NS][2];
+  typename Pair<F>::type b[NS][W];
 };
 
 // group g (0..3) of the 64-deep product Lt * Ut
 template <typename F>
 __device__ __forceinline__ void frag_load(Frag<F>& f, const GLOBAL F* __restrict__ Lt, const GLOBAL F* __restrict__ Ut, int g) {
+  using C = typename Chunk<F>::type;
+  using P = typename Pair<F>::type;
+  constexpr int W = Chunk<F>::W, NS = 4 / W;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int R0 = (wave >> 1) * 32, C0 = (wave & 1) * 32;
   const int lr = lane & 15, lk = lane >> 4;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int kc = (4 * g + q) * 4 + lk;
-    f.a0[q] = Lt[tile_off<F>(R0 + lr, kc)];
-    f.a1[q] = Lt[tile_off<F>(R0 + 16 + lr, kc)];
-    f.b0[q] = Ut[tile_off<F>(kc, C0 + lr)];
-    f.b1[q] = Ut[tile_off<F>(kc, C0 + 16 + lr)];
+  for (int u = 0; u < NS; ++u) {
+    const GLOBAL C* la = (const GLOBAL C*)Lt + (16 / W * g + 4 * u + lk) * 64 + R0 + lr;
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) f.a[u][rb] = la[16 * rb];
+    const GLOBAL F* ub = Ut + tile_off<F>(16 * g + 4 * W * u + W * lk, C0 + 2 * lr);
+#pragma unroll
+    for (int s = 0; s < W; ++s) f.b[u][s] = *(const GLOBAL P*)(ub + W * s);
   }
 }
 
 template <typename F>
 __device__ __forceinline__ void frag_mma(const Frag<F>& f, typename Mma<F>::acc_t (&acc)[2][2]) {
+  constexpr int W = Chunk<F>::W, NS = 4 / W;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    acc[0][0] = Mma<F>::op(f.a0[q], f.b0[q], acc[0][0]);
-    acc[0][1] = Mma<F>::op(f.a0[q], f.b1[q], acc[0][1]);
-    acc[1][0] = Mma<F>::op(f.a1[q], f.b0[q], acc[1][0]);
-    acc[1][1] = Mma<F>::op(f.a1[q], f.b1[q], acc[1][1]);
-  }
+  for (int u = 0; u < NS; ++u)
+#pragma unroll
+    for (int s = 0; s < W; ++s)
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = Mma<F>::op(f.a[u][rb][s], f.b[u][s][cb], acc[rb][cb]);
 }
 
 // acc += sum_{s<depth} Ls(s) * Us(s), where Ls(s) = a + lt0 + s*lstep tiles and
@@ -476,47 +508,60 @@ __global__ __launch_bounds__(256) void k_lu_panel(const FacDesc* __restrict__ d,
 // trailing update past block column k0 .. k0+depth-1:
 // A_ij -= sum_{s<depth} L_{i,k0+s} U_{k0+s,j} for all i, j >= k0+depth.
 // A work-group covers 2x2 tiles; each wave owns one whole 64x64 tile (4x4
-// MFMA blocks, 16 products per 8 operand loads), the wave pairs that share
-// a tile row or column fetch the same L or U operands through L1.
+// MFMA blocks), the wave pairs that share a tile row or column fetch the
+// same L or U operands through L1.
 // ---------------------------------------------------------------------------
+// Operands of one k-group of the whole-tile product, read as 16-byte chunks
+// (W values).  Inside every 16x16 MFMA block the order of k and of the
+// output columns is permuted so that one chunk feeds W MFMAs: in group g
+// (4W consecutive k) a lane (lr = lane % 16, lk = lane / 16) takes in step
+// s = 0 .. W-1 the k index 4W g + W lk + s, and output block cb holds the
+// columns 16W (cb / W) + W lr + cb % W.  So the lane's A chunk (row
+// 16 rb + lr, W consecutive k) serves its W steps and its B chunk (one k,
+// W consecutive columns) serves W output blocks: 8 loads per 16W MFMAs.
+// The sum over k is the same; only the order in which the MFMAs add the
+// k values changes.
 template <typename F>
-struct Frag64 {
-  F a[2][4], b[2][4];  // two k-steps of four 16-row (A) and 16-column (B) blocks
+struct FragC {
+  using C = typename Chunk<F>::type;
+  static constexpr int W = Chunk<F>::W;
+  C a[4];          // block row rb
+  C b[W][4 / W];   // step s, column chunk c
 };
 
-// k-steps 2h, 2h+1 (h = 0..7) of the 64-deep product Lt * Ut, whole-tile
-// operands.  With W values per 16-byte chunk, A element (16b + lr, kc) of a
-// tile sits at abase + 512h + 256q + 16Wb and B element (kc, 16b + lr) at
-// bbase + 1024b + 4W(2h + q) (kc = 8h + 4q + lk), so every load is a lane
-// offset plus a constant.
+// chunk offsets of a lane inside a tile: A (row 16 rb + lr, k chunk 4g + lk),
+// B (k row 4W g + W lk + s, column chunk 16 c + lr)
 template <typename F>
-__device__ __forceinline__ void frag64_load(Frag64<F>& f, const GLOBAL F* __restrict__ Lt,
-                                           const GLOBAL F* __restrict__ Ut, int h, int abase, int bbase) {
-  constexpr int W = 16 / sizeof(F);
-  const GLOBAL F* la = Lt + abase + 512 * h;
-  const GLOBAL F* ub = Ut + bbase + 8 * W * h;
+__device__ __forceinline__ void fragc_load(FragC<F>& f, const GLOBAL typename Chunk<F>::type* __restrict__ Lt,
+                                          const GLOBAL typename Chunk<F>::type* __restrict__ Ut, int g, int acb,
+                                          int bcb) {
+  constexpr int W = Chunk<F>::W;
+  const GLOBAL typename Chunk<F>::type* la = Lt + acb + 256 * g;
+  const GLOBAL typename Chunk<F>::type* ub = Ut + bcb + 4 * W * g;
 #pragma unroll
-  for (int q = 0; q < 2; ++q)
+  for (int rb = 0; rb < 4; ++rb) f.a[rb] = la[16 * rb];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      f.a[q][b] = la[256 * q + 16 * W * b];
-      f.b[q][b] = ub[1024 * b + 4 * W * q];
-    }
+  for (int s = 0; s < W; ++s)
+#pragma unroll
+    for (int c = 0; c < 4 / W; ++c) f.b[s][c] = ub[1024 * c + s];
 }
 
 template <typename F>
-__device__ __forceinline__ void frag64_mma(const Frag64<F>& f, typename Mma<F>::acc_t (&acc)[4][4]) {
+__device__ __forceinline__ void fragc_mma(const FragC<F>& f, typename Mma<F>::acc_t (&acc)[4][4]) {
+  constexpr int W = Chunk<F>::W;
 #pragma unroll
-  for (int q = 0; q < 2; ++q)
+  for (int s = 0; s < W; ++s)
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = Mma<F>::op(f.a[q][rb], f.b[q][cb], acc[rb][cb]);
+      for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = Mma<F>::op(f.a[rb][s], f.b[s][cb / W][cb % W], acc[rb][cb]);
 }
 
 template <typename F>
 __global__ __launch_bounds__(256, 2) void k_lu_trail(const FacDesc* __restrict__ d, int k0, int depth) {
-  constexpr int W = 16 / sizeof(F);
+  using C = typename Chunk<F>::type;
+  constexpr int W = Chunk<F>::W;
+  constexpr int TC = TILE_ELEMS / W;  // chunks per tile
   // XCD-aware order: each XCD takes a contiguous range of (subdomain,
   // super-tile) work items, so the panels one subdomain's super-tiles share
   // stay in one XCD's L2 instead of being fetched by all eight
@@ -534,49 +579,53 @@ __global__ __launch_bounds__(256, 2) void k_lu_trail(const FacDesc* __restrict__
   if (ti >= nr || tj >= nr) return;  // no barriers below: a wave may leave alone
   const size_t N = D.N;
   const size_t i = k0 + depth + ti, j = k0 + depth + tj;
-  GLOBAL F* fac = gptr((F*)D.fac);
-  GLOBAL F* C = fac + (i * N + j) * TILE_ELEMS;
+  GLOBAL C* fac = gptr((C*)D.fac);
+  GLOBAL C* Ct = fac + (i * N + j) * TC;
   const int lr = lane & 15, lk = lane >> 4;
-  const int abase = ((lk / W) * 64 + lr) * W + lk % W;
-  const int bbase = (lr / W) * 64 * W + lk * W + lr % W;
+  const int acb = lk * 64 + lr, bcb = lr * 64 + W * lk;
   typename Mma<F>::acc_t acc[4][4];
 #pragma unroll
   for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = typename Mma<F>::acc_t{0, 0, 0, 0};
-  const GLOBAL F* L0 = fac + (i * N + k0) * TILE_ELEMS;          // L_{i,k0+s} = L0 + s tiles
-  const GLOBAL F* U0 = fac + (size_t(k0) * N + j) * TILE_ELEMS;  // U_{k0+s,j} = U0 + s*N tiles
-  const int ng = 8 * depth;  // pairs of k-steps
-  Frag64<F> f0, f1;
-  frag64_load<F>(f0, L0, U0, 0, abase, bbase);
-  // branch-free pipeline: the loads of the next pair of k-steps are issued
-  // before the products of the current one (the last pass reloads group
-  // ng-1, which is in bounds and unused)
+  const GLOBAL C* L0 = fac + (i * N + k0) * TC;          // L_{i,k0+s} = L0 + s tiles
+  const GLOBAL C* U0 = fac + (size_t(k0) * N + j) * TC;  // U_{k0+s,j} = U0 + s*N tiles
+  constexpr int GPT = 16 / W;  // k-groups per tile
+  const int ng = GPT * depth;  // even: GPT is 4 or 8
+  FragC<F> f0, f1;
+  fragc_load<F>(f0, L0, U0, 0, acb, bcb);
+  // branch-free pipeline: the loads of the next k-group are issued before
+  // the products of the current one (the last pass reloads group ng-1,
+  // which is in bounds and unused)
   for (int g = 0; g < ng; g += 2) {
     {
-      const int h = g + 1, s = h >> 3;
-      frag64_load<F>(f1, L0 + size_t(s) * TILE_ELEMS, U0 + size_t(s) * N * TILE_ELEMS, h & 7, abase, bbase);
+      const int h = g + 1, s = h / GPT;
+      fragc_load<F>(f1, L0 + size_t(s) * TC, U0 + size_t(s) * N * TC, h % GPT, acb, bcb);
     }
     __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of the products
-    frag64_mma<F>(f0, acc);
+    fragc_mma<F>(f0, acc);
     __builtin_amdgcn_sched_barrier(0);
     {
-      const int h = min(g + 2, ng - 1), s = h >> 3;
-      frag64_load<F>(f0, L0 + size_t(s) * TILE_ELEMS, U0 + size_t(s) * N * TILE_ELEMS, h & 7, abase, bbase);
+      const int h = min(g + 2, ng - 1), s = h / GPT;
+      fragc_load<F>(f0, L0 + size_t(s) * TC, U0 + size_t(s) * N * TC, h % GPT, acb, bcb);
     }
     __builtin_amdgcn_sched_barrier(0);
-    frag64_mma<F>(f1, acc);
+    fragc_mma<F>(f1, acc);
     __builtin_amdgcn_sched_barrier(0);
   }
-  // C -= acc, one 16-row block at a time
+  // C -= acc: output (16 rb + row(lane, v), 16W c + W lr + w) is element w
+  // of chunk (16 c + lr) * 64 + row of the tile
 #pragma unroll
   for (int rb = 0; rb < 4; ++rb) {
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb)
+    for (int v = 0; v < 4; ++v)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        GLOBAL F* e = C + tile_off<F>(16 * rb + Mma<F>::row(lane, v), 16 * cb + lr);
-        *e = *e - acc[rb][cb][v];
+      for (int c = 0; c < 4 / W; ++c) {
+        GLOBAL C* e = Ct + (16 * c + lr) * 64 + 16 * rb + Mma<F>::row(lane, v);
+        C x = *e;
+#pragma unroll
+        for (int w = 0; w < W; ++w) x[w] -= acc[rb][W * c + w][v];
+        *e = x;
       }
     __builtin_amdgcn_sched_barrier(0);
   }
@@ -695,7 +744,7 @@ __global__ __launch_bounds__(256) void k_xinv(const FacDesc* __restrict__ d, int
       for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int r = R0 + rb * 16 + Mma<F>::row(lane, v), c = C0 + cb * 16 + (lane & 15);
+          const int r = R0 + rb * 16 + Mma<F>::row(lane, v), c = C0 + 2 * (lane & 15) + cb;
           acc[rb][cb][v] = (r == c + off && 64 * j + c < nown) ? F(-1) : F(0);
         }
     acc_add_products<F>(acc, fac, size_t(i) * n + m0, 1, X, col + m0, 1, i - m0);
