@@ -474,22 +474,27 @@ __global__ __launch_bounds__(256) void k_lu_diag(const FacDesc* __restrict__ d, 
 // pending in-block updates fused in front of the product with the inverse.
 template <typename F>
 __global__ __launch_bounds__(256) void k_lu_panel(const FacDesc* __restrict__ d, int k0, int k) {
-  const FacDesc D = d[blockIdx.y];
+  // XCD-aware order: the panel tiles of one subdomain (which share the
+  // diagonal tile's inverse and the pending-update operands) run on one XCD
+  const int gx = int(gridDim.x);
+  const int lin = xcd_block(int(blockIdx.y) * gx + int(blockIdx.x), gx * int(gridDim.y));
+  const int bx = lin % gx;
+  const FacDesc D = d[lin / gx];
   const int nr = D.N - k - 1;
-  if (nr <= 0 || int(blockIdx.x) >= 2 * nr) return;
+  if (nr <= 0 || bx >= 2 * nr) return;
   __shared__ F As[64][LDP], Bs[64][LDP];
   const size_t N = D.N;
   GLOBAL F* fac = gptr((F*)D.fac);
   typename Mma<F>::acc_t acc[2][2];
   size_t target;
-  if (int(blockIdx.x) < nr) {  // L_ik = (A_ik - sum_s L_is U_sk) inv(U_kk)
-    const size_t i = k + 1 + blockIdx.x;
+  if (bx < nr) {  // L_ik = (A_ik - sum_s L_is U_sk) inv(U_kk)
+    const size_t i = k + 1 + bx;
     target = i * N + k;
     acc_updated_tile<F>(acc, fac, target, i * N + k0, 1, size_t(k0) * N + k, N, k - k0);
     acc_to_lds<F>(acc, As);
     tile_to_lds<F>(fac + (size_t(k) * N + k) * TILE_ELEMS, Bs);
   } else {  // U_kj = inv(L_kk) (A_kj - sum_s L_ks U_sj)
-    const size_t j = k + 1 + (blockIdx.x - nr);
+    const size_t j = k + 1 + (bx - nr);
     target = size_t(k) * N + j;
     acc_updated_tile<F>(acc, fac, target, size_t(k) * N + k0, 1, size_t(k0) * N + j, N, k - k0);
     acc_to_lds<F>(acc, Bs);
@@ -703,76 +708,210 @@ hipError_t launch_lu(const FacDesc* d, int nd, int maxN, int* err, hipStream_t s
 //   forward   Y_ij = inv(L_ii) (E_ij - sum_{m0(j) <= m < i} L_im Y_mj),
 //             where Y_mj = 0 for m < m0(j) = floor((nv + 64 j) / 64) (the
 //             unit vectors of column tile j start in tile row m0(j));
-//   backward  X_ij = inv(U_ii) (Y_ij - sum_{m > i} U_im X_mj),  i = N-1 .. 0,
-// one launch per tile row (the rows depend on each other), every
-// (subdomain, tile column) of that row a work-group; X overwrites Y in
-// place.  Tile (i, j) of X sits at tile j N + i.  Padding rows (unit
-// diagonal in the factor, no unit vector) and padding columns stay zero.
+//   backward  X_ij = inv(U_ii) (Y_ij - sum_{m > i} U_im X_mj),  i = N-1 .. 0.
+// X overwrites Y in place; tile (i, j) of X sits at tile j N + i.  Padding
+// rows (unit diagonal in the factor, no unit vector) and padding columns
+// stay zero.
+//
+// The tile rows are taken in blocks of four, one launch per block (the
+// forward from tile row nv / 64 down, the backward from N - 1 up).  A
+// work-group owns one tile column j of one subdomain, and wave t the whole
+// tile of the block's row t (the layout of the trailing update):
+//   phase 1: the products with the rows already final (outside the block),
+//            every wave reading the same X (or Y) tiles, through L1;
+//   phase 2: the block row by row, nearest the final rows first: the row's
+//            wave puts its tile in LDS, the work-group multiplies it by the
+//            diagonal inverse and stores it, and the waves of the later rows
+//            add its products (their tiles hold minus the right-hand side).
 // ---------------------------------------------------------------------------
+constexpr int XINV_ROWS = 4;
+
+// whole-tile accumulator of a wave (the trailing update's layout: block
+// (rb, cb) holds rows 16 rb + MFMA row and columns 16W (cb / W) + W lr + cb % W)
 template <typename F>
-__global__ __launch_bounds__(256) void k_xinv(const FacDesc* __restrict__ d, int step, int fwd) {
-  const FacDesc D = d[blockIdx.y];
-  const int j = int(blockIdx.x);
+__device__ __forceinline__ void acc4_load(const GLOBAL F* __restrict__ T, typename Mma<F>::acc_t (&acc)[4][4]) {
+  using C = typename Chunk<F>::type;
+  constexpr int W = Chunk<F>::W;
+  const int lane = threadIdx.x & 63, lr = lane & 15;
+  const GLOBAL C* Tc = (const GLOBAL C*)T;
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int c = 0; c < 4 / W; ++c) {
+        const C x = Tc[(16 * c + lr) * 64 + 16 * rb + Mma<F>::row(lane, v)];
+#pragma unroll
+        for (int w = 0; w < W; ++w) acc[rb][W * c + w][v] = x[w];
+      }
+}
+
+template <typename F>
+__device__ __forceinline__ void acc4_to_lds(typename Mma<F>::acc_t (&acc)[4][4], F (*Cs)[LDP], F scale) {
+  constexpr int W = Chunk<F>::W;
+  const int lane = threadIdx.x & 63, lr = lane & 15;
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Cs[16 * rb + Mma<F>::row(lane, v)][16 * W * (cb / W) + W * lr + cb % W] = scale * acc[rb][cb][v];
+}
+
+// acc += A * Bs for a whole tile: A in global memory (16-byte chunks), Bs in LDS
+template <typename F>
+__device__ __forceinline__ void acc4_add_product_lds(typename Mma<F>::acc_t (&acc)[4][4], const GLOBAL F* __restrict__ A,
+                                                     F (*Bs)[LDP]) {
+  using C = typename Chunk<F>::type;
+  constexpr int W = Chunk<F>::W, GPT = 16 / W;
+  const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+  const GLOBAL C* Ac = (const GLOBAL C*)A + lk * 64 + lr;
+  C a0[4], a1[4];
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb) a0[rb] = Ac[16 * rb];
+#pragma unroll
+  for (int g = 0; g < GPT; ++g) {
+    C(&cur)[4] = (g & 1) ? a1 : a0;
+    C(&nxt)[4] = (g & 1) ? a0 : a1;
+    if (g + 1 < GPT) {
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) nxt[rb] = Ac[256 * (g + 1) + 16 * rb];
+    }
+#pragma unroll
+    for (int s = 0; s < W; ++s) {
+      const int k = 4 * W * g + W * lk + s;
+      F b[4];
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) b[cb] = Bs[k][16 * W * (cb / W) + W * lr + cb % W];
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = Mma<F>::op(cur[rb][s], b[cb], acc[rb][cb]);
+    }
+  }
+}
+
+template <typename F>
+__global__ __launch_bounds__(256, 2) void k_xinv(const FacDesc* __restrict__ d, int blk, int fwd) {
+  using C = typename Chunk<F>::type;
+  constexpr int W = Chunk<F>::W, TC = TILE_ELEMS / W, GPT = 16 / W;
+  // XCD-aware order: the tile columns of one subdomain (which share its
+  // factor's tile rows) run on one XCD
+  const int gx = int(gridDim.x);
+  const int lin = xcd_block(int(blockIdx.y) * gx + int(blockIdx.x), gx * int(gridDim.y));
+  const FacDesc D = d[lin / gx];
+  const int j = lin % gx;
   if (!D.X || j >= D.No) return;
   const int N = D.N;
-  int i, m0 = 0;
+  // rows of the block this work-group forms: r(t) = r0 + dir t, t < nr
+  int r0, dir, nr, m0 = 0;
   if (fwd) {
+    const int i0 = D.nv / 64 + XINV_ROWS * blk;
     m0 = (D.nv + 64 * j) / 64;
-    i = D.nv / 64 + step;
-    if (i >= N || i < m0) return;  // past the last tile row, or a zero tile
+    r0 = max(i0, m0);  // Y_rj = 0 above tile row m0(j)
+    nr = min(i0 + XINV_ROWS, N) - r0;
+    dir = 1;
   } else {
-    i = N - 1 - step;
+    const int i0 = N - 1 - XINV_ROWS * blk;
+    r0 = i0;
+    nr = min(XINV_ROWS, i0 + 1);
     // Without overlap rows (the coarsest level: X is the whole inverse,
     // symmetric, and its tile rows are its tile columns) only the lower
     // triangle is kept, and X_ij, i >= j, reads only X_mj, m > i: the
     // upper tiles are not formed.
-    if (i < 0 || (D.nv == 0 && j > i)) return;
+    if (D.nv == 0) nr = min(nr, i0 - j + 1);
+    dir = -1;
   }
+  if (nr <= 0) return;
   __shared__ F As[64][LDP], Bs[64][LDP];
   const size_t n = size_t(N), NN = n * n, col = size_t(j) * n;
   const GLOBAL F* fac = gptr((const F*)D.fac);
   GLOBAL F* X = gptr((F*)D.X);
-  typename Mma<F>::acc_t acc[2][2];
+  // wave-uniform: keeps the tile base addresses in scalar registers
+  const int t = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int lr = lane & 15, lk = lane >> 4;
+  const bool mine = t < nr;  // this wave holds row r(t) of the block
+  const int r = r0 + dir * t;
+  typename Mma<F>::acc_t acc[4][4];
+  // phase 1: acc = -(right-hand side of row r) + products with the final rows
+  int m1 = 0, depth = 0;
   if (fwd) {
-    // acc = -E_ij: E(r, c) = 1 where 64 i + r = nv + 64 j + c, for owned columns 64 j + c < n - nv
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int R0 = (wave >> 1) * 32, C0 = (wave & 1) * 32;
-    const int off = D.nv + 64 * j - 64 * i, nown = D.n - D.nv;
+    // -E: E(r, c) = 1 where 64 i + r = nv + 64 j + c, for owned columns 64 j + c < n - nv
+    const int off = D.nv + 64 * j - 64 * r, nown = D.n - D.nv;
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
+    for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-      for (int cb = 0; cb < 2; ++cb)
+      for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int r = R0 + rb * 16 + Mma<F>::row(lane, v), c = C0 + 2 * (lane & 15) + cb;
-          acc[rb][cb][v] = (r == c + off && 64 * j + c < nown) ? F(-1) : F(0);
+          const int rr = 16 * rb + Mma<F>::row(lane, v), c = 16 * W * (cb / W) + W * lr + cb % W;
+          acc[rb][cb][v] = (rr == c + off && 64 * j + c < nown) ? F(-1) : F(0);
         }
-    acc_add_products<F>(acc, fac, size_t(i) * n + m0, 1, X, col + m0, 1, i - m0);
-    acc_negate<F>(acc);
-    acc_to_lds<F>(acc, Bs);
-    tile_to_lds<F>(fac + (NN + i) * TILE_ELEMS, As);  // inv(L_ii)
+    m1 = m0, depth = r0 - m0;  // final rows m0(j) .. r0 - 1 (none when the block starts at m0(j))
   } else {
-    acc_load<F>(X + (col + i) * TILE_ELEMS, acc);
-    acc_negate<F>(acc);
-    acc_add_products<F>(acc, fac, size_t(i) * n + i + 1, 1, X, col + i + 1, 1, N - 1 - i);
-    acc_negate<F>(acc);
-    acc_to_lds<F>(acc, Bs);
-    tile_to_lds<F>(fac + (size_t(i) * n + i) * TILE_ELEMS, As);  // inv(U_ii), the diagonal tile
+    if (mine) {
+      acc4_load<F>(X + (col + r) * TILE_ELEMS, acc);
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = -acc[rb][cb];
+    }
+    m1 = r0 + 1, depth = N - 1 - r0;  // final rows r0 + 1 .. N - 1
   }
-  __syncthreads();
+  if (mine && depth > 0) {
+    const GLOBAL C* A0 = (const GLOBAL C*)fac + (size_t(r) * n + m1) * TC;  // L_{r, m1 + s} / U_{r, m1 + s}
+    const GLOBAL C* B0 = (const GLOBAL C*)X + (col + m1) * TC;              // Y_{m1 + s, j} / X_{m1 + s, j}
+    const int acb = lk * 64 + lr, bcb = lr * 64 + W * lk;
+    const int ng = GPT * depth;  // even
+    FragC<F> f0, f1;
+    fragc_load<F>(f0, A0, B0, 0, acb, bcb);
+    for (int g = 0; g < ng; g += 2) {
+      {
+        const int h = g + 1, s = h / GPT;
+        fragc_load<F>(f1, A0 + size_t(s) * TC, B0 + size_t(s) * TC, h % GPT, acb, bcb);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      fragc_mma<F>(f0, acc);
+      __builtin_amdgcn_sched_barrier(0);
+      {
+        const int h = min(g + 2, ng - 1), s = h / GPT;
+        fragc_load<F>(f0, A0 + size_t(s) * TC, B0 + size_t(s) * TC, h % GPT, acb, bcb);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      fragc_mma<F>(f1, acc);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  // phase 2: the block row by row
+  for (int q = 0; q < nr; ++q) {
+    const int rq = r0 + dir * q;
+    if (q > 0) __syncthreads();  // the previous row's products have read Bs
+    if (t == q) acc4_to_lds<F>(acc, Bs, F(-1));  // rhs - products
+    tile_to_lds<F>(fac + (fwd ? NN + rq : size_t(rq) * n + rq) * TILE_ELEMS, As);  // inv(L_qq) / inv(U_qq)
+    __syncthreads();
+    typename Mma<F>::acc_t x[2][2];
 #pragma unroll
-  for (int u = 0; u < 2; ++u)
+    for (int u = 0; u < 2; ++u)
 #pragma unroll
-    for (int v = 0; v < 2; ++v) acc[u][v] = typename Mma<F>::acc_t{0, 0, 0, 0};
-  tile_mma<F>(As, Bs, acc);
-  acc_store<F>(acc, X + (col + i) * TILE_ELEMS);
+      for (int v = 0; v < 2; ++v) x[u][v] = typename Mma<F>::acc_t{0, 0, 0, 0};
+    tile_mma<F>(As, Bs, x);
+    acc_store<F>(x, X + (col + rq) * TILE_ELEMS);
+    if (q + 1 < nr) {
+      __syncthreads();  // tile_mma has read Bs
+      acc_to_lds<F>(x, Bs);
+      __syncthreads();
+      // later rows hold -(rhs - products): add L_{r, rq} x / U_{r, rq} x
+      if (mine && t > q) acc4_add_product_lds<F>(acc, fac + (size_t(r) * n + rq) * TILE_ELEMS, Bs);
+    }
+  }
 }
 
 template <typename F>
 hipError_t launch_xinv(const FacDesc* d, int nd, int maxNo, int fsteps, int bsteps, hipStream_t s) {
   if (nd <= 0 || maxNo <= 0) return hipSuccess;
-  for (int k = 0; k < fsteps; ++k) hipLaunchKernelGGL((k_xinv<F>), dim3(maxNo, nd), dim3(256), 0, s, d, k, 1);
-  for (int k = 0; k < bsteps; ++k) hipLaunchKernelGGL((k_xinv<F>), dim3(maxNo, nd), dim3(256), 0, s, d, k, 0);
+  constexpr int R = XINV_ROWS;
+  for (int k = 0; k < (fsteps + R - 1) / R; ++k) hipLaunchKernelGGL((k_xinv<F>), dim3(maxNo, nd), dim3(256), 0, s, d, k, 1);
+  for (int k = 0; k < (bsteps + R - 1) / R; ++k) hipLaunchKernelGGL((k_xinv<F>), dim3(maxNo, nd), dim3(256), 0, s, d, k, 0);
   return hipGetLastError();
 }
 
