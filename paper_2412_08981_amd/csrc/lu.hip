@@ -48,31 +48,35 @@ struct Mma<float> {
   static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 
+// whole-tile copies between global memory and LDS by a work-group of 256:
+// every load of the thread is issued before the first write
 template <typename F>
 __device__ __forceinline__ void tile_to_lds(const GLOBAL F* g, F (*s)[LDP]) {
   using C = typename Chunk<F>::type;
-  constexpr int W = Chunk<F>::W;
+  constexpr int W = Chunk<F>::W, NC = TILE_ELEMS / W / 256;
   const GLOBAL C* gc = (const GLOBAL C*)g;
-  for (int q = threadIdx.x; q < TILE_ELEMS / W; q += 256) {
-    const int cg = q / 64, r = q % 64;
-    const C v = gc[q];
-    const F* e = (const F*)&v;
+  C v[NC];
 #pragma unroll
-    for (int k = 0; k < W; ++k) s[r][cg * W + k] = e[k];
+  for (int u = 0; u < NC; ++u) v[u] = gc[threadIdx.x + 256 * u];
+#pragma unroll
+  for (int u = 0; u < NC; ++u) {
+    const int q = threadIdx.x + 256 * u, cg = q / 64, r = q % 64;
+#pragma unroll
+    for (int k = 0; k < W; ++k) s[r][cg * W + k] = v[u][k];
   }
 }
 
 template <typename F>
 __device__ __forceinline__ void lds_to_tile(F (*s)[LDP], GLOBAL F* g) {
   using C = typename Chunk<F>::type;
-  constexpr int W = Chunk<F>::W;
+  constexpr int W = Chunk<F>::W, NC = TILE_ELEMS / W / 256;
   GLOBAL C* gc = (GLOBAL C*)g;
-  for (int q = threadIdx.x; q < TILE_ELEMS / W; q += 256) {
-    const int cg = q / 64, r = q % 64;
-    C v;
-    F* e = (F*)&v;
 #pragma unroll
-    for (int k = 0; k < W; ++k) e[k] = s[r][cg * W + k];
+  for (int u = 0; u < NC; ++u) {
+    const int q = threadIdx.x + 256 * u, cg = q / 64, r = q % 64;
+    C v;
+#pragma unroll
+    for (int k = 0; k < W; ++k) v[k] = s[r][cg * W + k];
     gc[q] = v;
   }
 }
@@ -470,45 +474,6 @@ __global__ __launch_bounds__(256) void k_lu_diag(const FacDesc* __restrict__ d, 
   lds_to_tile<F>(X, linv);
 }
 
-// panel of tile column k: blockIdx.x < nr -> L_{k+1+x, k}, else U_{k, k+1+x'};
-// pending in-block updates fused in front of the product with the inverse.
-template <typename F>
-__global__ __launch_bounds__(256) void k_lu_panel(const FacDesc* __restrict__ d, int k0, int k) {
-  // XCD-aware order: the panel tiles of one subdomain (which share the
-  // diagonal tile's inverse and the pending-update operands) run on one XCD
-  const int gx = int(gridDim.x);
-  const int lin = xcd_block(int(blockIdx.y) * gx + int(blockIdx.x), gx * int(gridDim.y));
-  const int bx = lin % gx;
-  const FacDesc D = d[lin / gx];
-  const int nr = D.N - k - 1;
-  if (nr <= 0 || bx >= 2 * nr) return;
-  __shared__ F As[64][LDP], Bs[64][LDP];
-  const size_t N = D.N;
-  GLOBAL F* fac = gptr((F*)D.fac);
-  typename Mma<F>::acc_t acc[2][2];
-  size_t target;
-  if (bx < nr) {  // L_ik = (A_ik - sum_s L_is U_sk) inv(U_kk)
-    const size_t i = k + 1 + bx;
-    target = i * N + k;
-    acc_updated_tile<F>(acc, fac, target, i * N + k0, 1, size_t(k0) * N + k, N, k - k0);
-    acc_to_lds<F>(acc, As);
-    tile_to_lds<F>(fac + (size_t(k) * N + k) * TILE_ELEMS, Bs);
-  } else {  // U_kj = inv(L_kk) (A_kj - sum_s L_ks U_sj)
-    const size_t j = k + 1 + (bx - nr);
-    target = size_t(k) * N + j;
-    acc_updated_tile<F>(acc, fac, target, size_t(k) * N + k0, 1, size_t(k0) * N + j, N, k - k0);
-    acc_to_lds<F>(acc, Bs);
-    tile_to_lds<F>(fac + (N * N + k) * TILE_ELEMS, As);
-  }
-  __syncthreads();
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = typename Mma<F>::acc_t{0, 0, 0, 0};
-  tile_mma<F>(As, Bs, acc);
-  acc_store<F>(acc, fac + target * TILE_ELEMS);
-}
-
 // ---------------------------------------------------------------------------
 // trailing update past block column k0 .. k0+depth-1:
 // A_ij -= sum_{s<depth} L_{i,k0+s} U_{k0+s,j} for all i, j >= k0+depth.
@@ -562,6 +527,72 @@ __device__ __forceinline__ void fragc_mma(const FragC<F>& f, typename Mma<F>::ac
       for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = Mma<F>::op(f.a[rb][s], f.b[s][cb / W][cb % W], acc[rb][cb]);
 }
 
+// whole-tile accumulator of a wave (the trailing update's layout: block
+// (rb, cb) holds rows 16 rb + MFMA row and columns 16W (cb / W) + W lr + cb % W)
+template <typename F>
+__device__ __forceinline__ void acc4_load(const GLOBAL F* __restrict__ T, typename Mma<F>::acc_t (&acc)[4][4]) {
+  using C = typename Chunk<F>::type;
+  constexpr int W = Chunk<F>::W;
+  const int lane = threadIdx.x & 63, lr = lane & 15;
+  const GLOBAL C* Tc = (const GLOBAL C*)T;
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int c = 0; c < 4 / W; ++c) {
+        const C x = Tc[(16 * c + lr) * 64 + 16 * rb + Mma<F>::row(lane, v)];
+#pragma unroll
+        for (int w = 0; w < W; ++w) acc[rb][W * c + w][v] = x[w];
+      }
+}
+
+template <typename F>
+__device__ __forceinline__ void acc4_to_lds(typename Mma<F>::acc_t (&acc)[4][4], F (*Cs)[LDP], F scale) {
+  constexpr int W = Chunk<F>::W;
+  const int lane = threadIdx.x & 63, lr = lane & 15;
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Cs[16 * rb + Mma<F>::row(lane, v)][16 * W * (cb / W) + W * lr + cb % W] = scale * acc[rb][cb][v];
+}
+
+// acc += sum_{s<depth} L0(s) * U0(s) for a whole tile, L0(s) = L0 + s tiles,
+// U0(s) = U0 + s*ustride tiles (16-byte chunk pointers); the loads of the
+// next k-group are issued before the products of the current one (the last
+// pass reloads group ng-1, which is in bounds and unused)
+template <typename F>
+__device__ __forceinline__ void acc4_add_products(typename Mma<F>::acc_t (&acc)[4][4],
+                                                  const GLOBAL typename Chunk<F>::type* __restrict__ L0,
+                                                  const GLOBAL typename Chunk<F>::type* __restrict__ U0, size_t ustride,
+                                                  int depth) {
+  constexpr int W = Chunk<F>::W, TC = TILE_ELEMS / W, GPT = 16 / W;  // k-groups per tile
+  if (depth <= 0) return;
+  const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+  const int acb = lk * 64 + lr, bcb = lr * 64 + W * lk;
+  const int ng = GPT * depth;  // even: GPT is 4 or 8
+  FragC<F> f0, f1;
+  fragc_load<F>(f0, L0, U0, 0, acb, bcb);
+  for (int g = 0; g < ng; g += 2) {
+    {
+      const int h = g + 1, s = h / GPT;
+      fragc_load<F>(f1, L0 + size_t(s) * TC, U0 + size_t(s) * ustride * TC, h % GPT, acb, bcb);
+    }
+    __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of the products
+    fragc_mma<F>(f0, acc);
+    __builtin_amdgcn_sched_barrier(0);
+    {
+      const int h = min(g + 2, ng - 1), s = h / GPT;
+      fragc_load<F>(f0, L0 + size_t(s) * TC, U0 + size_t(s) * ustride * TC, h % GPT, acb, bcb);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    fragc_mma<F>(f1, acc);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
 template <typename F>
 __global__ __launch_bounds__(256, 2) void k_lu_trail(const FacDesc* __restrict__ d, int k0, int depth) {
   using C = typename Chunk<F>::type;
@@ -586,38 +617,14 @@ __global__ __launch_bounds__(256, 2) void k_lu_trail(const FacDesc* __restrict__
   const size_t i = k0 + depth + ti, j = k0 + depth + tj;
   GLOBAL C* fac = gptr((C*)D.fac);
   GLOBAL C* Ct = fac + (i * N + j) * TC;
-  const int lr = lane & 15, lk = lane >> 4;
-  const int acb = lk * 64 + lr, bcb = lr * 64 + W * lk;
+  const int lr = lane & 15;
   typename Mma<F>::acc_t acc[4][4];
 #pragma unroll
   for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = typename Mma<F>::acc_t{0, 0, 0, 0};
-  const GLOBAL C* L0 = fac + (i * N + k0) * TC;          // L_{i,k0+s} = L0 + s tiles
-  const GLOBAL C* U0 = fac + (size_t(k0) * N + j) * TC;  // U_{k0+s,j} = U0 + s*N tiles
-  constexpr int GPT = 16 / W;  // k-groups per tile
-  const int ng = GPT * depth;  // even: GPT is 4 or 8
-  FragC<F> f0, f1;
-  fragc_load<F>(f0, L0, U0, 0, acb, bcb);
-  // branch-free pipeline: the loads of the next k-group are issued before
-  // the products of the current one (the last pass reloads group ng-1,
-  // which is in bounds and unused)
-  for (int g = 0; g < ng; g += 2) {
-    {
-      const int h = g + 1, s = h / GPT;
-      fragc_load<F>(f1, L0 + size_t(s) * TC, U0 + size_t(s) * N * TC, h % GPT, acb, bcb);
-    }
-    __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of the products
-    fragc_mma<F>(f0, acc);
-    __builtin_amdgcn_sched_barrier(0);
-    {
-      const int h = min(g + 2, ng - 1), s = h / GPT;
-      fragc_load<F>(f0, L0 + size_t(s) * TC, U0 + size_t(s) * N * TC, h % GPT, acb, bcb);
-    }
-    __builtin_amdgcn_sched_barrier(0);
-    fragc_mma<F>(f1, acc);
-    __builtin_amdgcn_sched_barrier(0);
-  }
+  // L_{i,k0+s} = L0 + s tiles, U_{k0+s,j} = U0 + s*N tiles
+  acc4_add_products<F>(acc, fac + (i * N + k0) * TC, fac + (size_t(k0) * N + j) * TC, N, depth);
   // C -= acc: output (16 rb + row(lane, v), 16W c + W lr + w) is element w
   // of chunk (16 c + lr) * 64 + row of the tile
 #pragma unroll
@@ -634,6 +641,45 @@ __global__ __launch_bounds__(256, 2) void k_lu_trail(const FacDesc* __restrict__
       }
     __builtin_amdgcn_sched_barrier(0);
   }
+}
+
+// panel of tile column k: blockIdx.x < nr -> L_{k+1+x, k}, else U_{k, k+1+x'};
+// pending in-block updates fused in front of the product with the inverse.
+template <typename F>
+__global__ __launch_bounds__(256) void k_lu_panel(const FacDesc* __restrict__ d, int k0, int k) {
+  // XCD-aware order: the panel tiles of one subdomain (which share the
+  // diagonal tile's inverse and the pending-update operands) run on one XCD
+  const int gx = int(gridDim.x);
+  const int lin = xcd_block(int(blockIdx.y) * gx + int(blockIdx.x), gx * int(gridDim.y));
+  const int bx = lin % gx;
+  const FacDesc D = d[lin / gx];
+  const int nr = D.N - k - 1;
+  if (nr <= 0 || bx >= 2 * nr) return;
+  __shared__ F As[64][LDP], Bs[64][LDP];
+  const size_t N = D.N;
+  GLOBAL F* fac = gptr((F*)D.fac);
+  typename Mma<F>::acc_t acc[2][2];
+  size_t target;
+  if (bx < nr) {  // L_ik = (A_ik - sum_s L_is U_sk) inv(U_kk)
+    const size_t i = k + 1 + bx;
+    target = i * N + k;
+    acc_updated_tile<F>(acc, fac, target, i * N + k0, 1, size_t(k0) * N + k, N, k - k0);
+    acc_to_lds<F>(acc, As);
+    tile_to_lds<F>(fac + (size_t(k) * N + k) * TILE_ELEMS, Bs);
+  } else {  // U_kj = inv(L_kk) (A_kj - sum_s L_ks U_sj)
+    const size_t j = k + 1 + (bx - nr);
+    target = size_t(k) * N + j;
+    acc_updated_tile<F>(acc, fac, target, size_t(k) * N + k0, 1, size_t(k0) * N + j, N, k - k0);
+    acc_to_lds<F>(acc, Bs);
+    tile_to_lds<F>(fac + (N * N + k) * TILE_ELEMS, As);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = typename Mma<F>::acc_t{0, 0, 0, 0};
+  tile_mma<F>(As, Bs, acc);
+  acc_store<F>(acc, fac + target * TILE_ELEMS);
 }
 
 // ---------------------------------------------------------------------------
@@ -726,38 +772,6 @@ hipError_t launch_lu(const FacDesc* d, int nd, int maxN, int* err, hipStream_t s
 // ---------------------------------------------------------------------------
 constexpr int XINV_ROWS = 4;
 
-// whole-tile accumulator of a wave (the trailing update's layout: block
-// (rb, cb) holds rows 16 rb + MFMA row and columns 16W (cb / W) + W lr + cb % W)
-template <typename F>
-__device__ __forceinline__ void acc4_load(const GLOBAL F* __restrict__ T, typename Mma<F>::acc_t (&acc)[4][4]) {
-  using C = typename Chunk<F>::type;
-  constexpr int W = Chunk<F>::W;
-  const int lane = threadIdx.x & 63, lr = lane & 15;
-  const GLOBAL C* Tc = (const GLOBAL C*)T;
-#pragma unroll
-  for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-#pragma unroll
-      for (int c = 0; c < 4 / W; ++c) {
-        const C x = Tc[(16 * c + lr) * 64 + 16 * rb + Mma<F>::row(lane, v)];
-#pragma unroll
-        for (int w = 0; w < W; ++w) acc[rb][W * c + w][v] = x[w];
-      }
-}
-
-template <typename F>
-__device__ __forceinline__ void acc4_to_lds(typename Mma<F>::acc_t (&acc)[4][4], F (*Cs)[LDP], F scale) {
-  constexpr int W = Chunk<F>::W;
-  const int lane = threadIdx.x & 63, lr = lane & 15;
-#pragma unroll
-  for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-    for (int cb = 0; cb < 4; ++cb)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) Cs[16 * rb + Mma<F>::row(lane, v)][16 * W * (cb / W) + W * lr + cb % W] = scale * acc[rb][cb][v];
-}
-
 // acc += A * Bs for a whole tile: A in global memory (16-byte chunks), Bs in LDS
 template <typename F>
 __device__ __forceinline__ void acc4_add_product_lds(typename Mma<F>::acc_t (&acc)[4][4], const GLOBAL F* __restrict__ A,
@@ -794,7 +808,7 @@ __device__ __forceinline__ void acc4_add_product_lds(typename Mma<F>::acc_t (&ac
 template <typename F>
 __global__ __launch_bounds__(256, 2) void k_xinv(const FacDesc* __restrict__ d, int blk, int fwd) {
   using C = typename Chunk<F>::type;
-  constexpr int W = Chunk<F>::W, TC = TILE_ELEMS / W, GPT = 16 / W;
+  constexpr int W = Chunk<F>::W, TC = TILE_ELEMS / W;
   // XCD-aware order: the tile columns of one subdomain (which share its
   // factor's tile rows) run on one XCD
   const int gx = int(gridDim.x);
@@ -829,7 +843,7 @@ __global__ __launch_bounds__(256, 2) void k_xinv(const FacDesc* __restrict__ d, 
   GLOBAL F* X = gptr((F*)D.X);
   // wave-uniform: keeps the tile base addresses in scalar registers
   const int t = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const int lr = lane & 15, lk = lane >> 4;
+  const int lr = lane & 15;
   const bool mine = t < nr;  // this wave holds row r(t) of the block
   const int r = r0 + dir * t;
   typename Mma<F>::acc_t acc[4][4];
@@ -858,30 +872,8 @@ __global__ __launch_bounds__(256, 2) void k_xinv(const FacDesc* __restrict__ d, 
     }
     m1 = r0 + 1, depth = N - 1 - r0;  // final rows r0 + 1 .. N - 1
   }
-  if (mine && depth > 0) {
-    const GLOBAL C* A0 = (const GLOBAL C*)fac + (size_t(r) * n + m1) * TC;  // L_{r, m1 + s} / U_{r, m1 + s}
-    const GLOBAL C* B0 = (const GLOBAL C*)X + (col + m1) * TC;              // Y_{m1 + s, j} / X_{m1 + s, j}
-    const int acb = lk * 64 + lr, bcb = lr * 64 + W * lk;
-    const int ng = GPT * depth;  // even
-    FragC<F> f0, f1;
-    fragc_load<F>(f0, A0, B0, 0, acb, bcb);
-    for (int g = 0; g < ng; g += 2) {
-      {
-        const int h = g + 1, s = h / GPT;
-        fragc_load<F>(f1, A0 + size_t(s) * TC, B0 + size_t(s) * TC, h % GPT, acb, bcb);
-      }
-      __builtin_amdgcn_sched_barrier(0);
-      fragc_mma<F>(f0, acc);
-      __builtin_amdgcn_sched_barrier(0);
-      {
-        const int h = min(g + 2, ng - 1), s = h / GPT;
-        fragc_load<F>(f0, A0 + size_t(s) * TC, B0 + size_t(s) * TC, h % GPT, acb, bcb);
-      }
-      __builtin_amdgcn_sched_barrier(0);
-      fragc_mma<F>(f1, acc);
-      __builtin_amdgcn_sched_barrier(0);
-    }
-  }
+  // L_{r, m1 + s} / U_{r, m1 + s} times Y_{m1 + s, j} / X_{m1 + s, j}
+  if (mine) acc4_add_products<F>(acc, (const GLOBAL C*)fac + (size_t(r) * n + m1) * TC, (const GLOBAL C*)X + (col + m1) * TC, 1, depth);
   // phase 2: the block row by row
   for (int q = 0; q < nr; ++q) {
     const int rq = r0 + dir * q;

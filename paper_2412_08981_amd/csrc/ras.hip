@@ -774,19 +774,33 @@ __global__ __launch_bounds__(256, 2) void k_xapply(RasLaunch P) {
 }
 
 // z_a = Cv_a + Co_a + sum_{b < a} P_{b,a}, scattered to the owned rows
-// (tasks: the owned parts' codes; Cv_a only where there are overlap rows)
+// (one wave per task, four tasks per work-group; the owned parts' codes
+// only; Cv_a only where there are overlap rows).  The partials are loaded
+// in batches of XRED_BATCH before they are added, in the order above.
+constexpr int XRED_BATCH = 16;
+
 template <typename F, typename V>
-__global__ __launch_bounds__(64) void k_xreduce(RasLaunch P) {
-  const int code = gptr(P.tasks)[blockIdx.x];
+__global__ __launch_bounds__(256) void k_xreduce(RasLaunch P) {
+  const int task = 4 * int(blockIdx.x) + int(threadIdx.x >> 6);
+  if (task >= P.ntasks) return;
+  const int code = gptr(P.tasks)[task];
   if (!((code >> 15) & 1)) return;
   const int sub = code >> 16, a = code & 0x7fff;
   const SubDesc S = P.subs[sub];
   if (!slot_active(S.st, WHEN_RUNNING)) return;
-  const int lane = threadIdx.x, No = (S.no + 63) / 64;
+  const int lane = threadIdx.x & 63, No = (S.no + 63) / 64;
   const GLOBAL F* part = gptr((const F*)S.part);
+  const GLOBAL F* pp = part + 128 * No + lane;
   F sum = S.nv > 0 ? part[64 * a + lane] : F(0);
   sum += part[64 * (No + a) + lane];
-  for (int b = 0; b < a; ++b) sum += part[128 * No + 64 * xpair(b, a, No) + lane];
+  for (int b0 = 0; b0 < a; b0 += XRED_BATCH) {
+    F v[XRED_BATCH];
+#pragma unroll
+    for (int u = 0; u < XRED_BATCH; ++u) v[u] = b0 + u < a ? pp[64 * xpair(b0 + u, a, No)] : F(0);
+#pragma unroll
+    for (int u = 0; u < XRED_BATCH; ++u)
+      if (b0 + u < a) sum += v[u];
+  }
   const int oc = 64 * a + lane;  // owned row index; local row nv + oc
   if (oc < S.no) {
     const int g = gptr(S.gidx)[S.nv + oc];
@@ -807,7 +821,7 @@ static hipError_t launch_xapply(const RasLaunch& p, hipStream_t s) {
     hipLaunchKernelGGL((k_xapply<F, V, true>), dim3(p.ntasks), dim3(256), ylds > red ? ylds : red, s, p);
   else
     hipLaunchKernelGGL((k_xapply<F, V, false>), dim3(p.ntasks), dim3(256), red, s, p);
-  hipLaunchKernelGGL((k_xreduce<F, V>), dim3(p.ntasks), dim3(64), 0, s, p);
+  hipLaunchKernelGGL((k_xreduce<F, V>), dim3((p.ntasks + 3) / 4), dim3(256), 0, s, p);
   return hipGetLastError();
 }
 
