@@ -569,12 +569,17 @@ nnms_status nnms_solve(nnms_system* s, const double* b, double* x, const nnms_so
  *                     when requests join or leave).  A system must not be
  *                     stepped by two batches at the same time.
  * nnms_batch_start    begin solving in `slot` with right-hand side b
- *                     (device pointer, nv_0 doubles; copied).
+ *                     (device pointer, nv_0 doubles; copied after the work
+ *                     enqueued so far on the stream given to
+ *                     nnms_batch_create).
  * nnms_batch_step     run up to `iterations` Arnoldi steps on every active
  *                     slot (replayed from a captured HIP graph unless
  *                     NNMS_NO_GRAPH); *active_host receives the number of
  *                     slots still iterating.
- * nnms_batch_result   copy slot's solution to x (device pointer) and info.
+ * nnms_batch_result   copy slot's solution to x (device pointer) and info;
+ *                     the copy follows the work enqueued so far on the stream
+ *                     given to nnms_batch_create, and that stream's later
+ *                     work follows the copy.
  * nnms_batch_destroy  wait for the batch's own stream (not the device) and
  *                     drop it; its stream, pinned word and small device
  *                     buffers are kept by the library for later batches

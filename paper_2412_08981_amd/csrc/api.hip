@@ -1852,6 +1852,7 @@ extern "C" nnms_status nnms_solve_opts_default(nnms_solve_opts* o) {
 struct nnms_batch {
   std::unique_ptr<Plan> plan;
   nnms_solve_opts opts{};
+  hipStream_t user = nullptr;  // the caller's stream: start and result are ordered with its work
 };
 
 static void run_plan(Plan& P, int max_steps) {
@@ -1960,7 +1961,8 @@ extern "C" nnms_status nnms_batch_create(nnms_system* const* systems, int32_t nb
   check_restart(sys, bt->opts);
   bt->plan = make_plan_any(sys, true);
   bt->plan->use_graph = !(bt->opts.flags & NNMS_NO_GRAPH);
-  join_in((hipStream_t)stream, bt->plan->stream);
+  bt->user = (hipStream_t)stream;
+  join_in(bt->user, bt->plan->stream);
   // slots keep their systems' solve state: a freshly assembled system is
   // idle, a system still iterating in an earlier batch goes on here
   HIP_CHECK(hipStreamSynchronize(bt->plan->stream));
@@ -1972,6 +1974,7 @@ extern "C" nnms_status nnms_batch_create(nnms_system* const* systems, int32_t nb
 extern "C" nnms_status nnms_batch_start(nnms_batch* bt, int32_t slot, const double* b_dev) {
   ABI_BEGIN
   if (!bt || !b_dev || slot < 0 || slot >= bt->plan->nd) throw Error(NNMS_ERR_INVALID_ARG, "bad arguments");
+  join_in(bt->user, bt->plan->stream);  // b as the caller's stream has it now
   plan_start_slot(*bt->plan, slot, b_dev, bt->opts);
   return NNMS_OK;
   ABI_END
@@ -1995,9 +1998,14 @@ extern "C" nnms_status nnms_batch_result(nnms_batch* bt, int32_t slot, double* x
   ABI_BEGIN
   if (!bt || slot < 0 || slot >= bt->plan->nd) throw Error(NNMS_ERR_INVALID_ARG, "bad arguments");
   nnms_system* s = bt->plan->sys[slot];
-  if (x_dev)
+  if (x_dev) {
+    // after the caller's stream has finished its earlier work on x, and
+    // before its later work
+    join_in(bt->user, bt->plan->stream);
     HIP_CHECK(hipMemcpyAsync(x_dev, s->x, s->h->host.lev[0].nv * sizeof(double), hipMemcpyDeviceToDevice,
                              bt->plan->stream));
+    join_in(bt->plan->stream, bt->user);
+  }
   nnms_solve_info in = read_info(s, bt->plan->stream);
   if (info) *info = in;
   return NNMS_OK;

@@ -88,3 +88,41 @@ def test_slots_join_a_running_batch():
         torch.cuda.synchronize()
         assert info.status == 0 and info.iterations == ref[k][1].iterations
         assert np.array_equal(x.cpu().numpy(), ref[k][0])
+
+
+def test_batch_start_and_result_follow_the_callers_stream():
+    """nnms_batch_start reads b, and nnms_batch_result writes x, after the
+    work already enqueued on the stream the batch was created with (here a
+    long product and then the writes of b and x on a torch stream), and that
+    stream's later work sees x."""
+    import torch
+
+    nnms = _nnms()
+    pb = _problems("fp64")[1]
+    ms = [nnms.Mesh.from_workload(m) for m in pb.meshes]
+    h = nnms.Hierarchy(ms, pb.nparts)
+    s = nnms.System(h, pb.kappa)
+    rhs = s.rhs()
+    ref = s.solve(rhs)
+    user = torch.cuda.Stream()
+    big = torch.randn(4096, 4096, device="cuda", dtype=torch.float64)
+    torch.cuda.synchronize()
+    bt = nnms.Batch([s], stream=user)
+    with torch.cuda.stream(user):
+        t = big @ big  # keeps the caller's stream busy
+        b = torch.zeros(s.n[0], dtype=torch.float64, device="cuda")
+        b.copy_(torch.from_numpy(rhs).to("cuda", non_blocking=False))
+    bt.start(0, b.data_ptr())
+    while bt.step(1) > 0:
+        pass
+    with torch.cuda.stream(user):
+        t = t @ big
+        x = torch.full((s.n[0],), float("nan"), dtype=torch.float64, device="cuda")
+    info = bt.result(0, x.data_ptr())
+    with torch.cuda.stream(user):
+        y = x * 1.0  # later work on the caller's stream
+    user.synchronize()
+    bt.destroy()
+    assert info.status == 0 and info.iterations == ref[1].iterations
+    assert np.array_equal(y.cpu().numpy(), ref[0])
+    del t
