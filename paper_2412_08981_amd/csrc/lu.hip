@@ -643,10 +643,99 @@ __global__ __launch_bounds__(256, 2) void k_lu_trail(const FacDesc* __restrict__
   }
 }
 
+// operand halves of a quadrant k-group (see Frag): 16-byte A chunks, B pairs
+template <typename F>
+struct FragA {
+  typename Chunk<F>::type a[4 / Chunk<F>::W][2];
+};
+template <typename F>
+struct FragB {
+  typename Pair<F>::type b[4 / Chunk<F>::W][Chunk<F>::W];
+};
+
+template <typename F>
+__device__ __forceinline__ void fraga_load(FragA<F>& f, const GLOBAL F* __restrict__ At, int g) {
+  using C = typename Chunk<F>::type;
+  constexpr int W = Chunk<F>::W, NS = 4 / W;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int R0 = (wave >> 1) * 32, lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int u = 0; u < NS; ++u) {
+    const GLOBAL C* la = (const GLOBAL C*)At + (16 / W * g + 4 * u + lk) * 64 + R0 + lr;
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) f.a[u][rb] = la[16 * rb];
+  }
+}
+
+template <typename F>
+__device__ __forceinline__ void fragb_load(FragB<F>& f, const GLOBAL F* __restrict__ Bt, int g) {
+  using P = typename Pair<F>::type;
+  constexpr int W = Chunk<F>::W, NS = 4 / W;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int C0 = (wave & 1) * 32, lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int u = 0; u < NS; ++u) {
+    const GLOBAL F* ub = Bt + tile_off<F>(16 * g + 4 * W * u + W * lk, C0 + 2 * lr);
+#pragma unroll
+    for (int s = 0; s < W; ++s) f.b[u][s] = *(const GLOBAL P*)(ub + W * s);
+  }
+}
+
+// acc += As * B (As in LDS, B a tile in global memory) or acc += A * Bs (A
+// in global memory, Bs in LDS): one tile product per quadrant, the global
+// operand's next k-group loaded before the current one's products
+template <typename F, bool LDS_A>
+__device__ __forceinline__ void acc_add_product_half_lds(typename Mma<F>::acc_t (&acc)[2][2], F (*S)[LDP],
+                                                         const GLOBAL F* __restrict__ G) {
+  constexpr int W = Chunk<F>::W, NS = 4 / W;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int R0 = (wave >> 1) * 32, C0 = (wave & 1) * 32, lr = lane & 15, lk = lane >> 4;
+  FragA<F> a0, a1;
+  FragB<F> b0, b1;
+  if (LDS_A)
+    fragb_load<F>(b0, G, 0);
+  else
+    fraga_load<F>(a0, G, 0);
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    FragA<F>& ac = (g & 1) ? a1 : a0;
+    FragA<F>& an = (g & 1) ? a0 : a1;
+    FragB<F>& bc = (g & 1) ? b1 : b0;
+    FragB<F>& bn = (g & 1) ? b0 : b1;
+    if (g + 1 < 4) {
+      if (LDS_A)
+        fragb_load<F>(bn, G, g + 1);
+      else
+        fraga_load<F>(an, G, g + 1);
+    }
+#pragma unroll
+    for (int u = 0; u < NS; ++u)
+#pragma unroll
+      for (int s = 0; s < W; ++s) {
+        const int k = 16 * g + 4 * W * u + W * lk + s;
+        F av[2], bv[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          av[q] = LDS_A ? S[R0 + 16 * q + lr][k] : ac.a[u][q][s];
+          bv[q] = LDS_A ? bc.b[u][s][q] : S[k][C0 + 2 * lr + q];
+        }
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+          for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = Mma<F>::op(av[rb], bv[cb], acc[rb][cb]);
+      }
+  }
+}
+
 // panel of tile column k: blockIdx.x < nr -> L_{k+1+x, k}, else U_{k, k+1+x'};
 // pending in-block updates fused in front of the product with the inverse.
+// FP64: only the updated tile goes through LDS and the inverse (the same
+// tile for the whole panel, so mostly an L2 hit) is read from global
+// memory, which leaves room for four work-groups per CU; FP32: both tiles
+// in LDS (four work-groups per CU already fit).
 template <typename F>
 __global__ __launch_bounds__(256) void k_lu_panel(const FacDesc* __restrict__ d, int k0, int k) {
+  constexpr bool ONE_TILE = sizeof(F) == 8;
   // XCD-aware order: the panel tiles of one subdomain (which share the
   // diagonal tile's inverse and the pending-update operands) run on one XCD
   const int gx = int(gridDim.x);
@@ -655,30 +744,41 @@ __global__ __launch_bounds__(256) void k_lu_panel(const FacDesc* __restrict__ d,
   const FacDesc D = d[lin / gx];
   const int nr = D.N - k - 1;
   if (nr <= 0 || bx >= 2 * nr) return;
-  __shared__ F As[64][LDP], Bs[64][LDP];
+  __shared__ F Ts[64][LDP];
+  __shared__ F Is[ONE_TILE ? 1 : 64][LDP];  // the inverse (FP32)
   const size_t N = D.N;
   GLOBAL F* fac = gptr((F*)D.fac);
   typename Mma<F>::acc_t acc[2][2];
+  const bool lower = bx < nr;
   size_t target;
-  if (bx < nr) {  // L_ik = (A_ik - sum_s L_is U_sk) inv(U_kk)
+  if (lower) {  // L_ik = (A_ik - sum_s L_is U_sk) inv(U_kk)
     const size_t i = k + 1 + bx;
     target = i * N + k;
     acc_updated_tile<F>(acc, fac, target, i * N + k0, 1, size_t(k0) * N + k, N, k - k0);
-    acc_to_lds<F>(acc, As);
-    tile_to_lds<F>(fac + (size_t(k) * N + k) * TILE_ELEMS, Bs);
   } else {  // U_kj = inv(L_kk) (A_kj - sum_s L_ks U_sj)
     const size_t j = k + 1 + (bx - nr);
     target = size_t(k) * N + j;
     acc_updated_tile<F>(acc, fac, target, size_t(k) * N + k0, 1, size_t(k0) * N + j, N, k - k0);
-    acc_to_lds<F>(acc, Bs);
-    tile_to_lds<F>(fac + (N * N + k) * TILE_ELEMS, As);
   }
+  acc_to_lds<F>(acc, Ts);
+  const GLOBAL F* inv = fac + (lower ? size_t(k) * N + k : N * N + k) * TILE_ELEMS;  // inv(U_kk) / inv(L_kk)
+  if (!ONE_TILE) tile_to_lds<F>(inv, Is);
   __syncthreads();
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = typename Mma<F>::acc_t{0, 0, 0, 0};
-  tile_mma<F>(As, Bs, acc);
+  if (ONE_TILE) {
+    if (lower)
+      acc_add_product_half_lds<F, true>(acc, Ts, inv);  // A_ik inv(U_kk)
+    else
+      acc_add_product_half_lds<F, false>(acc, Ts, inv);  // inv(L_kk) A_kj
+  } else {
+    if (lower)
+      tile_mma<F>(Ts, Is, acc);
+    else
+      tile_mma<F>(Is, Ts, acc);
+  }
   acc_store<F>(acc, fac + target * TILE_ELEMS);
 }
 
