@@ -828,6 +828,17 @@ __global__ __launch_bounds__(256) void k_lu_pairs(const FacDesc* __restrict__ d,
   acc_store<F>(acc, fac + out * TILE_ELEMS);
 }
 
+// LDS reserved, unused, by an FP32 launch of the trailing update and of the
+// inverse panels so that one work-group runs per CU: their waves share
+// operands through the CU's L1, and further resident work-groups evict
+// them (fine-level FP32 LU 11.4 ms with three per CU, 10.0 with two, 9.8
+// with one; in FP64 two per CU stay the faster).  `static_lds`: what the
+// kernel declares itself.
+template <typename F>
+constexpr size_t one_per_cu_lds(size_t static_lds) {
+  return sizeof(F) == 4 ? size_t(96 * 1024) - static_lds : 0;
+}
+
 template <typename F>
 hipError_t launch_lu(const FacDesc* d, int nd, int maxN, int* err, hipStream_t s) {
   if (nd <= 0) return hipSuccess;
@@ -839,7 +850,8 @@ hipError_t launch_lu(const FacDesc* d, int nd, int maxN, int* err, hipStream_t s
       if (nr > 0) hipLaunchKernelGGL((k_lu_panel<F>), dim3(2 * nr, nd), dim3(256), 0, s, d, k0, k);
     }
     const int nt = maxN - k0 - depth, ns = (nt + 1) / 2;
-    if (nt > 0) hipLaunchKernelGGL((k_lu_trail<F>), dim3(ns * ns, nd), dim3(256), 0, s, d, k0, depth);
+    if (nt > 0)
+      hipLaunchKernelGGL((k_lu_trail<F>), dim3(ns * ns, nd), dim3(256), one_per_cu_lds<F>(0), s, d, k0, depth);
   }
   const int npmax = maxN / 2;
   if (npmax > 0) hipLaunchKernelGGL((k_lu_pairs<F>), dim3(2 * npmax, nd), dim3(256), 0, s, d, npmax);
@@ -1002,8 +1014,9 @@ template <typename F>
 hipError_t launch_xinv(const FacDesc* d, int nd, int maxNo, int fsteps, int bsteps, hipStream_t s) {
   if (nd <= 0 || maxNo <= 0) return hipSuccess;
   constexpr int R = XINV_ROWS;
-  for (int k = 0; k < (fsteps + R - 1) / R; ++k) hipLaunchKernelGGL((k_xinv<F>), dim3(maxNo, nd), dim3(256), 0, s, d, k, 1);
-  for (int k = 0; k < (bsteps + R - 1) / R; ++k) hipLaunchKernelGGL((k_xinv<F>), dim3(maxNo, nd), dim3(256), 0, s, d, k, 0);
+  const size_t lds = one_per_cu_lds<F>(2 * 64 * LDP * sizeof(F));  // beside its two LDS tiles
+  for (int k = 0; k < (fsteps + R - 1) / R; ++k) hipLaunchKernelGGL((k_xinv<F>), dim3(maxNo, nd), dim3(256), lds, s, d, k, 1);
+  for (int k = 0; k < (bsteps + R - 1) / R; ++k) hipLaunchKernelGGL((k_xinv<F>), dim3(maxNo, nd), dim3(256), lds, s, d, k, 0);
   return hipGetLastError();
 }
 
