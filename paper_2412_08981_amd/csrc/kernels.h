@@ -42,8 +42,9 @@ hipError_t launch_extract(const FacDesc* d, int nd, int maxn, hipStream_t s);
 template <typename F>
 hipError_t launch_lu(const FacDesc* d, int nd, int maxN, int* err, hipStream_t s);
 // inverse panels X_p = J_p^{-1} E_o of every subdomain with d.X set, from its
-// LU factors: fsteps block forward-substitution launches, then bsteps block
-// back-substitution launches (X zero-filled before)
+// LU factors: block forward substitution over fsteps tile rows, then block
+// back substitution over bsteps tile rows, four tile rows per launch (X
+// zero-filled before)
 template <typename F>
 hipError_t launch_xinv(const FacDesc* d, int nd, int maxNo, int fsteps, int bsteps, hipStream_t s);
 // packed symmetric form d.Xs of every subdomain's panels d.X (maxPacked =
