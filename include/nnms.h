@@ -491,7 +491,15 @@ nnms_status nnms_time_kernel(nnms_system* s, int32_t kind, int32_t level, int32_
  *                  slice, 1 = the slice's entries split over the four waves
  *                  of a work-group and the four partial sums of a row added
  *                  in a fixed order
- *   pt_lanes[l]    the same choice for P_l^T (4..64, 0 or 1)
+ *   pt_lanes[l]    the same choice for P_l^T (4..64, 0 or 1), or 2: P_l^T in
+ *                  column-sorted slices (64 rows per slice, the slice's
+ *                  entries stored in fine-column order so that the gathers
+ *                  of a wave read runs of consecutive fine entries; the
+ *                  products regrouped by row in LDS and each row summed by
+ *                  four lanes in a fixed order); accepted where every slice
+ *                  holds at most 4096 entries spanning fewer than 2^19
+ *                  columns, else nnms_hierarchy_set_tuning returns
+ *                  NNMS_ERR_INVALID_ARG
  *   ras_groups[l]  work-groups of the persistent triangular-solve kernel on
  *                  level l (0 = 4 per compute unit)
  *   ras_blocks[l]  64-row blocks per work item of that kernel (1, 2 or 4);

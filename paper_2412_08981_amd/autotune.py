@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.path.join(HERE, "tuning.json")
 # Revision of the tuned kernels: launch shapes measured on an older revision
 # are not reused.  Raised whenever a tuned kernel changes its resource use.
-KERNEL_REV = 5
+KERNEL_REV = 6
 
 
 def _device_name() -> str:

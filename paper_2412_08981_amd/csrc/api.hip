@@ -153,6 +153,11 @@ struct DevLevel {
   int32_t *pts_off = nullptr, *pts_col = nullptr;  // P^T in sliced ELL layout
   double* pts_w64 = nullptr;
   float* pts_w32 = nullptr;
+  // P^T in column-sorted slices (null where a slice does not fit the keys)
+  int32_t *ptc_key = nullptr, *ptc_base = nullptr;
+  double* ptc_w64 = nullptr;
+  float* ptc_w32 = nullptr;
+  int32_t ptc_cap = 0;
   int32_t *pn_off = nullptr, *pn_col = nullptr;  // MLS: -P in sliced ELL layout
   double* pn_w64 = nullptr;
   float* pn_w32 = nullptr;
@@ -237,10 +242,12 @@ static int ras_grid_default() {
 // blocks of one SpMV launch: G lanes per CSR row, or the sliced ELL layout:
 // G = 0 four 64-row slices per block, G = 1 one slice per block (its steps
 // split over the four waves)
+// G = 2 (P^T only) the column-sorted slices, one slice per block
 static bool is_sell(int G) { return G == 0 || G == 1; }
+constexpr int SPMV_CSORT = 2;
 static int spmv_blocks(int64_t n, int G) {
   if (G == 0) return int((n + 255) / 256);
-  if (G == 1) return int((n + 63) / 64);
+  if (G == 1 || G == SPMV_CSORT) return int((n + 63) / 64);
   return int((n + (256 / G) - 1) / (256 / G));
 }
 static int vec_blocks(int64_t n) { return int((n + VBLK - 1) / VBLK); }
@@ -254,6 +261,7 @@ static int vec_blocks(int64_t n) { return int((n + VBLK - 1) / VBLK); }
 struct SpmvGroup {
   SpmvDesc* d = nullptr;
   int nd = 0, blocks = 0, g = 16;
+  int cap = 0;  // column-sorted slices: most entries of one slice
 };
 
 // items: (lanes per row, descriptor); blk0 is counted inside each group
@@ -265,16 +273,17 @@ static std::vector<SpmvGroup> spmv_groups(Arena& mem, const std::vector<std::pai
   std::vector<SpmvGroup> out;
   for (int g : gs) {
     std::vector<SpmvDesc> v;
-    int b = 0;
+    int b = 0, cap = 0;
     for (const auto& it : items)
       if (it.first == g) {
         SpmvDesc d = it.second;
         d.blk0 = b;
         b += spmv_blocks(d.n, g);
+        cap = std::max(cap, d.cap);
         v.push_back(d);
       }
     SpmvGroup G;
-    G.d = mem.upload(v, s), G.nd = int(v.size()), G.blocks = b, G.g = g;
+    G.d = mem.upload(v, s), G.nd = int(v.size()), G.blocks = b, G.g = g, G.cap = cap;
     out.push_back(G);
   }
   return out;
@@ -283,8 +292,9 @@ static std::vector<SpmvGroup> spmv_groups(Arena& mem, const std::vector<std::pai
 template <typename T>
 static hipError_t launch_spmv_groups(const std::vector<SpmvGroup>& gs, hipStream_t s) {
   for (const SpmvGroup& G : gs) {
-    const hipError_t e = is_sell(G.g) ? launch_sell<T>(G.d, G.nd, G.blocks, G.g, s)
-                                      : launch_spmv<T>(G.d, G.nd, G.blocks, G.g, s);
+    const hipError_t e = G.g == SPMV_CSORT ? launch_csort<T>(G.d, G.nd, G.blocks, G.cap, s)
+                         : is_sell(G.g)      ? launch_sell<T>(G.d, G.nd, G.blocks, G.g, s)
+                                             : launch_spmv<T>(G.d, G.nd, G.blocks, G.g, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -406,15 +416,19 @@ struct Plan {
   int* d_active = nullptr;
   int* h_active = nullptr;
   hipStream_t stream = nullptr;
-  hipGraphExec_t graph = nullptr;
+  // instantiated graphs of K consecutive Arnoldi steps, by K
+  std::map<int, hipGraphExec_t> graphs;
   bool use_graph = true;
+  // Arnoldi steps the plan's last solve took: the next solve replays that
+  // many steps as one graph before it reads the active count
+  int expect = 0;
   std::vector<int32_t*> counters;
   Plan() = default;
   ~Plan() {
     // this plan's own work is done before its graph and descriptors go (a
     // stream synchronisation: other streams are not waited for)
     if (stream) (void)hipStreamSynchronize(stream);
-    if (graph) (void)hipGraphExecDestroy(graph);
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
     std::lock_guard<std::mutex> g(plan_pools().mu);
     if (h_active) plan_pools().words.push_back(h_active);
     if (stream) plan_pools().streams.push_back(stream);
@@ -677,7 +691,10 @@ static void build_plan(Plan& P, const std::vector<nnms_system*>& sys, bool with_
       res.emplace_back(ga, d);
       SpmvDesc e{};
       const int gp = x->h->tune.pt_lanes[l];
-      if (is_sell(gp)) {
+      if (gp == SPMV_CSORT) {
+        e.rp = dl.pt_rp, e.col = dl.ptc_key, e.base = dl.ptc_base, e.cap = dl.ptc_cap;
+        e.val = std::is_same<T, float>::value ? (const void*)dl.ptc_w32 : (const void*)dl.ptc_w64;
+      } else if (is_sell(gp)) {
         e.rp = dl.pts_off, e.col = dl.pts_col;
         e.val = std::is_same<T, float>::value ? (const void*)dl.pts_w32 : (const void*)dl.pts_w64;
       } else {
@@ -802,36 +819,46 @@ static void enqueue_step(Plan& P, hipStream_t s) {
   HIP_CHECK(launch_krylov_cycle(P.kd, P.nd, s));
 }
 
-static void plan_step(Plan& P) {
+// K consecutive Arnoldi steps: one graph replay (captured on first use),
+// or the launches themselves with NNMS_NO_GRAPH.  Steps after a slot has
+// converged leave it unchanged (every kernel skips finished slots).
+static void plan_steps(Plan& P, int K) {
   hipStream_t s = P.stream;
-  if (P.use_graph) {
-    if (!P.graph) {
-      hipGraph_t g;
-      HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      try {
-        if (P.prec == NNMS_MIXED)
-          enqueue_step<float>(P, s);
-        else
-          enqueue_step<double>(P, s);
-      } catch (...) {
-        hipGraph_t junk;
-        (void)hipStreamEndCapture(s, &junk);
-        if (junk) (void)hipGraphDestroy(junk);
-        throw;
-      }
-      HIP_CHECK(hipStreamEndCapture(s, &g));
-      hipError_t e = hipGraphInstantiate(&P.graph, g, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(g);
-      HIP_CHECK(e);
+  auto enqueue = [&]() {
+    for (int k = 0; k < K; ++k) {
+      if (P.prec == NNMS_MIXED)
+        enqueue_step<float>(P, s);
+      else
+        enqueue_step<double>(P, s);
     }
-    HIP_CHECK(hipGraphLaunch(P.graph, s));
-  } else {
-    if (P.prec == NNMS_MIXED)
-      enqueue_step<float>(P, s);
-    else
-      enqueue_step<double>(P, s);
+  };
+  if (!P.use_graph) {
+    enqueue();
+    return;
   }
+  auto it = P.graphs.find(K);
+  if (it == P.graphs.end()) {
+    hipGraph_t g;
+    HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    try {
+      enqueue();
+    } catch (...) {
+      hipGraph_t junk;
+      (void)hipStreamEndCapture(s, &junk);
+      if (junk) (void)hipGraphDestroy(junk);
+      throw;
+    }
+    HIP_CHECK(hipStreamEndCapture(s, &g));
+    hipGraphExec_t ex = nullptr;
+    hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIP_CHECK(e);
+    it = P.graphs.emplace(K, ex).first;
+  }
+  HIP_CHECK(hipGraphLaunch(it->second, s));
 }
+
+static void plan_step(Plan& P) { plan_steps(P, 1); }
 
 static int plan_active(Plan& P) {
   HIP_CHECK(launch_count_active(P.kd, P.nd, P.d_active, P.stream));
@@ -1040,6 +1067,20 @@ extern "C" nnms_status nnms_hierarchy_setup(const nnms_mesh* const* levels, int3
       d.pts_col = A.upload(hl.pts_col, s);
       d.pts_w64 = A.upload(hl.pts_w, s);
       d.pts_w32 = A.upload(convert<double, float>(hl.pts_w), s);
+      {
+        std::vector<int32_t> key, base, src;
+        if (build_csort_layout(hl.pt_rp, hl.pt_col, int64_t(hl.pt_rp.size()) - 1, key, base, src, d.ptc_cap) &&
+            d.ptc_cap > 0) {
+          std::vector<double> w(src.size());
+          for (size_t e = 0; e < src.size(); ++e) w[e] = hl.pt_w[src[e]];
+          d.ptc_key = A.upload(key, s);
+          d.ptc_base = A.upload(base, s);
+          d.ptc_w64 = A.upload(w, s);
+          d.ptc_w32 = A.upload(convert<double, float>(w), s);
+        } else {
+          d.ptc_cap = 0;
+        }
+      }
       d.transfer = hl.transfer;
       if (hl.transfer == NNMS_TRANSFER_MLS) {
         d.pn_off = A.upload(hl.pn_off, s);
@@ -1855,10 +1896,19 @@ struct nnms_batch {
   hipStream_t user = nullptr;  // the caller's stream: start and result are ordered with its work
 };
 
+// Steps until no slot is running: first as many as the plan's last solve
+// took (at most MAX_GRAPH_STEPS), in one graph and with one host read of the
+// active count (parametric solves of one system take about the same number),
+// then one at a time.
+constexpr int MAX_GRAPH_STEPS = 64;
 static void run_plan(Plan& P, int max_steps) {
-  for (int k = 0; k < max_steps; ++k) {
-    plan_step(P);
+  int k = 0;
+  int K = std::max(1, std::min({P.expect, max_steps, MAX_GRAPH_STEPS}));
+  while (k < max_steps) {
+    plan_steps(P, K);
+    k += K;
     if (plan_active(P) == 0) return;
+    K = 1;
   }
 }
 
@@ -1912,9 +1962,12 @@ static nnms_status solve_many(nnms_system* const* systems, int32_t nb, const dou
       plan_start_slot(*P, k, s->bw, o);
     }
   }
-  if (plan_active(*P) > 0) run_plan(*P, o.max_it + 1);
+  // with an expected step count the first read is skipped: steps leave
+  // slots that are not running (a zero right-hand side) unchanged
+  if (P->expect > 0 || plan_active(*P) > 0) run_plan(*P, o.max_it + 1);
   check_counters(*P, P->stream);
   nnms_status worst = NNMS_OK;
+  int most_its = 0;
   for (int k = 0; k < nb; ++k) {
     nnms_system* s = sys[k];
     const int64_t n = s->h->host.lev[0].nv;
@@ -1923,8 +1976,10 @@ static nnms_status solve_many(nnms_system* const* systems, int32_t nb, const dou
     nnms_solve_info in = read_info(s, P->stream);
     if (infos) infos[k] = in;
     if (in.status != NNMS_OK) worst = NNMS_ERR_NOT_CONVERGED;
+    most_its = std::max(most_its, int(in.iterations));
   }
   HIP_CHECK(hipStreamSynchronize(P->stream));
+  P->expect = most_its;
   if (worst != NNMS_OK) nnms::set_last_error("iteration limit reached before the tolerance");
   return worst;
 }
@@ -2256,10 +2311,14 @@ extern "C" nnms_status nnms_hierarchy_get_tuning(const nnms_hierarchy* h, nnms_t
 extern "C" nnms_status nnms_hierarchy_set_tuning(nnms_hierarchy* h, const nnms_tuning* t) {
   ABI_BEGIN
   if (!h || !t) throw Error(NNMS_ERR_INVALID_ARG, "null argument");
-  for (int l = 0; l < NNMS_MAX_LEVELS; ++l)
-    if (!lanes_ok(t->spmv_lanes[l]) || !lanes_ok(t->pt_lanes[l]) || t->ras_groups[l] < 0 || t->ras_groups[l] > 65536 ||
-        !(t->ras_blocks[l] == 1 || t->ras_blocks[l] == 2 || t->ras_blocks[l] == 4))
+  for (int l = 0; l < NNMS_MAX_LEVELS; ++l) {
+    // the column-sorted slices only for a P^T that has them (entries of
+    // levels without a P^T are not used)
+    const bool csort_ok = t->pt_lanes[l] == SPMV_CSORT && (l + 1 >= h->host.L || h->dev[l].ptc_key);
+    if (!lanes_ok(t->spmv_lanes[l]) || !(lanes_ok(t->pt_lanes[l]) || csort_ok) || t->ras_groups[l] < 0 ||
+        t->ras_groups[l] > 65536 || !(t->ras_blocks[l] == 1 || t->ras_blocks[l] == 2 || t->ras_blocks[l] == 4))
       throw Error(NNMS_ERR_INVALID_ARG, "bad tuning entry");
+  }
   if (!lanes_ok(t->krylov_lanes)) throw Error(NNMS_ERR_INVALID_ARG, "bad tuning entry");
   h->tune = *t;
   h->tune.tuned = 1;
@@ -2296,17 +2355,22 @@ extern "C" nnms_status nnms_autotune(nnms_system* s, int32_t reps, nnms_tuning* 
   Arena tmp(h->has_alloc ? &h->alloc : nullptr);
   const int lanes[] = {4, 8, 16, 32, 64};
   // fastest lanes per CSR row; with the sliced ELL arrays given, 0 and 1
-  // (that layout, one wave per slice or four) are candidates too
+  // (that layout, one wave per slice or four) are candidates too, and with
+  // the column-sorted slices given, SPMV_CSORT
   auto spmv_best = [&](const int32_t* rp, const int32_t* col, const void* val, const void* x, const void* r, void* y,
                        int64_t n, bool dbl, const int32_t* soff = nullptr, const int32_t* scol = nullptr,
-                       const void* sval = nullptr) {
+                       const void* sval = nullptr, const int32_t* ckey = nullptr, const int32_t* cbase = nullptr,
+                       const void* cval = nullptr, int ccap = 0) {
     int best = 16;
     double bt = 1e30;
     std::vector<int> cand(std::begin(lanes), std::end(lanes));
     if (soff) cand.push_back(0), cand.push_back(1);
+    if (ckey && ccap > 0) cand.push_back(SPMV_CSORT);
     for (int g : cand) {
       SpmvDesc d{};
-      if (is_sell(g))
+      if (g == SPMV_CSORT)
+        d.rp = rp, d.col = ckey, d.val = cval, d.base = cbase, d.cap = ccap;
+      else if (is_sell(g))
         d.rp = soff, d.col = scol, d.val = sval;
       else
         d.rp = rp, d.col = col, d.val = val;
@@ -2315,7 +2379,12 @@ extern "C" nnms_status nnms_autotune(nnms_system* s, int32_t reps, nnms_tuning* 
       SpmvDesc* dd = tmp.upload(v, st);
       const int nb = spmv_blocks(n, g);
       double ms = time_ms(st, reps, [&]() {
-        if (is_sell(g)) {
+        if (g == SPMV_CSORT) {
+          if (dbl)
+            HIP_CHECK(launch_csort<double>(dd, 1, nb, ccap, st));
+          else
+            HIP_CHECK(launch_csort<float>(dd, 1, nb, ccap, st));
+        } else if (is_sell(g)) {
           if (dbl)
             HIP_CHECK(launch_sell<double>(dd, 1, nb, g, st));
           else
@@ -2368,8 +2437,9 @@ extern "C" nnms_status nnms_autotune(nnms_system* s, int32_t reps, nnms_tuning* 
     t.spmv_lanes[l] = spmv_best(dl.rp, dl.col, val, sl.z, sl.r, sl.t, n, f64, dl.sell_off, dl.sell_col, ell);
     const void* ptw = f64 ? (const void*)dl.pt_w64 : (const void*)dl.pt_w32;
     const void* ptsw = f64 ? (const void*)dl.pts_w64 : (const void*)dl.pts_w32;
+    const void* ptcw = f64 ? (const void*)dl.ptc_w64 : (const void*)dl.ptc_w32;
     t.pt_lanes[l] = spmv_best(dl.pt_rp, dl.pt_col, ptw, sl.t, nullptr, s->lev[l + 1].r, nc, f64, dl.pts_off,
-                              dl.pts_col, ptsw);
+                              dl.pts_col, ptsw, dl.ptc_key, dl.ptc_base, ptcw, dl.ptc_cap);
     // the dense smoother's launch shape (ILU levels have no dense factors)
     // (ILU levels have no dense factors; inverse panels have no shape to choose)
     if (h->host.lev[l].subsolver != NNMS_SUBSOLVER_ILU && !h->host.lev[l].xinv)

@@ -32,20 +32,29 @@ struct KState {
   double R[MMAX * MMAX];  // column-major upper triangle, R[k + j*MMAX]
 };
 
+// A CSR matrix in column-sorted slices (the restriction P^T): rows in slices
+// of 64; the entries of a slice are those of its rows, stored in column
+// order (ties in row order), each keyed by
+//   (column - the slice's smallest column) << CSORT_SLOT_BITS | p,
+// p its position in the slice's row-major (CSR) order.
+constexpr int CSORT_SLOT_BITS = 12;  // at most 4096 entries per slice
+constexpr int64_t CSORT_MAX_SPAN = int64_t(1) << (31 - CSORT_SLOT_BITS);  // columns a slice may span
+
 struct SpmvDesc {
   const int32_t* rp;
-  const int32_t* col;
+  const int32_t* col;  // column ids, or the keys of the column-sorted slices
   const void* val;
   const void* x;
   const void* r;       // optional: y = r - A x
   void* y;
   double* nrm;         // optional: per-block partial sums of y^2 (FP64 only)
   const KState* st;    // null: always active
+  const int32_t* base; // column-sorted slices: each slice's smallest column
   int64_t x_jstride;   // x += state.j * x_jstride
   int32_t n;
   int32_t blk0;        // first block of this descriptor
   int32_t when;
-  int32_t pad;
+  int32_t cap;         // column-sorted slices: most entries in one slice
 };
 
 struct ProlongDesc {

@@ -156,6 +156,38 @@ void build_sell_layout(const std::vector<int32_t>& rp, const std::vector<int32_t
   }
 }
 
+bool build_csort_layout(const std::vector<int32_t>& rp, const std::vector<int32_t>& col, int64_t nrows,
+                        std::vector<int32_t>& key, std::vector<int32_t>& base, std::vector<int32_t>& src,
+                        int32_t& cap) {
+  const int64_t ns = (nrows + 63) / 64;
+  key.assign(col.size(), 0);
+  src.assign(col.size(), 0);
+  base.assign(ns, 0);
+  cap = 0;
+  std::vector<int32_t> ord;
+  for (int64_t sl = 0; sl < ns; ++sl) {
+    const int32_t e0 = rp[sl * 64], e1 = rp[std::min(nrows, sl * 64 + 64)];
+    const int32_t ne = e1 - e0;
+    if (ne == 0) continue;
+    int32_t lo = col[e0], hi = col[e0];
+    for (int32_t e = e0; e < e1; ++e) lo = std::min(lo, col[e]), hi = std::max(hi, col[e]);
+    if (ne > (1 << CSORT_SLOT_BITS) || int64_t(hi) - lo >= CSORT_MAX_SPAN) {
+      key.clear(), src.clear(), base.clear(), cap = 0;
+      return false;
+    }
+    base[sl] = lo;
+    cap = std::max(cap, ne);
+    ord.resize(ne);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return col[e0 + a] < col[e0 + b]; });
+    for (int32_t k = 0; k < ne; ++k) {
+      key[e0 + k] = ((col[e0 + ord[k]] - lo) << CSORT_SLOT_BITS) | ord[k];
+      src[e0 + k] = e0 + ord[k];
+    }
+  }
+  return true;
+}
+
 void build_sell(HostLevel& lv) { build_sell_layout(lv.rp, lv.col, lv.nv, lv.sell_off, lv.sell_col, lv.sell_src); }
 
 void build_partition(HostLevel& lv, int nparts, int overlap, bool direct) {

@@ -15,6 +15,11 @@ hipError_t launch_spmv(const SpmvDesc* d, int nd, int nblocks, int group, hipStr
 // steps split over the four waves (nblocks = ceil(rows / 64))
 template <typename T>
 hipError_t launch_sell(const SpmvDesc* d, int nd, int nblocks, int split, hipStream_t s);
+// column-sorted slices (d.col = keys, d.base = slice bases, d.rp = the CSR
+// row pointers): one 64-row slice per block (nblocks = ceil(rows / 64) per
+// descriptor), cap = the most entries of one slice over the descriptors
+template <typename T>
+hipError_t launch_csort(const SpmvDesc* d, int nd, int nblocks, int cap, hipStream_t s);
 template <typename T>
 hipError_t launch_gather_ell(const int32_t* src, const double* csr, T* ell, int64_t n, hipStream_t s);
 template <typename T>

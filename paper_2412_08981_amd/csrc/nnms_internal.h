@@ -142,6 +142,13 @@ void build_pattern(HostLevel& lv);
 void build_sell_layout(const std::vector<int32_t>& rp, const std::vector<int32_t>& col, int64_t nrows,
                        std::vector<int32_t>& off, std::vector<int32_t>& scol, std::vector<int32_t>& src);
 void build_sell(HostLevel& lv);
+// the column-sorted slices of a CSR matrix (layout with CSORT_SLOT_BITS):
+// key, each slice's smallest column, the CSR position of every sorted entry
+// and the most entries in one slice; false (and empty arrays) when a slice
+// has more entries or spans more columns than a key holds
+bool build_csort_layout(const std::vector<int32_t>& rp, const std::vector<int32_t>& col, int64_t nrows,
+                        std::vector<int32_t>& key, std::vector<int32_t>& base, std::vector<int32_t>& src,
+                        int32_t& cap);
 void build_partition(HostLevel& lv, int nparts, int overlap, bool direct);
 // dense-factor bookkeeping of the partition (called by build_partition)
 void build_blocks(HostLevel& lv);

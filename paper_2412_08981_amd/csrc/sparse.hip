@@ -129,6 +129,57 @@ __global__ __launch_bounds__(256) void k_sell4(const SpmvDesc* __restrict__ d, i
   }
 }
 
+// Column-sorted slices (the restriction P^T, whose rows gather ~30 fine
+// entries from a few grid lines each): one 64-row slice per block.  The
+// slice's entries are stored in column order, so the gathers of a wave fall
+// on a few runs of consecutive fine entries instead of one scattered entry
+// per row; each product goes to its row-major position in LDS, and after a
+// barrier four lanes per row sum the row's products (lane q positions q,
+// q + 4, ..., in order; the four partial sums added pairwise).
+template <typename T>
+__global__ __launch_bounds__(256) void k_csort(const SpmvDesc* __restrict__ d, int nd) {
+  extern __shared__ __align__(16) unsigned char csort_lds[];
+  T* prod = reinterpret_cast<T*>(csort_lds);
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const SpmvDesc D = d[find_desc(d, nd, b)];
+  if (!slot_active(D.st, D.when)) return;
+  const int slice = b - D.blk0;
+  const int r0 = slice * 64;
+  const GLOBAL int32_t* __restrict__ rp = gptr(D.rp);
+  const int e0 = rp[r0], e1 = rp[min(r0 + 64, D.n)];
+  const GLOBAL T* __restrict__ x = gptr((const T*)D.x) + gptr(D.base)[slice];
+  if (D.x_jstride) x += int64_t(D.st->j) * D.x_jstride;
+  const GLOBAL int32_t* __restrict__ key = gptr(D.col);
+  const GLOBAL T* __restrict__ val = gptr((const T*)D.val);
+  constexpr int U = 4;  // entries per lane with their loads in flight together
+  constexpr int MASK = (1 << CSORT_SLOT_BITS) - 1;
+  for (int e = e0 + int(threadIdx.x); e < e1; e += 256 * U) {
+    int k[U];
+    T w[U], xv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int q = e + 256 * u;
+      k[u] = q < e1 ? key[q] : 0;  // key 0: the slice's first column, read again
+      w[u] = q < e1 ? val[q] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) xv[u] = x[k[u] >> CSORT_SLOT_BITS];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (e + 256 * u < e1) prod[k[u] & MASK] = w[u] * xv[u];
+  }
+  __syncthreads();
+  const int r = r0 + int(threadIdx.x >> 2), q = threadIdx.x & 3;
+  T sum = 0;
+  if (r < D.n) {
+    const int s0 = rp[r] - e0, s1 = rp[r + 1] - e0;
+    for (int k = s0 + q; k < s1; k += 4) sum += prod[k];
+  }
+  sum += __shfl_xor(sum, 1, 4);
+  sum += __shfl_xor(sum, 2, 4);
+  if (q == 0 && r < D.n) ((T*)D.y)[r] = D.r ? ((const T*)D.r)[r] - sum : sum;
+}
+
 // ell[e] = csr[src[e]] (0 for padding, src < 0)
 template <typename T>
 __global__ __launch_bounds__(256) void k_gather_ell(const int32_t* __restrict__ src, const double* __restrict__ csr,
@@ -157,6 +208,16 @@ hipError_t launch_gather_ell(const int32_t* src, const double* csr, T* ell, int6
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_csort(const SpmvDesc* d, int nd, int nblocks, int cap, hipStream_t s) {
+  if (nd <= 0 || nblocks <= 0) return hipSuccess;
+  if (cap < 1 || cap > (1 << CSORT_SLOT_BITS)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_csort<T>), dim3(nblocks), dim3(256), size_t(cap) * sizeof(T), s, d, nd);
+  return hipGetLastError();
+}
+
+template hipError_t launch_csort<double>(const SpmvDesc*, int, int, int, hipStream_t);
+template hipError_t launch_csort<float>(const SpmvDesc*, int, int, int, hipStream_t);
 template hipError_t launch_sell<double>(const SpmvDesc*, int, int, int, hipStream_t);
 template hipError_t launch_sell<float>(const SpmvDesc*, int, int, int, hipStream_t);
 template hipError_t launch_gather_ell<double>(const int32_t*, const double*, double*, int64_t, hipStream_t);

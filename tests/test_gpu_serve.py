@@ -2,6 +2,8 @@
 the GPU join the running batch as memory frees up; each result equals the
 same request solved alone (bitwise), and requests larger than the budget are
 rejected."""
+import time
+
 import numpy as np
 import pytest
 
@@ -30,7 +32,16 @@ def _setup(precision):
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
 def test_serving_results_equal_alone(precision):
     nnms, hier, keep = _setup(precision)
-    from paper_2412_08981_amd.serve import Request, Server
+    from paper_2412_08981_amd.serve import DeviceEngine, Request, Server
+
+    class HeldSteps(DeviceEngine):
+        """Each Arnoldi step held ~2 ms on the host, so that a running solve
+        outlasts the next request's assembly (one worker) on any box and
+        requests do share steps; the arithmetic is unchanged."""
+
+        def step(self, batch):
+            super().step(batch)
+            time.sleep(0.002)
 
     rng = np.random.default_rng(3)
     centres = W.serving_centres()
@@ -43,7 +54,7 @@ def test_serving_results_equal_alone(precision):
         reqs.append(Request(i, keys[i % 3], W.KappaField("loggauss", centres=centres, mu=mu, width=0.02), t))
     # budget for about two requests at once: later arrivals wait for memory
     budget = 2.5 * max(h.system_bytes() for h in hier.values())
-    srv = Server(hier, budget, keep_x=True)
+    srv = Server(hier, budget, keep_x=True, engine=HeldSteps())
     st = srv.run(reqs)
     assert st["completed"] == 12 and st["rejected"] == 0
     assert srv.batch_forms >= 3

@@ -28,7 +28,7 @@ def test_autotune_keeps_results_and_caches(tmp_path):
     cache = str(tmp_path / "tuning.json")
     t = autotune.tune(s, cache=cache, reps=3)
     assert t["tuned"] == 1 and t["spmv_lanes"][0] in (0, 1, 4, 8, 16, 32, 64)
-    assert t["pt_lanes"][0] in (0, 1, 4, 8, 16, 32, 64)
+    assert t["pt_lanes"][0] in (0, 1, 2, 4, 8, 16, 32, 64)  # 2: P^T in column-sorted slices
     assert h.get_tuning() == t
     x1, i1 = s.solve(b)
     assert i1.iterations == i0.iterations and np.linalg.norm(x1 - x0) <= 1e-10 * np.linalg.norm(x0)
@@ -54,6 +54,10 @@ def test_autotune_keeps_results_and_caches(tmp_path):
     with pytest.raises(nnms.NNMSError):
         bad = dict(t)
         bad["spmv_lanes"] = [3] * 8
+        h.set_tuning(bad)
+    with pytest.raises(nnms.NNMSError):  # column-sorted slices exist for P^T only
+        bad = dict(t)
+        bad["spmv_lanes"] = [2] * 8
         h.set_tuning(bad)
 
 
