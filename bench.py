@@ -434,10 +434,11 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
-    ap.add_argument("--workload", default="cube48", choices=["cube48", "cube16", "batched", "serving"],
+    ap.add_argument("--workload", default="cube48", choices=["cube48", "cube16", "batched", "serving", "served96"],
                     help="cube48: the three-level 48^3 problem (default); cube16: the two-level 16^3/6^3 problem "
                          "(kappa = 1, 8 subdomains); batched: ragged parametric instances; serving: continuous "
-                         "batching of Poisson arrivals")
+                         "batching of Poisson arrivals; served96: the largest served hierarchy (96^3/48^3/20^3, "
+                         "512 + 64 subdomains) as one system")
     ap.add_argument("--requests", type=int, default=60, help="requests of the serving trace")
     ap.add_argument("--tuning-cache", default=os.path.join(ROOT, "paper_2412_08981_amd", "tuning.json"),
                     help="launch-shape cache (measured on first use)")
@@ -473,6 +474,8 @@ def main():
                     help="time the fine level's numeric factorisation a few times (for counter runs)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="run the copy reference and the fine-level smoother a few times each (for counter runs)")
+    ap.add_argument("--transfers-only", action="store_true",
+                    help="time the prolongation and restriction of every level at the tuned shapes (JSON line)")
     args = ap.parse_args()
     if args.dense_apply is None:
         args.dense_apply = "sweeps" if args.workload == "serving" else "inverse"
@@ -497,6 +500,11 @@ def main():
     elif args.workload == "cube16":
         pb = W.cube16_two_level()
         pb.precision = args.precision
+    elif args.workload == "served96":
+        # the largest served hierarchy as a single system (96^3 / 48^3 / 20^3)
+        ms96 = W.served_hierarchy(96)
+        pb = W.Problem("served96", ms96, [W.nparts_rule(m.nv) for m in ms96[:-1]], W.kappa_draw(5003, 5004),
+                       precision=args.precision)
     else:
         pb = W.cube48_three_level(args.precision)
     prec = nnms.MIXED if args.precision == "mixed" else nnms.FP64
@@ -552,6 +560,22 @@ def main():
         tf = lu_flops(h, 0) / (msf * 1e-3) / 1e12
         print(json.dumps({"factor_l0_launches": 1 + 3, "factor_l0_ms": msf, "factor_l0_flops": lu_flops(h, 0),
                           "factor_l0_TFLOPs": tf, "frac_of_mfma_peak": tf / MFMA_PEAK_TFLOPS[fb]}))
+        return
+    if args.transfers_only:
+        # the transfers of every level at the tuned shapes (20 timed launches each)
+        sb = 8 if prec == nnms.FP64 else 4
+        out = {"workload": pb.name, "pt_lanes": tuning["pt_lanes"][:h.L - 1]}
+        for lvl in range(h.L - 1):
+            mst = s.time_kernel(3, lvl, reps=20)
+            msp = s.time_kernel(2, lvl, reps=20)
+            rb, pbytes = restrict_bytes(h, lvl, sb), prolong_bytes(h, lvl, sb)
+            out.update({f"restrict_l{lvl}_launches": 1 + 20, f"restrict_l{lvl}_ms": mst,
+                        f"restrict_l{lvl}_algorithmic_bytes": rb,
+                        f"restrict_l{lvl}_frac_of_hbm_peak": rb / (mst * 1e-3) / HBM_PEAK_GBS / 1e9,
+                        f"prolong_l{lvl}_launches": 1 + 20, f"prolong_l{lvl}_ms": msp,
+                        f"prolong_l{lvl}_algorithmic_bytes": pbytes,
+                        f"prolong_l{lvl}_frac_of_hbm_peak": pbytes / (msp * 1e-3) / HBM_PEAK_GBS / 1e9})
+        print(json.dumps(out))
         return
     if args.kernels_only:
         # same launch shapes and repetition counts as the roofline figures below
@@ -700,6 +724,9 @@ def main():
                                 f"{W.ELASTIC_NU}, body force {W.ELASTIC_FORCE}, " if elastic else
                                 "jittered unit cube, 2 non-nested levels 16^3/6^3 (4913 fine vertices, 24576 tets), "
                                 "kappa = 1, f = 1, " if args.workload == "cube16" else
+                                f"jittered unit cube, 3 non-nested levels 96^3/48^3/20^3 "
+                                f"({pb.meshes[0].nv} fine vertices), log-Gaussian kappa (8 centres), "
+                                if args.workload == "served96" else
                                 f"jittered unit cube, 3 non-nested levels 48^3/24^3/10^3 "
                                 f"(117649 fine vertices, 663552 tets), log-Gaussian kappa (8 centres), ")
                                + f"{'+'.join(str(p) for p in pb.nparts)} subdomains overlap 1, FGMRES(30) to 1e-8, "
