@@ -537,11 +537,12 @@ nnms_status nnms_autotune(nnms_system* s, int32_t reps, nnms_tuning* out);
  * ||b|| = 0 gives x = 0 and iterations = 0.
  * NNMS_ERR_NOT_CONVERGED: max_it reached; x holds the last iterate and info
  * is filled.
- * nnms_solve replays the Arnoldi steps from captured HIP graphs (unless
- * NNMS_NO_GRAPH): first as many steps in one graph as the system's previous
- * solve took (at most 64), then one step at a time while the slot still
- * iterates.  Steps after convergence change nothing, so x and info do not
- * depend on earlier solves.
+ * nnms_solve replays each Arnoldi step from one HIP graph, captured on the
+ * system's first solve (unless NNMS_NO_GRAPH): first as many steps back to
+ * back as the system's previous solve took (at most 64), with one host
+ * read of the running count after them, then one step at a time while the
+ * slot still iterates.  Steps after convergence change nothing, so x and
+ * info do not depend on earlier solves.
  * ------------------------------------------------------------------------- */
 #define NNMS_DEVICE_PTRS 1
 #define NNMS_NO_GRAPH 2

@@ -416,11 +416,10 @@ struct Plan {
   int* d_active = nullptr;
   int* h_active = nullptr;
   hipStream_t stream = nullptr;
-  // instantiated graphs of K consecutive Arnoldi steps, by K
-  std::map<int, hipGraphExec_t> graphs;
+  hipGraphExec_t graph = nullptr;  // one Arnoldi step, captured on first use
   bool use_graph = true;
-  // Arnoldi steps the plan's last solve took: the next solve replays that
-  // many steps as one graph before it reads the active count
+  // Arnoldi steps the plan's last solve took: the next solve enqueues that
+  // many steps before it reads the active count
   int expect = 0;
   std::vector<int32_t*> counters;
   Plan() = default;
@@ -428,7 +427,7 @@ struct Plan {
     // this plan's own work is done before its graph and descriptors go (a
     // stream synchronisation: other streams are not waited for)
     if (stream) (void)hipStreamSynchronize(stream);
-    for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+    if (graph) (void)hipGraphExecDestroy(graph);
     std::lock_guard<std::mutex> g(plan_pools().mu);
     if (h_active) plan_pools().words.push_back(h_active);
     if (stream) plan_pools().streams.push_back(stream);
@@ -819,25 +818,24 @@ static void enqueue_step(Plan& P, hipStream_t s) {
   HIP_CHECK(launch_krylov_cycle(P.kd, P.nd, s));
 }
 
-// K consecutive Arnoldi steps: one graph replay (captured on first use),
+// K consecutive Arnoldi steps enqueued back to back: K replays of the
+// plan's one-step graph (captured once, on first use: a capture in progress
+// makes other threads' legacy-stream calls fail, so none happens per solve),
 // or the launches themselves with NNMS_NO_GRAPH.  Steps after a slot has
 // converged leave it unchanged (every kernel skips finished slots).
 static void plan_steps(Plan& P, int K) {
   hipStream_t s = P.stream;
   auto enqueue = [&]() {
-    for (int k = 0; k < K; ++k) {
-      if (P.prec == NNMS_MIXED)
-        enqueue_step<float>(P, s);
-      else
-        enqueue_step<double>(P, s);
-    }
+    if (P.prec == NNMS_MIXED)
+      enqueue_step<float>(P, s);
+    else
+      enqueue_step<double>(P, s);
   };
   if (!P.use_graph) {
-    enqueue();
+    for (int k = 0; k < K; ++k) enqueue();
     return;
   }
-  auto it = P.graphs.find(K);
-  if (it == P.graphs.end()) {
+  if (!P.graph) {
     hipGraph_t g;
     HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     try {
@@ -849,13 +847,11 @@ static void plan_steps(Plan& P, int K) {
       throw;
     }
     HIP_CHECK(hipStreamEndCapture(s, &g));
-    hipGraphExec_t ex = nullptr;
-    hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    hipError_t e = hipGraphInstantiate(&P.graph, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     HIP_CHECK(e);
-    it = P.graphs.emplace(K, ex).first;
   }
-  HIP_CHECK(hipGraphLaunch(it->second, s));
+  for (int k = 0; k < K; ++k) HIP_CHECK(hipGraphLaunch(P.graph, s));
 }
 
 static void plan_step(Plan& P) { plan_steps(P, 1); }
@@ -1897,7 +1893,7 @@ struct nnms_batch {
 };
 
 // Steps until no slot is running: first as many as the plan's last solve
-// took (at most MAX_GRAPH_STEPS), in one graph and with one host read of the
+// took (at most MAX_GRAPH_STEPS), back to back with one host read of the
 // active count (parametric solves of one system take about the same number),
 // then one at a time.
 constexpr int MAX_GRAPH_STEPS = 64;

@@ -1,5 +1,6 @@
-"""A solve replays as many Arnoldi steps as the plan's previous solve took,
-in one HIP graph, before it reads the running-slot count.  Steps after a
+"""A solve enqueues as many Arnoldi steps as the plan's previous solve took
+(replays of the plan's one-step HIP graph, back to back) before it reads
+the running-slot count.  Steps after a
 slot has converged leave it unchanged, so a solve's result and iteration
 count do not depend on what the system solved before: after a longer solve
 (more steps replayed than needed), after a shorter one (the graph ends
